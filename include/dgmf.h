@@ -1,0 +1,199 @@
+/*
+ * dgmf: matrix-free discontinuous Galerkin operators on tensor-product
+ * hexahedra for AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Krank, Fehn, Wall & Kronbichler, "A high-order
+ * semi-explicit discontinuous Galerkin solver for 3D incompressible flow with
+ * application to DNS and LES of turbulent channel flow" (arXiv:1607.01323):
+ *   - nodal Lagrange basis of tensor degree k on Gauss-Lobatto nodes
+ *     (Sec. 3.1), Gauss quadrature with k+1 points per direction for the
+ *     linear forms and over-integration for the convective term (Sec. 5);
+ *   - the symmetric interior penalty (SIPG) Laplace operator of the pressure
+ *     Poisson step and the Helmholtz operator of the viscous step in its
+ *     scalar form (Sec. 3.2, eqs. poissonspat, ipflux, taue, tau; matrix
+ *     form Sec. 4.4, eqs. poissonmat and viscous);
+ *   - preconditioned conjugate gradients with matrix-free products, point
+ *     Jacobi or a Chebyshev polynomial preconditioner in single precision,
+ *     and the zero-mean projection of singular problems (Sec. 5.1);
+ *   - the divergence-form convective operator with the local Lax-Friedrichs
+ *     flux, Lambda evaluated per face quadrature point (Sec. 3.2, eq.
+ *     convstepspat; matrix form eq. advect), and its vector-Jacobian product.
+ *
+ * Conventions shared by every entry point
+ *   Reference cell [0,1]^3, n = k+1 nodes per direction.
+ *   Cell index c = (cz*ny + cy)*nx + cx.
+ *   DoF index g = c*n^3 + (l*n + j)*n + i (x node index i fastest).
+ *   Vector fields are component-major: [3][N], N = n_cells * n^3.
+ *   All vector arguments are DEVICE pointers on the device that was current
+ *   when the handle was created, contiguous, of the dtype the call states,
+ *   owned by the caller.  The library never keeps a pointer past the work it
+ *   enqueues; the caller keeps buffers alive until the stream passes it.
+ *   Work is enqueued on the given hipStream_t (0 = the null stream) and the
+ *   call returns without waiting unless it says otherwise.
+ *
+ * Errors: every function returns a dgmf_status; no exception crosses the
+ * ABI.  Argument errors are detected before anything is enqueued and leave
+ * outputs untouched.  dgmf_last_error() returns a thread-local message for
+ * the last non-OK status of the calling thread.  Launch failures are reported
+ * as DGMF_HIP_ERROR; device faults surface at the next synchronising call.
+ */
+#ifndef DGMF_H
+#define DGMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DGMF_OK = 0,
+  DGMF_INVALID = 1,        /* bad argument: null/misaligned pointer, size, degree, dtype */
+  DGMF_HIP_ERROR = 2,      /* a HIP runtime call or kernel launch failed */
+  DGMF_OOM = 3,            /* device allocation failed */
+  DGMF_NOT_CONVERGED = 4,  /* CG reached max_iter; outputs hold the last iterate */
+  DGMF_BREAKDOWN = 5,      /* CG: <r,z> <= 0 or <p,Ap> <= 0 (preconditioner/operator not SPD) */
+  DGMF_NONFINITE = 6,      /* CG: NaN/Inf in the data or in a scalar of the iteration */
+  DGMF_UNSUPPORTED = 7     /* valid request outside what this build implements */
+} dgmf_status;
+
+typedef enum { DGMF_F64 = 0, DGMF_F32 = 1 } dgmf_dtype;
+
+typedef struct dgmf_mesh_* dgmf_mesh;  /* opaque, library-owned */
+typedef struct dgmf_op_* dgmf_op;      /* opaque, library-owned */
+
+/* Thread-local text of the last error of the calling thread ("" if none). */
+const char* dgmf_last_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int dgmf_version(void);
+
+/* ---------------------------------------------------------------- mesh --- */
+/* Box [0,lx] x [y0,y0+ly] x [0,lz] of nx*ny*nz affine hexahedra (Sec. 3.1).
+ * periodic[d] = 1: faces at both ends of direction d are identified and
+ * treated as interior faces; 0: both ends are Dirichlet boundaries.
+ * y_tanh_gamma > 0 grades the y vertices with the hyperbolic mapping of
+ * Sec. 7.1, y = y0 + ly/2 (1 + tanh(gamma (2t-1)) / tanh(gamma)), t in [0,1].
+ * store_qp_metric = 1 makes SIPG operators on this mesh store and stream the
+ * geometry at every quadrature point (inverse Jacobian, Jacobian determinant
+ * times weight) instead of using the per-cell constant metric.
+ * degree k in 1..7; every cell count >= 1; lengths > 0. */
+typedef struct {
+  int degree;
+  int nx, ny, nz;
+  double lx, ly, lz;
+  double y0;
+  int periodic[3];
+  double y_tanh_gamma;
+  int store_qp_metric;
+} dgmf_box_desc;
+
+/* Allocates device geometry on the current device.  *out receives the handle. */
+dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out);
+/* Host outputs (either may be NULL). */
+dgmf_status dgmf_mesh_info(dgmf_mesh mesh, int64_t* n_cells, int64_t* n_dofs_per_field);
+/* Physical coordinates of every DoF: xyz is a device double array [3][N]. */
+dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t stream);
+/* Frees the mesh; operators created on it must be destroyed first (DGMF_INVALID otherwise). */
+dgmf_status dgmf_mesh_destroy(dgmf_mesh mesh);
+
+/* ------------------------------------------------------------ SIPG op --- */
+/* Operator H = mass_coeff * M + diff_coeff * A, A the SIPG Laplacian of
+ * Sec. 3.2 with homogeneous Dirichlet data on Dirichlet faces (boundary
+ * penalty 2 tau); tau_e = penalty_scale (k+1)^2 (A_int/2 + A_Dir)/V
+ * (eq. taue), tau_F = max over the two cells (eq. tau).  The paper's choice is
+ * penalty_scale = 1.  n_q must be 0 or k+1 (Sec. 5: k+1 Gauss points). */
+typedef struct {
+  double mass_coeff;     /* mu = gamma_0 / dt; 0 for the Laplacian */
+  double diff_coeff;     /* nu; 1 for the Laplacian */
+  double penalty_scale;  /* s in tau_e */
+  int n_q;               /* 0 -> k+1 */
+} dgmf_sipg_desc;
+
+dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op* out);
+/* dst = H src.  src, dst: device arrays of N values of the given dtype;
+ * must not alias.  Asynchronous on stream. */
+dgmf_status dgmf_operator_apply(dgmf_op op, dgmf_dtype dtype, const void* src, void* dst, hipStream_t stream);
+/* diag = diag(H), N values of dtype.  Asynchronous. */
+dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hipStream_t stream);
+/* Cell quadrature points of the operator's rule: xyz device double [3][n_cells*n_q^3],
+ * point index c*n_q^3 + (qz*n_q + qy)*n_q + qx.  Asynchronous. */
+dgmf_status dgmf_quadrature_points(dgmf_op op, double* xyz, hipStream_t stream);
+/* b_i = sum_K (f, phi_i)_K by the operator's Gauss rule, f given at the
+ * quadrature points (layout of dgmf_quadrature_points), fp64.  This is the
+ * load vector of the right-hand sides in Sec. 4.4.  Asynchronous. */
+dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_t stream);
+
+/* ------------------------------------------------------------------ CG --- */
+/* Preconditioned CG on H x = b (Sec. 5.1).  Convergence when
+ * ||r_k||_2 <= rtol ||b||_2 on the recursive residual (b projected first when
+ * project_mean).  precond 0: point Jacobi in fp64.  precond 1: Chebyshev
+ * acceleration of point Jacobi, error polynomial of degree cheb_degree on
+ * [lambda/smoothing_range, lambda] started from zero (cheb_degree-1 operator
+ * products in precond_dtype), lambda = lambda_safety * the largest Ritz value
+ * of lanczos_steps Lanczos steps on D^{-1/2} H D^{-1/2} in precond_dtype from
+ * a SplitMix64(seed) start vector (mean removed when project_mean).  With
+ * precond_dtype DGMF_F32 the preconditioner runs in fp32 while residual, dot
+ * products and updates stay fp64 (mixed precision).  project_mean = 1
+ * projects b and every operator product onto zero-mean vectors (singular
+ * periodic Laplacian).  check_every: iterations between host reads of the
+ * convergence flag (the iteration count is exact regardless). */
+typedef struct {
+  double rtol;
+  int max_iter;
+  int check_every;
+  int precond;           /* 0 Jacobi, 1 Chebyshev */
+  int precond_dtype;     /* dgmf_dtype of the Chebyshev preconditioner */
+  int cheb_degree;       /* >= 1 */
+  double smoothing_range;/* > 1 */
+  int lanczos_steps;     /* 2..64 */
+  double lambda_safety;  /* >= 1 */
+  uint64_t seed;
+  int project_mean;
+} dgmf_cg_params;
+
+typedef struct {
+  int iterations;
+  double rel_residual;   /* ||r_k|| / ||b|| of the recursive residual */
+  double lambda_max;     /* lambda used by the Chebyshev preconditioner (0 for Jacobi) */
+  int status;            /* dgmf_status of the solve */
+  double setup_s;        /* seconds in diagonal + eigenvalue estimate */
+  double solve_s;        /* seconds in the iteration */
+} dgmf_cg_result;
+
+/* Bytes of device workspace dgmf_cg_solve needs for these parameters. */
+dgmf_status dgmf_cg_workspace_bytes(dgmf_op op, const dgmf_cg_params* params, size_t* bytes);
+/* b: device fp64 [N]; x: device fp64 [N], initial guess on entry, solution on
+ * exit.  workspace: device memory of at least the queried size, 256-byte
+ * aligned.  Synchronous: returns after the work on stream has finished;
+ * *out (host) is filled on every path past argument validation, and the
+ * returned status equals out->status. */
+dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream,
+                          dgmf_cg_result* out);
+
+/* ---------------------------------------------------------- convective --- */
+/* Convective operator C(U)_{i,a} = -sum_K (d_b phi_i, u_a u_b)_K
+ *   + sum_K (phi_i, R_a)_{dK}, R = 1/2 (u-(u-.n) + u+(u+.n)) + lam (u- - u+),
+ * lam = max(|u-.n|, |u+.n|) per face quadrature point (Sec. 3.2); Dirichlet
+ * faces use the mirror state u+ = 2g - u- with g = 0.  n_q Gauss points per
+ * direction on cells and faces; 0 -> floor(3(k+1)/2). */
+typedef struct { int n_q; } dgmf_conv_desc;
+
+dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, dgmf_op* out);
+/* out = C(u); u, out: device fp64 [3][N], must not alias.  Asynchronous. */
+dgmf_status dgmf_convective_apply(dgmf_op op, const double* u, double* out, hipStream_t stream);
+/* grad = (dC/du)^T w; u, w, grad: device fp64 [3][N]; grad must not alias
+ * u or w.  Tie rule of the max: the minus side is active when
+ * |u-.n| >= |u+.n|; sgn(0) = 0.  Asynchronous. */
+dgmf_status dgmf_convective_vjp(dgmf_op op, const double* u, const double* w, double* grad,
+                                hipStream_t stream);
+
+/* Frees any operator handle. */
+dgmf_status dgmf_op_destroy(dgmf_op op);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGMF_H */

@@ -1,0 +1,314 @@
+// C-ABI entry points of libdgmf: handles, validation, launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace dgmf {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+}  // namespace
+
+dgmf_status fail(dgmf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+dgmf_status DevBuf::alloc(size_t nbytes) {
+  release();
+  if (nbytes == 0) return DGMF_OK;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? DGMF_OOM : DGMF_HIP_ERROR, "hipMalloc(%zu) failed: %s", nbytes,
+                hipGetErrorString(e));
+  }
+  bytes = nbytes;
+  return DGMF_OK;
+}
+
+dgmf_status DevBuf::upload(const void* host, size_t nbytes) {
+  dgmf_status st = alloc(nbytes);
+  if (st != DGMF_OK) return st;
+  DGMF_HIP_TRY(hipMemcpy(p, host, nbytes, hipMemcpyHostToDevice));
+  return DGMF_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+// Per-direction geometry arrays (x0, h, 1/h, tp) of a box mesh, contiguous.
+template <typename T>
+static dgmf_status upload_geometry(dgmf_mesh m, DevBuf& buf, CartGeom<T>& g) {
+  const int nd[3] = {m->desc.nx, m->desc.ny, m->desc.nz};
+  std::vector<T> host;
+  size_t off[3];
+  for (int d = 0; d < 3; ++d) {
+    off[d] = host.size();
+    const auto& v = m->verts[d];
+    for (int c = 0; c < nd[d]; ++c) host.push_back(static_cast<T>(v[c]));
+    for (int c = 0; c < nd[d]; ++c) host.push_back(static_cast<T>(v[c + 1] - v[c]));
+    for (int c = 0; c < nd[d]; ++c) host.push_back(static_cast<T>(1.0 / (v[c + 1] - v[c])));
+    for (int c = 0; c < nd[d]; ++c) {
+      double w = 1.0;   // two interior faces, half of each
+      if (!m->desc.periodic[d]) {
+        if (nd[d] == 1) w = 2.0;
+        else if (c == 0 || c == nd[d] - 1) w = 1.5;
+      }
+      host.push_back(static_cast<T>(w / (v[c + 1] - v[c])));
+    }
+  }
+  dgmf_status st = buf.upload(host.data(), host.size() * sizeof(T));
+  if (st != DGMF_OK) return st;
+  const T* base = static_cast<const T*>(buf.p);
+  g.nx = nd[0];
+  g.ny = nd[1];
+  g.nz = nd[2];
+  for (int d = 0; d < 3; ++d) {
+    g.per[d] = m->desc.periodic[d] ? 1 : 0;
+    g.x0[d] = base + off[d];
+    g.h[d] = base + off[d] + nd[d];
+    g.hinv[d] = base + off[d] + 2 * nd[d];
+    g.tp[d] = base + off[d] + 3 * nd[d];
+  }
+  return DGMF_OK;
+}
+
+template <typename T>
+static dgmf_status upload_tables(const Tables1D& t, DevBuf& buf) {
+  TabLayout L{t.n, t.nq};
+  std::vector<T> h(L.size());
+  for (int i = 0; i < t.n * t.n; ++i) {
+    h[L.mhat() + i] = static_cast<T>(t.Mhat[i]);
+    h[L.khat() + i] = static_cast<T>(t.Khat[i]);
+  }
+  for (int i = 0; i < t.n; ++i) {
+    h[L.g0() + i] = static_cast<T>(t.g0[i]);
+    h[L.g1() + i] = static_cast<T>(t.g1[i]);
+    h[L.nodes() + i] = static_cast<T>(t.nodes[i]);
+  }
+  for (int i = 0; i < t.nq * t.n; ++i) h[L.S() + i] = static_cast<T>(t.S[i]);
+  for (int q = 0; q < t.nq; ++q) {
+    h[L.wq() + q] = static_cast<T>(t.wq[q]);
+    h[L.xq() + q] = static_cast<T>(t.xq[q]);
+  }
+  return buf.upload(h.data(), h.size() * sizeof(T));
+}
+
+static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+static bool overlap(const void* a, const void* b, size_t bytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" {
+
+const char* dgmf_last_error(void) { return last_error_cstr(); }
+
+int dgmf_version(void) { return 100; }
+
+dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
+  if (!desc || !out) return fail(DGMF_INVALID, "mesh_create: null argument");
+  const dgmf_box_desc& d = *desc;
+  if (d.degree < kMinDegree || d.degree > kMaxDegree)
+    return fail(DGMF_INVALID, "mesh_create: degree %d outside %d..%d", d.degree, kMinDegree, kMaxDegree);
+  if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(DGMF_INVALID, "mesh_create: cell counts must be >= 1");
+  if (!(d.lx > 0) || !(d.ly > 0) || !(d.lz > 0) || !std::isfinite(d.lx) || !std::isfinite(d.ly) ||
+      !std::isfinite(d.lz) || !std::isfinite(d.y0))
+    return fail(DGMF_INVALID, "mesh_create: lengths must be finite and > 0");
+  if (!(d.y_tanh_gamma >= 0) || !std::isfinite(d.y_tanh_gamma))
+    return fail(DGMF_INVALID, "mesh_create: y_tanh_gamma must be finite and >= 0");
+  const int64_t n = d.degree + 1;
+  const int64_t ncells = static_cast<int64_t>(d.nx) * d.ny * d.nz;
+  if (ncells > (int64_t(1) << 40) / (n * n * n)) return fail(DGMF_INVALID, "mesh_create: mesh too large");
+  auto* m = new (std::nothrow) dgmf_mesh_;
+  if (!m) return fail(DGMF_OOM, "mesh_create: host allocation failed");
+  m->desc = d;
+  for (int a = 0; a < 3; ++a) m->desc.periodic[a] = d.periodic[a] ? 1 : 0;
+  m->ncells = ncells;
+  m->ndofs = ncells * n * n * n;
+  if (hipGetDevice(&m->device) != hipSuccess) {
+    delete m;
+    return fail(DGMF_HIP_ERROR, "mesh_create: no HIP device");
+  }
+  const int nd[3] = {d.nx, d.ny, d.nz};
+  const double len[3] = {d.lx, d.ly, d.lz};
+  const double org[3] = {0.0, d.y0, 0.0};
+  for (int a = 0; a < 3; ++a) {
+    auto& v = m->verts[a];
+    v.resize(nd[a] + 1);
+    for (int c = 0; c <= nd[a]; ++c) {
+      const double t = static_cast<double>(c) / nd[a];
+      if (a == 1 && d.y_tanh_gamma > 0)
+        v[c] = org[a] + 0.5 * len[a] * (1.0 + std::tanh(d.y_tanh_gamma * (2.0 * t - 1.0)) / std::tanh(d.y_tanh_gamma));
+      else
+        v[c] = org[a] + len[a] * t;
+    }
+    v[0] = org[a];
+    v[nd[a]] = org[a] + len[a];
+  }
+  make_tables(d.degree, d.degree + 1, m->tab);
+  dgmf_status st = upload_geometry<double>(m, m->geo64, m->g64);
+  if (st == DGMF_OK) st = upload_geometry<float>(m, m->geo32, m->g32);
+  if (st == DGMF_OK) st = upload_tables<double>(m->tab, m->tab64);
+  if (st != DGMF_OK) {
+    delete m;
+    return st;
+  }
+  m->g64.tab = static_cast<const double*>(m->tab64.p);
+  *out = m;
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_mesh_info(dgmf_mesh mesh, int64_t* n_cells, int64_t* n_dofs) {
+  if (!mesh) return fail(DGMF_INVALID, "mesh_info: null mesh");
+  if (n_cells) *n_cells = mesh->ncells;
+  if (n_dofs) *n_dofs = mesh->ndofs;
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_mesh_destroy(dgmf_mesh mesh) {
+  if (!mesh) return DGMF_OK;
+  if (mesh->nops > 0) return fail(DGMF_INVALID, "mesh_destroy: %d operator(s) still use this mesh", mesh->nops);
+  DeviceGuard g(mesh->device);
+  delete mesh;
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t stream) {
+  if (!mesh || !xyz) return fail(DGMF_INVALID, "mesh_node_coords: null argument");
+  if (!aligned(xyz, 8)) return fail(DGMF_INVALID, "mesh_node_coords: misaligned output");
+  DeviceGuard dg(mesh->device);
+  return launch_node_coords(mesh->tab.n, mesh->g64, xyz, mesh->ncells, stream);
+}
+
+dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op* out) {
+  if (!mesh || !desc || !out) return fail(DGMF_INVALID, "sipg_create: null argument");
+  const int n = mesh->desc.degree + 1;
+  if (desc->n_q != 0 && desc->n_q != n)
+    return fail(DGMF_UNSUPPORTED, "sipg_create: n_q must be 0 or k+1 (got %d)", desc->n_q);
+  if (!std::isfinite(desc->mass_coeff) || !std::isfinite(desc->diff_coeff) || !std::isfinite(desc->penalty_scale) ||
+      desc->mass_coeff < 0 || desc->diff_coeff < 0 || !(desc->penalty_scale > 0))
+    return fail(DGMF_INVALID, "sipg_create: coefficients must be finite, mass/diff >= 0, penalty > 0");
+  if (mesh->desc.store_qp_metric)
+    return fail(DGMF_UNSUPPORTED, "sipg_create: per-quadrature-point metric not available in this build");
+  DeviceGuard dg(mesh->device);
+  auto* op = new (std::nothrow) dgmf_op_;
+  if (!op) return fail(DGMF_OOM, "sipg_create: host allocation failed");
+  op->kind = 1;
+  op->mesh = mesh;
+  op->sipg = *desc;
+  op->nq = n;
+  make_tables(mesh->desc.degree, n, op->tab);
+  dgmf_status st = upload_tables<double>(op->tab, op->tab64);
+  if (st == DGMF_OK) st = upload_tables<float>(op->tab, op->tab32);
+  op->g64 = mesh->g64;
+  op->g32 = mesh->g32;
+  if (st != DGMF_OK) {
+    delete op;
+    return st;
+  }
+  const double pen = desc->penalty_scale * n * n;
+  op->g64.pen = pen;
+  op->g64.mu = desc->mass_coeff;
+  op->g64.nu = desc->diff_coeff;
+  op->g64.tab = static_cast<const double*>(op->tab64.p);
+  op->g32.pen = static_cast<float>(pen);
+  op->g32.mu = static_cast<float>(desc->mass_coeff);
+  op->g32.nu = static_cast<float>(desc->diff_coeff);
+  op->g32.tab = static_cast<const float*>(op->tab32.p);
+  mesh->nops++;
+  *out = op;
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_operator_apply(dgmf_op op, dgmf_dtype dtype, const void* src, void* dst, hipStream_t stream) {
+  if (!op || op->kind != 1) return fail(DGMF_INVALID, "operator_apply: not an SIPG operator");
+  if (!src || !dst) return fail(DGMF_INVALID, "operator_apply: null vector");
+  const size_t es = dtype == DGMF_F64 ? 8 : (dtype == DGMF_F32 ? 4 : 0);
+  if (!es) return fail(DGMF_INVALID, "operator_apply: unknown dtype %d", static_cast<int>(dtype));
+  if (!aligned(src, es) || !aligned(dst, es)) return fail(DGMF_INVALID, "operator_apply: misaligned vector");
+  if (overlap(src, dst, es * op->mesh->ndofs)) return fail(DGMF_INVALID, "operator_apply: src and dst overlap");
+  DeviceGuard dg(op->mesh->device);
+  const int n = op->mesh->desc.degree + 1;
+  if (dtype == DGMF_F64)
+    return launch_sipg_cart_apply<double>(n, op->g64, static_cast<const double*>(src), static_cast<double*>(dst),
+                                          op->mesh->ncells, nullptr, stream);
+  return launch_sipg_cart_apply<float>(n, op->g32, static_cast<const float*>(src), static_cast<float*>(dst),
+                                       op->mesh->ncells, nullptr, stream);
+}
+
+dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hipStream_t stream) {
+  if (!op || op->kind != 1) return fail(DGMF_INVALID, "operator_diagonal: not an SIPG operator");
+  if (!diag) return fail(DGMF_INVALID, "operator_diagonal: null vector");
+  const size_t es = dtype == DGMF_F64 ? 8 : (dtype == DGMF_F32 ? 4 : 0);
+  if (!es) return fail(DGMF_INVALID, "operator_diagonal: unknown dtype %d", static_cast<int>(dtype));
+  if (!aligned(diag, es)) return fail(DGMF_INVALID, "operator_diagonal: misaligned vector");
+  DeviceGuard dg(op->mesh->device);
+  const int n = op->mesh->desc.degree + 1;
+  if (dtype == DGMF_F64)
+    return launch_sipg_cart_diag<double>(n, op->g64, static_cast<double*>(diag), op->mesh->ncells, stream);
+  return launch_sipg_cart_diag<float>(n, op->g32, static_cast<float*>(diag), op->mesh->ncells, stream);
+}
+
+dgmf_status dgmf_quadrature_points(dgmf_op op, double* xyz, hipStream_t stream) {
+  if (!op || op->kind != 1) return fail(DGMF_INVALID, "quadrature_points: not an SIPG operator");
+  if (!xyz || !aligned(xyz, 8)) return fail(DGMF_INVALID, "quadrature_points: null or misaligned output");
+  DeviceGuard dg(op->mesh->device);
+  return launch_qp_coords(op->tab.n, op->nq, op->g64, xyz, op->mesh->ncells, stream);
+}
+
+dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_t stream) {
+  if (!op || op->kind != 1) return fail(DGMF_INVALID, "integrate: not an SIPG operator");
+  if (!f_qp || !b || !aligned(f_qp, 8) || !aligned(b, 8))
+    return fail(DGMF_INVALID, "integrate: null or misaligned vector");
+  const int64_t nq3 = static_cast<int64_t>(op->nq) * op->nq * op->nq;
+  if (overlap(f_qp, b, 8 * std::min<int64_t>(op->mesh->ndofs, op->mesh->ncells * nq3)))
+    return fail(DGMF_INVALID, "integrate: input and output overlap");
+  DeviceGuard dg(op->mesh->device);
+  return launch_integrate(op->tab.n, op->nq, op->g64, f_qp, b, op->mesh->ncells, stream);
+}
+
+dgmf_status dgmf_op_destroy(dgmf_op op) {
+  if (!op) return DGMF_OK;
+  DeviceGuard dg(op->mesh->device);
+  op->mesh->nops--;
+  delete op;
+  return DGMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Internal declarations of libdgmf (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dgmf.h"
+
+namespace dgmf {
+
+constexpr int kMinDegree = 1;
+constexpr int kMaxDegree = 7;
+constexpr int kMaxConvPoints = 12;
+
+// ---------------------------------------------------------------- errors ---
+dgmf_status fail(dgmf_status st, const char* fmt, ...);
+void clear_error();
+
+#define DGMF_HIP_TRY(expr)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::dgmf::fail(e_ == hipErrorOutOfMemory ? DGMF_OOM : DGMF_HIP_ERROR,    \
+                          "%s failed: %s", #expr, hipGetErrorString(e_));           \
+  } while (0)
+
+#define DGMF_LAUNCH_CHECK(name)                                                     \
+  do {                                                                              \
+    hipError_t e_ = hipGetLastError();                                              \
+    if (e_ != hipSuccess)                                                           \
+      return ::dgmf::fail(DGMF_HIP_ERROR, "launch of %s failed: %s", name,          \
+                          hipGetErrorString(e_));                                   \
+  } while (0)
+
+// ----------------------------------------------------------- 1D tables ---
+// Nodal basis on the Gauss-Lobatto nodes of degree k over [0,1] evaluated on
+// an nq-point Gauss rule.  Everything is computed here from the Legendre
+// three-term recurrence by Newton's method in long double.
+struct Tables1D {
+  int k = 0, n = 0, nq = 0;
+  std::vector<double> nodes;   // n GLL nodes on [0,1]
+  std::vector<double> gll_w;   // n integrals of the Lagrange polynomials
+  std::vector<double> xq, wq;  // nq Gauss points / weights on [0,1], sum w = 1
+  std::vector<double> S, D;    // nq x n: l_j(x_q), l_j'(x_q) (row q)
+  std::vector<double> Mhat;    // n x n: sum_q w_q l_i l_j  (1D reference mass)
+  std::vector<double> Khat;    // n x n: sum_q w_q l_i' l_j' (1D reference stiffness)
+  std::vector<double> g0, g1;  // n: l_j'(0), l_j'(1)
+};
+void gauss_legendre01(int nq, std::vector<double>& x, std::vector<double>& w);
+void gll_nodes01(int k, std::vector<double>& x);
+void lagrange_eval(const std::vector<double>& nodes, double x, double* val, double* der);
+void make_tables(int k, int nq, Tables1D& t);
+
+// ------------------------------------------------------ device buffers ---
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  dgmf_status alloc(size_t nbytes);
+  dgmf_status upload(const void* host, size_t nbytes);
+  void release();
+  ~DevBuf() { release(); }
+};
+
+// ------------------------------------------------------------- kernels ---
+// Geometry of an axis-aligned box mesh seen by the Cartesian kernels.  The
+// per-direction arrays are indexed by the cell coordinate along that axis.
+template <typename T>
+struct CartGeom {
+  int nx, ny, nz;
+  int per[3];
+  const T* h[3];      // cell size
+  const T* hinv[3];   // 1 / cell size
+  const T* tp[3];     // w_d / h_d: contribution of direction d to tau_e / (s (k+1)^2)
+  const T* x0[3];     // low vertex coordinate
+  T pen;              // s (k+1)^2
+  T mu, nu;           // mass and diffusion coefficients
+  const T* tab;       // Mhat[n*n], Khat[n*n], g0[n], g1[n], S[nq*n], wq[nq], xq[nq], nodes[n]
+};
+
+// Offsets into the device table of an SIPG operator.
+struct TabLayout {
+  int n, nq;
+  __host__ __device__ int mhat() const { return 0; }
+  __host__ __device__ int khat() const { return n * n; }
+  __host__ __device__ int g0() const { return 2 * n * n; }
+  __host__ __device__ int g1() const { return 2 * n * n + n; }
+  __host__ __device__ int S() const { return 2 * n * n + 2 * n; }
+  __host__ __device__ int wq() const { return S() + nq * n; }
+  __host__ __device__ int xq() const { return wq() + nq; }
+  __host__ __device__ int nodes() const { return xq() + nq; }
+  __host__ __device__ int size() const { return nodes() + n; }
+};
+
+dgmf_status launch_node_coords(int n, const CartGeom<double>& g, double* xyz, int64_t ncells, hipStream_t s);
+dgmf_status launch_qp_coords(int n, int nq, const CartGeom<double>& g, double* xyz, int64_t ncells,
+                             hipStream_t s);
+dgmf_status launch_integrate(int n, int nq, const CartGeom<double>& g, const double* f, double* b,
+                             int64_t ncells, hipStream_t s);
+
+// Operator apply; when partials is not null, also writes per-block partial
+// sums of <src, dst>, sum(dst) and sum(src) to partials[4*block + 0..2].
+template <typename T>
+dgmf_status launch_sipg_cart_apply(int n, const CartGeom<T>& g, const T* src, T* dst, int64_t ncells,
+                                   double* partials, hipStream_t s);
+template <typename T>
+dgmf_status launch_sipg_cart_diag(int n, const CartGeom<T>& g, T* diag, int64_t ncells, hipStream_t s);
+int sipg_cart_blocks(int n, int64_t ncells);
+
+}  // namespace dgmf
+
+// --------------------------------------------------------------- handles ---
+struct dgmf_mesh_ {
+  dgmf_box_desc desc{};
+  int device = 0;
+  int64_t ncells = 0, ndofs = 0;
+  std::vector<double> verts[3];
+  dgmf::DevBuf geo64, geo32;       // x0, h, 1/h, tp per direction (fp64 / fp32)
+  dgmf::CartGeom<double> g64{};    // geometry pointers (coefficients unset)
+  dgmf::CartGeom<float> g32{};
+  dgmf::Tables1D tab;              // tables with n_q = k+1
+  dgmf::DevBuf tab64;
+  int nops = 0;                    // live operators built on this mesh
+};
+
+struct dgmf_op_ {
+  int kind = 0;                    // 1 = SIPG, 2 = convective
+  dgmf_mesh mesh = nullptr;
+  dgmf_sipg_desc sipg{};
+  int nq = 0;
+  dgmf::Tables1D tab;
+  dgmf::DevBuf tab64, tab32;
+  dgmf::CartGeom<double> g64{};
+  dgmf::CartGeom<float> g32{};
+};

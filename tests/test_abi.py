@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports every entry point its header declares (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dgmf.h")
+LIB = os.path.join(ROOT, "paper_1607_01323_amd", "libdgmf.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgmf_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libdgmf.so is not built (python -m paper_1607_01323_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("dgmf_operator_apply", "dgmf_cg_solve", "dgmf_convective_apply", "dgmf_convective_vjp",
+                 "dgmf_operator_diagonal", "dgmf_mesh_create", "dgmf_sipg_create"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_invalid_arguments_are_rejected_without_a_device(lib):
+    import paper_1607_01323_amd as dg
+    d = dg.BoxDesc(0, 2, 2, 2, 1.0, 1.0, 1.0, 0.0, (ctypes.c_int * 3)(1, 1, 1), 0.0, 0)
+    h = ctypes.c_void_p()
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    assert b"degree" in dg._lib.dgmf_last_error()
+    d.degree, d.nx = 3, 0
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    d.nx, d.lx = 2, -1.0
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    assert dg._apply(None, 0, None, None, None) == dg.INVALID
+    assert dg._mesh_destroy(None) == dg.OK
+    assert dg.version() >= 100
