@@ -267,9 +267,9 @@ dgmf_status dgmf_operator_apply(dgmf_op op, dgmf_dtype dtype, const void* src, v
   const int n = op->mesh->desc.degree + 1;
   if (dtype == DGMF_F64)
     return launch_sipg_cart_apply<double>(n, op->g64, static_cast<const double*>(src), static_cast<double*>(dst),
-                                          op->mesh->ncells, nullptr, stream);
+                                          op->mesh->ncells, nullptr, nullptr, stream);
   return launch_sipg_cart_apply<float>(n, op->g32, static_cast<const float*>(src), static_cast<float*>(dst),
-                                       op->mesh->ncells, nullptr, stream);
+                                       op->mesh->ncells, nullptr, nullptr, stream);
 }
 
 dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hipStream_t stream) {

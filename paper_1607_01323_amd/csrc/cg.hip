@@ -1,0 +1,734 @@
+// Preconditioned conjugate gradients on the SIPG operator (Sec. 5.1).
+//
+// All scalars of the iteration live on the device: per-block partial sums are
+// written by the vector kernels (and by the operator apply's epilogue), a
+// single-workgroup kernel reduces them in a fixed order (deterministic) and
+// advances the recurrence, and every later kernel of the iteration reads the
+// new scalar from device memory.  A status word ends the iteration on the
+// device: once it is non-zero every remaining kernel of the batch returns at
+// once, so the host only reads the state every `check_every` iterations while
+// the iteration count stays exact.
+//
+// Preconditioners: point Jacobi (fp64), or the Chebyshev acceleration of
+// point Jacobi (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1)
+// from a zero start in fp32 or fp64, whose interval [lambda/range, lambda]
+// comes from Lanczos on D^{-1/2} H D^{-1/2} (Sec. 5.1: Chebyshev smoothing
+// with the matrix diagonal, eigenvalue estimates from a Krylov start-up).
+// Singular problems (periodic Laplacian) are solved on zero-mean vectors by
+// projecting b and every operator product (Sec. 5.1).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace dgmf {
+namespace {
+
+constexpr int RUNNING = 0, CONVERGED = 1;
+constexpr int kVecBlocks = 2048;   // grid of the vector kernels (grid-stride loops)
+constexpr int kMaxLanczos = 64;
+
+struct CgState {
+  double rz;        // <r, z>
+  double alpha, beta;
+  double mean_q;    // mean of H p when projecting
+  double rr;        // ||r||^2
+  double tol2;      // (rtol ||b||)^2
+  double bnorm2;    // ||b||^2 (projected)
+  double mean_b;    // mean of b when projecting
+  double lz_alpha[kMaxLanczos];
+  double lz_beta[kMaxLanczos];
+  double lz_tmp;
+  int iter, status, max_iter, project;
+};
+
+enum Mode { M_BSUM, M_BNORM, M_QMEAN, M_INIT, M_ALPHA, M_BETA, M_LZ_MEAN, M_LZ_NORM, M_LZ_ALPHA, M_LZ_BETA };
+
+// ------------------------------------------------------- reductions -----
+template <int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* __restrict__ partials, int blk) {
+  __shared__ double red[K][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_down(v[k], o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k][w] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) partials[4 * blk + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+}
+
+// One workgroup of 1024 threads: sums nparts partial rows in a fixed order,
+// then thread 0 advances the scalar recurrence of `mode`.
+__global__ void __launch_bounds__(1024) k_scalar(CgState* st, const double* __restrict__ partials, int nparts,
+                                                 int mode, int64_t N, int step, int stopmask) {
+  if (stopmask && st->status != RUNNING) return;
+  __shared__ double sh[4][1024];
+  double a[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nparts; b += 1024)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] += partials[4 * b + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double s0 = sh[0][0], s1 = sh[1][0], s2 = sh[2][0];
+  const double invN = 1.0 / static_cast<double>(N);
+  switch (mode) {
+    case M_BSUM:   // s0 = sum b, s1 = sum x0^2 (finiteness only)
+      st->mean_b = st->project ? s0 * invN : 0.0;
+      if (!isfinite(s0) || !isfinite(s1)) st->status = DGMF_NONFINITE;
+      break;
+    case M_BNORM:  // s0 = ||b_projected||^2
+      st->bnorm2 = s0;
+      break;
+    case M_QMEAN:  // s1 = sum(H x0)
+      st->mean_q = st->project ? s1 * invN : 0.0;
+      break;
+    case M_INIT:   // s0 = <r,z>, s1 = <r,r>
+      st->rz = s0;
+      st->rr = s1;
+      st->iter = 0;
+      if (!isfinite(s1) || !isfinite(st->bnorm2)) st->status = DGMF_NONFINITE;
+      else if (s1 <= st->tol2) st->status = CONVERGED;
+      else if (!(s0 > 0)) st->status = isfinite(s0) ? DGMF_BREAKDOWN : DGMF_NONFINITE;
+      break;
+    case M_ALPHA: {  // s0 = <p,Hp>, s1 = sum(Hp), s2 = sum(p)
+      const double mq = st->project ? s1 * invN : 0.0;
+      const double pq = s0 - (st->project ? s1 * s2 * invN : 0.0);
+      st->mean_q = mq;
+      if (!(pq > 0)) {
+        st->status = isfinite(pq) ? DGMF_BREAKDOWN : DGMF_NONFINITE;
+        break;
+      }
+      st->alpha = st->rz / pq;
+      break;
+    }
+    case M_BETA: {  // s0 = <r,z> (new), s1 = <r,r>
+      st->iter += 1;
+      st->rr = s1;
+      if (!isfinite(s1)) { st->status = DGMF_NONFINITE; break; }
+      if (s1 <= st->tol2) { st->status = CONVERGED; break; }
+      if (st->iter >= st->max_iter) { st->status = DGMF_NOT_CONVERGED; break; }
+      if (!(s0 > 0)) { st->status = isfinite(s0) ? DGMF_BREAKDOWN : DGMF_NONFINITE; break; }
+      st->beta = s0 / st->rz;
+      st->rz = s0;
+      break;
+    }
+    case M_LZ_MEAN:  // s0 = sum v
+      st->lz_tmp = st->project ? s0 * invN : 0.0;
+      break;
+    case M_LZ_NORM:  // s0 = ||v||^2
+      st->lz_tmp = 1.0 / sqrt(s0);
+      break;
+    case M_LZ_ALPHA:
+      st->lz_alpha[step] = s0;
+      break;
+    case M_LZ_BETA:
+      st->lz_beta[step] = sqrt(s0);
+      break;
+  }
+}
+
+#define GRID_STRIDE(i, N) \
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < (N); i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+
+// sum b, sum x0^2
+__global__ void __launch_bounds__(256) k_bsum(const double* __restrict__ b, const double* __restrict__ x, int64_t N,
+                                              double* partials) {
+  double v[2] = {0, 0};
+  GRID_STRIDE(i, N) {
+    v[0] += b[i];
+    v[1] += x[i] * x[i];
+  }
+  block_partials<2>(v, partials, blockIdx.x);
+}
+
+// bp = b - mean_b; ||bp||^2
+__global__ void __launch_bounds__(256) k_bproj(const double* __restrict__ b, double* __restrict__ bp, int64_t N,
+                                               const CgState* st, double* partials) {
+  const double m = st->mean_b;
+  double v[1] = {0};
+  GRID_STRIDE(i, N) {
+    const double t = b[i] - m;
+    bp[i] = t;
+    v[0] += t * t;
+  }
+  block_partials<1>(v, partials, blockIdx.x);
+}
+
+// tol2 = rtol^2 ||bp||^2 (host passes rtol^2)
+__global__ void k_set_tol(CgState* st, double rtol2, int max_iter) {
+  st->tol2 = rtol2 * st->bnorm2;
+  st->max_iter = max_iter;
+}
+
+// r = bp - (q - mean_q); optionally z = dinv r and partials <r,z>, <r,r>
+__global__ void __launch_bounds__(256) k_init_r(const double* __restrict__ bp, const double* __restrict__ q,
+                                                double* __restrict__ r, const double* __restrict__ dinv,
+                                                double* __restrict__ z, int64_t N, const CgState* st,
+                                                double* partials) {
+  if (st->status != RUNNING) return;
+  const double mq = st->mean_q;
+  double v[2] = {0, 0};
+  GRID_STRIDE(i, N) {
+    const double ri = bp[i] - (q[i] - mq);
+    r[i] = ri;
+    v[1] += ri * ri;
+    if (z) {
+      const double zi = dinv[i] * ri;
+      z[i] = zi;
+      v[0] += ri * zi;
+    }
+  }
+  block_partials<2>(v, partials, blockIdx.x);
+}
+
+// x += alpha p; r -= alpha (q - mean_q); Jacobi: z = dinv r, partials <r,z>, <r,r>
+__global__ void __launch_bounds__(256) k_update(double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ p, const double* __restrict__ q,
+                                                const double* __restrict__ dinv, double* __restrict__ z, int64_t N,
+                                                const CgState* st, double* partials) {
+  if (st->status != RUNNING) return;
+  const double a = st->alpha, mq = st->mean_q;
+  double v[2] = {0, 0};
+  GRID_STRIDE(i, N) {
+    x[i] = fma(a, p[i], x[i]);
+    const double ri = fma(-a, q[i] - mq, r[i]);
+    r[i] = ri;
+    v[1] += ri * ri;
+    if (z) {
+      const double zi = dinv[i] * ri;
+      z[i] = zi;
+      v[0] += ri * zi;
+    }
+  }
+  block_partials<2>(v, partials, blockIdx.x);
+}
+
+// p = z + beta p  (first = 1: p = z)
+__global__ void __launch_bounds__(256) k_update_p(double* __restrict__ p, const double* __restrict__ z, int64_t N,
+                                                  const CgState* st, int first) {
+  if (st->status != RUNNING) return;
+  const double b = first ? 0.0 : st->beta;
+  GRID_STRIDE(i, N) p[i] = first ? z[i] : fma(b, p[i], z[i]);
+}
+
+__global__ void __launch_bounds__(256) k_recip(const double* __restrict__ d, double* __restrict__ dinv, int64_t N) {
+  GRID_STRIDE(i, N) dinv[i] = 1.0 / d[i];
+}
+
+// ------------------------------------------------ Chebyshev (T = f32/f64) -
+template <typename T>
+__global__ void __launch_bounds__(256) k_cast_recip(const double* __restrict__ d, T* __restrict__ dinv,
+                                                    T* __restrict__ dsq, int64_t N) {
+  GRID_STRIDE(i, N) {
+    const double v = 1.0 / d[i];
+    dinv[i] = static_cast<T>(v);
+    if (dsq) dsq[i] = static_cast<T>(sqrt(v));
+  }
+}
+
+// res = T(r); d = dinv res / theta; zc = d   (degree 1: z64 = d, partial <r,z>)
+template <typename T>
+__global__ void __launch_bounds__(256) k_cheb_init(const double* __restrict__ r, T* __restrict__ res,
+                                                   T* __restrict__ d, T* __restrict__ zc, const T* __restrict__ dinv,
+                                                   T inv_theta, double* __restrict__ z64, int64_t N,
+                                                   const CgState* st, double* partials) {
+  if (st->status != RUNNING) return;
+  double v[1] = {0};
+  GRID_STRIDE(i, N) {
+    const T ri = static_cast<T>(r[i]);
+    const T di = dinv[i] * ri * inv_theta;
+    if (z64) {
+      const double zd = static_cast<double>(di);
+      z64[i] = zd;
+      v[0] += r[i] * zd;
+    } else {
+      res[i] = ri;
+      d[i] = di;
+      zc[i] = di;
+    }
+  }
+  if (z64) block_partials<1>(v, partials, blockIdx.x);
+}
+
+// res -= t; d = c1 d + c2 dinv res; zc += d  (last: z64 = zc, partial <r,z>)
+template <typename T>
+__global__ void __launch_bounds__(256) k_cheb_step(T* __restrict__ res, T* __restrict__ d, T* __restrict__ zc,
+                                                   const T* __restrict__ t, const T* __restrict__ dinv, T c1, T c2,
+                                                   const double* __restrict__ r, double* __restrict__ z64, int64_t N,
+                                                   const CgState* st, double* partials) {
+  if (st->status != RUNNING) return;
+  double v[1] = {0};
+  GRID_STRIDE(i, N) {
+    const T ri = res[i] - t[i];
+    const T di = fma(c1, d[i], c2 * dinv[i] * ri);
+    const T zi = zc[i] + di;
+    if (z64) {
+      const double zd = static_cast<double>(zi);
+      z64[i] = zd;
+      v[0] += r[i] * zd;
+    } else {
+      res[i] = ri;
+      d[i] = di;
+      zc[i] = zi;
+    }
+  }
+  if (z64) block_partials<1>(v, partials, blockIdx.x);
+}
+
+// ------------------------------------------------------------ Lanczos -----
+// SplitMix64 (Steele, Lea & Flood 2014): output i = mix(seed + (i+1) gamma),
+// mapped to [-1, 1) by its top 53 bits.
+__global__ void __launch_bounds__(256) k_splitmix_uniform(double* __restrict__ v, uint64_t seed, int64_t N,
+                                                          double* partials) {
+  double s[1] = {0};
+  GRID_STRIDE(i, N) {
+    uint64_t z = seed + static_cast<uint64_t>(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    const double u = 2.0 * static_cast<double>(z >> 11) * 0x1.0p-53 - 1.0;
+    v[i] = u;
+    s[0] += u;
+  }
+  block_partials<1>(s, partials, blockIdx.x);
+}
+
+// v64 -= mean; ||v64||^2
+__global__ void __launch_bounds__(256) k_lz_center(double* __restrict__ v, int64_t N, const CgState* st,
+                                                   double* partials) {
+  const double m = st->lz_tmp;
+  double s[1] = {0};
+  GRID_STRIDE(i, N) {
+    const double t = v[i] - m;
+    v[i] = t;
+    s[0] += t * t;
+  }
+  block_partials<1>(s, partials, blockIdx.x);
+}
+
+// v = T(v64 / ||v64||); vprev = 0
+template <typename T>
+__global__ void __launch_bounds__(256) k_lz_start(const double* __restrict__ v64, T* __restrict__ v,
+                                                  T* __restrict__ vprev, int64_t N, const CgState* st) {
+  const double s = st->lz_tmp;
+  GRID_STRIDE(i, N) {
+    v[i] = static_cast<T>(v64[i] * s);
+    vprev[i] = T(0);
+  }
+}
+
+// t = dsq v
+template <typename T>
+__global__ void __launch_bounds__(256) k_lz_scale(const T* __restrict__ v, const T* __restrict__ dsq,
+                                                  T* __restrict__ t, int64_t N) {
+  GRID_STRIDE(i, N) t[i] = dsq[i] * v[i];
+}
+
+// w = dsq w - beta_{j-1} vprev; partial <w, v>
+template <typename T>
+__global__ void __launch_bounds__(256) k_lz_w(T* __restrict__ w, const T* __restrict__ dsq, const T* __restrict__ v,
+                                              const T* __restrict__ vprev, int64_t N, const CgState* st, int step,
+                                              double* partials) {
+  const T b = step > 0 ? static_cast<T>(st->lz_beta[step - 1]) : T(0);
+  double s[1] = {0};
+  GRID_STRIDE(i, N) {
+    const T wi = fma(dsq[i], w[i], -b * vprev[i]);
+    w[i] = wi;
+    s[0] += static_cast<double>(wi) * static_cast<double>(v[i]);
+  }
+  block_partials<1>(s, partials, blockIdx.x);
+}
+
+// w -= alpha_j v; partial ||w||^2
+template <typename T>
+__global__ void __launch_bounds__(256) k_lz_orth(T* __restrict__ w, const T* __restrict__ v, int64_t N,
+                                                 const CgState* st, int step, double* partials) {
+  const T a = static_cast<T>(st->lz_alpha[step]);
+  double s[1] = {0};
+  GRID_STRIDE(i, N) {
+    const T wi = fma(-a, v[i], w[i]);
+    w[i] = wi;
+    s[0] += static_cast<double>(wi) * static_cast<double>(wi);
+  }
+  block_partials<1>(s, partials, blockIdx.x);
+}
+
+// vprev = w / beta_j  (the caller then swaps the roles of v and vprev)
+template <typename T>
+__global__ void __launch_bounds__(256) k_lz_next(const T* __restrict__ w, T* __restrict__ vprev, int64_t N,
+                                                 const CgState* st, int step) {
+  const double b = st->lz_beta[step];
+  const T s = static_cast<T>(b > 0 ? 1.0 / b : 0.0);
+  GRID_STRIDE(i, N) vprev[i] = w[i] * s;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (a, b) by bisection on the
+// Sturm sequence count (Wilkinson), bracketed by Gershgorin discs.
+double tridiag_max_eig(const double* a, const double* b, int m) {
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::fmin(lo, a[i] - r);
+    hi = std::fmax(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+      const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+      q = a[i] - x - (i > 0 ? bb / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::fmax(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= m) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+struct Layout {
+  size_t state, partials, bp, r, z, p, q, dinv, diag, v64;       // fp64 part
+  size_t cdinv, cdsq, cres, cd, czc, ct;                       // precond dtype part
+  size_t total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(int64_t N, int64_t nparts, bool cheb, size_t es) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  L.state = take(sizeof(CgState));
+  L.partials = take(sizeof(double) * 4 * nparts);
+  const size_t v8 = sizeof(double) * N;
+  L.bp = take(v8); L.r = take(v8); L.z = take(v8); L.p = take(v8); L.q = take(v8); L.dinv = take(v8);
+  L.diag = take(v8);
+  if (cheb) {
+    L.v64 = take(v8);
+    const size_t vc = es * N;
+    L.cdinv = take(vc); L.cdsq = take(vc); L.cres = take(vc); L.cd = take(vc); L.czc = take(vc); L.ct = take(vc);
+  }
+  L.total = off;
+  return L;
+}
+
+dgmf_status validate(dgmf_op op, const dgmf_cg_params* p) {
+  if (!op || op->kind != 1) return fail(DGMF_INVALID, "cg: not an SIPG operator");
+  if (!p) return fail(DGMF_INVALID, "cg: null params");
+  if (!(p->rtol >= 0) || !std::isfinite(p->rtol)) return fail(DGMF_INVALID, "cg: rtol must be finite and >= 0");
+  if (p->max_iter < 0) return fail(DGMF_INVALID, "cg: max_iter must be >= 0");
+  if (p->precond != 0 && p->precond != 1) return fail(DGMF_INVALID, "cg: precond must be 0 or 1");
+  if (p->precond == 1) {
+    if (p->precond_dtype != DGMF_F32 && p->precond_dtype != DGMF_F64)
+      return fail(DGMF_INVALID, "cg: precond_dtype must be DGMF_F32 or DGMF_F64");
+    if (p->cheb_degree < 1 || p->cheb_degree > 64) return fail(DGMF_INVALID, "cg: cheb_degree must be in 1..64");
+    if (!(p->smoothing_range > 1)) return fail(DGMF_INVALID, "cg: smoothing_range must be > 1");
+    if (p->lanczos_steps < 2 || p->lanczos_steps > kMaxLanczos)
+      return fail(DGMF_INVALID, "cg: lanczos_steps must be in 2..%d", kMaxLanczos);
+    if (!(p->lambda_safety >= 1)) return fail(DGMF_INVALID, "cg: lambda_safety must be >= 1");
+  }
+  return DGMF_OK;
+}
+
+int64_t nparts_for(dgmf_op op) {
+  const int64_t a = sipg_cart_blocks(op->mesh->desc.degree + 1, op->mesh->ncells);
+  return a > kVecBlocks ? a : kVecBlocks;
+}
+
+template <typename T>
+const CartGeom<T>& geom(dgmf_op op);
+template <>
+const CartGeom<double>& geom<double>(dgmf_op op) { return op->g64; }
+template <>
+const CartGeom<float>& geom<float>(dgmf_op op) { return op->g32; }
+
+struct Solver {
+  dgmf_op op;
+  const dgmf_cg_params& prm;
+  char* ws;
+  Layout L;
+  hipStream_t s;
+  int64_t N, nparts;
+  int n;
+  CgState* st;
+  double* partials;
+  double cheb_inv_theta = 0;
+  std::vector<double> c1, c2;
+  double lambda = 0;
+
+  template <typename V>
+  V* at(size_t off) { return reinterpret_cast<V*>(ws + off); }
+
+  dgmf_status scalar(int mode, int nblk, int step = 0, int stopmask = 1) {
+    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(1024), 0, s, st, partials, nblk, mode, N, step, stopmask);
+    DGMF_LAUNCH_CHECK("k_scalar");
+    return DGMF_OK;
+  }
+
+  template <typename T>
+  dgmf_status apply(const T* src, T* dst, bool with_partials) {
+    return launch_sipg_cart_apply<T>(n, geom<T>(op), src, dst, op->mesh->ncells, with_partials ? partials : nullptr,
+                                     &st->status, s);
+  }
+
+  // Lanczos in precision T on D^{-1/2} H D^{-1/2}; fills lambda and the Chebyshev coefficients.
+  template <typename T>
+  dgmf_status lanczos_and_coeffs() {
+    const int m = prm.lanczos_steps;
+    T* dsq = at<T>(L.cdsq);
+    T* v = at<T>(L.cres);
+    T* vp = at<T>(L.cd);
+    T* w = at<T>(L.czc);
+    T* t = at<T>(L.ct);
+    double* v64 = at<double>(L.v64);
+    const dim3 G(kVecBlocks), B(256);
+    hipLaunchKernelGGL(k_splitmix_uniform, G, B, 0, s, v64, static_cast<uint64_t>(prm.seed), N, partials);
+    DGMF_LAUNCH_CHECK("k_splitmix_uniform");
+    dgmf_status e = scalar(M_LZ_MEAN, kVecBlocks, 0, 0);
+    if (e) return e;
+    hipLaunchKernelGGL(k_lz_center, G, B, 0, s, v64, N, st, partials);
+    DGMF_LAUNCH_CHECK("k_lz_center");
+    if ((e = scalar(M_LZ_NORM, kVecBlocks, 0, 0))) return e;
+    hipLaunchKernelGGL((k_lz_start<T>), G, B, 0, s, v64, v, vp, N, st);
+    DGMF_LAUNCH_CHECK("k_lz_start");
+    for (int j = 0; j < m; ++j) {
+      hipLaunchKernelGGL((k_lz_scale<T>), G, B, 0, s, v, dsq, t, N);
+      DGMF_LAUNCH_CHECK("k_lz_scale");
+      if ((e = launch_sipg_cart_apply<T>(n, geom<T>(op), t, w, op->mesh->ncells, nullptr, nullptr, s))) return e;
+      hipLaunchKernelGGL((k_lz_w<T>), G, B, 0, s, w, dsq, v, vp, N, st, j, partials);
+      DGMF_LAUNCH_CHECK("k_lz_w");
+      if ((e = scalar(M_LZ_ALPHA, kVecBlocks, j, 0))) return e;
+      hipLaunchKernelGGL((k_lz_orth<T>), G, B, 0, s, w, v, N, st, j, partials);
+      DGMF_LAUNCH_CHECK("k_lz_orth");
+      if ((e = scalar(M_LZ_BETA, kVecBlocks, j, 0))) return e;
+      hipLaunchKernelGGL((k_lz_next<T>), G, B, 0, s, w, vp, N, st, j);
+      DGMF_LAUNCH_CHECK("k_lz_next");
+      T* tmp = v; v = vp; vp = tmp;
+    }
+    double ha[kMaxLanczos], hb[kMaxLanczos];
+    DGMF_HIP_TRY(hipMemcpyAsync(ha, st->lz_alpha, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    DGMF_HIP_TRY(hipMemcpyAsync(hb, st->lz_beta, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    DGMF_HIP_TRY(hipStreamSynchronize(s));
+    int mm = m;
+    for (int j = 0; j < m; ++j) {
+      if (!std::isfinite(ha[j])) { mm = j; break; }
+      if (j < m - 1 && !(hb[j] > 0)) { mm = j + 1; break; }
+    }
+    if (mm < 1) return fail(DGMF_NONFINITE, "cg: eigenvalue estimate is not finite");
+    const double theta = tridiag_max_eig(ha, hb, mm);
+    if (!(theta > 0) || !std::isfinite(theta)) return fail(DGMF_BREAKDOWN, "cg: eigenvalue estimate %g <= 0", theta);
+    lambda = prm.lambda_safety * theta;
+    const double a = lambda / prm.smoothing_range, b = lambda;
+    const double th = 0.5 * (a + b), de = 0.5 * (b - a), sigma = th / de;
+    cheb_inv_theta = 1.0 / th;
+    double rho = 1.0 / sigma;
+    c1.assign(prm.cheb_degree, 0.0);
+    c2.assign(prm.cheb_degree, 0.0);
+    for (int j = 1; j < prm.cheb_degree; ++j) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1[j] = rn * rho;
+      c2[j] = 2.0 * rn / de;
+      rho = rn;
+    }
+    return DGMF_OK;
+  }
+
+  // z64 = Chebyshev(r64) in precision T, with partial <r, z> in slot 0.
+  template <typename T>
+  dgmf_status cheb_apply(const double* r, double* z) {
+    const dim3 G(kVecBlocks), B(256);
+    T* dinv = at<T>(L.cdinv);
+    T* res = at<T>(L.cres);
+    T* d = at<T>(L.cd);
+    T* zc = at<T>(L.czc);
+    T* t = at<T>(L.ct);
+    const int m = prm.cheb_degree;
+    hipLaunchKernelGGL((k_cheb_init<T>), G, B, 0, s, r, res, d, zc, dinv, static_cast<T>(cheb_inv_theta),
+                       m == 1 ? z : nullptr, N, st, partials);
+    DGMF_LAUNCH_CHECK("k_cheb_init");
+    for (int j = 1; j < m; ++j) {
+      dgmf_status e = apply<T>(d, t, false);
+      if (e) return e;
+      hipLaunchKernelGGL((k_cheb_step<T>), G, B, 0, s, res, d, zc, t, dinv, static_cast<T>(c1[j]),
+                         static_cast<T>(c2[j]), r, j == m - 1 ? z : nullptr, N, st, partials);
+      DGMF_LAUNCH_CHECK("k_cheb_step");
+    }
+    return DGMF_OK;
+  }
+
+  dgmf_status precond(const double* r, double* z) {
+    if (prm.precond_dtype == DGMF_F32) return cheb_apply<float>(r, z);
+    return cheb_apply<double>(r, z);
+  }
+};
+
+}  // namespace
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" {
+
+dgmf_status dgmf_cg_workspace_bytes(dgmf_op op, const dgmf_cg_params* params, size_t* bytes) {
+  dgmf_status e = validate(op, params);
+  if (e) return e;
+  if (!bytes) return fail(DGMF_INVALID, "cg_workspace_bytes: null output");
+  const size_t es = params->precond_dtype == DGMF_F32 ? 4 : 8;
+  *bytes = make_layout(op->mesh->ndofs, nparts_for(op), params->precond == 1, es).total;
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream, dgmf_cg_result* out) {
+  dgmf_status e = validate(op, params);
+  if (e) return e;
+  if (!b || !x || !workspace || !out) return fail(DGMF_INVALID, "cg_solve: null argument");
+  if (reinterpret_cast<uintptr_t>(b) % 8 || reinterpret_cast<uintptr_t>(x) % 8 ||
+      reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(DGMF_INVALID, "cg_solve: misaligned argument (vectors 8 B, workspace 256 B)");
+  const int64_t N = op->mesh->ndofs;
+  const bool cheb = params->precond == 1;
+  const size_t es = params->precond_dtype == DGMF_F32 ? 4 : 8;
+  Layout L = make_layout(N, nparts_for(op), cheb, es);
+  if (workspace_bytes < L.total)
+    return fail(DGMF_INVALID, "cg_solve: workspace of %zu bytes, need %zu", workspace_bytes, L.total);
+  {
+    const char* wb = static_cast<const char*>(workspace);
+    const char* xb = reinterpret_cast<const char*>(x);
+    const char* bb = reinterpret_cast<const char*>(b);
+    if ((xb < wb + L.total && wb < xb + 8 * N) || (bb < wb + L.total && wb < bb + 8 * N) ||
+        (xb < bb + 8 * N && bb < xb + 8 * N))
+      return fail(DGMF_INVALID, "cg_solve: b, x and workspace must not overlap");
+  }
+  int prev_dev = -1;
+  (void)hipGetDevice(&prev_dev);
+  if (prev_dev != op->mesh->device) DGMF_HIP_TRY(hipSetDevice(op->mesh->device));
+  struct Restore {
+    int d;
+    ~Restore() { if (d >= 0) (void)hipSetDevice(d); }
+  } restore{prev_dev != op->mesh->device ? prev_dev : -1};
+
+  std::memset(out, 0, sizeof(*out));
+  out->status = DGMF_OK;
+  Solver S{op, *params, static_cast<char*>(workspace), L, stream, N, nparts_for(op), op->mesh->desc.degree + 1,
+           nullptr, nullptr};
+  S.st = S.at<CgState>(L.state);
+  S.partials = S.at<double>(L.partials);
+  double* bp = S.at<double>(L.bp);
+  double* r = S.at<double>(L.r);
+  double* z = S.at<double>(L.z);
+  double* p = S.at<double>(L.p);
+  double* q = S.at<double>(L.q);
+  double* dinv = S.at<double>(L.dinv);
+  double* diag = S.at<double>(L.diag);
+  const dim3 G(kVecBlocks), B(256);
+  const int napply = sipg_cart_blocks(S.n, op->mesh->ncells);
+  auto t0 = std::chrono::steady_clock::now();
+
+  // ---- set-up: state, diagonal, eigenvalue estimate
+  CgState init{};
+  init.project = params->project_mean ? 1 : 0;
+  init.max_iter = params->max_iter;
+  DGMF_HIP_TRY(hipMemcpyAsync(S.st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
+  if ((e = launch_sipg_cart_diag<double>(S.n, op->g64, diag, op->mesh->ncells, stream))) return e;
+  hipLaunchKernelGGL(k_recip, G, B, 0, stream, diag, dinv, N);
+  DGMF_LAUNCH_CHECK("k_recip");
+  if (cheb) {
+    if (params->precond_dtype == DGMF_F32) {
+      hipLaunchKernelGGL((k_cast_recip<float>), G, B, 0, stream, diag, S.at<float>(L.cdinv), S.at<float>(L.cdsq), N);
+      DGMF_LAUNCH_CHECK("k_cast_recip");
+      e = S.lanczos_and_coeffs<float>();
+    } else {
+      hipLaunchKernelGGL((k_cast_recip<double>), G, B, 0, stream, diag, S.at<double>(L.cdinv), S.at<double>(L.cdsq),
+                         N);
+      DGMF_LAUNCH_CHECK("k_cast_recip");
+      e = S.lanczos_and_coeffs<double>();
+    }
+    if (e) {
+      (void)hipStreamSynchronize(stream);
+      out->status = e;
+      return e;
+    }
+    out->lambda_max = S.lambda;
+  }
+  // ---- initial residual
+  hipLaunchKernelGGL(k_bsum, G, B, 0, stream, b, x, N, S.partials);
+  DGMF_LAUNCH_CHECK("k_bsum");
+  if ((e = S.scalar(M_BSUM, kVecBlocks, 0, 0))) return e;
+  hipLaunchKernelGGL(k_bproj, G, B, 0, stream, b, bp, N, S.st, S.partials);
+  DGMF_LAUNCH_CHECK("k_bproj");
+  if ((e = S.scalar(M_BNORM, kVecBlocks, 0, 0))) return e;
+  hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(1), 0, stream, S.st, params->rtol * params->rtol, params->max_iter);
+  DGMF_LAUNCH_CHECK("k_set_tol");
+  if ((e = launch_sipg_cart_apply<double>(S.n, op->g64, x, q, op->mesh->ncells, S.partials, nullptr, stream)))
+    return e;
+  if ((e = S.scalar(M_QMEAN, napply, 0, 0))) return e;
+  if (cheb) {
+    hipLaunchKernelGGL(k_init_r, G, B, 0, stream, bp, q, r, dinv, static_cast<double*>(nullptr), N, S.st,
+                       S.partials);
+    DGMF_LAUNCH_CHECK("k_init_r");
+    // <r,r> sits in slot 1 of the partials; the preconditioner writes <r,z> to slot 0
+    if ((e = S.precond(r, z))) return e;
+  } else {
+    hipLaunchKernelGGL(k_init_r, G, B, 0, stream, bp, q, r, dinv, z, N, S.st, S.partials);
+    DGMF_LAUNCH_CHECK("k_init_r");
+  }
+  if ((e = S.scalar(M_INIT, kVecBlocks))) return e;
+  hipLaunchKernelGGL(k_update_p, G, B, 0, stream, p, z, N, S.st, 1);
+  DGMF_LAUNCH_CHECK("k_update_p");
+  CgState h{};
+  DGMF_HIP_TRY(hipMemcpyAsync(&h, S.st, sizeof(h), hipMemcpyDeviceToHost, stream));
+  DGMF_HIP_TRY(hipStreamSynchronize(stream));
+  auto t1 = std::chrono::steady_clock::now();
+
+  // ---- iteration
+  const int batch = params->check_every > 0 ? params->check_every : 1;
+  while (h.status == RUNNING) {
+    for (int k = 0; k < batch; ++k) {
+      if ((e = S.apply<double>(p, q, true))) return e;
+      if ((e = S.scalar(M_ALPHA, napply))) return e;
+      hipLaunchKernelGGL(k_update, G, B, 0, stream, x, r, p, q, dinv, cheb ? static_cast<double*>(nullptr) : z, N,
+                         S.st, S.partials);
+      DGMF_LAUNCH_CHECK("k_update");
+      if (cheb && (e = S.precond(r, z))) return e;
+      if ((e = S.scalar(M_BETA, kVecBlocks))) return e;
+      hipLaunchKernelGGL(k_update_p, G, B, 0, stream, p, z, N, S.st, 0);
+      DGMF_LAUNCH_CHECK("k_update_p");
+    }
+    DGMF_HIP_TRY(hipMemcpyAsync(&h, S.st, sizeof(h), hipMemcpyDeviceToHost, stream));
+    DGMF_HIP_TRY(hipStreamSynchronize(stream));
+  }
+  auto t2 = std::chrono::steady_clock::now();
+  out->iterations = h.iter;
+  out->rel_residual = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : 0.0;
+  out->status = h.status == CONVERGED ? DGMF_OK : h.status;
+  out->setup_s = std::chrono::duration<double>(t1 - t0).count();
+  out->solve_s = std::chrono::duration<double>(t2 - t1).count();
+  if (out->status != DGMF_OK) {
+    static const char* names[] = {"OK", "INVALID", "HIP_ERROR", "OOM", "NOT_CONVERGED", "BREAKDOWN", "NONFINITE",
+                                  "UNSUPPORTED"};
+    return fail(static_cast<dgmf_status>(out->status), "cg_solve: %s after %d iterations (rel. residual %g)",
+                names[out->status], out->iterations, out->rel_residual);
+  }
+  return DGMF_OK;
+}
+
+}  // extern "C"

@@ -103,9 +103,11 @@ dgmf_status launch_integrate(int n, int nq, const CartGeom<double>& g, const dou
 
 // Operator apply; when partials is not null, also writes per-block partial
 // sums of <src, dst>, sum(dst) and sum(src) to partials[4*block + 0..2].
+// stop: optional device flag; when non-zero the launch does nothing (used by
+// CG to idle the remaining kernels of a batch once it has finished).
 template <typename T>
 dgmf_status launch_sipg_cart_apply(int n, const CartGeom<T>& g, const T* src, T* dst, int64_t ncells,
-                                   double* partials, hipStream_t s);
+                                   double* partials, const int* stop, hipStream_t s);
 template <typename T>
 dgmf_status launch_sipg_cart_diag(int n, const CartGeom<T>& g, T* diag, int64_t ncells, hipStream_t s);
 int sipg_cart_blocks(int n, int64_t ncells);

@@ -30,6 +30,17 @@
 namespace dgmf {
 namespace {
 
+// gfx950 dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with a private L2.  Remap so that every XCD walks a contiguous range of
+// cells: the face neighbours a block reads are then mostly in its own L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
+  const int64_t q = nblocks / kXcds, rem = nblocks % kXcds;
+  const int64_t x = b % kXcds, r = b / kXcds;
+  return x * q + (x < rem ? x : rem) + r;
+}
+
 template <int N>
 struct Shape {
   static constexpr int N2 = N * N;
@@ -192,7 +203,8 @@ __device__ __forceinline__ void dir_op(const CartGeom<T>& g, const T* __restrict
 template <int N, typename T>
 __global__ void __launch_bounds__(256) k_sipg_cart_apply(const T* __restrict__ src, T* __restrict__ dst,
                                                          const CartGeom<T> g, int64_t ncells,
-                                                         double* __restrict__ partials) {
+                                                         double* __restrict__ partials, const int* stop) {
+  if (stop && *stop) return;   // uniform for the whole grid: CG already finished
   using S = Shape<N>;
   constexpr int N2 = S::N2, N3 = S::N3, P = S::P, CL = S::CL, CPB = S::CPB;
   __shared__ T s_u[CPB * CL];
@@ -204,7 +216,8 @@ __global__ void __launch_bounds__(256) k_sipg_cart_apply(const T* __restrict__ s
   const int lc = tid / N2;
   const int t = tid - lc * N2;
   const int t0 = t % N, t1 = t / N;
-  const int64_t cell = static_cast<int64_t>(blockIdx.x) * CPB + lc;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t cell = blk * CPB + lc;
   const bool act = lc < CPB && cell < ncells;
   T* su = s_u + (lc < CPB ? lc : 0) * CL;
   T* sa = s_a + (lc < CPB ? lc : 0) * CL;
@@ -329,9 +342,9 @@ __global__ void __launch_bounds__(256) k_sipg_cart_apply(const T* __restrict__ s
         b += s_red[3 * k + 1];
         c += s_red[3 * k + 2];
       }
-      partials[4 * blockIdx.x] = a;
-      partials[4 * blockIdx.x + 1] = b;
-      partials[4 * blockIdx.x + 2] = c;
+      partials[4 * blk] = a;
+      partials[4 * blk + 1] = b;
+      partials[4 * blk + 2] = c;
     }
   }
 }
@@ -383,12 +396,12 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
 
 template <int N, typename T>
 dgmf_status launch_apply_n(const CartGeom<T>& g, const T* src, T* dst, int64_t ncells, double* partials,
-                           hipStream_t s) {
+                           const int* stop, hipStream_t s) {
   using S = Shape<N>;
   const int64_t blocks = (ncells + S::CPB - 1) / S::CPB;
   if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
   hipLaunchKernelGGL((k_sipg_cart_apply<N, T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                     src, dst, g, ncells, partials);
+                     src, dst, g, ncells, partials, stop);
   DGMF_LAUNCH_CHECK("k_sipg_cart_apply");
   return DGMF_OK;
 }
@@ -412,15 +425,15 @@ int sipg_cart_blocks(int n, int64_t ncells) {
 
 template <typename T>
 dgmf_status launch_sipg_cart_apply(int n, const CartGeom<T>& g, const T* src, T* dst, int64_t ncells,
-                                   double* partials, hipStream_t s) {
+                                   double* partials, const int* stop, hipStream_t s) {
   switch (n) {
-    case 2: return launch_apply_n<2, T>(g, src, dst, ncells, partials, s);
-    case 3: return launch_apply_n<3, T>(g, src, dst, ncells, partials, s);
-    case 4: return launch_apply_n<4, T>(g, src, dst, ncells, partials, s);
-    case 5: return launch_apply_n<5, T>(g, src, dst, ncells, partials, s);
-    case 6: return launch_apply_n<6, T>(g, src, dst, ncells, partials, s);
-    case 7: return launch_apply_n<7, T>(g, src, dst, ncells, partials, s);
-    case 8: return launch_apply_n<8, T>(g, src, dst, ncells, partials, s);
+    case 2: return launch_apply_n<2, T>(g, src, dst, ncells, partials, stop, s);
+    case 3: return launch_apply_n<3, T>(g, src, dst, ncells, partials, stop, s);
+    case 4: return launch_apply_n<4, T>(g, src, dst, ncells, partials, stop, s);
+    case 5: return launch_apply_n<5, T>(g, src, dst, ncells, partials, stop, s);
+    case 6: return launch_apply_n<6, T>(g, src, dst, ncells, partials, stop, s);
+    case 7: return launch_apply_n<7, T>(g, src, dst, ncells, partials, stop, s);
+    case 8: return launch_apply_n<8, T>(g, src, dst, ncells, partials, stop, s);
     default: return fail(DGMF_UNSUPPORTED, "degree %d not built", n - 1);
   }
 }
@@ -440,9 +453,9 @@ dgmf_status launch_sipg_cart_diag(int n, const CartGeom<T>& g, T* diag, int64_t 
 }
 
 template dgmf_status launch_sipg_cart_apply<double>(int, const CartGeom<double>&, const double*, double*, int64_t,
-                                                    double*, hipStream_t);
+                                                    double*, const int*, hipStream_t);
 template dgmf_status launch_sipg_cart_apply<float>(int, const CartGeom<float>&, const float*, float*, int64_t,
-                                                   double*, hipStream_t);
+                                                   double*, const int*, hipStream_t);
 template dgmf_status launch_sipg_cart_diag<double>(int, const CartGeom<double>&, double*, int64_t, hipStream_t);
 template dgmf_status launch_sipg_cart_diag<float>(int, const CartGeom<float>&, float*, int64_t, hipStream_t);
 

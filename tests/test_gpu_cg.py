@@ -1,0 +1,192 @@
+"""GPU parity of the preconditioned CG solves with the CPU oracle.
+
+Readings (shared with the oracle): convergence when ||r_k|| <= rtol ||b|| on the
+recursive residual, b projected to zero mean for the singular periodic
+Laplacian; the Chebyshev preconditioner and its interval are defined in
+oracle.solvers.  Bars: (i) true residual <= 2e-10 recomputed by the oracle;
+(ii) after a fixed 10 iterations the fp64 iterates match the oracle's to 1e-11
+relative; (iii) iteration counts equal the oracle's within 1 (fp64) or 2
+(fp32 preconditioner); (iv) distance to the exact discrete solution (fast
+diagonalisation) stated and bounded.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dgmf_inputs as inp
+from oracle import kron, mesh as omesh, rng, sipg as osipg, solvers
+from tests.gpu_util import dev, host, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(w, cells=None):
+    import paper_1607_01323_amd as dg
+    cells = cells or w.cells
+    om = omesh.BoxMesh(w.degree, *cells, lx=w.lengths[0], ly=w.lengths[1], lz=w.lengths[2], y0=w.y0,
+                       periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma)
+    oop = osipg.SIPG(om, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    gm = dg.Mesh(w.degree, *cells, *w.lengths, y0=w.y0, periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma)
+    gop = dg.SipgOperator(gm, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    return om, oop, gm, gop
+
+
+def _gauge(om, x):
+    wts = osipg.integral_weights(om)
+    return x - (wts @ x) / wts.sum()
+
+
+def test_c0_jacobi_matches_oracle():
+    require_gpu()
+    print("[case] cg jacobi c0", flush=True)
+    w = inp.POISSON_C0
+    om, oop, gm, gop = _setup(w)
+    A = oop.assemble()
+    b = oop.rhs(inp.poisson_rhs_sin3)
+    dinv = 1.0 / A.diagonal()
+    x0 = np.zeros(om.ndofs)
+    # (ii) fixed 10 iterations
+    xr, itr, st, _ = solvers.pcg(lambda v: A @ v, b, x0, lambda r: dinv * r, 1e-30, 10, project_mean=True)
+    xg = dev(x0)
+    out = gop.cg(dev(b), xg, rtol=1e-30, max_iter=10, project_mean=True, raise_on_failure=False)
+    assert out.status == 4 and out.iterations == 10
+    assert rel_err(host(xg), xr) < 1e-11
+    # full solve
+    xr, itr, st, _ = solvers.pcg(lambda v: A @ v, b, x0, lambda r: dinv * r, 1e-10, 1000, project_mean=True)
+    xg = dev(x0)
+    out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=1000, project_mean=True, check_every=4)
+    assert st == solvers.OK and out.status == 0
+    assert abs(out.iterations - itr) <= 1
+    xs = host(xg)
+    bp = b - b.mean()
+    assert np.linalg.norm(bp - A @ xs) <= 2e-10 * np.linalg.norm(bp)
+    xf = kron.KronPeriodic(w.degree, *w.cells, penalty_scale=w.penalty_scale).solve(bp)
+    assert np.linalg.norm(_gauge(om, xs) - xf) / np.linalg.norm(xf) < 1e-8
+    gm.close()
+
+
+def test_helmholtz_jacobi_random_guess():
+    require_gpu()
+    w = inp.scaled(inp.HELMHOLTZ_C1, (4, 3, 5))
+    om, oop, gm, gop = _setup(w)
+    A = oop.assemble()
+    b = oop.rhs(inp.helm_rhs(w.mass_coeff, w.diff_coeff))
+    x0 = inp.uniform(5, om.ndofs)
+    dinv = 1.0 / A.diagonal()
+    xr, itr, st, _ = solvers.pcg(lambda v: A @ v, b, x0, lambda r: dinv * r, 1e-30, 10)
+    xg = dev(x0)
+    gop.cg(dev(b), xg, rtol=1e-30, max_iter=10, raise_on_failure=False)
+    assert rel_err(host(xg), xr) < 1e-11
+    xr, itr, st, _ = solvers.pcg(lambda v: A @ v, b, x0, lambda r: dinv * r, 1e-10, 1000)
+    xg = dev(x0)
+    out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=1000)
+    assert abs(out.iterations - itr) <= 1
+    assert np.linalg.norm(b - A @ host(xg)) <= 2e-10 * np.linalg.norm(b)
+    gm.close()
+
+
+@pytest.mark.parametrize("pdtype", [torch.float64, torch.float32])
+def test_chebyshev_preconditioned_cg(pdtype):
+    require_gpu()
+    print(f"[case] cg chebyshev {pdtype}", flush=True)
+    w = inp.scaled(inp.POISSON_C2, (6, 5, 4))
+    om, oop, gm, gop = _setup(w)
+    A = oop.assemble()
+    b = oop.rhs(inp.poisson_rhs_sin3)
+    d = A.diagonal()
+    dinv = 1.0 / d
+    x0 = np.zeros(om.ndofs)
+    # oracle Lanczos from the same SplitMix64 start vector
+    v0 = rng.uniform_pm1(42, om.ndofs)
+    v0 -= v0.mean()
+    ritz, _ = solvers.lanczos_ritz(lambda v: (A @ (v / np.sqrt(d))) / np.sqrt(d), v0, 15)
+    lam_oracle = 1.2 * ritz[-1]
+    xg = dev(x0)
+    out = gop.cg(dev(b), xg, rtol=1e-30, max_iter=10, precond="chebyshev", precond_dtype=pdtype, seed=42,
+                 project_mean=True, raise_on_failure=False)
+    tol_lam = 1e-9 if pdtype == torch.float64 else 1e-3
+    assert abs(out.lambda_max - lam_oracle) < tol_lam * lam_oracle
+    lam = out.lambda_max   # the oracle runs the same preconditioner
+    P = lambda r: solvers.chebyshev_jacobi(lambda u: A @ u, dinv, r, lam, 20.0, 5)
+    xr, _, _, _ = solvers.pcg(lambda v: A @ v, b, x0, P, 1e-30, 10, project_mean=True)
+    assert rel_err(host(xg), xr) < (1e-11 if pdtype == torch.float64 else 1e-4)
+    xr, itr, st, _ = solvers.pcg(lambda v: A @ v, b, x0, P, 1e-10, 500, project_mean=True)
+    xg = dev(x0)
+    out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=500, precond="chebyshev", precond_dtype=pdtype, seed=42,
+                 project_mean=True)
+    assert abs(out.iterations - itr) <= (1 if pdtype == torch.float64 else 2)
+    xs = host(xg)
+    bp = b - b.mean()
+    assert np.linalg.norm(bp - A @ xs) <= 2e-10 * np.linalg.norm(bp)
+    gm.close()
+
+
+def test_status_codes():
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    w = inp.scaled(inp.POISSON_C0, (3, 3, 3))
+    om, oop, gm, gop = _setup(w)
+    b = oop.rhs(inp.poisson_rhs_sin3)
+    out = gop.cg(dev(b), dev(np.zeros(om.ndofs)), rtol=1e-14, max_iter=3, project_mean=True,
+                 raise_on_failure=False)
+    assert out.status == dg.NOT_CONVERGED and out.iterations == 3
+    bn = b.copy()
+    bn[7] = np.nan
+    out = gop.cg(dev(bn), dev(np.zeros(om.ndofs)), project_mean=True, raise_on_failure=False)
+    assert out.status == dg.NONFINITE and out.iterations == 0
+    with pytest.raises(dg.DgmfError):
+        gop.cg(dev(b), dev(np.zeros(om.ndofs)), precond="chebyshev", lanczos_steps=1)
+    # zero right-hand side and zero guess: converged without iterating
+    out = gop.cg(dev(np.zeros(om.ndofs)), dev(np.zeros(om.ndofs)))
+    assert out.status == 0 and out.iterations == 0
+    gm.close()
+    # penalty far below the coercivity bound: indefinite operator, CG breaks down as the oracle does
+    w2 = inp.scaled(inp.POISSON_C0, (2, 2, 2))
+    import dataclasses
+    w2 = dataclasses.replace(w2, penalty_scale=0.02)
+    om, oop, gm, gop = _setup(w2)
+    A = oop.assemble()
+    b = inp.uniform(9, om.ndofs)
+    _, itr, st, _ = solvers.pcg(lambda v: A @ v, b, np.zeros(om.ndofs), lambda r: r / A.diagonal(), 1e-10, 500)
+    out = gop.cg(dev(b), dev(np.zeros(om.ndofs)), max_iter=500, raise_on_failure=False)
+    assert st == solvers.BREAKDOWN and out.status == dg.BREAKDOWN
+    assert abs(out.iterations - itr) <= 1
+    gm.close()
+
+
+@pytest.mark.parametrize("case", ["helmholtz_c1_jacobi", "poisson_c2_mixed"])
+def test_full_size_solves(case):
+    require_gpu()
+    print(f"[case] cg full-size {case}", flush=True)
+    w = inp.HELMHOLTZ_C1 if case == "helmholtz_c1_jacobi" else inp.POISSON_C2
+    import paper_1607_01323_amd as dg
+    gm = dg.Mesh(w.degree, *w.cells, *w.lengths, periodic=w.periodic)
+    gop = dg.SipgOperator(gm, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    om = omesh.BoxMesh(w.degree, *w.cells)
+    oop = osipg.SIPG(om, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    kr = kron.KronPeriodic(w.degree, *w.cells, mass_coeff=w.mass_coeff, diff_coeff=w.diff_coeff,
+                           penalty_scale=w.penalty_scale)
+    if case == "helmholtz_c1_jacobi":
+        b = oop.rhs(inp.helm_rhs(w.mass_coeff, w.diff_coeff))
+        x0 = inp.uniform(11, om.ndofs)
+        xg = dev(x0)
+        out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=2000, check_every=16)
+        bp = b
+    else:
+        b = oop.rhs(inp.poisson_rhs_sin3)
+        xg = dev(np.zeros(om.ndofs))
+        out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=2000, check_every=8, precond="chebyshev",
+                     precond_dtype=torch.float32, project_mean=True)
+        bp = b - b.mean()
+    assert out.status == 0
+    xs = host(xg)
+    # true residual with the oracle's Kronecker-sum operator (exact same matrix)
+    assert np.linalg.norm(bp - kr.apply(xs)) <= 2e-10 * np.linalg.norm(bp)
+    xf = kr.solve(bp)
+    if case == "poisson_c2_mixed":
+        xs = xs - xs.mean()
+        xf = xf - xf.mean()
+    err = np.linalg.norm(xs - xf) / np.linalg.norm(xf)
+    print(f"[result] {case}: iterations {out.iterations}, rel. error vs exact discrete solution {err:.2e}")
+    assert err < 1e-7
+    gm.close()
