@@ -1,0 +1,196 @@
+"""Benchmark of the matrix-free DG hot path on one MI355X.
+
+Headline (``value``): fp64 SIPG Helmholtz operator applications per second
+times DoF (DoF/s) on the 32^3-cell, degree-4 periodic cube (4.096M DoF,
+H = 1000 M + 0.01 A), inputs resident in HBM.  One step is one operator
+application; the timed region is exactly ``--steps`` of them between two
+device synchronisations.  The same JSON line carries the roofline of that
+kernel (algorithmic bytes 16 B/DoF over the event-timed launch duration, the
+counter traffic when a committed profile matches the current kernel source),
+the fp32 apply, the CG time to 1e-10 (Jacobi fp64; mixed fp32-Chebyshev vs
+fp64), the convective forward + VJP throughput, and the CPU oracle timed on
+a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _events_time(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) * 1e-3 / steps
+
+
+def _traffic(kernel_key, n_launch_bytes_hint=None):
+    """HBM bytes per launch from the committed counter summary, or None if stale/missing."""
+    from paper_1607_01323_amd import profiling
+    p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_hashes", {}).get("sipg_cart.hip") != profiling.kernel_hash("sipg_cart.hip"):
+        return None
+    cal = d.get("calibration") or {}
+    f = d["fetch_kib_per_dispatch"].get(kernel_key)
+    w = d["write_kib_per_dispatch"].get(kernel_key)
+    if f is None or w is None or not cal:
+        return None
+    return f * 1024.0 * cal["fetch_factor"] + w * 1024.0 * cal["write_factor"]
+
+
+def cpu_baseline(w, budget_s=10.0):
+    """The oracle's row-restricted dense-block apply on a sample of cells, 1 thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import dgmf_inputs as inp
+    from oracle import mesh as omesh, sipg as osipg
+    with threadpool_limits(limits=1):
+        om = omesh.BoxMesh(w.degree, *w.cells, lx=w.lengths[0], ly=w.lengths[1], lz=w.lengths[2], y0=w.y0,
+                           periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma)
+        op = osipg.SIPG(om, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+        u = inp.uniform(7, om.ndofs)
+        rng = np.random.default_rng(0)
+        op.apply_cells(u, [0])            # block set-up outside the timing
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            cells = rng.integers(0, om.ncells, 256).tolist()
+            op.apply_cells(u, cells)
+            done += len(cells)
+        t = time.perf_counter() - t0
+    n3 = (w.degree + 1) ** 3
+    return {"value": done * n3 / t, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} random cells of {w.name} ({done * n3} DoF rows) through the oracle's dense-block "
+                      f"SIPG apply, {t:.1f} s, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="also run a 512 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_1607_01323_amd as dg
+    import dgmf_inputs as inp
+
+    w = inp.HELMHOLTZ_C1
+    mesh = dg.Mesh.from_workload(w)
+    op = dg.SipgOperator(mesh, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    N = mesh.ndofs
+    u = torch.as_tensor(inp.uniform(7, N), device="cuda")
+    y = torch.empty_like(u)
+    t = _events_time(lambda: op.apply(u, y), args.steps, args.warmup)
+    value = N / t
+    alg_bytes = 16.0 * N
+    achieved = alg_bytes / t / 1e9
+    traffic = _traffic("k_sipg_cart_apply<5, double>")
+    line = {
+        "metric": "SIPG apply DoF/s (fp64, Helmholtz)", "value": value, "unit": "DoF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "cells": list(w.cells), "degree": w.degree, "dofs": N,
+                   "mass_coeff": w.mass_coeff, "diff_coeff": w.diff_coeff, "penalty_scale": w.penalty_scale},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sipg_cart_apply<5, double>", "alg_bytes_per_launch": alg_bytes},
+    }
+    if args.calibrate_copy:
+        a = torch.empty(512 * 2 ** 20 // 8, dtype=torch.float64, device="cuda").uniform_()
+        b_ = torch.empty_like(a)
+        for _ in range(3):
+            b_.copy_(a)
+        torch.cuda.synchronize()
+        del a, b_
+    if not args.no_extra:
+        line["extra"] = extra_measurements(dg, inp, torch, mesh, op, u, t)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
+    ex = {}
+    N = mesh_c1.ndofs
+    u32 = u_c1.float()
+    y32 = torch.empty_like(u32)
+    t32 = _events_time(lambda: op_c1.apply(u32, y32), 100, 5)
+    ex["c1_apply_f32"] = {"dofs_per_s": N / t32, "alg_GBps": 8.0 * N / t32 / 1e9, "us": t32 * 1e6}
+    ex["c1_apply_f64"] = {"dofs_per_s": N / t_c1, "alg_GBps": 16.0 * N / t_c1 / 1e9, "us": t_c1 * 1e6}
+    # CG on C1: Jacobi fp64 from a random guess, b = (f, phi) through the library's quadrature
+    qp = op_c1.quadrature_points()
+    f = inp.helm_rhs(inp.HELMHOLTZ_C1.mass_coeff, inp.HELMHOLTZ_C1.diff_coeff)
+    fq = torch.as_tensor(f(*[qp[i].cpu().numpy() for i in range(3)]), device="cuda")
+    b = op_c1.integrate(fq)
+    x = torch.as_tensor(inp.uniform(11, N), device="cuda")
+    t0 = time.perf_counter()
+    out = op_c1.cg(b, x, rtol=1e-10, max_iter=5000, check_every=16)
+    torch.cuda.synchronize()
+    ex["c1_cg_jacobi_f64"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
+                              "setup_s": out.setup_s, "solve_s": out.solve_s, "rel_residual": out.rel_residual}
+    # C2: fp64 and fp32 apply, mixed vs fp64 CG to 1e-10
+    w2 = inp.POISSON_C2
+    m2 = dg.Mesh.from_workload(w2)
+    op2 = dg.SipgOperator(m2, w2.mass_coeff, w2.diff_coeff, w2.penalty_scale)
+    N2 = m2.ndofs
+    v = torch.as_tensor(inp.uniform(3, N2), device="cuda")
+    yv = torch.empty_like(v)
+    ta = _events_time(lambda: op2.apply(v, yv), 50, 5)
+    v32 = v.float()
+    yv32 = torch.empty_like(v32)
+    tb = _events_time(lambda: op2.apply(v32, yv32), 50, 5)
+    ex["c2_apply_f64"] = {"dofs_per_s": N2 / ta, "alg_GBps": 16.0 * N2 / ta / 1e9, "us": ta * 1e6,
+                          "hbm_frac": 16.0 * N2 / ta / 1e9 / HBM_PEAK_GBS}
+    ex["c2_apply_f32"] = {"dofs_per_s": N2 / tb, "alg_GBps": 8.0 * N2 / tb / 1e9, "us": tb * 1e6,
+                          "hbm_frac": 8.0 * N2 / tb / 1e9 / HBM_PEAK_GBS}
+    qp = op2.quadrature_points()
+    fq = torch.as_tensor(inp.poisson_rhs_sin3(*[qp[i].cpu().numpy() for i in range(3)]), device="cuda")
+    del qp
+    b2 = op2.integrate(fq)
+    del fq
+    for name, kw in (("c2_cg_mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
+                     ("c2_cg_f64cheb", dict(precond="chebyshev", precond_dtype=torch.float64)),
+                     ("c2_cg_jacobi_f64", dict(precond="jacobi"))):
+        best = None
+        for _ in range(2):
+            x2 = torch.zeros(N2, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = op2.cg(b2, x2, rtol=1e-10, max_iter=20000, check_every=16, project_mean=True, seed=42, **kw)
+            torch.cuda.synchronize()
+            tt = time.perf_counter() - t0
+            if best is None or tt < best["time_s"]:
+                best = {"time_s": tt, "iterations": out.iterations, "setup_s": out.setup_s, "solve_s": out.solve_s,
+                        "rel_residual": out.rel_residual, "lambda_max": out.lambda_max}
+        ex[name] = best
+    m2.close()
+    return ex
+
+
+if __name__ == "__main__":
+    main()
