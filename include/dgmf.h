@@ -138,7 +138,9 @@ dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_
  * products and updates stay fp64 (mixed precision).  project_mean = 1
  * projects b and every operator product onto zero-mean vectors (singular
  * periodic Laplacian).  check_every: iterations between host reads of the
- * convergence flag (the iteration count is exact regardless). */
+ * convergence flag (the iteration count is exact regardless).  flexible
+ * selects the Polak-Ribiere beta (flexible CG, Notay 2000), which tolerates
+ * the slight non-linearity of a preconditioner evaluated in fp32. */
 typedef struct {
   double rtol;
   int max_iter;
@@ -151,6 +153,8 @@ typedef struct {
   double lambda_safety;  /* >= 1 */
   uint64_t seed;
   int project_mean;
+  int flexible;          /* 0: beta = <r+,z+>/<r,z> (Fletcher-Reeves); 1: beta = <z+, r+ - r>/<r,z>
+                            (Polak-Ribiere, flexible CG: robust to the rounding of an fp32 preconditioner) */
 } dgmf_cg_params;
 
 typedef struct {

@@ -22,8 +22,11 @@ import numpy as np
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 4, 5, 6
 
 
-def pcg(apply, b, x0, precond, rtol, max_iter, project_mean=False, record=None):
+def pcg(apply, b, x0, precond, rtol, max_iter, project_mean=False, record=None, flexible=False):
     """Preconditioned CG (Hestenes-Stiefel form with Fletcher-Reeves beta).
+
+    flexible=True uses beta = <z_new, r_new - r_old>/<z_old, r_old> (Polak-Ribiere,
+    the flexible CG of Notay, SIAM J. Sci. Comput. 22, 2000).
 
     Returns (x, iterations, status, rel_residual).  ``record`` (a list) gets
     the iterate after every iteration when given.
@@ -57,6 +60,7 @@ def pcg(apply, b, x0, precond, rtol, max_iter, project_mean=False, record=None):
             return x, it - 1, (NONFINITE if not np.isfinite(pq) else BREAKDOWN), rnorm / bnorm
         alpha = rz / pq
         x = x + alpha * p
+        r_old = r
         r = r - alpha * q
         rnorm = np.sqrt(r @ r)
         if record is not None:
@@ -67,7 +71,7 @@ def pcg(apply, b, x0, precond, rtol, max_iter, project_mean=False, record=None):
             return x, it, OK, rnorm / bnorm
         z = precond(r)
         rz_new = r @ z
-        beta = rz_new / rz
+        beta = (z @ (r - r_old)) / rz if flexible else rz_new / rz
         rz = rz_new
         p = z + beta * p
     return x, max_iter, NOT_CONVERGED, rnorm / bnorm

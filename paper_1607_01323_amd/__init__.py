@@ -43,7 +43,8 @@ class CgParams(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("precond", ctypes.c_int), ("precond_dtype", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("smoothing_range", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
-                ("lambda_safety", ctypes.c_double), ("seed", ctypes.c_uint64), ("project_mean", ctypes.c_int)]
+                ("lambda_safety", ctypes.c_double), ("seed", ctypes.c_uint64), ("project_mean", ctypes.c_int),
+                ("flexible", ctypes.c_int)]
 
 
 class CgResult(ctypes.Structure):
@@ -205,10 +206,17 @@ class SipgOperator(_Op):
 
     def cg(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, precond="jacobi", precond_dtype=torch.float64,
            cheb_degree=5, smoothing_range=20.0, lanczos_steps=15, lambda_safety=1.2, seed=0, project_mean=False,
-           raise_on_failure=True):
+           flexible=None, raise_on_failure=True):
+        """PCG on H x = b; x (fp64, device) holds the initial guess and receives the solution.
+
+        flexible=None picks the Polak-Ribiere (flexible) beta exactly when the
+        preconditioner runs in fp32.
+        """
+        if flexible is None:
+            flexible = precond != "jacobi" and precond_dtype == torch.float32
         p = CgParams(rtol, max_iter, check_every, 0 if precond == "jacobi" else 1,
                      F64 if precond_dtype == torch.float64 else F32, cheb_degree, smoothing_range, lanczos_steps,
-                     lambda_safety, seed, int(bool(project_mean)))
+                     lambda_safety, seed, int(bool(project_mean)), int(bool(flexible)))
         nbytes = ctypes.c_size_t()
         _check(_ws_bytes(self._h, ctypes.byref(p), ctypes.byref(nbytes)), "cg_workspace_bytes")
         ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device="cuda")

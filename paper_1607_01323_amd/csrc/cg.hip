@@ -40,7 +40,7 @@ struct CgState {
   double lz_alpha[kMaxLanczos];
   double lz_beta[kMaxLanczos];
   double lz_tmp;
-  int iter, status, max_iter, project;
+  int iter, status, max_iter, project, flexible;
 };
 
 enum Mode { M_BSUM, M_BNORM, M_QMEAN, M_INIT, M_ALPHA, M_BETA, M_LZ_MEAN, M_LZ_NORM, M_LZ_ALPHA, M_LZ_BETA };
@@ -61,6 +61,7 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* __restric
   if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < K; ++k) partials[4 * blk + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+  __syncthreads();
 }
 
 // One workgroup of 1024 threads: sums nparts partial rows in a fixed order,
@@ -115,14 +116,15 @@ __global__ void __launch_bounds__(1024) k_scalar(CgState* st, const double* __re
       st->alpha = st->rz / pq;
       break;
     }
-    case M_BETA: {  // s0 = <r,z> (new), s1 = <r,r>
+    case M_BETA: {  // s0 = <r,z> (new), s1 = <r,r>, s2 = <z, q - mean_q>
       st->iter += 1;
       st->rr = s1;
       if (!isfinite(s1)) { st->status = DGMF_NONFINITE; break; }
       if (s1 <= st->tol2) { st->status = CONVERGED; break; }
       if (st->iter >= st->max_iter) { st->status = DGMF_NOT_CONVERGED; break; }
       if (!(s0 > 0)) { st->status = isfinite(s0) ? DGMF_BREAKDOWN : DGMF_NONFINITE; break; }
-      st->beta = s0 / st->rz;
+      // Polak-Ribiere: <z+, r+ - r> = -alpha <z+, q~> since r+ = r - alpha q~
+      st->beta = st->flexible ? -st->alpha * s2 / st->rz : s0 / st->rz;
       st->rz = s0;
       break;
     }
@@ -195,26 +197,29 @@ __global__ void __launch_bounds__(256) k_init_r(const double* __restrict__ bp, c
   block_partials<2>(v, partials, blockIdx.x);
 }
 
-// x += alpha p; r -= alpha (q - mean_q); Jacobi: z = dinv r, partials <r,z>, <r,r>
+// x += alpha p; r -= alpha (q - mean_q); Jacobi: z = dinv r and partials
+// <r,z>, <r,r>, <z, q - mean_q> (the last for the flexible beta)
 __global__ void __launch_bounds__(256) k_update(double* __restrict__ x, double* __restrict__ r,
                                                 const double* __restrict__ p, const double* __restrict__ q,
                                                 const double* __restrict__ dinv, double* __restrict__ z, int64_t N,
                                                 const CgState* st, double* partials) {
   if (st->status != RUNNING) return;
   const double a = st->alpha, mq = st->mean_q;
-  double v[2] = {0, 0};
+  double v[3] = {0, 0, 0};
   GRID_STRIDE(i, N) {
     x[i] = fma(a, p[i], x[i]);
-    const double ri = fma(-a, q[i] - mq, r[i]);
+    const double qi = q[i] - mq;
+    const double ri = fma(-a, qi, r[i]);
     r[i] = ri;
     v[1] += ri * ri;
     if (z) {
       const double zi = dinv[i] * ri;
       z[i] = zi;
       v[0] += ri * zi;
+      v[2] += zi * qi;
     }
   }
-  block_partials<2>(v, partials, blockIdx.x);
+  if (z) block_partials<3>(v, partials, blockIdx.x);
 }
 
 // p = z + beta p  (first = 1: p = z)
@@ -240,38 +245,50 @@ __global__ void __launch_bounds__(256) k_cast_recip(const double* __restrict__ d
   }
 }
 
-// res = T(r); d = dinv res / theta; zc = d   (degree 1: z64 = d, partial <r,z>)
+// When the preconditioner's last kernel writes z64 it also writes the partials
+// <r,z>, <r,r>, <z, q - mean_q> (q = null at the initial residual).
+__device__ __forceinline__ void final_terms(double (&v)[3], double ri, double zi, const double* __restrict__ q,
+                                            int64_t i, double mq) {
+  v[0] += ri * zi;
+  v[1] += ri * ri;
+  if (q) v[2] += zi * (q[i] - mq);
+}
+
+// res = T(r); d = dinv res / theta; zc = d   (degree 1: z64 = d directly)
 template <typename T>
 __global__ void __launch_bounds__(256) k_cheb_init(const double* __restrict__ r, T* __restrict__ res,
                                                    T* __restrict__ d, T* __restrict__ zc, const T* __restrict__ dinv,
-                                                   T inv_theta, double* __restrict__ z64, int64_t N,
-                                                   const CgState* st, double* partials) {
+                                                   T inv_theta, double* __restrict__ z64, const double* __restrict__ q,
+                                                   int64_t N, const CgState* st, double* partials) {
   if (st->status != RUNNING) return;
-  double v[1] = {0};
+  const double mq = st->mean_q;
+  double v[3] = {0, 0, 0};
   GRID_STRIDE(i, N) {
     const T ri = static_cast<T>(r[i]);
     const T di = dinv[i] * ri * inv_theta;
     if (z64) {
       const double zd = static_cast<double>(di);
       z64[i] = zd;
-      v[0] += r[i] * zd;
+      final_terms(v, r[i], zd, q, i, mq);
     } else {
       res[i] = ri;
       d[i] = di;
       zc[i] = di;
     }
   }
-  if (z64) block_partials<1>(v, partials, blockIdx.x);
+  if (z64) block_partials<3>(v, partials, blockIdx.x);
 }
 
-// res -= t; d = c1 d + c2 dinv res; zc += d  (last: z64 = zc, partial <r,z>)
+// res -= t; d = c1 d + c2 dinv res; zc += d  (last step: z64 = zc)
 template <typename T>
 __global__ void __launch_bounds__(256) k_cheb_step(T* __restrict__ res, T* __restrict__ d, T* __restrict__ zc,
                                                    const T* __restrict__ t, const T* __restrict__ dinv, T c1, T c2,
-                                                   const double* __restrict__ r, double* __restrict__ z64, int64_t N,
-                                                   const CgState* st, double* partials) {
+                                                   const double* __restrict__ r, double* __restrict__ z64,
+                                                   const double* __restrict__ q, int64_t N, const CgState* st,
+                                                   double* partials) {
   if (st->status != RUNNING) return;
-  double v[1] = {0};
+  const double mq = st->mean_q;
+  double v[3] = {0, 0, 0};
   GRID_STRIDE(i, N) {
     const T ri = res[i] - t[i];
     const T di = fma(c1, d[i], c2 * dinv[i] * ri);
@@ -279,14 +296,14 @@ __global__ void __launch_bounds__(256) k_cheb_step(T* __restrict__ res, T* __res
     if (z64) {
       const double zd = static_cast<double>(zi);
       z64[i] = zd;
-      v[0] += r[i] * zd;
+      final_terms(v, r[i], zd, q, i, mq);
     } else {
       res[i] = ri;
       d[i] = di;
       zc[i] = zi;
     }
   }
-  if (z64) block_partials<1>(v, partials, blockIdx.x);
+  if (z64) block_partials<3>(v, partials, blockIdx.x);
 }
 
 // ------------------------------------------------------------ Lanczos -----
@@ -550,9 +567,9 @@ struct Solver {
     return DGMF_OK;
   }
 
-  // z64 = Chebyshev(r64) in precision T, with partial <r, z> in slot 0.
+  // z64 = Chebyshev(r64) in precision T, with partials <r,z>, <r,r>, <z, q~>.
   template <typename T>
-  dgmf_status cheb_apply(const double* r, double* z) {
+  dgmf_status cheb_apply(const double* r, double* z, const double* q) {
     const dim3 G(kVecBlocks), B(256);
     T* dinv = at<T>(L.cdinv);
     T* res = at<T>(L.cres);
@@ -561,21 +578,21 @@ struct Solver {
     T* t = at<T>(L.ct);
     const int m = prm.cheb_degree;
     hipLaunchKernelGGL((k_cheb_init<T>), G, B, 0, s, r, res, d, zc, dinv, static_cast<T>(cheb_inv_theta),
-                       m == 1 ? z : nullptr, N, st, partials);
+                       m == 1 ? z : nullptr, q, N, st, partials);
     DGMF_LAUNCH_CHECK("k_cheb_init");
     for (int j = 1; j < m; ++j) {
       dgmf_status e = apply<T>(d, t, false);
       if (e) return e;
       hipLaunchKernelGGL((k_cheb_step<T>), G, B, 0, s, res, d, zc, t, dinv, static_cast<T>(c1[j]),
-                         static_cast<T>(c2[j]), r, j == m - 1 ? z : nullptr, N, st, partials);
+                         static_cast<T>(c2[j]), r, j == m - 1 ? z : nullptr, q, N, st, partials);
       DGMF_LAUNCH_CHECK("k_cheb_step");
     }
     return DGMF_OK;
   }
 
-  dgmf_status precond(const double* r, double* z) {
-    if (prm.precond_dtype == DGMF_F32) return cheb_apply<float>(r, z);
-    return cheb_apply<double>(r, z);
+  dgmf_status precond(const double* r, double* z, const double* q) {
+    if (prm.precond_dtype == DGMF_F32) return cheb_apply<float>(r, z, q);
+    return cheb_apply<double>(r, z, q);
   }
 };
 
@@ -646,6 +663,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
   // ---- set-up: state, diagonal, eigenvalue estimate
   CgState init{};
   init.project = params->project_mean ? 1 : 0;
+  init.flexible = params->flexible ? 1 : 0;
   init.max_iter = params->max_iter;
   DGMF_HIP_TRY(hipMemcpyAsync(S.st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
   if ((e = launch_sipg_cart_diag<double>(S.n, op->g64, diag, op->mesh->ncells, stream))) return e;
@@ -685,8 +703,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
     hipLaunchKernelGGL(k_init_r, G, B, 0, stream, bp, q, r, dinv, static_cast<double*>(nullptr), N, S.st,
                        S.partials);
     DGMF_LAUNCH_CHECK("k_init_r");
-    // <r,r> sits in slot 1 of the partials; the preconditioner writes <r,z> to slot 0
-    if ((e = S.precond(r, z))) return e;
+    if ((e = S.precond(r, z, nullptr))) return e;
   } else {
     hipLaunchKernelGGL(k_init_r, G, B, 0, stream, bp, q, r, dinv, z, N, S.st, S.partials);
     DGMF_LAUNCH_CHECK("k_init_r");
@@ -708,7 +725,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
       hipLaunchKernelGGL(k_update, G, B, 0, stream, x, r, p, q, dinv, cheb ? static_cast<double*>(nullptr) : z, N,
                          S.st, S.partials);
       DGMF_LAUNCH_CHECK("k_update");
-      if (cheb && (e = S.precond(r, z))) return e;
+      if (cheb && (e = S.precond(r, z, q))) return e;
       if ((e = S.scalar(M_BETA, kVecBlocks))) return e;
       hipLaunchKernelGGL(k_update_p, G, B, 0, stream, p, z, N, S.st, 0);
       DGMF_LAUNCH_CHECK("k_update_p");

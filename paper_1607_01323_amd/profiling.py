@@ -26,8 +26,8 @@ def kernel_hash(name):
 
 
 def short_name(k):
-    k = k.split("(")[0]
-    return k.replace("void ", "").replace("dgmf::(anonymous namespace)::", "")
+    k = k.replace("void ", "").replace("dgmf::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    return k.split("(")[0]
 
 
 def stats_table(csv_path, out_md, cmd):
@@ -51,12 +51,16 @@ def _per_kernel(csv_path, counter):
 def pmc_summary(fetch_csv, write_csv, out_json, cmd_fetch, cmd_write, copy_bytes):
     f = _per_kernel(fetch_csv, "FETCH_SIZE")
     w = _per_kernel(write_csv, "WRITE_SIZE")
-    copy = [k for k in f if "copyBuffer" in k or "copy" in k.lower()]
+    # calibration kernels of known traffic: torch's uniform_ fill writes copy_bytes,
+    # torch's sum reads copy_bytes (the largest dispatch of each kind)
+    kr = [k for k in f if "reduce" in k.lower()]
+    f = {k: max(v, 0.0) for k, v in f.items()}
+    kw_ = [k for k in w if "distribution" in k.lower()]
     cal = {}
-    if copy:
-        kf = max(copy, key=lambda k: f[k])
-        kw = max([k for k in w if k in copy] or [kf], key=lambda k: w.get(k, 0))
-        cal = {"copy_kernel": kf, "copy_bytes": copy_bytes,
+    if kr and kw_:
+        kf = max(kr, key=lambda k: f[k])
+        kw = max(kw_, key=lambda k: w[k])
+        cal = {"read_kernel": kf, "write_kernel": kw, "bytes": copy_bytes,
                "fetch_factor": copy_bytes / (f[kf] * 1024.0), "write_factor": copy_bytes / (w[kw] * 1024.0)}
     out = {"fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w, "calibration": cal,
            "kernel_hashes": {s: kernel_hash(s) for s in KERNEL_SOURCES},

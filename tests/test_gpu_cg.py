@@ -108,9 +108,10 @@ def test_chebyshev_preconditioned_cg(pdtype):
     assert abs(out.lambda_max - lam_oracle) < tol_lam * lam_oracle
     lam = out.lambda_max   # the oracle runs the same preconditioner
     P = lambda r: solvers.chebyshev_jacobi(lambda u: A @ u, dinv, r, lam, 20.0, 5)
-    xr, _, _, _ = solvers.pcg(lambda v: A @ v, b, x0, P, 1e-30, 10, project_mean=True)
+    flex = pdtype == torch.float32          # the binding's default: flexible beta with an fp32 preconditioner
+    xr, _, _, _ = solvers.pcg(lambda v: A @ v, b, x0, P, 1e-30, 10, project_mean=True, flexible=flex)
     assert rel_err(host(xg), xr) < (1e-11 if pdtype == torch.float64 else 1e-4)
-    xr, itr, st, _ = solvers.pcg(lambda v: A @ v, b, x0, P, 1e-10, 500, project_mean=True)
+    xr, itr, st, _ = solvers.pcg(lambda v: A @ v, b, x0, P, 1e-10, 500, project_mean=True, flexible=flex)
     xg = dev(x0)
     out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=500, precond="chebyshev", precond_dtype=pdtype, seed=42,
                  project_mean=True)
@@ -118,6 +119,21 @@ def test_chebyshev_preconditioned_cg(pdtype):
     xs = host(xg)
     bp = b - b.mean()
     assert np.linalg.norm(bp - A @ xs) <= 2e-10 * np.linalg.norm(bp)
+    gm.close()
+
+
+def test_flexible_beta_matches_oracle_fp64():
+    require_gpu()
+    w = inp.scaled(inp.HELMHOLTZ_C1, (3, 4, 3))
+    om, oop, gm, gop = _setup(w)
+    A = oop.assemble()
+    b = oop.rhs(inp.helm_rhs(w.mass_coeff, w.diff_coeff))
+    x0 = inp.uniform(21, om.ndofs)
+    dinv = 1.0 / A.diagonal()
+    xr, _, _, _ = solvers.pcg(lambda v: A @ v, b, x0, lambda r: dinv * r, 1e-30, 10, flexible=True)
+    xg = dev(x0)
+    gop.cg(dev(b), xg, rtol=1e-30, max_iter=10, flexible=True, raise_on_failure=False)
+    assert rel_err(host(xg), xr) < 1e-11
     gm.close()
 
 

@@ -103,3 +103,13 @@ def test_chebyshev_operator_is_symmetric():
     x, y = g.standard_normal(m.ndofs), g.standard_normal(m.ndofs)
     P = lambda r: solvers.chebyshev_jacobi(lambda u: A @ u, dinv, r, 2.0, 20.0, 5)
     assert abs(x @ P(y) - P(x) @ y) < 1e-12 * abs(x @ P(y))
+
+
+def test_flexible_beta_equals_standard_with_linear_preconditioner(c0):
+    m, op, A, b, kr = c0
+    dinv = 1.0 / A.diagonal()
+    xa, ia, _, _ = solvers.pcg(lambda v: A @ v, b, np.zeros_like(b), lambda r: dinv * r, 1e-10, 500, project_mean=True)
+    xb, ib, _, _ = solvers.pcg(lambda v: A @ v, b, np.zeros_like(b), lambda r: dinv * r, 1e-10, 500, project_mean=True,
+                               flexible=True)
+    assert ia == ib
+    assert np.linalg.norm(xa - xb) < 1e-9 * np.linalg.norm(xa)
