@@ -193,6 +193,25 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
                             "solve_s": out.solve_s, "rel_residual": out.rel_residual, "lambda_max": out.lambda_max}
             ex[f"c2_cg_{rhs_name}_{name}"] = best
     m2.close()
+    # convective forward + VJP on the 32^3-cell degree-5 periodic cube (n_q = 9)
+    w3 = inp.CONVECTIVE_C3
+    m3 = dg.Mesh.from_workload(w3)
+    op3 = dg.ConvectiveOperator(m3, n_q=w3.conv_points)
+    X = m3.node_coords()
+    two_pi = 2 * 3.141592653589793
+    U = torch.stack([torch.sin(two_pi * X[0]) * torch.cos(two_pi * X[1]) * torch.cos(two_pi * X[2]),
+                     -torch.cos(two_pi * X[0]) * torch.sin(two_pi * X[1]) * torch.cos(two_pi * X[2]),
+                     torch.zeros_like(X[0])]).reshape(-1)
+    U += 0.01 * torch.as_tensor(inp.uniform(5, 3 * m3.ndofs), device="cuda")
+    Wc = torch.as_tensor(inp.uniform(8, 3 * m3.ndofs), device="cuda")
+    Cout = torch.empty_like(U)
+    Gout = torch.empty_like(U)
+    tf = _events_time(lambda: op3.apply(U, Cout), 20, 3)
+    tv = _events_time(lambda: op3.vjp(U, Wc, Gout), 20, 3)
+    n3 = 3 * m3.ndofs
+    ex["c3_convective"] = {"fwd_us": tf * 1e6, "vjp_us": tv * 1e6, "fwd_dofs_per_s": n3 / tf, "vjp_dofs_per_s": n3 / tv,
+                           "fwd_plus_vjp_dofs_per_s": n3 / (tf + tv), "dofs": n3}
+    m3.close()
     return ex
 
 

@@ -312,3 +312,68 @@ dgmf_status dgmf_op_destroy(dgmf_op op) {
 }
 
 }  // extern "C"
+
+extern "C" {
+
+dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, dgmf_op* out) {
+  if (!mesh || !desc || !out) return fail(DGMF_INVALID, "convective_create: null argument");
+  const int k = mesh->desc.degree, n = k + 1;
+  const int nq = desc->n_q > 0 ? desc->n_q : (3 * (k + 1)) / 2;
+  if (desc->n_q < 0) return fail(DGMF_INVALID, "convective_create: n_q must be >= 0");
+  if (!conv_supported(n, nq))
+    return fail(DGMF_UNSUPPORTED, "convective_create: degree %d with %d points per direction not built", k, nq);
+  DeviceGuard dg(mesh->device);
+  auto* op = new (std::nothrow) dgmf_op_;
+  if (!op) return fail(DGMF_OOM, "convective_create: host allocation failed");
+  op->kind = 2;
+  op->mesh = mesh;
+  op->nq = nq;
+  make_tables(k, nq, op->tab);
+  std::vector<double> h;
+  h.insert(h.end(), op->tab.S.begin(), op->tab.S.end());
+  h.insert(h.end(), op->tab.D.begin(), op->tab.D.end());
+  h.insert(h.end(), op->tab.wq.begin(), op->tab.wq.end());
+  dgmf_status st = op->ctab.upload(h.data(), h.size() * sizeof(double));
+  if (st != DGMF_OK) {
+    delete op;
+    return st;
+  }
+  ConvGeom& g = op->cgeo;
+  g.nx = mesh->g64.nx;
+  g.ny = mesh->g64.ny;
+  g.nz = mesh->g64.nz;
+  for (int d = 0; d < 3; ++d) {
+    g.per[d] = mesh->g64.per[d];
+    g.h[d] = mesh->g64.h[d];
+    g.hinv[d] = mesh->g64.hinv[d];
+  }
+  g.tab = static_cast<const double*>(op->ctab.p);
+  g.S = 0;
+  g.D = nq * n;
+  g.w = 2 * nq * n;
+  mesh->nops++;
+  *out = op;
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_convective_apply(dgmf_op op, const double* u, double* out, hipStream_t stream) {
+  if (!op || op->kind != 2) return fail(DGMF_INVALID, "convective_apply: not a convective operator");
+  if (!u || !out || !aligned(u, 8) || !aligned(out, 8))
+    return fail(DGMF_INVALID, "convective_apply: null or misaligned vector");
+  if (overlap(u, out, 24 * op->mesh->ndofs)) return fail(DGMF_INVALID, "convective_apply: u and out overlap");
+  DeviceGuard dg(op->mesh->device);
+  return launch_conv_fwd(op->tab.n, op->nq, op->cgeo, u, out, op->mesh->ncells, stream);
+}
+
+dgmf_status dgmf_convective_vjp(dgmf_op op, const double* u, const double* w, double* grad, hipStream_t stream) {
+  if (!op || op->kind != 2) return fail(DGMF_INVALID, "convective_vjp: not a convective operator");
+  if (!u || !w || !grad || !aligned(u, 8) || !aligned(w, 8) || !aligned(grad, 8))
+    return fail(DGMF_INVALID, "convective_vjp: null or misaligned vector");
+  const size_t bytes = 24 * op->mesh->ndofs;
+  if (overlap(u, grad, bytes) || overlap(w, grad, bytes))
+    return fail(DGMF_INVALID, "convective_vjp: grad overlaps u or w");
+  DeviceGuard dg(op->mesh->device);
+  return launch_conv_vjp(op->tab.n, op->nq, op->cgeo, u, w, grad, op->mesh->ncells, stream);
+}
+
+}  // extern "C"

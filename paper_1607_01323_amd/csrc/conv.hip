@@ -1,0 +1,678 @@
+// Convective operator with the local Lax-Friedrichs flux and its
+// vector-Jacobian product, on axis-aligned hexahedra (gfx950).
+//
+// C(U)_{i,a} = - sum_K (d_b phi_i, u_a u_b)_K + sum_K (phi_i, R_a)_{dK}      (Sec. 3.2, eq. convstepspat)
+//   R = 1/2 (u- (u-.n) + u+ (u+.n)) + lam (u- - u+),  lam = max(|u-.n|, |u+.n|)
+// evaluated at every face quadrature point; Dirichlet faces use the mirror
+// state u+ = -u- (no-slip, g = 0).  Quadrature: Q Gauss points per direction
+// on cells and faces (Sec. 5 over-integration).
+//
+// VJP (transpose of the exact derivative of C, piecewise quadratic in U):
+//   cell: g_c = -(phi, sum_b u_b d_b w_c + sum_a u_a d_c w_a)_K
+//   face with L on the low side, n = +e_d, [w] = w_L - w_R:
+//     g_L += phi J-^T [w],  g_R += phi J+^T [w],
+//     J-^T v = 1/2 (a v + n (u-.v)) + lam v + dlam- ((u- - u+).v)
+//     J+^T v = 1/2 (b v + n (u+.v)) - lam v + dlam+ ((u- - u+).v)
+//     a = u-.n, b = u+.n, dlam- = sgn(a) n if |a| >= |b| else 0, dlam+ = sgn(b) n otherwise
+//   Dirichlet face: g += phi (J- - J+)^T w- with u+ = -u-.
+//
+// Kernel layout: one cell per workgroup.  Thread (qx, qy) owns the z-column
+// of quadrature points of its (qx, qy) in registers (values, fluxes, VJP
+// accumulators); sweeps along x and y are staged through LDS with one thread
+// per line; faces are processed one direction (or one face) at a time and
+// their lifts land on the cell's boundary node planes before a single
+// coalesced store.
+#include "internal.h"
+
+namespace dgmf {
+namespace {
+
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_cell(int64_t b, int64_t nblocks) {
+  const int64_t q = nblocks / kXcds, rem = nblocks % kXcds;
+  const int64_t x = b % kXcds, r = b / kXcds;
+  return x * q + (x < rem ? x : rem) + r;
+}
+
+template <int N, int Q>
+struct CShape {
+  static constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
+  static constexpr int THREADS = ((Q2 + 63) / 64) * 64;
+};
+
+struct CellGeo {
+  int c[3];
+  double h[3], hinv[3];
+};
+
+__device__ __forceinline__ void conv_cell(const ConvGeom& g, int64_t cell, CellGeo& cg) {
+  cg.c[0] = static_cast<int>(cell % g.nx);
+  const int64_t r = cell / g.nx;
+  cg.c[1] = static_cast<int>(r % g.ny);
+  cg.c[2] = static_cast<int>(r / g.ny);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    cg.h[d] = g.h[d][cg.c[d]];
+    cg.hinv[d] = g.hinv[d][cg.c[d]];
+  }
+}
+
+// neighbour across face (d, s) or -1 on a Dirichlet face
+__device__ __forceinline__ int64_t conv_nb(const ConvGeom& g, const CellGeo& cg, int64_t cell, int d, int s) {
+  const int nd = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+  int cc = cg.c[d] + (s ? 1 : -1);
+  if (cc < 0 || cc >= nd) {
+    if (!g.per[d]) return -1;
+    cc = cc < 0 ? nd - 1 : 0;
+  }
+  const int64_t stride = d == 0 ? 1 : (d == 1 ? g.nx : static_cast<int64_t>(g.nx) * g.ny);
+  return cell + static_cast<int64_t>(cc - cg.c[d]) * stride;
+}
+
+// node index (l, j, i) of a face-plane entry (p1 along t1, p2 along t2) of face (d, s)
+template <int N>
+__device__ __forceinline__ int face_node(int d, int s, int p1, int p2) {
+  const int e = s ? N - 1 : 0;
+  if (d == 0) return (p2 * N + p1) * N + e;        // t1 = y, t2 = z
+  if (d == 1) return (p2 * N + e) * N + p1;        // t1 = x, t2 = z
+  return (e * N + p2) * N + p1;                    // t1 = x, t2 = y
+}
+
+// Interpolate three nodal fields sIn[3][N^3] to the quadrature z-column of
+// this thread: out[a][qz].  T1 (3*N*N*Q) and T2 (3*N*Q*Q) are LDS scratch.
+template <int N, int Q>
+__device__ __forceinline__ void interp3(const double* __restrict__ S, const double* sIn, double* T1, double* T2,
+                                        int tid, int nthr, bool own, int qx, int qy, double (&out)[3][Q]) {
+  constexpr int N2 = N * N;
+  for (int job = tid; job < 3 * N2; job += nthr) {      // x: (a, l, j)
+    const double* in = sIn + job * N;
+    double v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = in[i];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double s = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) s = fma(S[q * N + i], v[i], s);
+      T1[job * Q + q] = s;
+    }
+  }
+  __syncthreads();
+  for (int job = tid; job < 3 * N * Q; job += nthr) {  // y: (a, l, qx)
+    const int qxx = job % Q, al = job / Q;
+    double v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = T1[(al * N + j) * Q + qxx];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s = fma(S[q * N + j], v[j], s);
+      T2[(al * Q + q) * Q + qxx] = s;
+    }
+  }
+  __syncthreads();
+  if (own) {                                            // z: registers
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double v[N];
+#pragma unroll
+      for (int l = 0; l < N; ++l) v[l] = T2[((a * N + l) * Q + qy) * Q + qx];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        double s = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(S[q * N + l], v[l], s);
+        out[a][q] = s;
+      }
+    }
+  }
+}
+
+// Tangential interpolation of `np` face planes (N x N, index [p2][p1]) to
+// Q x Q points ([q2][q1]); F1 (np*N*Q) scratch, F2 (np*Q*Q) result.
+template <int N, int Q>
+__device__ __forceinline__ void face_interp(const double* __restrict__ S, const double* P, double* F1, double* F2,
+                                            int np, int tid, int nthr) {
+  for (int job = tid; job < np * N; job += nthr) {     // along t1: (plane, p2)
+    double v[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) v[p] = P[job * N + p];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double s = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) s = fma(S[q * N + p], v[p], s);
+      F1[job * Q + q] = s;
+    }
+  }
+  __syncthreads();
+  for (int job = tid; job < np * Q; job += nthr) {     // along t2: (plane, q1)
+    const int q1 = job % Q, pl = job / Q;
+    double v[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) v[p] = F1[(pl * N + p) * Q + q1];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double s = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) s = fma(S[q * N + p], v[p], s);
+      F2[(pl * Q + q) * Q + q1] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Transposed tangential interpolation of `np` planes R ([q2][q1]) and
+// accumulation into sO at the face nodes: sO[comp][node(p1,p2)] += sum.
+// Plane pl belongs to face fsel[pl] (d, s) and component comp[pl].
+template <int N, int Q>
+__device__ __forceinline__ void face_lift(const double* __restrict__ S, const double* R, double* L1, double* sO,
+                                          int np, int d, const int* s_of, const int* comp_of, int tid, int nthr) {
+  constexpr int N3 = N * N * N;
+  for (int job = tid; job < np * Q; job += nthr) {     // along t2: [q2][q1] -> [p2][q1]
+    const int q1 = job % Q, pl = job / Q;
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = R[(pl * Q + q) * Q + q1];
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      double s = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s = fma(S[q * N + p], v[q], s);
+      L1[(pl * N + p) * Q + q1] = s;
+    }
+  }
+  __syncthreads();
+  for (int job = tid; job < np * N; job += nthr) {     // along t1: [p2][q1] -> [p2][p1]
+    const int p2 = job % N, pl = job / N;
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = L1[(pl * N + p2) * Q + q];
+    double* o = sO + comp_of[pl] * N3;
+#pragma unroll
+    for (int p1 = 0; p1 < N; ++p1) {
+      double s = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s = fma(S[q * N + p1], v[q], s);
+      o[face_node<N>(d, s_of[pl], p1, p2)] += s;
+    }
+  }
+  __syncthreads();
+}
+
+// Load the face plane (d, s) of cell `c` (3 components) from global memory.
+template <int N>
+__device__ __forceinline__ void load_plane(const double* __restrict__ U, int64_t Nd, int64_t c, int d, int s,
+                                           double* P, int tid, int nthr) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  for (int e = tid; e < 3 * N2; e += nthr) {
+    const int a = e / N2, r = e % N2;
+    P[e] = U[a * Nd + c * N3 + face_node<N>(d, s, r % N, r / N)];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void copy_plane(const double* sIn, int d, int s, double* P, double scale, int tid,
+                                           int nthr) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  for (int e = tid; e < 3 * N2; e += nthr) {
+    const int a = e / N2, r = e % N2;
+    P[e] = scale * sIn[a * N3 + face_node<N>(d, s, r % N, r / N)];
+  }
+}
+
+// ---------------------------------------------------------------- forward
+template <int N, int Q>
+__global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const double* __restrict__ U,
+                                                                    double* __restrict__ C, const ConvGeom g,
+                                                                    int64_t ncells) {
+  using SH = CShape<N, Q>;
+  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2;
+  constexpr int XR = (3 * N2 * Q + 3 * N * Q2) > (3 * N * Q2 + 2 * N2 * Q) ? (3 * N2 * Q + 3 * N * Q2)
+                                                                              : (3 * N * Q2 + 2 * N2 * Q);
+  constexpr int XF = 12 * N2 + 12 * N * Q + 12 * Q2 + 6 * Q2;   // planes, stage, traces, fluxes
+  constexpr int X = XR > XF ? XR : XF;
+  __shared__ double sU[3 * N3];
+  __shared__ double sO[3 * N3];
+  __shared__ double sX[X];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
+  if (cell >= ncells) return;
+  const int64_t Nd = ncells * N3;
+  const double* S = g.tab + g.S;
+  const double* D = g.tab + g.D;
+  const double* w = g.tab + g.w;
+  CellGeo cg;
+  conv_cell(g, cell, cg);
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int a = e / N3, r = e % N3;
+    sU[e] = U[a * Nd + cell * N3 + r];
+    sO[e] = 0.0;
+  }
+  __syncthreads();
+  const bool own = tid < Q2;
+  const int qx = tid % Q, qy = (tid / Q) % Q;
+  double u[3][Q];
+  interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
+  __syncthreads();
+  // cell term: for each a, A1 = Sz^T F_ax, A2 = Sz^T F_ay, A3 = Dz^T F_az  (z-columns in registers),
+  // then B1 = Sy^T A1, B23 = Dy^T A2 + Sy^T A3, out = -(Dx^T B1 + Sx^T B23)
+  const double vol = cg.h[0] * cg.h[1] * cg.h[2];
+  double* A = sX;                 // 3 * N*Q*Q  ([m][l][qy][qx])
+  double* B = sX + 3 * N * Q2;    // 2 * N*N*Q  ([m][l][j][qx])
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    if (own) {
+      double acc[3][N];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int l = 0; l < N; ++l) acc[m][l] = 0.0;
+      const double wxy = w[qx] * w[qy] * vol;
+#pragma unroll
+      for (int qz = 0; qz < Q; ++qz) {
+        const double f = wxy * w[qz] * u[a][qz];
+        const double fx = f * u[0][qz] * cg.hinv[0];
+        const double fy = f * u[1][qz] * cg.hinv[1];
+        const double fz = f * u[2][qz] * cg.hinv[2];
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          acc[0][l] = fma(S[qz * N + l], fx, acc[0][l]);
+          acc[1][l] = fma(S[qz * N + l], fy, acc[1][l]);
+          acc[2][l] = fma(D[qz * N + l], fz, acc[2][l]);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int l = 0; l < N; ++l) A[((m * N + l) * Q + qy) * Q + qx] = acc[m][l];
+    }
+    __syncthreads();
+    for (int job = tid; job < N * Q; job += nthr) {     // y: (l, qx)
+      const int qxx = job % Q, l = job / Q;
+      double v1[Q], v2[Q], v3[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        v1[q] = A[((0 * N + l) * Q + q) * Q + qxx];
+        v2[q] = A[((1 * N + l) * Q + q) * Q + qxx];
+        v3[q] = A[((2 * N + l) * Q + q) * Q + qxx];
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        double b1 = 0, b23 = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          b1 = fma(S[q * N + j], v1[q], b1);
+          b23 = fma(D[q * N + j], v2[q], fma(S[q * N + j], v3[q], b23));
+        }
+        B[(l * N + j) * Q + qxx] = b1;
+        B[N2 * Q + (l * N + j) * Q + qxx] = b23;
+      }
+    }
+    __syncthreads();
+    for (int job = tid; job < N2; job += nthr) {        // x: (l, j)
+      double v1[Q], v2[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        v1[q] = B[job * Q + q];
+        v2[q] = B[N2 * Q + job * Q + q];
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double s = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s = fma(D[q * N + i], v1[q], fma(S[q * N + i], v2[q], s));
+        sO[a * N3 + job * N + i] = -s;
+      }
+    }
+    __syncthreads();
+  }
+  // faces, one direction at a time (the two faces of a direction touch disjoint node planes)
+#pragma unroll 1
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const double area = cg.h[t1] * cg.h[t2];
+    double* P = sX;                   // 12 planes of N*N: [face s][side m][comp]
+    double* F1 = sX + 12 * N2;        // 12 * N*Q
+    double* F2 = F1 + 12 * N * Q;     // 12 * Q*Q
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      copy_plane<N>(sU, d, s, P + (s * 2 + 0) * 3 * N2, 1.0, tid, nthr);
+      const int64_t nb = conv_nb(g, cg, cell, d, s);
+      if (nb >= 0) load_plane<N>(U, Nd, nb, d, 1 - s, P + (s * 2 + 1) * 3 * N2, tid, nthr);
+      else copy_plane<N>(sU, d, s, P + (s * 2 + 1) * 3 * N2, -1.0, tid, nthr);   // mirror u+ = -u-
+    }
+    __syncthreads();
+    // P occupies the front of sX; interpolate into F1/F2 (disjoint)
+    face_interp<N, Q>(S, P, F1, F2, 12, tid, nthr);
+    double* R = F2 + 12 * Q2;         // 6 planes of Q*Q: [face s][comp]
+    for (int e = tid; e < 2 * Q2; e += nthr) {
+      const int s = e / Q2, pq = e % Q2;
+      const double wt = w[pq % Q] * w[pq / Q] * area;
+      // own state and exterior state at this face point, outward normal sign
+      const double sg = s ? 1.0 : -1.0;
+      double um[3], up[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        um[a] = F2[((s * 2 + 0) * 3 + a) * Q2 + pq];
+        up[a] = F2[((s * 2 + 1) * 3 + a) * Q2 + pq];
+      }
+      const double an = sg * um[d], bn = sg * up[d];
+      const double lam = fmax(fabs(an), fabs(bn));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) R[(s * 3 + a) * Q2 + pq] = wt * (0.5 * (um[a] * an + up[a] * bn) + lam * (um[a] - up[a]));
+    }
+    __syncthreads();
+    const int s_of[6] = {0, 0, 0, 1, 1, 1};
+    const int comp_of[6] = {0, 1, 2, 0, 1, 2};
+    face_lift<N, Q>(S, R, F1, sO, 6, d, s_of, comp_of, tid, nthr);
+  }
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int a = e / N3, r = e % N3;
+    C[a * Nd + cell * N3 + r] = sO[e];
+  }
+}
+
+// -------------------------------------------------------------------- VJP
+template <int N, int Q>
+__global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const double* __restrict__ U,
+                                                                    const double* __restrict__ W,
+                                                                    double* __restrict__ G, const ConvGeom g,
+                                                                    int64_t ncells) {
+  using SH = CShape<N, Q>;
+  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2;
+  constexpr int XI = 3 * N2 * Q + 3 * N * Q2;          // interp3 scratch
+  constexpr int XD = 2 * N2 * Q + 3 * N * Q2;          // gradient scratch
+  constexpr int XF = 12 * N2 + 12 * N * Q + 12 * Q2 + 3 * Q2;   // one face: 12 planes + fluxes
+  constexpr int X = XI > XD ? (XI > XF ? XI : XF) : (XD > XF ? XD : XF);
+  __shared__ double sU[3 * N3];
+  __shared__ double sW[3 * N3];
+  __shared__ double sO[3 * N3];
+  __shared__ double sX[X];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
+  if (cell >= ncells) return;
+  const int64_t Nd = ncells * N3;
+  const double* S = g.tab + g.S;
+  const double* D = g.tab + g.D;
+  const double* w = g.tab + g.w;
+  CellGeo cg;
+  conv_cell(g, cell, cg);
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int a = e / N3, r = e % N3;
+    sU[e] = U[a * Nd + cell * N3 + r];
+    sW[e] = W[a * Nd + cell * N3 + r];
+    sO[e] = 0.0;
+  }
+  __syncthreads();
+  const bool own = tid < Q2;
+  const int qx = tid % Q, qy = (tid / Q) % Q;
+  double u[3][Q];
+  interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
+  __syncthreads();
+  double t[3][Q];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) t[a][q] = 0.0;
+  double* T1 = sX;                  // [Sx w | Dx w] : 2 * N*N*Q, layout [m][l][j][qx]
+  double* T2 = sX + 2 * N2 * Q;     // [SySx | DySx | SyDx] : 3 * N*Q*Q, layout [m][l][qy][qx]
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    const double* wa = sW + a * N3;
+    for (int job = tid; job < N2; job += nthr) {        // x: (l, j)
+      double v[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = wa[job * N + i];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        double s0 = 0, s1 = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          s0 = fma(S[q * N + i], v[i], s0);
+          s1 = fma(D[q * N + i], v[i], s1);
+        }
+        T1[job * Q + q] = s0;
+        T1[N2 * Q + job * Q + q] = s1;
+      }
+    }
+    __syncthreads();
+    for (int job = tid; job < N * Q; job += nthr) {     // y: (l, qx)
+      const int qxx = job % Q, l = job / Q;
+      double v0[N], v1[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        v0[j] = T1[(l * N + j) * Q + qxx];
+        v1[j] = T1[N2 * Q + (l * N + j) * Q + qxx];
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        double ss = 0, ds = 0, sd = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          ss = fma(S[q * N + j], v0[j], ss);
+          ds = fma(D[q * N + j], v0[j], ds);
+          sd = fma(S[q * N + j], v1[j], sd);
+        }
+        T2[((0 * N + l) * Q + q) * Q + qxx] = ss;
+        T2[((1 * N + l) * Q + q) * Q + qxx] = ds;
+        T2[((2 * N + l) * Q + q) * Q + qxx] = sd;
+      }
+    }
+    __syncthreads();
+    if (own) {                                          // z: gradient of w_a on this column
+      double v0[N], v1[N], v2[N];
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        v0[l] = T2[((0 * N + l) * Q + qy) * Q + qx];
+        v1[l] = T2[((1 * N + l) * Q + qy) * Q + qx];
+        v2[l] = T2[((2 * N + l) * Q + qy) * Q + qx];
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        double gz = 0, gy = 0, gx = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          gz = fma(D[q * N + l], v0[l], gz);
+          gy = fma(S[q * N + l], v1[l], gy);
+          gx = fma(S[q * N + l], v2[l], gx);
+        }
+        gx *= cg.hinv[0];
+        gy *= cg.hinv[1];
+        gz *= cg.hinv[2];
+        // t_a += u . grad w_a ;  t_b += u_a d_b w_a
+        t[a][q] = fma(u[0][q], gx, fma(u[1][q], gy, fma(u[2][q], gz, t[a][q])));
+        t[0][q] = fma(u[a][q], gx, t[0][q]);
+        t[1][q] = fma(u[a][q], gy, t[1][q]);
+        t[2][q] = fma(u[a][q], gz, t[2][q]);
+      }
+    }
+    __syncthreads();
+  }
+  // g_c = -(S x S x S)^T (w vol t_c): z in registers, then y and x through LDS
+  const double vol = cg.h[0] * cg.h[1] * cg.h[2];
+  double* Z = sX;                   // 3 * N*Q*Q  [c][l][qy][qx]
+  double* Y = sX + 3 * N * Q2;      // 3 * N*N*Q  [c][l][j][qx]
+  if (own) {
+    const double wxy = w[qx] * w[qy] * vol;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double acc[N];
+#pragma unroll
+      for (int l = 0; l < N; ++l) acc[l] = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const double f = wxy * w[q] * t[c][q];
+#pragma unroll
+        for (int l = 0; l < N; ++l) acc[l] = fma(S[q * N + l], f, acc[l]);
+      }
+#pragma unroll
+      for (int l = 0; l < N; ++l) Z[((c * N + l) * Q + qy) * Q + qx] = acc[l];
+    }
+  }
+  __syncthreads();
+  for (int job = tid; job < 3 * N * Q; job += nthr) {   // y: (c, l, qx)
+    const int qxx = job % Q, cl = job / Q;
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = Z[(cl * Q + q) * Q + qxx];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double s = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s = fma(S[q * N + j], v[q], s);
+      Y[(cl * N + j) * Q + qxx] = s;
+    }
+  }
+  __syncthreads();
+  for (int job = tid; job < 3 * N2; job += nthr) {      // x: (c, l, j)
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = Y[job * Q + q];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double s = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s = fma(S[q * N + i], v[q], s);
+      sO[job * N + i] = -s;
+    }
+  }
+  __syncthreads();
+  // faces, one at a time: 12 planes = [u own, u ext, w own, w ext] x 3 components
+#pragma unroll 1
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, s = f & 1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const double area = cg.h[t1] * cg.h[t2];
+    double* P = sX;
+    double* F1 = sX + 12 * N2;
+    double* F2 = F1 + 12 * N * Q;
+    const int64_t nb = conv_nb(g, cg, cell, d, s);
+    copy_plane<N>(sU, d, s, P + 0 * 3 * N2, 1.0, tid, nthr);
+    copy_plane<N>(sW, d, s, P + 2 * 3 * N2, 1.0, tid, nthr);
+    if (nb >= 0) {
+      load_plane<N>(U, Nd, nb, d, 1 - s, P + 1 * 3 * N2, tid, nthr);
+      load_plane<N>(W, Nd, nb, d, 1 - s, P + 3 * 3 * N2, tid, nthr);
+    } else {
+      copy_plane<N>(sU, d, s, P + 1 * 3 * N2, -1.0, tid, nthr);
+    }
+    __syncthreads();
+    face_interp<N, Q>(S, P, F1, F2, nb >= 0 ? 12 : 9, tid, nthr);
+    double* R = F2 + 12 * Q2;       // 3 planes of Q*Q
+    for (int pq = tid; pq < Q2; pq += nthr) {
+      const double wt = w[pq % Q] * w[pq / Q] * area;
+      double uo[3], ue[3], wo[3], we[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        uo[a] = F2[(0 * 3 + a) * Q2 + pq];
+        ue[a] = F2[(1 * 3 + a) * Q2 + pq];
+        wo[a] = F2[(2 * 3 + a) * Q2 + pq];
+        we[a] = nb >= 0 ? F2[(3 * 3 + a) * Q2 + pq] : 0.0;
+      }
+      double res[3];
+      if (nb >= 0) {
+        // orient with the low cell as the minus side, n = +e_d
+        const double* um = s ? uo : ue;
+        const double* up = s ? ue : uo;
+        double jw[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) jw[a] = s ? (wo[a] - we[a]) : (we[a] - wo[a]);
+        const double an = um[d], bn = up[d];
+        const double lam = fmax(fabs(an), fabs(bn));
+        const bool mact = fabs(an) >= fabs(bn);
+        const double dj = (um[0] - up[0]) * jw[0] + (um[1] - up[1]) * jw[1] + (um[2] - up[2]) * jw[2];
+        if (s) {   // this cell is the minus side: J-^T [w]
+          const double ujw = um[0] * jw[0] + um[1] * jw[1] + um[2] * jw[2];
+          const double dl = mact ? (an > 0 ? 1.0 : (an < 0 ? -1.0 : 0.0)) : 0.0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) res[a] = 0.5 * an * jw[a] + lam * jw[a];
+          res[d] += 0.5 * ujw + dl * dj;
+        } else {   // this cell is the plus side: J+^T [w]
+          const double ujw = up[0] * jw[0] + up[1] * jw[1] + up[2] * jw[2];
+          const double dl = mact ? 0.0 : (bn > 0 ? 1.0 : (bn < 0 ? -1.0 : 0.0));
+#pragma unroll
+          for (int a = 0; a < 3; ++a) res[a] = 0.5 * bn * jw[a] - lam * jw[a];
+          res[d] += 0.5 * ujw + dl * dj;
+        }
+      } else {
+        // Dirichlet: (J- - J+)^T w- with u+ = -u-, outward normal sg e_d
+        const double sg = s ? 1.0 : -1.0;
+        const double an = sg * uo[d], bn = sg * ue[d];
+        const double lam = fmax(fabs(an), fabs(bn));
+        const bool mact = fabs(an) >= fabs(bn);
+        const double dj = (uo[0] - ue[0]) * wo[0] + (uo[1] - ue[1]) * wo[1] + (uo[2] - ue[2]) * wo[2];
+        const double ujm = uo[0] * wo[0] + uo[1] * wo[1] + uo[2] * wo[2];
+        const double ujp = ue[0] * wo[0] + ue[1] * wo[1] + ue[2] * wo[2];
+        const double sa = an > 0 ? 1.0 : (an < 0 ? -1.0 : 0.0);
+        const double sb = bn > 0 ? 1.0 : (bn < 0 ? -1.0 : 0.0);
+        const double dlm = mact ? sa : 0.0, dlp = mact ? 0.0 : sb;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) res[a] = 0.5 * (an - bn) * wo[a] + 2.0 * lam * wo[a];
+        res[d] += sg * (0.5 * (ujm - ujp) + (dlm - dlp) * dj);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) R[a * Q2 + pq] = wt * res[a];
+    }
+    __syncthreads();
+    const int s_of[3] = {s, s, s};
+    const int comp_of[3] = {0, 1, 2};
+    face_lift<N, Q>(S, R, F1, sO, 3, d, s_of, comp_of, tid, nthr);
+  }
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int a = e / N3, r = e % N3;
+    G[a * Nd + cell * N3 + r] = sO[e];
+  }
+}
+
+template <int N, int Q>
+dgmf_status launch_fwd_nq(const ConvGeom& g, const double* U, double* C, int64_t ncells, hipStream_t s) {
+  if (ncells > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
+  hipLaunchKernelGGL((k_conv_fwd<N, Q>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0, s, U,
+                     C, g, ncells);
+  DGMF_LAUNCH_CHECK("k_conv_fwd");
+  return DGMF_OK;
+}
+
+template <int N, int Q>
+dgmf_status launch_vjp_nq(const ConvGeom& g, const double* U, const double* W, double* G, int64_t ncells,
+                          hipStream_t s) {
+  if (ncells > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
+  hipLaunchKernelGGL((k_conv_vjp<N, Q>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0, s, U,
+                     W, G, g, ncells);
+  DGMF_LAUNCH_CHECK("k_conv_vjp");
+  return DGMF_OK;
+}
+
+}  // namespace
+
+// Supported (n, n_q): the paper's floor(3k/2)+1 and floor(3(k+1)/2) for k = 1..6
+// (k = 7 would need more than 64 KiB of LDS per workgroup in this layout).
+#define DGMF_CONV_CASES(X) \
+  X(2, 2) X(2, 3) X(3, 4) X(4, 5) X(4, 6) X(5, 7) X(6, 8) X(6, 9) X(7, 10) X(7, 11)
+
+bool conv_supported(int n, int nq) {
+#define X(a, b) if (n == a && nq == b) return true;
+  DGMF_CONV_CASES(X)
+#undef X
+  return false;
+}
+
+dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, double* C, int64_t ncells,
+                            hipStream_t s) {
+#define X(a, b) if (n == a && nq == b) return launch_fwd_nq<a, b>(g, U, C, ncells, s);
+  DGMF_CONV_CASES(X)
+#undef X
+  return fail(DGMF_UNSUPPORTED, "convective: (n, n_q) = (%d, %d) not built", n, nq);
+}
+
+dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
+                            int64_t ncells, hipStream_t s) {
+#define X(a, b) if (n == a && nq == b) return launch_vjp_nq<a, b>(g, U, W, G, ncells, s);
+  DGMF_CONV_CASES(X)
+#undef X
+  return fail(DGMF_UNSUPPORTED, "convective: (n, n_q) = (%d, %d) not built", n, nq);
+}
+
+}  // namespace dgmf

@@ -16,6 +16,15 @@ constexpr int kMinDegree = 1;
 constexpr int kMaxDegree = 7;
 constexpr int kMaxConvPoints = 12;
 
+struct ConvGeom {
+  int nx, ny, nz;
+  int per[3];
+  const double* h[3];
+  const double* hinv[3];
+  const double* tab;   // S[nq*n], D[nq*n], w[nq]
+  int S, D, w;         // offsets into tab
+};
+
 // ---------------------------------------------------------------- errors ---
 dgmf_status fail(dgmf_status st, const char* fmt, ...);
 void clear_error();
@@ -112,6 +121,12 @@ template <typename T>
 dgmf_status launch_sipg_cart_diag(int n, const CartGeom<T>& g, T* diag, int64_t ncells, hipStream_t s);
 int sipg_cart_blocks(int n, int64_t ncells);
 
+bool conv_supported(int n, int nq);
+dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, double* C, int64_t ncells,
+                            hipStream_t s);
+dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
+                            int64_t ncells, hipStream_t s);
+
 }  // namespace dgmf
 
 // --------------------------------------------------------------- handles ---
@@ -137,4 +152,6 @@ struct dgmf_op_ {
   dgmf::DevBuf tab64, tab32;
   dgmf::CartGeom<double> g64{};
   dgmf::CartGeom<float> g32{};
+  dgmf::DevBuf ctab;               // convective tables
+  dgmf::ConvGeom cgeo{};
 };

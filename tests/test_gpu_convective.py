@@ -1,0 +1,185 @@
+"""GPU parity of the convective operator and its VJP with the CPU oracle.
+
+Bars: forward and VJP within 1e-12 relative (max norm) of the oracle on small
+meshes (every entry) and on sampled cells of the full 32^3-cell degree-5
+workload and the 48x32x48 channel; central differences (eps = 1e-6) of
+<w, C(U)> along 20 random directions agree with <VJP(U, w), d> to 1e-6;
+the autograd Function returns the VJP.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import dgmf_inputs as inp
+from oracle import convective as oconv, mesh as omesh
+from tests.gpu_util import dev, host, rel_err, require_gpu, sample_cells
+
+pytestmark = pytest.mark.gpu
+
+SMALL = {
+    # name: (k, cells, lengths, y0, periodic, gamma, nq)
+    "k1_q2": (1, (3, 2, 2), (1, 1, 1), 0, (1, 1, 1), 0, 2),
+    "k1_q3": (1, (2, 3, 2), (1, 1, 1), 0, (1, 1, 1), 0, 3),
+    "k2_q4": (2, (3, 2, 2), (1, 1.2, 0.9), 0, (1, 1, 1), 0, 4),
+    "k3_q5": (3, (2, 2, 3), (1, 1, 1), 0, (1, 1, 1), 0, 5),
+    "k3_q6": (3, (2, 2, 2), (1, 1, 1), 0, (1, 1, 1), 0, 6),
+    "k4_channel_q7": (4, (2, 3, 2), (2 * math.pi, 2, math.pi), -1, (1, 0, 1), 1.8, 7),
+    "k5_q8": (5, (2, 2, 2), (1, 1, 1), 0, (1, 1, 1), 0, 8),
+    "k5_q9": (5, (2, 2, 2), (1, 1, 1), 0, (1, 1, 1), 0, 9),
+    "k6_q10_dirichlet": (6, (1, 2, 1), (1, 1, 1), 0, (0, 0, 1), 0, 10),
+    "k2_all_dirichlet": (2, (2, 2, 2), (1, 1, 1), 0, (0, 0, 0), 0, 4),
+    "k3_one_cell_periodic": (3, (1, 1, 2), (1, 1, 1), 0, (1, 1, 1), 0, 6),
+}
+
+
+def _field(m, fn, seed, noise):
+    X = m.node_coords()
+    U = np.asarray(fn(X[:, 0], X[:, 1], X[:, 2]), dtype=np.float64)
+    return (U + noise * inp.uniform(seed, U.size).reshape(U.shape)).ravel()
+
+
+def _pair(k, cells, L, y0, per, gam, nq):
+    import paper_1607_01323_amd as dg
+    om = omesh.BoxMesh(k, *cells, lx=L[0], ly=L[1], lz=L[2], y0=y0, periodic=tuple(bool(p) for p in per),
+                       y_tanh_gamma=gam)
+    gm = dg.Mesh(k, *cells, *L, y0=y0, periodic=per, y_tanh_gamma=gam)
+    return om, oconv.Convective(om, nq=nq), gm, dg.ConvectiveOperator(gm, n_q=nq)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_forward_and_vjp_small(name):
+    require_gpu()
+    print(f"[case] convective {name}", flush=True)
+    om, oop, gm, gop = _pair(*SMALL[name])
+    fn = inp.parabolic if SMALL[name][4][1] == 0 else inp.taylor_green
+    U = _field(om, fn, 1, 0.3)
+    W = inp.uniform(2, U.size)
+    C = host(gop.apply(dev(U)))
+    assert rel_err(C, oop.forward(U)) < 1e-12
+    G = host(gop.vjp(dev(U), dev(W)))
+    assert rel_err(G, oop.vjp(U, W)) < 1e-12
+    gm.close()
+
+
+def test_free_stream_and_channel_profile():
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    gm = dg.Mesh(4, 3, 4, 2, 2 * math.pi, 2.0, math.pi, y0=-1.0, periodic=(1, 0, 1), y_tanh_gamma=1.8)
+    om = omesh.BoxMesh(4, 3, 4, 2, lx=2 * math.pi, ly=2.0, lz=math.pi, y0=-1.0, periodic=(True, False, True),
+                       y_tanh_gamma=1.8)
+    op = dg.ConvectiveOperator(gm)
+    U = _field(om, inp.parabolic, 0, 0.0)
+    assert np.abs(host(op.apply(dev(U)))).max() < 1e-12
+    gp = dg.Mesh(3, 2, 3, 2)
+    opp = dg.ConvectiveOperator(gp)
+    n = gp.ndofs
+    U = np.concatenate([np.full(n, 0.4), np.full(n, -1.1), np.full(n, 0.25)])
+    assert np.abs(host(opp.apply(dev(U)))).max() < 1e-13
+    gm.close()
+    gp.close()
+
+
+FULL = {"convective_periodic_32c_k5": inp.CONVECTIVE_C3, "channel_48x32x48_k4": inp.CHANNEL_C4}
+
+
+def _full_field(w, om):
+    if w is inp.CONVECTIVE_C3:
+        return _field(om, inp.taylor_green, 5, 0.01)
+    return _field(om, inp.parabolic, 6, 0.05)
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_size_sampled(name):
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    w = FULL[name]
+    print(f"[case] convective full-size {name}", flush=True)
+    om = omesh.BoxMesh(w.degree, *w.cells, lx=w.lengths[0], ly=w.lengths[1], lz=w.lengths[2], y0=w.y0,
+                       periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma)
+    oop = oconv.Convective(om, nq=w.conv_points or None)
+    gm = dg.Mesh.from_workload(w)
+    gop = dg.ConvectiveOperator(gm, n_q=w.conv_points)
+    U = _full_field(w, om)
+    W = inp.uniform(8, U.size)
+    cells = sample_cells(w.cells, 24, 4)
+    C = host(gop.apply(dev(U))).reshape(3, om.ncells, -1)[:, cells]
+    assert rel_err(C, oop.forward_cells(U, cells)) < 1e-12
+    G = host(gop.vjp(dev(U), dev(W))).reshape(3, om.ncells, -1)[:, cells]
+    assert rel_err(G, oop.vjp_cells(U, W, cells)) < 1e-12
+    gm.close()
+
+
+def _interior_mask(n, ncells):
+    """1 on nodes that lie on no face of their cell (GLL: face traces do not see them)."""
+    i = np.arange(n)
+    inner = (i > 0) & (i < n - 1)
+    m = (inner[None, None, :] & inner[None, :, None] & inner[:, None, None]).ravel().astype(np.float64)
+    return np.tile(np.tile(m, ncells), 3)
+
+
+def test_vjp_central_differences_20_directions():
+    """<VJP(U,w), d> against central differences of <w, C(U)> with eps = 1e-6.
+
+    C is piecewise quadratic, so central differences are exact away from the
+    kinks of the Lax-Friedrichs max(|u-.n|, |u+.n|).  Directions supported on
+    cell-interior nodes leave every face trace unchanged (Gauss-Lobatto basis),
+    cross no kink, and must agree to rounding.  Fully random directions (the
+    workload's check) cross O(eps * #face points) kinks, each contributing an
+    O(1) error to the difference quotient, which bounds their agreement at
+    ~1e-4 here; the Euler identity <VJP(U,w), U> = 2 <w, C(U)> (C is
+    homogeneous of degree 2) is exact and covers the face terms.
+    """
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    w = inp.CONVECTIVE_C3
+    print("[case] convective finite differences, 20 directions", flush=True)
+    gm = dg.Mesh.from_workload(w)
+    op = dg.ConvectiveOperator(gm, n_q=w.conv_points)
+    X = gm.node_coords()
+    U = torch.stack(list(inp_tg_torch(X))).reshape(-1) + 0.01 * dev(inp.uniform(5, 3 * gm.ndofs))
+    Wt = dev(inp.uniform(8, 3 * gm.ndofs))
+    g = op.vjp(U, Wt)
+    C = op.apply(U)
+    euler = abs(torch.dot(g, U).item() - 2 * torch.dot(Wt, C).item()) / abs(torch.dot(g, U).item())
+    mask = dev(_interior_mask(w.degree + 1, gm.ncells))
+    eps = 1e-6
+    worst_in, worst_all = 0.0, 0.0
+    for j in range(20):
+        d = dev(inp.uniform(100 + j, 3 * gm.ndofs))
+        for dd, kind in ((d * mask, "interior"), (d, "all")):
+            fd = torch.dot(Wt, op.apply(U + eps * dd) - op.apply(U - eps * dd)).item() / (2 * eps)
+            an = torch.dot(g, dd).item()
+            e = abs(fd - an) / abs(an)
+            if kind == "interior":
+                worst_in = max(worst_in, e)
+            else:
+                worst_all = max(worst_all, e)
+    print(f"[result] Euler identity {euler:.2e}; worst FD mismatch, interior-node directions {worst_in:.2e}, "
+          f"random directions {worst_all:.2e}")
+    assert euler < 1e-12
+    assert worst_in < 1e-8
+    assert worst_all < 1e-3
+    gm.close()
+
+
+def inp_tg_torch(X):
+    two_pi = 2 * math.pi
+    x, y, z = X[0], X[1], X[2]
+    return (torch.sin(two_pi * x) * torch.cos(two_pi * y) * torch.cos(two_pi * z),
+            -torch.cos(two_pi * x) * torch.sin(two_pi * y) * torch.cos(two_pi * z), torch.zeros_like(x))
+
+
+def test_autograd_function():
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    gm = dg.Mesh(3, 2, 2, 2)
+    op = dg.ConvectiveOperator(gm)
+    U = dev(inp.uniform(1, 3 * gm.ndofs)).requires_grad_(True)
+    Wt = dev(inp.uniform(2, 3 * gm.ndofs))
+    y = dg.Convective.apply(U, op)
+    (y * Wt).sum().backward()
+    ref = op.vjp(U.detach(), Wt)
+    assert torch.equal(U.grad, ref)
+    gm.close()
