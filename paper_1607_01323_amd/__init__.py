@@ -6,7 +6,7 @@ PyTorch device tensors (contiguous, dtype as documented per call) and work
 is enqueued on ``torch.cuda.current_stream()``.  There is no CPU fallback:
 if the built library is missing, importing this package raises.
 
-Build the library with ``python -m paper_1607_01323_amd.build``.
+Build the library with ``python paper_1607_01323_amd/build.py``.
 """
 import ctypes
 import os
@@ -22,7 +22,7 @@ STATUS_NAMES = ["OK", "INVALID", "HIP_ERROR", "OOM", "NOT_CONVERGED", "BREAKDOWN
 F64, F32 = 0, 1
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1607_01323_amd.build` (hipcc, gfx950)")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_1607_01323_amd/build.py` (hipcc, gfx950)")
 _lib = ctypes.CDLL(LIB_PATH)
 
 _vp, _i64 = ctypes.c_void_p, ctypes.c_int64

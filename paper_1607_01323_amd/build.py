@@ -1,6 +1,7 @@
 """Build libdgmf.so (HIP kernels + C-ABI) in-tree for gfx950 with hipcc.
 
-Usage: python -m paper_1607_01323_amd.build [--jobs N] [--debug]
+Usage: python paper_1607_01323_amd/build.py [--jobs N] [--debug]
+(standalone: it does not import the package, whose import needs the library)
 """
 import argparse
 import os

@@ -103,9 +103,11 @@ static dgmf_status upload_geometry(dgmf_mesh m, DevBuf& buf, CartGeom<T>& g) {
 }
 
 template <typename T>
-static dgmf_status upload_tables(const Tables1D& t, DevBuf& buf) {
+static dgmf_status upload_tables(const Tables1D& t, DevBuf& buf, const std::vector<double>* xhat = nullptr) {
   TabLayout L{t.n, t.nq};
-  std::vector<T> h(L.size());
+  std::vector<T> h(L.size(), T(0));
+  if (xhat)
+    for (int i = 0; i < t.n * t.n; ++i) h[L.xhat() + i] = static_cast<T>((*xhat)[i]);
   for (int i = 0; i < t.n * t.n; ++i) {
     h[L.mhat() + i] = static_cast<T>(t.Mhat[i]);
     h[L.khat() + i] = static_cast<T>(t.Khat[i]);
@@ -119,6 +121,43 @@ static dgmf_status upload_tables(const Tables1D& t, DevBuf& buf) {
   for (int q = 0; q < t.nq; ++q) {
     h[L.wq() + q] = static_cast<T>(t.wq[q]);
     h[L.xq() + q] = static_cast<T>(t.xq[q]);
+  }
+  if (t.nq == t.n) {
+    // Mhat^{-1} by Gauss-Jordan elimination with partial pivoting in long double
+    const int n = t.n;
+    std::vector<long double> a(n * 2 * n, 0.0L);
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j) a[i * 2 * n + j] = t.Mhat[i * n + j];
+      a[i * 2 * n + n + i] = 1.0L;
+    }
+    for (int c = 0; c < n; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < n; ++r)
+        if (std::fabs(static_cast<double>(a[r * 2 * n + c])) > std::fabs(static_cast<double>(a[piv * 2 * n + c]))) piv = r;
+      for (int j = 0; j < 2 * n; ++j) std::swap(a[c * 2 * n + j], a[piv * 2 * n + j]);
+      const long double d = a[c * 2 * n + c];
+      for (int j = 0; j < 2 * n; ++j) a[c * 2 * n + j] /= d;
+      for (int r = 0; r < n; ++r)
+        if (r != c) {
+          const long double f = a[r * 2 * n + c];
+          for (int j = 0; j < 2 * n; ++j) a[r * 2 * n + j] -= f * a[c * 2 * n + j];
+        }
+    }
+    auto minv = [&](int i, int j) { return a[i * 2 * n + n + j]; };
+    for (int i = 0; i < n; ++i) {
+      long double g0 = 0, g1 = 0;
+      for (int j = 0; j < n; ++j) {
+        long double kk = 0;
+        for (int m = 0; m < n; ++m) kk += minv(i, m) * t.Khat[m * n + j];
+        h[L.ktil() + i * n + j] = static_cast<T>(kk);
+        g0 += minv(i, j) * t.g0[j];
+        g1 += minv(i, j) * t.g1[j];
+      }
+      h[L.g0t() + i] = static_cast<T>(g0);
+      h[L.g1t() + i] = static_cast<T>(g1);
+      h[L.e0t() + i] = static_cast<T>(minv(i, 0));
+      h[L.e1t() + i] = static_cast<T>(minv(i, n - 1));
+    }
   }
   return buf.upload(h.data(), h.size() * sizeof(T));
 }
@@ -221,6 +260,9 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
   const int n = mesh->desc.degree + 1;
   if (desc->n_q != 0 && desc->n_q != n)
     return fail(DGMF_UNSUPPORTED, "sipg_create: n_q must be 0 or k+1 (got %d)", desc->n_q);
+  if (mesh->ndofs >= (int64_t(1) << 31))
+    return fail(DGMF_UNSUPPORTED, "sipg_create: %lld DoF per field exceed the 32-bit indexing of this build",
+                static_cast<long long>(mesh->ndofs));
   if (!std::isfinite(desc->mass_coeff) || !std::isfinite(desc->diff_coeff) || !std::isfinite(desc->penalty_scale) ||
       desc->mass_coeff < 0 || desc->diff_coeff < 0 || !(desc->penalty_scale > 0))
     return fail(DGMF_INVALID, "sipg_create: coefficients must be finite, mass/diff >= 0, penalty > 0");
@@ -234,10 +276,24 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
   op->sipg = *desc;
   op->nq = n;
   make_tables(mesh->desc.degree, n, op->tab);
-  dgmf_status st = upload_tables<double>(op->tab, op->tab64);
-  if (st == DGMF_OK) st = upload_tables<float>(op->tab, op->tab32);
+  // x-line operator with the mass term folded in when the x spacing is uniform:
+  // nu hy hz/hx Khat + mu hx hy hz Mhat = (nu hy hz/hx) (Khat + (mu hx^2/nu) Mhat)
+  const auto& vx = mesh->verts[0];
+  bool uniform_x = true;
+  const double hx0 = vx[1] - vx[0];
+  for (size_t c = 1; c + 1 < vx.size(); ++c)
+    if (std::fabs((vx[c + 1] - vx[c]) - hx0) > 1e-14 * hx0) uniform_x = false;
+  std::vector<double> xhat(n * n);
+  for (int i = 0; i < n * n; ++i)
+    xhat[i] = desc->diff_coeff > 0 ? op->tab.Khat[i] + desc->mass_coeff * hx0 * hx0 / desc->diff_coeff * op->tab.Mhat[i]
+                                   : op->tab.Mhat[i];
+  dgmf_status st = upload_tables<double>(op->tab, op->tab64, &xhat);
+  if (st == DGMF_OK) st = upload_tables<float>(op->tab, op->tab32, &xhat);
   op->g64 = mesh->g64;
   op->g32 = mesh->g32;
+  const int allper = mesh->desc.periodic[0] && mesh->desc.periodic[1] && mesh->desc.periodic[2];
+  op->g64.xcomb = op->g32.xcomb = uniform_x ? 1 : 0;
+  op->g64.allper = op->g32.allper = allper;
   if (st != DGMF_OK) {
     delete op;
     return st;

@@ -465,7 +465,7 @@ dgmf_status validate(dgmf_op op, const dgmf_cg_params* p) {
 }
 
 int64_t nparts_for(dgmf_op op) {
-  const int64_t a = sipg_cart_blocks(op->mesh->desc.degree + 1, op->mesh->ncells);
+  const int64_t a = sipg_cart_blocks(op->mesh->desc.degree + 1, op->g64);
   return a > kVecBlocks ? a : kVecBlocks;
 }
 
@@ -657,7 +657,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
   double* dinv = S.at<double>(L.dinv);
   double* diag = S.at<double>(L.diag);
   const dim3 G(kVecBlocks), B(256);
-  const int napply = sipg_cart_blocks(S.n, op->mesh->ncells);
+  const int napply = sipg_cart_blocks(S.n, op->g64);
   auto t0 = std::chrono::steady_clock::now();
 
   // ---- set-up: state, diagonal, eigenvalue estimate

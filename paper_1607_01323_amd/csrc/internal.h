@@ -87,7 +87,9 @@ struct CartGeom {
   const T* x0[3];     // low vertex coordinate
   T pen;              // s (k+1)^2
   T mu, nu;           // mass and diffusion coefficients
-  const T* tab;       // Mhat[n*n], Khat[n*n], g0[n], g1[n], S[nq*n], wq[nq], xq[nq], nodes[n]
+  const T* tab;       // Mhat[n*n], Khat[n*n], g0[n], g1[n], S[nq*n], wq[nq], xq[nq], nodes[n], Xhat[n*n]
+  int xcomb;          // 1: uniform x spacing, Xhat = Khat + (mu hx^2/nu) Mhat (or Mhat if nu = 0) is valid
+  int allper;         // 1: every direction periodic
 };
 
 // Offsets into the device table of an SIPG operator.
@@ -101,7 +103,14 @@ struct TabLayout {
   __host__ __device__ int wq() const { return S() + nq * n; }
   __host__ __device__ int xq() const { return wq() + nq; }
   __host__ __device__ int nodes() const { return xq() + nq; }
-  __host__ __device__ int size() const { return nodes() + n; }
+  __host__ __device__ int xhat() const { return nodes() + n; }
+  // Mhat^{-1} Khat and the Mhat^{-1} images of l'(0), l'(1), e_0, e_{n-1}
+  __host__ __device__ int ktil() const { return xhat() + n * n; }
+  __host__ __device__ int g0t() const { return ktil() + n * n; }
+  __host__ __device__ int g1t() const { return g0t() + n; }
+  __host__ __device__ int e0t() const { return g1t() + n; }
+  __host__ __device__ int e1t() const { return e0t() + n; }
+  __host__ __device__ int size() const { return e1t() + n; }
 };
 
 dgmf_status launch_node_coords(int n, const CartGeom<double>& g, double* xyz, int64_t ncells, hipStream_t s);
@@ -119,7 +128,8 @@ dgmf_status launch_sipg_cart_apply(int n, const CartGeom<T>& g, const T* src, T*
                                    double* partials, const int* stop, hipStream_t s);
 template <typename T>
 dgmf_status launch_sipg_cart_diag(int n, const CartGeom<T>& g, T* diag, int64_t ncells, hipStream_t s);
-int sipg_cart_blocks(int n, int64_t ncells);
+// Grid size of the apply kernel (also the number of partial-sum rows it writes).
+int sipg_cart_blocks(int n, const CartGeom<double>& g);
 
 bool conv_supported(int n, int nq);
 dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, double* C, int64_t ncells,

@@ -30,23 +30,14 @@
 namespace dgmf {
 namespace {
 
-// gfx950 dispatches consecutive workgroups round-robin over its 8 XCDs, each
-// with a private L2.  Remap so that every XCD walks a contiguous range of
-// cells: the face neighbours a block reads are then mostly in its own L2.
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
-  const int64_t q = nblocks / kXcds, rem = nblocks % kXcds;
-  const int64_t x = b % kXcds, r = b / kXcds;
-  return x * q + (x < rem ? x : rem) + r;
-}
+constexpr int kApplyThreads = 128;   // threads per workgroup of the apply kernel
 
 template <int N>
 struct Shape {
   static constexpr int N2 = N * N;
   static constexpr int N3 = N2 * N;
-  static constexpr int CPB = 256 / N2;        // cells per block
-  static constexpr int P = N + 1;             // padded x-line pitch in LDS
+  static constexpr int CPB = (kApplyThreads / N2) > 0 ? kApplyThreads / N2 : 1;   // cells per block
+  static constexpr int P = (N % 2) ? N : N + 1;   // odd x-line pitch in LDS: conflict-free x-line access
   static constexpr int CL = N2 * P;           // LDS words per cell per buffer
 };
 
@@ -200,122 +191,348 @@ __device__ __forceinline__ void dir_op(const CartGeom<T>& g, const T* __restrict
   sipg_line<N, T>(g.tab, u, ul, ur, !hasL, !hasR, ci.hinv[d], hl, hr, tauL, tauR, sigma, massc, out);
 }
 
+// ---------------------------------------------------------------- apply ---
+// Traversal order: the mesh is cut into y-strips, one per XCD when ny >= 8
+// (workgroup b runs on XCD b % 8), and each strip is walked z-major, then y,
+// then x.  The z-neighbour layer a workgroup reads was written a strip layer
+// earlier (nx * ny/8 cells), so it is still in that XCD's L2.
+__host__ __device__ inline int strip_count(int ny) { return ny >= 8 ? 8 : 1; }
+
+// out = smain (mat u) [+ massc (Mhat u)] + the two face fluxes of this line.
+// ul / ur: the same line of the low / high neighbour (ignored on Dirichlet faces).
+template <int N, typename T, bool MASS>
+__device__ __forceinline__ void line_apply(const T* __restrict__ tab, const T* __restrict__ mat, T smain, T massc,
+                                           const T (&u)[N], const T (&ul)[N], const T (&ur)[N], bool dirL,
+                                           bool dirR, T hinv, T hlinv, T hrinv, T tauL, T tauR, T sigma,
+                                           T (&out)[N]) {
+  const T* g0 = tab + 2 * N * N;
+  const T* g1 = g0 + N;
+  T gu0 = g0[0] * u[0], gu1 = g1[0] * u[0];
+#pragma unroll
+  for (int m = 1; m < N; ++m) {
+    gu0 = fma(g0[m], u[m], gu0);
+    gu1 = fma(g1[m], u[m], gu1);
+  }
+  gu0 *= hinv;
+  gu1 *= hinv;
+  const T sh = sigma * hinv;
+  T cR, eR, cL, eL;   // coefficients of l'(1)_i and l'(0)_i, and the end-node terms
+  if (dirR) {
+    cR = -sh * u[N - 1];
+    eR = sigma * fma(T(2) * tauR, u[N - 1], -gu1);
+  } else {
+    T gr = g0[0] * ur[0];
+#pragma unroll
+    for (int m = 1; m < N; ++m) gr = fma(g0[m], ur[m], gr);
+    const T jump = u[N - 1] - ur[0];
+    const T avg = T(0.5) * fma(gr, hrinv, gu1);
+    cR = T(-0.5) * sh * jump;
+    eR = sigma * fma(tauR, jump, -avg);
+  }
+  if (dirL) {
+    cL = sh * u[0];
+    eL = sigma * fma(T(2) * tauL, u[0], gu0);
+  } else {
+    T gl = g1[0] * ul[0];
+#pragma unroll
+    for (int m = 1; m < N; ++m) gl = fma(g1[m], ul[m], gl);
+    const T jump = ul[N - 1] - u[0];
+    const T avg = T(0.5) * fma(gl, hlinv, gu0);
+    cL = T(-0.5) * sh * jump;
+    eL = sigma * fma(-tauL, jump, avg);
+  }
+  T us[N], um[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    us[m] = smain * u[m];
+    if (MASS) um[m] = massc * u[m];
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = fma(cL, g0[i], cR * g1[i]);
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc = fma(mat[i * N + m], us[m], acc);
+    if (MASS) {
+#pragma unroll
+      for (int m = 0; m < N; ++m) acc = fma(tab[i * N + m], um[m], acc);
+    }
+    out[i] = acc;
+  }
+  out[0] += eL;
+  out[N - 1] += eR;
+}
+
+// y = A x + c (c optional: accumulate into y's initial value)
 template <int N, typename T>
-__global__ void __launch_bounds__(256) k_sipg_cart_apply(const T* __restrict__ src, T* __restrict__ dst,
-                                                         const CartGeom<T> g, int64_t ncells,
-                                                         double* __restrict__ partials, const int* stop) {
+__device__ __forceinline__ void matvec_acc(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = y[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) s = fma(A[i * N + j], x[j], s);
+    y[i] = s;
+  }
+}
+
+template <int N, typename T, bool PER>
+struct Nb {
+  int idx;       // neighbour cell
+  T hinv, tau;   // its 1/h along d and the face penalty
+  bool dir;      // Dirichlet face
+};
+
+// Low (side 0) / high (side 1) neighbour along d of a cell at coordinate cd.
+template <int N, typename T, bool PER>
+__device__ __forceinline__ Nb<N, T, PER> nbr(const CartGeom<T>& g, int cell, int cd, int nd, int stride, int d,
+                                             int side, T tau_c, T tp_other) {
+  Nb<N, T, PER> r;
+  int cn = cd + (side ? 1 : -1);
+  r.dir = false;
+  if (cn < 0 || cn >= nd) {
+    if (!PER && !g.per[d]) {
+      r.dir = true;
+      r.idx = cell;
+      r.hinv = T(0);
+      r.tau = tau_c;
+      return r;
+    }
+    cn = cn < 0 ? nd - 1 : 0;
+  }
+  r.idx = cell + (cn - cd) * stride;
+  r.hinv = g.hinv[d][cn];
+  const T tn = g.pen * (g.tp[d][cn] + tp_other);
+  r.tau = tau_c > tn ? tau_c : tn;
+  return r;
+}
+
+// w += s [ hinv (Mhat^-1 Khat u) + Mhat^-1 (face fluxes of this line) ]: one
+// direction's line operator, premultiplied by the inverse 1D mass matrix.
+// Face fluxes (unit tangential area): interior high face, [u] = u_N-1 - ur_0,
+// {{u'}} = (l'(1).u/h + l'(0).ur/hr)/2:
+//   -1/2 l'(1)_i/h [u] + delta_{i,N-1} (tau [u] - {{u'}});
+// interior low face, [u] = ul_N-1 - u_0, {{u'}} = (l'(1).ul/hl + l'(0).u/h)/2:
+//   -1/2 l'(0)_i/h [u] + delta_{i,0} ({{u'}} - tau [u]);
+// Dirichlet faces mirror these with [u] = u and the boundary penalty 2 tau.
+template <int N, typename T>
+__device__ __forceinline__ void bline(const T* __restrict__ tab, const T (&u)[N], const T (&ul)[N],
+                                      const T (&ur)[N], bool dirL, bool dirR, T hinv, T hlinv, T hrinv, T tauL,
+                                      T tauR, T s, T (&w)[N]) {
+  constexpr TabLayout L{N, N};
+  const T* g0 = tab + L.g0();
+  const T* g1 = tab + L.g1();
+  const T* Kt = tab + L.ktil();
+  const T* g0t = tab + L.g0t();
+  const T* g1t = tab + L.g1t();
+  const T* e0t = tab + L.e0t();
+  const T* e1t = tab + L.e1t();
+  T gu0 = g0[0] * u[0], gu1 = g1[0] * u[0];
+#pragma unroll
+  for (int m = 1; m < N; ++m) {
+    gu0 = fma(g0[m], u[m], gu0);
+    gu1 = fma(g1[m], u[m], gu1);
+  }
+  gu0 *= hinv;
+  gu1 *= hinv;
+  T cR, eR, cL, eL;
+  if (dirR) {
+    cR = -hinv * u[N - 1];
+    eR = fma(T(2) * tauR, u[N - 1], -gu1);
+  } else {
+    T gr = g0[0] * ur[0];
+#pragma unroll
+    for (int m = 1; m < N; ++m) gr = fma(g0[m], ur[m], gr);
+    const T jump = u[N - 1] - ur[0];
+    const T avg = T(0.5) * fma(gr, hrinv, gu1);
+    cR = T(-0.5) * hinv * jump;
+    eR = fma(tauR, jump, -avg);
+  }
+  if (dirL) {
+    cL = hinv * u[0];
+    eL = fma(T(2) * tauL, u[0], gu0);
+  } else {
+    T gl = g1[0] * ul[0];
+#pragma unroll
+    for (int m = 1; m < N; ++m) gl = fma(g1[m], ul[m], gl);
+    const T jump = ul[N - 1] - u[0];
+    const T avg = T(0.5) * fma(gl, hlinv, gu0);
+    cL = T(-0.5) * hinv * jump;
+    eL = fma(-tauL, jump, avg);
+  }
+  const T sh = s * hinv;
+  cR *= s;
+  cL *= s;
+  eR *= s;
+  eL *= s;
+  T us[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) us[m] = sh * u[m];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = fma(cR, g1t[i], fma(cL, g0t[i], fma(eR, e1t[i], fma(eL, e0t[i], w[i]))));
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc = fma(Kt[i * N + m], us[m], acc);
+    w[i] = acc;
+  }
+}
+
+// The operator in factored form: with V = hx hy hz and Mhat the 1D mass matrix,
+//   H u = V (Mz x My x Mx) ( mu u + sum_d (nu/h_d) Mhat^-1 A_d u ),
+// A_d the line operator of direction d (stiffness and the fluxes of its two
+// faces).  Five passes, each thread owning one line of its cell per pass:
+//   1 z-lines: load u (coalesced), w = mu V u + B_z u   (z-neighbour lines)
+//   2 y-lines: w += B_y u                              (y-neighbour lines)
+//   3 x-lines: w += B_x u; w = Mx w                    (x-neighbours from LDS in-block)
+//   4 y-lines: w = My w
+//   5 z-lines: dst = Mz w                               (coalesced store)
+template <int N, typename T, bool PER>
+__global__ void __launch_bounds__(kApplyThreads) k_sipg_cart_apply(const T* __restrict__ src, T* __restrict__ dst,
+                                                         const CartGeom<T> g, double* __restrict__ partials,
+                                                         const int* stop) {
   if (stop && *stop) return;   // uniform for the whole grid: CG already finished
   using S = Shape<N>;
   constexpr int N2 = S::N2, N3 = S::N3, P = S::P, CL = S::CL, CPB = S::CPB;
   __shared__ T s_u[CPB * CL];
-  __shared__ T s_a[CPB * CL];
-  __shared__ T s_b[CPB * CL];
-  __shared__ double s_red[3 * (256 / 64)];
+  __shared__ T s_w[CPB * CL];
+  __shared__ double s_red[3 * (kApplyThreads / 64)];
 
   const int tid = threadIdx.x;
   const int lc = tid / N2;
   const int t = tid - lc * N2;
   const int t0 = t % N, t1 = t / N;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t cell = blk * CPB + lc;
-  const bool act = lc < CPB && cell < ncells;
-  T* su = s_u + (lc < CPB ? lc : 0) * CL;
-  T* sa = s_a + (lc < CPB ? lc : 0) * CL;
-  T* sb = s_b + (lc < CPB ? lc : 0) * CL;
-  CellInfo<T> ci;
-  if (act) cell_info(g, cell, ci);
-  const T* cs = src + (act ? cell : 0) * N3;
+  // strip decomposition of the block index
+  const int nstrip = strip_count(g.ny);
+  const int sidx = blockIdx.x % nstrip, r = blockIdx.x / nstrip;
+  const int base = g.ny / nstrip, extra = g.ny % nstrip;
+  const int hs = base + (sidx < extra ? 1 : 0);
+  const int ys = sidx * base + (sidx < extra ? sidx : extra);
+  const int ncs = g.nx * hs * g.nz;
+  const int q = r * CPB + lc;
+  const bool act = lc < CPB && q < ncs;
+  int c[3] = {0, 0, 0}, cell = 0;
+  if (act) {
+    c[0] = q % g.nx;
+    const int tq = q / g.nx;
+    c[1] = ys + tq % hs;
+    c[2] = tq / hs;
+    cell = (c[2] * g.ny + c[1]) * g.nx + c[0];
+  }
+  const int nd[3] = {g.nx, g.ny, g.nz};
+  const int stride[3] = {1, g.nx, g.nx * g.ny};
+  const int slot = (lc < CPB ? lc : 0) * CL;
+  T* su = s_u + slot;
+  T* sw = s_w + slot;
+  T h[3], hinv[3], tp[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    h[d] = g.h[d][c[d]];
+    hinv[d] = g.hinv[d][c[d]];
+    tp[d] = g.tp[d][c[d]];
+  }
+  const T tau_c = g.pen * (tp[0] + tp[1] + tp[2]);
+  const T vol = h[0] * h[1] * h[2];
+  const T vnu = vol * g.nu;
+  const T* Mh = g.tab;
 
-  // pass 1: x-lines (j, l) = (t0, t1)
+  // pass 1: z-lines (i, j) = (t0, t1)
+  T u[N];
   if (act) {
-    const int j = t0, l = t1;
-    T u[N], out[N];
-    load_line<N, T>(cs + (l * N + j) * N, 1, u);
-    dir_op<N, T>(g, src, ci, cell, 0, u, (l * N + j) * N, 1, g.mu * ci.h[0] * ci.h[1] * ci.h[2], out);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      su[(l * N + j) * P + i] = u[i];
-      sa[(l * N + j) * P + i] = out[i];
-    }
-  }
-  __syncthreads();
-  // pass 2: y-lines (i, l) = (t0, t1): f = A_y u -> sb, c = My a -> sa
-  if (act) {
-    const int i = t0, l = t1;
-    T u[N], f[N], a[N], c[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      u[j] = su[(l * N + j) * P + i];
-      a[j] = sa[(l * N + j) * P + i];
-    }
-    dir_op<N, T>(g, src, ci, cell, 1, u, l * N2 + i, N, T(0), f);
-    matvec<N, T>(g.tab, a, c);
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      sa[(l * N + j) * P + i] = c[j];
-      sb[(l * N + j) * P + i] = f[j];
-    }
-  }
-  __syncthreads();
-  // pass 3: z-lines (i, j) = (t0, t1): g = A_z u -> su (in place)
-  if (act) {
-    const int i = t0, j = t1;
-    T u[N], o[N];
-#pragma unroll
-    for (int l = 0; l < N; ++l) u[l] = su[(l * N + j) * P + i];
-    dir_op<N, T>(g, src, ci, cell, 2, u, j * N + i, N2, T(0), o);
-#pragma unroll
-    for (int l = 0; l < N; ++l) su[(l * N + j) * P + i] = o[l];
-  }
-  __syncthreads();
-  // pass 4: x-lines: c += Mx f (sa), g = Mx g (su)
-  if (act) {
-    const int j = t0, l = t1;
-    T f[N], gg[N], c[N], r1[N], r2[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      f[i] = sb[(l * N + j) * P + i];
-      gg[i] = su[(l * N + j) * P + i];
-      c[i] = sa[(l * N + j) * P + i];
-    }
-    matvec<N, T>(g.tab, f, r1);
-    matvec<N, T>(g.tab, gg, r2);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      sa[(l * N + j) * P + i] = c[i] + r1[i];
-      su[(l * N + j) * P + i] = r2[i];
-    }
-  }
-  __syncthreads();
-  // pass 5: y-lines: g = My g
-  if (act) {
-    const int i = t0, l = t1;
-    T gg[N], r[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) gg[j] = su[(l * N + j) * P + i];
-    matvec<N, T>(g.tab, gg, r);
-#pragma unroll
-    for (int j = 0; j < N; ++j) su[(l * N + j) * P + i] = r[j];
-  }
-  __syncthreads();
-  // pass 6: z-lines: dst = Mz c + g
-  double pq = 0.0, sq = 0.0, sp = 0.0;
-  if (act) {
-    const int i = t0, j = t1;
-    T c[N], r[N];
-#pragma unroll
-    for (int l = 0; l < N; ++l) c[l] = sa[(l * N + j) * P + i];
-    matvec<N, T>(g.tab, c, r);
-    T* cd = dst + cell * N3;
+    const int off = t1 * N + t0;
+    const Nb<N, T, PER> L = nbr<N, T, PER>(g, cell, c[2], nd[2], stride[2], 2, 0, tau_c, tp[0] + tp[1]);
+    const Nb<N, T, PER> R = nbr<N, T, PER>(g, cell, c[2], nd[2], stride[2], 2, 1, tau_c, tp[0] + tp[1]);
+    T zl[N], zr[N], w[N];
 #pragma unroll
     for (int l = 0; l < N; ++l) {
-      const T v = r[l] + su[(l * N + j) * P + i];
-      cd[(l * N + j) * N + i] = v;
-      if (partials) {
-        const double pv = static_cast<double>(cs[(l * N + j) * N + i]);
-        pq += pv * static_cast<double>(v);
-        sq += static_cast<double>(v);
-        sp += pv;
+      u[l] = src[cell * N3 + off + l * N2];
+      zl[l] = L.dir ? T(0) : src[L.idx * N3 + off + l * N2];
+      zr[l] = R.dir ? T(0) : src[R.idx * N3 + off + l * N2];
+    }
+    const T mv = g.mu * vol;
+#pragma unroll
+    for (int l = 0; l < N; ++l) w[l] = mv * u[l];
+    bline<N, T>(g.tab, u, zl, zr, L.dir, R.dir, hinv[2], L.hinv, R.hinv, L.tau, R.tau, vnu * hinv[2], w);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      su[(l * N + t1) * P + t0] = u[l];
+      sw[(l * N + t1) * P + t0] = w[l];
+    }
+  }
+  __syncthreads();
+  // pass 2: y-lines (i, l) = (t0, t1)
+  if (act) {
+    const int i = t0, l = t1;
+    const Nb<N, T, PER> L = nbr<N, T, PER>(g, cell, c[1], nd[1], stride[1], 1, 0, tau_c, tp[0] + tp[2]);
+    const Nb<N, T, PER> R = nbr<N, T, PER>(g, cell, c[1], nd[1], stride[1], 1, 1, tau_c, tp[0] + tp[2]);
+    T uy[N], yl[N], yr[N], w[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      yl[j] = L.dir ? T(0) : src[L.idx * N3 + l * N2 + j * N + i];
+      yr[j] = R.dir ? T(0) : src[R.idx * N3 + l * N2 + j * N + i];
+      uy[j] = su[(l * N + j) * P + i];
+      w[j] = sw[(l * N + j) * P + i];
+    }
+    bline<N, T>(g.tab, uy, yl, yr, L.dir, R.dir, hinv[1], L.hinv, R.hinv, L.tau, R.tau, vnu * hinv[1], w);
+#pragma unroll
+    for (int j = 0; j < N; ++j) sw[(l * N + j) * P + i] = w[j];
+  }
+  __syncthreads();
+  // pass 3: x-lines (j, l) = (t0, t1); x-neighbour lines from LDS when in this block
+  if (act) {
+    const Nb<N, T, PER> L = nbr<N, T, PER>(g, cell, c[0], nd[0], stride[0], 0, 0, tau_c, tp[1] + tp[2]);
+    const Nb<N, T, PER> R = nbr<N, T, PER>(g, cell, c[0], nd[0], stride[0], 0, 1, tau_c, tp[1] + tp[2]);
+    const int lo = (t1 * N + t0) * P;
+    const int sl_l = lc + (c[0] > 0 ? -1 : g.nx - 1);
+    const int sl_r = lc + (c[0] < g.nx - 1 ? 1 : 1 - g.nx);
+    const bool inl = sl_l >= 0 && sl_l < CPB && q + (sl_l - lc) < ncs;
+    const bool inr = sl_r >= 0 && sl_r < CPB && q + (sl_r - lc) < ncs;
+    const int offx = (t1 * N + t0) * N;
+    T ux[N], xl[N], xr[N], w[N], o[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      ux[i] = su[lo + i];
+      w[i] = sw[lo + i];
+      xl[i] = L.dir ? T(0) : (inl ? s_u[sl_l * CL + lo + i] : src[L.idx * N3 + offx + i]);
+      xr[i] = R.dir ? T(0) : (inr ? s_u[sl_r * CL + lo + i] : src[R.idx * N3 + offx + i]);
+      o[i] = T(0);
+    }
+    bline<N, T>(g.tab, ux, xl, xr, L.dir, R.dir, hinv[0], L.hinv, R.hinv, L.tau, R.tau, vnu * hinv[0], w);
+    matvec_acc<N, T>(Mh, w, o);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sw[lo + i] = o[i];
+  }
+  __syncthreads();
+  // pass 4: y-lines: w = My w
+  if (act) {
+    const int i = t0, l = t1;
+    T w[N], o[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      w[j] = sw[(l * N + j) * P + i];
+      o[j] = T(0);
+    }
+    matvec_acc<N, T>(Mh, w, o);
+#pragma unroll
+    for (int j = 0; j < N; ++j) sw[(l * N + j) * P + i] = o[j];
+  }
+  __syncthreads();
+  // pass 5: z-lines: dst = Mz w
+  double pq = 0.0, sq = 0.0, sp = 0.0;
+  if (act) {
+    T w[N], o[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      w[l] = sw[(l * N + t1) * P + t0];
+      o[l] = T(0);
+    }
+    matvec_acc<N, T>(Mh, w, o);
+    T* cd = dst + cell * N3 + t1 * N + t0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) __builtin_nontemporal_store(o[l], cd + l * N2);
+    if (partials) {
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        pq += static_cast<double>(u[l]) * static_cast<double>(o[l]);
+        sq += static_cast<double>(o[l]);
+        sp += static_cast<double>(u[l]);
       }
     }
   }
@@ -335,16 +552,15 @@ __global__ void __launch_bounds__(256) k_sipg_cart_apply(const T* __restrict__ s
     }
     __syncthreads();
     if (tid == 0) {
-      const int nw = blockDim.x >> 6;
-      double a = 0, b = 0, c = 0;
-      for (int k = 0; k < nw; ++k) {
-        a += s_red[3 * k];
-        b += s_red[3 * k + 1];
-        c += s_red[3 * k + 2];
+      double x = 0, y = 0, z = 0;
+      for (int k = 0; k < kApplyThreads / 64; ++k) {
+        x += s_red[3 * k];
+        y += s_red[3 * k + 1];
+        z += s_red[3 * k + 2];
       }
-      partials[4 * blk] = a;
-      partials[4 * blk + 1] = b;
-      partials[4 * blk + 2] = c;
+      partials[4 * blockIdx.x] = x;
+      partials[4 * blockIdx.x + 1] = y;
+      partials[4 * blockIdx.x + 2] = z;
     }
   }
 }
@@ -397,11 +613,14 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
 template <int N, typename T>
 dgmf_status launch_apply_n(const CartGeom<T>& g, const T* src, T* dst, int64_t ncells, double* partials,
                            const int* stop, hipStream_t s) {
-  using S = Shape<N>;
-  const int64_t blocks = (ncells + S::CPB - 1) / S::CPB;
-  if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
-  hipLaunchKernelGGL((k_sipg_cart_apply<N, T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                     src, dst, g, ncells, partials, stop);
+  (void)ncells;
+  const int blocks = sipg_cart_blocks(N, CartGeom<double>{g.nx, g.ny, g.nz});
+  if (g.allper)
+    hipLaunchKernelGGL((k_sipg_cart_apply<N, T, true>), dim3(blocks), dim3(kApplyThreads), 0, s, src, dst, g, partials,
+                       stop);
+  else
+    hipLaunchKernelGGL((k_sipg_cart_apply<N, T, false>), dim3(blocks), dim3(kApplyThreads), 0, s, src, dst, g,
+                       partials, stop);
   DGMF_LAUNCH_CHECK("k_sipg_cart_apply");
   return DGMF_OK;
 }
@@ -418,9 +637,12 @@ dgmf_status launch_diag_n(const CartGeom<T>& g, T* diag, int64_t ncells, hipStre
 
 }  // namespace
 
-int sipg_cart_blocks(int n, int64_t ncells) {
-  const int cpb = 256 / (n * n);
-  return static_cast<int>((ncells + cpb - 1) / cpb);
+int sipg_cart_blocks(int n, const CartGeom<double>& g) {
+  const int cpb = (kApplyThreads / (n * n)) > 0 ? kApplyThreads / (n * n) : 1;
+  const int nstrip = strip_count(g.ny);
+  const int hmax = g.ny / nstrip + (g.ny % nstrip ? 1 : 0);
+  const int64_t per_strip = static_cast<int64_t>(g.nx) * hmax * g.nz;
+  return static_cast<int>(nstrip * ((per_strip + cpb - 1) / cpb));
 }
 
 template <typename T>

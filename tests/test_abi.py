@@ -19,7 +19,7 @@ def declared():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("libdgmf.so is not built (python -m paper_1607_01323_amd.build)")
+        pytest.fail("libdgmf.so is not built (python paper_1607_01323_amd/build.py)")
     return ctypes.CDLL(LIB)
 
 
