@@ -14,7 +14,7 @@
 // its end node, and the normal derivative is the end-point derivative row
 // l'(0) or l'(1) applied to the line.
 //
-// Kernel layout: one workgroup per batch of CPB = 256 / n^2 cells, n^2
+// Kernel layout: one workgroup per batch of CPB = 128 / n^2 cells, n^2
 // threads per cell, each thread owning one line of its cell per pass.  The
 // cell tensor and intermediates live in LDS with a padded line pitch n+1;
 // neighbour lines are read straight from global memory (L2 / Infinity Cache
