@@ -76,8 +76,13 @@ int dgmf_version(void);
  * y_tanh_gamma > 0 grades the y vertices with the hyperbolic mapping of
  * Sec. 7.1, y = y0 + ly/2 (1 + tanh(gamma (2t-1)) / tanh(gamma)), t in [0,1].
  * store_qp_metric = 1 makes SIPG operators on this mesh store and stream the
- * geometry at every quadrature point (inverse Jacobian, Jacobian determinant
- * times weight) instead of using the per-cell constant metric.
+ * geometry at every quadrature point (w detJ J^{-1}J^{-T}, w detJ; on faces
+ * w dA and J^{-1}n w dA of both cells) instead of using the per-cell constant
+ * metric of axis-aligned cells (then periodic directions need >= 2 cells).
+ * shear: row-major 3x3 matrix S applied to every point of the box, x = S p
+ * (a constant affine lattice, so cells are parallelepipeds); all zeros means
+ * the identity.  A non-identity shear needs store_qp_metric = 1 and is not
+ * supported by the convective operator.
  * degree k in 1..7; every cell count >= 1; lengths > 0. */
 typedef struct {
   int degree;
@@ -87,6 +92,7 @@ typedef struct {
   int periodic[3];
   double y_tanh_gamma;
   int store_qp_metric;
+  double shear[9];
 } dgmf_box_desc;
 
 /* Allocates device geometry on the current device.  *out receives the handle. */

@@ -31,7 +31,8 @@ _vp, _i64 = ctypes.c_void_p, ctypes.c_int64
 class BoxDesc(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double), ("y0", ctypes.c_double),
-                ("periodic", ctypes.c_int * 3), ("y_tanh_gamma", ctypes.c_double), ("store_qp_metric", ctypes.c_int)]
+                ("periodic", ctypes.c_int * 3), ("y_tanh_gamma", ctypes.c_double), ("store_qp_metric", ctypes.c_int),
+                ("shear", ctypes.c_double * 9)]
 
 
 class SipgDesc(ctypes.Structure):
@@ -120,9 +121,10 @@ class Mesh:
     """Box mesh of affine hexahedra (see ``dgmf_box_desc``)."""
 
     def __init__(self, degree, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, y0=0.0, periodic=(1, 1, 1),
-                 y_tanh_gamma=0.0, store_qp_metric=False):
+                 y_tanh_gamma=0.0, store_qp_metric=False, shear=None):
+        sh = [0.0] * 9 if shear is None else [float(v) for row in shear for v in row]
         d = BoxDesc(degree, nx, ny, nz, lx, ly, lz, y0, (ctypes.c_int * 3)(*[int(bool(p)) for p in periodic]),
-                    y_tanh_gamma, int(bool(store_qp_metric)))
+                    y_tanh_gamma, int(bool(store_qp_metric)), (ctypes.c_double * 9)(*sh))
         self._h = _vp()
         _check(_mesh_create(ctypes.byref(d), ctypes.byref(self._h)), "mesh_create")
         nc, nd = _i64(), _i64()

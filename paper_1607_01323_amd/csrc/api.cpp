@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -162,6 +163,108 @@ static dgmf_status upload_tables(const Tables1D& t, DevBuf& buf, const std::vect
   return buf.upload(h.data(), h.size() * sizeof(T));
 }
 
+// Inverse of a small dense matrix by Gauss-Jordan elimination with partial
+// pivoting in long double; false when singular.
+static bool invert(int n, const double* a_in, std::vector<long double>& inv) {
+  std::vector<long double> a(n * 2 * n, 0.0L);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) a[i * 2 * n + j] = a_in[i * n + j];
+    a[i * 2 * n + n + i] = 1.0L;
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(static_cast<double>(a[r * 2 * n + c])) > std::fabs(static_cast<double>(a[piv * 2 * n + c]))) piv = r;
+    if (a[piv * 2 * n + c] == 0.0L) return false;
+    for (int j = 0; j < 2 * n; ++j) std::swap(a[c * 2 * n + j], a[piv * 2 * n + j]);
+    const long double d = a[c * 2 * n + c];
+    for (int j = 0; j < 2 * n; ++j) a[c * 2 * n + j] /= d;
+    for (int r = 0; r < n; ++r)
+      if (r != c) {
+        const long double f = a[r * 2 * n + c];
+        for (int j = 0; j < 2 * n; ++j) a[r * 2 * n + j] -= f * a[c * 2 * n + j];
+      }
+  }
+  inv.assign(n * n, 0.0L);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) inv[i * n + j] = a[i * 2 * n + n + j];
+  return true;
+}
+
+// Quadrature-point metric of a lattice mesh: tables S, D, Dg = D S^{-1},
+// l'(0), l'(1), w; cell and face geometry filled on the device in fp64, then
+// copied to fp32.
+static dgmf_status setup_metric(dgmf_mesh m) {
+  const int n = m->tab.n;
+  const Tables1D& t = m->tab;
+  const int nd[3] = {m->desc.nx, m->desc.ny, m->desc.nz};
+  std::vector<long double> sinv;
+  if (!invert(n, t.S.data(), sinv)) return fail(DGMF_INVALID, "mesh_create: singular interpolation matrix");
+  std::vector<double> tab(metric_tab_size(n), 0.0);
+  for (int i = 0; i < n * n; ++i) {
+    tab[i] = t.S[i];
+    tab[n * n + i] = t.D[i];
+  }
+  for (int q = 0; q < n; ++q)
+    for (int j = 0; j < n; ++j) {
+      long double a = 0;
+      for (int m2 = 0; m2 < n; ++m2) a += static_cast<long double>(t.D[q * n + m2]) * sinv[m2 * n + j];
+      tab[2 * n * n + q * n + j] = static_cast<double>(a);
+    }
+  for (int i = 0; i < n; ++i) {
+    tab[3 * n * n + i] = t.g0[i];
+    tab[3 * n * n + n + i] = t.g1[i];
+    tab[3 * n * n + 2 * n + i] = t.wq[i];
+  }
+  std::vector<float> tab32(tab.begin(), tab.end());
+  dgmf_status st = m->mtab64.upload(tab.data(), tab.size() * sizeof(double));
+  if (st == DGMF_OK) st = m->mtab32.upload(tab32.data(), tab32.size() * sizeof(float));
+  if (st != DGMF_OK) return st;
+
+  const int64_t nc = m->ncells, n2 = n * n, n3 = n2 * n;
+  int64_t nlow = 0;
+  int lbase[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    lbase[d] = static_cast<int>(nlow);
+    if (!m->desc.periodic[d]) nlow += static_cast<int64_t>(nd[0]) * nd[1] * nd[2] / nd[d];
+  }
+  const int64_t o_cm = 0, o_fm = o_cm + nc * 7 * n3, o_ft = o_fm + nc * 21 * n2, o_lm = o_ft + nc * 3,
+                o_lt = o_lm + nlow * 7 * n2, total = o_lt + nlow;
+  if ((st = m->met64.alloc(static_cast<size_t>(total) * 8))) return st;
+  if ((st = m->met32.alloc(static_cast<size_t>(total) * 4))) return st;
+  auto setg = [&](auto& g, auto* base, auto* tb) {
+    g.nx = nd[0];
+    g.ny = nd[1];
+    g.nz = nd[2];
+    for (int d = 0; d < 3; ++d) {
+      g.per[d] = m->desc.periodic[d] ? 1 : 0;
+      g.lbase[d] = lbase[d];
+    }
+    g.cm = base + o_cm;
+    g.fm = base + o_fm;
+    g.ftau = base + o_ft;
+    g.lm = base + o_lm;
+    g.ltau = base + o_lt;
+    g.tab = tb;
+  };
+  double* b64 = static_cast<double*>(m->met64.p);
+  setg(m->mg64, static_cast<const double*>(b64), static_cast<const double*>(m->mtab64.p));
+  setg(m->mg32, static_cast<const float*>(m->met32.p), static_cast<const float*>(m->mtab32.p));
+  const double* x0[3] = {m->g64.x0[0], m->g64.x0[1], m->g64.x0[2]};
+  const double* h[3] = {m->g64.h[0], m->g64.h[1], m->g64.h[2]};
+  std::vector<long double> shinv;
+  if (!invert(3, m->shear.m, shinv)) return fail(DGMF_INVALID, "mesh_create: singular shear");
+  double shi[9];
+  for (int i = 0; i < 9; ++i) shi[i] = static_cast<double>(shinv[i]);
+  const double* wdev = static_cast<const double*>(m->mtab64.p) + 3 * n * n + 2 * n;
+  if ((st = launch_metric_fill(n, m->mg64, x0, h, shi, m->shear.det, wdev, b64 + o_cm, b64 + o_fm, b64 + o_ft,
+                               b64 + o_lm, b64 + o_lt, nullptr)))
+    return st;
+  if ((st = launch_to_f32(b64, static_cast<float*>(m->met32.p), total, nullptr))) return st;
+  DGMF_HIP_TRY(hipStreamSynchronize(nullptr));
+  return DGMF_OK;
+}
+
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 static bool overlap(const void* a, const void* b, size_t bytes) {
@@ -191,12 +294,42 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
     return fail(DGMF_INVALID, "mesh_create: lengths must be finite and > 0");
   if (!(d.y_tanh_gamma >= 0) || !std::isfinite(d.y_tanh_gamma))
     return fail(DGMF_INVALID, "mesh_create: y_tanh_gamma must be finite and >= 0");
+  Shear sh{{1, 0, 0, 0, 1, 0, 0, 0, 1}, 1.0, 0};
+  {
+    bool zero = true, ident = true;
+    for (int i = 0; i < 9; ++i) {
+      if (!std::isfinite(d.shear[i])) return fail(DGMF_INVALID, "mesh_create: shear entries must be finite");
+      if (d.shear[i] != 0.0) zero = false;
+      if (d.shear[i] != (i % 4 == 0 ? 1.0 : 0.0)) ident = false;
+    }
+    if (!zero && !ident) {
+      for (int i = 0; i < 9; ++i) sh.m[i] = d.shear[i];
+      const double* a = d.shear;
+      sh.det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+               a[2] * (a[3] * a[7] - a[4] * a[6]);
+      double nrm = 0.0;
+      for (int i = 0; i < 9; ++i) nrm = std::max(nrm, std::fabs(a[i]));
+      if (!(std::fabs(sh.det) > 1e-12 * nrm * nrm * nrm))
+        return fail(DGMF_INVALID, "mesh_create: shear matrix is singular");
+      sh.on = 1;
+      if (!d.store_qp_metric)
+        return fail(DGMF_INVALID, "mesh_create: a non-identity shear needs store_qp_metric = 1");
+    }
+  }
+  if (d.store_qp_metric) {
+    const int ndc[3] = {d.nx, d.ny, d.nz};
+    for (int a = 0; a < 3; ++a)
+      if (d.periodic[a] && ndc[a] < 2)
+        return fail(DGMF_UNSUPPORTED, "mesh_create: store_qp_metric needs >= 2 cells in periodic direction %d", a);
+  }
   const int64_t n = d.degree + 1;
   const int64_t ncells = static_cast<int64_t>(d.nx) * d.ny * d.nz;
   if (ncells > (int64_t(1) << 40) / (n * n * n)) return fail(DGMF_INVALID, "mesh_create: mesh too large");
   auto* m = new (std::nothrow) dgmf_mesh_;
   if (!m) return fail(DGMF_OOM, "mesh_create: host allocation failed");
   m->desc = d;
+  m->shear = sh;
+  m->desc.store_qp_metric = d.store_qp_metric ? 1 : 0;
   for (int a = 0; a < 3; ++a) m->desc.periodic[a] = d.periodic[a] ? 1 : 0;
   m->ncells = ncells;
   m->ndofs = ncells * n * n * n;
@@ -224,6 +357,10 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
   dgmf_status st = upload_geometry<double>(m, m->geo64, m->g64);
   if (st == DGMF_OK) st = upload_geometry<float>(m, m->geo32, m->g32);
   if (st == DGMF_OK) st = upload_tables<double>(m->tab, m->tab64);
+  if (st == DGMF_OK && m->desc.store_qp_metric) {
+    DeviceGuard dg(m->device);
+    st = setup_metric(m);
+  }
   if (st != DGMF_OK) {
     delete m;
     return st;
@@ -252,7 +389,7 @@ dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t strea
   if (!mesh || !xyz) return fail(DGMF_INVALID, "mesh_node_coords: null argument");
   if (!aligned(xyz, 8)) return fail(DGMF_INVALID, "mesh_node_coords: misaligned output");
   DeviceGuard dg(mesh->device);
-  return launch_node_coords(mesh->tab.n, mesh->g64, xyz, mesh->ncells, stream);
+  return launch_node_coords(mesh->tab.n, mesh->g64, mesh->shear, xyz, mesh->ncells, stream);
 }
 
 dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op* out) {
@@ -266,8 +403,6 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
   if (!std::isfinite(desc->mass_coeff) || !std::isfinite(desc->diff_coeff) || !std::isfinite(desc->penalty_scale) ||
       desc->mass_coeff < 0 || desc->diff_coeff < 0 || !(desc->penalty_scale > 0))
     return fail(DGMF_INVALID, "sipg_create: coefficients must be finite, mass/diff >= 0, penalty > 0");
-  if (mesh->desc.store_qp_metric)
-    return fail(DGMF_UNSUPPORTED, "sipg_create: per-quadrature-point metric not available in this build");
   DeviceGuard dg(mesh->device);
   auto* op = new (std::nothrow) dgmf_op_;
   if (!op) return fail(DGMF_OOM, "sipg_create: host allocation failed");
@@ -307,6 +442,18 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
   op->g32.mu = static_cast<float>(desc->mass_coeff);
   op->g32.nu = static_cast<float>(desc->diff_coeff);
   op->g32.tab = static_cast<const float*>(op->tab32.p);
+  if (mesh->desc.store_qp_metric) {
+    // stored metric: tau geometry already carries (k+1)^2
+    op->metric = true;
+    op->mg64 = mesh->mg64;
+    op->mg32 = mesh->mg32;
+    op->mg64.mu = desc->mass_coeff;
+    op->mg64.nu = desc->diff_coeff;
+    op->mg64.pen = desc->penalty_scale;
+    op->mg32.mu = static_cast<float>(desc->mass_coeff);
+    op->mg32.nu = static_cast<float>(desc->diff_coeff);
+    op->mg32.pen = static_cast<float>(desc->penalty_scale);
+  }
   mesh->nops++;
   *out = op;
   return DGMF_OK;
@@ -320,12 +467,9 @@ dgmf_status dgmf_operator_apply(dgmf_op op, dgmf_dtype dtype, const void* src, v
   if (!aligned(src, es) || !aligned(dst, es)) return fail(DGMF_INVALID, "operator_apply: misaligned vector");
   if (overlap(src, dst, es * op->mesh->ndofs)) return fail(DGMF_INVALID, "operator_apply: src and dst overlap");
   DeviceGuard dg(op->mesh->device);
-  const int n = op->mesh->desc.degree + 1;
   if (dtype == DGMF_F64)
-    return launch_sipg_cart_apply<double>(n, op->g64, static_cast<const double*>(src), static_cast<double*>(dst),
-                                          op->mesh->ncells, nullptr, nullptr, stream);
-  return launch_sipg_cart_apply<float>(n, op->g32, static_cast<const float*>(src), static_cast<float*>(dst),
-                                       op->mesh->ncells, nullptr, nullptr, stream);
+    return sipg_apply<double>(op, static_cast<const double*>(src), static_cast<double*>(dst), nullptr, nullptr, stream);
+  return sipg_apply<float>(op, static_cast<const float*>(src), static_cast<float*>(dst), nullptr, nullptr, stream);
 }
 
 dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hipStream_t stream) {
@@ -336,6 +480,10 @@ dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hip
   if (!aligned(diag, es)) return fail(DGMF_INVALID, "operator_diagonal: misaligned vector");
   DeviceGuard dg(op->mesh->device);
   const int n = op->mesh->desc.degree + 1;
+  if (op->metric) {
+    if (dtype == DGMF_F64) return launch_sipg_metric_diag<double>(n, op->mg64, static_cast<double*>(diag), stream);
+    return launch_sipg_metric_diag<float>(n, op->mg64, static_cast<float*>(diag), stream);
+  }
   if (dtype == DGMF_F64)
     return launch_sipg_cart_diag<double>(n, op->g64, static_cast<double*>(diag), op->mesh->ncells, stream);
   return launch_sipg_cart_diag<float>(n, op->g32, static_cast<float*>(diag), op->mesh->ncells, stream);
@@ -345,7 +493,7 @@ dgmf_status dgmf_quadrature_points(dgmf_op op, double* xyz, hipStream_t stream) 
   if (!op || op->kind != 1) return fail(DGMF_INVALID, "quadrature_points: not an SIPG operator");
   if (!xyz || !aligned(xyz, 8)) return fail(DGMF_INVALID, "quadrature_points: null or misaligned output");
   DeviceGuard dg(op->mesh->device);
-  return launch_qp_coords(op->tab.n, op->nq, op->g64, xyz, op->mesh->ncells, stream);
+  return launch_qp_coords(op->tab.n, op->nq, op->g64, op->mesh->shear, xyz, op->mesh->ncells, stream);
 }
 
 dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_t stream) {
@@ -356,8 +504,44 @@ dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_
   if (overlap(f_qp, b, 8 * std::min<int64_t>(op->mesh->ndofs, op->mesh->ncells * nq3)))
     return fail(DGMF_INVALID, "integrate: input and output overlap");
   DeviceGuard dg(op->mesh->device);
-  return launch_integrate(op->tab.n, op->nq, op->g64, f_qp, b, op->mesh->ncells, stream);
+  return launch_integrate(op->tab.n, op->nq, op->g64, op->mesh->shear, f_qp, b, op->mesh->ncells, stream);
 }
+
+}  // extern "C"
+
+namespace dgmf {
+
+template <typename T>
+dgmf_status sipg_apply(dgmf_op op, const T* src, T* dst, double* partials, const int* stop, hipStream_t s) {
+  const int n = op->mesh->desc.degree + 1;
+  if (op->metric) {
+    if constexpr (std::is_same<T, double>::value)
+      return launch_sipg_metric_apply<double>(n, op->mg64, src, dst, partials, stop, s);
+    else
+      return launch_sipg_metric_apply<float>(n, op->mg32, src, dst, partials, stop, s);
+  }
+  if constexpr (std::is_same<T, double>::value)
+    return launch_sipg_cart_apply<double>(n, op->g64, src, dst, op->mesh->ncells, partials, stop, s);
+  else
+    return launch_sipg_cart_apply<float>(n, op->g32, src, dst, op->mesh->ncells, partials, stop, s);
+}
+template dgmf_status sipg_apply<double>(dgmf_op, const double*, double*, double*, const int*, hipStream_t);
+template dgmf_status sipg_apply<float>(dgmf_op, const float*, float*, double*, const int*, hipStream_t);
+
+dgmf_status sipg_diag64(dgmf_op op, double* diag, hipStream_t s) {
+  const int n = op->mesh->desc.degree + 1;
+  if (op->metric) return launch_sipg_metric_diag<double>(n, op->mg64, diag, s);
+  return launch_sipg_cart_diag<double>(n, op->g64, diag, op->mesh->ncells, s);
+}
+
+int64_t sipg_apply_blocks(dgmf_op op) {
+  if (op->metric) return op->mesh->ncells;
+  return sipg_cart_blocks(op->mesh->desc.degree + 1, op->g64);
+}
+
+}  // namespace dgmf
+
+extern "C" {
 
 dgmf_status dgmf_op_destroy(dgmf_op op) {
   if (!op) return DGMF_OK;
@@ -376,6 +560,7 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
   const int k = mesh->desc.degree, n = k + 1;
   const int nq = desc->n_q > 0 ? desc->n_q : (3 * (k + 1)) / 2;
   if (desc->n_q < 0) return fail(DGMF_INVALID, "convective_create: n_q must be >= 0");
+  if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "convective_create: sheared meshes are not supported");
   if (!conv_supported(n, nq))
     return fail(DGMF_UNSUPPORTED, "convective_create: degree %d with %d points per direction not built", k, nq);
   DeviceGuard dg(mesh->device);

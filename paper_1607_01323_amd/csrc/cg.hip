@@ -465,16 +465,9 @@ dgmf_status validate(dgmf_op op, const dgmf_cg_params* p) {
 }
 
 int64_t nparts_for(dgmf_op op) {
-  const int64_t a = sipg_cart_blocks(op->mesh->desc.degree + 1, op->g64);
+  const int64_t a = sipg_apply_blocks(op);
   return a > kVecBlocks ? a : kVecBlocks;
 }
-
-template <typename T>
-const CartGeom<T>& geom(dgmf_op op);
-template <>
-const CartGeom<double>& geom<double>(dgmf_op op) { return op->g64; }
-template <>
-const CartGeom<float>& geom<float>(dgmf_op op) { return op->g32; }
 
 struct Solver {
   dgmf_op op;
@@ -501,8 +494,7 @@ struct Solver {
 
   template <typename T>
   dgmf_status apply(const T* src, T* dst, bool with_partials) {
-    return launch_sipg_cart_apply<T>(n, geom<T>(op), src, dst, op->mesh->ncells, with_partials ? partials : nullptr,
-                                     &st->status, s);
+    return sipg_apply<T>(op, src, dst, with_partials ? partials : nullptr, &st->status, s);
   }
 
   // Lanczos in precision T on D^{-1/2} H D^{-1/2}; fills lambda and the Chebyshev coefficients.
@@ -528,7 +520,7 @@ struct Solver {
     for (int j = 0; j < m; ++j) {
       hipLaunchKernelGGL((k_lz_scale<T>), G, B, 0, s, v, dsq, t, N);
       DGMF_LAUNCH_CHECK("k_lz_scale");
-      if ((e = launch_sipg_cart_apply<T>(n, geom<T>(op), t, w, op->mesh->ncells, nullptr, nullptr, s))) return e;
+      if ((e = sipg_apply<T>(op, t, w, nullptr, nullptr, s))) return e;
       hipLaunchKernelGGL((k_lz_w<T>), G, B, 0, s, w, dsq, v, vp, N, st, j, partials);
       DGMF_LAUNCH_CHECK("k_lz_w");
       if ((e = scalar(M_LZ_ALPHA, kVecBlocks, j, 0))) return e;
@@ -657,7 +649,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
   double* dinv = S.at<double>(L.dinv);
   double* diag = S.at<double>(L.diag);
   const dim3 G(kVecBlocks), B(256);
-  const int napply = sipg_cart_blocks(S.n, op->g64);
+  const int napply = static_cast<int>(sipg_apply_blocks(op));
   auto t0 = std::chrono::steady_clock::now();
 
   // ---- set-up: state, diagonal, eigenvalue estimate
@@ -666,7 +658,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
   init.flexible = params->flexible ? 1 : 0;
   init.max_iter = params->max_iter;
   DGMF_HIP_TRY(hipMemcpyAsync(S.st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
-  if ((e = launch_sipg_cart_diag<double>(S.n, op->g64, diag, op->mesh->ncells, stream))) return e;
+  if ((e = sipg_diag64(op, diag, stream))) return e;
   hipLaunchKernelGGL(k_recip, G, B, 0, stream, diag, dinv, N);
   DGMF_LAUNCH_CHECK("k_recip");
   if (cheb) {
@@ -696,8 +688,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
   if ((e = S.scalar(M_BNORM, kVecBlocks, 0, 0))) return e;
   hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(1), 0, stream, S.st, params->rtol * params->rtol, params->max_iter);
   DGMF_LAUNCH_CHECK("k_set_tol");
-  if ((e = launch_sipg_cart_apply<double>(S.n, op->g64, x, q, op->mesh->ncells, S.partials, nullptr, stream)))
-    return e;
+  if ((e = sipg_apply<double>(op, x, q, S.partials, nullptr, stream))) return e;
   if ((e = S.scalar(M_QMEAN, napply, 0, 0))) return e;
   if (cheb) {
     hipLaunchKernelGGL(k_init_r, G, B, 0, stream, bp, q, r, dinv, static_cast<double*>(nullptr), N, S.st,

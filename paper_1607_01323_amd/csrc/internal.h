@@ -16,6 +16,21 @@ constexpr int kMinDegree = 1;
 constexpr int kMaxDegree = 7;
 constexpr int kMaxConvPoints = 12;
 
+// Geometry of a mesh whose metric is stored at every quadrature point.
+template <typename T>
+struct MetricGeom {
+  int nx, ny, nz;
+  int per[3];
+  const T* cm;     // [ncells][7][n^3]: G00 G01 G02 G11 G12 G22 (w detJ J^-1 J^-T), w detJ
+  const T* fm;     // [ncells][3][7][n^2]: high face of each direction: wdA, vL(3), vR(3)
+  const T* ftau;   // [ncells][3]: penalty geometry of those faces
+  const T* lm;     // low boundary faces of non-periodic directions, [faces][7][n^2]
+  const T* ltau;
+  int lbase[3];    // first low-boundary face of direction d
+  T mu, nu, pen;   // mass, diffusion, penalty scale s
+  const T* tab;    // S, D, Dg (n x n), l'(0), l'(1), w (n)
+};
+
 struct ConvGeom {
   int nx, ny, nz;
   int per[3];
@@ -113,10 +128,18 @@ struct TabLayout {
   __host__ __device__ int size() const { return e1t() + n; }
 };
 
-dgmf_status launch_node_coords(int n, const CartGeom<double>& g, double* xyz, int64_t ncells, hipStream_t s);
-dgmf_status launch_qp_coords(int n, int nq, const CartGeom<double>& g, double* xyz, int64_t ncells,
-                             hipStream_t s);
-dgmf_status launch_integrate(int n, int nq, const CartGeom<double>& g, const double* f, double* b,
+// Constant lattice map x = m p of a sheared box (on = 0: identity).
+struct Shear {
+  double m[9];
+  double det;
+  int on;
+};
+
+dgmf_status launch_node_coords(int n, const CartGeom<double>& g, const Shear& sh, double* xyz, int64_t ncells,
+                               hipStream_t s);
+dgmf_status launch_qp_coords(int n, int nq, const CartGeom<double>& g, const Shear& sh, double* xyz,
+                             int64_t ncells, hipStream_t s);
+dgmf_status launch_integrate(int n, int nq, const CartGeom<double>& g, const Shear& sh, const double* f, double* b,
                              int64_t ncells, hipStream_t s);
 
 // Operator apply; when partials is not null, also writes per-block partial
@@ -131,11 +154,35 @@ dgmf_status launch_sipg_cart_diag(int n, const CartGeom<T>& g, T* diag, int64_t 
 // Grid size of the apply kernel (also the number of partial-sum rows it writes).
 int sipg_cart_blocks(int n, const CartGeom<double>& g);
 
+// Apply with the metric stored at the quadrature points; partials/stop as above,
+// one partial row per cell.
+template <typename T>
+dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials,
+                                     const int* stop, hipStream_t s);
+template <typename TO>
+dgmf_status launch_sipg_metric_diag(int n, const MetricGeom<double>& g, TO* diag, hipStream_t s);
+// Fills cm, fm, ftau, lm, ltau of a lattice mesh with J = Sh diag(h_c).
+dgmf_status launch_metric_fill(int n, const MetricGeom<double>& g, const double* const x0[3], const double* const h[3],
+                               const double shinv[9], double shdet, const double* wq, double* cm, double* fm,
+                               double* ftau, double* lm, double* ltau, hipStream_t s);
+
+dgmf_status launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
+// Layout of the metric tables: S, D, Dg = D S^{-1} (n x n), l'(0), l'(1), Gauss weights w (n).
+constexpr int metric_tab_size(int n) { return 3 * n * n + 3 * n; }
+
 bool conv_supported(int n, int nq);
 dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, double* C, int64_t ncells,
                             hipStream_t s);
 dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
                             int64_t ncells, hipStream_t s);
+
+// Dispatch over the two SIPG apply kernels (tables of axis-aligned cells or
+// metric stored at the quadrature points), and the number of partial rows the
+// apply writes.
+template <typename T>
+dgmf_status sipg_apply(dgmf_op op, const T* src, T* dst, double* partials, const int* stop, hipStream_t s);
+dgmf_status sipg_diag64(dgmf_op op, double* diag, hipStream_t s);
+int64_t sipg_apply_blocks(dgmf_op op);
 
 }  // namespace dgmf
 
@@ -150,6 +197,11 @@ struct dgmf_mesh_ {
   dgmf::CartGeom<float> g32{};
   dgmf::Tables1D tab;              // tables with n_q = k+1
   dgmf::DevBuf tab64;
+  dgmf::Shear shear{{1, 0, 0, 0, 1, 0, 0, 0, 1}, 1.0, 0};
+  // stored quadrature-point geometry (store_qp_metric): fp64 and fp32 copies
+  dgmf::DevBuf met64, met32, mtab64, mtab32;
+  dgmf::MetricGeom<double> mg64{};   // coefficients unset
+  dgmf::MetricGeom<float> mg32{};
   int nops = 0;                    // live operators built on this mesh
 };
 
@@ -164,4 +216,7 @@ struct dgmf_op_ {
   dgmf::CartGeom<float> g32{};
   dgmf::DevBuf ctab;               // convective tables
   dgmf::ConvGeom cgeo{};
+  dgmf::MetricGeom<double> mg64{};   // metric path (mesh->desc.store_qp_metric)
+  dgmf::MetricGeom<float> mg32{};
+  bool metric = false;
 };

@@ -2,12 +2,19 @@
 // and the load-vector integral b_i = sum_K (f, phi_i)_K (Sec. 4.4 right-hand
 // sides) by the operator's Gauss rule, f given at the quadrature points.
 // These run once per problem, so they use one thread per output value.
+// Sheared lattices map every box point p to S p.
 #include "internal.h"
 
 namespace dgmf {
 namespace {
 
-__global__ void k_node_coords(int n, CartGeom<double> g, double* __restrict__ xyz, int64_t ncells, TabLayout L) {
+__device__ __forceinline__ void store_point(const Shear& sh, const double p[3], double* xyz, int64_t N, int64_t gid) {
+  for (int d = 0; d < 3; ++d)
+    xyz[d * N + gid] = sh.on ? sh.m[3 * d] * p[0] + sh.m[3 * d + 1] * p[1] + sh.m[3 * d + 2] * p[2] : p[d];
+}
+
+__global__ void k_node_coords(int n, CartGeom<double> g, Shear sh, double* __restrict__ xyz, int64_t ncells,
+                              TabLayout L) {
   const int64_t n3 = static_cast<int64_t>(n) * n * n;
   const int64_t N = ncells * n3;
   const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -18,10 +25,13 @@ __global__ void k_node_coords(int n, CartGeom<double> g, double* __restrict__ xy
   const int c[3] = {static_cast<int>(cell % g.nx), static_cast<int>((cell / g.nx) % g.ny),
                     static_cast<int>(cell / (static_cast<int64_t>(g.nx) * g.ny))};
   const double* nodes = g.tab + L.nodes();
-  for (int d = 0; d < 3; ++d) xyz[d * N + gid] = g.x0[d][c[d]] + g.h[d][c[d]] * nodes[idx[d]];
+  double p[3];
+  for (int d = 0; d < 3; ++d) p[d] = g.x0[d][c[d]] + g.h[d][c[d]] * nodes[idx[d]];
+  store_point(sh, p, xyz, N, gid);
 }
 
-__global__ void k_qp_coords(int nq, CartGeom<double> g, double* __restrict__ xyz, int64_t ncells, TabLayout L) {
+__global__ void k_qp_coords(int nq, CartGeom<double> g, Shear sh, double* __restrict__ xyz, int64_t ncells,
+                            TabLayout L) {
   const int64_t q3 = static_cast<int64_t>(nq) * nq * nq;
   const int64_t M = ncells * q3;
   const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -32,11 +42,13 @@ __global__ void k_qp_coords(int nq, CartGeom<double> g, double* __restrict__ xyz
   const int c[3] = {static_cast<int>(cell % g.nx), static_cast<int>((cell / g.nx) % g.ny),
                     static_cast<int>(cell / (static_cast<int64_t>(g.nx) * g.ny))};
   const double* xq = g.tab + L.xq();
-  for (int d = 0; d < 3; ++d) xyz[d * M + gid] = g.x0[d][c[d]] + g.h[d][c[d]] * xq[idx[d]];
+  double p[3];
+  for (int d = 0; d < 3; ++d) p[d] = g.x0[d][c[d]] + g.h[d][c[d]] * xq[idx[d]];
+  store_point(sh, p, xyz, M, gid);
 }
 
-__global__ void k_integrate(int n, int nq, CartGeom<double> g, const double* __restrict__ f, double* __restrict__ b,
-                            int64_t ncells, TabLayout L) {
+__global__ void k_integrate(int n, int nq, CartGeom<double> g, Shear sh, const double* __restrict__ f,
+                            double* __restrict__ b, int64_t ncells, TabLayout L) {
   const int64_t n3 = static_cast<int64_t>(n) * n * n;
   const int64_t q3 = static_cast<int64_t>(nq) * nq * nq;
   const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -46,7 +58,7 @@ __global__ void k_integrate(int n, int nq, CartGeom<double> g, const double* __r
   const int i = loc % n, j = (loc / n) % n, l = loc / (n * n);
   const int c[3] = {static_cast<int>(cell % g.nx), static_cast<int>((cell / g.nx) % g.ny),
                     static_cast<int>(cell / (static_cast<int64_t>(g.nx) * g.ny))};
-  const double vol = g.h[0][c[0]] * g.h[1][c[1]] * g.h[2][c[2]];
+  const double vol = g.h[0][c[0]] * g.h[1][c[1]] * g.h[2][c[2]] * (sh.on ? fabs(sh.det) : 1.0);
   const double* S = g.tab + L.S();
   const double* w = g.tab + L.wq();
   const double* fc = f + cell * q3;
@@ -67,25 +79,28 @@ unsigned grid_for(int64_t total) { return static_cast<unsigned>((total + 255) / 
 
 }  // namespace
 
-dgmf_status launch_node_coords(int n, const CartGeom<double>& g, double* xyz, int64_t ncells, hipStream_t s) {
+dgmf_status launch_node_coords(int n, const CartGeom<double>& g, const Shear& sh, double* xyz, int64_t ncells,
+                               hipStream_t s) {
   TabLayout L{n, n};
-  hipLaunchKernelGGL(k_node_coords, dim3(grid_for(ncells * n * n * n)), dim3(256), 0, s, n, g, xyz, ncells, L);
+  hipLaunchKernelGGL(k_node_coords, dim3(grid_for(ncells * n * n * n)), dim3(256), 0, s, n, g, sh, xyz, ncells, L);
   DGMF_LAUNCH_CHECK("k_node_coords");
   return DGMF_OK;
 }
 
-dgmf_status launch_qp_coords(int n, int nq, const CartGeom<double>& g, double* xyz, int64_t ncells,
-                             hipStream_t s) {
+dgmf_status launch_qp_coords(int n, int nq, const CartGeom<double>& g, const Shear& sh, double* xyz,
+                             int64_t ncells, hipStream_t s) {
   TabLayout L{n, nq};
-  hipLaunchKernelGGL(k_qp_coords, dim3(grid_for(ncells * nq * nq * nq)), dim3(256), 0, s, nq, g, xyz, ncells, L);
+  hipLaunchKernelGGL(k_qp_coords, dim3(grid_for(ncells * nq * nq * nq)), dim3(256), 0, s, nq, g, sh, xyz, ncells,
+                     L);
   DGMF_LAUNCH_CHECK("k_qp_coords");
   return DGMF_OK;
 }
 
-dgmf_status launch_integrate(int n, int nq, const CartGeom<double>& g, const double* f, double* b,
+dgmf_status launch_integrate(int n, int nq, const CartGeom<double>& g, const Shear& sh, const double* f, double* b,
                              int64_t ncells, hipStream_t s) {
   TabLayout L{n, nq};
-  hipLaunchKernelGGL(k_integrate, dim3(grid_for(ncells * n * n * n)), dim3(256), 0, s, n, nq, g, f, b, ncells, L);
+  hipLaunchKernelGGL(k_integrate, dim3(grid_for(ncells * n * n * n)), dim3(256), 0, s, n, nq, g, sh, f, b, ncells,
+                     L);
   DGMF_LAUNCH_CHECK("k_integrate");
   return DGMF_OK;
 }

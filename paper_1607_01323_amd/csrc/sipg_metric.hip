@@ -1,0 +1,659 @@
+// SIPG Laplace / Helmholtz apply with geometry stored at every quadrature
+// point (gfx950): the sum-factorised evaluation of Sec. 5 for general
+// (parallelepiped) affine cells, streaming the metric from HBM.
+//
+// Stored geometry (filled once per mesh by k_metric_fill):
+//   cell point q:  G = w_q detJ J^{-1} J^{-T} (6 symmetric entries), m = w_q detJ
+//   face point q:  wdA = tangential weight x surface Jacobian,
+//                  vL = J_L^{-1} n wdA, vR = J_R^{-1} n wdA   (n: unit normal from L to R;
+//                  on a boundary face L is the cell and n points outwards)
+//   face:          tau geometry (k+1)^2 (A_int/2 + A_Dir)/V, maximum over both cells.
+// With hat-gradients of the reference basis,
+//   (grad v, grad u)_K = sum_q hat(grad v)^T G hat(grad u),
+//   (grad u . n) wdA   = hat(grad u) . (J^{-1} n wdA).
+// Interior faces (Sec. 3.2, eqs. ipflux, tau), [u] = uL - uR, {{du/dn}} over both sides:
+//   - ({{grad v}}.n, [u]) - ([v], {{grad u}}.n) + tau ([v], [u])
+// Dirichlet faces: - (grad v.n, u) - (v, grad u.n) + 2 tau (v, u).
+//
+// Kernel layout: one cell per workgroup (128 threads); the cell tensor and
+// its quadrature-point fields live in LDS; the 12 cell sweeps and the face
+// sweeps are distributed over the threads line by line; faces are handled
+// cell-centrically, one at a time.
+#include "internal.h"
+
+namespace dgmf {
+namespace {
+
+constexpr int kMetThreads = 128;
+
+// ----------------------------------------------------------- table layout
+struct MTab {
+  int n;
+  __host__ __device__ int S() const { return 0; }
+  __host__ __device__ int D() const { return n * n; }
+  __host__ __device__ int Dg() const { return 2 * n * n; }
+  __host__ __device__ int g0() const { return 3 * n * n; }
+  __host__ __device__ int g1() const { return 3 * n * n + n; }
+  __host__ __device__ int w() const { return 3 * n * n + 2 * n; }
+  __host__ __device__ int size() const { return 3 * n * n + 3 * n; }
+};
+
+// ------------------------------------------------------------ LDS sweeps
+// 3D array [z][y][x] of extent N^3.  For every line along `axis`:
+//   out[line][q] (+)= sum_m A'[q][m] in[line][m],  A' = A or A^T (row-major N x N)
+template <int N, bool TR, bool ACC, typename T>
+__device__ __forceinline__ void sweep3(const T* __restrict__ A, const T* in, T* out, int axis, int tid, int nthr) {
+  constexpr int N2 = N * N;
+  const int st = axis == 0 ? 1 : (axis == 1 ? N : N2);
+  for (int job = tid; job < N2; job += nthr) {
+    const int a = job % N, b = job / N;
+    const int base = axis == 0 ? job * N : (axis == 1 ? b * N2 + a : job);
+    T v[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = in[base + m * st];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      T s = ACC ? out[base + q * st] : T(0);
+#pragma unroll
+      for (int m = 0; m < N; ++m) s = fma(TR ? A[m * N + q] : A[q * N + m], v[m], s);
+      out[base + q * st] = s;
+    }
+  }
+}
+
+// 2D plane [p2][p1] of extent N^2; lines along axis 0 (p1) or 1 (p2).
+template <int N, bool TR, bool ACC, typename T>
+__device__ __forceinline__ void sweep2(const T* __restrict__ A, const T* in, T* out, int axis, int tid, int nthr) {
+  const int st = axis == 0 ? 1 : N;
+  for (int job = tid; job < N; job += nthr) {
+    const int base = axis == 0 ? job * N : job;
+    T v[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = in[base + m * st];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      T s = ACC ? out[base + q * st] : T(0);
+#pragma unroll
+      for (int m = 0; m < N; ++m) s = fma(TR ? A[m * N + q] : A[q * N + m], v[m], s);
+      out[base + q * st] = s;
+    }
+  }
+}
+
+// several independent plane sweeps in one pass: job (plane k, line)
+template <typename T>
+struct PlaneOp {
+  const T* A;
+  const T* in;
+  T* out;
+  int axis, tr, acc;
+};
+
+template <int N, int K, typename T>
+__device__ __forceinline__ void plane_ops(const PlaneOp<T> (&ops)[K], int tid, int nthr) {
+  for (int job = tid; job < K * N; job += nthr) {
+    const int k = job / N, line = job % N;
+    const PlaneOp<T>& o = ops[k];
+    const int st = o.axis == 0 ? 1 : N;
+    const int base = o.axis == 0 ? line * N : line;
+    T v[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = o.in[base + m * st];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      T s = o.acc ? o.out[base + q * st] : T(0);
+#pragma unroll
+      for (int m = 0; m < N; ++m) s = fma(o.tr ? o.A[m * N + q] : o.A[q * N + m], v[m], s);
+      o.out[base + q * st] = s;
+    }
+  }
+}
+
+// node index of face-plane entry (p1 along t1, p2 along t2) of the plane at
+// coordinate e along direction d
+template <int N>
+__device__ __forceinline__ int fnode(int d, int e, int p1, int p2) {
+  if (d == 0) return (p2 * N + p1) * N + e;
+  if (d == 1) return (p2 * N + e) * N + p1;
+  return (e * N + p2) * N + p1;
+}
+
+template <typename T>
+__device__ __forceinline__ int plane_index(const MetricGeom<T>& g, int d, int c0, int c1, int c2) {
+  if (d == 0) return c2 * g.ny + c1;
+  if (d == 1) return c2 * g.nx + c0;
+  return c1 * g.nx + c0;
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(kMetThreads) k_sipg_metric_apply(const T* __restrict__ src,
+                                                                   T* __restrict__ dst, const MetricGeom<T> g,
+                                                                   double* __restrict__ partials,
+                                                                   const int* stop) {
+  if (stop && *stop) return;
+  constexpr int N2 = N * N, N3 = N2 * N;
+  __shared__ T sU[N3], sO[N3], sA[N3], sB[3 * N3], sC[N3];
+  __shared__ T sF[24 * N2];
+  __shared__ double s_red[3 * (kMetThreads / 64)];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int cell = blockIdx.x;
+  const int c[3] = {cell % g.nx, (cell / g.nx) % g.ny, cell / (g.nx * g.ny)};
+  const int nd[3] = {g.nx, g.ny, g.nz};
+  const int stride[3] = {1, g.nx, g.nx * g.ny};
+  const T* S = g.tab + MTab{N}.S();
+  const T* D = g.tab + MTab{N}.D();
+  const T* Dg = g.tab + MTab{N}.Dg();
+  const T* g0 = g.tab + MTab{N}.g0();
+  const T* g1 = g.tab + MTab{N}.g1();
+  for (int e = tid; e < N3; e += nthr) {
+    sU[e] = src[cell * N3 + e];
+    sO[e] = T(0);
+  }
+  __syncthreads();
+  // ---- cell integral: values and reference gradients at the Gauss points
+  sweep3<N, false, false>(S, sU, sC, 0, tid, nthr);
+  __syncthreads();
+  sweep3<N, false, false>(S, sC, sB, 1, tid, nthr);
+  __syncthreads();
+  sweep3<N, false, false>(S, sB, sA, 2, tid, nthr);   // sA = u at the points
+  __syncthreads();
+  sweep3<N, false, false>(Dg, sA, sB, 0, tid, nthr);
+  sweep3<N, false, false>(Dg, sA, sB + N3, 1, tid, nthr);
+  sweep3<N, false, false>(Dg, sA, sB + 2 * N3, 2, tid, nthr);
+  __syncthreads();
+  {
+    const T* cm = g.cm + static_cast<int64_t>(cell) * 7 * N3;
+    for (int q = tid; q < N3; q += nthr) {
+      const T gx = sB[q], gy = sB[N3 + q], gz = sB[2 * N3 + q];
+      const T G00 = cm[q], G01 = cm[N3 + q], G02 = cm[2 * N3 + q];
+      const T G11 = cm[3 * N3 + q], G12 = cm[4 * N3 + q], G22 = cm[5 * N3 + q], m = cm[6 * N3 + q];
+      sB[q] = g.nu * (G00 * gx + G01 * gy + G02 * gz);
+      sB[N3 + q] = g.nu * (G01 * gx + G11 * gy + G12 * gz);
+      sB[2 * N3 + q] = g.nu * (G02 * gx + G12 * gy + G22 * gz);
+      sC[q] = g.mu * m * sA[q];
+    }
+  }
+  __syncthreads();
+  sweep3<N, true, true>(Dg, sB, sC, 0, tid, nthr);
+  __syncthreads();
+  sweep3<N, true, true>(Dg, sB + N3, sC, 1, tid, nthr);
+  __syncthreads();
+  sweep3<N, true, true>(Dg, sB + 2 * N3, sC, 2, tid, nthr);
+  __syncthreads();
+  sweep3<N, true, false>(S, sC, sA, 2, tid, nthr);
+  __syncthreads();
+  sweep3<N, true, false>(S, sA, sC, 1, tid, nthr);
+  __syncthreads();
+  sweep3<N, true, true>(S, sC, sO, 0, tid, nthr);
+  __syncthreads();
+
+  // ---- faces
+  // sF layout (planes of N2): 0 Pown, 1 PNown, 2 Pnb, 3 PNnb, 4..5 stage own, 6..7 stage nb,
+  //  8 val_own, 9 dt1_own, 10 dt2_own, 11 dn_own, 12 val_nb, 13 dt1_nb, 14 dt2_nb, 15 dn_nb,
+  //  16 fv, 17 fg_d, 18 fg_t1, 19 fg_t2, 20..23 lift stages
+#pragma unroll 1
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, s = f & 1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    int cn = c[d] + (s ? 1 : -1), nb = -1;
+    if (cn < 0 || cn >= nd[d]) {
+      if (g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
+      else cn = -1;
+    }
+    if (cn >= 0) nb = cell + (cn - c[d]) * stride[d];
+    const T* gs = s ? g1 : g0;      // normal derivative row at the own face
+    const T* gn = s ? g0 : g1;      // ... at the neighbour's face
+    const int eo = s ? N - 1 : 0, en = s ? 0 : N - 1;
+    for (int p = tid; p < N2; p += nthr) {
+      const int p1 = p % N, p2 = p / N;
+      sF[0 * N2 + p] = sU[fnode<N>(d, eo, p1, p2)];
+      T dn = T(0);
+#pragma unroll
+      for (int m = 0; m < N; ++m) dn = fma(gs[m], sU[fnode<N>(d, m, p1, p2)], dn);
+      sF[1 * N2 + p] = dn;
+      if (nb >= 0) {
+        const T* un = src + static_cast<int64_t>(nb) * N3;
+        sF[2 * N2 + p] = un[fnode<N>(d, en, p1, p2)];
+        T dnn = T(0);
+#pragma unroll
+        for (int m = 0; m < N; ++m) dnn = fma(gn[m], un[fnode<N>(d, m, p1, p2)], dnn);
+        sF[3 * N2 + p] = dnn;
+      }
+    }
+    __syncthreads();
+    // first sweeps along t1 (p1): S P, D P for both sides, S PN for both sides
+    {
+      const PlaneOp<T> ops[6] = {{S, sF + 0 * N2, sF + 4 * N2, 0, 0, 0}, {D, sF + 0 * N2, sF + 5 * N2, 0, 0, 0},
+                              {S, sF + 1 * N2, sF + 20 * N2, 0, 0, 0}, {S, sF + 2 * N2, sF + 6 * N2, 0, 0, 0},
+                              {D, sF + 2 * N2, sF + 7 * N2, 0, 0, 0}, {S, sF + 3 * N2, sF + 21 * N2, 0, 0, 0}};
+      plane_ops<N, 6>(ops, tid, nthr);
+    }
+    __syncthreads();
+    // second sweeps along t2 (p2): val = S(SP), dt1 = S(DP), dt2 = D(SP), dn = S(S PN)
+    {
+      const PlaneOp<T> ops[8] = {{S, sF + 4 * N2, sF + 8 * N2, 1, 0, 0},   {S, sF + 5 * N2, sF + 9 * N2, 1, 0, 0},
+                              {D, sF + 4 * N2, sF + 10 * N2, 1, 0, 0},  {S, sF + 20 * N2, sF + 11 * N2, 1, 0, 0},
+                              {S, sF + 6 * N2, sF + 12 * N2, 1, 0, 0},  {S, sF + 7 * N2, sF + 13 * N2, 1, 0, 0},
+                              {D, sF + 6 * N2, sF + 14 * N2, 1, 0, 0},  {S, sF + 21 * N2, sF + 15 * N2, 1, 0, 0}};
+      plane_ops<N, 8>(ops, tid, nthr);
+    }
+    __syncthreads();
+    // flux at the face points
+    {
+      const T* fm;
+      T tau;
+      bool own_is_L;
+      if (s == 1) {
+        fm = g.fm + (static_cast<int64_t>(cell) * 3 + d) * 7 * N2;
+        tau = g.ftau[cell * 3 + d];
+        own_is_L = true;
+      } else if (nb >= 0) {
+        fm = g.fm + (static_cast<int64_t>(nb) * 3 + d) * 7 * N2;
+        tau = g.ftau[nb * 3 + d];
+        own_is_L = false;
+      } else {
+        const int pi = plane_index(g, d, c[0], c[1], c[2]);
+        fm = g.lm + (static_cast<int64_t>(g.lbase[d]) + pi) * 7 * N2;
+        tau = g.ltau[g.lbase[d] + pi];
+        own_is_L = true;
+      }
+      tau *= g.pen;
+      for (int p = tid; p < N2; p += nthr) {
+        const T wdA = fm[p];
+        const T vL[3] = {fm[N2 + p], fm[2 * N2 + p], fm[3 * N2 + p]};
+        const T vR[3] = {fm[4 * N2 + p], fm[5 * N2 + p], fm[6 * N2 + p]};
+        const T* vo = own_is_L ? vL : vR;
+        const T* vn = own_is_L ? vR : vL;
+        T go[3], gnb[3];
+        go[d] = sF[11 * N2 + p];
+        go[t1] = sF[9 * N2 + p];
+        go[t2] = sF[10 * N2 + p];
+        const T uo = sF[8 * N2 + p];
+        const T ano = go[0] * vo[0] + go[1] * vo[1] + go[2] * vo[2];
+        T fv, fgc;
+        if (nb >= 0) {
+          gnb[d] = sF[15 * N2 + p];
+          gnb[t1] = sF[13 * N2 + p];
+          gnb[t2] = sF[14 * N2 + p];
+          const T un = sF[12 * N2 + p];
+          const T ann = gnb[0] * vn[0] + gnb[1] * vn[1] + gnb[2] * vn[2];
+          const T jump = own_is_L ? uo - un : un - uo;
+          const T avg = T(0.5) * (ano + ann);
+          fv = own_is_L ? (-avg + tau * jump * wdA) : (avg - tau * jump * wdA);
+          fgc = T(-0.5) * jump;
+        } else {
+          fv = -ano + T(2) * tau * uo * wdA;
+          fgc = -uo;
+        }
+        sF[16 * N2 + p] = g.nu * fv;
+        sF[17 * N2 + p] = g.nu * fgc * vo[d];
+        sF[18 * N2 + p] = g.nu * fgc * vo[t1];
+        sF[19 * N2 + p] = g.nu * fgc * vo[t2];
+      }
+    }
+    __syncthreads();
+    // transposed sweeps along t2: a = S^T fv + D^T fg_t2, b = S^T fg_t1, c = S^T fg_d
+    {
+      // the two ops writing plane 20 run one after the other
+      const PlaneOp<T> first[1] = {{S, sF + 16 * N2, sF + 20 * N2, 1, 1, 0}};
+      plane_ops<N, 1>(first, tid, nthr);
+      __syncthreads();
+      const PlaneOp<T> rest[3] = {{D, sF + 19 * N2, sF + 20 * N2, 1, 1, 1}, {S, sF + 18 * N2, sF + 21 * N2, 1, 1, 0},
+                               {S, sF + 17 * N2, sF + 22 * N2, 1, 1, 0}};
+      plane_ops<N, 3>(rest, tid, nthr);
+    }
+    __syncthreads();
+    // along t1: face plane = S^T a + D^T b; normal plane = S^T c
+    {
+      const PlaneOp<T> ops[2] = {{S, sF + 20 * N2, sF + 4 * N2, 0, 1, 0}, {S, sF + 22 * N2, sF + 5 * N2, 0, 1, 0}};
+      plane_ops<N, 2>(ops, tid, nthr);
+    }
+    __syncthreads();
+    {
+      const PlaneOp<T> ops[1] = {{D, sF + 21 * N2, sF + 4 * N2, 0, 1, 1}};
+      plane_ops<N, 1>(ops, tid, nthr);
+    }
+    __syncthreads();
+    // scatter: value/tangential part onto the own face plane, normal part along the normal lines
+    for (int p = tid; p < N2; p += nthr) {
+      const int p1 = p % N, p2 = p / N;
+      const T cn_ = sF[5 * N2 + p];
+      sO[fnode<N>(d, eo, p1, p2)] += sF[4 * N2 + p];
+#pragma unroll
+      for (int m = 0; m < N; ++m) sO[fnode<N>(d, m, p1, p2)] += gs[m] * cn_;
+    }
+    __syncthreads();
+  }
+  double pq = 0.0, sq = 0.0, sp = 0.0;
+  for (int e = tid; e < N3; e += nthr) {
+    const T v = sO[e];
+    dst[cell * N3 + e] = v;
+    if (partials) {
+      pq += static_cast<double>(sU[e]) * v;
+      sq += v;
+      sp += sU[e];
+    }
+  }
+  if (partials) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      pq += __shfl_down(pq, o, 64);
+      sq += __shfl_down(sq, o, 64);
+      sp += __shfl_down(sp, o, 64);
+    }
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) {
+      s_red[3 * w] = pq;
+      s_red[3 * w + 1] = sq;
+      s_red[3 * w + 2] = sp;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double x = 0, y = 0, z = 0;
+      for (int k = 0; k < kMetThreads / 64; ++k) {
+        x += s_red[3 * k];
+        y += s_red[3 * k + 1];
+        z += s_red[3 * k + 2];
+      }
+      partials[4 * blockIdx.x] = x;
+      partials[4 * blockIdx.x + 1] = y;
+      partials[4 * blockIdx.x + 2] = z;
+    }
+  }
+}
+
+// Diagonal of the operator: one thread per DoF, direct quadrature of the
+// cell term and of the own-side face terms of the faces the node lies on.
+template <int N, typename TO>
+__global__ void __launch_bounds__(256) k_sipg_metric_diag(TO* __restrict__ diag, const MetricGeom<double> g) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t ncells = static_cast<int64_t>(g.nx) * g.ny * g.nz;
+  if (gid >= ncells * N3) return;
+  const int cell = static_cast<int>(gid / N3);
+  const int loc = static_cast<int>(gid - static_cast<int64_t>(cell) * N3);
+  const int idx[3] = {loc % N, (loc / N) % N, loc / N2};
+  const int c[3] = {cell % g.nx, (cell / g.nx) % g.ny, cell / (g.nx * g.ny)};
+  const int nd[3] = {g.nx, g.ny, g.nz};
+  const double* S = g.tab + MTab{N}.S();
+  const double* D = g.tab + MTab{N}.D();
+  const double* g0 = g.tab + MTab{N}.g0();
+  const double* g1 = g.tab + MTab{N}.g1();
+  const double* cm = g.cm + static_cast<int64_t>(cell) * 7 * N3;
+  double acc = 0.0;
+  for (int qz = 0; qz < N; ++qz)
+    for (int qy = 0; qy < N; ++qy)
+      for (int qx = 0; qx < N; ++qx) {
+        const int q = (qz * N + qy) * N + qx;
+        const double sx = S[qx * N + idx[0]], sy = S[qy * N + idx[1]], sz = S[qz * N + idx[2]];
+        const double gx = D[qx * N + idx[0]] * sy * sz, gy = sx * D[qy * N + idx[1]] * sz,
+                     gz = sx * sy * D[qz * N + idx[2]];
+        const double G00 = cm[q], G01 = cm[N3 + q], G02 = cm[2 * N3 + q];
+        const double G11 = cm[3 * N3 + q], G12 = cm[4 * N3 + q], G22 = cm[5 * N3 + q], m = cm[6 * N3 + q];
+        const double phi = sx * sy * sz;
+        acc += g.nu * (gx * (G00 * gx + G01 * gy + G02 * gz) + gy * (G01 * gx + G11 * gy + G12 * gz) +
+                       gz * (G02 * gx + G12 * gy + G22 * gz)) +
+               g.mu * m * phi * phi;
+      }
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    for (int s = 0; s < 2; ++s) {
+      if (idx[d] != (s ? N - 1 : 0)) continue;          // the node is not on this face
+      int cn = c[d] + (s ? 1 : -1);
+      bool dir = false;
+      if (cn < 0 || cn >= nd[d]) {
+        if (g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
+        else dir = true;
+      }
+      const double* fm;
+      double tau;
+      bool own_is_L;
+      if (s == 1) {
+        fm = g.fm + (static_cast<int64_t>(cell) * 3 + d) * 7 * N2;
+        tau = g.ftau[cell * 3 + d];
+        own_is_L = true;
+      } else if (!dir) {
+        const int nb = cell + (cn - c[d]) * (d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny));
+        fm = g.fm + (static_cast<int64_t>(nb) * 3 + d) * 7 * N2;
+        tau = g.ftau[nb * 3 + d];
+        own_is_L = false;
+      } else {
+        const int pi = plane_index(g, d, c[0], c[1], c[2]);
+        fm = g.lm + (static_cast<int64_t>(g.lbase[d]) + pi) * 7 * N2;
+        tau = g.ltau[g.lbase[d] + pi];
+        own_is_L = true;
+      }
+      tau *= g.pen;
+      const double gsd = (s ? g1 : g0)[idx[d]];
+      const double fac = dir ? 2.0 : 1.0;
+      const double sgn = own_is_L ? -1.0 : 1.0;    // -(grad phi.n_out, phi): n_out = n for L, -n for R
+      for (int q2 = 0; q2 < N; ++q2)
+        for (int q1 = 0; q1 < N; ++q1) {
+          const int p = q2 * N + q1;
+          const double a1 = S[q1 * N + idx[t1]], a2 = S[q2 * N + idx[t2]];
+          const double phi = a1 * a2;
+          double gh[3];
+          gh[d] = gsd * phi;
+          gh[t1] = D[q1 * N + idx[t1]] * a2;
+          gh[t2] = a1 * D[q2 * N + idx[t2]];
+          const double* v = fm + (own_is_L ? 1 : 4) * N2;
+          const double gv = gh[0] * v[p] + gh[1] * v[N2 + p] + gh[2] * v[2 * N2 + p];
+          acc += g.nu * fac * (sgn * gv * phi + tau * fm[p] * phi * phi);
+        }
+    }
+  }
+  diag[gid] = static_cast<TO>(acc);
+}
+
+// Geometry fill: one thread per (cell, entry).  J = Sh diag(h) on every cell,
+// Sh the constant lattice matrix (identity for plain boxes).
+struct FillArgs {
+  MetricGeom<double> g;
+  const double* x0[3];
+  const double* h[3];
+  double shinv[9];   // Sh^{-1}, row-major
+  double shdet;      // det Sh
+  double k1sq;       // (k+1)^2
+  const double* wq;  // Gauss weights (N)
+};
+
+__device__ __forceinline__ void cell_jinv(const FillArgs& a, const int c[3], double Jinv[9], double& detJ) {
+  double hv[3];
+  for (int d = 0; d < 3; ++d) hv[d] = a.h[d][c[d]];
+  // J^{-1} = diag(1/h) Sh^{-1}
+  for (int r = 0; r < 3; ++r)
+    for (int col = 0; col < 3; ++col) Jinv[r * 3 + col] = a.shinv[r * 3 + col] / hv[r];
+  detJ = fabs(a.shdet) * hv[0] * hv[1] * hv[2];
+}
+
+__device__ __forceinline__ double cell_tau(const FillArgs& a, const int c[3]) {
+  double Jinv[9], detJ;
+  cell_jinv(a, c, Jinv, detJ);
+  const int nd[3] = {a.g.nx, a.g.ny, a.g.nz};
+  double t = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double rn = sqrt(Jinv[d * 3] * Jinv[d * 3] + Jinv[d * 3 + 1] * Jinv[d * 3 + 1] + Jinv[d * 3 + 2] * Jinv[d * 3 + 2]);
+    double wsum = 1.0;   // two interior faces, half each
+    if (!a.g.per[d]) {
+      if (nd[d] == 1) wsum = 2.0;
+      else if (c[d] == 0 || c[d] == nd[d] - 1) wsum = 1.5;
+    }
+    t += wsum * rn;      // A_f / V = |J^{-T} e_d|
+  }
+  return a.k1sq * t;
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_metric_fill_cells(FillArgs a, double* cm) {
+  constexpr int N3 = N * N * N;
+  const int64_t ncells = static_cast<int64_t>(a.g.nx) * a.g.ny * a.g.nz;
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= ncells * N3) return;
+  const int cell = static_cast<int>(gid / N3);
+  const int q = static_cast<int>(gid - static_cast<int64_t>(cell) * N3);
+  const int c[3] = {cell % a.g.nx, (cell / a.g.nx) % a.g.ny, cell / (a.g.nx * a.g.ny)};
+  double Jinv[9], detJ;
+  cell_jinv(a, c, Jinv, detJ);
+  const double w = a.wq[q % N] * a.wq[(q / N) % N] * a.wq[q / (N * N)] * detJ;
+  double G[6];
+  int k = 0;
+  for (int r = 0; r < 3; ++r)
+    for (int col = r; col < 3; ++col) {
+      double s = 0.0;
+      for (int m = 0; m < 3; ++m) s += Jinv[r * 3 + m] * Jinv[col * 3 + m];
+      G[k++] = w * s;
+    }
+  double* out = cm + static_cast<int64_t>(cell) * 7 * N3;
+  for (int e = 0; e < 6; ++e) out[e * N3 + q] = G[e];
+  out[6 * N3 + q] = w;
+}
+
+// high faces (cell, d): entries 7 x N2; low boundary faces in non-periodic directions
+template <int N>
+__global__ void __launch_bounds__(256) k_metric_fill_faces(FillArgs a, double* fm, double* ftau, double* lm,
+                                                           double* ltau) {
+  constexpr int N2 = N * N;
+  const int64_t ncells = static_cast<int64_t>(a.g.nx) * a.g.ny * a.g.nz;
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= ncells * 6 * N2) return;
+  const int p = static_cast<int>(gid % N2);
+  const int64_t fc = gid / N2;
+  const int f = static_cast<int>(fc % 6);
+  const int cell = static_cast<int>(fc / 6);
+  const int d = f >> 1, s = f & 1;
+  const int c[3] = {cell % a.g.nx, (cell / a.g.nx) % a.g.ny, cell / (a.g.nx * a.g.ny)};
+  const int nd[3] = {a.g.nx, a.g.ny, a.g.nz};
+  int cn = c[d] + (s ? 1 : -1);
+  bool dir = false;
+  if (cn < 0 || cn >= nd[d]) {
+    if (a.g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
+    else dir = true;
+  }
+  if (s == 0 && !dir) return;            // an interior low face is stored as the neighbour's high face
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  (void)t1;
+  (void)t2;
+  double Jl[9], detl;
+  cell_jinv(a, c, Jl, detl);
+  double rn = 0.0;
+  for (int m = 0; m < 3; ++m) rn += Jl[d * 3 + m] * Jl[d * 3 + m];
+  rn = sqrt(rn);
+  double n[3];
+  for (int m = 0; m < 3; ++m) n[m] = (s ? 1.0 : -1.0) * Jl[d * 3 + m] / rn;   // outward from this cell
+  const double wdA = a.wq[p % N] * a.wq[p / N] * detl * rn;
+  double vL[3], vR[3] = {0.0, 0.0, 0.0};
+  for (int r = 0; r < 3; ++r) vL[r] = wdA * (Jl[r * 3] * n[0] + Jl[r * 3 + 1] * n[1] + Jl[r * 3 + 2] * n[2]);
+  double tau = cell_tau(a, c);
+  if (!dir) {
+    int cr[3] = {c[0], c[1], c[2]};
+    cr[d] = cn;
+    double Jr[9], detr;
+    cell_jinv(a, cr, Jr, detr);
+    for (int r = 0; r < 3; ++r) vR[r] = wdA * (Jr[r * 3] * n[0] + Jr[r * 3 + 1] * n[1] + Jr[r * 3 + 2] * n[2]);
+    const double tr = cell_tau(a, cr);
+    tau = tau > tr ? tau : tr;
+  }
+  double* out;
+  if (s == 1) {
+    out = fm + (static_cast<int64_t>(cell) * 3 + d) * 7 * N2;
+    if (p == 0) ftau[cell * 3 + d] = tau;
+  } else {
+    const int pi = plane_index(a.g, d, c[0], c[1], c[2]);
+    out = lm + (static_cast<int64_t>(a.g.lbase[d]) + pi) * 7 * N2;
+    if (p == 0) ltau[a.g.lbase[d] + pi] = tau;
+  }
+  out[p] = wdA;
+  for (int r = 0; r < 3; ++r) {
+    out[(1 + r) * N2 + p] = vL[r];
+    out[(4 + r) * N2 + p] = vR[r];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b[i] = static_cast<float>(a[i]);
+}
+
+}  // namespace
+
+#define DGMF_MET_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+
+template <typename T>
+dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials,
+                                     const int* stop, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>(g.nx * g.ny * g.nz);
+#define X(a)                                                                                         \
+  if (n == a) {                                                                                      \
+    hipLaunchKernelGGL((k_sipg_metric_apply<a, T>), dim3(blocks), dim3(kMetThreads), 0, s, src, dst, g, \
+                       partials, stop);                                                              \
+    DGMF_LAUNCH_CHECK("k_sipg_metric_apply");                                                        \
+    return DGMF_OK;                                                                                  \
+  }
+  DGMF_MET_CASES(X)
+#undef X
+  return fail(DGMF_UNSUPPORTED, "metric apply: degree %d not built", n - 1);
+}
+
+template dgmf_status launch_sipg_metric_apply<double>(int, const MetricGeom<double>&, const double*, double*,
+                                                      double*, const int*, hipStream_t);
+template dgmf_status launch_sipg_metric_apply<float>(int, const MetricGeom<float>&, const float*, float*, double*,
+                                                     const int*, hipStream_t);
+
+dgmf_status launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
+  if (n <= 0) return DGMF_OK;
+  const int64_t want = (n + 255) / 256;
+  const unsigned blocks = static_cast<unsigned>(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(k_to_f32, dim3(blocks), dim3(256), 0, s, a, b, n);
+  DGMF_LAUNCH_CHECK("k_to_f32");
+  return DGMF_OK;
+}
+
+template <typename TO>
+dgmf_status launch_sipg_metric_diag(int n, const MetricGeom<double>& g, TO* diag, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(g.nx) * g.ny * g.nz * n * n * n;
+  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+#define X(a)                                                                                   \
+  if (n == a) {                                                                                \
+    hipLaunchKernelGGL((k_sipg_metric_diag<a, TO>), dim3(blocks), dim3(256), 0, s, diag, g);  \
+    DGMF_LAUNCH_CHECK("k_sipg_metric_diag");                                                   \
+    return DGMF_OK;                                                                            \
+  }
+  DGMF_MET_CASES(X)
+#undef X
+  return fail(DGMF_UNSUPPORTED, "metric diagonal: degree %d not built", n - 1);
+}
+
+template dgmf_status launch_sipg_metric_diag<double>(int, const MetricGeom<double>&, double*, hipStream_t);
+template dgmf_status launch_sipg_metric_diag<float>(int, const MetricGeom<double>&, float*, hipStream_t);
+
+dgmf_status launch_metric_fill(int n, const MetricGeom<double>& g, const double* const x0[3], const double* const h[3],
+                               const double shinv[9], double shdet, const double* wq, double* cm, double* fm,
+                               double* ftau, double* lm, double* ltau, hipStream_t s) {
+  FillArgs a{};
+  a.g = g;
+  for (int d = 0; d < 3; ++d) {
+    a.x0[d] = x0[d];
+    a.h[d] = h[d];
+  }
+  for (int i = 0; i < 9; ++i) a.shinv[i] = shinv[i];
+  a.shdet = shdet;
+  a.k1sq = static_cast<double>(n) * n;
+  a.wq = wq;
+  const int64_t ncells = static_cast<int64_t>(g.nx) * g.ny * g.nz;
+#define X(q)                                                                                               \
+  if (n == q) {                                                                                            \
+    const unsigned b1 = static_cast<unsigned>((ncells * q * q * q + 255) / 256);                          \
+    hipLaunchKernelGGL((k_metric_fill_cells<q>), dim3(b1), dim3(256), 0, s, a, cm);                       \
+    DGMF_LAUNCH_CHECK("k_metric_fill_cells");                                                             \
+    const unsigned b2 = static_cast<unsigned>((ncells * 6 * q * q + 255) / 256);                          \
+    hipLaunchKernelGGL((k_metric_fill_faces<q>), dim3(b2), dim3(256), 0, s, a, fm, ftau, lm, ltau);       \
+    DGMF_LAUNCH_CHECK("k_metric_fill_faces");                                                             \
+    return DGMF_OK;                                                                                        \
+  }
+  DGMF_MET_CASES(X)
+#undef X
+  return fail(DGMF_UNSUPPORTED, "metric fill: degree %d not built", n - 1);
+}
+
+}  // namespace dgmf

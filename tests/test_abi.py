@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_invalid_arguments_are_rejected_without_a_device(lib):
     import paper_1607_01323_amd as dg
-    d = dg.BoxDesc(0, 2, 2, 2, 1.0, 1.0, 1.0, 0.0, (ctypes.c_int * 3)(1, 1, 1), 0.0, 0)
+    d = dg.BoxDesc(0, 2, 2, 2, 1.0, 1.0, 1.0, 0.0, (ctypes.c_int * 3)(1, 1, 1), 0.0, 0, (ctypes.c_double * 9)())
     h = ctypes.c_void_p()
     assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
     assert b"degree" in dg._lib.dgmf_last_error()
@@ -45,6 +45,18 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
     d.nx, d.lx = 2, -1.0
     assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    d.lx = 1.0
+    d.shear = (ctypes.c_double * 9)(1, 0.3, 0, 0, 1, 0, 0, 0, 1)       # shear needs the stored metric
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    assert b"store_qp_metric" in dg._lib.dgmf_last_error()
+    d.store_qp_metric = 1
+    d.shear = (ctypes.c_double * 9)(1, 0, 0, 2, 0, 0, 0, 0, 1)         # singular
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    d.shear = (ctypes.c_double * 9)(1, float("nan"), 0, 0, 1, 0, 0, 0, 1)
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    d.shear = (ctypes.c_double * 9)()
+    d.ny = 1                                                              # one periodic cell, stored metric
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.UNSUPPORTED
     assert dg._apply(None, 0, None, None, None) == dg.INVALID
     assert dg._mesh_destroy(None) == dg.OK
     assert dg.version() >= 100
