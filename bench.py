@@ -212,6 +212,74 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     ex["c3_convective"] = {"fwd_us": tf * 1e6, "vjp_us": tv * 1e6, "fwd_dofs_per_s": n3 / tf, "vjp_dofs_per_s": n3 / tv,
                            "fwd_plus_vjp_dofs_per_s": n3 / (tf + tv), "dofs": n3}
     m3.close()
+    ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4, "c4"))
+    ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4_SMALL, "c4small", cg=False))
+    return ex
+
+
+def metric_bytes_per_launch(n, ncells, es):
+    """Algorithmic bytes of one stored-metric apply: src + dst, 7 metric values per
+    cell point, 7 per face point of the 3 faces each cell owns, 3 face penalties."""
+    return ncells * es * (2 * n ** 3 + 7 * n ** 3 + 21 * n ** 2 + 3)
+
+
+def channel_measurements(dg, inp, torch, w, tag, cg=True):
+    """Stretched channel with the stored quadrature-point metric: apply (fp64, fp32),
+    Helmholtz PCG to 1e-10 (mixed vs fp64), convective forward + VJP on the
+    perturbed laminar profile."""
+    ex = {}
+    m = dg.Mesh.from_workload(w)
+    op = dg.SipgOperator(m, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    N, n = m.ndofs, w.degree + 1
+    v = torch.as_tensor(inp.uniform(3, N), device="cuda")
+    yv = torch.empty_like(v)
+    ta = _events_time(lambda: op.apply(v, yv), 50, 5)
+    v32 = v.float()
+    yv32 = torch.empty_like(v32)
+    tb = _events_time(lambda: op.apply(v32, yv32), 50, 5)
+    b64 = metric_bytes_per_launch(n, m.ncells, 8)
+    b32 = metric_bytes_per_launch(n, m.ncells, 4)
+    ex[f"{tag}_apply_f64"] = {"dofs_per_s": N / ta, "alg_GBps": b64 / ta / 1e9, "us": ta * 1e6,
+                              "alg_bytes": b64, "hbm_frac": b64 / ta / 1e9 / HBM_PEAK_GBS, "dofs": N}
+    ex[f"{tag}_apply_f32"] = {"dofs_per_s": N / tb, "alg_GBps": b32 / tb / 1e9, "us": tb * 1e6,
+                              "alg_bytes": b32, "hbm_frac": b32 / tb / 1e9 / HBM_PEAK_GBS}
+    del v32, yv32
+    if cg:
+        qp = op.quadrature_points()
+        f = inp.channel_rhs(w.mass_coeff, w.diff_coeff)
+        fq = torch.as_tensor(f(*[qp[i].cpu().numpy() for i in range(3)]), device="cuda")
+        del qp
+        b = op.integrate(fq)
+        del fq
+        for name, kw in (("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
+                         ("f64cheb", dict(precond="chebyshev", precond_dtype=torch.float64)),
+                         ("jacobi_f64", dict(precond="jacobi"))):
+            best = None
+            for _ in range(2):
+                x = torch.zeros(N, dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = op.cg(b, x, rtol=1e-10, max_iter=5000, check_every=8, seed=42, **kw)
+                torch.cuda.synchronize()
+                tt = time.perf_counter() - t0
+                if best is None or tt < best["time_s"]:
+                    best = {"time_s": tt, "iterations": out.iterations, "setup_s": out.setup_s,
+                            "solve_s": out.solve_s, "rel_residual": out.rel_residual, "lambda_max": out.lambda_max}
+            ex[f"{tag}_cg_{name}"] = best
+    opc = dg.ConvectiveOperator(m, n_q=w.conv_points)
+    X = m.node_coords()
+    U = torch.stack([1.0 - X[1] ** 2, torch.zeros_like(X[0]), torch.zeros_like(X[0])]).reshape(-1)
+    U += 0.05 * torch.as_tensor(inp.uniform(6, 3 * N), device="cuda")
+    del X
+    Wc = torch.as_tensor(inp.uniform(9, 3 * N), device="cuda")
+    Cout = torch.empty_like(U)
+    Gout = torch.empty_like(U)
+    tf = _events_time(lambda: opc.apply(U, Cout), 10, 2)
+    tv = _events_time(lambda: opc.vjp(U, Wc, Gout), 10, 2)
+    ex[f"{tag}_convective"] = {"fwd_us": tf * 1e6, "vjp_us": tv * 1e6, "fwd_dofs_per_s": 3 * N / tf,
+                               "vjp_dofs_per_s": 3 * N / tv, "fwd_plus_vjp_dofs_per_s": 3 * N / (tf + tv),
+                               "dofs": 3 * N, "n_q": w.conv_points or (3 * n) // 2}
+    m.close()
     return ex
 
 

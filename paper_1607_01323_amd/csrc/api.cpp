@@ -265,6 +265,69 @@ static dgmf_status setup_metric(dgmf_mesh m) {
   return DGMF_OK;
 }
 
+// Line operators of a uniform, fully periodic mesh (layout UTab).  With
+// Kt = Mhat^-1 Khat and the Mhat^-1 images g0t, g1t, e0t, e1t of l'(0),
+// l'(1), e_0, e_{n-1}, one direction's contribution to
+//   w = mu u + sum_d (nu/h_d) Mhat^-1 A_d u        (per unit cell volume V)
+// is, with s = nu V / h_d, h = h_d and tau the face penalty,
+//   w += s/h (Abar u) + s [ 1/2 ur_0/h g1t + (tau (u_{n-1} - ur_0) - 1/2 l'(0).ur/h) e1t
+//                         - 1/2 ul_{n-1}/h g0t + (tau (u_0 - ul_{n-1}) + 1/2 l'(1).ul/h) e0t ],
+//   Abar = Kt + 1/2 (g0t e_0^T - g1t e_{n-1}^T + e0t l'(0)^T - e1t l'(1)^T),
+// the own-cell part of both face fluxes folded into Abar.  mu V is added to
+// the diagonal of the z operator.
+template <typename T>
+static dgmf_status upload_uniform_tables(const Tables1D& t, const double h[3], double mu, double nu, double pen,
+                                         DevBuf& buf) {
+  const int n = t.n;
+  UTab L{n};
+  std::vector<long double> minv;
+  if (!invert(n, t.Mhat.data(), minv)) return fail(DGMF_INVALID, "sipg_create: singular mass matrix");
+  auto mv = [&](const std::vector<double>& v, int i) {
+    long double a = 0;
+    for (int m = 0; m < n; ++m) a += minv[i * n + m] * v[m];
+    return a;
+  };
+  std::vector<long double> kt(n * n), g0t(n), g1t(n), e0t(n), e1t(n), abar(n * n);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      long double a = 0;
+      for (int m = 0; m < n; ++m) a += minv[i * n + m] * t.Khat[m * n + j];
+      kt[i * n + j] = a;
+    }
+    g0t[i] = mv(t.g0, i);
+    g1t[i] = mv(t.g1, i);
+    e0t[i] = minv[i * n];
+    e1t[i] = minv[i * n + n - 1];
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      abar[i * n + j] = kt[i * n + j] +
+                        0.5L * ((j == 0 ? g0t[i] : 0.0L) - (j == n - 1 ? g1t[i] : 0.0L) + e0t[i] * t.g0[j] -
+                                e1t[i] * t.g1[j]);
+  const long double V = static_cast<long double>(h[0]) * h[1] * h[2];
+  const long double tau = pen * (1.0L / h[0] + 1.0L / h[1] + 1.0L / h[2]);
+  std::vector<T> out(L.size(), T(0));
+  for (int d = 0; d < 3; ++d) {
+    const long double hi = 1.0L / h[d], s = nu * V * hi;
+    for (int i = 0; i < n * n; ++i) out[L.A(d) + i] = static_cast<T>(s * hi * abar[i]);
+    if (d == 2)
+      for (int i = 0; i < n; ++i) out[L.A(d) + i * n + i] = static_cast<T>(s * hi * abar[i * n + i] + mu * V);
+    for (int i = 0; i < n; ++i) {
+      out[L.G1(d) + i] = static_cast<T>(0.5L * s * hi * g1t[i]);
+      out[L.G0(d) + i] = static_cast<T>(-0.5L * s * hi * g0t[i]);
+      out[L.g0s(d) + i] = static_cast<T>(-0.5L * s * hi * t.g0[i]);
+      out[L.g1s(d) + i] = static_cast<T>(0.5L * s * hi * t.g1[i]);
+    }
+    out[L.c(d)] = static_cast<T>(s * tau);
+  }
+  for (int i = 0; i < n; ++i) {
+    out[L.E1() + i] = static_cast<T>(e1t[i]);
+    out[L.E0() + i] = static_cast<T>(e0t[i]);
+  }
+  for (int i = 0; i < n * n; ++i) out[L.Mh() + i] = static_cast<T>(t.Mhat[i]);
+  return buf.upload(out.data(), out.size() * sizeof(T));
+}
+
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 static bool overlap(const void* a, const void* b, size_t bytes) {
@@ -434,6 +497,30 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
     return st;
   }
   const double pen = desc->penalty_scale * n * n;
+  // uniform spacing in every direction and every direction periodic: pre-scaled line operators
+  op->g64.utab = nullptr;
+  op->g32.utab = nullptr;
+  if (allper && !mesh->desc.store_qp_metric) {
+    bool uni = true;
+    double hu[3];
+    for (int a = 0; a < 3 && uni; ++a) {
+      const auto& v = mesh->verts[a];
+      hu[a] = v[1] - v[0];
+      for (size_t c = 1; c + 1 < v.size(); ++c)
+        if (std::fabs((v[c + 1] - v[c]) - hu[a]) > 1e-14 * hu[a]) uni = false;
+    }
+    if (uni) {
+      st = upload_uniform_tables<double>(op->tab, hu, desc->mass_coeff, desc->diff_coeff, pen, op->utab64);
+      if (st == DGMF_OK)
+        st = upload_uniform_tables<float>(op->tab, hu, desc->mass_coeff, desc->diff_coeff, pen, op->utab32);
+      if (st != DGMF_OK) {
+        delete op;
+        return st;
+      }
+      op->g64.utab = static_cast<const double*>(op->utab64.p);
+      op->g32.utab = static_cast<const float*>(op->utab32.p);
+    }
+  }
   op->g64.pen = pen;
   op->g64.mu = desc->mass_coeff;
   op->g64.nu = desc->diff_coeff;

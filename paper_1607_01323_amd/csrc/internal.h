@@ -105,6 +105,26 @@ struct CartGeom {
   const T* tab;       // Mhat[n*n], Khat[n*n], g0[n], g1[n], S[nq*n], wq[nq], xq[nq], nodes[n], Xhat[n*n]
   int xcomb;          // 1: uniform x spacing, Xhat = Khat + (mu hx^2/nu) Mhat (or Mhat if nu = 0) is valid
   int allper;         // 1: every direction periodic
+  const T* utab;      // uniform periodic meshes: pre-scaled line operators (UTab), else null
+};
+
+// Pre-scaled tables of a uniform, fully periodic mesh: there every face has
+// the same geometry, so the own-cell part of each face flux folds into one
+// n x n line matrix per direction.  Per direction d: A_d (n*n), G1_d, G0_d,
+// g0s_d, g1s_d (n each), c_d; then E1, E0 (n each) and Mhat (n*n).
+struct UTab {
+  int n;
+  __host__ __device__ int dir(int d) const { return d * (n * n + 4 * n + 1); }
+  __host__ __device__ int A(int d) const { return dir(d); }
+  __host__ __device__ int G1(int d) const { return dir(d) + n * n; }
+  __host__ __device__ int G0(int d) const { return dir(d) + n * n + n; }
+  __host__ __device__ int g0s(int d) const { return dir(d) + n * n + 2 * n; }
+  __host__ __device__ int g1s(int d) const { return dir(d) + n * n + 3 * n; }
+  __host__ __device__ int c(int d) const { return dir(d) + n * n + 4 * n; }
+  __host__ __device__ int E1() const { return dir(3); }
+  __host__ __device__ int E0() const { return dir(3) + n; }
+  __host__ __device__ int Mh() const { return dir(3) + 2 * n; }
+  __host__ __device__ int size() const { return dir(3) + 2 * n + n * n; }
 };
 
 // Offsets into the device table of an SIPG operator.
@@ -212,6 +232,7 @@ struct dgmf_op_ {
   int nq = 0;
   dgmf::Tables1D tab;
   dgmf::DevBuf tab64, tab32;
+  dgmf::DevBuf utab64, utab32;     // uniform periodic meshes only
   dgmf::CartGeom<double> g64{};
   dgmf::CartGeom<float> g32{};
   dgmf::DevBuf ctab;               // convective tables

@@ -30,15 +30,16 @@
 namespace dgmf {
 namespace {
 
-constexpr int kApplyThreads = 128;   // threads per workgroup of the apply kernel
+// Tables and per-layer geometry are read through the constant address space:
+// they are never written while a kernel runs, so uniform reads become scalar
+// loads that do not wait behind the vector loads in flight.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
 
-template <int N>
-struct Shape {
-  static constexpr int N2 = N * N;
-  static constexpr int N3 = N2 * N;
-  static constexpr int CPB = (kApplyThreads / N2) > 0 ? kApplyThreads / N2 : 1;   // cells per block
-  static constexpr int P = (N % 2) ? N : N + 1;   // odd x-line pitch in LDS: conflict-free x-line access
-  static constexpr int CL = N2 * P;           // LDS words per cell per buffer
+// Work decomposition of the z-marching apply: tx * ty tiles, segs z-segments
+// of seglen layers; total work items spread over 8 XCDs, per_xcd each.
+struct ZmPlan {
+  int tx, ty, segs, seglen, total, per_xcd;
 };
 
 template <int N, typename T>
@@ -166,105 +167,9 @@ __device__ __forceinline__ bool neighbour(const CartGeom<T>& g, const CellInfo<T
   return true;
 }
 
-template <int N, typename T>
-__device__ __forceinline__ void load_line(const T* __restrict__ base, int stride, T (&v)[N]) {
-#pragma unroll
-  for (int m = 0; m < N; ++m) v[m] = base[m * stride];
-}
-
-// Apply A_d to the line of this cell that starts at element offset `off`
-// (element stride `stride` inside a cell), reading own values from LDS.
-template <int N, typename T>
-__device__ __forceinline__ void dir_op(const CartGeom<T>& g, const T* __restrict__ src, const CellInfo<T>& ci,
-                                       int64_t cell, int d, const T (&u)[N], int goff, int gstride, T massc,
-                                       T (&out)[N]) {
-  constexpr int N3 = N * N * N;
-  T ul[N], ur[N];
-  int64_t nb;
-  T hl = 0, hr = 0, tauL, tauR;
-  const bool hasL = neighbour(g, ci, cell, d, 0, nb, hl, tauL);
-  if (hasL) load_line<N, T>(src + nb * N3 + goff, gstride, ul);
-  const bool hasR = neighbour(g, ci, cell, d, 1, nb, hr, tauR);
-  if (hasR) load_line<N, T>(src + nb * N3 + goff, gstride, ur);
-  const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
-  const T sigma = g.nu * ci.h[d1] * ci.h[d2];
-  sipg_line<N, T>(g.tab, u, ul, ur, !hasL, !hasR, ci.hinv[d], hl, hr, tauL, tauR, sigma, massc, out);
-}
-
-// ---------------------------------------------------------------- apply ---
-// Traversal order: the mesh is cut into y-strips, one per XCD when ny >= 8
-// (workgroup b runs on XCD b % 8), and each strip is walked z-major, then y,
-// then x.  The z-neighbour layer a workgroup reads was written a strip layer
-// earlier (nx * ny/8 cells), so it is still in that XCD's L2.
-__host__ __device__ inline int strip_count(int ny) { return ny >= 8 ? 8 : 1; }
-
-// out = smain (mat u) [+ massc (Mhat u)] + the two face fluxes of this line.
-// ul / ur: the same line of the low / high neighbour (ignored on Dirichlet faces).
-template <int N, typename T, bool MASS>
-__device__ __forceinline__ void line_apply(const T* __restrict__ tab, const T* __restrict__ mat, T smain, T massc,
-                                           const T (&u)[N], const T (&ul)[N], const T (&ur)[N], bool dirL,
-                                           bool dirR, T hinv, T hlinv, T hrinv, T tauL, T tauR, T sigma,
-                                           T (&out)[N]) {
-  const T* g0 = tab + 2 * N * N;
-  const T* g1 = g0 + N;
-  T gu0 = g0[0] * u[0], gu1 = g1[0] * u[0];
-#pragma unroll
-  for (int m = 1; m < N; ++m) {
-    gu0 = fma(g0[m], u[m], gu0);
-    gu1 = fma(g1[m], u[m], gu1);
-  }
-  gu0 *= hinv;
-  gu1 *= hinv;
-  const T sh = sigma * hinv;
-  T cR, eR, cL, eL;   // coefficients of l'(1)_i and l'(0)_i, and the end-node terms
-  if (dirR) {
-    cR = -sh * u[N - 1];
-    eR = sigma * fma(T(2) * tauR, u[N - 1], -gu1);
-  } else {
-    T gr = g0[0] * ur[0];
-#pragma unroll
-    for (int m = 1; m < N; ++m) gr = fma(g0[m], ur[m], gr);
-    const T jump = u[N - 1] - ur[0];
-    const T avg = T(0.5) * fma(gr, hrinv, gu1);
-    cR = T(-0.5) * sh * jump;
-    eR = sigma * fma(tauR, jump, -avg);
-  }
-  if (dirL) {
-    cL = sh * u[0];
-    eL = sigma * fma(T(2) * tauL, u[0], gu0);
-  } else {
-    T gl = g1[0] * ul[0];
-#pragma unroll
-    for (int m = 1; m < N; ++m) gl = fma(g1[m], ul[m], gl);
-    const T jump = ul[N - 1] - u[0];
-    const T avg = T(0.5) * fma(gl, hlinv, gu0);
-    cL = T(-0.5) * sh * jump;
-    eL = sigma * fma(-tauL, jump, avg);
-  }
-  T us[N], um[N];
-#pragma unroll
-  for (int m = 0; m < N; ++m) {
-    us[m] = smain * u[m];
-    if (MASS) um[m] = massc * u[m];
-  }
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    T acc = fma(cL, g0[i], cR * g1[i]);
-#pragma unroll
-    for (int m = 0; m < N; ++m) acc = fma(mat[i * N + m], us[m], acc);
-    if (MASS) {
-#pragma unroll
-      for (int m = 0; m < N; ++m) acc = fma(tab[i * N + m], um[m], acc);
-    }
-    out[i] = acc;
-  }
-  out[0] += eL;
-  out[N - 1] += eR;
-}
-
 // y = A x + c (c optional: accumulate into y's initial value)
 template <int N, typename T>
-__device__ __forceinline__ void matvec_acc(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
+__device__ __forceinline__ void matvec_acc(cptr<T> A, const T (&x)[N], T (&y)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T s = y[i];
@@ -272,37 +177,6 @@ __device__ __forceinline__ void matvec_acc(const T* __restrict__ A, const T (&x)
     for (int j = 0; j < N; ++j) s = fma(A[i * N + j], x[j], s);
     y[i] = s;
   }
-}
-
-template <int N, typename T, bool PER>
-struct Nb {
-  int idx;       // neighbour cell
-  T hinv, tau;   // its 1/h along d and the face penalty
-  bool dir;      // Dirichlet face
-};
-
-// Low (side 0) / high (side 1) neighbour along d of a cell at coordinate cd.
-template <int N, typename T, bool PER>
-__device__ __forceinline__ Nb<N, T, PER> nbr(const CartGeom<T>& g, int cell, int cd, int nd, int stride, int d,
-                                             int side, T tau_c, T tp_other) {
-  Nb<N, T, PER> r;
-  int cn = cd + (side ? 1 : -1);
-  r.dir = false;
-  if (cn < 0 || cn >= nd) {
-    if (!PER && !g.per[d]) {
-      r.dir = true;
-      r.idx = cell;
-      r.hinv = T(0);
-      r.tau = tau_c;
-      return r;
-    }
-    cn = cn < 0 ? nd - 1 : 0;
-  }
-  r.idx = cell + (cn - cd) * stride;
-  r.hinv = g.hinv[d][cn];
-  const T tn = g.pen * (g.tp[d][cn] + tp_other);
-  r.tau = tau_c > tn ? tau_c : tn;
-  return r;
 }
 
 // w += s [ hinv (Mhat^-1 Khat u) + Mhat^-1 (face fluxes of this line) ]: one
@@ -314,17 +188,17 @@ __device__ __forceinline__ Nb<N, T, PER> nbr(const CartGeom<T>& g, int cell, int
 //   -1/2 l'(0)_i/h [u] + delta_{i,0} ({{u'}} - tau [u]);
 // Dirichlet faces mirror these with [u] = u and the boundary penalty 2 tau.
 template <int N, typename T>
-__device__ __forceinline__ void bline(const T* __restrict__ tab, const T (&u)[N], const T (&ul)[N],
+__device__ __forceinline__ void bline(cptr<T> tab, const T (&u)[N], const T (&ul)[N],
                                       const T (&ur)[N], bool dirL, bool dirR, T hinv, T hlinv, T hrinv, T tauL,
                                       T tauR, T s, T (&w)[N]) {
   constexpr TabLayout L{N, N};
-  const T* g0 = tab + L.g0();
-  const T* g1 = tab + L.g1();
-  const T* Kt = tab + L.ktil();
-  const T* g0t = tab + L.g0t();
-  const T* g1t = tab + L.g1t();
-  const T* e0t = tab + L.e0t();
-  const T* e1t = tab + L.e1t();
+  cptr<T> g0 = tab + L.g0();
+  cptr<T> g1 = tab + L.g1();
+  cptr<T> Kt = tab + L.ktil();
+  cptr<T> g0t = tab + L.g0t();
+  cptr<T> g1t = tab + L.g1t();
+  cptr<T> e0t = tab + L.e0t();
+  cptr<T> e1t = tab + L.e1t();
   T gu0 = g0[0] * u[0], gu1 = g1[0] * u[0];
 #pragma unroll
   for (int m = 1; m < N; ++m) {
@@ -375,133 +249,214 @@ __device__ __forceinline__ void bline(const T* __restrict__ tab, const T (&u)[N]
   }
 }
 
-// The operator in factored form: with V = hx hy hz and Mhat the 1D mass matrix,
-//   H u = V (Mz x My x Mx) ( mu u + sum_d (nu/h_d) Mhat^-1 A_d u ),
-// A_d the line operator of direction d (stiffness and the fluxes of its two
-// faces).  Five passes, each thread owning one line of its cell per pass:
-//   1 z-lines: load u (coalesced), w = mu V u + B_z u   (z-neighbour lines)
-//   2 y-lines: w += B_y u                              (y-neighbour lines)
-//   3 x-lines: w += B_x u; w = Mx w                    (x-neighbours from LDS in-block)
-//   4 y-lines: w = My w
-//   5 z-lines: dst = Mz w                               (coalesced store)
-template <int N, typename T, bool PER>
-__global__ void __launch_bounds__(kApplyThreads) k_sipg_cart_apply(const T* __restrict__ src, T* __restrict__ dst,
-                                                         const CartGeom<T> g, double* __restrict__ partials,
-                                                         const int* stop) {
-  if (stop && *stop) return;   // uniform for the whole grid: CG already finished
-  using S = Shape<N>;
-  constexpr int N2 = S::N2, N3 = S::N3, P = S::P, CL = S::CL, CPB = S::CPB;
-  __shared__ T s_u[CPB * CL];
-  __shared__ T s_w[CPB * CL];
-  __shared__ double s_red[3 * (kApplyThreads / 64)];
+// ------------------------------------------------------ z-marching apply ---
+// Same factored operator and line operators as above, with a different data
+// movement: a workgroup owns a TX x TY tile of cells in the x-y plane and
+// marches along z over a segment of layers.  Each thread owns one z-line (i,j)
+// of one tile cell; the z-lines of the layers below, at and above the current
+// one stay in registers (the layer two ahead is prefetched while the current
+// one is processed), so z-neighbours cost nothing extra.  x- and y-neighbour
+// lines come from the tile in LDS, and only the tile rim reads neighbour cells
+// from L2.  Tiles are handed to XCDs in compact bands (workgroup b runs on XCD
+// b % 8), so the rim cells a workgroup reads were loaded by a tile on the same
+// XCD at about the same z.
+template <int N>
+struct ZmTile;
+template <> struct ZmTile<2> { static constexpr int TX = 8, TY = 8; };
+template <> struct ZmTile<3> { static constexpr int TX = 4, TY = 7; };
+template <> struct ZmTile<4> { static constexpr int TX = 4, TY = 4; };
+template <> struct ZmTile<5> { static constexpr int TX = 4, TY = 2; };
+template <> struct ZmTile<6> { static constexpr int TX = 3, TY = 2; };
+template <> struct ZmTile<7> { static constexpr int TX = 2, TY = 2; };
+template <> struct ZmTile<8> { static constexpr int TX = 2, TY = 2; };
 
+template <int N>
+struct Zm {
+  static constexpr int N2 = N * N, N3 = N2 * N;
+  static constexpr int P = (N % 2) ? N : N + 1;
+  static constexpr int CL = (N2 * P) | 1;   // odd cell stride: cells of one wavefront start on different banks
+  static constexpr int TX = ZmTile<N>::TX, TY = ZmTile<N>::TY, NC = TX * TY;
+  // a cell's n^2 threads never straddle two wavefronts, so transposes of a
+  // cell's own lines through LDS need no workgroup barrier
+  static constexpr int CPW = 64 / N2;                       // cells per wavefront
+  static constexpr int THREADS = ((NC + CPW - 1) / CPW) * 64;
+};
+
+// Orders this wavefront's LDS accesses (all lanes of a cell are in it).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The z-line (i, j) = off of a cell: n values, stride n^2 (coalesced across the
+// n^2 threads of a cell).
+template <int N, typename T>
+__device__ __forceinline__ void load_zline(const T* __restrict__ src, int cell, int off, T (&v)[N]) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+#pragma unroll
+  for (int l = 0; l < N; ++l) v[l] = src[cell * N3 + off + l * N2];
+}
+
+// Line operator of direction d on a uniform, fully periodic mesh (tables
+// UTab, pre-scaled on the host): w += A_d u + ur_0 G1_d + bR E1 + ul_{n-1} G0_d
+// + bL E0 with bR = c_d (u_{n-1} - ur_0) + g0s_d.ur, bL = c_d (u_0 - ul_{n-1}) + g1s_d.ul.
+template <int N, typename T>
+__device__ __forceinline__ void uline(cptr<T> ut, int d, const T (&u)[N], const T (&ul)[N], const T (&ur)[N],
+                                      T (&w)[N]) {
+  constexpr UTab L{N};
+  const cptr<T> A = ut + L.A(d), G1 = ut + L.G1(d), G0 = ut + L.G0(d), g0s = ut + L.g0s(d), g1s = ut + L.g1s(d);
+  const cptr<T> E1 = ut + L.E1(), E0 = ut + L.E0();
+  const T c = ut[L.c(d)];
+  T dr = g0s[0] * ur[0], dl = g1s[0] * ul[0];
+#pragma unroll
+  for (int m = 1; m < N; ++m) {
+    dr = fma(g0s[m], ur[m], dr);
+    dl = fma(g1s[m], ul[m], dl);
+  }
+  const T bR = fma(c, u[N - 1] - ur[0], dr);
+  const T bL = fma(c, u[0] - ul[N - 1], dl);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = fma(G1[i], ur[0], fma(E1[i], bR, fma(G0[i], ul[N - 1], fma(E0[i], bL, w[i]))));
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc = fma(A[i * N + m], u[m], acc);
+    w[i] = acc;
+  }
+}
+
+// Work state of one workgroup of the z-marching apply.
+template <int N, typename T>
+struct ZmCtx {
+  static constexpr int N2 = N * N, N3 = N2 * N, P = Zm<N>::P, CL = Zm<N>::CL;
+  static constexpr int NR = 2 * (Zm<N>::TX + Zm<N>::TY);                    // rim cells per layer
+  static constexpr int RPT = (NR * N3 + Zm<N>::THREADS - 1) / Zm<N>::THREADS;  // rim values per thread
+  bool act, zper;
+  int col, nxy, zoff, slot, t0, t1;
+  T hx, hy, hinvx, hinvy, tpx, tpy;
+  bool xl_dir, xr_dir, yl_dir, yr_dir;
+  T xl_hinv, xr_hinv, yl_hinv, yr_hinv, xl_tp, xr_tp, yl_tp, yr_tp;
+  int xl_nb, xr_nb, yl_nb, yr_nb;   // LDS offset of the neighbour cell (tile slot or rim slot)
+  T rim[RPT];                       // rim values of the next layer, in flight
+};
+
+// One layer of the march.  W: z-line window (layer offset -1, 0, +1, and the
+// slot that receives layer +2).
+template <int N, typename T, bool PER, bool UNI>
+__device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restrict__ dst, const CartGeom<T>& g,
+                                         ZmCtx<N, T>& c, int cz, int z1, T* s_u, T* s_w, T* s_rim_next,
+                                         const int* s_rimcol, cptr<T> tab, cptr<T> gh, cptr<T> ghinv,
+                                         cptr<T> gtp, const T (&up)[N], const T (&uc)[N], const T (&un)[N],
+                                         T (&unn)[N], bool want_partials, double& pq, double& sq, double& sp) {
+  using C = ZmCtx<N, T>;
+  constexpr int N2 = C::N2, N3 = C::N3, P = C::P, NR = C::NR, RPT = C::RPT, TH = Zm<N>::THREADS;
   const int tid = threadIdx.x;
-  const int lc = tid / N2;
-  const int t = tid - lc * N2;
-  const int t0 = t % N, t1 = t / N;
-  // strip decomposition of the block index
-  const int nstrip = strip_count(g.ny);
-  const int sidx = blockIdx.x % nstrip, r = blockIdx.x / nstrip;
-  const int base = g.ny / nstrip, extra = g.ny % nstrip;
-  const int hs = base + (sidx < extra ? 1 : 0);
-  const int ys = sidx * base + (sidx < extra ? sidx : extra);
-  const int ncs = g.nx * hs * g.nz;
-  const int q = r * CPB + lc;
-  const bool act = lc < CPB && q < ncs;
-  int c[3] = {0, 0, 0}, cell = 0;
-  if (act) {
-    c[0] = q % g.nx;
-    const int tq = q / g.nx;
-    c[1] = ys + tq % hs;
-    c[2] = tq / hs;
-    cell = (c[2] * g.ny + c[1]) * g.nx + c[0];
-  }
-  const int nd[3] = {g.nx, g.ny, g.nz};
-  const int stride[3] = {1, g.nx, g.nx * g.ny};
-  const int slot = (lc < CPB ? lc : 0) * CL;
-  T* su = s_u + slot;
-  T* sw = s_w + slot;
-  T h[3], hinv[3], tp[3];
+  const int t0 = c.t0, t1 = c.t1;
+  T* su = s_u + c.slot;
+  T* sw = s_w + c.slot;
+  wave_sync();   // the previous layer's last reads of sw by this wavefront
+  // prefetch: z-lines two layers ahead (own column), rim cells one layer ahead (whole workgroup)
+  if (cz + 1 < z1) {
+    const int zq = cz + 2;
+    if (c.act && (zq < g.nz || c.zper)) load_zline<N, T>(src, (zq >= g.nz ? zq - g.nz : zq) * c.nxy + c.col, c.zoff, unn);
+    const int lay1 = (cz + 1) * c.nxy;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    h[d] = g.h[d][c[d]];
-    hinv[d] = g.hinv[d][c[d]];
-    tp[d] = g.tp[d][c[d]];
-  }
-  const T tau_c = g.pen * (tp[0] + tp[1] + tp[2]);
-  const T vol = h[0] * h[1] * h[2];
-  const T vnu = vol * g.nu;
-  const T* Mh = g.tab;
-
-  // pass 1: z-lines (i, j) = (t0, t1)
-  T u[N];
-  if (act) {
-    const int off = t1 * N + t0;
-    const Nb<N, T, PER> L = nbr<N, T, PER>(g, cell, c[2], nd[2], stride[2], 2, 0, tau_c, tp[0] + tp[1]);
-    const Nb<N, T, PER> R = nbr<N, T, PER>(g, cell, c[2], nd[2], stride[2], 2, 1, tau_c, tp[0] + tp[1]);
-    T zl[N], zr[N], w[N];
-#pragma unroll
-    for (int l = 0; l < N; ++l) {
-      u[l] = src[cell * N3 + off + l * N2];
-      zl[l] = L.dir ? T(0) : src[L.idx * N3 + off + l * N2];
-      zr[l] = R.dir ? T(0) : src[R.idx * N3 + off + l * N2];
+    for (int k = 0; k < RPT; ++k) {
+      const int e = tid + k * TH;
+      if (e < NR * N3) {
+        const int r = e / N3;
+        const int rc = s_rimcol[r];
+        if (rc >= 0) c.rim[k] = src[(lay1 + rc) * N3 + (e - r * N3)];
+      }
     }
-    const T mv = g.mu * vol;
+  }
+  const cptr<T> ut = (cptr<T>)(g.utab);
+  // layer geometry (uniform: scalar loads)
+  const T hz = UNI ? T(0) : gh[cz], hinvz = UNI ? T(0) : ghinv[cz], tpz = UNI ? T(0) : gtp[cz];
+  int zlo = cz - 1, zhi = cz + 1;
+  const bool zl_dir = zlo < 0 && !c.zper, zr_dir = zhi >= g.nz && !c.zper;
+  zlo = zlo < 0 ? g.nz - 1 : zlo;
+  zhi = zhi >= g.nz ? 0 : zhi;
+  const T zl_hinv = (UNI || zl_dir) ? T(0) : ghinv[zlo], zr_hinv = (UNI || zr_dir) ? T(0) : ghinv[zhi];
+  const T zl_tp = UNI ? T(0) : gtp[zlo], zr_tp = UNI ? T(0) : gtp[zhi];
+  const T tau_c = g.pen * (c.tpx + c.tpy + tpz);
+  const T vol = c.hx * c.hy * hz;
+  const T vnu = vol * g.nu;
+  // pass 1: z-lines from registers: w = mu V u + B_z u
+  if (c.act) {
+    T w[N];
+    if constexpr (UNI) {
 #pragma unroll
-    for (int l = 0; l < N; ++l) w[l] = mv * u[l];
-    bline<N, T>(g.tab, u, zl, zr, L.dir, R.dir, hinv[2], L.hinv, R.hinv, L.tau, R.tau, vnu * hinv[2], w);
+      for (int l = 0; l < N; ++l) w[l] = T(0);
+      uline<N, T>(ut, 2, uc, up, un, w);
+    } else {
+      const T tzl = zl_dir ? tau_c : fmax(tau_c, g.pen * (c.tpx + c.tpy + zl_tp));
+      const T tzr = zr_dir ? tau_c : fmax(tau_c, g.pen * (c.tpx + c.tpy + zr_tp));
+      const T mv = g.mu * vol;
+#pragma unroll
+      for (int l = 0; l < N; ++l) w[l] = mv * uc[l];
+      bline<N, T>(tab, uc, up, un, zl_dir, zr_dir, hinvz, zl_hinv, zr_hinv, tzl, tzr, vnu * hinvz, w);
+    }
 #pragma unroll
     for (int l = 0; l < N; ++l) {
-      su[(l * N + t1) * P + t0] = u[l];
+      su[(l * N + t1) * P + t0] = uc[l];
       sw[(l * N + t1) * P + t0] = w[l];
     }
   }
   __syncthreads();
-  // pass 2: y-lines (i, l) = (t0, t1)
-  if (act) {
+  // pass 2: y-lines (i, l) = (t0, t1): w += B_y u
+  if (c.act) {
     const int i = t0, l = t1;
-    const Nb<N, T, PER> L = nbr<N, T, PER>(g, cell, c[1], nd[1], stride[1], 1, 0, tau_c, tp[0] + tp[2]);
-    const Nb<N, T, PER> R = nbr<N, T, PER>(g, cell, c[1], nd[1], stride[1], 1, 1, tau_c, tp[0] + tp[2]);
-    T uy[N], yl[N], yr[N], w[N];
+    const T* nl = s_u + c.yl_nb;
+    const T* nr = s_u + c.yr_nb;
+    T uy[N], vl[N], vr[N], w[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      yl[j] = L.dir ? T(0) : src[L.idx * N3 + l * N2 + j * N + i];
-      yr[j] = R.dir ? T(0) : src[R.idx * N3 + l * N2 + j * N + i];
-      uy[j] = su[(l * N + j) * P + i];
-      w[j] = sw[(l * N + j) * P + i];
+      const int e = (l * N + j) * P + i;
+      uy[j] = su[e];
+      w[j] = sw[e];
+      vl[j] = nl[e];
+      vr[j] = nr[e];
     }
-    bline<N, T>(g.tab, uy, yl, yr, L.dir, R.dir, hinv[1], L.hinv, R.hinv, L.tau, R.tau, vnu * hinv[1], w);
+    if constexpr (UNI) {
+      uline<N, T>(ut, 1, uy, vl, vr, w);
+    } else {
+      const T tl = c.yl_dir ? tau_c : fmax(tau_c, g.pen * (c.tpx + c.yl_tp + tpz));
+      const T tr = c.yr_dir ? tau_c : fmax(tau_c, g.pen * (c.tpx + c.yr_tp + tpz));
+      bline<N, T>(tab, uy, vl, vr, c.yl_dir, c.yr_dir, c.hinvy, c.yl_hinv, c.yr_hinv, tl, tr, vnu * c.hinvy, w);
+    }
 #pragma unroll
     for (int j = 0; j < N; ++j) sw[(l * N + j) * P + i] = w[j];
   }
-  __syncthreads();
-  // pass 3: x-lines (j, l) = (t0, t1); x-neighbour lines from LDS when in this block
-  if (act) {
-    const Nb<N, T, PER> L = nbr<N, T, PER>(g, cell, c[0], nd[0], stride[0], 0, 0, tau_c, tp[1] + tp[2]);
-    const Nb<N, T, PER> R = nbr<N, T, PER>(g, cell, c[0], nd[0], stride[0], 0, 1, tau_c, tp[1] + tp[2]);
+  wave_sync();
+  // pass 3: x-lines (j, l) = (t0, t1): w += B_x u, then w = Mx w
+  if (c.act) {
     const int lo = (t1 * N + t0) * P;
-    const int sl_l = lc + (c[0] > 0 ? -1 : g.nx - 1);
-    const int sl_r = lc + (c[0] < g.nx - 1 ? 1 : 1 - g.nx);
-    const bool inl = sl_l >= 0 && sl_l < CPB && q + (sl_l - lc) < ncs;
-    const bool inr = sl_r >= 0 && sl_r < CPB && q + (sl_r - lc) < ncs;
-    const int offx = (t1 * N + t0) * N;
-    T ux[N], xl[N], xr[N], w[N], o[N];
+    const T* nl = s_u + c.xl_nb;
+    const T* nr = s_u + c.xr_nb;
+    T ux[N], vl[N], vr[N], w[N], o[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       ux[i] = su[lo + i];
       w[i] = sw[lo + i];
-      xl[i] = L.dir ? T(0) : (inl ? s_u[sl_l * CL + lo + i] : src[L.idx * N3 + offx + i]);
-      xr[i] = R.dir ? T(0) : (inr ? s_u[sl_r * CL + lo + i] : src[R.idx * N3 + offx + i]);
+      vl[i] = nl[lo + i];
+      vr[i] = nr[lo + i];
       o[i] = T(0);
     }
-    bline<N, T>(g.tab, ux, xl, xr, L.dir, R.dir, hinv[0], L.hinv, R.hinv, L.tau, R.tau, vnu * hinv[0], w);
-    matvec_acc<N, T>(Mh, w, o);
+    if constexpr (UNI) {
+      uline<N, T>(ut, 0, ux, vl, vr, w);
+    } else {
+      const T tl = c.xl_dir ? tau_c : fmax(tau_c, g.pen * (c.xl_tp + c.tpy + tpz));
+      const T tr = c.xr_dir ? tau_c : fmax(tau_c, g.pen * (c.xr_tp + c.tpy + tpz));
+      bline<N, T>(tab, ux, vl, vr, c.xl_dir, c.xr_dir, c.hinvx, c.xl_hinv, c.xr_hinv, tl, tr, vnu * c.hinvx, w);
+    }
+    matvec_acc<N, T>(tab, w, o);
 #pragma unroll
     for (int i = 0; i < N; ++i) sw[lo + i] = o[i];
   }
-  __syncthreads();
+  __syncthreads();   // every wavefront is done with s_u (tile and rim) of this layer
   // pass 4: y-lines: w = My w
-  if (act) {
+  if (c.act) {
     const int i = t0, l = t1;
     T w[N], o[N];
 #pragma unroll
@@ -509,35 +464,205 @@ __global__ void __launch_bounds__(kApplyThreads) k_sipg_cart_apply(const T* __re
       w[j] = sw[(l * N + j) * P + i];
       o[j] = T(0);
     }
-    matvec_acc<N, T>(Mh, w, o);
+    matvec_acc<N, T>(tab, w, o);
 #pragma unroll
     for (int j = 0; j < N; ++j) sw[(l * N + j) * P + i] = o[j];
   }
-  __syncthreads();
-  // pass 5: z-lines: dst = Mz w
-  double pq = 0.0, sq = 0.0, sp = 0.0;
-  if (act) {
+  wave_sync();
+  // pass 5: z-lines: dst = Mz w (coalesced store); the rim of the next layer goes to LDS
+  if (c.act) {
     T w[N], o[N];
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       w[l] = sw[(l * N + t1) * P + t0];
       o[l] = T(0);
     }
-    matvec_acc<N, T>(Mh, w, o);
-    T* cd = dst + cell * N3 + t1 * N + t0;
+    matvec_acc<N, T>(tab, w, o);
+    T* cd = dst + (cz * c.nxy + c.col) * N3 + c.zoff;
 #pragma unroll
     for (int l = 0; l < N; ++l) __builtin_nontemporal_store(o[l], cd + l * N2);
-    if (partials) {
+    if (want_partials) {
 #pragma unroll
       for (int l = 0; l < N; ++l) {
-        pq += static_cast<double>(u[l]) * static_cast<double>(o[l]);
+        pq += static_cast<double>(uc[l]) * static_cast<double>(o[l]);
         sq += static_cast<double>(o[l]);
-        sp += static_cast<double>(u[l]);
+        sp += static_cast<double>(uc[l]);
       }
     }
   }
+  if (cz + 1 < z1) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int e = tid + k * TH;
+      if (e < NR * N3) {
+        const int r = e / N3, q = e - r * N3;
+        s_rim_next[r * C::CL + (q / N) * P + q % N] = c.rim[k];
+      }
+    }
+  }
+}
+
+template <int N, typename T, bool PER, bool UNI>
+__global__ void __launch_bounds__(Zm<N>::THREADS) k_sipg_zm_apply(const T* __restrict__ src, T* __restrict__ dst,
+                                                                 const CartGeom<T> g, const ZmPlan pl,
+                                                                 double* __restrict__ partials, const int* stop) {
+  if (stop && *stop) return;   // uniform for the whole grid: CG already finished
+  using Z = Zm<N>;
+  using C = ZmCtx<N, T>;
+  constexpr int N3 = Z::N3, P = Z::P, CL = Z::CL, TX = Z::TX, TY = Z::TY, NC = Z::NC, NR = C::NR;
+  // s_u holds the tile cells followed by the rim cells: neighbour lines are
+  // read from one array whether the neighbour is in the tile or not.
+  // s_u holds the tile cells followed by the rim cells, so neighbour lines are
+  // read from one array whether the neighbour is in the tile or not; s_w is
+  // private to each cell's wavefront.
+  __shared__ T s_u[1][(NC + NR) * CL];
+  __shared__ T s_w[NC * CL];
+  __shared__ int s_rimcol[NR];
+  __shared__ double s_red[3 * (Z::THREADS / 64)];
+  const cptr<T> tab = (cptr<T>)(g.tab);
+  const cptr<T> gh = (cptr<T>)(g.h[2]);
+  const cptr<T> ghinv = (cptr<T>)(g.hinv[2]);
+  const cptr<T> gtp = (cptr<T>)(g.tp[2]);
+  const int tid = threadIdx.x;
+  const int item = (blockIdx.x % 8) * pl.per_xcd + blockIdx.x / 8;
+  double pq = 0.0, sq = 0.0, sp = 0.0;
+  if (item < pl.total) {   // uniform over the workgroup
+    const int ntile = pl.tx * pl.ty;
+    const int seg = item / ntile, tile = item - seg * ntile;
+    const int tyi = tile / pl.tx, txi = tile - tyi * pl.tx;
+    const int x0 = txi * TX, y0 = tyi * TY;
+    const int wx = g.nx - x0 < TX ? g.nx - x0 : TX;   // active tile extent
+    const int wy = g.ny - y0 < TY ? g.ny - y0 : TY;
+    const int z0 = seg * pl.seglen;
+    const int z1 = z0 + pl.seglen < g.nz ? z0 + pl.seglen : g.nz;
+    C c;
+    const int lane = tid & 63, cw = lane / Z::N2;
+    const int lc = cw < Z::CPW ? (tid >> 6) * Z::CPW + cw : NC;
+    const int t = lane - cw * Z::N2;
+    c.t0 = t % N;
+    c.t1 = t / N;
+    const int a = lc % TX, b = lc / TX;
+    const int cx = x0 + a, cy = y0 + b;
+    c.act = lc < NC && a < wx && b < wy;
+    c.slot = (lc < NC ? lc : 0) * CL;
+    c.nxy = g.nx * g.ny;
+    c.col = c.act ? cy * g.nx + cx : 0;
+    c.zoff = c.t1 * N + c.t0;
+    c.zper = PER || g.per[2];
+    // rim cells: [0,TX) y-low of column a, [TX,2TX) y-high, then x-low / x-high of row b
+    if (tid < NR) {
+      int r = tid, col = -1;
+      if (r < 2 * TX) {
+        const int aa = r % TX, hi = r / TX;
+        if (aa < wx) {
+          int yy = hi ? y0 + wy : y0 - 1;
+          if (yy < 0 || yy >= g.ny) yy = (PER || g.per[1]) ? (yy < 0 ? g.ny - 1 : 0) : -1;
+          const bool inside = yy >= y0 && yy < y0 + wy;
+          if (yy >= 0 && !inside) col = yy * g.nx + x0 + aa;
+        }
+      } else {
+        r -= 2 * TX;
+        const int bb = r % TY, hi = r / TY;
+        if (bb < wy) {
+          int xx = hi ? x0 + wx : x0 - 1;
+          if (xx < 0 || xx >= g.nx) xx = (PER || g.per[0]) ? (xx < 0 ? g.nx - 1 : 0) : -1;
+          const bool inside = xx >= x0 && xx < x0 + wx;
+          if (xx >= 0 && !inside) col = (y0 + bb) * g.nx + xx;
+        }
+      }
+      s_rimcol[tid] = col;
+    }
+    // per-column geometry and neighbour slots (x and y do not change along the march)
+    c.hx = c.hy = c.hinvx = c.hinvy = c.tpx = c.tpy = T(0);
+    c.xl_dir = c.xr_dir = c.yl_dir = c.yr_dir = true;
+    c.xl_hinv = c.xr_hinv = c.yl_hinv = c.yr_hinv = c.xl_tp = c.xr_tp = c.yl_tp = c.yr_tp = T(0);
+    c.xl_nb = c.xr_nb = c.yl_nb = c.yr_nb = c.slot;
+#pragma unroll
+    for (int k = 0; k < C::RPT; ++k) c.rim[k] = T(0);
+    if (c.act) {
+      c.hx = g.h[0][cx];
+      c.hy = g.h[1][cy];
+      c.hinvx = g.hinv[0][cx];
+      c.hinvy = g.hinv[1][cy];
+      c.tpx = g.tp[0][cx];
+      c.tpy = g.tp[1][cy];
+      // x-low
+      int n = cx - 1;
+      if (n < 0) n = (PER || g.per[0]) ? g.nx - 1 : -1;
+      if (n >= 0) {
+        c.xl_dir = false;
+        c.xl_hinv = g.hinv[0][n];
+        c.xl_tp = g.tp[0][n];
+        c.xl_nb = (n >= x0 && n < x0 + wx) ? (lc + (n - cx)) * CL : (NC + 2 * TX + b) * CL;
+      }
+      n = cx + 1;
+      if (n >= g.nx) n = (PER || g.per[0]) ? 0 : -1;
+      if (n >= 0) {
+        c.xr_dir = false;
+        c.xr_hinv = g.hinv[0][n];
+        c.xr_tp = g.tp[0][n];
+        c.xr_nb = (n >= x0 && n < x0 + wx) ? (lc + (n - cx)) * CL : (NC + 2 * TX + TY + b) * CL;
+      }
+      n = cy - 1;
+      if (n < 0) n = (PER || g.per[1]) ? g.ny - 1 : -1;
+      if (n >= 0) {
+        c.yl_dir = false;
+        c.yl_hinv = g.hinv[1][n];
+        c.yl_tp = g.tp[1][n];
+        c.yl_nb = (n >= y0 && n < y0 + wy) ? (lc + (n - cy) * TX) * CL : (NC + a) * CL;
+      }
+      n = cy + 1;
+      if (n >= g.ny) n = (PER || g.per[1]) ? 0 : -1;
+      if (n >= 0) {
+        c.yr_dir = false;
+        c.yr_hinv = g.hinv[1][n];
+        c.yr_tp = g.tp[1][n];
+        c.yr_nb = (n >= y0 && n < y0 + wy) ? (lc + (n - cy) * TX) * CL : (NC + TX + a) * CL;
+      }
+    }
+    // z-line window: slots hold layers z0-1, z0, z0+1 (slot 2 receives z0+2)
+    T z[4][N];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int l = 0; l < N; ++l) z[s][l] = T(0);
+    if (c.act) {
+      const int zl = z0 - 1, zr = z0 + 1;
+      if (zl >= 0 || c.zper) load_zline<N, T>(src, (zl < 0 ? g.nz - 1 : zl) * c.nxy + c.col, c.zoff, z[3]);
+      load_zline<N, T>(src, z0 * c.nxy + c.col, c.zoff, z[0]);
+      if (zr < g.nz || c.zper) load_zline<N, T>(src, (zr >= g.nz ? 0 : zr) * c.nxy + c.col, c.zoff, z[1]);
+    }
+    __syncthreads();   // s_rimcol
+    // rim of the first layer
+#pragma unroll
+    for (int k = 0; k < C::RPT; ++k) {
+      const int e = tid + k * Z::THREADS;
+      if (e < NR * N3) {
+        const int r = e / N3, q = e - r * N3;
+        const int rc = s_rimcol[r];
+        if (rc >= 0) s_u[0][(NC + r) * CL + (q / N) * P + q % N] = src[(z0 * c.nxy + rc) * N3 + q];
+      }
+    }
+    // s_rim is read after the first barrier inside zm_layer
+    const bool wp = partials != nullptr;
+#pragma unroll 1
+    for (int cz = z0; cz < z1; cz += 4) {
+      T* const u0 = s_u[0];
+      T* const u1 = s_u[0];
+      zm_layer<N, T, PER, UNI>(src, dst, g, c, cz, z1, u0, s_w, u1 + NC * CL, s_rimcol, tab, gh, ghinv, gtp, z[3], z[0],
+                          z[1], z[2], wp, pq, sq, sp);
+      if (cz + 1 < z1)
+        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 1, z1, u1, s_w, u0 + NC * CL, s_rimcol, tab, gh, ghinv, gtp, z[0],
+                            z[1], z[2], z[3], wp, pq, sq, sp);
+      if (cz + 2 < z1)
+        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 2, z1, u0, s_w, u1 + NC * CL, s_rimcol, tab, gh, ghinv, gtp, z[1],
+                            z[2], z[3], z[0], wp, pq, sq, sp);
+      if (cz + 3 < z1)
+        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 3, z1, u1, s_w, u0 + NC * CL, s_rimcol, tab, gh, ghinv, gtp, z[2],
+                            z[3], z[0], z[1], wp, pq, sq, sp);
+    }
+  }
   if (partials) {
-    // wave64 shuffle reduction, then across the block's waves
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       pq += __shfl_down(pq, o, 64);
@@ -552,15 +677,15 @@ __global__ void __launch_bounds__(kApplyThreads) k_sipg_cart_apply(const T* __re
     }
     __syncthreads();
     if (tid == 0) {
-      double x = 0, y = 0, z = 0;
-      for (int k = 0; k < kApplyThreads / 64; ++k) {
+      double x = 0, y = 0, zz = 0;
+      for (int k = 0; k < Zm<N>::THREADS / 64; ++k) {
         x += s_red[3 * k];
         y += s_red[3 * k + 1];
-        z += s_red[3 * k + 2];
+        zz += s_red[3 * k + 2];
       }
       partials[4 * blockIdx.x] = x;
       partials[4 * blockIdx.x + 1] = y;
-      partials[4 * blockIdx.x + 2] = z;
+      partials[4 * blockIdx.x + 2] = zz;
     }
   }
 }
@@ -610,18 +735,53 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
   diag[gid] = dd[0] * md[1] * md[2] + md[0] * dd[1] * md[2] + md[0] * md[1] * dd[2];
 }
 
+template <int N>
+ZmPlan zm_plan_n(int nx, int ny, int nz) {
+  constexpr int TX = Zm<N>::TX, TY = Zm<N>::TY;
+  constexpr int kTargetBlocks = 1024;   // about four workgroups per compute unit
+  constexpr int kMinLayers = 4;         // shortest z segment
+  ZmPlan p{};
+  p.tx = (nx + TX - 1) / TX;
+  p.ty = (ny + TY - 1) / TY;
+  const int tiles = p.tx * p.ty;
+  int segs = (kTargetBlocks + tiles - 1) / tiles;
+  const int maxseg = nz / kMinLayers > 1 ? nz / kMinLayers : 1;
+  segs = segs < 1 ? 1 : (segs > maxseg ? maxseg : segs);
+  p.seglen = (nz + segs - 1) / segs;
+  p.segs = (nz + p.seglen - 1) / p.seglen;
+  p.total = tiles * p.segs;
+  p.per_xcd = (p.total + 7) / 8;
+  return p;
+}
+
+ZmPlan zm_plan(int n, int nx, int ny, int nz) {
+  switch (n) {
+    case 2: return zm_plan_n<2>(nx, ny, nz);
+    case 3: return zm_plan_n<3>(nx, ny, nz);
+    case 4: return zm_plan_n<4>(nx, ny, nz);
+    case 5: return zm_plan_n<5>(nx, ny, nz);
+    case 6: return zm_plan_n<6>(nx, ny, nz);
+    case 7: return zm_plan_n<7>(nx, ny, nz);
+    default: return zm_plan_n<8>(nx, ny, nz);
+  }
+}
+
 template <int N, typename T>
 dgmf_status launch_apply_n(const CartGeom<T>& g, const T* src, T* dst, int64_t ncells, double* partials,
                            const int* stop, hipStream_t s) {
   (void)ncells;
-  const int blocks = sipg_cart_blocks(N, CartGeom<double>{g.nx, g.ny, g.nz});
-  if (g.allper)
-    hipLaunchKernelGGL((k_sipg_cart_apply<N, T, true>), dim3(blocks), dim3(kApplyThreads), 0, s, src, dst, g, partials,
-                       stop);
+  const ZmPlan pl = zm_plan_n<N>(g.nx, g.ny, g.nz);
+  const int blocks = 8 * pl.per_xcd;
+  if (g.utab)
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, true>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst, g,
+                       pl, partials, stop);
+  else if (g.allper)
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, false>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst, g,
+                       pl, partials, stop);
   else
-    hipLaunchKernelGGL((k_sipg_cart_apply<N, T, false>), dim3(blocks), dim3(kApplyThreads), 0, s, src, dst, g,
-                       partials, stop);
-  DGMF_LAUNCH_CHECK("k_sipg_cart_apply");
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, false, false>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst, g,
+                       pl, partials, stop);
+  DGMF_LAUNCH_CHECK("k_sipg_zm_apply");
   return DGMF_OK;
 }
 
@@ -637,13 +797,7 @@ dgmf_status launch_diag_n(const CartGeom<T>& g, T* diag, int64_t ncells, hipStre
 
 }  // namespace
 
-int sipg_cart_blocks(int n, const CartGeom<double>& g) {
-  const int cpb = (kApplyThreads / (n * n)) > 0 ? kApplyThreads / (n * n) : 1;
-  const int nstrip = strip_count(g.ny);
-  const int hmax = g.ny / nstrip + (g.ny % nstrip ? 1 : 0);
-  const int64_t per_strip = static_cast<int64_t>(g.nx) * hmax * g.nz;
-  return static_cast<int>(nstrip * ((per_strip + cpb - 1) / cpb));
-}
+int sipg_cart_blocks(int n, const CartGeom<double>& g) { return 8 * zm_plan(n, g.nx, g.ny, g.nz).per_xcd; }
 
 template <typename T>
 dgmf_status launch_sipg_cart_apply(int n, const CartGeom<T>& g, const T* src, T* dst, int64_t ncells,
