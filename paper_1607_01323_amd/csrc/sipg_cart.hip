@@ -274,7 +274,7 @@ template <int N>
 struct Zm {
   static constexpr int N2 = N * N, N3 = N2 * N;
   static constexpr int P = (N % 2) ? N : N + 1;
-  static constexpr int CL = (N2 * P) | 1;   // odd cell stride: cells of one wavefront start on different banks
+  static constexpr int CL = N2 * P;
   static constexpr int TX = ZmTile<N>::TX, TY = ZmTile<N>::TY, NC = TX * TY;
   // a cell's n^2 threads never straddle two wavefronts, so transposes of a
   // cell's own lines through LDS need no workgroup barrier

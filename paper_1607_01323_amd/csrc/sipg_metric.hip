@@ -24,7 +24,6 @@
 namespace dgmf {
 namespace {
 
-constexpr int kMetThreads = 128;
 
 // ----------------------------------------------------------- table layout
 struct MTab {
@@ -39,74 +38,83 @@ struct MTab {
 };
 
 // ------------------------------------------------------------ LDS sweeps
-// 3D array [z][y][x] of extent N^3.  For every line along `axis`:
-//   out[line][q] (+)= sum_m A'[q][m] in[line][m],  A' = A or A^T (row-major N x N)
-template <int N, bool TR, bool ACC, typename T>
-__device__ __forceinline__ void sweep3(const T* __restrict__ A, const T* in, T* out, int axis, int tid, int nthr) {
-  constexpr int N2 = N * N;
-  const int st = axis == 0 ? 1 : (axis == 1 ? N : N2);
-  for (int job = tid; job < N2; job += nthr) {
-    const int a = job % N, b = job / N;
-    const int base = axis == 0 ? job * N : (axis == 1 ? b * N2 + a : job);
-    T v[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) v[m] = in[base + m * st];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = ACC ? out[base + q * st] : T(0);
-#pragma unroll
-      for (int m = 0; m < N; ++m) s = fma(TR ? A[m * N + q] : A[q * N + m], v[m], s);
-      out[base + q * st] = s;
-    }
-  }
+// Work of one cell is done by the n^2 lanes of that cell, which all sit in
+// one wavefront (several cells per wavefront when n^2 <= 32): the LDS
+// exchanges between the steps below only need this wavefront's ordering.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 2D plane [p2][p1] of extent N^2; lines along axis 0 (p1) or 1 (p2).
-template <int N, bool TR, bool ACC, typename T>
-__device__ __forceinline__ void sweep2(const T* __restrict__ A, const T* in, T* out, int axis, int tid, int nthr) {
-  const int st = axis == 0 ? 1 : N;
-  for (int job = tid; job < N; job += nthr) {
-    const int base = axis == 0 ? job * N : job;
-    T v[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) v[m] = in[base + m * st];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = ACC ? out[base + q * st] : T(0);
-#pragma unroll
-      for (int m = 0; m < N; ++m) s = fma(TR ? A[m * N + q] : A[q * N + m], v[m], s);
-      out[base + q * st] = s;
-    }
-  }
-}
-
-// several independent plane sweeps in one pass: job (plane k, line)
-template <typename T>
-struct PlaneOp {
-  const T* A;
-  const T* in;
-  T* out;
-  int axis, tr, acc;
+template <int N>
+struct MetShape {
+  static constexpr int N2 = N * N, N3 = N2 * N;
+  static constexpr int CPW = 64 / N2;              // cells per wavefront
+  static constexpr int WAVES = 4;
+  static constexpr int CPB = CPW * WAVES;          // cells per workgroup
+  static constexpr int THREADS = 64 * WAVES;
+  // LDS words per cell: u, out and the cell-part scratch (5 n^3), whose place
+  // the 23 face planes take after the cell part
+  static constexpr int CELL = 7 * N3 > 2 * N3 + 23 * N2 ? 7 * N3 : 2 * N3 + 23 * N2;
 };
 
-template <int N, int K, typename T>
-__device__ __forceinline__ void plane_ops(const PlaneOp<T> (&ops)[K], int tid, int nthr) {
-  for (int job = tid; job < K * N; job += nthr) {
-    const int k = job / N, line = job % N;
-    const PlaneOp<T>& o = ops[k];
-    const int st = o.axis == 0 ? 1 : N;
-    const int base = o.axis == 0 ? line * N : line;
+// 3D array [z][y][x] of extent N^3: lane t (0..n^2-1) owns line t along `axis`:
+//   out[line][q] (+)= sum_m A'[q][m] in[line][m],  A' = A or A^T (row-major N x N)
+template <int N, int AXIS, bool TR, bool ACC, typename T>
+__device__ __forceinline__ void sweep3(const T* __restrict__ A, const T* in, T* out, int t) {
+  constexpr int N2 = N * N;
+  constexpr int st = AXIS == 0 ? 1 : (AXIS == 1 ? N : N2);
+  const int a = t % N, b = t / N;
+  const int base = AXIS == 0 ? t * N : (AXIS == 1 ? b * N2 + a : t);
+  T v[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] = in[base + m * st];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    T s = ACC ? out[base + q * st] : T(0);
+#pragma unroll
+    for (int m = 0; m < N; ++m) s = fma(TR ? A[m * N + q] : A[q * N + m], v[m], s);
+    out[base + q * st] = s;
+  }
+}
+
+// Several independent sweeps over 2D planes [p2][p1] of extent N^2 (planes of
+// the face buffer F, n^2 words each), one job per (op, line).  Op k reads
+// plane in(k), writes plane out(k) (5-bit fields of icode / ocode), uses D
+// when bit k of dmask is set (else S), accumulates when bit k of amask is set.
+template <int N, int AXIS, bool TR, typename T>
+__device__ __forceinline__ void plane_ops(int nops, unsigned long long icode, unsigned long long ocode, unsigned dmask,
+                                          unsigned amask, const T* __restrict__ S, const T* __restrict__ D, T* F,
+                                          int t) {
+  constexpr int N2 = N * N;
+  constexpr int st = AXIS == 0 ? 1 : N;
+  for (int job = t; job < nops * N; job += N2) {
+    const int k = job / N, line = job - k * N;
+    const int pin = static_cast<int>((icode >> (5 * k)) & 31), pout = static_cast<int>((ocode >> (5 * k)) & 31);
+    const T* A = ((dmask >> k) & 1) ? D : S;
+    const bool acc = (amask >> k) & 1;
+    const int base = AXIS == 0 ? line * N : line;
+    const T* in = F + pin * N2;
+    T* out = F + pout * N2;
     T v[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) v[m] = o.in[base + m * st];
+    for (int m = 0; m < N; ++m) v[m] = in[base + m * st];
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-      T s = o.acc ? o.out[base + q * st] : T(0);
+      T s = acc ? out[base + q * st] : T(0);
 #pragma unroll
-      for (int m = 0; m < N; ++m) s = fma(o.tr ? o.A[m * N + q] : o.A[q * N + m], v[m], s);
-      o.out[base + q * st] = s;
+      for (int m = 0; m < N; ++m) s = fma(TR ? A[m * N + q] : A[q * N + m], v[m], s);
+      out[base + q * st] = s;
     }
   }
+}
+
+constexpr unsigned long long codes(int a0, int a1 = 0, int a2 = 0, int a3 = 0, int a4 = 0, int a5 = 0, int a6 = 0,
+                                   int a7 = 0) {
+  return (unsigned long long)a0 | ((unsigned long long)a1 << 5) | ((unsigned long long)a2 << 10) |
+         ((unsigned long long)a3 << 15) | ((unsigned long long)a4 << 20) | ((unsigned long long)a5 << 25) |
+         ((unsigned long long)a6 << 30) | ((unsigned long long)a7 << 35);
 }
 
 // node index of face-plane entry (p1 along t1, p2 along t2) of the plane at
@@ -126,145 +134,147 @@ __device__ __forceinline__ int plane_index(const MetricGeom<T>& g, int d, int c0
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__(kMetThreads) k_sipg_metric_apply(const T* __restrict__ src,
-                                                                   T* __restrict__ dst, const MetricGeom<T> g,
-                                                                   double* __restrict__ partials,
-                                                                   const int* stop) {
+__global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(const T* __restrict__ src,
+                                                                             T* __restrict__ dst, const MetricGeom<T> g,
+                                                                             double* __restrict__ partials,
+                                                                             const int* stop) {
   if (stop && *stop) return;
-  constexpr int N2 = N * N, N3 = N2 * N;
-  __shared__ T sU[N3], sO[N3], sA[N3], sB[3 * N3], sC[N3];
-  __shared__ T sF[24 * N2];
-  __shared__ double s_red[3 * (kMetThreads / 64)];
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int cell = blockIdx.x;
-  const int c[3] = {cell % g.nx, (cell / g.nx) % g.ny, cell / (g.nx * g.ny)};
-  const int nd[3] = {g.nx, g.ny, g.nz};
-  const int stride[3] = {1, g.nx, g.nx * g.ny};
+  using M = MetShape<N>;
+  constexpr int N2 = M::N2, N3 = M::N3;
+  __shared__ T s_cells[M::CPB * M::CELL];
+  __shared__ double s_red[3 * M::WAVES];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int cw = lane / N2;
+  const int t = lane - cw * N2;
+  const int ncells = g.nx * g.ny * g.nz;
+  const int cell = blockIdx.x * M::CPB + w * M::CPW + cw;
+  const bool act = cw < M::CPW && cell < ncells;
+  T* sU = s_cells + (w * M::CPW + (cw < M::CPW ? cw : 0)) * M::CELL;
+  T* sO = sU + N3;
+  T* sA = sU + 2 * N3;
+  T* sB = sU + 3 * N3;   // 3 N^3
+  T* sC = sU + 6 * N3;
+  T* sF = sA;            // face planes, after the cell part
   const T* S = g.tab + MTab{N}.S();
   const T* D = g.tab + MTab{N}.D();
   const T* Dg = g.tab + MTab{N}.Dg();
   const T* g0 = g.tab + MTab{N}.g0();
   const T* g1 = g.tab + MTab{N}.g1();
-  for (int e = tid; e < N3; e += nthr) {
-    sU[e] = src[cell * N3 + e];
-    sO[e] = T(0);
-  }
-  __syncthreads();
-  // ---- cell integral: values and reference gradients at the Gauss points
-  sweep3<N, false, false>(S, sU, sC, 0, tid, nthr);
-  __syncthreads();
-  sweep3<N, false, false>(S, sC, sB, 1, tid, nthr);
-  __syncthreads();
-  sweep3<N, false, false>(S, sB, sA, 2, tid, nthr);   // sA = u at the points
-  __syncthreads();
-  sweep3<N, false, false>(Dg, sA, sB, 0, tid, nthr);
-  sweep3<N, false, false>(Dg, sA, sB + N3, 1, tid, nthr);
-  sweep3<N, false, false>(Dg, sA, sB + 2 * N3, 2, tid, nthr);
-  __syncthreads();
-  {
-    const T* cm = g.cm + static_cast<int64_t>(cell) * 7 * N3;
-    for (int q = tid; q < N3; q += nthr) {
-      const T gx = sB[q], gy = sB[N3 + q], gz = sB[2 * N3 + q];
-      const T G00 = cm[q], G01 = cm[N3 + q], G02 = cm[2 * N3 + q];
-      const T G11 = cm[3 * N3 + q], G12 = cm[4 * N3 + q], G22 = cm[5 * N3 + q], m = cm[6 * N3 + q];
-      sB[q] = g.nu * (G00 * gx + G01 * gy + G02 * gz);
-      sB[N3 + q] = g.nu * (G01 * gx + G11 * gy + G12 * gz);
-      sB[2 * N3 + q] = g.nu * (G02 * gx + G12 * gy + G22 * gz);
-      sC[q] = g.mu * m * sA[q];
+  double pq = 0.0, sq = 0.0, sp = 0.0;
+  if (act) {
+    const int c[3] = {cell % g.nx, (cell / g.nx) % g.ny, cell / (g.nx * g.ny)};
+    const int nd[3] = {g.nx, g.ny, g.nz};
+    const int stride[3] = {1, g.nx, g.nx * g.ny};
+    for (int e = t; e < N3; e += N2) {
+      sU[e] = src[cell * N3 + e];
+      sO[e] = T(0);
     }
-  }
-  __syncthreads();
-  sweep3<N, true, true>(Dg, sB, sC, 0, tid, nthr);
-  __syncthreads();
-  sweep3<N, true, true>(Dg, sB + N3, sC, 1, tid, nthr);
-  __syncthreads();
-  sweep3<N, true, true>(Dg, sB + 2 * N3, sC, 2, tid, nthr);
-  __syncthreads();
-  sweep3<N, true, false>(S, sC, sA, 2, tid, nthr);
-  __syncthreads();
-  sweep3<N, true, false>(S, sA, sC, 1, tid, nthr);
-  __syncthreads();
-  sweep3<N, true, true>(S, sC, sO, 0, tid, nthr);
-  __syncthreads();
+    wave_sync();
+    // ---- cell integral: values and reference gradients at the Gauss points
+    sweep3<N, 0, false, false>(S, sU, sC, t);
+    wave_sync();
+    sweep3<N, 1, false, false>(S, sC, sB, t);
+    wave_sync();
+    sweep3<N, 2, false, false>(S, sB, sA, t);   // sA = u at the points
+    wave_sync();
+    sweep3<N, 0, false, false>(Dg, sA, sB, t);
+    sweep3<N, 1, false, false>(Dg, sA, sB + N3, t);
+    sweep3<N, 2, false, false>(Dg, sA, sB + 2 * N3, t);
+    wave_sync();
+    {
+      const T* cm = g.cm + static_cast<int64_t>(cell) * 7 * N3;
+      for (int q = t; q < N3; q += N2) {
+        const T gx = sB[q], gy = sB[N3 + q], gz = sB[2 * N3 + q];
+        const T G00 = cm[q], G01 = cm[N3 + q], G02 = cm[2 * N3 + q];
+        const T G11 = cm[3 * N3 + q], G12 = cm[4 * N3 + q], G22 = cm[5 * N3 + q], m = cm[6 * N3 + q];
+        sB[q] = g.nu * (G00 * gx + G01 * gy + G02 * gz);
+        sB[N3 + q] = g.nu * (G01 * gx + G11 * gy + G12 * gz);
+        sB[2 * N3 + q] = g.nu * (G02 * gx + G12 * gy + G22 * gz);
+        sC[q] = g.mu * m * sA[q];
+      }
+    }
+    wave_sync();
+    sweep3<N, 0, true, true>(Dg, sB, sC, t);
+    wave_sync();
+    sweep3<N, 1, true, true>(Dg, sB + N3, sC, t);
+    wave_sync();
+    sweep3<N, 2, true, true>(Dg, sB + 2 * N3, sC, t);
+    wave_sync();
+    sweep3<N, 2, true, false>(S, sC, sA, t);
+    wave_sync();
+    sweep3<N, 1, true, false>(S, sA, sC, t);
+    wave_sync();
+    sweep3<N, 0, true, true>(S, sC, sO, t);
+    wave_sync();
 
-  // ---- faces
-  // sF layout (planes of N2): 0 Pown, 1 PNown, 2 Pnb, 3 PNnb, 4..5 stage own, 6..7 stage nb,
-  //  8 val_own, 9 dt1_own, 10 dt2_own, 11 dn_own, 12 val_nb, 13 dt1_nb, 14 dt2_nb, 15 dn_nb,
-  //  16 fv, 17 fg_d, 18 fg_t1, 19 fg_t2, 20..23 lift stages
+    // ---- faces
+    // sF planes (n^2 each): 0 Pown, 1 PNown, 2 Pnb, 3 PNnb, 4..5 stage own, 6..7 stage nb,
+    //  8 val_own, 9 dt1_own, 10 dt2_own, 11 dn_own, 12 val_nb, 13 dt1_nb, 14 dt2_nb, 15 dn_nb,
+    //  16 fv, 17 fg_d, 18 fg_t1, 19 fg_t2, 20..22 lift stages
 #pragma unroll 1
-  for (int f = 0; f < 6; ++f) {
-    const int d = f >> 1, s = f & 1;
-    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    int cn = c[d] + (s ? 1 : -1), nb = -1;
-    if (cn < 0 || cn >= nd[d]) {
-      if (g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
-      else cn = -1;
-    }
-    if (cn >= 0) nb = cell + (cn - c[d]) * stride[d];
-    const T* gs = s ? g1 : g0;      // normal derivative row at the own face
-    const T* gn = s ? g0 : g1;      // ... at the neighbour's face
-    const int eo = s ? N - 1 : 0, en = s ? 0 : N - 1;
-    for (int p = tid; p < N2; p += nthr) {
-      const int p1 = p % N, p2 = p / N;
-      sF[0 * N2 + p] = sU[fnode<N>(d, eo, p1, p2)];
-      T dn = T(0);
-#pragma unroll
-      for (int m = 0; m < N; ++m) dn = fma(gs[m], sU[fnode<N>(d, m, p1, p2)], dn);
-      sF[1 * N2 + p] = dn;
-      if (nb >= 0) {
-        const T* un = src + static_cast<int64_t>(nb) * N3;
-        sF[2 * N2 + p] = un[fnode<N>(d, en, p1, p2)];
-        T dnn = T(0);
-#pragma unroll
-        for (int m = 0; m < N; ++m) dnn = fma(gn[m], un[fnode<N>(d, m, p1, p2)], dnn);
-        sF[3 * N2 + p] = dnn;
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1, s = f & 1;
+      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      int cn = c[d] + (s ? 1 : -1), nb = -1;
+      if (cn < 0 || cn >= nd[d]) {
+        if (g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
+        else cn = -1;
       }
-    }
-    __syncthreads();
-    // first sweeps along t1 (p1): S P, D P for both sides, S PN for both sides
-    {
-      const PlaneOp<T> ops[6] = {{S, sF + 0 * N2, sF + 4 * N2, 0, 0, 0}, {D, sF + 0 * N2, sF + 5 * N2, 0, 0, 0},
-                              {S, sF + 1 * N2, sF + 20 * N2, 0, 0, 0}, {S, sF + 2 * N2, sF + 6 * N2, 0, 0, 0},
-                              {D, sF + 2 * N2, sF + 7 * N2, 0, 0, 0}, {S, sF + 3 * N2, sF + 21 * N2, 0, 0, 0}};
-      plane_ops<N, 6>(ops, tid, nthr);
-    }
-    __syncthreads();
-    // second sweeps along t2 (p2): val = S(SP), dt1 = S(DP), dt2 = D(SP), dn = S(S PN)
-    {
-      const PlaneOp<T> ops[8] = {{S, sF + 4 * N2, sF + 8 * N2, 1, 0, 0},   {S, sF + 5 * N2, sF + 9 * N2, 1, 0, 0},
-                              {D, sF + 4 * N2, sF + 10 * N2, 1, 0, 0},  {S, sF + 20 * N2, sF + 11 * N2, 1, 0, 0},
-                              {S, sF + 6 * N2, sF + 12 * N2, 1, 0, 0},  {S, sF + 7 * N2, sF + 13 * N2, 1, 0, 0},
-                              {D, sF + 6 * N2, sF + 14 * N2, 1, 0, 0},  {S, sF + 21 * N2, sF + 15 * N2, 1, 0, 0}};
-      plane_ops<N, 8>(ops, tid, nthr);
-    }
-    __syncthreads();
-    // flux at the face points
-    {
-      const T* fm;
-      T tau;
-      bool own_is_L;
-      if (s == 1) {
-        fm = g.fm + (static_cast<int64_t>(cell) * 3 + d) * 7 * N2;
-        tau = g.ftau[cell * 3 + d];
-        own_is_L = true;
-      } else if (nb >= 0) {
-        fm = g.fm + (static_cast<int64_t>(nb) * 3 + d) * 7 * N2;
-        tau = g.ftau[nb * 3 + d];
-        own_is_L = false;
-      } else {
-        const int pi = plane_index(g, d, c[0], c[1], c[2]);
-        fm = g.lm + (static_cast<int64_t>(g.lbase[d]) + pi) * 7 * N2;
-        tau = g.ltau[g.lbase[d] + pi];
-        own_is_L = true;
+      if (cn >= 0) nb = cell + (cn - c[d]) * stride[d];
+      const T* gs = s ? g1 : g0;      // normal derivative row at the own face
+      const T* gn = s ? g0 : g1;      // ... at the neighbour's face
+      const int eo = s ? N - 1 : 0, en = s ? 0 : N - 1;
+      {
+        const int p1 = t % N, p2 = t / N;
+        sF[0 * N2 + t] = sU[fnode<N>(d, eo, p1, p2)];
+        T dn = T(0);
+#pragma unroll
+        for (int m = 0; m < N; ++m) dn = fma(gs[m], sU[fnode<N>(d, m, p1, p2)], dn);
+        sF[1 * N2 + t] = dn;
+        if (nb >= 0) {
+          const T* un = src + static_cast<int64_t>(nb) * N3;
+          sF[2 * N2 + t] = un[fnode<N>(d, en, p1, p2)];
+          T dnn = T(0);
+#pragma unroll
+          for (int m = 0; m < N; ++m) dnn = fma(gn[m], un[fnode<N>(d, m, p1, p2)], dnn);
+          sF[3 * N2 + t] = dnn;
+        }
       }
-      tau *= g.pen;
-      for (int p = tid; p < N2; p += nthr) {
+      wave_sync();
+      // along t1 (p1): S P, D P for both sides, S PN for both sides
+      plane_ops<N, 0, false, T>(6, codes(0, 0, 1, 2, 2, 3), codes(4, 5, 20, 6, 7, 21), 0b010010u, 0u, S, D, sF, t);
+      wave_sync();
+      // along t2 (p2): val = S(SP), dt1 = S(DP), dt2 = D(SP), dn = S(S PN)
+      plane_ops<N, 1, false, T>(8, codes(4, 5, 4, 20, 6, 7, 6, 21), codes(8, 9, 10, 11, 12, 13, 14, 15), 0b01000100u,
+                                0u, S, D, sF, t);
+      wave_sync();
+      {
+        const T* fm;
+        T tau;
+        bool own_is_L;
+        if (s == 1) {
+          fm = g.fm + (static_cast<int64_t>(cell) * 3 + d) * 7 * N2;
+          tau = g.ftau[cell * 3 + d];
+          own_is_L = true;
+        } else if (nb >= 0) {
+          fm = g.fm + (static_cast<int64_t>(nb) * 3 + d) * 7 * N2;
+          tau = g.ftau[nb * 3 + d];
+          own_is_L = false;
+        } else {
+          const int pi = plane_index(g, d, c[0], c[1], c[2]);
+          fm = g.lm + (static_cast<int64_t>(g.lbase[d]) + pi) * 7 * N2;
+          tau = g.ltau[g.lbase[d] + pi];
+          own_is_L = true;
+        }
+        tau *= g.pen;
+        const int p = t;
         const T wdA = fm[p];
-        const T vL[3] = {fm[N2 + p], fm[2 * N2 + p], fm[3 * N2 + p]};
-        const T vR[3] = {fm[4 * N2 + p], fm[5 * N2 + p], fm[6 * N2 + p]};
-        const T* vo = own_is_L ? vL : vR;
-        const T* vn = own_is_L ? vR : vL;
-        T go[3], gnb[3];
+        const T vL0 = fm[N2 + p], vL1 = fm[2 * N2 + p], vL2 = fm[3 * N2 + p];
+        const T vR0 = fm[4 * N2 + p], vR1 = fm[5 * N2 + p], vR2 = fm[6 * N2 + p];
+        const T vo[3] = {own_is_L ? vL0 : vR0, own_is_L ? vL1 : vR1, own_is_L ? vL2 : vR2};
+        const T vn[3] = {own_is_L ? vR0 : vL0, own_is_L ? vR1 : vL1, own_is_L ? vR2 : vL2};
+        T go[3];
         go[d] = sF[11 * N2 + p];
         go[t1] = sF[9 * N2 + p];
         go[t2] = sF[10 * N2 + p];
@@ -272,6 +282,7 @@ __global__ void __launch_bounds__(kMetThreads) k_sipg_metric_apply(const T* __re
         const T ano = go[0] * vo[0] + go[1] * vo[1] + go[2] * vo[2];
         T fv, fgc;
         if (nb >= 0) {
+          T gnb[3];
           gnb[d] = sF[15 * N2 + p];
           gnb[t1] = sF[13 * N2 + p];
           gnb[t2] = sF[14 * N2 + p];
@@ -290,48 +301,35 @@ __global__ void __launch_bounds__(kMetThreads) k_sipg_metric_apply(const T* __re
         sF[18 * N2 + p] = g.nu * fgc * vo[t1];
         sF[19 * N2 + p] = g.nu * fgc * vo[t2];
       }
-    }
-    __syncthreads();
-    // transposed sweeps along t2: a = S^T fv + D^T fg_t2, b = S^T fg_t1, c = S^T fg_d
-    {
-      // the two ops writing plane 20 run one after the other
-      const PlaneOp<T> first[1] = {{S, sF + 16 * N2, sF + 20 * N2, 1, 1, 0}};
-      plane_ops<N, 1>(first, tid, nthr);
-      __syncthreads();
-      const PlaneOp<T> rest[3] = {{D, sF + 19 * N2, sF + 20 * N2, 1, 1, 1}, {S, sF + 18 * N2, sF + 21 * N2, 1, 1, 0},
-                               {S, sF + 17 * N2, sF + 22 * N2, 1, 1, 0}};
-      plane_ops<N, 3>(rest, tid, nthr);
-    }
-    __syncthreads();
-    // along t1: face plane = S^T a + D^T b; normal plane = S^T c
-    {
-      const PlaneOp<T> ops[2] = {{S, sF + 20 * N2, sF + 4 * N2, 0, 1, 0}, {S, sF + 22 * N2, sF + 5 * N2, 0, 1, 0}};
-      plane_ops<N, 2>(ops, tid, nthr);
-    }
-    __syncthreads();
-    {
-      const PlaneOp<T> ops[1] = {{D, sF + 21 * N2, sF + 4 * N2, 0, 1, 1}};
-      plane_ops<N, 1>(ops, tid, nthr);
-    }
-    __syncthreads();
-    // scatter: value/tangential part onto the own face plane, normal part along the normal lines
-    for (int p = tid; p < N2; p += nthr) {
-      const int p1 = p % N, p2 = p / N;
-      const T cn_ = sF[5 * N2 + p];
-      sO[fnode<N>(d, eo, p1, p2)] += sF[4 * N2 + p];
+      wave_sync();
+      // transposed along t2: a = S^T fv (then += D^T fg_t2), b = S^T fg_t1, c = S^T fg_d
+      plane_ops<N, 1, true, T>(3, codes(16, 18, 17), codes(20, 21, 22), 0u, 0u, S, D, sF, t);
+      wave_sync();
+      plane_ops<N, 1, true, T>(1, codes(19), codes(20), 1u, 1u, S, D, sF, t);
+      wave_sync();
+      // along t1: face plane = S^T a (+ D^T b); normal plane = S^T c
+      plane_ops<N, 0, true, T>(2, codes(20, 22), codes(4, 5), 0u, 0u, S, D, sF, t);
+      wave_sync();
+      plane_ops<N, 0, true, T>(1, codes(21), codes(4), 1u, 1u, S, D, sF, t);
+      wave_sync();
+      // scatter: face part onto the own face plane, normal part along the normal lines
+      {
+        const int p1 = t % N, p2 = t / N;
+        const T cn_ = sF[5 * N2 + t];
+        sO[fnode<N>(d, eo, p1, p2)] += sF[4 * N2 + t];
 #pragma unroll
-      for (int m = 0; m < N; ++m) sO[fnode<N>(d, m, p1, p2)] += gs[m] * cn_;
+        for (int m = 0; m < N; ++m) sO[fnode<N>(d, m, p1, p2)] += gs[m] * cn_;
+      }
+      wave_sync();
     }
-    __syncthreads();
-  }
-  double pq = 0.0, sq = 0.0, sp = 0.0;
-  for (int e = tid; e < N3; e += nthr) {
-    const T v = sO[e];
-    dst[cell * N3 + e] = v;
-    if (partials) {
-      pq += static_cast<double>(sU[e]) * v;
-      sq += v;
-      sp += sU[e];
+    for (int e = t; e < N3; e += N2) {
+      const T v = sO[e];
+      dst[cell * N3 + e] = v;
+      if (partials) {
+        pq += static_cast<double>(sU[e]) * v;
+        sq += v;
+        sp += sU[e];
+      }
     }
   }
   if (partials) {
@@ -341,8 +339,7 @@ __global__ void __launch_bounds__(kMetThreads) k_sipg_metric_apply(const T* __re
       sq += __shfl_down(sq, o, 64);
       sp += __shfl_down(sp, o, 64);
     }
-    const int w = tid >> 6;
-    if ((tid & 63) == 0) {
+    if (lane == 0) {
       s_red[3 * w] = pq;
       s_red[3 * w + 1] = sq;
       s_red[3 * w + 2] = sp;
@@ -350,7 +347,7 @@ __global__ void __launch_bounds__(kMetThreads) k_sipg_metric_apply(const T* __re
     __syncthreads();
     if (tid == 0) {
       double x = 0, y = 0, z = 0;
-      for (int k = 0; k < kMetThreads / 64; ++k) {
+      for (int k = 0; k < M::WAVES; ++k) {
         x += s_red[3 * k];
         y += s_red[3 * k + 1];
         z += s_red[3 * k + 2];
@@ -579,16 +576,22 @@ __global__ void __launch_bounds__(256) k_to_f32(const double* __restrict__ a, fl
 
 #define DGMF_MET_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
+int metric_apply_blocks(int n, int64_t ncells) {
+  const int cpb = 4 * (64 / (n * n));
+  return static_cast<int>((ncells + cpb - 1) / cpb);
+}
+
 template <typename T>
 dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials,
                                      const int* stop, hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>(g.nx * g.ny * g.nz);
-#define X(a)                                                                                         \
-  if (n == a) {                                                                                      \
-    hipLaunchKernelGGL((k_sipg_metric_apply<a, T>), dim3(blocks), dim3(kMetThreads), 0, s, src, dst, g, \
-                       partials, stop);                                                              \
-    DGMF_LAUNCH_CHECK("k_sipg_metric_apply");                                                        \
-    return DGMF_OK;                                                                                  \
+  const int64_t ncells = static_cast<int64_t>(g.nx) * g.ny * g.nz;
+  const unsigned blocks = static_cast<unsigned>(metric_apply_blocks(n, ncells));
+#define X(a)                                                                                                 \
+  if (n == a) {                                                                                              \
+    hipLaunchKernelGGL((k_sipg_metric_apply<a, T>), dim3(blocks), dim3(MetShape<a>::THREADS), 0, s, src, dst, \
+                       g, partials, stop);                                                                   \
+    DGMF_LAUNCH_CHECK("k_sipg_metric_apply");                                                                \
+    return DGMF_OK;                                                                                          \
   }
   DGMF_MET_CASES(X)
 #undef X
