@@ -166,9 +166,67 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
     const int c[3] = {cell % g.nx, (cell / g.nx) % g.ny, cell / (g.nx * g.ny)};
     const int nd[3] = {g.nx, g.ny, g.nz};
     const int stride[3] = {1, g.nx, g.nx * g.ny};
-    for (int e = t; e < N3; e += N2) {
-      sU[e] = src[cell * N3 + e];
-      sO[e] = T(0);
+    const int p1 = t % N, p2 = t / N;
+    // ---- every global load of this cell is issued up front, so that their
+    // latencies overlap the cell integral instead of stalling each face
+    // (in fp64 the cell and face metric are loaded where they are used:
+    // hoisting them too would cost the registers of a second wavefront per SIMD)
+    constexpr bool kHoistCm = sizeof(T) == 4;
+    const T* cm = g.cm + static_cast<int64_t>(cell) * 7 * N3;
+    T uo[N], cmv[7][N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) uo[m] = src[cell * N3 + t + m * N2];
+    if constexpr (kHoistCm) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k)
+#pragma unroll
+        for (int m = 0; m < N; ++m) cmv[k][m] = cm[k * N3 + t + m * N2];
+    }
+    int nbc[6];
+    bool ownL[6];
+    const T* fmp[6];
+    T ftau[6], nbv[6][N], fmv[6][7];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1, s = f & 1;
+      int cn = c[d] + (s ? 1 : -1);
+      nbc[f] = -1;
+      if (cn < 0 || cn >= nd[d]) {
+        if (g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
+        else cn = -1;
+      }
+      if (cn >= 0) nbc[f] = cell + (cn - c[d]) * stride[d];
+      if (s == 1) {
+        fmp[f] = g.fm + (static_cast<int64_t>(cell) * 3 + d) * 7 * N2;
+        ftau[f] = g.ftau[cell * 3 + d];
+        ownL[f] = true;
+      } else if (nbc[f] >= 0) {
+        fmp[f] = g.fm + (static_cast<int64_t>(nbc[f]) * 3 + d) * 7 * N2;
+        ftau[f] = g.ftau[nbc[f] * 3 + d];
+        ownL[f] = false;
+      } else {
+        const int pi = plane_index(g, d, c[0], c[1], c[2]);
+        fmp[f] = g.lm + (static_cast<int64_t>(g.lbase[d]) + pi) * 7 * N2;
+        ftau[f] = g.ltau[g.lbase[d] + pi];
+        ownL[f] = true;
+      }
+      if constexpr (kHoistCm) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
+      }
+      if (nbc[f] >= 0) {
+        const T* un = src + static_cast<int64_t>(nbc[f]) * N3;
+#pragma unroll
+        for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
+      } else {
+#pragma unroll
+        for (int m = 0; m < N; ++m) nbv[f][m] = T(0);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      sU[t + m * N2] = uo[m];
+      sO[t + m * N2] = T(0);
     }
     wave_sync();
     // ---- cell integral: values and reference gradients at the Gauss points
@@ -182,17 +240,20 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
     sweep3<N, 1, false, false>(Dg, sA, sB + N3, t);
     sweep3<N, 2, false, false>(Dg, sA, sB + 2 * N3, t);
     wave_sync();
-    {
-      const T* cm = g.cm + static_cast<int64_t>(cell) * 7 * N3;
-      for (int q = t; q < N3; q += N2) {
-        const T gx = sB[q], gy = sB[N3 + q], gz = sB[2 * N3 + q];
-        const T G00 = cm[q], G01 = cm[N3 + q], G02 = cm[2 * N3 + q];
-        const T G11 = cm[3 * N3 + q], G12 = cm[4 * N3 + q], G22 = cm[5 * N3 + q], m = cm[6 * N3 + q];
-        sB[q] = g.nu * (G00 * gx + G01 * gy + G02 * gz);
-        sB[N3 + q] = g.nu * (G01 * gx + G11 * gy + G12 * gz);
-        sB[2 * N3 + q] = g.nu * (G02 * gx + G12 * gy + G22 * gz);
-        sC[q] = g.mu * m * sA[q];
-      }
+    if constexpr (!kHoistCm) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k)
+#pragma unroll
+        for (int m = 0; m < N; ++m) cmv[k][m] = cm[k * N3 + t + m * N2];
+    }
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const int q = t + m * N2;
+      const T gx = sB[q], gy = sB[N3 + q], gz = sB[2 * N3 + q];
+      sB[q] = g.nu * (cmv[0][m] * gx + cmv[1][m] * gy + cmv[2][m] * gz);
+      sB[N3 + q] = g.nu * (cmv[1][m] * gx + cmv[3][m] * gy + cmv[4][m] * gz);
+      sB[2 * N3 + q] = g.nu * (cmv[2][m] * gx + cmv[4][m] * gy + cmv[5][m] * gz);
+      sC[q] = g.mu * cmv[6][m] * sA[q];
     }
     wave_sync();
     sweep3<N, 0, true, true>(Dg, sB, sC, t);
@@ -212,32 +273,25 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
     // sF planes (n^2 each): 0 Pown, 1 PNown, 2 Pnb, 3 PNnb, 4..5 stage own, 6..7 stage nb,
     //  8 val_own, 9 dt1_own, 10 dt2_own, 11 dn_own, 12 val_nb, 13 dt1_nb, 14 dt2_nb, 15 dn_nb,
     //  16 fv, 17 fg_d, 18 fg_t1, 19 fg_t2, 20..22 lift stages
-#pragma unroll 1
+#pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1, s = f & 1;
       const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-      int cn = c[d] + (s ? 1 : -1), nb = -1;
-      if (cn < 0 || cn >= nd[d]) {
-        if (g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
-        else cn = -1;
-      }
-      if (cn >= 0) nb = cell + (cn - c[d]) * stride[d];
+      const int nb = nbc[f];
       const T* gs = s ? g1 : g0;      // normal derivative row at the own face
       const T* gn = s ? g0 : g1;      // ... at the neighbour's face
       const int eo = s ? N - 1 : 0, en = s ? 0 : N - 1;
       {
-        const int p1 = t % N, p2 = t / N;
         sF[0 * N2 + t] = sU[fnode<N>(d, eo, p1, p2)];
         T dn = T(0);
 #pragma unroll
         for (int m = 0; m < N; ++m) dn = fma(gs[m], sU[fnode<N>(d, m, p1, p2)], dn);
         sF[1 * N2 + t] = dn;
         if (nb >= 0) {
-          const T* un = src + static_cast<int64_t>(nb) * N3;
-          sF[2 * N2 + t] = un[fnode<N>(d, en, p1, p2)];
+          sF[2 * N2 + t] = nbv[f][en];
           T dnn = T(0);
 #pragma unroll
-          for (int m = 0; m < N; ++m) dnn = fma(gn[m], un[fnode<N>(d, m, p1, p2)], dnn);
+          for (int m = 0; m < N; ++m) dnn = fma(gn[m], nbv[f][m], dnn);
           sF[3 * N2 + t] = dnn;
         }
       }
@@ -249,36 +303,24 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
       plane_ops<N, 1, false, T>(8, codes(4, 5, 4, 20, 6, 7, 6, 21), codes(8, 9, 10, 11, 12, 13, 14, 15), 0b01000100u,
                                 0u, S, D, sF, t);
       wave_sync();
+      if constexpr (!kHoistCm) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
+      }
       {
-        const T* fm;
-        T tau;
-        bool own_is_L;
-        if (s == 1) {
-          fm = g.fm + (static_cast<int64_t>(cell) * 3 + d) * 7 * N2;
-          tau = g.ftau[cell * 3 + d];
-          own_is_L = true;
-        } else if (nb >= 0) {
-          fm = g.fm + (static_cast<int64_t>(nb) * 3 + d) * 7 * N2;
-          tau = g.ftau[nb * 3 + d];
-          own_is_L = false;
-        } else {
-          const int pi = plane_index(g, d, c[0], c[1], c[2]);
-          fm = g.lm + (static_cast<int64_t>(g.lbase[d]) + pi) * 7 * N2;
-          tau = g.ltau[g.lbase[d] + pi];
-          own_is_L = true;
-        }
-        tau *= g.pen;
+        const bool own_is_L = ownL[f];
+        const T tau = ftau[f] * g.pen;
         const int p = t;
-        const T wdA = fm[p];
-        const T vL0 = fm[N2 + p], vL1 = fm[2 * N2 + p], vL2 = fm[3 * N2 + p];
-        const T vR0 = fm[4 * N2 + p], vR1 = fm[5 * N2 + p], vR2 = fm[6 * N2 + p];
-        const T vo[3] = {own_is_L ? vL0 : vR0, own_is_L ? vL1 : vR1, own_is_L ? vL2 : vR2};
-        const T vn[3] = {own_is_L ? vR0 : vL0, own_is_L ? vR1 : vL1, own_is_L ? vR2 : vL2};
+        const T wdA = fmv[f][0];
+        const T vo[3] = {own_is_L ? fmv[f][1] : fmv[f][4], own_is_L ? fmv[f][2] : fmv[f][5],
+                         own_is_L ? fmv[f][3] : fmv[f][6]};
+        const T vn[3] = {own_is_L ? fmv[f][4] : fmv[f][1], own_is_L ? fmv[f][5] : fmv[f][2],
+                         own_is_L ? fmv[f][6] : fmv[f][3]};
         T go[3];
         go[d] = sF[11 * N2 + p];
         go[t1] = sF[9 * N2 + p];
         go[t2] = sF[10 * N2 + p];
-        const T uo = sF[8 * N2 + p];
+        const T uo_f = sF[8 * N2 + p];
         const T ano = go[0] * vo[0] + go[1] * vo[1] + go[2] * vo[2];
         T fv, fgc;
         if (nb >= 0) {
@@ -288,13 +330,13 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
           gnb[t2] = sF[14 * N2 + p];
           const T un = sF[12 * N2 + p];
           const T ann = gnb[0] * vn[0] + gnb[1] * vn[1] + gnb[2] * vn[2];
-          const T jump = own_is_L ? uo - un : un - uo;
+          const T jump = own_is_L ? uo_f - un : un - uo_f;
           const T avg = T(0.5) * (ano + ann);
           fv = own_is_L ? (-avg + tau * jump * wdA) : (avg - tau * jump * wdA);
           fgc = T(-0.5) * jump;
         } else {
-          fv = -ano + T(2) * tau * uo * wdA;
-          fgc = -uo;
+          fv = -ano + T(2) * tau * uo_f * wdA;
+          fgc = -uo_f;
         }
         sF[16 * N2 + p] = g.nu * fv;
         sF[17 * N2 + p] = g.nu * fgc * vo[d];
@@ -314,7 +356,6 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
       wave_sync();
       // scatter: face part onto the own face plane, normal part along the normal lines
       {
-        const int p1 = t % N, p2 = t / N;
         const T cn_ = sF[5 * N2 + t];
         sO[fnode<N>(d, eo, p1, p2)] += sF[4 * N2 + t];
 #pragma unroll
