@@ -166,10 +166,11 @@ __device__ __forceinline__ void face_interp(const double* __restrict__ S, const 
 
 // Transposed tangential interpolation of `np` planes R ([q2][q1]) and
 // accumulation into sO at the face nodes: sO[comp][node(p1,p2)] += sum.
-// Plane pl belongs to face fsel[pl] (d, s) and component comp[pl].
+// Plane pl is component pl % 3 of face (d, s), s = pl / 3 when s_all < 0,
+// else s = s_all.
 template <int N, int Q>
 __device__ __forceinline__ void face_lift(const double* __restrict__ S, const double* R, double* L1, double* sO,
-                                          int np, int d, const int* s_of, const int* comp_of, int tid, int nthr) {
+                                          int np, int d, int s_all, int tid, int nthr) {
   constexpr int N3 = N * N * N;
   for (int job = tid; job < np * Q; job += nthr) {     // along t2: [q2][q1] -> [p2][q1]
     const int q1 = job % Q, pl = job / Q;
@@ -190,13 +191,14 @@ __device__ __forceinline__ void face_lift(const double* __restrict__ S, const do
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = L1[(pl * N + p2) * Q + q];
-    double* o = sO + comp_of[pl] * N3;
+    double* o = sO + (pl % 3) * N3;
+    const int side = s_all < 0 ? pl / 3 : s_all;
 #pragma unroll
     for (int p1 = 0; p1 < N; ++p1) {
       double s = 0;
 #pragma unroll
       for (int q = 0; q < Q; ++q) s = fma(S[q * N + p1], v[q], s);
-      o[face_node<N>(d, s_of[pl], p1, p2)] += s;
+      o[face_node<N>(d, side, p1, p2)] += s;
     }
   }
   __syncthreads();
@@ -262,7 +264,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
   const double vol = cg.h[0] * cg.h[1] * cg.h[2];
   double* A = sX;                 // 3 * N*Q*Q  ([m][l][qy][qx])
   double* B = sX + 3 * N * Q2;    // 2 * N*N*Q  ([m][l][j][qx])
-#pragma unroll 1
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (own) {
       double acc[3][N];
@@ -330,7 +332,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
     __syncthreads();
   }
   // faces, one direction at a time (the two faces of a direction touch disjoint node planes)
-#pragma unroll 1
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const double area = cg.h[t1] * cg.h[t2];
@@ -365,9 +367,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
       for (int a = 0; a < 3; ++a) R[(s * 3 + a) * Q2 + pq] = wt * (0.5 * (um[a] * an + up[a] * bn) + lam * (um[a] - up[a]));
     }
     __syncthreads();
-    const int s_of[6] = {0, 0, 0, 1, 1, 1};
-    const int comp_of[6] = {0, 1, 2, 0, 1, 2};
-    face_lift<N, Q>(S, R, F1, sO, 6, d, s_of, comp_of, tid, nthr);
+    face_lift<N, Q>(S, R, F1, sO, 6, d, -1, tid, nthr);
   }
   for (int e = tid; e < 3 * N3; e += nthr) {
     const int a = e / N3, r = e % N3;
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     for (int q = 0; q < Q; ++q) t[a][q] = 0.0;
   double* T1 = sX;                  // [Sx w | Dx w] : 2 * N*N*Q, layout [m][l][j][qx]
   double* T2 = sX + 2 * N2 * Q;     // [SySx | DySx | SyDx] : 3 * N*Q*Q, layout [m][l][qy][qx]
-#pragma unroll 1
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double* wa = sW + a * N3;
     for (int job = tid; job < N2; job += nthr) {        // x: (l, j)
@@ -541,7 +541,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   }
   __syncthreads();
   // faces, one at a time: 12 planes = [u own, u ext, w own, w ext] x 3 components
-#pragma unroll 1
+#pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int d = f >> 1, s = f & 1;
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
@@ -616,9 +616,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
       for (int a = 0; a < 3; ++a) R[a * Q2 + pq] = wt * res[a];
     }
     __syncthreads();
-    const int s_of[3] = {s, s, s};
-    const int comp_of[3] = {0, 1, 2};
-    face_lift<N, Q>(S, R, F1, sO, 3, d, s_of, comp_of, tid, nthr);
+    face_lift<N, Q>(S, R, F1, sO, 3, d, s, tid, nthr);
   }
   for (int e = tid; e < 3 * N3; e += nthr) {
     const int a = e / N3, r = e % N3;
