@@ -90,7 +90,7 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
     double v[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = in[i];
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < Q; ++q) {
       double s = 0;
 #pragma unroll
@@ -104,7 +104,7 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
     double v[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) v[j] = T1[(al * N + j) * Q + qxx];
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < Q; ++q) {
       double s = 0;
 #pragma unroll
@@ -113,18 +113,22 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
     }
   }
   __syncthreads();
-  if (own) {                                            // z: registers
+  if (own) {                                            // z: registers, one table column per step
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double v[N];
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int l = 0; l < N; ++l) v[l] = T2[((a * N + l) * Q + qy) * Q + qx];
+      for (int q = 0; q < Q; ++q) out[a][q] = 0.0;
+#pragma unroll 1
+    for (int l = 0; l < N; ++l) {
+      const double x0 = T2[((0 * N + l) * Q + qy) * Q + qx];
+      const double x1 = T2[((1 * N + l) * Q + qy) * Q + qx];
+      const double x2 = T2[((2 * N + l) * Q + qy) * Q + qx];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        double s = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) s = fma(S[q * N + l], v[l], s);
-        out[a][q] = s;
+        const double c = S[q * N + l];
+        out[0][q] = fma(c, x0, out[0][q]);
+        out[1][q] = fma(c, x1, out[1][q]);
+        out[2][q] = fma(c, x2, out[2][q]);
       }
     }
   }
@@ -139,7 +143,7 @@ __device__ __forceinline__ void face_interp(const double* __restrict__ S, const 
     double v[N];
 #pragma unroll
     for (int p = 0; p < N; ++p) v[p] = P[job * N + p];
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < Q; ++q) {
       double s = 0;
 #pragma unroll
@@ -153,7 +157,7 @@ __device__ __forceinline__ void face_interp(const double* __restrict__ S, const 
     double v[N];
 #pragma unroll
     for (int p = 0; p < N; ++p) v[p] = F1[(pl * N + p) * Q + q1];
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < Q; ++q) {
       double s = 0;
 #pragma unroll
@@ -177,7 +181,7 @@ __device__ __forceinline__ void face_lift(const double* __restrict__ S, const do
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = R[(pl * Q + q) * Q + q1];
-#pragma unroll
+#pragma unroll 1
     for (int p = 0; p < N; ++p) {
       double s = 0;
 #pragma unroll
@@ -193,7 +197,7 @@ __device__ __forceinline__ void face_lift(const double* __restrict__ S, const do
     for (int q = 0; q < Q; ++q) v[q] = L1[(pl * N + p2) * Q + q];
     double* o = sO + (pl % 3) * N3;
     const int side = s_all < 0 ? pl / 3 : s_all;
-#pragma unroll
+#pragma unroll 1
     for (int p1 = 0; p1 < N; ++p1) {
       double s = 0;
 #pragma unroll
@@ -267,29 +271,29 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (own) {
-      double acc[3][N];
-#pragma unroll
-      for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int l = 0; l < N; ++l) acc[m][l] = 0.0;
       const double wxy = w[qx] * w[qy] * vol;
+      double fx[Q], fy[Q], fz[Q];
 #pragma unroll
       for (int qz = 0; qz < Q; ++qz) {
         const double f = wxy * w[qz] * u[a][qz];
-        const double fx = f * u[0][qz] * cg.hinv[0];
-        const double fy = f * u[1][qz] * cg.hinv[1];
-        const double fz = f * u[2][qz] * cg.hinv[2];
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-          acc[0][l] = fma(S[qz * N + l], fx, acc[0][l]);
-          acc[1][l] = fma(S[qz * N + l], fy, acc[1][l]);
-          acc[2][l] = fma(D[qz * N + l], fz, acc[2][l]);
-        }
+        fx[qz] = f * u[0][qz] * cg.hinv[0];
+        fy[qz] = f * u[1][qz] * cg.hinv[1];
+        fz[qz] = f * u[2][qz] * cg.hinv[2];
       }
+      // one node l per step: the S and D columns of l only
+#pragma unroll 1
+      for (int l = 0; l < N; ++l) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
-      for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int l = 0; l < N; ++l) A[((m * N + l) * Q + qy) * Q + qx] = acc[m][l];
+        for (int qz = 0; qz < Q; ++qz) {
+          a0 = fma(S[qz * N + l], fx[qz], a0);
+          a1 = fma(S[qz * N + l], fy[qz], a1);
+          a2 = fma(D[qz * N + l], fz[qz], a2);
+        }
+        A[((0 * N + l) * Q + qy) * Q + qx] = a0;
+        A[((1 * N + l) * Q + qy) * Q + qx] = a1;
+        A[((2 * N + l) * Q + qy) * Q + qx] = a2;
+      }
     }
     __syncthreads();
     for (int job = tid; job < N * Q; job += nthr) {     // y: (l, qx)
@@ -301,7 +305,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
         v2[q] = A[((1 * N + l) * Q + q) * Q + qxx];
         v3[q] = A[((2 * N + l) * Q + q) * Q + qxx];
       }
-#pragma unroll
+#pragma unroll 1
       for (int j = 0; j < N; ++j) {
         double b1 = 0, b23 = 0;
 #pragma unroll
@@ -321,7 +325,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
         v1[q] = B[job * Q + q];
         v2[q] = B[N2 * Q + job * Q + q];
       }
-#pragma unroll
+#pragma unroll 1
       for (int i = 0; i < N; ++i) {
         double s = 0;
 #pragma unroll
@@ -426,7 +430,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
       double v[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) v[i] = wa[job * N + i];
-#pragma unroll
+#pragma unroll 1
       for (int q = 0; q < Q; ++q) {
         double s0 = 0, s1 = 0;
 #pragma unroll
@@ -447,7 +451,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
         v0[j] = T1[(l * N + j) * Q + qxx];
         v1[j] = T1[N2 * Q + (l * N + j) * Q + qxx];
       }
-#pragma unroll
+#pragma unroll 1
       for (int q = 0; q < Q; ++q) {
         double ss = 0, ds = 0, sd = 0;
 #pragma unroll
@@ -463,22 +467,25 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     }
     __syncthreads();
     if (own) {                                          // z: gradient of w_a on this column
-      double v0[N], v1[N], v2[N];
+      double gzq[Q], gyq[Q], gxq[Q];
 #pragma unroll
+      for (int q = 0; q < Q; ++q) gzq[q] = gyq[q] = gxq[q] = 0.0;
+      // one node l per step: the S and D columns of l only
+#pragma unroll 1
       for (int l = 0; l < N; ++l) {
-        v0[l] = T2[((0 * N + l) * Q + qy) * Q + qx];
-        v1[l] = T2[((1 * N + l) * Q + qy) * Q + qx];
-        v2[l] = T2[((2 * N + l) * Q + qy) * Q + qx];
+        const double v0 = T2[((0 * N + l) * Q + qy) * Q + qx];
+        const double v1 = T2[((1 * N + l) * Q + qy) * Q + qx];
+        const double v2 = T2[((2 * N + l) * Q + qy) * Q + qx];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          gzq[q] = fma(D[q * N + l], v0, gzq[q]);
+          gyq[q] = fma(S[q * N + l], v1, gyq[q]);
+          gxq[q] = fma(S[q * N + l], v2, gxq[q]);
+        }
       }
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        double gz = 0, gy = 0, gx = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-          gz = fma(D[q * N + l], v0[l], gz);
-          gy = fma(S[q * N + l], v1[l], gy);
-          gx = fma(S[q * N + l], v2[l], gx);
-        }
+        double gz = gzq[q], gy = gyq[q], gx = gxq[q];
         gx *= cg.hinv[0];
         gy *= cg.hinv[1];
         gz *= cg.hinv[2];
@@ -498,18 +505,23 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   if (own) {
     const double wxy = w[qx] * w[qy] * vol;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double acc[N];
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int l = 0; l < N; ++l) acc[l] = 0.0;
+      for (int q = 0; q < Q; ++q) t[c][q] *= wxy * w[q];
+    // one node l per step: the S column of l only
+#pragma unroll 1
+    for (int l = 0; l < N; ++l) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const double f = wxy * w[q] * t[c][q];
-#pragma unroll
-        for (int l = 0; l < N; ++l) acc[l] = fma(S[q * N + l], f, acc[l]);
+        const double c = S[q * N + l];
+        a0 = fma(c, t[0][q], a0);
+        a1 = fma(c, t[1][q], a1);
+        a2 = fma(c, t[2][q], a2);
       }
-#pragma unroll
-      for (int l = 0; l < N; ++l) Z[((c * N + l) * Q + qy) * Q + qx] = acc[l];
+      Z[((0 * N + l) * Q + qy) * Q + qx] = a0;
+      Z[((1 * N + l) * Q + qy) * Q + qx] = a1;
+      Z[((2 * N + l) * Q + qy) * Q + qx] = a2;
     }
   }
   __syncthreads();
@@ -518,7 +530,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = Z[(cl * Q + q) * Q + qxx];
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < N; ++j) {
       double s = 0;
 #pragma unroll
@@ -531,7 +543,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = Y[job * Q + q];
-#pragma unroll
+#pragma unroll 1
     for (int i = 0; i < N; ++i) {
       double s = 0;
 #pragma unroll
