@@ -41,6 +41,13 @@ struct CShape {
   static constexpr int THREADS = ((Q2 + 63) / 64) * 64;
 };
 
+// Unroll factor of the sweep loops that step over table rows / columns: small
+// tables fit the scalar registers whole and are unrolled completely; large
+// ones (n * n_q > 48) step one row or column at a time, which keeps the
+// compiler from spilling table entries.
+template <int N, int Q>
+constexpr int kSweepUnroll = N * Q > 48 ? 1 : 16;
+
 struct CellGeo {
   int c[3];
   double h[3], hinv[3];
@@ -90,7 +97,7 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
     double v[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = in[i];
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int q = 0; q < Q; ++q) {
       double s = 0;
 #pragma unroll
@@ -104,7 +111,7 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
     double v[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) v[j] = T1[(al * N + j) * Q + qxx];
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int q = 0; q < Q; ++q) {
       double s = 0;
 #pragma unroll
@@ -118,7 +125,7 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int q = 0; q < Q; ++q) out[a][q] = 0.0;
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int l = 0; l < N; ++l) {
       const double x0 = T2[((0 * N + l) * Q + qy) * Q + qx];
       const double x1 = T2[((1 * N + l) * Q + qy) * Q + qx];
@@ -143,7 +150,7 @@ __device__ __forceinline__ void face_interp(const double* __restrict__ S, const 
     double v[N];
 #pragma unroll
     for (int p = 0; p < N; ++p) v[p] = P[job * N + p];
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int q = 0; q < Q; ++q) {
       double s = 0;
 #pragma unroll
@@ -157,7 +164,7 @@ __device__ __forceinline__ void face_interp(const double* __restrict__ S, const 
     double v[N];
 #pragma unroll
     for (int p = 0; p < N; ++p) v[p] = F1[(pl * N + p) * Q + q1];
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int q = 0; q < Q; ++q) {
       double s = 0;
 #pragma unroll
@@ -181,7 +188,7 @@ __device__ __forceinline__ void face_lift(const double* __restrict__ S, const do
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = R[(pl * Q + q) * Q + q1];
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int p = 0; p < N; ++p) {
       double s = 0;
 #pragma unroll
@@ -197,7 +204,7 @@ __device__ __forceinline__ void face_lift(const double* __restrict__ S, const do
     for (int q = 0; q < Q; ++q) v[q] = L1[(pl * N + p2) * Q + q];
     double* o = sO + (pl % 3) * N3;
     const int side = s_all < 0 ? pl / 3 : s_all;
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int p1 = 0; p1 < N; ++p1) {
       double s = 0;
 #pragma unroll
@@ -281,7 +288,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
         fz[qz] = f * u[2][qz] * cg.hinv[2];
       }
       // one node l per step: the S and D columns of l only
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
       for (int l = 0; l < N; ++l) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
@@ -305,7 +312,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
         v2[q] = A[((1 * N + l) * Q + q) * Q + qxx];
         v3[q] = A[((2 * N + l) * Q + q) * Q + qxx];
       }
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
       for (int j = 0; j < N; ++j) {
         double b1 = 0, b23 = 0;
 #pragma unroll
@@ -325,7 +332,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
         v1[q] = B[job * Q + q];
         v2[q] = B[N2 * Q + job * Q + q];
       }
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
       for (int i = 0; i < N; ++i) {
         double s = 0;
 #pragma unroll
@@ -430,7 +437,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
       double v[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) v[i] = wa[job * N + i];
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
       for (int q = 0; q < Q; ++q) {
         double s0 = 0, s1 = 0;
 #pragma unroll
@@ -451,7 +458,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
         v0[j] = T1[(l * N + j) * Q + qxx];
         v1[j] = T1[N2 * Q + (l * N + j) * Q + qxx];
       }
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
       for (int q = 0; q < Q; ++q) {
         double ss = 0, ds = 0, sd = 0;
 #pragma unroll
@@ -471,7 +478,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
 #pragma unroll
       for (int q = 0; q < Q; ++q) gzq[q] = gyq[q] = gxq[q] = 0.0;
       // one node l per step: the S and D columns of l only
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
       for (int l = 0; l < N; ++l) {
         const double v0 = T2[((0 * N + l) * Q + qy) * Q + qx];
         const double v1 = T2[((1 * N + l) * Q + qy) * Q + qx];
@@ -509,7 +516,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
 #pragma unroll
       for (int q = 0; q < Q; ++q) t[c][q] *= wxy * w[q];
     // one node l per step: the S column of l only
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int l = 0; l < N; ++l) {
       double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
@@ -530,7 +537,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = Z[(cl * Q + q) * Q + qxx];
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int j = 0; j < N; ++j) {
       double s = 0;
 #pragma unroll
@@ -543,7 +550,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = Y[job * Q + q];
-#pragma unroll 1
+#pragma unroll kSweepUnroll<N, Q>
     for (int i = 0; i < N; ++i) {
       double s = 0;
 #pragma unroll
