@@ -738,7 +738,9 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
 template <int N>
 ZmPlan zm_plan_n(int nx, int ny, int nz) {
   constexpr int TX = Zm<N>::TX, TY = Zm<N>::TY;
-  constexpr int kTargetBlocks = 1024;   // about four workgroups per compute unit
+  // about four workgroups per compute unit (two at k = 4, whose workgroups hold
+  // two waves per SIMD: longer segments pay fewer prologue layers)
+  constexpr int kTargetBlocks = N == 5 ? 512 : 1024;
   constexpr int kMinLayers = 4;         // shortest z segment
   ZmPlan p{};
   p.tx = (nx + TX - 1) / TX;
