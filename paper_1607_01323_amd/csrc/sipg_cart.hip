@@ -282,6 +282,7 @@ struct Zm {
   static constexpr int THREADS = ((NC + CPW - 1) / CPW) * 64;
 };
 
+
 // Orders this wavefront's LDS accesses (all lanes of a cell are in it).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -735,12 +736,12 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
   diag[gid] = dd[0] * md[1] * md[2] + md[0] * dd[1] * md[2] + md[0] * md[1] * dd[2];
 }
 
-template <int N>
+template <int N, typename T>
 ZmPlan zm_plan_n(int nx, int ny, int nz) {
   constexpr int TX = Zm<N>::TX, TY = Zm<N>::TY;
-  // about four workgroups per compute unit (two at k = 4, whose workgroups hold
-  // two waves per SIMD: longer segments pay fewer prologue layers)
-  constexpr int kTargetBlocks = N == 5 ? 512 : 1024;
+  // about four workgroups per compute unit; two for the fp64 kernel at k = 4,
+  // which runs two waves per SIMD: longer segments pay fewer prologue layers
+  constexpr int kTargetBlocks = (N == 5 && sizeof(T) == 8) ? 512 : 1024;
   constexpr int kMinLayers = 4;         // shortest z segment
   ZmPlan p{};
   p.tx = (nx + TX - 1) / TX;
@@ -758,13 +759,13 @@ ZmPlan zm_plan_n(int nx, int ny, int nz) {
 
 ZmPlan zm_plan(int n, int nx, int ny, int nz) {
   switch (n) {
-    case 2: return zm_plan_n<2>(nx, ny, nz);
-    case 3: return zm_plan_n<3>(nx, ny, nz);
-    case 4: return zm_plan_n<4>(nx, ny, nz);
-    case 5: return zm_plan_n<5>(nx, ny, nz);
-    case 6: return zm_plan_n<6>(nx, ny, nz);
-    case 7: return zm_plan_n<7>(nx, ny, nz);
-    default: return zm_plan_n<8>(nx, ny, nz);
+    case 2: return zm_plan_n<2, double>(nx, ny, nz);
+    case 3: return zm_plan_n<3, double>(nx, ny, nz);
+    case 4: return zm_plan_n<4, double>(nx, ny, nz);
+    case 5: return zm_plan_n<5, double>(nx, ny, nz);
+    case 6: return zm_plan_n<6, double>(nx, ny, nz);
+    case 7: return zm_plan_n<7, double>(nx, ny, nz);
+    default: return zm_plan_n<8, double>(nx, ny, nz);
   }
 }
 
@@ -772,7 +773,8 @@ template <int N, typename T>
 dgmf_status launch_apply_n(const CartGeom<T>& g, const T* src, T* dst, int64_t ncells, double* partials,
                            const int* stop, hipStream_t s) {
   (void)ncells;
-  const ZmPlan pl = zm_plan_n<N>(g.nx, g.ny, g.nz);
+  // with partial sums, the decomposition whose row count sipg_cart_blocks reports
+  const ZmPlan pl = partials ? zm_plan_n<N, double>(g.nx, g.ny, g.nz) : zm_plan_n<N, T>(g.nx, g.ny, g.nz);
   const int blocks = 8 * pl.per_xcd;
   if (g.utab)
     hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, true>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst, g,
