@@ -215,6 +215,16 @@ static dgmf_status setup_metric(dgmf_mesh m) {
     tab[3 * n * n + i] = t.g0[i];
     tab[3 * n * n + n + i] = t.g1[i];
     tab[3 * n * n + 2 * n + i] = t.wq[i];
+    // Lagrange basis through the Gauss points, at 0 and at 1
+    long double e0 = 1.0L, e1 = 1.0L;
+    for (int k = 0; k < n; ++k)
+      if (k != i) {
+        const long double den = static_cast<long double>(t.xq[i]) - t.xq[k];
+        e0 *= (0.0L - t.xq[k]) / den;
+        e1 *= (1.0L - t.xq[k]) / den;
+      }
+    tab[3 * n * n + 3 * n + i] = static_cast<double>(e0);
+    tab[3 * n * n + 4 * n + i] = static_cast<double>(e1);
   }
   std::vector<float> tab32(tab.begin(), tab.end());
   dgmf_status st = m->mtab64.upload(tab.data(), tab.size() * sizeof(double));

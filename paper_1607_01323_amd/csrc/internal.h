@@ -28,7 +28,7 @@ struct MetricGeom {
   const T* ltau;
   int lbase[3];    // first low-boundary face of direction d
   T mu, nu, pen;   // mass, diffusion, penalty scale s
-  const T* tab;    // S, D, Dg (n x n), l'(0), l'(1), w (n)
+  const T* tab;    // S, D, Dg (n x n), l'(0), l'(1), w, E0, E1 (n)
 };
 
 struct ConvGeom {
@@ -188,8 +188,9 @@ dgmf_status launch_metric_fill(int n, const MetricGeom<double>& g, const double*
                                double* ftau, double* lm, double* ltau, hipStream_t s);
 
 dgmf_status launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
-// Layout of the metric tables: S, D, Dg = D S^{-1} (n x n), l'(0), l'(1), Gauss weights w (n).
-constexpr int metric_tab_size(int n) { return 3 * n * n + 3 * n; }
+// Layout of the metric tables: S, D, Dg = D S^{-1} (n x n), l'(0), l'(1), Gauss
+// weights w, and the Lagrange basis on the Gauss points at 0 and at 1 (n each).
+constexpr int metric_tab_size(int n) { return 3 * n * n + 5 * n; }
 
 bool conv_supported(int n, int nq);
 dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, double* C, int64_t ncells,

@@ -34,7 +34,11 @@ struct MTab {
   __host__ __device__ int g0() const { return 3 * n * n; }
   __host__ __device__ int g1() const { return 3 * n * n + n; }
   __host__ __device__ int w() const { return 3 * n * n + 2 * n; }
-  __host__ __device__ int size() const { return 3 * n * n + 3 * n; }
+  // Lagrange basis on the Gauss points evaluated at 0 and 1: the value at a
+  // face of any polynomial of degree < n along the normal line
+  __host__ __device__ int e0() const { return 3 * n * n + 3 * n; }
+  __host__ __device__ int e1() const { return 3 * n * n + 4 * n; }
+  __host__ __device__ int size() const { return 3 * n * n + 5 * n; }
 };
 
 // ------------------------------------------------------------ LDS sweeps
@@ -54,9 +58,10 @@ struct MetShape {
   static constexpr int WAVES = 4;
   static constexpr int CPB = CPW * WAVES;          // cells per workgroup
   static constexpr int THREADS = 64 * WAVES;
-  // LDS words per cell: u, out and the cell-part scratch (5 n^3), whose place
-  // the 23 face planes take after the cell part
-  static constexpr int CELL = 7 * N3 > 2 * N3 + 23 * N2 ? 7 * N3 : 2 * N3 + 23 * N2;
+  // LDS words per cell: u at the points, its three reference gradients, the
+  // three gradient fluxes, the value flux (8 n^3), and the neighbour face
+  // planes (9 n^2)
+  static constexpr int CELL = 8 * N3 + 9 * N2;
 };
 
 // 3D array [z][y][x] of extent N^3: lane t (0..n^2-1) owns line t along `axis`:
@@ -150,17 +155,18 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
   const int ncells = g.nx * g.ny * g.nz;
   const int cell = blockIdx.x * M::CPB + w * M::CPW + cw;
   const bool act = cw < M::CPW && cell < ncells;
-  T* sU = s_cells + (w * M::CPW + (cw < M::CPW ? cw : 0)) * M::CELL;
-  T* sO = sU + N3;
-  T* sA = sU + 2 * N3;
-  T* sB = sU + 3 * N3;   // 3 N^3
-  T* sC = sU + 6 * N3;
-  T* sF = sA;            // face planes, after the cell part
+  T* sA = s_cells + (w * M::CPW + (cw < M::CPW ? cw : 0)) * M::CELL;   // u at the Gauss points
+  T* sB = sA + N3;           // 3 n^3: reference gradients at the points
+  T* sG = sA + 4 * N3;       // 3 n^3: gradient fluxes (nodal u on entry)
+  T* sC = sA + 7 * N3;       // value flux
+  T* sF = sA + 8 * N3;       // neighbour face planes: 0 P, 1 PN, 2..4 stages, 5 val, 6 dt1, 7 dt2, 8 dn
   const T* S = g.tab + MTab{N}.S();
   const T* D = g.tab + MTab{N}.D();
   const T* Dg = g.tab + MTab{N}.Dg();
   const T* g0 = g.tab + MTab{N}.g0();
   const T* g1 = g.tab + MTab{N}.g1();
+  const T* E0 = g.tab + MTab{N}.e0();
+  const T* E1 = g.tab + MTab{N}.e1();
   double pq = 0.0, sq = 0.0, sp = 0.0;
   if (act) {
     const int c[3] = {cell % g.nx, (cell / g.nx) % g.ny, cell / (g.nx * g.ny)};
@@ -168,15 +174,18 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
     const int stride[3] = {1, g.nx, g.nx * g.ny};
     const int p1 = t % N, p2 = t / N;
     // ---- every global load of this cell is issued up front, so that their
-    // latencies overlap the cell integral instead of stalling each face
-    // (in fp64 the cell and face metric are loaded where they are used:
-    // hoisting them too would cost the registers of a second wavefront per SIMD)
-    constexpr bool kHoistCm = sizeof(T) == 4;
+    // latencies overlap the cell integral (in fp64 the cell and face metric
+    // are loaded where they are used: hoisting them too would cost the
+    // registers of a second wavefront per SIMD)
+    constexpr bool kHoist = sizeof(T) == 4;
+    // neighbour face lines: up front unless that alone exhausts the fp64
+    // register file (n >= 7), where they are read per face
+    constexpr bool kHoistNb = sizeof(T) == 4 || N <= 6;
     const T* cm = g.cm + static_cast<int64_t>(cell) * 7 * N3;
     T uo[N], cmv[7][N];
 #pragma unroll
     for (int m = 0; m < N; ++m) uo[m] = src[cell * N3 + t + m * N2];
-    if constexpr (kHoistCm) {
+    if constexpr (kHoist) {
 #pragma unroll
       for (int k = 0; k < 7; ++k)
 #pragma unroll
@@ -210,11 +219,11 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
         ftau[f] = g.ltau[g.lbase[d] + pi];
         ownL[f] = true;
       }
-      if constexpr (kHoistCm) {
+      if constexpr (kHoist) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
       }
-      if (nbc[f] >= 0) {
+      if (kHoistNb && nbc[f] >= 0) {
         const T* un = src + static_cast<int64_t>(nbc[f]) * N3;
 #pragma unroll
         for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
@@ -223,24 +232,22 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
         for (int m = 0; m < N; ++m) nbv[f][m] = T(0);
       }
     }
+    // ---- values and reference gradients at the Gauss points
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      sU[t + m * N2] = uo[m];
-      sO[t + m * N2] = T(0);
-    }
+    for (int m = 0; m < N; ++m) sG[t + m * N2] = uo[m];
     wave_sync();
-    // ---- cell integral: values and reference gradients at the Gauss points
-    sweep3<N, 0, false, false>(S, sU, sC, t);
+    sweep3<N, 0, false, false>(S, sG, sC, t);
     wave_sync();
-    sweep3<N, 1, false, false>(S, sC, sB, t);
+    sweep3<N, 1, false, false>(S, sC, sG + N3, t);
     wave_sync();
-    sweep3<N, 2, false, false>(S, sB, sA, t);   // sA = u at the points
+    sweep3<N, 2, false, false>(S, sG + N3, sA, t);   // sA = u at the points
     wave_sync();
     sweep3<N, 0, false, false>(Dg, sA, sB, t);
     sweep3<N, 1, false, false>(Dg, sA, sB + N3, t);
     sweep3<N, 2, false, false>(Dg, sA, sB + 2 * N3, t);
     wave_sync();
-    if constexpr (!kHoistCm) {
+    // ---- cell integrand: nu (w detJ J^-1 J^-T) grad u and mu w detJ u at every point
+    if constexpr (!kHoist) {
 #pragma unroll
       for (int k = 0; k < 7; ++k)
 #pragma unroll
@@ -250,126 +257,119 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
     for (int m = 0; m < N; ++m) {
       const int q = t + m * N2;
       const T gx = sB[q], gy = sB[N3 + q], gz = sB[2 * N3 + q];
-      sB[q] = g.nu * (cmv[0][m] * gx + cmv[1][m] * gy + cmv[2][m] * gz);
-      sB[N3 + q] = g.nu * (cmv[1][m] * gx + cmv[3][m] * gy + cmv[4][m] * gz);
-      sB[2 * N3 + q] = g.nu * (cmv[2][m] * gx + cmv[4][m] * gy + cmv[5][m] * gz);
+      sG[q] = g.nu * (cmv[0][m] * gx + cmv[1][m] * gy + cmv[2][m] * gz);
+      sG[N3 + q] = g.nu * (cmv[1][m] * gx + cmv[3][m] * gy + cmv[4][m] * gz);
+      sG[2 * N3 + q] = g.nu * (cmv[2][m] * gx + cmv[4][m] * gy + cmv[5][m] * gz);
       sC[q] = g.mu * cmv[6][m] * sA[q];
     }
     wave_sync();
-    sweep3<N, 0, true, true>(Dg, sB, sC, t);
-    wave_sync();
-    sweep3<N, 1, true, true>(Dg, sB + N3, sC, t);
-    wave_sync();
-    sweep3<N, 2, true, true>(Dg, sB + 2 * N3, sC, t);
-    wave_sync();
-    sweep3<N, 2, true, false>(S, sC, sA, t);
-    wave_sync();
-    sweep3<N, 1, true, false>(S, sA, sC, t);
-    wave_sync();
-    sweep3<N, 0, true, true>(S, sC, sO, t);
-    wave_sync();
-
-    // ---- faces
-    // sF planes (n^2 each): 0 Pown, 1 PNown, 2 Pnb, 3 PNnb, 4..5 stage own, 6..7 stage nb,
-    //  8 val_own, 9 dt1_own, 10 dt2_own, 11 dn_own, 12 val_nb, 13 dt1_nb, 14 dt2_nb, 15 dn_nb,
-    //  16 fv, 17 fg_d, 18 fg_t1, 19 fg_t2, 20..22 lift stages
+    // ---- faces.  Lane t is face point (p1, p2).  Own traces are the values
+    // of the Gauss-point data extrapolated along the normal line (exact: every
+    // field is a polynomial of degree < n along it); the face terms go back
+    // through the transpose of that extrapolation into the point fluxes, so
+    // the transposed cell sweeps below lift them.  The neighbour's traces
+    // come from its nodal face plane and normal-derivative plane.
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1, s = f & 1;
       const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
       const int nb = nbc[f];
-      const T* gs = s ? g1 : g0;      // normal derivative row at the own face
-      const T* gn = s ? g0 : g1;      // ... at the neighbour's face
-      const int eo = s ? N - 1 : 0, en = s ? 0 : N - 1;
-      {
-        sF[0 * N2 + t] = sU[fnode<N>(d, eo, p1, p2)];
-        T dn = T(0);
+      const T* Es = s ? E1 : E0;
+      const T* gn = s ? g0 : g1;      // normal derivative row at the neighbour's face
+      const int en = s ? 0 : N - 1;
+      if (nb >= 0) {
+        if constexpr (!kHoistNb) {
+          const T* un = src + static_cast<int64_t>(nb) * N3;
 #pragma unroll
-        for (int m = 0; m < N; ++m) dn = fma(gs[m], sU[fnode<N>(d, m, p1, p2)], dn);
-        sF[1 * N2 + t] = dn;
-        if (nb >= 0) {
-          sF[2 * N2 + t] = nbv[f][en];
-          T dnn = T(0);
-#pragma unroll
-          for (int m = 0; m < N; ++m) dnn = fma(gn[m], nbv[f][m], dnn);
-          sF[3 * N2 + t] = dnn;
+          for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
         }
+        sF[0 * N2 + t] = nbv[f][en];
+        T dnn = T(0);
+#pragma unroll
+        for (int m = 0; m < N; ++m) dnn = fma(gn[m], nbv[f][m], dnn);
+        sF[1 * N2 + t] = dnn;
+        wave_sync();
+        // along t1 (p1): S P, D P, S PN; along t2 (p2): val, dt1, dt2, dn
+        plane_ops<N, 0, false, T>(3, codes(0, 0, 1), codes(2, 3, 4), 0b010u, 0u, S, D, sF, t);
+        wave_sync();
+        plane_ops<N, 1, false, T>(4, codes(2, 3, 2, 4), codes(5, 6, 7, 8), 0b0100u, 0u, S, D, sF, t);
+        wave_sync();
       }
-      wave_sync();
-      // along t1 (p1): S P, D P for both sides, S PN for both sides
-      plane_ops<N, 0, false, T>(6, codes(0, 0, 1, 2, 2, 3), codes(4, 5, 20, 6, 7, 21), 0b010010u, 0u, S, D, sF, t);
-      wave_sync();
-      // along t2 (p2): val = S(SP), dt1 = S(DP), dt2 = D(SP), dn = S(S PN)
-      plane_ops<N, 1, false, T>(8, codes(4, 5, 4, 20, 6, 7, 6, 21), codes(8, 9, 10, 11, 12, 13, 14, 15), 0b01000100u,
-                                0u, S, D, sF, t);
-      wave_sync();
-      if constexpr (!kHoistCm) {
+      if constexpr (!kHoist) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
       }
-      {
-        const bool own_is_L = ownL[f];
-        const T tau = ftau[f] * g.pen;
-        const int p = t;
-        const T wdA = fmv[f][0];
-        const T vo[3] = {own_is_L ? fmv[f][1] : fmv[f][4], own_is_L ? fmv[f][2] : fmv[f][5],
-                         own_is_L ? fmv[f][3] : fmv[f][6]};
-        const T vn[3] = {own_is_L ? fmv[f][4] : fmv[f][1], own_is_L ? fmv[f][5] : fmv[f][2],
-                         own_is_L ? fmv[f][6] : fmv[f][3]};
-        T go[3];
-        go[d] = sF[11 * N2 + p];
-        go[t1] = sF[9 * N2 + p];
-        go[t2] = sF[10 * N2 + p];
-        const T uo_f = sF[8 * N2 + p];
-        const T ano = go[0] * vo[0] + go[1] * vo[1] + go[2] * vo[2];
-        T fv, fgc;
-        if (nb >= 0) {
-          T gnb[3];
-          gnb[d] = sF[15 * N2 + p];
-          gnb[t1] = sF[13 * N2 + p];
-          gnb[t2] = sF[14 * N2 + p];
-          const T un = sF[12 * N2 + p];
-          const T ann = gnb[0] * vn[0] + gnb[1] * vn[1] + gnb[2] * vn[2];
-          const T jump = own_is_L ? uo_f - un : un - uo_f;
-          const T avg = T(0.5) * (ano + ann);
-          fv = own_is_L ? (-avg + tau * jump * wdA) : (avg - tau * jump * wdA);
-          fgc = T(-0.5) * jump;
-        } else {
-          fv = -ano + T(2) * tau * uo_f * wdA;
-          fgc = -uo_f;
-        }
-        sF[16 * N2 + p] = g.nu * fv;
-        sF[17 * N2 + p] = g.nu * fgc * vo[d];
-        sF[18 * N2 + p] = g.nu * fgc * vo[t1];
-        sF[19 * N2 + p] = g.nu * fgc * vo[t2];
-      }
-      wave_sync();
-      // transposed along t2: a = S^T fv (then += D^T fg_t2), b = S^T fg_t1, c = S^T fg_d
-      plane_ops<N, 1, true, T>(3, codes(16, 18, 17), codes(20, 21, 22), 0u, 0u, S, D, sF, t);
-      wave_sync();
-      plane_ops<N, 1, true, T>(1, codes(19), codes(20), 1u, 1u, S, D, sF, t);
-      wave_sync();
-      // along t1: face plane = S^T a (+ D^T b); normal plane = S^T c
-      plane_ops<N, 0, true, T>(2, codes(20, 22), codes(4, 5), 0u, 0u, S, D, sF, t);
-      wave_sync();
-      plane_ops<N, 0, true, T>(1, codes(21), codes(4), 1u, 1u, S, D, sF, t);
-      wave_sync();
-      // scatter: face part onto the own face plane, normal part along the normal lines
-      {
-        const T cn_ = sF[5 * N2 + t];
-        sO[fnode<N>(d, eo, p1, p2)] += sF[4 * N2 + t];
+      const bool own_is_L = ownL[f];
+      const T tau = ftau[f] * g.pen;
+      const T wdA = fmv[f][0];
+      T vo[3], vn[3];
 #pragma unroll
-        for (int m = 0; m < N; ++m) sO[fnode<N>(d, m, p1, p2)] += gs[m] * cn_;
+      for (int k = 0; k < 3; ++k) {
+        vo[k] = own_is_L ? fmv[f][1 + k] : fmv[f][4 + k];
+        vn[k] = own_is_L ? fmv[f][4 + k] : fmv[f][1 + k];
+      }
+      // own traces
+      T uo_f = T(0), go[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        const int q = fnode<N>(d, m, p1, p2);
+        uo_f = fma(Es[m], sA[q], uo_f);
+        go[0] = fma(Es[m], sB[q], go[0]);
+        go[1] = fma(Es[m], sB[N3 + q], go[1]);
+        go[2] = fma(Es[m], sB[2 * N3 + q], go[2]);
+      }
+      const T ano = go[0] * vo[0] + go[1] * vo[1] + go[2] * vo[2];
+      T fv, fgc;
+      if (nb >= 0) {
+        T gnb[3];
+        gnb[d] = sF[8 * N2 + t];
+        gnb[t1] = sF[6 * N2 + t];
+        gnb[t2] = sF[7 * N2 + t];
+        const T un = sF[5 * N2 + t];
+        const T ann = gnb[0] * vn[0] + gnb[1] * vn[1] + gnb[2] * vn[2];
+        const T jump = own_is_L ? uo_f - un : un - uo_f;
+        const T avg = T(0.5) * (ano + ann);
+        fv = own_is_L ? (-avg + tau * jump * wdA) : (avg - tau * jump * wdA);
+        fgc = T(-0.5) * jump;
+      } else {
+        fv = -ano + T(2) * tau * uo_f * wdA;
+        fgc = -uo_f;
+      }
+      fv *= g.nu;
+      fgc *= g.nu;
+      const T f0 = fgc * vo[0], f1 = fgc * vo[1], f2 = fgc * vo[2];
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        const int q = fnode<N>(d, m, p1, p2);
+        sC[q] = fma(Es[m], fv, sC[q]);
+        sG[q] = fma(Es[m], f0, sG[q]);
+        sG[N3 + q] = fma(Es[m], f1, sG[N3 + q]);
+        sG[2 * N3 + q] = fma(Es[m], f2, sG[2 * N3 + q]);
       }
       wave_sync();
     }
-    for (int e = t; e < N3; e += N2) {
-      const T v = sO[e];
+    // ---- transposed sweeps: sC += sum_d Dg_d^T sG_d, then S^T in every direction
+    sweep3<N, 0, true, true>(Dg, sG, sC, t);
+    wave_sync();
+    sweep3<N, 1, true, true>(Dg, sG + N3, sC, t);
+    wave_sync();
+    sweep3<N, 2, true, true>(Dg, sG + 2 * N3, sC, t);
+    wave_sync();
+    sweep3<N, 2, true, false>(S, sC, sA, t);
+    wave_sync();
+    sweep3<N, 1, true, false>(S, sA, sB, t);
+    wave_sync();
+    sweep3<N, 0, true, false>(S, sB, sC, t);
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const int e = t + m * N2;
+      const T v = sC[e];
       dst[cell * N3 + e] = v;
       if (partials) {
-        pq += static_cast<double>(sU[e]) * v;
+        pq += static_cast<double>(uo[m]) * v;
         sq += v;
-        sp += sU[e];
+        sp += uo[m];
       }
     }
   }
