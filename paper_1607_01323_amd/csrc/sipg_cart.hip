@@ -187,10 +187,12 @@ __device__ __forceinline__ void matvec_acc(cptr<T> A, const T (&x)[N], T (&y)[N]
 // interior low face, [u] = ul_N-1 - u_0, {{u'}} = (l'(1).ul/hl + l'(0).u/h)/2:
 //   -1/2 l'(0)_i/h [u] + delta_{i,0} ({{u'}} - tau [u]);
 // Dirichlet faces mirror these with [u] = u and the boundary penalty 2 tau.
+// The low neighbour enters only through its end value ul_{N-1} and
+// gl = l'(1).ul (unscaled); bline_t takes those, bline the line.
 template <int N, typename T>
-__device__ __forceinline__ void bline(cptr<T> tab, const T (&u)[N], const T (&ul)[N],
-                                      const T (&ur)[N], bool dirL, bool dirR, T hinv, T hlinv, T hrinv, T tauL,
-                                      T tauR, T s, T (&w)[N]) {
+__device__ __forceinline__ void bline_t(cptr<T> tab, const T (&u)[N], T ul_end, T gl,
+                                        const T (&ur)[N], bool dirL, bool dirR, T hinv, T hlinv, T hrinv, T tauL,
+                                        T tauR, T s, T (&w)[N]) {
   constexpr TabLayout L{N, N};
   cptr<T> g0 = tab + L.g0();
   cptr<T> g1 = tab + L.g1();
@@ -224,10 +226,7 @@ __device__ __forceinline__ void bline(cptr<T> tab, const T (&u)[N], const T (&ul
     cL = hinv * u[0];
     eL = fma(T(2) * tauL, u[0], gu0);
   } else {
-    T gl = g1[0] * ul[0];
-#pragma unroll
-    for (int m = 1; m < N; ++m) gl = fma(g1[m], ul[m], gl);
-    const T jump = ul[N - 1] - u[0];
+    const T jump = ul_end - u[0];
     const T avg = T(0.5) * fma(gl, hlinv, gu0);
     cL = T(-0.5) * hinv * jump;
     eL = fma(-tauL, jump, avg);
@@ -247,6 +246,22 @@ __device__ __forceinline__ void bline(cptr<T> tab, const T (&u)[N], const T (&ul
     for (int m = 0; m < N; ++m) acc = fma(Kt[i * N + m], us[m], acc);
     w[i] = acc;
   }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ T dot_row(cptr<T> r, const T (&v)[N]) {
+  T d = r[0] * v[0];
+#pragma unroll
+  for (int m = 1; m < N; ++m) d = fma(r[m], v[m], d);
+  return d;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void bline(cptr<T> tab, const T (&u)[N], const T (&ul)[N], const T (&ur)[N], bool dirL,
+                                      bool dirR, T hinv, T hlinv, T hrinv, T tauL, T tauR, T s, T (&w)[N]) {
+  constexpr TabLayout L{N, N};
+  const T gl = dirL ? T(0) : dot_row<N, T>(tab + L.g1(), ul);
+  bline_t<N, T>(tab, u, ul[N - 1], gl, ur, dirL, dirR, hinv, hlinv, hrinv, tauL, tauR, s, w);
 }
 
 // ------------------------------------------------------ z-marching apply ---
@@ -302,28 +317,33 @@ __device__ __forceinline__ void load_zline(const T* __restrict__ src, int cell, 
 // Line operator of direction d on a uniform, fully periodic mesh (tables
 // UTab, pre-scaled on the host): w += A_d u + ur_0 G1_d + bR E1 + ul_{n-1} G0_d
 // + bL E0 with bR = c_d (u_{n-1} - ur_0) + g0s_d.ur, bL = c_d (u_0 - ul_{n-1}) + g1s_d.ul.
+// (uline_t: the low neighbour given by ul_{n-1} and dl = g1s_d.ul)
 template <int N, typename T>
-__device__ __forceinline__ void uline(cptr<T> ut, int d, const T (&u)[N], const T (&ul)[N], const T (&ur)[N],
-                                      T (&w)[N]) {
+__device__ __forceinline__ void uline_t(cptr<T> ut, int d, const T (&u)[N], T ul_end, T dl, const T (&ur)[N],
+                                        T (&w)[N]) {
   constexpr UTab L{N};
-  const cptr<T> A = ut + L.A(d), G1 = ut + L.G1(d), G0 = ut + L.G0(d), g0s = ut + L.g0s(d), g1s = ut + L.g1s(d);
+  const cptr<T> A = ut + L.A(d), G1 = ut + L.G1(d), G0 = ut + L.G0(d), g0s = ut + L.g0s(d);
   const cptr<T> E1 = ut + L.E1(), E0 = ut + L.E0();
   const T c = ut[L.c(d)];
-  T dr = g0s[0] * ur[0], dl = g1s[0] * ul[0];
+  T dr = g0s[0] * ur[0];
 #pragma unroll
-  for (int m = 1; m < N; ++m) {
-    dr = fma(g0s[m], ur[m], dr);
-    dl = fma(g1s[m], ul[m], dl);
-  }
+  for (int m = 1; m < N; ++m) dr = fma(g0s[m], ur[m], dr);
   const T bR = fma(c, u[N - 1] - ur[0], dr);
-  const T bL = fma(c, u[0] - ul[N - 1], dl);
+  const T bL = fma(c, u[0] - ul_end, dl);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    T acc = fma(G1[i], ur[0], fma(E1[i], bR, fma(G0[i], ul[N - 1], fma(E0[i], bL, w[i]))));
+    T acc = fma(G1[i], ur[0], fma(E1[i], bR, fma(G0[i], ul_end, fma(E0[i], bL, w[i]))));
 #pragma unroll
     for (int m = 0; m < N; ++m) acc = fma(A[i * N + m], u[m], acc);
     w[i] = acc;
   }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void uline(cptr<T> ut, int d, const T (&u)[N], const T (&ul)[N], const T (&ur)[N],
+                                      T (&w)[N]) {
+  constexpr UTab L{N};
+  uline_t<N, T>(ut, d, u, ul[N - 1], dot_row<N, T>(ut + L.g1s(d), ul), ur, w);
 }
 
 // Work state of one workgroup of the z-marching apply.
@@ -347,7 +367,7 @@ template <int N, typename T, bool PER, bool UNI>
 __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restrict__ dst, const CartGeom<T>& g,
                                          ZmCtx<N, T>& c, int cz, int z1, T* s_u, T* s_w, T* s_rim_next,
                                          const int* s_rimcol, cptr<T> tab, cptr<T> gh, cptr<T> ghinv,
-                                         cptr<T> gtp, const T (&up)[N], const T (&uc)[N], const T (&un)[N],
+                                         cptr<T> gtp, T& up_end, T& up_dot, const T (&uc)[N], const T (&un)[N],
                                          T (&unn)[N], bool want_partials, double& pq, double& sq, double& sp) {
   using C = ZmCtx<N, T>;
   constexpr int N2 = C::N2, N3 = C::N3, P = C::P, NR = C::NR, RPT = C::RPT, TH = Zm<N>::THREADS;
@@ -389,14 +409,14 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
     if constexpr (UNI) {
 #pragma unroll
       for (int l = 0; l < N; ++l) w[l] = T(0);
-      uline<N, T>(ut, 2, uc, up, un, w);
+      uline_t<N, T>(ut, 2, uc, up_end, up_dot, un, w);
     } else {
       const T tzl = zl_dir ? tau_c : fmax(tau_c, g.pen * (c.tpx + c.tpy + zl_tp));
       const T tzr = zr_dir ? tau_c : fmax(tau_c, g.pen * (c.tpx + c.tpy + zr_tp));
       const T mv = g.mu * vol;
 #pragma unroll
       for (int l = 0; l < N; ++l) w[l] = mv * uc[l];
-      bline<N, T>(tab, uc, up, un, zl_dir, zr_dir, hinvz, zl_hinv, zr_hinv, tzl, tzr, vnu * hinvz, w);
+      bline_t<N, T>(tab, uc, up_end, up_dot, un, zl_dir, zr_dir, hinvz, zl_hinv, zr_hinv, tzl, tzr, vnu * hinvz, w);
     }
 #pragma unroll
     for (int l = 0; l < N; ++l) {
@@ -404,6 +424,10 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
       sw[(l * N + t1) * P + t0] = w[l];
     }
   }
+  // this layer's high-face trace is the next layer's low-neighbour trace
+  up_end = uc[N - 1];
+  if constexpr (UNI) up_dot = dot_row<N, T>(ut + UTab{N}.g1s(2), uc);
+  else up_dot = dot_row<N, T>(tab + TabLayout{N, N}.g1(), uc);
   __syncthreads();
   // pass 2: y-lines (i, l) = (t0, t1): w += B_y u
   if (c.act) {
@@ -621,15 +645,23 @@ __global__ void __launch_bounds__(Zm<N>::THREADS) k_sipg_zm_apply(const T* __res
         c.yr_nb = (n >= y0 && n < y0 + wy) ? (lc + (n - cy) * TX) * CL : (NC + TX + a) * CL;
       }
     }
-    // z-line window: slots hold layers z0-1, z0, z0+1 (slot 2 receives z0+2)
-    T z[4][N];
+    // z-line window: slots hold layers z0 and z0+1 (slot 2 receives z0+2);
+    // the layer below enters only through its high-face trace (end value and
+    // end derivative)
+    T z[3][N];
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 3; ++s)
 #pragma unroll
       for (int l = 0; l < N; ++l) z[s][l] = T(0);
+    T up_end = T(0), up_dot = T(0);
     if (c.act) {
       const int zl = z0 - 1, zr = z0 + 1;
-      if (zl >= 0 || c.zper) load_zline<N, T>(src, (zl < 0 ? g.nz - 1 : zl) * c.nxy + c.col, c.zoff, z[3]);
+      if (zl >= 0 || c.zper) {
+        load_zline<N, T>(src, (zl < 0 ? g.nz - 1 : zl) * c.nxy + c.col, c.zoff, z[2]);
+        up_end = z[2][N - 1];
+        if constexpr (UNI) up_dot = dot_row<N, T>((cptr<T>)(g.utab) + UTab{N}.g1s(2), z[2]);
+        else up_dot = dot_row<N, T>(tab + TabLayout{N, N}.g1(), z[2]);
+      }
       load_zline<N, T>(src, z0 * c.nxy + c.col, c.zoff, z[0]);
       if (zr < g.nz || c.zper) load_zline<N, T>(src, (zr >= g.nz ? 0 : zr) * c.nxy + c.col, c.zoff, z[1]);
     }
@@ -646,21 +678,17 @@ __global__ void __launch_bounds__(Zm<N>::THREADS) k_sipg_zm_apply(const T* __res
     }
     // s_rim is read after the first barrier inside zm_layer
     const bool wp = partials != nullptr;
+    T* const su = s_u[0];
 #pragma unroll 1
-    for (int cz = z0; cz < z1; cz += 4) {
-      T* const u0 = s_u[0];
-      T* const u1 = s_u[0];
-      zm_layer<N, T, PER, UNI>(src, dst, g, c, cz, z1, u0, s_w, u1 + NC * CL, s_rimcol, tab, gh, ghinv, gtp, z[3], z[0],
-                          z[1], z[2], wp, pq, sq, sp);
+    for (int cz = z0; cz < z1; cz += 3) {
+      zm_layer<N, T, PER, UNI>(src, dst, g, c, cz, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv, gtp, up_end,
+                               up_dot, z[0], z[1], z[2], wp, pq, sq, sp);
       if (cz + 1 < z1)
-        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 1, z1, u1, s_w, u0 + NC * CL, s_rimcol, tab, gh, ghinv, gtp, z[0],
-                            z[1], z[2], z[3], wp, pq, sq, sp);
+        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 1, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv, gtp,
+                                 up_end, up_dot, z[1], z[2], z[0], wp, pq, sq, sp);
       if (cz + 2 < z1)
-        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 2, z1, u0, s_w, u1 + NC * CL, s_rimcol, tab, gh, ghinv, gtp, z[1],
-                            z[2], z[3], z[0], wp, pq, sq, sp);
-      if (cz + 3 < z1)
-        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 3, z1, u1, s_w, u0 + NC * CL, s_rimcol, tab, gh, ghinv, gtp, z[2],
-                            z[3], z[0], z[1], wp, pq, sq, sp);
+        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 2, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv, gtp,
+                                 up_end, up_dot, z[2], z[0], z[1], wp, pq, sq, sp);
     }
   }
   if (partials) {
