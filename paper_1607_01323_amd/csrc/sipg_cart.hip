@@ -767,9 +767,9 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
 template <int N, typename T>
 ZmPlan zm_plan_n(int nx, int ny, int nz) {
   constexpr int TX = Zm<N>::TX, TY = Zm<N>::TY;
-  // about four workgroups per compute unit; two for the fp64 kernel at k = 4,
-  // which runs two waves per SIMD: longer segments pay fewer prologue layers
-  constexpr int kTargetBlocks = (N == 5 && sizeof(T) == 8) ? 512 : 1024;
+  // one round of resident workgroups: four per compute unit, three for the
+  // fp64 kernel at k = 4 (three waves per SIMD)
+  constexpr int kTargetBlocks = (N == 5 && sizeof(T) == 8) ? 768 : 1024;
   constexpr int kMinLayers = 4;         // shortest z segment
   ZmPlan p{};
   p.tx = (nx + TX - 1) / TX;
