@@ -30,6 +30,10 @@ CASES = {
     "one_cell_periodic": (3, (1, 2, 1), (1, 1, 1), 0, (1, 1, 1), 0, 1.0, 1.0, 1.0),
     "one_cell_dirichlet": (2, (1, 1, 1), (1, 1, 1), 0, (0, 0, 0), 0, 0.0, 1.0, 1.0),
     "k4_channel_tanh": (4, (3, 5, 2), (2 * math.pi, 2, math.pi), -1, (1, 0, 1), 1.8, 1000.0, 0.01, 1.0),
+    # ragged x-y tiles and several z segments of the z-marching kernel
+    "k3_uniform_long_z": (3, (7, 5, 37), (1, 1, 1), 0, (1, 1, 1), 0, 0.0, 1.0, 1 / 3),
+    "k4_uniform_aniso_ragged": (4, (9, 3, 21), (1.3, 0.4, 2.0), 0, (1, 1, 1), 0, 1000.0, 0.01, 1.0),
+    "k3_dirichlet_long_z": (3, (6, 5, 30), (1, 1, 1), 0, (0, 0, 0), 0, 1.0, 1.0, 1.0),
 }
 
 
