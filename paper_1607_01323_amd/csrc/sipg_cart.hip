@@ -14,17 +14,11 @@
 // its end node, and the normal derivative is the end-point derivative row
 // l'(0) or l'(1) applied to the line.
 //
-// Kernel layout: one workgroup per batch of CPB = 128 / n^2 cells, n^2
-// threads per cell, each thread owning one line of its cell per pass.  The
-// cell tensor and intermediates live in LDS with a padded line pitch n+1;
-// neighbour lines are read straight from global memory (L2 / Infinity Cache
-// hits: each cell is read by its six neighbours).  Six passes:
-//   1 x-lines: a = A_x u                         (neighbour x-lines)
-//   2 y-lines: f = A_y u, c = My a              (neighbour y-lines)
-//   3 z-lines: g = A_z u                         (neighbour z-lines)
-//   4 x-lines: c += Mx f, g = Mx g
-//   5 y-lines: g = My g
-//   6 z-lines: dst = Mz c + g                    (coalesced store)
+// The apply kernel uses the factored form (with V = hx hy hz)
+//   H u = V (Mz x My x Mx) (mu u + sum_d (nu/h_d) Mhat^-1 A_d u)
+// in five line passes (z, y, x + Mx, My, Mz) of a z-marching tile kernel
+// (k_sipg_zm_apply, below); the diagonal kernel applies each A_d to unit
+// vectors.
 #include "internal.h"
 
 namespace dgmf {

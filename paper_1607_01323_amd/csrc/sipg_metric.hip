@@ -15,10 +15,12 @@
 //   - ({{grad v}}.n, [u]) - ([v], {{grad u}}.n) + tau ([v], [u])
 // Dirichlet faces: - (grad v.n, u) - (v, grad u.n) + 2 tau (v, u).
 //
-// Kernel layout: one cell per workgroup (128 threads); the cell tensor and
-// its quadrature-point fields live in LDS; the 12 cell sweeps and the face
-// sweeps are distributed over the threads line by line; faces are handled
-// cell-centrically, one at a time.
+// Kernel layout: the n^2 lanes of a cell sit in one wavefront (several cells
+// per wavefront when n^2 <= 32, four wavefronts per workgroup); the cell's
+// point fields live in LDS and the sweeps go line by line over its lanes.
+// Own face traces are extrapolated from the Gauss-point data along the normal
+// lines and the face terms are injected back into the point fluxes, so the
+// transposed cell sweeps lift cell and face terms together.
 #include "internal.h"
 
 namespace dgmf {
