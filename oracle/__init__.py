@@ -28,6 +28,8 @@ solvers     textbook PCG, Lanczos, Chebyshev (Sec. 5.1 "Solving linear systems")
 convective  divergence-form convective operator with local Lax-Friedrichs
             flux, its JVP/VJP and assembled Jacobian (Sec. 3.2 eq. convstepspat)
 rng         SplitMix64 counter-based generator (published definition)
+mass        block-diagonal inverse mass matrix and the explicit convective
+            substep of the matrix form (eq. advect)
 
 Every function that has no independent pin says so; see the test-suite
 docstrings for the pins (closed forms, invariants, brute force).
