@@ -8,8 +8,9 @@ device synchronisations.  The same JSON line carries the roofline of that
 kernel (algorithmic bytes 16 B/DoF over the event-timed launch duration, the
 counter traffic when a committed profile matches the current kernel source),
 the fp32 apply, the CG time to 1e-10 (Jacobi fp64; mixed fp32-Chebyshev vs
-fp64), the convective forward + VJP throughput, and the CPU oracle timed on
-a bounded sample.
+fp64), the convective forward + VJP throughput, the explicit convective
+substep U - dt M^{-1} C(U) (fused kernel vs the two-launch composition), the
+inverse mass apply, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -228,9 +229,40 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     n3 = 3 * m3.ndofs
     ex["c3_convective"] = {"fwd_us": tf * 1e6, "vjp_us": tv * 1e6, "fwd_dofs_per_s": n3 / tf, "vjp_dofs_per_s": n3 / tv,
                            "fwd_plus_vjp_dofs_per_s": n3 / (tf + tv), "dofs": n3}
+    ex.update(step_measurements(m3, op3, U, Cout, "c3"))
     m3.close()
     ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4, "c4"))
     ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4_SMALL, "c4small", cg=False))
+    return ex
+
+
+def step_measurements(mesh, opc, U, C, tag, dt=1e-3):
+    """Explicit convective substep U - dt M^{-1} C(U): fused kernel against the
+    two-launch composition, and the inverse mass apply alone on the three
+    velocity components (fp64, fp32), whose algorithmic traffic is one read and
+    one write of every value."""
+    import torch
+    ex = {}
+    n3 = U.numel()
+    out = torch.empty_like(U)
+    ts = _events_time(lambda: opc.step(U, dt, out), 10, 2)
+    Mi = torch.empty_like(U)
+
+    def unfused():
+        opc.apply(U, C)
+        mesh.inverse_mass(C, Mi)
+        torch.add(U, Mi, alpha=-dt, out=out)
+
+    tu = _events_time(unfused, 10, 2)
+    tm = _events_time(lambda: mesh.inverse_mass(C, Mi), 50, 5)
+    U32 = U.float()
+    M32 = torch.empty_like(U32)
+    tm32 = _events_time(lambda: mesh.inverse_mass(U32, M32), 50, 5)
+    ex[f"{tag}_step"] = {"fused_us": ts * 1e6, "unfused_us": tu * 1e6, "dofs_per_s": n3 / ts, "dofs": n3}
+    ex[f"{tag}_inverse_mass_f64"] = {"us": tm * 1e6, "alg_GBps": 16.0 * n3 / tm / 1e9,
+                                     "hbm_frac": 16.0 * n3 / tm / 1e9 / HBM_PEAK_GBS, "fields": 3}
+    ex[f"{tag}_inverse_mass_f32"] = {"us": tm32 * 1e6, "alg_GBps": 8.0 * n3 / tm32 / 1e9,
+                                     "hbm_frac": 8.0 * n3 / tm32 / 1e9 / HBM_PEAK_GBS, "fields": 3}
     return ex
 
 
@@ -296,6 +328,7 @@ def channel_measurements(dg, inp, torch, w, tag, cg=True):
     ex[f"{tag}_convective"] = {"fwd_us": tf * 1e6, "vjp_us": tv * 1e6, "fwd_dofs_per_s": 3 * N / tf,
                                "vjp_dofs_per_s": 3 * N / tv, "fwd_plus_vjp_dofs_per_s": 3 * N / (tf + tv),
                                "dofs": 3 * N, "n_q": w.conv_points or (3 * n) // 2}
+    ex.update(step_measurements(m, opc, U, Cout, tag))
     m.close()
     return ex
 

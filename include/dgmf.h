@@ -17,7 +17,9 @@
  *     and the zero-mean projection of singular problems (Sec. 5.1);
  *   - the divergence-form convective operator with the local Lax-Friedrichs
  *     flux, Lambda evaluated per face quadrature point (Sec. 3.2, eq.
- *     convstepspat; matrix form eq. advect), and its vector-Jacobian product.
+ *     convstepspat; matrix form eq. advect), its vector-Jacobian product,
+ *     and the explicit convective substep with the tensorial inverse of the
+ *     block-diagonal mass matrix (Sec. 4 matrix formulation, Sec. 5).
  *
  * Conventions shared by every entry point
  *   Reference cell [0,1]^3, n = k+1 nodes per direction.
@@ -101,6 +103,18 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out);
 dgmf_status dgmf_mesh_info(dgmf_mesh mesh, int64_t* n_cells, int64_t* n_dofs_per_field);
 /* Physical coordinates of every DoF: xyz is a device double array [3][N]. */
 dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t stream);
+/* dst = M^{-1} src for n_fields consecutive scalar fields ([n_fields][N],
+ * dtype DGMF_F64 or DGMF_F32), M the block-diagonal DG mass matrix of the
+ * nodal basis, (phi_i, phi_j)_K with k+1 Gauss points per direction (exact on
+ * these affine cells).  Applied per cell through the tensorial inverse of
+ * Sec. 5 (implementation): the inverted 1D node-to-Gauss-point transform and
+ * inverse weights, Mh^{-1} = S^{-1} W^{-1} S^{-T} along each direction, times
+ * 1/|det J|.  This is the M^{-1} of the explicit convective step (Sec. 4,
+ * matrix formulation, eq. advect) and of the inverse-mass preconditioners of
+ * Sec. 5.1.  n_fields in 1..64; src == dst (in place) is allowed, any other
+ * overlap is DGMF_INVALID.  Asynchronous. */
+dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
+                                    hipStream_t stream);
 /* Frees the mesh; operators created on it must be destroyed first (DGMF_INVALID otherwise). */
 dgmf_status dgmf_mesh_destroy(dgmf_mesh mesh);
 
@@ -194,6 +208,15 @@ typedef struct { int n_q; } dgmf_conv_desc;
 dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, dgmf_op* out);
 /* out = C(u); u, out: device fp64 [3][N], must not alias.  Asynchronous. */
 dgmf_status dgmf_convective_apply(dgmf_op op, const double* u, double* out, hipStream_t stream);
+/* out = u - dt M^{-1} C(u): one explicit convective substep of the matrix
+ * form (Sec. 4, matrix formulation, eq. advect, with gamma_0 = alpha_0 =
+ * beta_0 = 1 and no body force), M the block-diagonal mass matrix as in
+ * dgmf_inverse_mass_apply.  Fused: C(u) stays on chip.  Higher-order
+ * combinations sum_i alpha_i U^{n-i} - dt M^{-1} sum_i beta_i F^c(U^{n-i})
+ * follow from dgmf_convective_apply, dgmf_inverse_mass_apply and vector
+ * sums.  u, out: device fp64 [3][N], must not overlap; dt finite.
+ * Asynchronous. */
+dgmf_status dgmf_convective_step(dgmf_op op, double dt, const double* u, double* out, hipStream_t stream);
 /* grad = (dC/du)^T w; u, w, grad: device fp64 [3][N]; grad must not alias
  * u or w.  Tie rule of the max: the minus side is active when
  * |u-.n| >= |u+.n|; sgn(0) = 0.  Asynchronous. */

@@ -71,6 +71,7 @@ _mesh_create = _sig("dgmf_mesh_create", ctypes.POINTER(BoxDesc), ctypes.POINTER(
 _mesh_info = _sig("dgmf_mesh_info", _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64))
 _mesh_coords = _sig("dgmf_mesh_node_coords", _vp, _vp, _vp)
 _mesh_destroy = _sig("dgmf_mesh_destroy", _vp)
+_inv_mass = _sig("dgmf_inverse_mass_apply", _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp)
 _sipg_create = _sig("dgmf_sipg_create", _vp, ctypes.POINTER(SipgDesc), ctypes.POINTER(_vp))
 _apply = _sig("dgmf_operator_apply", _vp, ctypes.c_int, _vp, _vp, _vp)
 _diag = _sig("dgmf_operator_diagonal", _vp, ctypes.c_int, _vp, _vp)
@@ -82,6 +83,7 @@ _cg = _sig("dgmf_cg_solve", _vp, _vp, _vp, ctypes.POINTER(CgParams), _vp, ctypes
 _conv_create = _sig("dgmf_convective_create", _vp, ctypes.POINTER(ConvDesc), ctypes.POINTER(_vp))
 _conv_apply = _sig("dgmf_convective_apply", _vp, _vp, _vp, _vp)
 _conv_vjp = _sig("dgmf_convective_vjp", _vp, _vp, _vp, _vp, _vp)
+_conv_step = _sig("dgmf_convective_step", _vp, ctypes.c_double, _vp, _vp, _vp)
 _op_destroy = _sig("dgmf_op_destroy", _vp)
 
 
@@ -142,6 +144,20 @@ class Mesh:
         out = torch.empty(3 * self.ndofs, dtype=torch.float64, device="cuda")
         _check(_mesh_coords(self._h, _ptr(out, torch.float64, 3 * self.ndofs, "xyz"), _stream()), "node_coords")
         return out.view(3, self.ndofs)
+
+    def inverse_mass(self, src, out=None):
+        """M^{-1} src for one or more scalar fields laid out [n_fields][N] (fp64 or fp32); out may be src."""
+        if src.numel() % self.ndofs:
+            raise ValueError(f"src must hold a whole number of fields of {self.ndofs} values")
+        nf = src.numel() // self.ndofs
+        dt = {torch.float64: F64, torch.float32: F32}.get(src.dtype)
+        if dt is None:
+            raise TypeError(f"src must be float64 or float32, got {src.dtype}")
+        if out is None:
+            out = torch.empty_like(src)
+        _check(_inv_mass(self._h, dt, nf, _ptr(src, src.dtype, src.numel(), "src"),
+                         _ptr(out, src.dtype, src.numel(), "out"), _stream()), "inverse_mass_apply")
+        return out
 
     def close(self):
         for op in self._ops:
@@ -255,6 +271,15 @@ class ConvectiveOperator(_Op):
             out = torch.empty_like(u)
         _check(_conv_apply(self._h, _ptr(u, torch.float64, n, "u"), _ptr(out, torch.float64, n, "out"), _stream()),
                "convective_apply")
+        return out
+
+    def step(self, u, dt, out=None):
+        """u - dt M^{-1} C(u), one explicit convective substep."""
+        n = 3 * self.mesh.ndofs
+        if out is None:
+            out = torch.empty_like(u)
+        _check(_conv_step(self._h, float(dt), _ptr(u, torch.float64, n, "u"), _ptr(out, torch.float64, n, "out"),
+                          _stream()), "convective_step")
         return out
 
     def vjp(self, u, w, out=None):

@@ -191,6 +191,21 @@ static bool invert(int n, const double* a_in, std::vector<long double>& inv) {
   return true;
 }
 
+bool inverse_mass_1d(const Tables1D& t, std::vector<double>& out) {
+  const int n = t.n;
+  if (t.nq != n) return false;
+  std::vector<long double> sinv;
+  if (!invert(n, t.S.data(), sinv)) return false;
+  out.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      long double a = 0;
+      for (int q = 0; q < n; ++q) a += sinv[i * n + q] * sinv[j * n + q] / static_cast<long double>(t.wq[q]);
+      out[i * n + j] = static_cast<double>(a);
+    }
+  return true;
+}
+
 // Quadrature-point metric of a lattice mesh: tables S, D, Dg = D S^{-1},
 // l'(0), l'(1), w; cell and face geometry filled on the device in fp64, then
 // copied to fp32.
@@ -430,6 +445,13 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
   dgmf_status st = upload_geometry<double>(m, m->geo64, m->g64);
   if (st == DGMF_OK) st = upload_geometry<float>(m, m->geo32, m->g32);
   if (st == DGMF_OK) st = upload_tables<double>(m->tab, m->tab64);
+  if (st == DGMF_OK) {
+    std::vector<double> mi;
+    if (!inverse_mass_1d(m->tab, mi)) st = fail(DGMF_INVALID, "mesh_create: singular interpolation matrix");
+    std::vector<float> mi32(mi.begin(), mi.end());
+    if (st == DGMF_OK) st = m->minv64.upload(mi.data(), mi.size() * sizeof(double));
+    if (st == DGMF_OK) st = m->minv32.upload(mi32.data(), mi32.size() * sizeof(float));
+  }
   if (st == DGMF_OK && m->desc.store_qp_metric) {
     DeviceGuard dg(m->device);
     st = setup_metric(m);
@@ -463,6 +485,27 @@ dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t strea
   if (!aligned(xyz, 8)) return fail(DGMF_INVALID, "mesh_node_coords: misaligned output");
   DeviceGuard dg(mesh->device);
   return launch_node_coords(mesh->tab.n, mesh->g64, mesh->shear, xyz, mesh->ncells, stream);
+}
+
+dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
+                                    hipStream_t stream) {
+  if (!mesh || !src || !dst) return fail(DGMF_INVALID, "inverse_mass_apply: null argument");
+  const size_t es = dtype == DGMF_F64 ? 8 : (dtype == DGMF_F32 ? 4 : 0);
+  if (!es) return fail(DGMF_INVALID, "inverse_mass_apply: unknown dtype %d", static_cast<int>(dtype));
+  if (n_fields < 1 || n_fields > 64) return fail(DGMF_INVALID, "inverse_mass_apply: n_fields must be in 1..64");
+  if (!aligned(src, es) || !aligned(dst, es)) return fail(DGMF_INVALID, "inverse_mass_apply: misaligned vector");
+  if (src != dst && overlap(src, dst, es * mesh->ndofs * n_fields))
+    return fail(DGMF_INVALID, "inverse_mass_apply: src and dst overlap without being the same array");
+  DeviceGuard dg(mesh->device);
+  const double js = 1.0 / std::fabs(mesh->shear.det);
+  const int n = mesh->tab.n;
+  if (dtype == DGMF_F64)
+    return launch_inverse_mass<double>(n, mesh->g64, js, static_cast<const double*>(mesh->minv64.p),
+                                       static_cast<const double*>(src), static_cast<double*>(dst), mesh->ncells,
+                                       n_fields, stream);
+  return launch_inverse_mass<float>(n, mesh->g32, static_cast<float>(js), static_cast<const float*>(mesh->minv32.p),
+                                    static_cast<const float*>(src), static_cast<float*>(dst), mesh->ncells, n_fields,
+                                    stream);
 }
 
 dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op* out) {
@@ -671,6 +714,12 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
   h.insert(h.end(), op->tab.S.begin(), op->tab.S.end());
   h.insert(h.end(), op->tab.D.begin(), op->tab.D.end());
   h.insert(h.end(), op->tab.wq.begin(), op->tab.wq.end());
+  std::vector<double> mi;
+  if (!inverse_mass_1d(mesh->tab, mi)) {
+    delete op;
+    return fail(DGMF_INVALID, "convective_create: singular interpolation matrix");
+  }
+  h.insert(h.end(), mi.begin(), mi.end());
   dgmf_status st = op->ctab.upload(h.data(), h.size() * sizeof(double));
   if (st != DGMF_OK) {
     delete op;
@@ -689,6 +738,7 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
   g.S = 0;
   g.D = nq * n;
   g.w = 2 * nq * n;
+  g.Mi = 2 * nq * n + nq;
   mesh->nops++;
   *out = op;
   return DGMF_OK;
@@ -700,7 +750,17 @@ dgmf_status dgmf_convective_apply(dgmf_op op, const double* u, double* out, hipS
     return fail(DGMF_INVALID, "convective_apply: null or misaligned vector");
   if (overlap(u, out, 24 * op->mesh->ndofs)) return fail(DGMF_INVALID, "convective_apply: u and out overlap");
   DeviceGuard dg(op->mesh->device);
-  return launch_conv_fwd(op->tab.n, op->nq, op->cgeo, u, out, op->mesh->ncells, stream);
+  return launch_conv_fwd(op->tab.n, op->nq, op->cgeo, u, out, op->mesh->ncells, false, 0.0, stream);
+}
+
+dgmf_status dgmf_convective_step(dgmf_op op, double dt, const double* u, double* out, hipStream_t stream) {
+  if (!op || op->kind != 2) return fail(DGMF_INVALID, "convective_step: not a convective operator");
+  if (!std::isfinite(dt)) return fail(DGMF_INVALID, "convective_step: dt must be finite");
+  if (!u || !out || !aligned(u, 8) || !aligned(out, 8))
+    return fail(DGMF_INVALID, "convective_step: null or misaligned vector");
+  if (overlap(u, out, 24 * op->mesh->ndofs)) return fail(DGMF_INVALID, "convective_step: u and out overlap");
+  DeviceGuard dg(op->mesh->device);
+  return launch_conv_fwd(op->tab.n, op->nq, op->cgeo, u, out, op->mesh->ncells, true, dt, stream);
 }
 
 dgmf_status dgmf_convective_vjp(dgmf_op op, const double* u, const double* w, double* grad, hipStream_t stream) {

@@ -1,5 +1,6 @@
-// Convective operator with the local Lax-Friedrichs flux and its
-// vector-Jacobian product, on axis-aligned hexahedra (gfx950).
+// Convective operator with the local Lax-Friedrichs flux, the explicit
+// convective substep U - dt M^{-1} C(U), and the vector-Jacobian product, on
+// axis-aligned hexahedra (gfx950).
 //
 // C(U)_{i,a} = - sum_K (d_b phi_i, u_a u_b)_K + sum_K (phi_i, R_a)_{dK}      (Sec. 3.2, eq. convstepspat)
 //   R = 1/2 (u- (u-.n) + u+ (u+.n)) + lam (u- - u+),  lam = max(|u-.n|, |u+.n|)
@@ -21,7 +22,10 @@
 // accumulators); sweeps along x and y are staged through LDS with one thread
 // per line; faces are processed one direction (or one face) at a time and
 // their lifts land on the cell's boundary node planes before a single
-// coalesced store.
+// coalesced store.  The substep variant applies the inverse mass block
+// (Mh^{-1} along x, y and z, times 1/|det J|; Sec. 5, implementation) to the
+// cell's result in LDS and writes U - dt M^{-1} C(U) in the same store, so
+// C(U) never travels through HBM.
 #include "internal.h"
 
 namespace dgmf {
@@ -238,10 +242,10 @@ __device__ __forceinline__ void copy_plane(const double* sIn, int d, int s, doub
 }
 
 // ---------------------------------------------------------------- forward
-template <int N, int Q>
+template <int N, int Q, bool STEP>
 __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const double* __restrict__ U,
                                                                     double* __restrict__ C, const ConvGeom g,
-                                                                    int64_t ncells) {
+                                                                    int64_t ncells, double dt) {
   using SH = CShape<N, Q>;
   constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2;
   constexpr int XR = (3 * N2 * Q + 3 * N * Q2) > (3 * N * Q2 + 2 * N2 * Q) ? (3 * N2 * Q + 3 * N * Q2)
@@ -381,9 +385,42 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
     __syncthreads();
     face_lift<N, Q>(S, R, F1, sO, 6, d, -1, tid, nthr);
   }
-  for (int e = tid; e < 3 * N3; e += nthr) {
-    const int a = e / N3, r = e % N3;
-    C[a * Nd + cell * N3 + r] = sO[e];
+  __syncthreads();
+  if constexpr (STEP) {
+    // U - dt M^{-1} C(U): three 1D sweeps by Mh^{-1} (x, y, z lines of the
+    // three components, in place, one line per thread) and the scale 1/|det J|
+    const double* Mi = g.tab + g.Mi;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int stride = d == 0 ? 1 : (d == 1 ? N : N2);
+      for (int job = tid; job < 3 * N2; job += nthr) {
+        const int a = job / N2, r = job % N2;
+        // line start: x lines (j, l) -> r * N; y lines (i, l) -> l N^2 + i; z lines (i, j) -> r
+        const int start = d == 0 ? r * N : (d == 1 ? (r / N) * N2 + r % N : r);
+        double* p = sO + a * N3 + start;
+        double v[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = p[m * stride];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          double t = 0;
+#pragma unroll
+          for (int m = 0; m < N; ++m) t = fma(Mi[i * N + m], v[m], t);
+          p[i * stride] = t;
+        }
+      }
+      __syncthreads();
+    }
+    const double sc = -dt * cg.hinv[0] * cg.hinv[1] * cg.hinv[2];
+    for (int e = tid; e < 3 * N3; e += nthr) {
+      const int a = e / N3, r = e % N3;
+      C[a * Nd + cell * N3 + r] = fma(sc, sO[e], sU[e]);
+    }
+  } else {
+    for (int e = tid; e < 3 * N3; e += nthr) {
+      const int a = e / N3, r = e % N3;
+      C[a * Nd + cell * N3 + r] = sO[e];
+    }
   }
 }
 
@@ -638,6 +675,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     __syncthreads();
     face_lift<N, Q>(S, R, F1, sO, 3, d, s, tid, nthr);
   }
+  __syncthreads();
   for (int e = tid; e < 3 * N3; e += nthr) {
     const int a = e / N3, r = e % N3;
     G[a * Nd + cell * N3 + r] = sO[e];
@@ -645,10 +683,15 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
 }
 
 template <int N, int Q>
-dgmf_status launch_fwd_nq(const ConvGeom& g, const double* U, double* C, int64_t ncells, hipStream_t s) {
+dgmf_status launch_fwd_nq(const ConvGeom& g, const double* U, double* C, int64_t ncells, bool step, double dt,
+                          hipStream_t s) {
   if (ncells > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
-  hipLaunchKernelGGL((k_conv_fwd<N, Q>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0, s, U,
-                     C, g, ncells);
+  if (step)
+    hipLaunchKernelGGL((k_conv_fwd<N, Q, true>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0,
+                       s, U, C, g, ncells, dt);
+  else
+    hipLaunchKernelGGL((k_conv_fwd<N, Q, false>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0,
+                       s, U, C, g, ncells, dt);
   DGMF_LAUNCH_CHECK("k_conv_fwd");
   return DGMF_OK;
 }
@@ -678,8 +721,8 @@ bool conv_supported(int n, int nq) {
 }
 
 dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, double* C, int64_t ncells,
-                            hipStream_t s) {
-#define X(a, b) if (n == a && nq == b) return launch_fwd_nq<a, b>(g, U, C, ncells, s);
+                            bool step, double dt, hipStream_t s) {
+#define X(a, b) if (n == a && nq == b) return launch_fwd_nq<a, b>(g, U, C, ncells, step, dt, s);
   DGMF_CONV_CASES(X)
 #undef X
   return fail(DGMF_UNSUPPORTED, "convective: (n, n_q) = (%d, %d) not built", n, nq);

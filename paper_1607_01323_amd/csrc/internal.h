@@ -36,8 +36,8 @@ struct ConvGeom {
   int per[3];
   const double* h[3];
   const double* hinv[3];
-  const double* tab;   // S[nq*n], D[nq*n], w[nq]
-  int S, D, w;         // offsets into tab
+  const double* tab;   // S[nq*n], D[nq*n], w[nq], Mh^{-1}[n*n] (k+1-point 1D mass, inverted)
+  int S, D, w, Mi;     // offsets into tab
 };
 
 // ---------------------------------------------------------------- errors ---
@@ -193,10 +193,21 @@ dgmf_status launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
 constexpr int metric_tab_size(int n) { return 3 * n * n + 5 * n; }
 
 bool conv_supported(int n, int nq);
+// C = C(U); with step, C = U - dt M^{-1} C(U) instead (explicit convective substep).
 dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, double* C, int64_t ncells,
-                            hipStream_t s);
+                            bool step, double dt, hipStream_t s);
 dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
                             int64_t ncells, hipStream_t s);
+
+// dst = M^{-1} src on nfields consecutive scalar fields of an affine mesh:
+// minv the n x n inverse 1D mass (k+1 Gauss points), jscale = 1/|det shear|.
+// src and dst may be the same array.
+template <typename T>
+dgmf_status launch_inverse_mass(int n, const CartGeom<T>& g, T jscale, const T* minv, const T* src, T* dst,
+                                int64_t ncells, int nfields, hipStream_t s);
+// Inverse of the 1D reference mass S^T W S (square S: n_q = k+1) as
+// S^{-1} W^{-1} S^{-T}, row-major n x n; false when S is singular.
+bool inverse_mass_1d(const Tables1D& t, std::vector<double>& out);
 
 // Dispatch over the two SIPG apply kernels (tables of axis-aligned cells or
 // metric stored at the quadrature points), and the number of partial rows the
@@ -224,6 +235,7 @@ struct dgmf_mesh_ {
   dgmf::DevBuf met64, met32, mtab64, mtab32;
   dgmf::MetricGeom<double> mg64{};   // coefficients unset
   dgmf::MetricGeom<float> mg32{};
+  dgmf::DevBuf minv64, minv32;     // inverse 1D mass (n x n) for dgmf_inverse_mass_apply
   int nops = 0;                    // live operators built on this mesh
 };
 

@@ -133,3 +133,14 @@ def test_step_is_consistent_with_the_advection_term(k):
         errs.append(np.sqrt(np.mean((est - ex) ** 2)))
     assert errs[1] < 0.1 * np.abs(ex).max()
     assert errs[0] / errs[1] > 2.0 ** (k - 0.5)
+
+
+def test_sampled_cells_match_the_whole_mesh():
+    m = mesh.BoxMesh(2, 3, 2, 2, lx=1.0, ly=2.0, lz=1.0, y0=-1.0, periodic=(True, False, True),
+                     y_tanh_gamma=1.2)
+    op = convective.Convective(m)
+    X = m.node_coords()
+    U = (inp.parabolic(X[:, 0], X[:, 1], X[:, 2]) + 0.2 * inp.uniform(3, 3 * m.ndofs).reshape(3, -1)).ravel()
+    cells = [0, 4, 11]
+    full = mass.convective_step(op, U, 0.07).reshape(3, m.ncells, -1)[:, cells]
+    np.testing.assert_allclose(mass.convective_step_cells(op, U, 0.07, cells), full, rtol=0, atol=1e-14)
