@@ -28,6 +28,7 @@ solvers     textbook PCG, Lanczos, Chebyshev (Sec. 5.1 "Solving linear systems")
 convective  divergence-form convective operator with local Lax-Friedrichs
             flux, its JVP/VJP and assembled Jacobian (Sec. 3.2 eq. convstepspat)
 rng         SplitMix64 counter-based generator (published definition)
+multigrid   geometric multigrid V-cycle preconditioner (Sec. 5.1, Poisson solver)
 mass        block-diagonal inverse mass matrix and the explicit convective
             substep of the matrix form (eq. advect)
 
