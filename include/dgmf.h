@@ -13,8 +13,9 @@
  *     scalar form (Sec. 3.2, eqs. poissonspat, ipflux, taue, tau; matrix
  *     form Sec. 4.4, eqs. poissonmat and viscous);
  *   - preconditioned conjugate gradients with matrix-free products, point
- *     Jacobi or a Chebyshev polynomial preconditioner in single precision,
- *     and the zero-mean projection of singular problems (Sec. 5.1);
+ *     Jacobi, a Chebyshev polynomial preconditioner or a geometric multigrid
+ *     V-cycle with Chebyshev smoothing, in single precision, and the
+ *     zero-mean projection of singular problems (Sec. 5.1);
  *   - the divergence-form convective operator with the local Lax-Friedrichs
  *     flux, Lambda evaluated per face quadrature point (Sec. 3.2, eq.
  *     convstepspat; matrix form eq. advect), its vector-Jacobian product,
@@ -160,12 +161,28 @@ dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_
  * periodic Laplacian).  check_every: iterations between host reads of the
  * convergence flag (the iteration count is exact regardless).  flexible
  * selects the Polak-Ribiere beta (flexible CG, Notay 2000), which tolerates
- * the slight non-linearity of a preconditioner evaluated in fp32. */
+ * the slight non-linearity of a preconditioner evaluated in fp32.
+ * precond 2: one V-cycle of geometric multigrid in precond_dtype (Sec. 5.1,
+ * Poisson solver) over the hierarchy that halves every even cell count until
+ * none is even, the operator discretised anew on every level (coarse levels
+ * use the per-cell metric of axis-aligned cells; sheared meshes are
+ * DGMF_UNSUPPORTED).  Smoother before and after the coarse correction: the
+ * Chebyshev-Jacobi polynomial above (cheb_degree, smoothing_range,
+ * lanczos_steps, lambda_safety; level l uses seed + l).  Coarse solver:
+ * Chebyshev-Jacobi from zero on [theta_min / lambda_safety, lambda_safety
+ * theta_max] (fp64 Lanczos with full re-orthogonalisation, at most 64 steps,
+ * the null vector deflated when project_mean) with the smallest degree whose
+ * Chebyshev error estimate 1/T_m((b+a)/(b-a)) is below mg_coarse_tol
+ * (0 -> 1e-3; at most 2000).  Transfers: the mother cell's polynomial
+ * evaluated at its children's nodes (reference-cell embedding) and its
+ * transpose.  The hierarchy (level meshes, operators, vectors, eigenvalue
+ * estimates) is built on the first call and kept with the operator until
+ * dgmf_op_destroy or a call with different preconditioner parameters. */
 typedef struct {
   double rtol;
   int max_iter;
   int check_every;
-  int precond;           /* 0 Jacobi, 1 Chebyshev */
+  int precond;           /* 0 Jacobi, 1 Chebyshev, 2 geometric multigrid V-cycle */
   int precond_dtype;     /* dgmf_dtype of the Chebyshev preconditioner */
   int cheb_degree;       /* >= 1 */
   double smoothing_range;/* > 1 */
@@ -175,6 +192,7 @@ typedef struct {
   int project_mean;
   int flexible;          /* 0: beta = <r+,z+>/<r,z> (Fletcher-Reeves); 1: beta = <z+, r+ - r>/<r,z>
                             (Polak-Ribiere, flexible CG: robust to the rounding of an fp32 preconditioner) */
+  double mg_coarse_tol;  /* precond 2: coarse Chebyshev error estimate target, 0 -> 1e-3 */
 } dgmf_cg_params;
 
 typedef struct {
@@ -196,6 +214,20 @@ dgmf_status dgmf_cg_workspace_bytes(dgmf_op op, const dgmf_cg_params* params, si
 dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params,
                           void* workspace, size_t workspace_bytes, hipStream_t stream,
                           dgmf_cg_result* out);
+
+/* z = B r, one application of the multigrid preconditioner (params->precond
+ * must be 2; other fields as for dgmf_cg_solve), no mean projection.  r, z:
+ * device fp64 [N], must not overlap.  Builds the hierarchy synchronously on
+ * first use, then asynchronous on stream. */
+dgmf_status dgmf_precond_apply(dgmf_op op, const dgmf_cg_params* params, const double* r, double* z,
+                               hipStream_t stream);
+/* Host outputs of the operator's multigrid hierarchy (any may be NULL):
+ * number of levels, lambda of every level's smoother (host array of at
+ * least 32 entries; the coarsest entry is the upper end of its interval), the
+ * coarse Chebyshev degree and interval [lo, hi].  DGMF_INVALID before the
+ * hierarchy exists. */
+dgmf_status dgmf_precond_info(dgmf_op op, int* levels, double* lambdas, int* coarse_degree,
+                              double* coarse_interval);
 
 /* ---------------------------------------------------------- convective --- */
 /* Convective operator C(U)_{i,a} = -sum_K (d_b phi_i, u_a u_b)_K

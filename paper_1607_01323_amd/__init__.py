@@ -45,7 +45,7 @@ class CgParams(ctypes.Structure):
                 ("precond", ctypes.c_int), ("precond_dtype", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("smoothing_range", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
                 ("lambda_safety", ctypes.c_double), ("seed", ctypes.c_uint64), ("project_mean", ctypes.c_int),
-                ("flexible", ctypes.c_int)]
+                ("flexible", ctypes.c_int), ("mg_coarse_tol", ctypes.c_double)]
 
 
 class CgResult(ctypes.Structure):
@@ -80,6 +80,9 @@ _integ = _sig("dgmf_integrate", _vp, _vp, _vp, _vp)
 _ws_bytes = _sig("dgmf_cg_workspace_bytes", _vp, ctypes.POINTER(CgParams), ctypes.POINTER(ctypes.c_size_t))
 _cg = _sig("dgmf_cg_solve", _vp, _vp, _vp, ctypes.POINTER(CgParams), _vp, ctypes.c_size_t, _vp,
            ctypes.POINTER(CgResult))
+_pc_apply = _sig("dgmf_precond_apply", _vp, ctypes.POINTER(CgParams), _vp, _vp, _vp)
+_pc_info = _sig("dgmf_precond_info", _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double))
 _conv_create = _sig("dgmf_convective_create", _vp, ctypes.POINTER(ConvDesc), ctypes.POINTER(_vp))
 _conv_apply = _sig("dgmf_convective_apply", _vp, _vp, _vp, _vp)
 _conv_vjp = _sig("dgmf_convective_vjp", _vp, _vp, _vp, _vp, _vp)
@@ -222,19 +225,48 @@ class SipgOperator(_Op):
                       _stream()), "integrate")
         return b
 
-    def cg(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, precond="jacobi", precond_dtype=torch.float64,
-           cheb_degree=5, smoothing_range=20.0, lanczos_steps=15, lambda_safety=1.2, seed=0, project_mean=False,
-           flexible=None, raise_on_failure=True):
-        """PCG on H x = b; x (fp64, device) holds the initial guess and receives the solution.
+    _PRECONDS = {"jacobi": 0, "chebyshev": 1, "multigrid": 2}
 
-        flexible=None picks the Polak-Ribiere (flexible) beta exactly when the
-        preconditioner runs in fp32.
-        """
+    def _params(self, rtol, max_iter, check_every, precond, precond_dtype, cheb_degree, smoothing_range,
+                lanczos_steps, lambda_safety, seed, project_mean, flexible, mg_coarse_tol):
+        if precond not in self._PRECONDS:
+            raise ValueError(f"precond must be one of {sorted(self._PRECONDS)}")
         if flexible is None:
             flexible = precond != "jacobi" and precond_dtype == torch.float32
-        p = CgParams(rtol, max_iter, check_every, 0 if precond == "jacobi" else 1,
-                     F64 if precond_dtype == torch.float64 else F32, cheb_degree, smoothing_range, lanczos_steps,
-                     lambda_safety, seed, int(bool(project_mean)), int(bool(flexible)))
+        return CgParams(rtol, max_iter, check_every, self._PRECONDS[precond],
+                        F64 if precond_dtype == torch.float64 else F32, cheb_degree, smoothing_range, lanczos_steps,
+                        lambda_safety, seed, int(bool(project_mean)), int(bool(flexible)), mg_coarse_tol)
+
+    def precond_apply(self, r, precond_dtype=torch.float32, cheb_degree=5, smoothing_range=20.0, lanczos_steps=15,
+                      lambda_safety=1.2, seed=0, project_mean=False, mg_coarse_tol=0.0, out=None):
+        """z = B r, one multigrid V-cycle (fp64 in and out, computed in precond_dtype)."""
+        p = self._params(0.0, 0, 1, "multigrid", precond_dtype, cheb_degree, smoothing_range, lanczos_steps,
+                         lambda_safety, seed, project_mean, False, mg_coarse_tol)
+        n = self.mesh.ndofs
+        if out is None:
+            out = torch.empty_like(r)
+        _check(_pc_apply(self._h, ctypes.byref(p), _ptr(r, torch.float64, n, "r"), _ptr(out, torch.float64, n, "z"),
+                         _stream()), "precond_apply")
+        return out
+
+    def precond_info(self):
+        """(levels, per-level lambdas, coarse degree, coarse interval) of the built multigrid hierarchy."""
+        lv, deg = ctypes.c_int(), ctypes.c_int()
+        lam = (ctypes.c_double * 32)()
+        iv = (ctypes.c_double * 2)()
+        _check(_pc_info(self._h, ctypes.byref(lv), lam, ctypes.byref(deg), iv), "precond_info")
+        return lv.value, list(lam[:lv.value]), deg.value, (iv[0], iv[1])
+
+    def cg(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, precond="jacobi", precond_dtype=torch.float64,
+           cheb_degree=5, smoothing_range=20.0, lanczos_steps=15, lambda_safety=1.2, seed=0, project_mean=False,
+           flexible=None, raise_on_failure=True, mg_coarse_tol=0.0):
+        """PCG on H x = b; x (fp64, device) holds the initial guess and receives the solution.
+
+        precond: "jacobi", "chebyshev" or "multigrid".  flexible=None picks the
+        Polak-Ribiere (flexible) beta exactly when the preconditioner runs in fp32.
+        """
+        p = self._params(rtol, max_iter, check_every, precond, precond_dtype, cheb_degree, smoothing_range,
+                         lanczos_steps, lambda_safety, seed, project_mean, flexible, mg_coarse_tol)
         nbytes = ctypes.c_size_t()
         _check(_ws_bytes(self._h, ctypes.byref(p), ctypes.byref(nbytes)), "cg_workspace_bytes")
         ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device="cuda")

@@ -686,6 +686,7 @@ extern "C" {
 dgmf_status dgmf_op_destroy(dgmf_op op) {
   if (!op) return DGMF_OK;
   DeviceGuard dg(op->mesh->device);
+  if (op->mgh) mg_destroy(op->mgh);
   op->mesh->nops--;
   delete op;
   return DGMF_OK;

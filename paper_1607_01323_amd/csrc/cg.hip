@@ -16,9 +16,11 @@
 // with the matrix diagonal, eigenvalue estimates from a Krylov start-up).
 // Singular problems (periodic Laplacian) are solved on zero-mean vectors by
 // projecting b and every operator product (Sec. 5.1).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 
 #include "internal.h"
 
@@ -393,33 +395,6 @@ __global__ void __launch_bounds__(256) k_lz_next(const T* __restrict__ w, T* __r
   GRID_STRIDE(i, N) vprev[i] = w[i] * s;
 }
 
-// Largest eigenvalue of the symmetric tridiagonal (a, b) by bisection on the
-// Sturm sequence count (Wilkinson), bracketed by Gershgorin discs.
-double tridiag_max_eig(const double* a, const double* b, int m) {
-  double lo = 1e300, hi = -1e300;
-  for (int i = 0; i < m; ++i) {
-    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
-    lo = std::fmin(lo, a[i] - r);
-    hi = std::fmax(hi, a[i] + r);
-  }
-  auto count_below = [&](double x) {
-    int c = 0;
-    double q = 1.0;
-    for (int i = 0; i < m; ++i) {
-      const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
-      q = a[i] - x - (i > 0 ? bb / q : 0.0);
-      if (q == 0.0) q = -1e-300;
-      if (q < 0) ++c;
-    }
-    return c;
-  };
-  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::fmax(std::fabs(lo), std::fabs(hi)); ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (count_below(mid) >= m) hi = mid; else lo = mid;
-  }
-  return hi;
-}
-
 struct Layout {
   size_t state, partials, bp, r, z, p, q, dinv, diag, v64;       // fp64 part
   size_t cdinv, cdsq, cres, cd, czc, ct;                       // precond dtype part
@@ -451,8 +426,8 @@ dgmf_status validate(dgmf_op op, const dgmf_cg_params* p) {
   if (!p) return fail(DGMF_INVALID, "cg: null params");
   if (!(p->rtol >= 0) || !std::isfinite(p->rtol)) return fail(DGMF_INVALID, "cg: rtol must be finite and >= 0");
   if (p->max_iter < 0) return fail(DGMF_INVALID, "cg: max_iter must be >= 0");
-  if (p->precond != 0 && p->precond != 1) return fail(DGMF_INVALID, "cg: precond must be 0 or 1");
-  if (p->precond == 1) {
+  if (p->precond < 0 || p->precond > 2) return fail(DGMF_INVALID, "cg: precond must be 0, 1 or 2");
+  if (p->precond >= 1) {
     if (p->precond_dtype != DGMF_F32 && p->precond_dtype != DGMF_F64)
       return fail(DGMF_INVALID, "cg: precond_dtype must be DGMF_F32 or DGMF_F64");
     if (p->cheb_degree < 1 || p->cheb_degree > 64) return fail(DGMF_INVALID, "cg: cheb_degree must be in 1..64");
@@ -461,12 +436,442 @@ dgmf_status validate(dgmf_op op, const dgmf_cg_params* p) {
       return fail(DGMF_INVALID, "cg: lanczos_steps must be in 2..%d", kMaxLanczos);
     if (!(p->lambda_safety >= 1)) return fail(DGMF_INVALID, "cg: lambda_safety must be >= 1");
   }
+  if (p->precond == 2 && !(p->mg_coarse_tol >= 0 && p->mg_coarse_tol < 1))
+    return fail(DGMF_INVALID, "cg: mg_coarse_tol must be in [0, 1)");
   return DGMF_OK;
 }
 
 int64_t nparts_for(dgmf_op op) {
   const int64_t a = sipg_apply_blocks(op);
   return a > kVecBlocks ? a : kVecBlocks;
+}
+
+
+dgmf_status launch_scalar(CgState* st, const double* partials, int nblk, int mode, int64_t N, int step, int stopmask,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(1024), 0, s, st, partials, nblk, mode, N, step, stopmask);
+  DGMF_LAUNCH_CHECK("k_scalar");
+  return DGMF_OK;
+}
+
+// k-th smallest eigenvalue (k = 0..m-1) of the symmetric tridiagonal (a, b)
+// by bisection on the Sturm sequence count, bracketed by Gershgorin discs.
+double tridiag_eig(const double* a, const double* b, int m, int k) {
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::fmin(lo, a[i] - r);
+    hi = std::fmax(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+      const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+      q = a[i] - x - (i > 0 ? bb / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::fmax(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= k + 1) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+// Chebyshev acceleration of Jacobi on [a, b] with an error polynomial of degree m
+// (Saad, Alg. 12.1): d_0 = dinv r / theta; d_j = c1[j] d_{j-1} + c2[j] dinv r_j.
+void cheb_coeffs(double a, double b, int m, double& inv_theta, std::vector<double>& c1, std::vector<double>& c2) {
+  const double th = 0.5 * (a + b), de = 0.5 * (b - a), sigma = th / de;
+  inv_theta = 1.0 / th;
+  double rho = 1.0 / sigma;
+  c1.assign(m, 0.0);
+  c2.assign(m, 0.0);
+  for (int j = 1; j < m; ++j) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c1[j] = rn * rho;
+    c2[j] = 2.0 * rn / de;
+    rho = rn;
+  }
+}
+
+template <typename T>
+struct LzBufs {
+  T* dsq;
+  T* v;
+  T* vp;
+  T* w;
+  T* t;
+  double* v64;
+};
+
+// Largest Ritz value of m Lanczos steps (no re-orthogonalisation) on
+// D^{-1/2} H D^{-1/2} in precision T, start vector SplitMix64(seed) with its
+// mean removed when st->project.
+template <typename T>
+dgmf_status lanczos_max(dgmf_op op, int64_t N, const LzBufs<T>& B, CgState* st, double* partials, int m,
+                        uint64_t seed, hipStream_t s, double& theta) {
+  T* v = B.v;
+  T* vp = B.vp;
+  const dim3 G(kVecBlocks), Bk(256);
+  hipLaunchKernelGGL(k_splitmix_uniform, G, Bk, 0, s, B.v64, seed, N, partials);
+  DGMF_LAUNCH_CHECK("k_splitmix_uniform");
+  dgmf_status e = launch_scalar(st, partials, kVecBlocks, M_LZ_MEAN, N, 0, 0, s);
+  if (e) return e;
+  hipLaunchKernelGGL(k_lz_center, G, Bk, 0, s, B.v64, N, st, partials);
+  DGMF_LAUNCH_CHECK("k_lz_center");
+  if ((e = launch_scalar(st, partials, kVecBlocks, M_LZ_NORM, N, 0, 0, s))) return e;
+  hipLaunchKernelGGL((k_lz_start<T>), G, Bk, 0, s, B.v64, v, vp, N, st);
+  DGMF_LAUNCH_CHECK("k_lz_start");
+  for (int j = 0; j < m; ++j) {
+    hipLaunchKernelGGL((k_lz_scale<T>), G, Bk, 0, s, v, B.dsq, B.t, N);
+    DGMF_LAUNCH_CHECK("k_lz_scale");
+    if ((e = sipg_apply<T>(op, B.t, B.w, nullptr, nullptr, s))) return e;
+    hipLaunchKernelGGL((k_lz_w<T>), G, Bk, 0, s, B.w, B.dsq, v, vp, N, st, j, partials);
+    DGMF_LAUNCH_CHECK("k_lz_w");
+    if ((e = launch_scalar(st, partials, kVecBlocks, M_LZ_ALPHA, N, j, 0, s))) return e;
+    hipLaunchKernelGGL((k_lz_orth<T>), G, Bk, 0, s, B.w, v, N, st, j, partials);
+    DGMF_LAUNCH_CHECK("k_lz_orth");
+    if ((e = launch_scalar(st, partials, kVecBlocks, M_LZ_BETA, N, j, 0, s))) return e;
+    hipLaunchKernelGGL((k_lz_next<T>), G, Bk, 0, s, B.w, vp, N, st, j);
+    DGMF_LAUNCH_CHECK("k_lz_next");
+    T* tmp = v; v = vp; vp = tmp;
+  }
+  double ha[kMaxLanczos], hb[kMaxLanczos];
+  DGMF_HIP_TRY(hipMemcpyAsync(ha, st->lz_alpha, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  DGMF_HIP_TRY(hipMemcpyAsync(hb, st->lz_beta, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  DGMF_HIP_TRY(hipStreamSynchronize(s));
+  int mm = m;
+  for (int j = 0; j < m; ++j) {
+    if (!std::isfinite(ha[j])) { mm = j; break; }
+    if (j < m - 1 && !(hb[j] > 0)) { mm = j + 1; break; }
+  }
+  if (mm < 1) return fail(DGMF_NONFINITE, "cg: eigenvalue estimate is not finite");
+  theta = tridiag_eig(ha, hb, mm, mm - 1);
+  if (!(theta > 0) || !std::isfinite(theta)) return fail(DGMF_BREAKDOWN, "cg: eigenvalue estimate %g <= 0", theta);
+  return DGMF_OK;
+}
+
+// The i-th SplitMix64 output of a generator seeded with `seed`, as a double in [-1, 1).
+double splitmix_uniform_host(uint64_t seed, int64_t i) {
+  uint64_t z = seed + static_cast<uint64_t>(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return 2.0 * static_cast<double>(z >> 11) * 0x1.0p-53 - 1.0;
+}
+
+// z64 = x (precision T) and the partials <r,z>, <r,r>, <z, q - mean_q>.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mg_out(const T* __restrict__ x, const double* __restrict__ r,
+                                                double* __restrict__ z, const double* __restrict__ q, int64_t N,
+                                                const CgState* st, double* partials) {
+  if (st->status != RUNNING) return;
+  const double mq = st->mean_q;
+  double v[3] = {0, 0, 0};
+  GRID_STRIDE(i, N) {
+    const double zd = static_cast<double>(x[i]);
+    z[i] = zd;
+    final_terms(v, r[i], zd, q, i, mq);
+  }
+  block_partials<3>(v, partials, blockIdx.x);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------- multigrid ---
+// One level of the hierarchy: its mesh and operator (the caller's on the
+// finest level), seven vectors in the preconditioner precision (b, x, res,
+// d, t, dinv, dsq), the transfer to the next coarser level, and the
+// Chebyshev parameters of its smoother (or of the coarse solver).
+struct MgLevel {
+  dgmf_mesh mesh = nullptr;
+  dgmf_op op = nullptr;
+  bool owned = false;
+  int64_t N = 0;
+  int nc[3] = {0, 0, 0};
+  MgXfer xf{};
+  DevBuf vec, etab;
+  double lambda = 0, lo = 0, hi = 0, inv_theta = 0;
+  int m = 0;
+  std::vector<double> c1, c2;
+  template <typename T>
+  T* v(int k) { return static_cast<T*>(vec.p) + k * N; }
+};
+
+struct MgHierarchy {
+  dgmf_cg_params key{};
+  std::vector<MgLevel> lv;
+  DevBuf scratch;
+  ~MgHierarchy() {
+    for (auto& l : lv)
+      if (l.owned) {
+        l.vec.release();
+        l.etab.release();
+        if (l.op) dgmf_op_destroy(l.op);
+        if (l.mesh) dgmf_mesh_destroy(l.mesh);
+      }
+  }
+};
+
+void mg_destroy(MgHierarchy* h) { delete h; }
+
+namespace {
+
+bool mg_same(const dgmf_cg_params& a, const dgmf_cg_params& b) {
+  return a.precond_dtype == b.precond_dtype && a.cheb_degree == b.cheb_degree &&
+         a.smoothing_range == b.smoothing_range && a.lanczos_steps == b.lanczos_steps &&
+         a.lambda_safety == b.lambda_safety && a.seed == b.seed && (a.project_mean != 0) == (b.project_mean != 0) &&
+         a.mg_coarse_tol == b.mg_coarse_tol;
+}
+
+double coarse_tol(const dgmf_cg_params& p) { return p.mg_coarse_tol > 0 ? p.mg_coarse_tol : 1e-3; }
+
+constexpr int kMaxCoarseDegree = 2000;
+
+// Extreme Ritz values of fp64 Lanczos with full re-orthogonalisation on the
+// coarsest level's D^{-1/2} H D^{-1/2} (host-driven; the level is small), the
+// null vector D^{1/2} 1 deflated for singular problems.
+dgmf_status coarse_interval(MgLevel& c, const std::vector<double>& diag, bool singular, uint64_t seed, double* dv,
+                            double* dw, hipStream_t s, double& tmin, double& tmax) {
+  const int64_t N = c.N;
+  std::vector<double> sq(N), nul;
+  for (int64_t i = 0; i < N; ++i) sq[i] = std::sqrt(diag[i]);
+  if (singular) {
+    double nn = 0;
+    for (double v : sq) nn += v * v;
+    nn = std::sqrt(nn);
+    nul.resize(N);
+    for (int64_t i = 0; i < N; ++i) nul[i] = sq[i] / nn;
+  }
+  auto dot = [&](const std::vector<double>& a, const std::vector<double>& b) {
+    double r = 0;
+    for (int64_t i = 0; i < N; ++i) r += a[i] * b[i];
+    return r;
+  };
+  auto deflate = [&](std::vector<double>& w) {
+    if (!singular) return;
+    const double a = dot(nul, w);
+    for (int64_t i = 0; i < N; ++i) w[i] -= a * nul[i];
+  };
+  auto normalise = [&](std::vector<double>& w) {
+    const double nrm = std::sqrt(dot(w, w));
+    for (auto& x : w) x /= nrm;
+  };
+  const int steps = static_cast<int>(std::min<int64_t>(64, N - (singular ? 1 : 0)));
+  if (steps < 1) return fail(DGMF_UNSUPPORTED, "multigrid: coarse level too small");
+  std::vector<std::vector<double>> V;
+  std::vector<double> v(N), w(N), t(N), al, be;
+  for (int64_t i = 0; i < N; ++i) v[i] = splitmix_uniform_host(seed, i);
+  deflate(v);
+  normalise(v);
+  for (int j = 0; j < steps; ++j) {
+    V.push_back(v);
+    for (int64_t i = 0; i < N; ++i) t[i] = v[i] / sq[i];
+    DGMF_HIP_TRY(hipMemcpyAsync(dv, t.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    dgmf_status e = sipg_apply<double>(c.op, dv, dw, nullptr, nullptr, s);
+    if (e) return e;
+    DGMF_HIP_TRY(hipMemcpyAsync(w.data(), dw, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    DGMF_HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < N; ++i) w[i] /= sq[i];
+    const double alpha = dot(w, v);
+    deflate(w);
+    for (int pass = 0; pass < 2; ++pass)
+      for (const auto& u : V) {
+        const double a = dot(u, w);
+        for (int64_t i = 0; i < N; ++i) w[i] -= a * u[i];
+      }
+    al.push_back(alpha);
+    const double beta = std::sqrt(dot(w, w));
+    double scale = 0;
+    for (double a : al) scale = std::fmax(scale, std::fabs(a));
+    if (j == steps - 1 || beta <= 1e-8 * scale) break;
+    be.push_back(beta);
+    for (int64_t i = 0; i < N; ++i) v[i] = w[i] / beta;
+    deflate(v);
+    normalise(v);
+  }
+  const int m = static_cast<int>(al.size());
+  be.resize(m);
+  tmin = tridiag_eig(al.data(), be.data(), m, 0);
+  tmax = tridiag_eig(al.data(), be.data(), m, m - 1);
+  if (!(tmin > 0) || !(tmax >= tmin) || !std::isfinite(tmax))
+    return fail(DGMF_BREAKDOWN, "multigrid: coarse eigenvalue estimates [%g, %g] are not positive", tmin, tmax);
+  return DGMF_OK;
+}
+
+template <typename T>
+dgmf_status mg_build(dgmf_op op, const dgmf_cg_params& prm, hipStream_t s, MgHierarchy*& out) {
+  if (op->mesh->shear.on) return fail(DGMF_UNSUPPORTED, "multigrid: sheared meshes are not supported");
+  auto* h = new (std::nothrow) MgHierarchy;
+  if (!h) return fail(DGMF_OOM, "multigrid: host allocation failed");
+  std::unique_ptr<MgHierarchy> guard(h);
+  h->key = prm;
+  const int n = op->mesh->tab.n;
+  int c[3] = {op->mesh->desc.nx, op->mesh->desc.ny, op->mesh->desc.nz};
+  {
+    MgLevel f;
+    f.mesh = op->mesh;
+    f.op = op;
+    f.N = op->mesh->ndofs;
+    for (int d = 0; d < 3; ++d) f.nc[d] = c[d];
+    h->lv.push_back(std::move(f));
+  }
+  for (;;) {
+    int nxt[3];
+    bool any = false;
+    for (int d = 0; d < 3; ++d) {
+      nxt[d] = c[d] % 2 == 0 ? c[d] / 2 : c[d];
+      any = any || nxt[d] != c[d];
+    }
+    if (!any) break;
+    dgmf_box_desc d = op->mesh->desc;
+    d.nx = nxt[0];
+    d.ny = nxt[1];
+    d.nz = nxt[2];
+    d.store_qp_metric = 0;
+    for (double& v : d.shear) v = 0.0;
+    MgLevel l;
+    l.owned = true;
+    dgmf_status e = dgmf_mesh_create(&d, &l.mesh);
+    if (e) return e;
+    e = dgmf_sipg_create(l.mesh, &op->sipg, &l.op);
+    if (e) {
+      dgmf_mesh_destroy(l.mesh);
+      return e;
+    }
+    l.N = l.mesh->ndofs;
+    for (int k = 0; k < 3; ++k) l.nc[k] = nxt[k];
+    h->lv.push_back(std::move(l));
+    for (int k = 0; k < 3; ++k) c[k] = nxt[k];
+  }
+  const int L = static_cast<int>(h->lv.size());
+  // transfer tables E_d[s][i][a] = l_a((s + xi_i) / r_d)
+  const Tables1D& tb = op->mesh->tab;
+  for (int l = 0; l + 1 < L; ++l) {
+    MgLevel& f = h->lv[l];
+    const MgLevel& g = h->lv[l + 1];
+    f.xf = MgXfer{g.nc[0], g.nc[1], g.nc[2], f.nc[0], f.nc[1], {f.nc[0] / g.nc[0], f.nc[1] / g.nc[1], f.nc[2] / g.nc[2]}};
+    std::vector<T> tab(6 * n * n, T(0));
+    std::vector<double> val(n);
+    for (int d = 0; d < 3; ++d)
+      for (int sd = 0; sd < f.xf.r[d]; ++sd)
+        for (int i = 0; i < n; ++i) {
+          if (f.xf.r[d] == 1) {
+            tab[(d * 2 + sd) * n * n + i * n + i] = T(1);
+            continue;
+          }
+          lagrange_eval(tb.nodes, 0.5 * (sd + tb.nodes[i]), val.data(), nullptr);
+          for (int a = 0; a < n; ++a) tab[(d * 2 + sd) * n * n + i * n + a] = static_cast<T>(val[a]);
+        }
+    dgmf_status e = f.etab.upload(tab.data(), tab.size() * sizeof(T));
+    if (e) return e;
+  }
+  for (auto& l : h->lv) {
+    dgmf_status e = l.vec.alloc(7 * l.N * sizeof(T));
+    if (e) return e;
+  }
+  // scratch: CgState, partials, two fp64 vectors of the finest size
+  const int64_t N0 = h->lv[0].N;
+  const size_t o_part = align256(sizeof(CgState)), o_v64 = align256(o_part + sizeof(double) * 4 * kVecBlocks),
+               o_d64 = align256(o_v64 + sizeof(double) * N0), total = align256(o_d64 + sizeof(double) * N0);
+  dgmf_status e = h->scratch.alloc(total);
+  if (e) return e;
+  char* sc = static_cast<char*>(h->scratch.p);
+  CgState* st = reinterpret_cast<CgState*>(sc);
+  double* partials = reinterpret_cast<double*>(sc + o_part);
+  double* v64 = reinterpret_cast<double*>(sc + o_v64);
+  double* d64 = reinterpret_cast<double*>(sc + o_d64);
+  CgState init{};
+  init.project = prm.project_mean ? 1 : 0;
+  DGMF_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  for (int l = 0; l < L; ++l) {
+    MgLevel& a = h->lv[l];
+    if ((e = sipg_diag64(a.op, d64, s))) return e;
+    if ((e = launch_mg_diag<T>(d64, a.v<T>(5), a.v<T>(6), a.N, s))) return e;
+    if (l + 1 < L) {
+      LzBufs<T> B{a.v<T>(6), a.v<T>(0), a.v<T>(1), a.v<T>(2), a.v<T>(3), v64};
+      double theta = 0;
+      if ((e = lanczos_max<T>(a.op, a.N, B, st, partials, prm.lanczos_steps, prm.seed + l, s, theta))) return e;
+      a.lambda = prm.lambda_safety * theta;
+      a.lo = a.lambda / prm.smoothing_range;
+      a.hi = a.lambda;
+      a.m = prm.cheb_degree;
+    } else {
+      std::vector<double> dh(a.N);
+      DGMF_HIP_TRY(hipMemcpyAsync(dh.data(), d64, sizeof(double) * a.N, hipMemcpyDeviceToHost, s));
+      DGMF_HIP_TRY(hipStreamSynchronize(s));
+      double tmin = 0, tmax = 0;
+      if ((e = coarse_interval(a, dh, prm.project_mean != 0, prm.seed + l, v64, d64, s, tmin, tmax))) return e;
+      a.lo = tmin / prm.lambda_safety;
+      a.hi = prm.lambda_safety * tmax;
+      a.lambda = a.hi;
+      const double sigma = (a.hi + a.lo) / (a.hi - a.lo);
+      const double m = std::ceil(std::acosh(1.0 / coarse_tol(prm)) / std::acosh(sigma));
+      if (!(m <= kMaxCoarseDegree))
+        return fail(DGMF_UNSUPPORTED, "multigrid: coarse Chebyshev would need %g steps (limit %d)", m,
+                    kMaxCoarseDegree);
+      a.m = std::max(1, static_cast<int>(m));
+    }
+    cheb_coeffs(a.lo, a.hi, a.m, a.inv_theta, a.c1, a.c2);
+  }
+  DGMF_HIP_TRY(hipStreamSynchronize(s));
+  out = guard.release();
+  return DGMF_OK;
+}
+
+dgmf_status mg_ensure(dgmf_op op, const dgmf_cg_params& prm, hipStream_t s) {
+  if (op->mgh && mg_same(op->mgh->key, prm)) return DGMF_OK;
+  if (op->mgh) {
+    mg_destroy(op->mgh);
+    op->mgh = nullptr;
+  }
+  MgHierarchy* h = nullptr;
+  dgmf_status e = prm.precond_dtype == DGMF_F32 ? mg_build<float>(op, prm, s, h) : mg_build<double>(op, prm, s, h);
+  if (e) return e;
+  op->mgh = h;
+  return DGMF_OK;
+}
+
+// x_l = V-cycle(b_l) on level l (Sec. 5.1): pre-smoothing from zero, residual
+// restricted to the next level, its V-cycle prolongated and added,
+// post-smoothing from the corrected x; the coarsest level runs the coarse
+// Chebyshev from zero.
+template <typename T>
+dgmf_status vcycle(MgHierarchy& h, int l, const int* stop, hipStream_t s) {
+  MgLevel& a = h.lv[l];
+  const int L = static_cast<int>(h.lv.size());
+  const int n = a.mesh->tab.n;
+  T* b = a.v<T>(0);
+  T* x = a.v<T>(1);
+  T* res = a.v<T>(2);
+  T* d = a.v<T>(3);
+  T* t = a.v<T>(4);
+  const T* dinv = a.v<T>(5);
+  auto cheb = [&](bool from_x) -> dgmf_status {
+    dgmf_status e = DGMF_OK;
+    if (from_x) {
+      if ((e = sipg_apply<T>(a.op, x, t, nullptr, stop, s))) return e;
+      if ((e = launch_mg_first<T>(b, t, res, d, x, dinv, a.inv_theta, true, a.N, stop, s))) return e;
+    } else if ((e = launch_mg_first<T>(b, nullptr, res, d, x, dinv, a.inv_theta, false, a.N, stop, s))) {
+      return e;
+    }
+    for (int j = 1; j < a.m; ++j) {
+      if ((e = sipg_apply<T>(a.op, d, t, nullptr, stop, s))) return e;
+      if ((e = launch_mg_step<T>(res, d, x, t, dinv, a.c1[j], a.c2[j], a.N, stop, s))) return e;
+    }
+    return DGMF_OK;
+  };
+  dgmf_status e = cheb(false);
+  if (e || l == L - 1) return e;
+  MgLevel& c = h.lv[l + 1];
+  if ((e = sipg_apply<T>(a.op, x, t, nullptr, stop, s))) return e;
+  if ((e = launch_mg_restrict<T>(n, a.xf, b, t, c.v<T>(0), static_cast<const T*>(a.etab.p), stop, s))) return e;
+  if ((e = vcycle<T>(h, l + 1, stop, s))) return e;
+  if ((e = launch_mg_prolong<T>(n, a.xf, c.v<T>(1), x, static_cast<const T*>(a.etab.p), stop, s))) return e;
+  return cheb(true);
 }
 
 struct Solver {
@@ -500,62 +905,12 @@ struct Solver {
   // Lanczos in precision T on D^{-1/2} H D^{-1/2}; fills lambda and the Chebyshev coefficients.
   template <typename T>
   dgmf_status lanczos_and_coeffs() {
-    const int m = prm.lanczos_steps;
-    T* dsq = at<T>(L.cdsq);
-    T* v = at<T>(L.cres);
-    T* vp = at<T>(L.cd);
-    T* w = at<T>(L.czc);
-    T* t = at<T>(L.ct);
-    double* v64 = at<double>(L.v64);
-    const dim3 G(kVecBlocks), B(256);
-    hipLaunchKernelGGL(k_splitmix_uniform, G, B, 0, s, v64, static_cast<uint64_t>(prm.seed), N, partials);
-    DGMF_LAUNCH_CHECK("k_splitmix_uniform");
-    dgmf_status e = scalar(M_LZ_MEAN, kVecBlocks, 0, 0);
+    LzBufs<T> B{at<T>(L.cdsq), at<T>(L.cres), at<T>(L.cd), at<T>(L.czc), at<T>(L.ct), at<double>(L.v64)};
+    double theta = 0;
+    dgmf_status e = lanczos_max<T>(op, N, B, st, partials, prm.lanczos_steps, prm.seed, s, theta);
     if (e) return e;
-    hipLaunchKernelGGL(k_lz_center, G, B, 0, s, v64, N, st, partials);
-    DGMF_LAUNCH_CHECK("k_lz_center");
-    if ((e = scalar(M_LZ_NORM, kVecBlocks, 0, 0))) return e;
-    hipLaunchKernelGGL((k_lz_start<T>), G, B, 0, s, v64, v, vp, N, st);
-    DGMF_LAUNCH_CHECK("k_lz_start");
-    for (int j = 0; j < m; ++j) {
-      hipLaunchKernelGGL((k_lz_scale<T>), G, B, 0, s, v, dsq, t, N);
-      DGMF_LAUNCH_CHECK("k_lz_scale");
-      if ((e = sipg_apply<T>(op, t, w, nullptr, nullptr, s))) return e;
-      hipLaunchKernelGGL((k_lz_w<T>), G, B, 0, s, w, dsq, v, vp, N, st, j, partials);
-      DGMF_LAUNCH_CHECK("k_lz_w");
-      if ((e = scalar(M_LZ_ALPHA, kVecBlocks, j, 0))) return e;
-      hipLaunchKernelGGL((k_lz_orth<T>), G, B, 0, s, w, v, N, st, j, partials);
-      DGMF_LAUNCH_CHECK("k_lz_orth");
-      if ((e = scalar(M_LZ_BETA, kVecBlocks, j, 0))) return e;
-      hipLaunchKernelGGL((k_lz_next<T>), G, B, 0, s, w, vp, N, st, j);
-      DGMF_LAUNCH_CHECK("k_lz_next");
-      T* tmp = v; v = vp; vp = tmp;
-    }
-    double ha[kMaxLanczos], hb[kMaxLanczos];
-    DGMF_HIP_TRY(hipMemcpyAsync(ha, st->lz_alpha, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    DGMF_HIP_TRY(hipMemcpyAsync(hb, st->lz_beta, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    DGMF_HIP_TRY(hipStreamSynchronize(s));
-    int mm = m;
-    for (int j = 0; j < m; ++j) {
-      if (!std::isfinite(ha[j])) { mm = j; break; }
-      if (j < m - 1 && !(hb[j] > 0)) { mm = j + 1; break; }
-    }
-    if (mm < 1) return fail(DGMF_NONFINITE, "cg: eigenvalue estimate is not finite");
-    const double theta = tridiag_max_eig(ha, hb, mm);
-    if (!(theta > 0) || !std::isfinite(theta)) return fail(DGMF_BREAKDOWN, "cg: eigenvalue estimate %g <= 0", theta);
     lambda = prm.lambda_safety * theta;
-    const double a = lambda / prm.smoothing_range, b = lambda;
-    const double th = 0.5 * (a + b), de = 0.5 * (b - a), sigma = th / de;
-    cheb_inv_theta = 1.0 / th;
-    double rho = 1.0 / sigma;
-    c1.assign(prm.cheb_degree, 0.0);
-    c2.assign(prm.cheb_degree, 0.0);
-    for (int j = 1; j < prm.cheb_degree; ++j) {
-      const double rn = 1.0 / (2.0 * sigma - rho);
-      c1[j] = rn * rho;
-      c2[j] = 2.0 * rn / de;
-      rho = rn;
-    }
+    cheb_coeffs(lambda / prm.smoothing_range, lambda, prm.cheb_degree, cheb_inv_theta, c1, c2);
     return DGMF_OK;
   }
 
@@ -582,7 +937,22 @@ struct Solver {
     return DGMF_OK;
   }
 
+  // z64 = V-cycle(r64) in precision T, with the same partials.
+  template <typename T>
+  dgmf_status mg_apply(const double* r, double* z, const double* q) {
+    MgLevel& a = op->mgh->lv[0];
+    dgmf_status e = launch_mg_cast_in<T>(r, a.v<T>(0), N, &st->status, s);
+    if (e || (e = vcycle<T>(*op->mgh, 0, &st->status, s))) return e;
+    hipLaunchKernelGGL((k_mg_out<T>), dim3(kVecBlocks), dim3(256), 0, s, a.v<T>(1), r, z, q, N, st, partials);
+    DGMF_LAUNCH_CHECK("k_mg_out");
+    return DGMF_OK;
+  }
+
   dgmf_status precond(const double* r, double* z, const double* q) {
+    if (prm.precond == 2) {
+      if (prm.precond_dtype == DGMF_F32) return mg_apply<float>(r, z, q);
+      return mg_apply<double>(r, z, q);
+    }
     if (prm.precond_dtype == DGMF_F32) return cheb_apply<float>(r, z, q);
     return cheb_apply<double>(r, z, q);
   }
@@ -615,6 +985,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
     return fail(DGMF_INVALID, "cg_solve: misaligned argument (vectors 8 B, workspace 256 B)");
   const int64_t N = op->mesh->ndofs;
   const bool cheb = params->precond == 1;
+  const bool poly = params->precond != 0;   // preconditioner kernels write z and the partials
   const size_t es = params->precond_dtype == DGMF_F32 ? 4 : 8;
   Layout L = make_layout(N, nparts_for(op), cheb, es);
   if (workspace_bytes < L.total)
@@ -678,6 +1049,12 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
       return e;
     }
     out->lambda_max = S.lambda;
+  } else if (params->precond == 2) {
+    if ((e = mg_ensure(op, *params, stream))) {
+      out->status = e;
+      return e;
+    }
+    out->lambda_max = op->mgh->lv[0].lambda;
   }
   // ---- initial residual
   hipLaunchKernelGGL(k_bsum, G, B, 0, stream, b, x, N, S.partials);
@@ -690,7 +1067,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
   DGMF_LAUNCH_CHECK("k_set_tol");
   if ((e = sipg_apply<double>(op, x, q, S.partials, nullptr, stream))) return e;
   if ((e = S.scalar(M_QMEAN, napply, 0, 0))) return e;
-  if (cheb) {
+  if (poly) {
     hipLaunchKernelGGL(k_init_r, G, B, 0, stream, bp, q, r, dinv, static_cast<double*>(nullptr), N, S.st,
                        S.partials);
     DGMF_LAUNCH_CHECK("k_init_r");
@@ -713,10 +1090,10 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
     for (int k = 0; k < batch; ++k) {
       if ((e = S.apply<double>(p, q, true))) return e;
       if ((e = S.scalar(M_ALPHA, napply))) return e;
-      hipLaunchKernelGGL(k_update, G, B, 0, stream, x, r, p, q, dinv, cheb ? static_cast<double*>(nullptr) : z, N,
+      hipLaunchKernelGGL(k_update, G, B, 0, stream, x, r, p, q, dinv, poly ? static_cast<double*>(nullptr) : z, N,
                          S.st, S.partials);
       DGMF_LAUNCH_CHECK("k_update");
-      if (cheb && (e = S.precond(r, z, q))) return e;
+      if (poly && (e = S.precond(r, z, q))) return e;
       if ((e = S.scalar(M_BETA, kVecBlocks))) return e;
       hipLaunchKernelGGL(k_update_p, G, B, 0, stream, p, z, N, S.st, 0);
       DGMF_LAUNCH_CHECK("k_update_p");
@@ -735,6 +1112,55 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
                                   "UNSUPPORTED"};
     return fail(static_cast<dgmf_status>(out->status), "cg_solve: %s after %d iterations (rel. residual %g)",
                 names[out->status], out->iterations, out->rel_residual);
+  }
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_precond_apply(dgmf_op op, const dgmf_cg_params* params, const double* r, double* z,
+                               hipStream_t stream) {
+  dgmf_status e = validate(op, params);
+  if (e) return e;
+  if (params->precond != 2) return fail(DGMF_UNSUPPORTED, "precond_apply: only precond = 2 (multigrid) is exposed");
+  if (!r || !z) return fail(DGMF_INVALID, "precond_apply: null vector");
+  if (reinterpret_cast<uintptr_t>(r) % 8 || reinterpret_cast<uintptr_t>(z) % 8)
+    return fail(DGMF_INVALID, "precond_apply: misaligned vector");
+  const int64_t N = op->mesh->ndofs;
+  {
+    const char* a = reinterpret_cast<const char*>(r);
+    const char* b = reinterpret_cast<const char*>(z);
+    if (a < b + 8 * N && b < a + 8 * N) return fail(DGMF_INVALID, "precond_apply: r and z overlap");
+  }
+  int prev_dev = -1;
+  (void)hipGetDevice(&prev_dev);
+  if (prev_dev != op->mesh->device) DGMF_HIP_TRY(hipSetDevice(op->mesh->device));
+  struct Restore {
+    int d;
+    ~Restore() { if (d >= 0) (void)hipSetDevice(d); }
+  } restore{prev_dev != op->mesh->device ? prev_dev : -1};
+  if ((e = mg_ensure(op, *params, stream))) return e;
+  MgLevel& a = op->mgh->lv[0];
+  if (params->precond_dtype == DGMF_F32) {
+    if ((e = launch_mg_cast_in<float>(r, a.v<float>(0), N, nullptr, stream))) return e;
+    if ((e = vcycle<float>(*op->mgh, 0, nullptr, stream))) return e;
+    return launch_mg_cast_out<float>(a.v<float>(1), z, N, stream);
+  }
+  if ((e = launch_mg_cast_in<double>(r, a.v<double>(0), N, nullptr, stream))) return e;
+  if ((e = vcycle<double>(*op->mgh, 0, nullptr, stream))) return e;
+  return launch_mg_cast_out<double>(a.v<double>(1), z, N, stream);
+}
+
+dgmf_status dgmf_precond_info(dgmf_op op, int* levels, double* lambdas, int* coarse_degree, double* coarse_interval) {
+  if (!op || op->kind != 1) return fail(DGMF_INVALID, "precond_info: not an SIPG operator");
+  if (!op->mgh) return fail(DGMF_INVALID, "precond_info: no multigrid hierarchy has been built on this operator");
+  const auto& lv = op->mgh->lv;
+  const int L = static_cast<int>(lv.size());
+  if (levels) *levels = L;
+  if (lambdas)
+    for (int l = 0; l < L; ++l) lambdas[l] = lv[l].lambda;
+  if (coarse_degree) *coarse_degree = lv[L - 1].m;
+  if (coarse_interval) {
+    coarse_interval[0] = lv[L - 1].lo;
+    coarse_interval[1] = lv[L - 1].hi;
   }
   return DGMF_OK;
 }

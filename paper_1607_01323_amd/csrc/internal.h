@@ -209,6 +209,39 @@ dgmf_status launch_inverse_mass(int n, const CartGeom<T>& g, T jscale, const T* 
 // S^{-1} W^{-1} S^{-T}, row-major n x n; false when S is singular.
 bool inverse_mass_1d(const Tables1D& t, std::vector<double>& out);
 
+// Geometric multigrid transfers between a fine box mesh and the mesh with
+// every even cell count halved: coarse counts, fine counts in x and y, and
+// the ratio (1 or 2) per direction.  The transfer table holds, per direction
+// d and child s, the n x n matrix E_d[s][i][a] = l_a((s + xi_i) / 2) (the
+// identity in E_d[0] when direction d is not halved): [d][s][i][a].
+struct MgXfer {
+  int cnx, cny, cnz;
+  int fnx, fny;
+  int r[3];
+};
+template <typename T>
+dgmf_status launch_mg_prolong(int n, const MgXfer& x, const T* xc, T* xf, const T* etab, const int* stop,
+                              hipStream_t s);   // xf += P xc
+template <typename T>
+dgmf_status launch_mg_restrict(int n, const MgXfer& x, const T* bf, const T* tf, T* bc, const T* etab,
+                               const int* stop, hipStream_t s);   // bc = P^T (bf - tf)
+template <typename T>
+dgmf_status launch_mg_cast_in(const double* r, T* b, int64_t N, const int* stop, hipStream_t s);
+template <typename T>
+dgmf_status launch_mg_cast_out(const T* x, double* z, int64_t N, hipStream_t s);
+// Chebyshev-Jacobi pieces: first (res = b - t, d = dinv res inv_theta, x = d or x + d) and step
+template <typename T>
+dgmf_status launch_mg_first(const T* b, const T* t, T* res, T* d, T* x, const T* dinv, double inv_theta,
+                            bool accumulate, int64_t N, const int* stop, hipStream_t s);
+template <typename T>
+dgmf_status launch_mg_step(T* res, T* d, T* x, const T* t, const T* dinv, double c1, double c2, int64_t N,
+                           const int* stop, hipStream_t s);
+template <typename T>
+dgmf_status launch_mg_diag(const double* diag, T* dinv, T* dsq, int64_t N, hipStream_t s);
+// Cached multigrid hierarchy of an SIPG operator (built by the CG code).
+struct MgHierarchy;
+void mg_destroy(MgHierarchy* h);
+
 // Dispatch over the two SIPG apply kernels (tables of axis-aligned cells or
 // metric stored at the quadrature points), and the number of partial rows the
 // apply writes.
@@ -254,4 +287,5 @@ struct dgmf_op_ {
   dgmf::MetricGeom<double> mg64{};   // metric path (mesh->desc.store_qp_metric)
   dgmf::MetricGeom<float> mg32{};
   bool metric = false;
+  dgmf::MgHierarchy* mgh = nullptr;   // multigrid levels, built on first use
 };

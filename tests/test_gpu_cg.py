@@ -106,8 +106,8 @@ def test_chebyshev_preconditioned_cg(pdtype):
                  project_mean=True, raise_on_failure=False)
     tol_lam = 1e-9 if pdtype == torch.float64 else 1e-3
     assert abs(out.lambda_max - lam_oracle) < tol_lam * lam_oracle
-    lam = out.lambda_max   # the oracle runs the same preconditioner
-    P = lambda r: solvers.chebyshev_jacobi(lambda u: A @ u, dinv, r, lam, 20.0, 5)
+    # the oracle runs its own preconditioner (its own lambda), never the GPU's
+    P = lambda r: solvers.chebyshev_jacobi(lambda u: A @ u, dinv, r, lam_oracle, 20.0, 5)
     flex = pdtype == torch.float32          # the binding's default: flexible beta with an fp32 preconditioner
     xr, _, _, _ = solvers.pcg(lambda v: A @ v, b, x0, P, 1e-30, 10, project_mean=True, flexible=flex)
     assert rel_err(host(xg), xr) < (1e-11 if pdtype == torch.float64 else 1e-4)
