@@ -111,7 +111,7 @@ def main():
     value = N / t
     alg_bytes = 16.0 * N
     achieved = alg_bytes / t / 1e9
-    kernel = "k_sipg_zm_apply<5, double, true, true>"
+    kernel = "k_sipg_zm_apply<5, double, true, true, false>"
     traffic = _traffic(kernel)
     line = {
         "metric": "SIPG apply DoF/s (fp64, Helmholtz)", "value": value, "unit": "DoF/s", "n_gpus": 1,
@@ -195,7 +195,8 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     # the configured smooth right-hand side (nearly one eigenmode) and a random one
     b_rand = torch.as_tensor(inp.uniform(5, N2), device="cuda")
     for rhs_name, b2 in (("sinrhs", b_sin), ("randrhs", b_rand)):
-        for name, kw in (("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
+        for name, kw in (("mixed_f32mg", dict(precond="multigrid", precond_dtype=torch.float32)),
+                         ("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
                          ("f64cheb", dict(precond="chebyshev", precond_dtype=torch.float64)),
                          ("jacobi_f64", dict(precond="jacobi"))):
             best = None
@@ -300,7 +301,8 @@ def channel_measurements(dg, inp, torch, w, tag, cg=True):
         del qp
         b = op.integrate(fq)
         del fq
-        for name, kw in (("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
+        for name, kw in (("mixed_f32mg", dict(precond="multigrid", precond_dtype=torch.float32)),
+                         ("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
                          ("f64cheb", dict(precond="chebyshev", precond_dtype=torch.float64)),
                          ("jacobi_f64", dict(precond="jacobi"))):
             best = None

@@ -668,6 +668,19 @@ dgmf_status sipg_apply(dgmf_op op, const T* src, T* dst, double* partials, const
 template dgmf_status sipg_apply<double>(dgmf_op, const double*, double*, double*, const int*, hipStream_t);
 template dgmf_status sipg_apply<float>(dgmf_op, const float*, float*, double*, const int*, hipStream_t);
 
+template <typename T>
+dgmf_status sipg_cheb(dgmf_op op, const T* xk, T* dst, const ChebEpi<T>& epi, const int* stop, hipStream_t s) {
+  const int n = op->mesh->desc.degree + 1;
+  if (op->metric) return DGMF_UNSUPPORTED;
+  if constexpr (std::is_same<T, double>::value)
+    return launch_sipg_cart_cheb<double>(n, op->g64, xk, dst, epi, stop, s);
+  else
+    return launch_sipg_cart_cheb<float>(n, op->g32, xk, dst, epi, stop, s);
+}
+template dgmf_status sipg_cheb<double>(dgmf_op, const double*, double*, const ChebEpi<double>&, const int*,
+                                       hipStream_t);
+template dgmf_status sipg_cheb<float>(dgmf_op, const float*, float*, const ChebEpi<float>&, const int*, hipStream_t);
+
 dgmf_status sipg_diag64(dgmf_op op, double* diag, hipStream_t s) {
   const int n = op->mesh->desc.degree + 1;
   if (op->metric) return launch_sipg_metric_diag<double>(n, op->mg64, diag, s);

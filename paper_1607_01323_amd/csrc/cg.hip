@@ -583,9 +583,10 @@ __global__ void __launch_bounds__(256) k_mg_out(const T* __restrict__ x, const d
 
 // ---------------------------------------------------------- multigrid ---
 // One level of the hierarchy: its mesh and operator (the caller's on the
-// finest level), seven vectors in the preconditioner precision (b, x, res,
-// d, t, dinv, dsq), the transfer to the next coarser level, and the
-// Chebyshev parameters of its smoother (or of the coarse solver).
+// finest level), seven vectors in the preconditioner precision (b, two
+// alternating iterates, one spare used by the set-up, t = H x, dinv, dsq),
+// the transfer to the next coarser level, and the Chebyshev parameters of its
+// smoother (or of the coarse solver).
 struct MgLevel {
   dgmf_mesh mesh = nullptr;
   dgmf_op op = nullptr;
@@ -596,6 +597,7 @@ struct MgLevel {
   DevBuf vec, etab;
   double lambda = 0, lo = 0, hi = 0, inv_theta = 0;
   int m = 0;
+  int xout = 1;   // buffer (1 or 2) that holds the last V-cycle result
   std::vector<double> c1, c2;
   template <typename T>
   T* v(int k) { return static_cast<T*>(vec.p) + k * N; }
@@ -835,43 +837,74 @@ dgmf_status mg_ensure(dgmf_op op, const dgmf_cg_params& prm, hipStream_t s) {
   return DGMF_OK;
 }
 
+// One Chebyshev-Jacobi step on level a: buffer dst (holding x_{k-1}) becomes
+// x_{k+1} from x_k in buffer src; fused into the apply where the operator
+// allows it, else an apply into t and a vector update.
+template <typename T>
+dgmf_status cheb_step(MgLevel& a, int src, int dst, double c1, double c2, bool prev_zero, const int* stop,
+                      hipStream_t s) {
+  const T* b = a.v<T>(0);
+  const T* dinv = a.v<T>(5);
+  const ChebEpi<T> epi{b, dinv, static_cast<T>(c1), static_cast<T>(c2), prev_zero ? 1 : 0};
+  dgmf_status e = sipg_cheb<T>(a.op, a.v<T>(src), a.v<T>(dst), epi, stop, s);
+  if (e != DGMF_UNSUPPORTED) return e;
+  clear_error();
+  T* t = a.v<T>(4);
+  if ((e = sipg_apply<T>(a.op, a.v<T>(src), t, nullptr, stop, s))) return e;
+  return launch_mg_cheb_vec<T>(a.v<T>(src), a.v<T>(dst), b, t, dinv, c1, c2, prev_zero, a.N, stop, s);
+}
+
+// Chebyshev smoothing (or the coarse solve) on level a, from zero or from the
+// iterate in buffer cur; on return cur names the buffer holding the result.
+// Buffers 1 and 2 alternate as x_k and x_{k-1}.
+template <typename T>
+dgmf_status smooth(MgLevel& a, bool from_zero, int& cur, const int* stop, hipStream_t s) {
+  dgmf_status e = DGMF_OK;
+  int prev = 3 - cur;
+  bool prev_zero = true;
+  if (from_zero) {
+    if ((e = launch_mg_jacobi<T>(a.v<T>(0), a.v<T>(5), a.v<T>(cur), a.inv_theta, a.N, stop, s))) return e;
+  } else {
+    // x_1 = x_0 + dinv (b - H x_0) / theta into the other buffer
+    if ((e = cheb_step<T>(a, cur, prev, 0.0, a.inv_theta, true, stop, s))) return e;
+    std::swap(cur, prev);
+    prev_zero = false;
+  }
+  for (int j = 1; j < a.m; ++j) {
+    if ((e = cheb_step<T>(a, cur, prev, a.c1[j], a.c2[j], prev_zero, stop, s))) return e;
+    std::swap(cur, prev);
+    prev_zero = false;
+  }
+  return DGMF_OK;
+}
+
 // x_l = V-cycle(b_l) on level l (Sec. 5.1): pre-smoothing from zero, residual
 // restricted to the next level, its V-cycle prolongated and added,
 // post-smoothing from the corrected x; the coarsest level runs the coarse
-// Chebyshev from zero.
+// Chebyshev from zero.  The result is left in buffer a.xout.
 template <typename T>
 dgmf_status vcycle(MgHierarchy& h, int l, const int* stop, hipStream_t s) {
   MgLevel& a = h.lv[l];
   const int L = static_cast<int>(h.lv.size());
-  const int n = a.mesh->tab.n;
-  T* b = a.v<T>(0);
-  T* x = a.v<T>(1);
-  T* res = a.v<T>(2);
-  T* d = a.v<T>(3);
-  T* t = a.v<T>(4);
-  const T* dinv = a.v<T>(5);
-  auto cheb = [&](bool from_x) -> dgmf_status {
-    dgmf_status e = DGMF_OK;
-    if (from_x) {
-      if ((e = sipg_apply<T>(a.op, x, t, nullptr, stop, s))) return e;
-      if ((e = launch_mg_first<T>(b, t, res, d, x, dinv, a.inv_theta, true, a.N, stop, s))) return e;
-    } else if ((e = launch_mg_first<T>(b, nullptr, res, d, x, dinv, a.inv_theta, false, a.N, stop, s))) {
-      return e;
-    }
-    for (int j = 1; j < a.m; ++j) {
-      if ((e = sipg_apply<T>(a.op, d, t, nullptr, stop, s))) return e;
-      if ((e = launch_mg_step<T>(res, d, x, t, dinv, a.c1[j], a.c2[j], a.N, stop, s))) return e;
-    }
+  int cur = 1;
+  dgmf_status e = smooth<T>(a, true, cur, stop, s);
+  if (e) return e;
+  if (l == L - 1) {
+    a.xout = cur;
     return DGMF_OK;
-  };
-  dgmf_status e = cheb(false);
-  if (e || l == L - 1) return e;
+  }
   MgLevel& c = h.lv[l + 1];
-  if ((e = sipg_apply<T>(a.op, x, t, nullptr, stop, s))) return e;
-  if ((e = launch_mg_restrict<T>(n, a.xf, b, t, c.v<T>(0), static_cast<const T*>(a.etab.p), stop, s))) return e;
+  const int n = a.mesh->tab.n;
+  T* t = a.v<T>(4);
+  if ((e = sipg_apply<T>(a.op, a.v<T>(cur), t, nullptr, stop, s))) return e;
+  if ((e = launch_mg_restrict<T>(n, a.xf, a.v<T>(0), t, c.v<T>(0), static_cast<const T*>(a.etab.p), stop, s)))
+    return e;
   if ((e = vcycle<T>(h, l + 1, stop, s))) return e;
-  if ((e = launch_mg_prolong<T>(n, a.xf, c.v<T>(1), x, static_cast<const T*>(a.etab.p), stop, s))) return e;
-  return cheb(true);
+  if ((e = launch_mg_prolong<T>(n, a.xf, c.v<T>(c.xout), a.v<T>(cur), static_cast<const T*>(a.etab.p), stop, s)))
+    return e;
+  if ((e = smooth<T>(a, false, cur, stop, s))) return e;
+  a.xout = cur;
+  return DGMF_OK;
 }
 
 struct Solver {
@@ -943,7 +976,7 @@ struct Solver {
     MgLevel& a = op->mgh->lv[0];
     dgmf_status e = launch_mg_cast_in<T>(r, a.v<T>(0), N, &st->status, s);
     if (e || (e = vcycle<T>(*op->mgh, 0, &st->status, s))) return e;
-    hipLaunchKernelGGL((k_mg_out<T>), dim3(kVecBlocks), dim3(256), 0, s, a.v<T>(1), r, z, q, N, st, partials);
+    hipLaunchKernelGGL((k_mg_out<T>), dim3(kVecBlocks), dim3(256), 0, s, a.v<T>(a.xout), r, z, q, N, st, partials);
     DGMF_LAUNCH_CHECK("k_mg_out");
     return DGMF_OK;
   }
@@ -1142,11 +1175,11 @@ dgmf_status dgmf_precond_apply(dgmf_op op, const dgmf_cg_params* params, const d
   if (params->precond_dtype == DGMF_F32) {
     if ((e = launch_mg_cast_in<float>(r, a.v<float>(0), N, nullptr, stream))) return e;
     if ((e = vcycle<float>(*op->mgh, 0, nullptr, stream))) return e;
-    return launch_mg_cast_out<float>(a.v<float>(1), z, N, stream);
+    return launch_mg_cast_out<float>(a.v<float>(a.xout), z, N, stream);
   }
   if ((e = launch_mg_cast_in<double>(r, a.v<double>(0), N, nullptr, stream))) return e;
   if ((e = vcycle<double>(*op->mgh, 0, nullptr, stream))) return e;
-  return launch_mg_cast_out<double>(a.v<double>(1), z, N, stream);
+  return launch_mg_cast_out<double>(a.v<double>(a.xout), z, N, stream);
 }
 
 dgmf_status dgmf_precond_info(dgmf_op op, int* levels, double* lambdas, int* coarse_degree, double* coarse_interval) {

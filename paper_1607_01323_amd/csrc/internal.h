@@ -162,6 +162,22 @@ dgmf_status launch_qp_coords(int n, int nq, const CartGeom<double>& g, const She
 dgmf_status launch_integrate(int n, int nq, const CartGeom<double>& g, const Shear& sh, const double* f, double* b,
                              int64_t ncells, hipStream_t s);
 
+// Chebyshev-Jacobi step fused into the store of an operator apply: with x_k
+// the apply's input and y = H x_k, the kernel overwrites dst (holding x_{k-1})
+// with x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 dinv (b - y); prev_zero reads
+// x_{k-1} as zero (Saad, Iterative Methods for Sparse Linear Systems,
+// Alg. 12.1 written as a three-term recurrence on x).
+template <typename T>
+struct ChebEpi {
+  const T* b;
+  const T* dinv;
+  T c1, c2;
+  int prev_zero;
+};
+template <typename T>
+dgmf_status launch_sipg_cart_cheb(int n, const CartGeom<T>& g, const T* xk, T* dst, const ChebEpi<T>& epi,
+                                  const int* stop, hipStream_t s);
+
 // Operator apply; when partials is not null, also writes per-block partial
 // sums of <src, dst>, sum(dst) and sum(src) to partials[4*block + 0..2].
 // stop: optional device flag; when non-zero the launch does nothing (used by
@@ -229,15 +245,16 @@ template <typename T>
 dgmf_status launch_mg_cast_in(const double* r, T* b, int64_t N, const int* stop, hipStream_t s);
 template <typename T>
 dgmf_status launch_mg_cast_out(const T* x, double* z, int64_t N, hipStream_t s);
-// Chebyshev-Jacobi pieces: first (res = b - t, d = dinv res inv_theta, x = d or x + d) and step
-template <typename T>
-dgmf_status launch_mg_first(const T* b, const T* t, T* res, T* d, T* x, const T* dinv, double inv_theta,
-                            bool accumulate, int64_t N, const int* stop, hipStream_t s);
-template <typename T>
-dgmf_status launch_mg_step(T* res, T* d, T* x, const T* t, const T* dinv, double c1, double c2, int64_t N,
-                           const int* stop, hipStream_t s);
 template <typename T>
 dgmf_status launch_mg_diag(const double* diag, T* dinv, T* dsq, int64_t N, hipStream_t s);
+// x = scale dinv b
+template <typename T>
+dgmf_status launch_mg_jacobi(const T* b, const T* dinv, T* x, double scale, int64_t N, const int* stop,
+                             hipStream_t s);
+// dst = xk + c1 (xk - dst) + c2 dinv (b - t)  (dst read as zero when prev_zero)
+template <typename T>
+dgmf_status launch_mg_cheb_vec(const T* xk, T* dst, const T* b, const T* t, const T* dinv, double c1, double c2,
+                               bool prev_zero, int64_t N, const int* stop, hipStream_t s);
 // Cached multigrid hierarchy of an SIPG operator (built by the CG code).
 struct MgHierarchy;
 void mg_destroy(MgHierarchy* h);
@@ -248,6 +265,10 @@ void mg_destroy(MgHierarchy* h);
 template <typename T>
 dgmf_status sipg_apply(dgmf_op op, const T* src, T* dst, double* partials, const int* stop, hipStream_t s);
 dgmf_status sipg_diag64(dgmf_op op, double* diag, hipStream_t s);
+// The fused apply + Chebyshev step on axis-aligned operators; DGMF_UNSUPPORTED
+// for operators with the stored metric (callers then apply and update apart).
+template <typename T>
+dgmf_status sipg_cheb(dgmf_op op, const T* xk, T* dst, const ChebEpi<T>& epi, const int* stop, hipStream_t s);
 int64_t sipg_apply_blocks(dgmf_op op);
 
 }  // namespace dgmf

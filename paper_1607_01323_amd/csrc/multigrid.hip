@@ -14,10 +14,11 @@
 // read or written once; a mother owns its children, so no atomics.
 //
 // The smoother and the coarse solver are Chebyshev accelerations of point
-// Jacobi (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1):
-//   first:  res = b - t (t = A x or nothing), d = dinv res / theta,
-//           x = d (zero start) or x + d;
-//   step:   res -= A d, d = c1 d + c2 dinv res, x += d.
+// Jacobi (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1) in
+// three-term form on the iterate: x_1 = x_0 + dinv (b - A x_0) / theta and
+//   x_{k+1} = x_k + c1_k (x_k - x_{k-1}) + c2_k dinv (b - A x_k);
+// on axis-aligned levels the update is fused into the apply kernel's store,
+// elsewhere k_mg_cheb_vec applies it after a plain apply.
 #include "internal.h"
 
 namespace dgmf {
@@ -185,31 +186,24 @@ __global__ void __launch_bounds__(256) k_mg_cast_in(const double* __restrict__ r
   MG_GRID_STRIDE(i, N) b[i] = static_cast<T>(r[i]);
 }
 
+// x = s dinv b: the first Chebyshev iterate from zero
 template <typename T>
-__global__ void __launch_bounds__(256) k_mg_first(const T* __restrict__ b, const T* __restrict__ t, T* __restrict__ res,
-                                                  T* __restrict__ d, T* __restrict__ x, const T* __restrict__ dinv,
-                                                  T inv_theta, int accumulate, int64_t N, const int* stop) {
+__global__ void __launch_bounds__(256) k_mg_jacobi(const T* __restrict__ b, const T* __restrict__ dinv,
+                                                   T* __restrict__ x, T s, int64_t N, const int* stop) {
   if (stop && *stop) return;
-  MG_GRID_STRIDE(i, N) {
-    const T ri = t ? b[i] - t[i] : b[i];
-    const T di = dinv[i] * ri * inv_theta;
-    res[i] = ri;
-    d[i] = di;
-    x[i] = accumulate ? x[i] + di : di;
-  }
+  MG_GRID_STRIDE(i, N) x[i] = s * dinv[i] * b[i];
 }
 
+// dst = xk + c1 (xk - dst) + c2 dinv (b - t), t = H xk (dst read as zero when prev_zero)
 template <typename T>
-__global__ void __launch_bounds__(256) k_mg_step(T* __restrict__ res, T* __restrict__ d, T* __restrict__ x,
-                                                 const T* __restrict__ t, const T* __restrict__ dinv, T c1, T c2,
-                                                 int64_t N, const int* stop) {
+__global__ void __launch_bounds__(256) k_mg_cheb_vec(const T* __restrict__ xk, T* __restrict__ dst,
+                                                     const T* __restrict__ b, const T* __restrict__ t,
+                                                     const T* __restrict__ dinv, T c1, T c2, int prev_zero, int64_t N,
+                                                     const int* stop) {
   if (stop && *stop) return;
   MG_GRID_STRIDE(i, N) {
-    const T ri = res[i] - t[i];
-    const T di = fma(c1, d[i], c2 * dinv[i] * ri);
-    res[i] = ri;
-    d[i] = di;
-    x[i] += di;
+    const T x = xk[i], p = prev_zero ? T(0) : dst[i];
+    dst[i] = fma(c2 * dinv[i], b[i] - t[i], fma(c1, x - p, x));
   }
 }
 
@@ -297,20 +291,20 @@ dgmf_status launch_mg_cast_out(const T* x, double* z, int64_t N, hipStream_t s) 
 }
 
 template <typename T>
-dgmf_status launch_mg_first(const T* b, const T* t, T* res, T* d, T* x, const T* dinv, double inv_theta,
-                            bool accumulate, int64_t N, const int* stop, hipStream_t s) {
-  hipLaunchKernelGGL((k_mg_first<T>), dim3(vec_grid(N)), dim3(256), 0, s, b, t, res, d, x, dinv,
-                     static_cast<T>(inv_theta), accumulate ? 1 : 0, N, stop);
-  DGMF_LAUNCH_CHECK("k_mg_first");
+dgmf_status launch_mg_jacobi(const T* b, const T* dinv, T* x, double scale, int64_t N, const int* stop,
+                             hipStream_t s) {
+  hipLaunchKernelGGL((k_mg_jacobi<T>), dim3(vec_grid(N)), dim3(256), 0, s, b, dinv, x, static_cast<T>(scale), N,
+                     stop);
+  DGMF_LAUNCH_CHECK("k_mg_jacobi");
   return DGMF_OK;
 }
 
 template <typename T>
-dgmf_status launch_mg_step(T* res, T* d, T* x, const T* t, const T* dinv, double c1, double c2, int64_t N,
-                           const int* stop, hipStream_t s) {
-  hipLaunchKernelGGL((k_mg_step<T>), dim3(vec_grid(N)), dim3(256), 0, s, res, d, x, t, dinv, static_cast<T>(c1),
-                     static_cast<T>(c2), N, stop);
-  DGMF_LAUNCH_CHECK("k_mg_step");
+dgmf_status launch_mg_cheb_vec(const T* xk, T* dst, const T* b, const T* t, const T* dinv, double c1, double c2,
+                               bool prev_zero, int64_t N, const int* stop, hipStream_t s) {
+  hipLaunchKernelGGL((k_mg_cheb_vec<T>), dim3(vec_grid(N)), dim3(256), 0, s, xk, dst, b, t, dinv, static_cast<T>(c1),
+                     static_cast<T>(c2), prev_zero ? 1 : 0, N, stop);
+  DGMF_LAUNCH_CHECK("k_mg_cheb_vec");
   return DGMF_OK;
 }
 
@@ -327,11 +321,10 @@ dgmf_status launch_mg_diag(const double* diag, T* dinv, T* dsq, int64_t N, hipSt
                                              hipStream_t);                                                         \
   template dgmf_status launch_mg_cast_in<T>(const double*, T*, int64_t, const int*, hipStream_t);                  \
   template dgmf_status launch_mg_cast_out<T>(const T*, double*, int64_t, hipStream_t);                             \
-  template dgmf_status launch_mg_first<T>(const T*, const T*, T*, T*, T*, const T*, double, bool, int64_t,         \
-                                          const int*, hipStream_t);                                                \
-  template dgmf_status launch_mg_step<T>(T*, T*, T*, const T*, const T*, double, double, int64_t, const int*,     \
-                                         hipStream_t);                                                             \
-  template dgmf_status launch_mg_diag<T>(const double*, T*, T*, int64_t, hipStream_t);
+  template dgmf_status launch_mg_diag<T>(const double*, T*, T*, int64_t, hipStream_t);                          \
+  template dgmf_status launch_mg_jacobi<T>(const T*, const T*, T*, double, int64_t, const int*, hipStream_t);     \
+  template dgmf_status launch_mg_cheb_vec<T>(const T*, T*, const T*, const T*, const T*, double, double, bool,    \
+                                             int64_t, const int*, hipStream_t);
 DGMF_MG_INST(double)
 DGMF_MG_INST(float)
 #undef DGMF_MG_INST

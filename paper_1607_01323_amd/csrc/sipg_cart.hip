@@ -357,12 +357,13 @@ struct ZmCtx {
 
 // One layer of the march.  W: z-line window (layer offset -1, 0, +1, and the
 // slot that receives layer +2).
-template <int N, typename T, bool PER, bool UNI>
+template <int N, typename T, bool PER, bool UNI, bool EPI>
 __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restrict__ dst, const CartGeom<T>& g,
                                          ZmCtx<N, T>& c, int cz, int z1, T* s_u, T* s_w, T* s_rim_next,
                                          const int* s_rimcol, cptr<T> tab, cptr<T> gh, cptr<T> ghinv,
                                          cptr<T> gtp, T& up_end, T& up_dot, const T (&uc)[N], const T (&un)[N],
-                                         T (&unn)[N], bool want_partials, double& pq, double& sq, double& sp) {
+                                         T (&unn)[N], bool want_partials, double& pq, double& sq, double& sp,
+                                         const ChebEpi<T>& epi) {
   using C = ZmCtx<N, T>;
   constexpr int N2 = C::N2, N3 = C::N3, P = C::P, NR = C::NR, RPT = C::RPT, TH = Zm<N>::THREADS;
   const int tid = threadIdx.x;
@@ -491,13 +492,28 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
   // pass 5: z-lines: dst = Mz w (coalesced store); the rim of the next layer goes to LDS
   if (c.act) {
     T w[N], o[N];
+    const int at = (cz * c.nxy + c.col) * N3 + c.zoff;
+    T* cd = dst + at;
+    T eb[N], ed[N], ep[N];
+    if constexpr (EPI) {   // issued before the sweep so that their latency overlaps it
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        eb[l] = epi.b[at + l * N2];
+        ed[l] = epi.dinv[at + l * N2];
+        ep[l] = epi.prev_zero ? T(0) : cd[l * N2];
+      }
+    }
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       w[l] = sw[(l * N + t1) * P + t0];
       o[l] = T(0);
     }
     matvec_acc<N, T>(tab, w, o);
-    T* cd = dst + (cz * c.nxy + c.col) * N3 + c.zoff;
+    if constexpr (EPI) {
+#pragma unroll
+      for (int l = 0; l < N; ++l)
+        o[l] = fma(epi.c2 * ed[l], eb[l] - o[l], fma(epi.c1, uc[l] - ep[l], uc[l]));
+    }
 #pragma unroll
     for (int l = 0; l < N; ++l) __builtin_nontemporal_store(o[l], cd + l * N2);
     if (want_partials) {
@@ -521,10 +537,11 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
   }
 }
 
-template <int N, typename T, bool PER, bool UNI>
+template <int N, typename T, bool PER, bool UNI, bool EPI>
 __global__ void __launch_bounds__(Zm<N>::THREADS) k_sipg_zm_apply(const T* __restrict__ src, T* __restrict__ dst,
                                                                  const CartGeom<T> g, const ZmPlan pl,
-                                                                 double* __restrict__ partials, const int* stop) {
+                                                                 double* __restrict__ partials, const int* stop,
+                                                                 const ChebEpi<T> epi) {
   if (stop && *stop) return;   // uniform for the whole grid: CG already finished
   using Z = Zm<N>;
   using C = ZmCtx<N, T>;
@@ -675,14 +692,14 @@ __global__ void __launch_bounds__(Zm<N>::THREADS) k_sipg_zm_apply(const T* __res
     T* const su = s_u[0];
 #pragma unroll 1
     for (int cz = z0; cz < z1; cz += 3) {
-      zm_layer<N, T, PER, UNI>(src, dst, g, c, cz, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv, gtp, up_end,
-                               up_dot, z[0], z[1], z[2], wp, pq, sq, sp);
+      zm_layer<N, T, PER, UNI, EPI>(src, dst, g, c, cz, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv, gtp,
+                                    up_end, up_dot, z[0], z[1], z[2], wp, pq, sq, sp, epi);
       if (cz + 1 < z1)
-        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 1, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv, gtp,
-                                 up_end, up_dot, z[1], z[2], z[0], wp, pq, sq, sp);
+        zm_layer<N, T, PER, UNI, EPI>(src, dst, g, c, cz + 1, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv,
+                                      gtp, up_end, up_dot, z[1], z[2], z[0], wp, pq, sq, sp, epi);
       if (cz + 2 < z1)
-        zm_layer<N, T, PER, UNI>(src, dst, g, c, cz + 2, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv, gtp,
-                                 up_end, up_dot, z[2], z[0], z[1], wp, pq, sq, sp);
+        zm_layer<N, T, PER, UNI, EPI>(src, dst, g, c, cz + 2, z1, su, s_w, su + NC * CL, s_rimcol, tab, gh, ghinv,
+                                      gtp, up_end, up_dot, z[2], z[0], z[1], wp, pq, sq, sp, epi);
     }
   }
   if (partials) {
@@ -791,22 +808,22 @@ ZmPlan zm_plan(int n, int nx, int ny, int nz) {
   }
 }
 
-template <int N, typename T>
+template <int N, typename T, bool EPI>
 dgmf_status launch_apply_n(const CartGeom<T>& g, const T* src, T* dst, int64_t ncells, double* partials,
-                           const int* stop, hipStream_t s) {
+                           const int* stop, const ChebEpi<T>& epi, hipStream_t s) {
   (void)ncells;
   // with partial sums, the decomposition whose row count sipg_cart_blocks reports
   const ZmPlan pl = partials ? zm_plan_n<N, double>(g.nx, g.ny, g.nz) : zm_plan_n<N, T>(g.nx, g.ny, g.nz);
   const int blocks = 8 * pl.per_xcd;
   if (g.utab)
-    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, true>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst, g,
-                       pl, partials, stop);
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, true, EPI>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst,
+                       g, pl, partials, stop, epi);
   else if (g.allper)
-    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, false>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst, g,
-                       pl, partials, stop);
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, false, EPI>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src,
+                       dst, g, pl, partials, stop, epi);
   else
-    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, false, false>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst, g,
-                       pl, partials, stop);
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, false, false, EPI>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src,
+                       dst, g, pl, partials, stop, epi);
   DGMF_LAUNCH_CHECK("k_sipg_zm_apply");
   return DGMF_OK;
 }
@@ -828,14 +845,31 @@ int sipg_cart_blocks(int n, const CartGeom<double>& g) { return 8 * zm_plan(n, g
 template <typename T>
 dgmf_status launch_sipg_cart_apply(int n, const CartGeom<T>& g, const T* src, T* dst, int64_t ncells,
                                    double* partials, const int* stop, hipStream_t s) {
+  const ChebEpi<T> none{nullptr, nullptr, T(0), T(0), 1};
   switch (n) {
-    case 2: return launch_apply_n<2, T>(g, src, dst, ncells, partials, stop, s);
-    case 3: return launch_apply_n<3, T>(g, src, dst, ncells, partials, stop, s);
-    case 4: return launch_apply_n<4, T>(g, src, dst, ncells, partials, stop, s);
-    case 5: return launch_apply_n<5, T>(g, src, dst, ncells, partials, stop, s);
-    case 6: return launch_apply_n<6, T>(g, src, dst, ncells, partials, stop, s);
-    case 7: return launch_apply_n<7, T>(g, src, dst, ncells, partials, stop, s);
-    case 8: return launch_apply_n<8, T>(g, src, dst, ncells, partials, stop, s);
+    case 2: return launch_apply_n<2, T, false>(g, src, dst, ncells, partials, stop, none, s);
+    case 3: return launch_apply_n<3, T, false>(g, src, dst, ncells, partials, stop, none, s);
+    case 4: return launch_apply_n<4, T, false>(g, src, dst, ncells, partials, stop, none, s);
+    case 5: return launch_apply_n<5, T, false>(g, src, dst, ncells, partials, stop, none, s);
+    case 6: return launch_apply_n<6, T, false>(g, src, dst, ncells, partials, stop, none, s);
+    case 7: return launch_apply_n<7, T, false>(g, src, dst, ncells, partials, stop, none, s);
+    case 8: return launch_apply_n<8, T, false>(g, src, dst, ncells, partials, stop, none, s);
+    default: return fail(DGMF_UNSUPPORTED, "degree %d not built", n - 1);
+  }
+}
+
+template <typename T>
+dgmf_status launch_sipg_cart_cheb(int n, const CartGeom<T>& g, const T* xk, T* dst, const ChebEpi<T>& epi,
+                                  const int* stop, hipStream_t s) {
+  const int64_t nc = static_cast<int64_t>(g.nx) * g.ny * g.nz;
+  switch (n) {
+    case 2: return launch_apply_n<2, T, true>(g, xk, dst, nc, nullptr, stop, epi, s);
+    case 3: return launch_apply_n<3, T, true>(g, xk, dst, nc, nullptr, stop, epi, s);
+    case 4: return launch_apply_n<4, T, true>(g, xk, dst, nc, nullptr, stop, epi, s);
+    case 5: return launch_apply_n<5, T, true>(g, xk, dst, nc, nullptr, stop, epi, s);
+    case 6: return launch_apply_n<6, T, true>(g, xk, dst, nc, nullptr, stop, epi, s);
+    case 7: return launch_apply_n<7, T, true>(g, xk, dst, nc, nullptr, stop, epi, s);
+    case 8: return launch_apply_n<8, T, true>(g, xk, dst, nc, nullptr, stop, epi, s);
     default: return fail(DGMF_UNSUPPORTED, "degree %d not built", n - 1);
   }
 }
@@ -858,6 +892,10 @@ template dgmf_status launch_sipg_cart_apply<double>(int, const CartGeom<double>&
                                                     double*, const int*, hipStream_t);
 template dgmf_status launch_sipg_cart_apply<float>(int, const CartGeom<float>&, const float*, float*, int64_t,
                                                    double*, const int*, hipStream_t);
+template dgmf_status launch_sipg_cart_cheb<double>(int, const CartGeom<double>&, const double*, double*,
+                                                   const ChebEpi<double>&, const int*, hipStream_t);
+template dgmf_status launch_sipg_cart_cheb<float>(int, const CartGeom<float>&, const float*, float*,
+                                                  const ChebEpi<float>&, const int*, hipStream_t);
 template dgmf_status launch_sipg_cart_diag<double>(int, const CartGeom<double>&, double*, int64_t, hipStream_t);
 template dgmf_status launch_sipg_cart_diag<float>(int, const CartGeom<float>&, float*, int64_t, hipStream_t);
 
