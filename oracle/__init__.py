@@ -29,6 +29,8 @@ convective  divergence-form convective operator with local Lax-Friedrichs
             flux, its JVP/VJP and assembled Jacobian (Sec. 3.2 eq. convstepspat)
 rng         SplitMix64 counter-based generator (published definition)
 multigrid   geometric multigrid V-cycle preconditioner (Sec. 5.1, Poisson solver)
+v3          divergence and gradient operators, mass, div-div penalty and the
+            local projection of variant V3c (eqs. av3, bv3, div-div, tauD, project)
 mass        block-diagonal inverse mass matrix and the explicit convective
             substep of the matrix form (eq. advect)
 
