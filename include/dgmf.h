@@ -20,7 +20,9 @@
  *     flux, Lambda evaluated per face quadrature point (Sec. 3.2, eq.
  *     convstepspat; matrix form eq. advect), its vector-Jacobian product,
  *     and the explicit convective substep with the tensorial inverse of the
- *     block-diagonal mass matrix (Sec. 4 matrix formulation, Sec. 5).
+ *     block-diagonal mass matrix (Sec. 4 matrix formulation, Sec. 5);
+ *   - the divergence and gradient operators, the div-div penalty and the
+ *     element-local projection of variant V3c (Sec. 4.2, Sec. 5.1).
  *
  * Conventions shared by every entry point
  *   Reference cell [0,1]^3, n = k+1 nodes per direction.
@@ -116,6 +118,45 @@ dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t strea
  * overlap is DGMF_INVALID.  Asynchronous. */
 dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
                                     hipStream_t stream);
+/* dst = M src, the block-diagonal mass matrix of dgmf_inverse_mass_apply
+ * itself (|det J| (Mh (x) Mh (x) Mh) per cell); the M U-hat term of the
+ * projection's right-hand side (Sec. 4, eq. project).  Same arguments and
+ * rules as dgmf_inverse_mass_apply.  Asynchronous. */
+dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
+                            hipStream_t stream);
+
+/* ------------------------------------------------- variant V3c (fp64) --- */
+/* Operators of the projection and pressure steps of variant V3c (Sec. 4.2,
+ * V3b/V3c; matrix form Sec. 4, eqs. poissonmat and project) on axis-aligned
+ * meshes (sheared meshes: DGMF_UNSUPPORTED).  Averages are central on
+ * interior faces; on boundary faces the cell's own trace is used (the ND
+ * extension of Sec. 3.1).  All vectors are device fp64; [3][N] for vector
+ * fields, [N] for scalar fields, [n_cells] for per-cell values. */
+/* out = A u, the divergence of eq. av3 without the factor gamma_0/dt:
+ * (A u)_i = sum_K (grad phi_i, u)_K - (phi_i, {{u}}.n)_dK.  u [3][N],
+ * out [N]; must not overlap.  Asynchronous. */
+dgmf_status dgmf_divergence_apply(dgmf_mesh mesh, const double* u, double* out, hipStream_t stream);
+/* out = B p, the gradient of eq. bv3 without the factor dt/gamma_0:
+ * (B p)_{i,a} = sum_K (d_a phi_i, p)_K - (phi_i, {{p}} n_a)_dK.  p [N],
+ * out [3][N]; must not overlap.  On periodic meshes B = -A^T.  Asynchronous. */
+dgmf_status dgmf_gradient_apply(dgmf_mesh mesh, const double* p, double* out, hipStream_t stream);
+/* tau[c] = zeta |u_bar_c| V_c^(1/3) dt (eq. tauD), u_bar_c the volume average
+ * of the velocity u [3][N] on cell c; zeta, dt finite and >= 0 (the paper
+ * takes zeta = 1/CFL).  Asynchronous. */
+dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, double dt, double* tau,
+                                hipStream_t stream);
+/* Solves the local projection of eq. project with the div-div penalty only
+ * (V3, tau_C = 0): on every cell (M_e + tau[c] D_e) x_e = rhs_e with
+ * D_e = (div v, div u)_K (eq. div-div), by CG preconditioned with the inverse
+ * cell mass, one independent iteration per cell (Sec. 5.1, projection
+ * solver), started from x on entry and stopped when that cell's residual is
+ * at most rtol times its right-hand side or after max_iter iterations.  rhs,
+ * x [3][N] (x in/out; must not overlap rhs); tau [n_cells] >= 0;
+ * iterations: device int [n_cells] receiving each cell's iteration count, or
+ * NULL.  Degrees k <= 6.  Asynchronous. */
+dgmf_status dgmf_projection_solve(dgmf_mesh mesh, const double* tau, const double* rhs, double* x, double rtol,
+                                  int max_iter, int* iterations, hipStream_t stream);
+
 /* Frees the mesh; operators created on it must be destroyed first (DGMF_INVALID otherwise). */
 dgmf_status dgmf_mesh_destroy(dgmf_mesh mesh);
 

@@ -72,6 +72,11 @@ _mesh_info = _sig("dgmf_mesh_info", _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i
 _mesh_coords = _sig("dgmf_mesh_node_coords", _vp, _vp, _vp)
 _mesh_destroy = _sig("dgmf_mesh_destroy", _vp)
 _inv_mass = _sig("dgmf_inverse_mass_apply", _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp)
+_mass = _sig("dgmf_mass_apply", _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp)
+_div = _sig("dgmf_divergence_apply", _vp, _vp, _vp, _vp)
+_grad = _sig("dgmf_gradient_apply", _vp, _vp, _vp, _vp)
+_divdiv_tau = _sig("dgmf_divdiv_penalty", _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp)
+_proj = _sig("dgmf_projection_solve", _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp)
 _sipg_create = _sig("dgmf_sipg_create", _vp, ctypes.POINTER(SipgDesc), ctypes.POINTER(_vp))
 _apply = _sig("dgmf_operator_apply", _vp, ctypes.c_int, _vp, _vp, _vp)
 _diag = _sig("dgmf_operator_diagonal", _vp, ctypes.c_int, _vp, _vp)
@@ -147,6 +152,57 @@ class Mesh:
         out = torch.empty(3 * self.ndofs, dtype=torch.float64, device="cuda")
         _check(_mesh_coords(self._h, _ptr(out, torch.float64, 3 * self.ndofs, "xyz"), _stream()), "node_coords")
         return out.view(3, self.ndofs)
+
+    def mass(self, src, out=None):
+        """M src for one or more scalar fields laid out [n_fields][N] (fp64 or fp32); out may be src."""
+        return self._block_mass(_mass, "mass_apply", src, out)
+
+    def divergence(self, u, out=None):
+        """A u: weak divergence with central fluxes (eq. av3 without gamma_0/dt); u [3][N] -> [N]."""
+        if out is None:
+            out = torch.empty(self.ndofs, dtype=torch.float64, device=u.device)
+        _check(_div(self._h, _ptr(u, torch.float64, 3 * self.ndofs, "u"), _ptr(out, torch.float64, self.ndofs, "out"),
+                    _stream()), "divergence_apply")
+        return out
+
+    def gradient(self, p, out=None):
+        """B p: weak gradient with central fluxes (eq. bv3 without dt/gamma_0); p [N] -> [3][N]."""
+        if out is None:
+            out = torch.empty(3 * self.ndofs, dtype=torch.float64, device=p.device)
+        _check(_grad(self._h, _ptr(p, torch.float64, self.ndofs, "p"),
+                     _ptr(out, torch.float64, 3 * self.ndofs, "out"), _stream()), "gradient_apply")
+        return out
+
+    def divdiv_penalty(self, u, zeta, dt, out=None):
+        """tau_D per cell = zeta |u_bar| V^(1/3) dt (eq. tauD)."""
+        if out is None:
+            out = torch.empty(self.ncells, dtype=torch.float64, device=u.device)
+        _check(_divdiv_tau(self._h, _ptr(u, torch.float64, 3 * self.ndofs, "u"), float(zeta), float(dt),
+                           _ptr(out, torch.float64, self.ncells, "tau"), _stream()), "divdiv_penalty")
+        return out
+
+    def projection_solve(self, tau, rhs, x=None, rtol=1e-12, max_iter=1000, iterations=None):
+        """Per cell (M_e + tau_e D_e) x_e = rhs_e by element-local CG; x (in/out) starts at zero when None."""
+        if x is None:
+            x = torch.zeros_like(rhs)
+        it = _vp(None) if iterations is None else _ptr(iterations, torch.int32, self.ncells, "iterations")
+        _check(_proj(self._h, _ptr(tau, torch.float64, self.ncells, "tau"), _ptr(rhs, torch.float64, 3 * self.ndofs,
+                     "rhs"), _ptr(x, torch.float64, 3 * self.ndofs, "x"), float(rtol), int(max_iter), it, _stream()),
+               "projection_solve")
+        return x
+
+    def _block_mass(self, fn, name, src, out):
+        if src.numel() % self.ndofs:
+            raise ValueError(f"src must hold a whole number of fields of {self.ndofs} values")
+        nf = src.numel() // self.ndofs
+        dt = {torch.float64: F64, torch.float32: F32}.get(src.dtype)
+        if dt is None:
+            raise TypeError(f"src must be float64 or float32, got {src.dtype}")
+        if out is None:
+            out = torch.empty_like(src)
+        _check(fn(self._h, dt, nf, _ptr(src, src.dtype, src.numel(), "src"), _ptr(out, src.dtype, src.numel(), "out"),
+                  _stream()), name)
+        return out
 
     def inverse_mass(self, src, out=None):
         """M^{-1} src for one or more scalar fields laid out [n_fields][N] (fp64 or fp32); out may be src."""

@@ -361,6 +361,13 @@ static bool overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+// [a, a + abytes) and [b, b + bbytes) intersect
+static bool overlap2(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bbytes && y < x + abytes;
+}
+
 }  // namespace dgmf
 
 using namespace dgmf;
@@ -451,6 +458,28 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
     std::vector<float> mi32(mi.begin(), mi.end());
     if (st == DGMF_OK) st = m->minv64.upload(mi.data(), mi.size() * sizeof(double));
     if (st == DGMF_OK) st = m->minv32.upload(mi32.data(), mi32.size() * sizeof(float));
+    // V3c tables: Mh, Ch, Mh^{-1}, S, D, w, gw
+    const Tables1D& t = m->tab;
+    const V3Tab L{static_cast<int>(n)};
+    std::vector<double> v3(L.size(), 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        long double c = 0;
+        for (int q = 0; q < t.nq; ++q)
+          c += static_cast<long double>(t.wq[q]) * t.D[q * n + i] * t.S[q * n + j];
+        v3[L.Mh() + i * n + j] = t.Mhat[i * n + j];
+        v3[L.Ch() + i * n + j] = static_cast<double>(c);
+        if (st == DGMF_OK) v3[L.Mi() + i * n + j] = mi[i * n + j];
+        v3[L.S() + i * n + j] = t.S[i * n + j];
+        v3[L.D() + i * n + j] = t.D[i * n + j];
+      }
+    for (int i = 0; i < n; ++i) {
+      v3[L.w() + i] = t.wq[i];
+      v3[L.gw() + i] = t.gll_w[i];
+    }
+    std::vector<float> mh32(t.Mhat.begin(), t.Mhat.end());
+    if (st == DGMF_OK) st = m->v3tab.upload(v3.data(), v3.size() * sizeof(double));
+    if (st == DGMF_OK) st = m->mh32.upload(mh32.data(), mh32.size() * sizeof(float));
   }
   if (st == DGMF_OK && m->desc.store_qp_metric) {
     DeviceGuard dg(m->device);
@@ -500,12 +529,97 @@ dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fiel
   const double js = 1.0 / std::fabs(mesh->shear.det);
   const int n = mesh->tab.n;
   if (dtype == DGMF_F64)
-    return launch_inverse_mass<double>(n, mesh->g64, js, static_cast<const double*>(mesh->minv64.p),
-                                       static_cast<const double*>(src), static_cast<double*>(dst), mesh->ncells,
-                                       n_fields, stream);
-  return launch_inverse_mass<float>(n, mesh->g32, static_cast<float>(js), static_cast<const float*>(mesh->minv32.p),
-                                    static_cast<const float*>(src), static_cast<float*>(dst), mesh->ncells, n_fields,
-                                    stream);
+    return launch_block_mass<double>(n, mesh->g64, js, static_cast<const double*>(mesh->minv64.p),
+                                     static_cast<const double*>(src), static_cast<double*>(dst), mesh->ncells,
+                                     n_fields, true, stream);
+  return launch_block_mass<float>(n, mesh->g32, static_cast<float>(js), static_cast<const float*>(mesh->minv32.p),
+                                  static_cast<const float*>(src), static_cast<float*>(dst), mesh->ncells, n_fields,
+                                  true, stream);
+}
+
+dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
+                            hipStream_t stream) {
+  if (!mesh || !src || !dst) return fail(DGMF_INVALID, "mass_apply: null argument");
+  const size_t es = dtype == DGMF_F64 ? 8 : (dtype == DGMF_F32 ? 4 : 0);
+  if (!es) return fail(DGMF_INVALID, "mass_apply: unknown dtype %d", static_cast<int>(dtype));
+  if (n_fields < 1 || n_fields > 64) return fail(DGMF_INVALID, "mass_apply: n_fields must be in 1..64");
+  if (!aligned(src, es) || !aligned(dst, es)) return fail(DGMF_INVALID, "mass_apply: misaligned vector");
+  if (src != dst && overlap(src, dst, es * mesh->ndofs * n_fields))
+    return fail(DGMF_INVALID, "mass_apply: src and dst overlap without being the same array");
+  DeviceGuard dg(mesh->device);
+  const double js = std::fabs(mesh->shear.det);
+  const int n = mesh->tab.n;
+  if (dtype == DGMF_F64)
+    return launch_block_mass<double>(n, mesh->g64, js, static_cast<const double*>(mesh->v3tab.p),
+                                     static_cast<const double*>(src), static_cast<double*>(dst), mesh->ncells,
+                                     n_fields, false, stream);
+  return launch_block_mass<float>(n, mesh->g32, static_cast<float>(js), static_cast<const float*>(mesh->mh32.p),
+                                  static_cast<const float*>(src), static_cast<float*>(dst), mesh->ncells, n_fields,
+                                  false, stream);
+}
+
+static dgmf_status v3_check(dgmf_mesh mesh, const char* who) {
+  if (!mesh) return fail(DGMF_INVALID, "%s: null mesh", who);
+  if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "%s: sheared meshes are not supported", who);
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_divergence_apply(dgmf_mesh mesh, const double* u, double* out, hipStream_t stream) {
+  dgmf_status e = v3_check(mesh, "divergence_apply");
+  if (e) return e;
+  if (!u || !out || !aligned(u, 8) || !aligned(out, 8))
+    return fail(DGMF_INVALID, "divergence_apply: null or misaligned vector");
+  if (overlap2(u, 24 * mesh->ndofs, out, 8 * mesh->ndofs))
+    return fail(DGMF_INVALID, "divergence_apply: u and out overlap");
+  DeviceGuard dg(mesh->device);
+  return launch_v3_divergence(mesh->tab.n, mesh->g64, static_cast<const double*>(mesh->v3tab.p), u, out,
+                              mesh->ncells, stream);
+}
+
+dgmf_status dgmf_gradient_apply(dgmf_mesh mesh, const double* p, double* out, hipStream_t stream) {
+  dgmf_status e = v3_check(mesh, "gradient_apply");
+  if (e) return e;
+  if (!p || !out || !aligned(p, 8) || !aligned(out, 8))
+    return fail(DGMF_INVALID, "gradient_apply: null or misaligned vector");
+  if (overlap2(p, 8 * mesh->ndofs, out, 24 * mesh->ndofs))
+    return fail(DGMF_INVALID, "gradient_apply: p and out overlap");
+  DeviceGuard dg(mesh->device);
+  return launch_v3_gradient(mesh->tab.n, mesh->g64, static_cast<const double*>(mesh->v3tab.p), p, out, mesh->ncells,
+                            stream);
+}
+
+dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, double dt, double* tau,
+                                hipStream_t stream) {
+  dgmf_status e = v3_check(mesh, "divdiv_penalty");
+  if (e) return e;
+  if (!u || !tau || !aligned(u, 8) || !aligned(tau, 8))
+    return fail(DGMF_INVALID, "divdiv_penalty: null or misaligned vector");
+  if (!std::isfinite(zeta) || !std::isfinite(dt) || zeta < 0 || dt < 0)
+    return fail(DGMF_INVALID, "divdiv_penalty: zeta and dt must be finite and >= 0");
+  if (overlap2(u, 24 * mesh->ndofs, tau, 8 * mesh->ncells))
+    return fail(DGMF_INVALID, "divdiv_penalty: u and tau overlap");
+  DeviceGuard dg(mesh->device);
+  return launch_v3_tau(mesh->tab.n, mesh->g64, static_cast<const double*>(mesh->v3tab.p), u, zeta, dt, tau,
+                       mesh->ncells, stream);
+}
+
+dgmf_status dgmf_projection_solve(dgmf_mesh mesh, const double* tau, const double* rhs, double* x, double rtol,
+                                  int max_iter, int* iterations, hipStream_t stream) {
+  dgmf_status e = v3_check(mesh, "projection_solve");
+  if (e) return e;
+  if (!v3_projection_supported(mesh->tab.n))
+    return fail(DGMF_UNSUPPORTED, "projection_solve: degree %d not built (k <= 6)", mesh->tab.n - 1);
+  if (!tau || !rhs || !x || !aligned(tau, 8) || !aligned(rhs, 8) || !aligned(x, 8) ||
+      (iterations && !aligned(iterations, 4)))
+    return fail(DGMF_INVALID, "projection_solve: null or misaligned argument");
+  if (!(rtol >= 0) || !std::isfinite(rtol) || max_iter < 0)
+    return fail(DGMF_INVALID, "projection_solve: rtol must be finite and >= 0, max_iter >= 0");
+  const size_t vb = 24 * mesh->ndofs, tb = 8 * mesh->ncells, ib = 4 * mesh->ncells;
+  if (overlap2(rhs, vb, x, vb) || overlap2(tau, tb, x, vb) || (iterations && overlap2(iterations, ib, x, vb)))
+    return fail(DGMF_INVALID, "projection_solve: x overlaps another argument");
+  DeviceGuard dg(mesh->device);
+  return launch_v3_projection(mesh->tab.n, mesh->g64, static_cast<const double*>(mesh->v3tab.p), tau, rhs, x, rtol,
+                              max_iter, iterations, mesh->ncells, stream);
 }
 
 dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op* out) {

@@ -215,12 +215,39 @@ dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, d
 dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
                             int64_t ncells, hipStream_t s);
 
-// dst = M^{-1} src on nfields consecutive scalar fields of an affine mesh:
-// minv the n x n inverse 1D mass (k+1 Gauss points), jscale = 1/|det shear|.
+// dst = M^{-1} src (inverse: table the n x n inverse 1D mass, jscale =
+// 1/|det shear|) or dst = M src (table the 1D mass, jscale = |det shear|) on
+// nfields consecutive scalar fields of an affine mesh (k+1 Gauss points).
 // src and dst may be the same array.
 template <typename T>
-dgmf_status launch_inverse_mass(int n, const CartGeom<T>& g, T jscale, const T* minv, const T* src, T* dst,
-                                int64_t ncells, int nfields, hipStream_t s);
+dgmf_status launch_block_mass(int n, const CartGeom<T>& g, T jscale, const T* table, const T* src, T* dst,
+                              int64_t ncells, int nfields, bool inverse, hipStream_t s);
+
+// Variant V3c operators on axis-aligned box meshes (fp64).  Table layout
+// (V3Tab): Mh, Ch (Ch[i][j] = int l_i' l_j), Mh^{-1}, S, D (Gauss rule of
+// k+1 points, row q), all n x n, then the Gauss weights w (n) and the
+// integrals of the Lagrange basis gw (n).
+struct V3Tab {
+  int n;
+  __host__ __device__ int Mh() const { return 0; }
+  __host__ __device__ int Ch() const { return n * n; }
+  __host__ __device__ int Mi() const { return 2 * n * n; }
+  __host__ __device__ int S() const { return 3 * n * n; }
+  __host__ __device__ int D() const { return 4 * n * n; }
+  __host__ __device__ int w() const { return 5 * n * n; }
+  __host__ __device__ int gw() const { return 5 * n * n + n; }
+  __host__ __device__ int size() const { return 5 * n * n + 2 * n; }
+};
+dgmf_status launch_v3_divergence(int n, const CartGeom<double>& g, const double* tab, const double* u, double* out,
+                                 int64_t ncells, hipStream_t s);
+dgmf_status launch_v3_gradient(int n, const CartGeom<double>& g, const double* tab, const double* p, double* out,
+                               int64_t ncells, hipStream_t s);
+dgmf_status launch_v3_tau(int n, const CartGeom<double>& g, const double* tab, const double* u, double zeta,
+                          double dt, double* tau, int64_t ncells, hipStream_t s);
+bool v3_projection_supported(int n);
+dgmf_status launch_v3_projection(int n, const CartGeom<double>& g, const double* tab, const double* tau,
+                                 const double* rhs, double* x, double rtol, int max_iter, int* iters, int64_t ncells,
+                                 hipStream_t s);
 // Inverse of the 1D reference mass S^T W S (square S: n_q = k+1) as
 // S^{-1} W^{-1} S^{-T}, row-major n x n; false when S is singular.
 bool inverse_mass_1d(const Tables1D& t, std::vector<double>& out);
@@ -290,6 +317,8 @@ struct dgmf_mesh_ {
   dgmf::MetricGeom<double> mg64{};   // coefficients unset
   dgmf::MetricGeom<float> mg32{};
   dgmf::DevBuf minv64, minv32;     // inverse 1D mass (n x n) for dgmf_inverse_mass_apply
+  dgmf::DevBuf mh32;               // 1D mass in fp32 (the fp64 one heads v3tab)
+  dgmf::DevBuf v3tab;              // V3Tab tables (fp64)
   int nops = 0;                    // live operators built on this mesh
 };
 

@@ -1,4 +1,4 @@
-// Inverse of the block-diagonal DG mass matrix on affine hexahedra (gfx950).
+// The block-diagonal DG mass matrix and its inverse on affine hexahedra (gfx950).
 //
 // With the nodal basis on Gauss-Lobatto points the mass block of a cell is
 // not diagonal (Sec. 5, implementation).  On an affine cell it is
@@ -8,7 +8,8 @@
 // inverse Mh^{-1} = S^{-1} W^{-1} S^{-T}, formed on the host in long double.
 // Because |det J| is constant on an affine cell, the paper's
 // transform / inverse-weight / transform sequence collapses into three 1D
-// sweeps by Mh^{-1} and one scale by 1/|det J|.
+// sweeps by Mh^{-1} and one scale by 1/|det J|.  The same kernel applies M
+// itself (three sweeps by Mh and the scale |det J|).
 //
 // Layout: n^2 lanes per cell, 64/n^2 cells per wavefront, four independent
 // wavefronts per workgroup (no workgroup barrier).  Lane (i, j) loads the
@@ -39,8 +40,10 @@ struct IMShape {
   static constexpr int WAVES = 4, THREADS = 64 * WAVES;
 };
 
-template <int N, typename T>
-__global__ void __launch_bounds__(256) k_inverse_mass(const T* src, T* dst, const CartGeom<T> g, const T jscale,
+// INV: dst = M^{-1} src (table Mh^{-1}, scale jscale / (hx hy hz)); else
+// dst = M src (table Mh, scale jscale hx hy hz).
+template <int N, typename T, bool INV>
+__global__ void __launch_bounds__(256) k_block_mass(const T* src, T* dst, const CartGeom<T> g, const T jscale,
                                                       const T* minv_g, const int64_t ncells, const int64_t total) {
   using SH = IMShape<N>;
   constexpr int N2 = SH::N2, N3 = SH::N3, CP = SH::CP, CPW = SH::CPW;
@@ -86,7 +89,8 @@ __global__ void __launch_bounds__(256) k_inverse_mass(const T* src, T* dst, cons
     const int cx = static_cast<int>(c % g.nx);
     const int64_t r2 = c / g.nx;
     const int cy = static_cast<int>(r2 % g.ny), cz = static_cast<int>(r2 / g.ny);
-    const T sc = jscale * g.hinv[0][cx] * g.hinv[1][cy] * g.hinv[2][cz];
+    const T sc = INV ? jscale * g.hinv[0][cx] * g.hinv[1][cy] * g.hinv[2][cz]
+                     : jscale * g.h[0][cx] * g.h[1][cy] * g.h[2][cz];
     T* p = cell + t * N;
 #pragma unroll
     for (int m = 0; m < N; ++m) v[m] = p[m];
@@ -107,39 +111,43 @@ __global__ void __launch_bounds__(256) k_inverse_mass(const T* src, T* dst, cons
 
 template <int N, typename T>
 dgmf_status launch_n(const CartGeom<T>& g, T jscale, const T* minv, const T* src, T* dst, int64_t ncells,
-                     int64_t total, hipStream_t s) {
+                     int64_t total, bool inv, hipStream_t s) {
   using SH = IMShape<N>;
   const int64_t waves = (total + SH::CPW - 1) / SH::CPW;
   const int64_t blocks = (waves + SH::WAVES - 1) / SH::WAVES;
   if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "inverse_mass: too many cells for one launch");
-  hipLaunchKernelGGL((k_inverse_mass<N, T>), dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s, src,
-                     dst, g, jscale, minv, ncells, total);
-  DGMF_LAUNCH_CHECK("k_inverse_mass");
+  if (inv)
+    hipLaunchKernelGGL((k_block_mass<N, T, true>), dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s,
+                       src, dst, g, jscale, minv, ncells, total);
+  else
+    hipLaunchKernelGGL((k_block_mass<N, T, false>), dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s,
+                       src, dst, g, jscale, minv, ncells, total);
+  DGMF_LAUNCH_CHECK("k_block_mass");
   return DGMF_OK;
 }
 
 }  // namespace
 
 template <typename T>
-dgmf_status launch_inverse_mass(int n, const CartGeom<T>& g, T jscale, const T* minv, const T* src, T* dst,
-                                int64_t ncells, int nfields, hipStream_t s) {
+dgmf_status launch_block_mass(int n, const CartGeom<T>& g, T jscale, const T* table, const T* src, T* dst,
+                              int64_t ncells, int nfields, bool inverse, hipStream_t s) {
   const int64_t total = ncells * nfields;
   if (total == 0) return DGMF_OK;
   switch (n) {
-    case 2: return launch_n<2, T>(g, jscale, minv, src, dst, ncells, total, s);
-    case 3: return launch_n<3, T>(g, jscale, minv, src, dst, ncells, total, s);
-    case 4: return launch_n<4, T>(g, jscale, minv, src, dst, ncells, total, s);
-    case 5: return launch_n<5, T>(g, jscale, minv, src, dst, ncells, total, s);
-    case 6: return launch_n<6, T>(g, jscale, minv, src, dst, ncells, total, s);
-    case 7: return launch_n<7, T>(g, jscale, minv, src, dst, ncells, total, s);
-    case 8: return launch_n<8, T>(g, jscale, minv, src, dst, ncells, total, s);
-    default: return fail(DGMF_UNSUPPORTED, "inverse_mass: n = %d not built", n);
+    case 2: return launch_n<2, T>(g, jscale, table, src, dst, ncells, total, inverse, s);
+    case 3: return launch_n<3, T>(g, jscale, table, src, dst, ncells, total, inverse, s);
+    case 4: return launch_n<4, T>(g, jscale, table, src, dst, ncells, total, inverse, s);
+    case 5: return launch_n<5, T>(g, jscale, table, src, dst, ncells, total, inverse, s);
+    case 6: return launch_n<6, T>(g, jscale, table, src, dst, ncells, total, inverse, s);
+    case 7: return launch_n<7, T>(g, jscale, table, src, dst, ncells, total, inverse, s);
+    case 8: return launch_n<8, T>(g, jscale, table, src, dst, ncells, total, inverse, s);
+    default: return fail(DGMF_UNSUPPORTED, "mass: n = %d not built", n);
   }
 }
 
-template dgmf_status launch_inverse_mass<double>(int, const CartGeom<double>&, double, const double*, const double*,
-                                                 double*, int64_t, int, hipStream_t);
-template dgmf_status launch_inverse_mass<float>(int, const CartGeom<float>&, float, const float*, const float*, float*,
-                                                int64_t, int, hipStream_t);
+template dgmf_status launch_block_mass<double>(int, const CartGeom<double>&, double, const double*, const double*,
+                                               double*, int64_t, int, bool, hipStream_t);
+template dgmf_status launch_block_mass<float>(int, const CartGeom<float>&, float, const float*, const float*, float*,
+                                              int64_t, int, bool, hipStream_t);
 
 }  // namespace dgmf

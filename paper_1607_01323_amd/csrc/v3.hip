@@ -1,0 +1,552 @@
+// Operators of variant V3c on axis-aligned box meshes (gfx950, fp64).
+//
+// Divergence A (eq. av3 without gamma_0/dt) and gradient B (eq. bv3 without
+// dt/gamma_0), with the central average on interior faces and the cell's own
+// trace on boundary faces (the ND extension of Sec. 3.1):
+//   (A u)_i = sum_a (d_a phi_i, u_a)_K - (phi_i, {{u}}.n)_dK
+//   (B p)_{i,a} = (d_a phi_i, p)_K - (phi_i, {{p}} n_a)_dK
+// On an axis-aligned cell with sizes h the cell terms are tensor products of
+// the 1D mass Mh and Ch[i][j] = int_0^1 l_i' l_j scaled by |det J| / h_a,
+// e.g. (d_x phi, u)_K = (hy hz) (Mh (x) Mh (x) Ch) u.  GLL nodes include the
+// end points, so a face trace is the node plane on that face and the face
+// integral of a trace polynomial is area (Mh (x) Mh) on the plane.
+//
+// The div-div projection (eq. div-div, eq. project with tau_C = 0) is cell
+// local: (M_e + tau_e D_e) u = rhs_e with D_e = (div v, div u)_K.  Each cell is
+// solved by its own CG (Sec. 5.1, projection solver: element-local CG
+// preconditioned by the inverse mass), one wavefront per cell with every
+// vector in the wavefront's LDS slice, iterating until its own residual falls
+// below rtol times its own right-hand side; D_e is applied through the Gauss
+// points (k+1 per direction): div at the points from S and D sweeps, then the
+// transposed sweeps.
+//
+// Layout: one cell per wavefront, a few wavefronts per workgroup (LDS bound),
+// wavefront barriers only after the tables are staged.
+#include "internal.h"
+
+namespace dgmf {
+namespace {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct CellIdx {
+  int c[3];
+  double h[3];
+};
+
+__device__ __forceinline__ CellIdx cell_of(const CartGeom<double>& g, int64_t cell) {
+  CellIdx r;
+  r.c[0] = static_cast<int>(cell % g.nx);
+  const int64_t q = cell / g.nx;
+  r.c[1] = static_cast<int>(q % g.ny);
+  r.c[2] = static_cast<int>(q / g.ny);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r.h[d] = g.h[d][r.c[d]];
+  return r;
+}
+
+// neighbour across face (d, s) or -1 on a boundary face
+__device__ __forceinline__ int64_t nb_of(const CartGeom<double>& g, const CellIdx& ci, int64_t cell, int d, int s) {
+  const int nd = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+  int cc = ci.c[d] + (s ? 1 : -1);
+  if (cc < 0 || cc >= nd) {
+    if (!g.per[d]) return -1;
+    cc = cc < 0 ? nd - 1 : 0;
+  }
+  const int64_t stride = d == 0 ? 1 : (d == 1 ? g.nx : static_cast<int64_t>(g.nx) * g.ny);
+  return cell + static_cast<int64_t>(cc - ci.c[d]) * stride;
+}
+
+// node index of entry (p1, p2) of the node plane e along direction d (p1, p2: the
+// other two directions in increasing order)
+template <int N>
+__device__ __forceinline__ int plane_node(int d, int e, int p1, int p2) {
+  if (d == 0) return (p2 * N + p1) * N + e;
+  if (d == 1) return (p2 * N + e) * N + p1;
+  return (e * N + p2) * N + p1;
+}
+
+// out = M applied along `axis` of an N^3 array (lines along the axis), one
+// line per lane step; accumulate with scale when ACC.  M row-major [out][in],
+// or its transpose when TR.
+template <int N, bool TR, bool ACC>
+__device__ __forceinline__ void sweep(const double* M, int axis, const double* in, double* out, double scale,
+                                      int lane) {
+  constexpr int N2 = N * N;
+  const int stride = axis == 0 ? 1 : (axis == 1 ? N : N2);
+  for (int L = lane; L < N2; L += 64) {
+    const int a = L % N, b = L / N;
+    const int base = axis == 0 ? (b * N + a) * N : (axis == 1 ? b * N2 + a : b * N + a);
+    double v[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = in[base + m * stride];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double r = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) r = fma(TR ? M[m * N + i] : M[i * N + m], v[m], r);
+      if (ACC) out[base + i * stride] += scale * r;
+      else out[base + i * stride] = scale * r;
+    }
+  }
+}
+
+template <int N>
+struct V3Shape {
+  static constexpr int N2 = N * N, N3 = N2 * N;
+  static constexpr int TABN = 5 * N2 + 2 * N;
+};
+
+// ------------------------------------------------------------ divergence --
+template <int N, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __restrict__ u, double* __restrict__ out,
+                                                              const CartGeom<double> g,
+                                                              const double* __restrict__ tab, int64_t ncells) {
+  using SH = V3Shape<N>;
+  constexpr int N2 = SH::N2, N3 = SH::N3, SLICE = 9 * N3 + 2 * N2;
+  __shared__ double s_tab[SH::TABN];
+  __shared__ double s_all[WAVES * SLICE];
+  for (int e = threadIdx.x; e < SH::TABN; e += blockDim.x) s_tab[e] = tab[e];
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t cell = static_cast<int64_t>(blockIdx.x) * WAVES + wave;
+  if (cell >= ncells) return;
+  const V3Tab L{N};
+  const double* Mh = s_tab + L.Mh();
+  const double* Ch = s_tab + L.Ch();
+  double* U = s_all + wave * SLICE;     // 3 N3
+  double* A3 = U + 3 * N3;              // 3 N3: after x sweeps
+  double* C1 = A3 + 3 * N3;             // N3
+  double* C2 = C1 + N3;                 // N3
+  double* O = C2 + N3;                  // N3
+  double* F = O + N3;                   // 2 N2: face plane scratch
+  const int64_t Nd = ncells * N3;
+  const CellIdx ci = cell_of(g, cell);
+  const double vol = ci.h[0] * ci.h[1] * ci.h[2];
+  double s[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s[a] = vol / ci.h[a];
+  for (int e = lane; e < 3 * N3; e += 64) U[e] = u[(e / N3) * Nd + cell * N3 + e % N3];
+  wave_sync();
+  sweep<N, false, false>(Ch, 0, U, A3, 1.0, lane);                     // Ch_x u_x
+  sweep<N, false, false>(Mh, 0, U + N3, A3 + N3, 1.0, lane);           // Mh_x u_y
+  sweep<N, false, false>(Mh, 0, U + 2 * N3, A3 + 2 * N3, 1.0, lane);   // Mh_x u_z
+  wave_sync();
+  sweep<N, false, false>(Mh, 1, A3, C1, s[0], lane);                   // sx Mh_y Ch_x u_x
+  sweep<N, false, false>(Mh, 1, A3 + 2 * N3, C2, s[2], lane);          // sz Mh_y Mh_x u_z
+  wave_sync();
+  sweep<N, false, true>(Ch, 1, A3 + N3, C1, s[1], lane);               // + sy Ch_y Mh_x u_y
+  wave_sync();
+  sweep<N, false, false>(Mh, 2, C1, O, 1.0, lane);
+  wave_sync();
+  sweep<N, false, true>(Ch, 2, C2, O, 1.0, lane);
+  wave_sync();
+  // faces: O -= sign area (Mh (x) Mh) {{u_d}} on the face plane
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const double area = ci.h[t1] * ci.h[t2];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int e = sd ? N - 1 : 0;
+      const int64_t nb = nb_of(g, ci, cell, d, sd);
+      for (int q = lane; q < N2; q += 64) {
+        const int p1 = q % N, p2 = q / N;
+        const double own = U[d * N3 + plane_node<N>(d, e, p1, p2)];
+        F[q] = nb >= 0 ? 0.5 * (own + u[d * Nd + nb * N3 + plane_node<N>(d, N - 1 - e, p1, p2)]) : own;
+      }
+      wave_sync();
+      for (int q = lane; q < N2; q += 64) {          // F2 = Mh_t1 F along p1
+        const int p1 = q % N, p2 = q / N;
+        double r = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) r = fma(Mh[p1 * N + m], F[p2 * N + m], r);
+        F[N2 + q] = r;
+      }
+      wave_sync();
+      const double sg = (sd ? 1.0 : -1.0) * area;
+      for (int q = lane; q < N2; q += 64) {          // along p2, subtract
+        const int p1 = q % N, p2 = q / N;
+        double r = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) r = fma(Mh[p2 * N + m], F[N2 + m * N + p1], r);
+        O[plane_node<N>(d, e, p1, p2)] -= sg * r;
+      }
+      wave_sync();
+    }
+  }
+  for (int e = lane; e < N3; e += 64) out[cell * N3 + e] = O[e];
+}
+
+// -------------------------------------------------------------- gradient --
+template <int N, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __restrict__ p, double* __restrict__ out,
+                                                            const CartGeom<double> g, const double* __restrict__ tab,
+                                                            int64_t ncells) {
+  using SH = V3Shape<N>;
+  constexpr int N2 = SH::N2, N3 = SH::N3, SLICE = 9 * N3 + 2 * N2;
+  __shared__ double s_tab[SH::TABN];
+  __shared__ double s_all[WAVES * SLICE];
+  for (int e = threadIdx.x; e < SH::TABN; e += blockDim.x) s_tab[e] = tab[e];
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t cell = static_cast<int64_t>(blockIdx.x) * WAVES + wave;
+  if (cell >= ncells) return;
+  const V3Tab L{N};
+  const double* Mh = s_tab + L.Mh();
+  const double* Ch = s_tab + L.Ch();
+  double* P = s_all + wave * SLICE;     // N3
+  double* G = P + N3;                   // 2 N3: Ch_x p, Mh_x p
+  double* H = G + 2 * N3;               // 3 N3
+  double* O3 = H + 3 * N3;              // 3 N3: output components
+  double* F = O3 + 3 * N3;              // 2 N2: face plane scratch
+  const int64_t Nd = ncells * N3;
+  const CellIdx ci = cell_of(g, cell);
+  const double vol = ci.h[0] * ci.h[1] * ci.h[2];
+  double s[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s[a] = vol / ci.h[a];
+  for (int e = lane; e < N3; e += 64) P[e] = p[cell * N3 + e];
+  wave_sync();
+  sweep<N, false, false>(Ch, 0, P, G, 1.0, lane);
+  sweep<N, false, false>(Mh, 0, P, G + N3, 1.0, lane);
+  wave_sync();
+  sweep<N, false, false>(Mh, 1, G, H, 1.0, lane);
+  sweep<N, false, false>(Ch, 1, G + N3, H + N3, 1.0, lane);
+  sweep<N, false, false>(Mh, 1, G + N3, H + 2 * N3, 1.0, lane);
+  wave_sync();
+  sweep<N, false, false>(Mh, 2, H, O3, s[0], lane);
+  sweep<N, false, false>(Mh, 2, H + N3, O3 + N3, s[1], lane);
+  sweep<N, false, false>(Ch, 2, H + 2 * N3, O3 + 2 * N3, s[2], lane);
+  wave_sync();
+  // faces: O_d -= sign area (Mh (x) Mh) {{p}} on the face plane; the own trace comes from global memory
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const double area = ci.h[t1] * ci.h[t2];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int e = sd ? N - 1 : 0;
+      const int64_t nb = nb_of(g, ci, cell, d, sd);
+      for (int q = lane; q < N2; q += 64) {
+        const int p1 = q % N, p2 = q / N;
+        const double own = p[cell * N3 + plane_node<N>(d, e, p1, p2)];
+        F[q] = nb >= 0 ? 0.5 * (own + p[nb * N3 + plane_node<N>(d, N - 1 - e, p1, p2)]) : own;
+      }
+      wave_sync();
+      for (int q = lane; q < N2; q += 64) {
+        const int p1 = q % N, p2 = q / N;
+        double r = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) r = fma(Mh[p1 * N + m], F[p2 * N + m], r);
+        F[N2 + q] = r;
+      }
+      wave_sync();
+      const double sg = (sd ? 1.0 : -1.0) * area;
+      for (int q = lane; q < N2; q += 64) {
+        const int p1 = q % N, p2 = q / N;
+        double r = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) r = fma(Mh[p2 * N + m], F[N2 + m * N + p1], r);
+        O3[d * N3 + plane_node<N>(d, e, p1, p2)] -= sg * r;
+      }
+      wave_sync();
+    }
+  }
+  for (int e = lane; e < 3 * N3; e += 64) out[(e / N3) * Nd + cell * N3 + e % N3] = O3[e];
+}
+
+// ------------------------------------------------------------------ tau_D --
+// tau = zeta |u_bar| V^(1/3) dt, u_bar_a = sum_i gw_i u_a,i (gw: basis integrals on the unit cube)
+template <int N>
+__global__ void __launch_bounds__(256) k_v3_tau(const double* __restrict__ u, const CartGeom<double> g,
+                                                const double* __restrict__ tab, double zeta, double dt,
+                                                double* __restrict__ tau, int64_t ncells) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t cell = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+  if (cell >= ncells) return;
+  const double* gw = tab + V3Tab{N}.gw();
+  const int64_t Nd = ncells * N3;
+  double a[3] = {0, 0, 0};
+  for (int e = lane; e < N3; e += 64) {
+    const double w = gw[e % N] * gw[(e / N) % N] * gw[e / N2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c] = fma(w, u[c * Nd + cell * N3 + e], a[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a[c] += __shfl_xor(a[c], o, 64);
+  if (lane == 0) {
+    const CellIdx ci = cell_of(g, cell);
+    const double vol = ci.h[0] * ci.h[1] * ci.h[2];
+    tau[cell] = zeta * sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) * cbrt(vol) * dt;
+  }
+}
+
+// ------------------------------------------------------ projection (CG) --
+template <int N>
+struct PShape {
+  static constexpr int N2 = N * N, N3 = N2 * N, V = 3 * N3;
+  static constexpr int SLICE = 5 * V + 2 * V + N3;   // x r z p q, two 3-component temporaries, div at points
+  static constexpr int BYTES = SLICE * 8;
+  static constexpr int WAVES = BYTES * 4 <= 58000 ? 4 : (BYTES * 2 <= 58000 ? 2 : 1);
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// q = (M_e (x) I_3 + tau D_e) p on one cell.  T1, T2: 3-component temporaries, DQ: N3.
+template <int N>
+__device__ __forceinline__ void proj_apply(const double* tb, const double* p, double* q, double* T1, double* T2,
+                                           double* DQ, const double (&hinv)[3], double vol, double tau, int lane) {
+  constexpr int N3 = N * N * N;
+  const V3Tab L{N};
+  const double* Mh = tb + L.Mh();
+  const double* S = tb + L.S();
+  const double* D = tb + L.D();
+  const double* w = tb + L.w();
+  // mass: q_a = vol Mh_z Mh_y Mh_x p_a
+  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mh, 0, p + a * N3, T1 + a * N3, 1.0, lane);
+  wave_sync();
+  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mh, 1, T1 + a * N3, T2 + a * N3, 1.0, lane);
+  wave_sync();
+  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mh, 2, T2 + a * N3, q + a * N3, vol, lane);
+  wave_sync();
+  if (tau == 0.0) return;   // uniform over the wavefront
+  // div at the Gauss points: sum_b hinv_b (D along b, S along the others) p_b
+  for (int b = 0; b < 3; ++b) sweep<N, false, false>(b == 0 ? D : S, 0, p + b * N3, T1 + b * N3, 1.0, lane);
+  wave_sync();
+  for (int b = 0; b < 3; ++b) sweep<N, false, false>(b == 1 ? D : S, 1, T1 + b * N3, T2 + b * N3, 1.0, lane);
+  wave_sync();
+  sweep<N, false, false>(S, 2, T2, DQ, hinv[0], lane);
+  wave_sync();
+  sweep<N, false, true>(S, 2, T2 + N3, DQ, hinv[1], lane);
+  wave_sync();
+  sweep<N, false, true>(D, 2, T2 + 2 * N3, DQ, hinv[2], lane);
+  wave_sync();
+  for (int e = lane; e < N3; e += 64) DQ[e] *= tau * vol * w[e % N] * w[(e / N) % N] * w[e / (N * N)];
+  wave_sync();
+  // q_a += hinv_a (D along a, S along the others)^T DQ
+  for (int a = 0; a < 3; ++a) sweep<N, true, false>(a == 2 ? D : S, 2, DQ, T1 + a * N3, 1.0, lane);
+  wave_sync();
+  for (int a = 0; a < 3; ++a) sweep<N, true, false>(a == 1 ? D : S, 1, T1 + a * N3, T2 + a * N3, 1.0, lane);
+  wave_sync();
+  for (int a = 0; a < 3; ++a) sweep<N, true, true>(a == 0 ? D : S, 0, T2 + a * N3, q + a * N3, hinv[a], lane);
+  wave_sync();
+}
+
+// z = M_e^{-1} r = (1/vol) Mi_z Mi_y Mi_x r per component
+template <int N>
+__device__ __forceinline__ void proj_precond(const double* tb, const double* r, double* z, double* T1, double* T2,
+                                             double vol, int lane) {
+  constexpr int N3 = N * N * N;
+  const double* Mi = tb + V3Tab{N}.Mi();
+  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mi, 0, r + a * N3, T1 + a * N3, 1.0, lane);
+  wave_sync();
+  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mi, 1, T1 + a * N3, T2 + a * N3, 1.0, lane);
+  wave_sync();
+  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mi, 2, T2 + a * N3, z + a * N3, 1.0 / vol, lane);
+  wave_sync();
+}
+
+template <int N>
+__global__ void __launch_bounds__(64 * PShape<N>::WAVES) k_v3_projection(
+    const double* __restrict__ rhs, double* __restrict__ xg, const CartGeom<double> g,
+    const double* __restrict__ tab, const double* __restrict__ taus, double rtol, int max_iter, int* iters,
+    int64_t ncells) {
+  using SH = PShape<N>;
+  constexpr int N3 = SH::N3, V = SH::V;
+  __shared__ double s_tab[V3Shape<N>::TABN];
+  __shared__ double s_all[SH::WAVES * SH::SLICE];
+  for (int e = threadIdx.x; e < V3Shape<N>::TABN; e += blockDim.x) s_tab[e] = tab[e];
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t cell = static_cast<int64_t>(blockIdx.x) * SH::WAVES + wave;
+  if (cell >= ncells) return;
+  double* x = s_all + wave * SH::SLICE;
+  double* r = x + V;
+  double* z = r + V;
+  double* p = z + V;
+  double* q = p + V;
+  double* T1 = q + V;
+  double* T2 = T1 + V;
+  double* DQ = T2 + V;
+  const int64_t Nd = ncells * N3;
+  const CellIdx ci = cell_of(g, cell);
+  const double vol = ci.h[0] * ci.h[1] * ci.h[2];
+  const double hinv[3] = {1.0 / ci.h[0], 1.0 / ci.h[1], 1.0 / ci.h[2]};
+  const double tau = taus[cell];
+  double bb = 0;
+  for (int e = lane; e < V; e += 64) {
+    const int64_t at = (e / N3) * Nd + cell * N3 + e % N3;
+    x[e] = xg[at];
+    const double b = rhs[at];
+    r[e] = b;
+    bb = fma(b, b, bb);
+  }
+  bb = wave_sum(bb);
+  wave_sync();
+  proj_apply<N>(s_tab, x, q, T1, T2, DQ, hinv, vol, tau, lane);
+  double rr = 0;
+  for (int e = lane; e < V; e += 64) {
+    const double t = r[e] - q[e];
+    r[e] = t;
+    rr = fma(t, t, rr);
+  }
+  rr = wave_sum(rr);
+  wave_sync();
+  const double tol2 = rtol * rtol * bb;
+  int it = 0;
+  if (rr > tol2) {
+    proj_precond<N>(s_tab, r, z, T1, T2, vol, lane);
+    double rz = 0;
+    for (int e = lane; e < V; e += 64) {
+      p[e] = z[e];
+      rz = fma(r[e], z[e], rz);
+    }
+    rz = wave_sum(rz);
+    wave_sync();
+    while (it < max_iter) {
+      proj_apply<N>(s_tab, p, q, T1, T2, DQ, hinv, vol, tau, lane);
+      double pq = 0;
+      for (int e = lane; e < V; e += 64) pq = fma(p[e], q[e], pq);
+      pq = wave_sum(pq);
+      if (!(pq > 0)) break;    // breakdown (only for a non-positive tau)
+      const double alpha = rz / pq;
+      rr = 0;
+      for (int e = lane; e < V; e += 64) {
+        x[e] = fma(alpha, p[e], x[e]);
+        const double t = fma(-alpha, q[e], r[e]);
+        r[e] = t;
+        rr = fma(t, t, rr);
+      }
+      rr = wave_sum(rr);
+      ++it;
+      wave_sync();
+      if (rr <= tol2) break;
+      proj_precond<N>(s_tab, r, z, T1, T2, vol, lane);
+      double rz1 = 0;
+      for (int e = lane; e < V; e += 64) rz1 = fma(r[e], z[e], rz1);
+      rz1 = wave_sum(rz1);
+      const double beta = rz1 / rz;
+      rz = rz1;
+      for (int e = lane; e < V; e += 64) p[e] = fma(beta, p[e], z[e]);
+      wave_sync();
+    }
+  }
+  for (int e = lane; e < V; e += 64) xg[(e / N3) * Nd + cell * N3 + e % N3] = x[e];
+  if (iters && lane == 0) iters[cell] = it;
+}
+
+template <int N>
+constexpr int xwaves() {
+  return (9 * N * N * N + 2 * N * N) * 8 * 4 <= 58000 ? 4 : ((9 * N * N * N + 2 * N * N) * 8 * 2 <= 58000 ? 2 : 1);
+}
+
+template <int N>
+dgmf_status div_n(bool grad, const CartGeom<double>& g, const double* tab, const double* in, double* out,
+                  int64_t ncells, hipStream_t s) {
+  constexpr int W = xwaves<N>();
+  const int64_t blocks = (ncells + W - 1) / W;
+  if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "v3: too many cells for one launch");
+  if (grad) {
+    hipLaunchKernelGGL((k_v3_gradient<N, W>), dim3(static_cast<unsigned>(blocks)), dim3(64 * W), 0, s, in, out, g,
+                       tab, ncells);
+    DGMF_LAUNCH_CHECK("k_v3_gradient");
+  } else {
+    hipLaunchKernelGGL((k_v3_divergence<N, W>), dim3(static_cast<unsigned>(blocks)), dim3(64 * W), 0, s, in, out, g,
+                       tab, ncells);
+    DGMF_LAUNCH_CHECK("k_v3_divergence");
+  }
+  return DGMF_OK;
+}
+
+dgmf_status div_dispatch(int n, bool grad, const CartGeom<double>& g, const double* tab, const double* in,
+                         double* out, int64_t ncells, hipStream_t s) {
+  switch (n) {
+    case 2: return div_n<2>(grad, g, tab, in, out, ncells, s);
+    case 3: return div_n<3>(grad, g, tab, in, out, ncells, s);
+    case 4: return div_n<4>(grad, g, tab, in, out, ncells, s);
+    case 5: return div_n<5>(grad, g, tab, in, out, ncells, s);
+    case 6: return div_n<6>(grad, g, tab, in, out, ncells, s);
+    case 7: return div_n<7>(grad, g, tab, in, out, ncells, s);
+    case 8: return div_n<8>(grad, g, tab, in, out, ncells, s);
+    default: return fail(DGMF_UNSUPPORTED, "v3: n = %d not built", n);
+  }
+}
+
+template <int N>
+dgmf_status tau_n(const CartGeom<double>& g, const double* tab, const double* u, double zeta, double dt, double* tau,
+                  int64_t ncells, hipStream_t s) {
+  const int64_t blocks = (ncells + 3) / 4;
+  hipLaunchKernelGGL((k_v3_tau<N>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, u, g, tab, zeta, dt, tau,
+                     ncells);
+  DGMF_LAUNCH_CHECK("k_v3_tau");
+  return DGMF_OK;
+}
+
+template <int N>
+dgmf_status proj_n(const CartGeom<double>& g, const double* tab, const double* tau, const double* rhs, double* x,
+                   double rtol, int max_iter, int* iters, int64_t ncells, hipStream_t s) {
+  constexpr int W = PShape<N>::WAVES;
+  const int64_t blocks = (ncells + W - 1) / W;
+  if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "v3: too many cells for one launch");
+  hipLaunchKernelGGL((k_v3_projection<N>), dim3(static_cast<unsigned>(blocks)), dim3(64 * W), 0, s, rhs, x, g, tab,
+                     tau, rtol, max_iter, iters, ncells);
+  DGMF_LAUNCH_CHECK("k_v3_projection");
+  return DGMF_OK;
+}
+
+}  // namespace
+
+dgmf_status launch_v3_divergence(int n, const CartGeom<double>& g, const double* tab, const double* u, double* out,
+                                 int64_t ncells, hipStream_t s) {
+  return div_dispatch(n, false, g, tab, u, out, ncells, s);
+}
+
+dgmf_status launch_v3_gradient(int n, const CartGeom<double>& g, const double* tab, const double* p, double* out,
+                               int64_t ncells, hipStream_t s) {
+  return div_dispatch(n, true, g, tab, p, out, ncells, s);
+}
+
+dgmf_status launch_v3_tau(int n, const CartGeom<double>& g, const double* tab, const double* u, double zeta,
+                          double dt, double* tau, int64_t ncells, hipStream_t s) {
+  if ((ncells + 3) / 4 > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "v3: too many cells for one launch");
+  switch (n) {
+    case 2: return tau_n<2>(g, tab, u, zeta, dt, tau, ncells, s);
+    case 3: return tau_n<3>(g, tab, u, zeta, dt, tau, ncells, s);
+    case 4: return tau_n<4>(g, tab, u, zeta, dt, tau, ncells, s);
+    case 5: return tau_n<5>(g, tab, u, zeta, dt, tau, ncells, s);
+    case 6: return tau_n<6>(g, tab, u, zeta, dt, tau, ncells, s);
+    case 7: return tau_n<7>(g, tab, u, zeta, dt, tau, ncells, s);
+    case 8: return tau_n<8>(g, tab, u, zeta, dt, tau, ncells, s);
+    default: return fail(DGMF_UNSUPPORTED, "v3: n = %d not built", n);
+  }
+}
+
+bool v3_projection_supported(int n) { return n >= 2 && n <= 7; }
+
+dgmf_status launch_v3_projection(int n, const CartGeom<double>& g, const double* tab, const double* tau,
+                                 const double* rhs, double* x, double rtol, int max_iter, int* iters, int64_t ncells,
+                                 hipStream_t s) {
+  switch (n) {
+    case 2: return proj_n<2>(g, tab, tau, rhs, x, rtol, max_iter, iters, ncells, s);
+    case 3: return proj_n<3>(g, tab, tau, rhs, x, rtol, max_iter, iters, ncells, s);
+    case 4: return proj_n<4>(g, tab, tau, rhs, x, rtol, max_iter, iters, ncells, s);
+    case 5: return proj_n<5>(g, tab, tau, rhs, x, rtol, max_iter, iters, ncells, s);
+    case 6: return proj_n<6>(g, tab, tau, rhs, x, rtol, max_iter, iters, ncells, s);
+    case 7: return proj_n<7>(g, tab, tau, rhs, x, rtol, max_iter, iters, ncells, s);
+    default: return fail(DGMF_UNSUPPORTED, "projection: degree %d not built (k <= 6)", n - 1);
+  }
+}
+
+}  // namespace dgmf
