@@ -10,7 +10,8 @@ counter traffic when a committed profile matches the current kernel source),
 the fp32 apply, the CG time to 1e-10 (Jacobi fp64; mixed fp32-Chebyshev vs
 fp64), the convective forward + VJP throughput, the explicit convective
 substep U - dt M^{-1} C(U) (fused kernel vs the two-launch composition), the
-inverse mass apply, and the CPU oracle timed on a bounded sample.
+inverse mass apply, the variant-V3c divergence, gradient and element-local
+projection solve, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -231,6 +232,7 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     ex["c3_convective"] = {"fwd_us": tf * 1e6, "vjp_us": tv * 1e6, "fwd_dofs_per_s": n3 / tf, "vjp_dofs_per_s": n3 / tv,
                            "fwd_plus_vjp_dofs_per_s": n3 / (tf + tv), "dofs": n3}
     ex.update(step_measurements(m3, op3, U, Cout, "c3"))
+    ex.update(v3_measurements(m3, U, "c3"))
     m3.close()
     ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4, "c4"))
     ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4_SMALL, "c4small", cg=False))
@@ -264,6 +266,38 @@ def step_measurements(mesh, opc, U, C, tag, dt=1e-3):
                                      "hbm_frac": 16.0 * n3 / tm / 1e9 / HBM_PEAK_GBS, "fields": 3}
     ex[f"{tag}_inverse_mass_f32"] = {"us": tm32 * 1e6, "alg_GBps": 8.0 * n3 / tm32 / 1e9,
                                      "hbm_frac": 8.0 * n3 / tm32 / 1e9 / HBM_PEAK_GBS, "fields": 3}
+    return ex
+
+
+def v3_measurements(mesh, U, tag):
+    """Variant V3c operators on the velocity U [3][N]: divergence A (reads 3 fields,
+    writes 1: 32 B per scalar DoF), gradient B (reads 1, writes 3: 32 B), tau_D,
+    and the element-local projection solve (M_e + tau_e D_e) x = M U to 1e-12 from
+    zero with tau_D = |u_bar| h dt (zeta = 1, dt = 1e-2)."""
+    import torch
+    ex = {}
+    N = mesh.ndofs
+    P = U[:N].clone()
+    out1 = torch.empty(N, dtype=torch.float64, device="cuda")
+    out3 = torch.empty_like(U)
+    td = _events_time(lambda: mesh.divergence(U, out1), 20, 3)
+    tg = _events_time(lambda: mesh.gradient(P, out3), 20, 3)
+    tau = mesh.divdiv_penalty(U, 1.0, 1e-2)
+    rhs = mesh.mass(U)
+    x = torch.zeros_like(U)
+    its = torch.zeros(mesh.ncells, dtype=torch.int32, device="cuda")
+
+    def solve():
+        x.zero_()
+        mesh.projection_solve(tau, rhs, x=x, rtol=1e-12, max_iter=2000, iterations=its)
+
+    tp = _events_time(solve, 3, 1)
+    ex[f"{tag}_divergence"] = {"us": td * 1e6, "alg_GBps": 32.0 * N / td / 1e9,
+                               "hbm_frac": 32.0 * N / td / 1e9 / HBM_PEAK_GBS}
+    ex[f"{tag}_gradient"] = {"us": tg * 1e6, "alg_GBps": 32.0 * N / tg / 1e9,
+                             "hbm_frac": 32.0 * N / tg / 1e9 / HBM_PEAK_GBS}
+    ex[f"{tag}_projection"] = {"ms": tp * 1e3, "cells_per_s": mesh.ncells / tp,
+                               "iterations_max": int(its.max()), "iterations_mean": float(its.float().mean())}
     return ex
 
 
@@ -331,6 +365,8 @@ def channel_measurements(dg, inp, torch, w, tag, cg=True):
                                "vjp_dofs_per_s": 3 * N / tv, "fwd_plus_vjp_dofs_per_s": 3 * N / (tf + tv),
                                "dofs": 3 * N, "n_q": w.conv_points or (3 * n) // 2}
     ex.update(step_measurements(m, opc, U, Cout, tag))
+    if cg:
+        ex.update(v3_measurements(m, U, tag))
     m.close()
     return ex
 
