@@ -31,6 +31,7 @@ rng         SplitMix64 counter-based generator (published definition)
 multigrid   geometric multigrid V-cycle preconditioner (Sec. 5.1, Poisson solver)
 v3          divergence and gradient operators, mass, div-div penalty and the
             local projection of variant V3c (eqs. av3, bv3, div-div, tauD, project)
+viscous     the viscous operator in the symmetric-gradient form (SIPG, Sec. 3.2)
 mass        block-diagonal inverse mass matrix and the explicit convective
             substep of the matrix form (eq. advect)
 

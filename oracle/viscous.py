@@ -1,0 +1,138 @@
+"""Viscous operator in the symmetric-gradient form (oracle; test infrastructure).
+
+Sec. 3.2, implicit viscous step, with s = 1 (SIPG) and F^nu(u) = 2 nu eps(u),
+eps(u) = (grad u + grad u^T)/2, homogeneous Dirichlet data on boundary faces
+(g_u = 0) and no Neumann faces:
+
+  a(v, u) = mu (v, u) + sum_K (eps(v), 2 nu eps(u))_K
+          - sum_F ({{2 nu eps(v)}}, [u] (x) n)_F - sum_F ([v], {{2 nu eps(u)}} n)_F
+          + sum_F tau nu ([v], [u])_F,
+
+on interior faces with n the unit normal of the minus side and [w] = w- - w+;
+on a boundary face the averages are the own values, [w] = w, and the penalty
+is 2 tau nu.  tau is the SIPG penalty of eqs. taue/tau.  Cell and face
+integrals by Gauss quadrature with k+1 points, dense blocks from Kronecker
+evaluation matrices, assembled into a sparse 3N x 3N matrix acting on
+[u_x; u_y; u_z].
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from . import sipg
+
+
+def _face_grads(T, J, f):
+    """Trace Tr, physical gradient matrices grad[a] at the face points, dA, unit normal towards +d."""
+    d, s = divmod(f, 2)
+    Jinv = np.linalg.inv(J)
+    detJ = abs(np.linalg.det(J))
+    m = Jinv.T[:, d]
+    nrm = m / np.linalg.norm(m)
+    val = [T.S, T.S, T.S]
+    val[d] = T.e[s]
+    Tr = sipg._kron3(val[2], val[1], val[0])
+    G = []
+    for b in range(3):
+        mats = [T.S, T.S, T.S]
+        mats[d] = T.e[s]
+        mats[b] = T.de[s] if b == d else T.D
+        G.append(sipg._kron3(mats[2], mats[1], mats[0]))
+    grad = [sum(Jinv[b, a] * G[b] for b in range(3)) for a in range(3)]
+    wt = [T.wq, T.wq, T.wq]
+    wt[d] = np.ones(1)
+    dA = sipg._kron3(wt[2], wt[1], wt[0]) * detJ * np.linalg.norm(m)
+    return Tr, grad, dA, nrm
+
+
+def _cell_block(T, J, mu, nu):
+    """[c][c'] = mu delta M + nu (delta sum_a G_a^T W G_a + G_c'^T W G_c)."""
+    Phi = sipg._kron3(T.S, T.S, T.S)
+    G = sipg._ref_gradients_cell(T)
+    Jinv = np.linalg.inv(J)
+    grad = [sum(Jinv[b, a] * G[b] for b in range(3)) for a in range(3)]
+    w = sipg._kron3(T.wq, T.wq, T.wq) * abs(np.linalg.det(J))
+    M = Phi.T @ (w[:, None] * Phi)
+    K = sum(grad[a].T @ (w[:, None] * grad[a]) for a in range(3))
+    blk = [[None] * 3 for _ in range(3)]
+    for c in range(3):
+        for cp in range(3):
+            B = nu * (grad[cp].T @ (w[:, None] * grad[c]))
+            if c == cp:
+                B = B + mu * M + nu * K
+            blk[c][cp] = B
+    return blk
+
+
+def _face_terms(Tv, gradv, Tu, gradu, W, n, nu, pen):
+    """Boundary-face blocks [c][c'] of -(2nu eps(v), u (x) n) - (v, 2nu eps(u) n) + pen (v, u)
+    (own traces and gradients, n the outward normal)."""
+    Gnv = sum(n[a] * gradv[a] for a in range(3))
+    Gnu = sum(n[a] * gradu[a] for a in range(3))
+    blk = [[None] * 3 for _ in range(3)]
+    for c in range(3):
+        for cp in range(3):
+            B = -nu * (n[c] * (gradv[cp].T @ (W[:, None] * Tu)) + n[cp] * (Tv.T @ (W[:, None] * gradu[c])))
+            if c == cp:
+                B = B - nu * (Gnv.T @ (W[:, None] * Tu) + Tv.T @ (W[:, None] * Gnu)) + pen * (Tv.T @ (W[:, None] * Tu))
+            blk[c][cp] = B
+    return blk
+
+
+def viscous_matrix(m, mu, nu, penalty_scale=1.0):
+    """Sparse 3N x 3N matrix of a(v, u)."""
+    T = sipg.Tables(m.k)
+    nb, N = m.n ** 3, m.ndofs
+    tau = sipg.penalty_per_cell(m, penalty_scale)
+    rows, cols, vals = [], [], []
+
+    def add(c, cell_r, cp, cell_c, B):
+        r = c * N + cell_r * nb + np.arange(nb)
+        cc = cp * N + cell_c * nb + np.arange(nb)
+        R, Cc = np.meshgrid(r, cc, indexing="ij")
+        rows.append(R.ravel())
+        cols.append(Cc.ravel())
+        vals.append(B.ravel())
+
+    for cell in range(m.ncells):
+        blk = _cell_block(T, m.jacobian(cell), mu, nu)
+        for c in range(3):
+            for cp in range(3):
+                add(c, cell, cp, cell, blk[c][cp])
+    for cL, cR, d in m.interior_faces():
+        TrL, gL, dA, nrm = _face_grads(T, m.jacobian(cL), 2 * d + 1)
+        TrR, gR, _, _ = _face_grads(T, m.jacobian(cR), 2 * d)
+        pen = nu * max(tau[cL], tau[cR])
+        sides = ((cL, TrL, gL, 1.0), (cR, TrR, gR, -1.0))   # jump sign of each side
+        for (cv, Tv, gv, sv) in sides:
+            for (cu, Tu, gu, su) in sides:
+                blk = _interior_pair(Tv, gv, sv, Tu, gu, su, dA, nrm, nu, pen)
+                for c in range(3):
+                    for cp in range(3):
+                        add(c, cv, cp, cu, blk[c][cp])
+    for cell, f in m.boundary_faces():
+        Tr, g, dA, nrm = _face_grads(T, m.jacobian(cell), f)
+        n_out = nrm if f % 2 == 1 else -nrm
+        blk = _face_terms(Tr, g, Tr, g, dA, n_out, nu, 2.0 * nu * tau[cell])
+        for c in range(3):
+            for cp in range(3):
+                add(c, cell, cp, cell, blk[c][cp])
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(3 * N, 3 * N))
+    return A.tocsr()
+
+
+def _interior_pair(Tv, gv, sv, Tu, gu, su, W, n, nu, pen):
+    """Interior-face blocks between a test side (sign sv in [v]) and a trial side (su in [u]):
+    -({{2nu eps(v)}}, [u] (x) n) takes 1/2 of the test side's eps and the trial side's jump;
+    -([v], {{2nu eps(u)}} n) the test side's jump and 1/2 of the trial side's eps."""
+    Gnv = sum(n[a] * gv[a] for a in range(3))
+    Gnu = sum(n[a] * gu[a] for a in range(3))
+    blk = [[None] * 3 for _ in range(3)]
+    for c in range(3):
+        for cp in range(3):
+            B = -nu * (0.5 * su * n[c] * (gv[cp].T @ (W[:, None] * Tu))
+                       + 0.5 * sv * n[cp] * (Tv.T @ (W[:, None] * gu[c])))
+            if c == cp:
+                B = B - nu * (0.5 * su * (Gnv.T @ (W[:, None] * Tu)) + 0.5 * sv * (Tv.T @ (W[:, None] * Gnu)))
+                B = B + pen * sv * su * (Tv.T @ (W[:, None] * Tu))
+            blk[c][cp] = B
+    return blk
