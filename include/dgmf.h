@@ -177,6 +177,14 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
 /* dst = H src.  src, dst: device arrays of N values of the given dtype;
  * must not alias.  Asynchronous on stream. */
 dgmf_status dgmf_operator_apply(dgmf_op op, dgmf_dtype dtype, const void* src, void* dst, hipStream_t stream);
+/* out = H_eps u for a velocity u [3][N] (fp64): the viscous operator of the
+ * implicit viscous step in its symmetric-gradient form (Sec. 3.2, s = 1,
+ * F^nu(u) = 2 nu eps(u), fluxes U* and F^nu* with penalty tau nu, boundary
+ * faces with g_u = 0 and penalty 2 tau nu), plus mass_coeff M, with the
+ * operator's coefficients and penalty.  Computed as this operator applied to
+ * every component plus nu times the component coupling.  Axis-aligned meshes
+ * (sheared: DGMF_UNSUPPORTED).  u, out must not overlap.  Asynchronous. */
+dgmf_status dgmf_viscous_apply(dgmf_op op, const double* u, double* out, hipStream_t stream);
 /* diag = diag(H), N values of dtype.  Asynchronous. */
 dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hipStream_t stream);
 /* Cell quadrature points of the operator's rule: xyz device double [3][n_cells*n_q^3],

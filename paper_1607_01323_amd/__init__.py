@@ -74,6 +74,7 @@ _mesh_destroy = _sig("dgmf_mesh_destroy", _vp)
 _inv_mass = _sig("dgmf_inverse_mass_apply", _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp)
 _mass = _sig("dgmf_mass_apply", _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp)
 _div = _sig("dgmf_divergence_apply", _vp, _vp, _vp, _vp)
+_visc = _sig("dgmf_viscous_apply", _vp, _vp, _vp, _vp)
 _grad = _sig("dgmf_gradient_apply", _vp, _vp, _vp, _vp)
 _divdiv_tau = _sig("dgmf_divdiv_penalty", _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp)
 _proj = _sig("dgmf_projection_solve", _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp)
@@ -260,6 +261,15 @@ class SipgOperator(_Op):
             out = torch.empty_like(src)
         _check(_apply(self._h, dt, _ptr(src, src.dtype, self.mesh.ndofs, "src"),
                       _ptr(out, src.dtype, self.mesh.ndofs, "dst"), _stream()), "operator_apply")
+        return out
+
+    def viscous_apply(self, u, out=None):
+        """H_eps u for a velocity [3][N]: mu M + the SIPG form of (eps(v), 2 nu eps(u))."""
+        n = 3 * self.mesh.ndofs
+        if out is None:
+            out = torch.empty_like(u)
+        _check(_visc(self._h, _ptr(u, torch.float64, n, "u"), _ptr(out, torch.float64, n, "out"), _stream()),
+               "viscous_apply")
         return out
 
     def diagonal(self, dtype=torch.float64):

@@ -476,6 +476,14 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
     for (int i = 0; i < n; ++i) {
       v3[L.w() + i] = t.wq[i];
       v3[L.gw() + i] = t.gll_w[i];
+      v3[L.g0() + i] = t.g0[i];
+      v3[L.g1() + i] = t.g1[i];
+      std::vector<double> der(n);
+      lagrange_eval(t.nodes, t.nodes[i], nullptr, der.data());
+      for (int j = 0; j < n; ++j) {
+        v3[L.Kh() + i * n + j] = t.Khat[i * n + j];
+        v3[L.Dn() + i * n + j] = der[j];
+      }
     }
     std::vector<float> mh32(t.Mhat.begin(), t.Mhat.end());
     if (st == DGMF_OK) st = m->v3tab.upload(v3.data(), v3.size() * sizeof(double));
@@ -562,6 +570,21 @@ static dgmf_status v3_check(dgmf_mesh mesh, const char* who) {
   if (!mesh) return fail(DGMF_INVALID, "%s: null mesh", who);
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "%s: sheared meshes are not supported", who);
   return DGMF_OK;
+}
+
+dgmf_status dgmf_viscous_apply(dgmf_op op, const double* u, double* out, hipStream_t stream) {
+  if (!op || op->kind != 1) return fail(DGMF_INVALID, "viscous_apply: not an SIPG operator");
+  dgmf_status e = v3_check(op->mesh, "viscous_apply");
+  if (e) return e;
+  if (!u || !out || !aligned(u, 8) || !aligned(out, 8))
+    return fail(DGMF_INVALID, "viscous_apply: null or misaligned vector");
+  const int64_t N = op->mesh->ndofs;
+  if (overlap(u, out, 24 * N)) return fail(DGMF_INVALID, "viscous_apply: u and out overlap");
+  DeviceGuard dg(op->mesh->device);
+  for (int a = 0; a < 3; ++a)
+    if ((e = sipg_apply<double>(op, u + a * N, out + a * N, nullptr, nullptr, stream))) return e;
+  return launch_eps_coupling(op->mesh->tab.n, op->mesh->g64, static_cast<const double*>(op->mesh->v3tab.p), u, out,
+                             op->sipg.diff_coeff, op->mesh->ncells, stream);
 }
 
 dgmf_status dgmf_divergence_apply(dgmf_mesh mesh, const double* u, double* out, hipStream_t stream) {

@@ -236,7 +236,12 @@ struct V3Tab {
   __host__ __device__ int D() const { return 4 * n * n; }
   __host__ __device__ int w() const { return 5 * n * n; }
   __host__ __device__ int gw() const { return 5 * n * n + n; }
-  __host__ __device__ int size() const { return 5 * n * n + 2 * n; }
+  // viscous coupling: Kh (int l_i' l_j'), Dn (l_j'(x_i) at the nodes), l'(0), l'(1)
+  __host__ __device__ int Kh() const { return 5 * n * n + 2 * n; }
+  __host__ __device__ int Dn() const { return 6 * n * n + 2 * n; }
+  __host__ __device__ int g0() const { return 7 * n * n + 2 * n; }
+  __host__ __device__ int g1() const { return 7 * n * n + 3 * n; }
+  __host__ __device__ int size() const { return 7 * n * n + 4 * n; }
 };
 dgmf_status launch_v3_divergence(int n, const CartGeom<double>& g, const double* tab, const double* u, double* out,
                                  int64_t ncells, hipStream_t s);
@@ -244,6 +249,10 @@ dgmf_status launch_v3_gradient(int n, const CartGeom<double>& g, const double* t
                                int64_t ncells, hipStream_t s);
 dgmf_status launch_v3_tau(int n, const CartGeom<double>& g, const double* tab, const double* u, double zeta,
                           double dt, double* tau, int64_t ncells, hipStream_t s);
+// out += nu C(u), the component coupling of the symmetric-gradient viscous
+// operator (u, out: [3][N]); see eps.hip.
+dgmf_status launch_eps_coupling(int n, const CartGeom<double>& g, const double* tab, const double* u, double* out,
+                                double nu, int64_t ncells, hipStream_t s);
 bool v3_projection_supported(int n);
 dgmf_status launch_v3_projection(int n, const CartGeom<double>& g, const double* tab, const double* tau,
                                  const double* rhs, double* x, double rtol, int max_iter, int* iters, int64_t ncells,

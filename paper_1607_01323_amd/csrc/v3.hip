@@ -98,7 +98,7 @@ __device__ __forceinline__ void sweep(const double* M, int axis, const double* i
 template <int N>
 struct V3Shape {
   static constexpr int N2 = N * N, N3 = N2 * N;
-  static constexpr int TABN = 5 * N2 + 2 * N;
+  static constexpr int TABN = 5 * N2 + 2 * N;   // the V3Tab entries these kernels use
 };
 
 // ------------------------------------------------------------ divergence --
