@@ -11,7 +11,8 @@ the fp32 apply, the CG time to 1e-10 (Jacobi fp64; mixed fp32-Chebyshev vs
 fp64), the convective forward + VJP throughput, the explicit convective
 substep U - dt M^{-1} C(U) (fused kernel vs the two-launch composition), the
 inverse mass apply, the variant-V3c divergence, gradient and element-local
-projection solve, and the CPU oracle timed on a bounded sample.
+projection solve, the symmetric-gradient viscous operator, and the CPU oracle
+timed on a bounded sample.
 """
 import argparse
 import json
@@ -146,6 +147,14 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     t32 = _events_time(lambda: op_c1.apply(u32, y32), 100, 5)
     ex["c1_apply_f32"] = {"dofs_per_s": N / t32, "alg_GBps": 8.0 * N / t32 / 1e9, "us": t32 * 1e6}
     ex["c1_apply_f64"] = {"dofs_per_s": N / t_c1, "alg_GBps": 16.0 * N / t_c1 / 1e9, "us": t_c1 * 1e6}
+    # symmetric-gradient viscous operator on a velocity (3 scalar applies + the coupling kernel);
+    # algorithmic bytes 48 per velocity node (3 reads, 3 writes)
+    Uv = torch.as_tensor(inp.uniform(12, 3 * N), device="cuda")
+    Yv = torch.empty_like(Uv)
+    tv = _events_time(lambda: op_c1.viscous_apply(Uv, Yv), 20, 3)
+    ex["c1_viscous_eps"] = {"us": tv * 1e6, "velocity_nodes_per_s": N / tv, "alg_GBps": 48.0 * N / tv / 1e9,
+                            "vs_three_scalar_applies": tv / (3 * t_c1)}
+    del Uv, Yv
     # the same apply with a 512 MiB write between repetitions, so that its 33 MB
     # working set is not resident in the 256 MB Infinity Cache
     flush = torch.empty(512 * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
