@@ -242,6 +242,8 @@ typedef struct {
   int flexible;          /* 0: beta = <r+,z+>/<r,z> (Fletcher-Reeves); 1: beta = <z+, r+ - r>/<r,z>
                             (Polak-Ribiere, flexible CG: robust to the rounding of an fp32 preconditioner) */
   double mg_coarse_tol;  /* precond 2: coarse Chebyshev error estimate target, 0 -> 1e-3 */
+  int mg_graph;          /* precond 2: 1 replays the V-cycle from a captured HIP graph (kept with the
+                            hierarchy, one per workspace), 0 launches it kernel by kernel */
 } dgmf_cg_params;
 
 typedef struct {

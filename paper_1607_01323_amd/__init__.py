@@ -45,7 +45,7 @@ class CgParams(ctypes.Structure):
                 ("precond", ctypes.c_int), ("precond_dtype", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("smoothing_range", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
                 ("lambda_safety", ctypes.c_double), ("seed", ctypes.c_uint64), ("project_mean", ctypes.c_int),
-                ("flexible", ctypes.c_int), ("mg_coarse_tol", ctypes.c_double)]
+                ("flexible", ctypes.c_int), ("mg_coarse_tol", ctypes.c_double), ("mg_graph", ctypes.c_int)]
 
 
 class CgResult(ctypes.Structure):
@@ -294,20 +294,21 @@ class SipgOperator(_Op):
     _PRECONDS = {"jacobi": 0, "chebyshev": 1, "multigrid": 2}
 
     def _params(self, rtol, max_iter, check_every, precond, precond_dtype, cheb_degree, smoothing_range,
-                lanczos_steps, lambda_safety, seed, project_mean, flexible, mg_coarse_tol):
+                lanczos_steps, lambda_safety, seed, project_mean, flexible, mg_coarse_tol, mg_graph=True):
         if precond not in self._PRECONDS:
             raise ValueError(f"precond must be one of {sorted(self._PRECONDS)}")
         if flexible is None:
             flexible = precond != "jacobi" and precond_dtype == torch.float32
         return CgParams(rtol, max_iter, check_every, self._PRECONDS[precond],
                         F64 if precond_dtype == torch.float64 else F32, cheb_degree, smoothing_range, lanczos_steps,
-                        lambda_safety, seed, int(bool(project_mean)), int(bool(flexible)), mg_coarse_tol)
+                        lambda_safety, seed, int(bool(project_mean)), int(bool(flexible)), mg_coarse_tol,
+                        int(bool(mg_graph)))
 
     def precond_apply(self, r, precond_dtype=torch.float32, cheb_degree=5, smoothing_range=20.0, lanczos_steps=15,
-                      lambda_safety=1.2, seed=0, project_mean=False, mg_coarse_tol=0.0, out=None):
+                      lambda_safety=1.2, seed=0, project_mean=False, mg_coarse_tol=0.0, out=None, mg_graph=True):
         """z = B r, one multigrid V-cycle (fp64 in and out, computed in precond_dtype)."""
         p = self._params(0.0, 0, 1, "multigrid", precond_dtype, cheb_degree, smoothing_range, lanczos_steps,
-                         lambda_safety, seed, project_mean, False, mg_coarse_tol)
+                         lambda_safety, seed, project_mean, False, mg_coarse_tol, mg_graph)
         n = self.mesh.ndofs
         if out is None:
             out = torch.empty_like(r)
@@ -325,14 +326,14 @@ class SipgOperator(_Op):
 
     def cg(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, precond="jacobi", precond_dtype=torch.float64,
            cheb_degree=5, smoothing_range=20.0, lanczos_steps=15, lambda_safety=1.2, seed=0, project_mean=False,
-           flexible=None, raise_on_failure=True, mg_coarse_tol=0.0):
+           flexible=None, raise_on_failure=True, mg_coarse_tol=0.0, mg_graph=True):
         """PCG on H x = b; x (fp64, device) holds the initial guess and receives the solution.
 
         precond: "jacobi", "chebyshev" or "multigrid".  flexible=None picks the
         Polak-Ribiere (flexible) beta exactly when the preconditioner runs in fp32.
         """
         p = self._params(rtol, max_iter, check_every, precond, precond_dtype, cheb_degree, smoothing_range,
-                         lanczos_steps, lambda_safety, seed, project_mean, flexible, mg_coarse_tol)
+                         lanczos_steps, lambda_safety, seed, project_mean, flexible, mg_coarse_tol, mg_graph)
         nbytes = ctypes.c_size_t()
         _check(_ws_bytes(self._h, ctypes.byref(p), ctypes.byref(nbytes)), "cg_workspace_bytes")
         ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device="cuda")

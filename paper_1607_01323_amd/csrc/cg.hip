@@ -438,6 +438,7 @@ dgmf_status validate(dgmf_op op, const dgmf_cg_params* p) {
   }
   if (p->precond == 2 && !(p->mg_coarse_tol >= 0 && p->mg_coarse_tol < 1))
     return fail(DGMF_INVALID, "cg: mg_coarse_tol must be in [0, 1)");
+  if (p->precond == 2 && p->mg_graph != 0 && p->mg_graph != 1) return fail(DGMF_INVALID, "cg: mg_graph must be 0 or 1");
   return DGMF_OK;
 }
 
@@ -607,7 +608,13 @@ struct MgHierarchy {
   dgmf_cg_params key{};
   std::vector<MgLevel> lv;
   DevBuf scratch;
+  // captured V-cycles (HIP graphs) keyed by the stop flag their kernels read,
+  // and the private stream they are captured on
+  hipStream_t cap = nullptr;
+  std::vector<std::pair<const int*, hipGraphExec_t>> graphs;
   ~MgHierarchy() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (cap) (void)hipStreamDestroy(cap);
     for (auto& l : lv)
       if (l.owned) {
         l.vec.release();
@@ -907,6 +914,45 @@ dgmf_status vcycle(MgHierarchy& h, int l, const int* stop, hipStream_t s) {
   return DGMF_OK;
 }
 
+constexpr size_t kMaxGraphs = 4;
+
+// The whole V-cycle on stream s: launched kernel by kernel, or (graph) replayed
+// from a HIP graph captured once per stop flag on the hierarchy's own stream.
+// The coarse levels are launch-latency bound, and the graph removes the host
+// launch gaps between their ~150 small kernels.  The V-cycle records no
+// memset or copy, only kernels with fixed arguments.
+template <typename T>
+dgmf_status vcycle_run(MgHierarchy& h, const int* stop, bool graph, hipStream_t s) {
+  if (!graph) return vcycle<T>(h, 0, stop, s);
+  for (auto& g : h.graphs)
+    if (g.first == stop) {
+      DGMF_HIP_TRY(hipGraphLaunch(g.second, s));
+      return DGMF_OK;
+    }
+  if (!h.cap) DGMF_HIP_TRY(hipStreamCreateWithFlags(&h.cap, hipStreamNonBlocking));
+  DGMF_HIP_TRY(hipStreamBeginCapture(h.cap, hipStreamCaptureModeThreadLocal));
+  dgmf_status e = vcycle<T>(h, 0, stop, h.cap);
+  hipGraph_t gr = nullptr;
+  const hipError_t ce = hipStreamEndCapture(h.cap, &gr);
+  if (e) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return e;
+  }
+  if (ce != hipSuccess || !gr)
+    return fail(DGMF_HIP_ERROR, "multigrid: V-cycle capture failed: %s", hipGetErrorString(ce));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (ie != hipSuccess) return fail(DGMF_HIP_ERROR, "multigrid: graph instantiation failed: %s", hipGetErrorString(ie));
+  if (h.graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(h.graphs.front().second);
+    h.graphs.erase(h.graphs.begin());
+  }
+  h.graphs.push_back({stop, ex});
+  DGMF_HIP_TRY(hipGraphLaunch(ex, s));
+  return DGMF_OK;
+}
+
 struct Solver {
   dgmf_op op;
   const dgmf_cg_params& prm;
@@ -975,7 +1021,7 @@ struct Solver {
   dgmf_status mg_apply(const double* r, double* z, const double* q) {
     MgLevel& a = op->mgh->lv[0];
     dgmf_status e = launch_mg_cast_in<T>(r, a.v<T>(0), N, &st->status, s);
-    if (e || (e = vcycle<T>(*op->mgh, 0, &st->status, s))) return e;
+    if (e || (e = vcycle_run<T>(*op->mgh, &st->status, prm.mg_graph != 0, s))) return e;
     hipLaunchKernelGGL((k_mg_out<T>), dim3(kVecBlocks), dim3(256), 0, s, a.v<T>(a.xout), r, z, q, N, st, partials);
     DGMF_LAUNCH_CHECK("k_mg_out");
     return DGMF_OK;
@@ -1174,11 +1220,11 @@ dgmf_status dgmf_precond_apply(dgmf_op op, const dgmf_cg_params* params, const d
   MgLevel& a = op->mgh->lv[0];
   if (params->precond_dtype == DGMF_F32) {
     if ((e = launch_mg_cast_in<float>(r, a.v<float>(0), N, nullptr, stream))) return e;
-    if ((e = vcycle<float>(*op->mgh, 0, nullptr, stream))) return e;
+    if ((e = vcycle_run<float>(*op->mgh, nullptr, params->mg_graph != 0, stream))) return e;
     return launch_mg_cast_out<float>(a.v<float>(a.xout), z, N, stream);
   }
   if ((e = launch_mg_cast_in<double>(r, a.v<double>(0), N, nullptr, stream))) return e;
-  if ((e = vcycle<double>(*op->mgh, 0, nullptr, stream))) return e;
+  if ((e = vcycle_run<double>(*op->mgh, nullptr, params->mg_graph != 0, stream))) return e;
   return launch_mg_cast_out<double>(a.v<double>(a.xout), z, N, stream);
 }
 

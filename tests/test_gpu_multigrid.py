@@ -164,3 +164,30 @@ def test_full_size_channel_mg():
     print(f"[result] channel MG iterations {out.iterations}", flush=True)
     assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
     gm.close()
+
+
+def test_graph_replays_match_eager_launches():
+    """The V-cycle replayed from its captured HIP graph equals the kernel-by-kernel
+    launches bit for bit, on every replay, with eager work in between."""
+    require_gpu()
+    c = CASES["k3_aniso_coarsening"]
+    om, gm, gop, singular = _setup(*c)
+    rs = [dev(inp.uniform(100 + i, om.ndofs)) for i in range(3)]
+    kw = dict(precond_dtype=torch.float32, seed=42, project_mean=singular)
+    eager = [host(gop.precond_apply(r, mg_graph=False, **kw)) for r in rs]
+    for rep in range(4):
+        for i, r in enumerate(rs):
+            z = host(gop.precond_apply(r, mg_graph=True, **kw))
+            assert np.array_equal(z, eager[i]), (rep, i)
+            torch.cuda.synchronize()
+            _ = host(gop.precond_apply(rs[(i + 1) % 3], mg_graph=False, **kw))   # eager work between replays
+    b = inp.uniform(5, om.ndofs)
+    outs = []
+    for graph in (False, True, True):
+        x = dev(np.zeros(om.ndofs))
+        o = gop.cg(dev(b), x, rtol=1e-10, max_iter=200, check_every=2, precond="multigrid",
+                   precond_dtype=torch.float32, seed=42, project_mean=singular, mg_graph=graph)
+        outs.append((o.iterations, host(x)))
+    assert outs[0][0] == outs[1][0] == outs[2][0]
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[1][1], outs[2][1])
+    gm.close()
