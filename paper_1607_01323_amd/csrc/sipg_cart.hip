@@ -781,13 +781,17 @@ ZmPlan zm_plan_n(int nx, int ny, int nz) {
   // one round of resident workgroups: four per compute unit, three for the
   // fp64 kernel at k = 4 (three waves per SIMD)
   constexpr int kTargetBlocks = (N == 5 && sizeof(T) == 8) ? 768 : 1024;
-  constexpr int kMinLayers = 4;         // shortest z segment
+  constexpr int kMinLayers = 4;         // shortest z segment of a large mesh
   ZmPlan p{};
   p.tx = (nx + TX - 1) / TX;
   p.ty = (ny + TY - 1) / TY;
   const int tiles = p.tx * p.ty;
   int segs = (kTargetBlocks + tiles - 1) / tiles;
-  const int maxseg = nz / kMinLayers > 1 ? nz / kMinLayers : 1;
+  // a mesh whose every layer fits one round of workgroups (coarse multigrid
+  // levels) marches one layer per workgroup: latency, not the z-window set-up,
+  // bounds those launches
+  const int minl = tiles * nz <= kTargetBlocks ? 1 : kMinLayers;
+  const int maxseg = nz / minl > 1 ? nz / minl : 1;
   segs = segs < 1 ? 1 : (segs > maxseg ? maxseg : segs);
   p.seglen = (nz + segs - 1) / segs;
   p.segs = (nz + p.seglen - 1) / p.seglen;
