@@ -404,3 +404,13 @@ class Convective(torch.autograd.Function):
     def backward(ctx, g):
         (u,) = ctx.saved_tensors
         return ctx.op.vjp(u, g.contiguous()), None
+
+
+def apply(op, x, out=None):
+    """H x through the operator's apply (SIPG: fp64 or fp32 input; convective: C(x))."""
+    return op.apply(x, out)
+
+
+def cg(op, b, x0, **params):
+    """Preconditioned CG on H x = b from x0 (updated in place); params as SipgOperator.cg."""
+    return op.cg(b, x0, **params)
