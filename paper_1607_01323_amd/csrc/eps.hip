@@ -17,7 +17,9 @@
 // along c, Mh along the rest).  Faces: GLL end points make traces node planes;
 // tangential derivatives of a trace use the nodal derivative matrix, the
 // normal derivative of u_d the end-point derivatives l_j'(0), l_j'(1) along
-// the line, and face integrals of trace polynomials area (Mh (x) Mh).
+// the line, and face integrals of trace polynomials area (Mh (x) Mh); the six
+// plane integrals of a face run as one batch of sweeps along each plane axis,
+// so a face costs six wavefront steps.
 #include "internal.h"
 
 namespace dgmf {
@@ -60,31 +62,18 @@ __device__ __forceinline__ int plane_node(int d, int e, int p1, int p2) {
   return (e * N + p2) * N + p1;
 }
 
-// out[q] = sum_m A[row(q)][m] in[..m..] along plane axis ax (0: p1, 1: p2); TR uses A^T
-template <int N, bool TR>
-__device__ __forceinline__ void psweep(const double* A, int ax, const double* in, double* out, int lane) {
-  constexpr int N2 = N * N;
-  for (int q = lane; q < N2; q += 64) {
-    const int p1 = q % N, p2 = q / N;
-    double r = 0;
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-      const double a = ax == 0 ? (TR ? A[m * N + p1] : A[p1 * N + m]) : (TR ? A[m * N + p2] : A[p2 * N + m]);
-      const double x = ax == 0 ? in[p2 * N + m] : in[m * N + p1];
-      r = fma(a, x, r);
-    }
-    out[q] = r;
-  }
-}
-
 template <int N>
 struct EShape {
   static constexpr int N2 = N * N, N3 = N2 * N;
   static constexpr int TABN = 7 * N2 + 4 * N;
-  // U (3 N3), O (3 N3), T1, T2, NB (N3 each), planes: NBt (2), J (3), G (3), A, S1, S2 (N2 each)
-  static constexpr int SLICE = 9 * N3 + 11 * N2;
+  // U (3 N3), O (3 N3), T1, T2, NB (N3 each), planes: NBt (2), J (3), G (3), A (1), X (6), Y (6)
+  static constexpr int SLICE = 9 * N3 + 21 * N2;
   static constexpr int BYTES = SLICE * 8;
-  static constexpr int WAVES = BYTES * 4 <= 56000 ? 4 : (BYTES * 2 <= 56000 ? 2 : 1);
+  // wavefronts per workgroup: the most resident wavefronts per compute unit
+  // (160 KiB of LDS, allocated in 1 KiB steps), fewer per workgroup on ties
+  static constexpr int lds_round(int b) { return (b + 1023) / 1024 * 1024; }
+  static constexpr int per_cu(int w) { return w * (163840 / lds_round(w * BYTES + TABN * 8)); }
+  static constexpr int WAVES = per_cu(1) >= per_cu(2) && per_cu(1) >= per_cu(4) ? 1 : (per_cu(2) >= per_cu(4) ? 2 : 4);
 };
 
 template <int N>
@@ -118,8 +107,8 @@ __global__ void __launch_bounds__(64 * EShape<N>::WAVES) k_eps_coupling(const do
   double* J = NBt + 2 * N2;    // 3 planes: jumps of u_c'
   double* G = J + 3 * N2;      // 3 planes: averaged d_c u_d
   double* A = G + 3 * N2;      // averaged trace of u_d
-  double* S1 = A + N2;
-  double* S2 = S1 + N2;
+  double* X = A + N2;          // 6 planes after the p1 sweeps
+  double* Y = X + 6 * N2;      // 6 planes after the p2 sweeps
   const int64_t Nd = ncells * N3;
   int ci[3];
   ci[0] = static_cast<int>(cell % g.nx);
@@ -214,50 +203,55 @@ __global__ void __launch_bounds__(64 * EShape<N>::WAVES) k_eps_coupling(const do
         G[d * N2 + q] = interior ? 0.5 * (hi[d] * dn_own + hinb * dn_nb) : hi[d] * dn_own;
       }
       wave_sync();
-      // tangential derivatives of the averaged trace: G_t1 = hinv_t1 Dn along p1, G_t2 along p2
-      psweep<N, false>(Dn, 0, A, S1, lane);
-      psweep<N, false>(Dn, 1, A, S2, lane);
-      wave_sync();
-      for (int q = lane; q < N2; q += 64) {
-        G[t1 * N2 + q] = hi[t1] * S1[q];
-        G[t2 * N2 + q] = hi[t2] * S2[q];
-      }
-      wave_sync();
-      // term 2: O_c[plane] -= sigma area (Mh (x) Mh) G_c, every c
-      for (int c = 0; c < 3; ++c) {
-        psweep<N, false>(Mh, 0, G + c * N2, S1, lane);
-        wave_sync();
-        psweep<N, false>(Mh, 1, S1, S2, lane);
-        wave_sync();
-        for (int q = lane; q < N2; q += 64)
-          O[c * N3 + plane_node<N>(d, e, q % N, q / N)] -= sigma * area * S2[q];
-        wave_sync();
-      }
-      // term 1 (output component d): -w sigma sum_c' int d_c' phi_i J_c', w = 1/2 inside, 1 on the boundary
-      const double w1 = (interior ? 0.5 : 1.0) * sigma * area;
-      // c' tangential: plane nodes only, Ch along c' and Mh along the other tangential axis
+      // tangential derivatives of the averaged trace, scaled: G_t1 = hinv_t1 Dn_p1 A, G_t2 = hinv_t2 Dn_p2 A
+      for (int w = lane; w < 2 * N2; w += 64) {
+        const int k = w / N2, q = w % N2, p1 = q % N, p2 = q / N;
+        double r = 0;
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int cp = k == 0 ? t1 : t2;
-        psweep<N, false>(k == 0 ? Ch : Mh, 0, J + cp * N2, S1, lane);
-        wave_sync();
-        psweep<N, false>(k == 0 ? Mh : Ch, 1, S1, S2, lane);
-        wave_sync();
-        for (int q = lane; q < N2; q += 64)
-          O[d * N3 + plane_node<N>(d, e, q % N, q / N)] -= w1 * hi[cp] * S2[q];
-        wave_sync();
+        for (int m = 0; m < N; ++m)
+          r = fma(k == 0 ? Dn[p1 * N + m] : Dn[p2 * N + m], k == 0 ? A[p2 * N + m] : A[m * N + p1], r);
+        G[(k == 0 ? t1 : t2) * N2 + q] = (k == 0 ? hi[t1] : hi[t2]) * r;
       }
-      // c' = d: the test function's normal derivative, hinv_d l'_{i_d}(end) (Mh (x) Mh J_d)
-      psweep<N, false>(Mh, 0, J + d * N2, S1, lane);
       wave_sync();
-      psweep<N, false>(Mh, 1, S1, S2, lane);
+      // six plane integrals at once, first along p1 then along p2:
+      //   0..2: (Mh (x) Mh) G_c      3: (Ch_p1, Mh_p2) J_t1      4: (Mh_p1, Ch_p2) J_t2      5: (Mh (x) Mh) J_d
+      for (int w = lane; w < 6 * N2; w += 64) {
+        const int k = w / N2, q = w % N2, p1 = q % N, p2 = q / N;
+        const double* in = k < 3 ? G + k * N2 : J + (k == 3 ? t1 : (k == 4 ? t2 : d)) * N2;
+        const double* M = k == 3 ? Ch : Mh;
+        double r = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) r = fma(M[p1 * N + m], in[p2 * N + m], r);
+        X[w] = r;
+      }
       wave_sync();
-      for (int q = lane; q < N3; q += 64) {
-        int id, p1, p2;
-        if (d == 0) { id = q % N; p1 = (q / N) % N; p2 = q / N2; }
-        else if (d == 1) { id = (q / N) % N; p1 = q % N; p2 = q / N2; }
-        else { id = q / N2; p1 = q % N; p2 = (q / N) % N; }
-        O[d * N3 + q] -= w1 * hi[d] * gend[id] * S2[p2 * N + p1];
+      for (int w = lane; w < 6 * N2; w += 64) {
+        const int k = w / N2, q = w % N2, p1 = q % N, p2 = q / N;
+        const double* M = k == 4 ? Ch : Mh;
+        double r = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) r = fma(M[p2 * N + m], X[k * N2 + m * N + p1], r);
+        Y[w] = r;
+      }
+      wave_sync();
+      // accumulate: term 2 on the plane of every component, term 1 on component d (plane: tangential
+      // test derivatives; every node along the normal: the test function's normal derivative)
+      const double w1 = (interior ? 0.5 : 1.0) * sigma * area;
+      for (int w = lane; w < N3 + 2 * N2; w += 64) {
+        if (w < N3) {
+          int id, p1, p2;
+          if (d == 0) { id = w % N; p1 = (w / N) % N; p2 = w / N2; }
+          else if (d == 1) { id = (w / N) % N; p1 = w % N; p2 = w / N2; }
+          else { id = w / N2; p1 = w % N; p2 = (w / N) % N; }
+          const int q = p2 * N + p1;
+          double v = w1 * hi[d] * gend[id] * Y[5 * N2 + q];
+          if (id == e) v += sigma * area * Y[d * N2 + q] + w1 * (hi[t1] * Y[3 * N2 + q] + hi[t2] * Y[4 * N2 + q]);
+          O[d * N3 + w] -= v;
+        } else {
+          const int k = (w - N3) / N2, q = (w - N3) % N2;
+          const int c = k == 0 ? t1 : t2;
+          O[c * N3 + plane_node<N>(d, e, q % N, q / N)] -= sigma * area * Y[c * N2 + q];
+        }
       }
       wave_sync();
     }
