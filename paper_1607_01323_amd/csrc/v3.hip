@@ -20,8 +20,10 @@
 // points (k+1 per direction): div at the points from S and D sweeps, then the
 // transposed sweeps.
 //
-// Layout: one cell per wavefront, a few wavefronts per workgroup (LDS bound),
-// wavefront barriers only after the tables are staged.
+// Layout: A and B pack 64/n^2 cells per wavefront with one line (and one face
+// node) per lane; the projection runs one cell per wavefront.  A few
+// wavefronts per workgroup (LDS bound), wavefront barriers only after the
+// tables are staged.
 #include "internal.h"
 
 namespace dgmf {
@@ -101,24 +103,87 @@ struct V3Shape {
   static constexpr int TABN = 5 * N2 + 2 * N;   // the V3Tab entries these kernels use
 };
 
+// One line along `axis` of an N^3 array per lane (line t = a + N b), as sweep().
+template <int N, bool TR, bool ACC>
+__device__ __forceinline__ void sweep1(const double* M, int axis, const double* in, double* out, double scale,
+                                       int t) {
+  constexpr int N2 = N * N;
+  const int stride = axis == 0 ? 1 : (axis == 1 ? N : N2);
+  const int a = t % N, b = t / N;
+  const int base = axis == 0 ? (b * N + a) * N : (axis == 1 ? b * N2 + a : b * N + a);
+  double v[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] = in[base + m * stride];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double r = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) r = fma(TR ? M[m * N + i] : M[i * N + m], v[m], r);
+    if (ACC) out[base + i * stride] += scale * r;
+    else out[base + i * stride] = scale * r;
+  }
+}
+
+// Packing of the divergence and gradient kernels: 64/N^2 cells per
+// wavefront, N^2 lanes per cell; lane t of a cell owns one line in every
+// sweep and one node of every face plane.
+template <int N>
+struct XPack {
+  static constexpr int N2 = N * N, N3 = N2 * N;
+  static constexpr int CPW = 64 / N2 > 0 ? 64 / N2 : 1;
+  static constexpr int SLICE = 9 * N3 + 2 * N2;     // per cell
+  static constexpr int BYTES = CPW * SLICE * 8;     // per wavefront
+  static constexpr int lds_round(int b) { return (b + 1023) / 1024 * 1024; }
+  static constexpr int per_cu(int w) { return w * (163840 / lds_round(w * BYTES + V3Shape<N>::TABN * 8)); }
+  static constexpr int WAVES = per_cu(1) >= per_cu(2) && per_cu(1) >= per_cu(4) ? 1 : (per_cu(2) >= per_cu(4) ? 2 : 4);
+};
+
+// Face term of one face on this lane's plane node: O[plane] -= sigma area (Mh (x) Mh) avg,
+// avg = central average of the own plane `own` and the neighbour's (or own on a boundary face).
+template <int N>
+__device__ __forceinline__ void face_plane_term(const double* Mh, double* F, double* Oc, double own, double other,
+                                                bool interior, int d, int e, double sg, int t, bool act) {
+  constexpr int N2 = N * N;
+  const int p1 = t % N, p2 = t / N;
+  if (act) F[t] = interior ? 0.5 * (own + other) : own;
+  wave_sync();
+  double r = 0;
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) r = fma(Mh[p1 * N + m], F[p2 * N + m], r);
+    F[N2 + t] = r;
+  }
+  wave_sync();
+  if (act) {
+    r = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) r = fma(Mh[p2 * N + m], F[N2 + m * N + p1], r);
+    Oc[plane_node<N>(d, e, p1, p2)] -= sg * r;
+  }
+  wave_sync();
+}
+
 // ------------------------------------------------------------ divergence --
 template <int N, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __restrict__ u, double* __restrict__ out,
                                                               const CartGeom<double> g,
                                                               const double* __restrict__ tab, int64_t ncells) {
-  using SH = V3Shape<N>;
-  constexpr int N2 = SH::N2, N3 = SH::N3, SLICE = 9 * N3 + 2 * N2;
-  __shared__ double s_tab[SH::TABN];
-  __shared__ double s_all[WAVES * SLICE];
-  for (int e = threadIdx.x; e < SH::TABN; e += blockDim.x) s_tab[e] = tab[e];
+  using X = XPack<N>;
+  constexpr int N2 = X::N2, N3 = X::N3, CPW = X::CPW, SLICE = X::SLICE;
+  __shared__ double s_tab[V3Shape<N>::TABN];
+  __shared__ double s_all[WAVES * CPW * SLICE];
+  for (int e = threadIdx.x; e < V3Shape<N>::TABN; e += blockDim.x) s_tab[e] = tab[e];
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t cell = static_cast<int64_t>(blockIdx.x) * WAVES + wave;
-  if (cell >= ncells) return;
+  const int64_t first = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * CPW;
+  if (first >= ncells) return;
+  const int slot = lane / N2, t = lane % N2;
+  const bool act = slot < CPW && first + slot < ncells;
+  const int64_t cell = act ? first + slot : first;
   const V3Tab L{N};
   const double* Mh = s_tab + L.Mh();
   const double* Ch = s_tab + L.Ch();
-  double* U = s_all + wave * SLICE;     // 3 N3
+  double* U = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;   // 3 N3
   double* A3 = U + 3 * N3;              // 3 N3: after x sweeps
   double* C1 = A3 + 3 * N3;             // N3
   double* C2 = C1 + N3;                 // N3
@@ -130,20 +195,29 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __re
   double s[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) s[a] = vol / ci.h[a];
-  for (int e = lane; e < 3 * N3; e += 64) U[e] = u[(e / N3) * Nd + cell * N3 + e % N3];
+  if (act)
+#pragma unroll
+    for (int r = 0; r < 3 * N; ++r) {
+      const int e = t + N2 * r;
+      U[e] = u[(e / N3) * Nd + cell * N3 + e % N3];
+    }
   wave_sync();
-  sweep<N, false, false>(Ch, 0, U, A3, 1.0, lane);                     // Ch_x u_x
-  sweep<N, false, false>(Mh, 0, U + N3, A3 + N3, 1.0, lane);           // Mh_x u_y
-  sweep<N, false, false>(Mh, 0, U + 2 * N3, A3 + 2 * N3, 1.0, lane);   // Mh_x u_z
+  if (act) {
+    sweep1<N, false, false>(Ch, 0, U, A3, 1.0, t);                     // Ch_x u_x
+    sweep1<N, false, false>(Mh, 0, U + N3, A3 + N3, 1.0, t);           // Mh_x u_y
+    sweep1<N, false, false>(Mh, 0, U + 2 * N3, A3 + 2 * N3, 1.0, t);   // Mh_x u_z
+  }
   wave_sync();
-  sweep<N, false, false>(Mh, 1, A3, C1, s[0], lane);                   // sx Mh_y Ch_x u_x
-  sweep<N, false, false>(Mh, 1, A3 + 2 * N3, C2, s[2], lane);          // sz Mh_y Mh_x u_z
+  if (act) {
+    sweep1<N, false, false>(Mh, 1, A3, C1, s[0], t);                   // sx Mh_y Ch_x u_x
+    sweep1<N, false, true>(Ch, 1, A3 + N3, C1, s[1], t);               // + sy Ch_y Mh_x u_y (same line)
+    sweep1<N, false, false>(Mh, 1, A3 + 2 * N3, C2, s[2], t);          // sz Mh_y Mh_x u_z
+  }
   wave_sync();
-  sweep<N, false, true>(Ch, 1, A3 + N3, C1, s[1], lane);               // + sy Ch_y Mh_x u_y
-  wave_sync();
-  sweep<N, false, false>(Mh, 2, C1, O, 1.0, lane);
-  wave_sync();
-  sweep<N, false, true>(Ch, 2, C2, O, 1.0, lane);
+  if (act) {
+    sweep1<N, false, false>(Mh, 2, C1, O, 1.0, t);
+    sweep1<N, false, true>(Ch, 2, C2, O, 1.0, t);                      // same line
+  }
   wave_sync();
   // faces: O -= sign area (Mh (x) Mh) {{u_d}} on the face plane
 #pragma unroll
@@ -154,32 +228,15 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __re
     for (int sd = 0; sd < 2; ++sd) {
       const int e = sd ? N - 1 : 0;
       const int64_t nb = nb_of(g, ci, cell, d, sd);
-      for (int q = lane; q < N2; q += 64) {
-        const int p1 = q % N, p2 = q / N;
-        const double own = U[d * N3 + plane_node<N>(d, e, p1, p2)];
-        F[q] = nb >= 0 ? 0.5 * (own + u[d * Nd + nb * N3 + plane_node<N>(d, N - 1 - e, p1, p2)]) : own;
-      }
-      wave_sync();
-      for (int q = lane; q < N2; q += 64) {          // F2 = Mh_t1 F along p1
-        const int p1 = q % N, p2 = q / N;
-        double r = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) r = fma(Mh[p1 * N + m], F[p2 * N + m], r);
-        F[N2 + q] = r;
-      }
-      wave_sync();
-      const double sg = (sd ? 1.0 : -1.0) * area;
-      for (int q = lane; q < N2; q += 64) {          // along p2, subtract
-        const int p1 = q % N, p2 = q / N;
-        double r = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) r = fma(Mh[p2 * N + m], F[N2 + m * N + p1], r);
-        O[plane_node<N>(d, e, p1, p2)] -= sg * r;
-      }
-      wave_sync();
+      const int p1 = t % N, p2 = t / N;
+      const double own = act ? U[d * N3 + plane_node<N>(d, e, p1, p2)] : 0.0;
+      const double other = (act && nb >= 0) ? u[d * Nd + nb * N3 + plane_node<N>(d, N - 1 - e, p1, p2)] : 0.0;
+      face_plane_term<N>(Mh, F, O, own, other, nb >= 0, d, e, (sd ? 1.0 : -1.0) * area, t, act);
     }
   }
-  for (int e = lane; e < N3; e += 64) out[cell * N3 + e] = O[e];
+  if (act)
+#pragma unroll
+    for (int r = 0; r < N; ++r) out[cell * N3 + t + N2 * r] = O[t + N2 * r];
 }
 
 // -------------------------------------------------------------- gradient --
@@ -187,19 +244,22 @@ template <int N, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __restrict__ p, double* __restrict__ out,
                                                             const CartGeom<double> g, const double* __restrict__ tab,
                                                             int64_t ncells) {
-  using SH = V3Shape<N>;
-  constexpr int N2 = SH::N2, N3 = SH::N3, SLICE = 9 * N3 + 2 * N2;
-  __shared__ double s_tab[SH::TABN];
-  __shared__ double s_all[WAVES * SLICE];
-  for (int e = threadIdx.x; e < SH::TABN; e += blockDim.x) s_tab[e] = tab[e];
+  using X = XPack<N>;
+  constexpr int N2 = X::N2, N3 = X::N3, CPW = X::CPW, SLICE = X::SLICE;
+  __shared__ double s_tab[V3Shape<N>::TABN];
+  __shared__ double s_all[WAVES * CPW * SLICE];
+  for (int e = threadIdx.x; e < V3Shape<N>::TABN; e += blockDim.x) s_tab[e] = tab[e];
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t cell = static_cast<int64_t>(blockIdx.x) * WAVES + wave;
-  if (cell >= ncells) return;
+  const int64_t first = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * CPW;
+  if (first >= ncells) return;
+  const int slot = lane / N2, t = lane % N2;
+  const bool act = slot < CPW && first + slot < ncells;
+  const int64_t cell = act ? first + slot : first;
   const V3Tab L{N};
   const double* Mh = s_tab + L.Mh();
   const double* Ch = s_tab + L.Ch();
-  double* P = s_all + wave * SLICE;     // N3
+  double* P = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;   // N3
   double* G = P + N3;                   // 2 N3: Ch_x p, Mh_x p
   double* H = G + 2 * N3;               // 3 N3
   double* O3 = H + 3 * N3;              // 3 N3: output components
@@ -210,20 +270,28 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __rest
   double s[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) s[a] = vol / ci.h[a];
-  for (int e = lane; e < N3; e += 64) P[e] = p[cell * N3 + e];
+  if (act)
+#pragma unroll
+    for (int r = 0; r < N; ++r) P[t + N2 * r] = p[cell * N3 + t + N2 * r];
   wave_sync();
-  sweep<N, false, false>(Ch, 0, P, G, 1.0, lane);
-  sweep<N, false, false>(Mh, 0, P, G + N3, 1.0, lane);
+  if (act) {
+    sweep1<N, false, false>(Ch, 0, P, G, 1.0, t);
+    sweep1<N, false, false>(Mh, 0, P, G + N3, 1.0, t);
+  }
   wave_sync();
-  sweep<N, false, false>(Mh, 1, G, H, 1.0, lane);
-  sweep<N, false, false>(Ch, 1, G + N3, H + N3, 1.0, lane);
-  sweep<N, false, false>(Mh, 1, G + N3, H + 2 * N3, 1.0, lane);
+  if (act) {
+    sweep1<N, false, false>(Mh, 1, G, H, 1.0, t);
+    sweep1<N, false, false>(Ch, 1, G + N3, H + N3, 1.0, t);
+    sweep1<N, false, false>(Mh, 1, G + N3, H + 2 * N3, 1.0, t);
+  }
   wave_sync();
-  sweep<N, false, false>(Mh, 2, H, O3, s[0], lane);
-  sweep<N, false, false>(Mh, 2, H + N3, O3 + N3, s[1], lane);
-  sweep<N, false, false>(Ch, 2, H + 2 * N3, O3 + 2 * N3, s[2], lane);
+  if (act) {
+    sweep1<N, false, false>(Mh, 2, H, O3, s[0], t);
+    sweep1<N, false, false>(Mh, 2, H + N3, O3 + N3, s[1], t);
+    sweep1<N, false, false>(Ch, 2, H + 2 * N3, O3 + 2 * N3, s[2], t);
+  }
   wave_sync();
-  // faces: O_d -= sign area (Mh (x) Mh) {{p}} on the face plane; the own trace comes from global memory
+  // faces: O_d -= sign area (Mh (x) Mh) {{p}} on the face plane
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
@@ -232,32 +300,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __rest
     for (int sd = 0; sd < 2; ++sd) {
       const int e = sd ? N - 1 : 0;
       const int64_t nb = nb_of(g, ci, cell, d, sd);
-      for (int q = lane; q < N2; q += 64) {
-        const int p1 = q % N, p2 = q / N;
-        const double own = p[cell * N3 + plane_node<N>(d, e, p1, p2)];
-        F[q] = nb >= 0 ? 0.5 * (own + p[nb * N3 + plane_node<N>(d, N - 1 - e, p1, p2)]) : own;
-      }
-      wave_sync();
-      for (int q = lane; q < N2; q += 64) {
-        const int p1 = q % N, p2 = q / N;
-        double r = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) r = fma(Mh[p1 * N + m], F[p2 * N + m], r);
-        F[N2 + q] = r;
-      }
-      wave_sync();
-      const double sg = (sd ? 1.0 : -1.0) * area;
-      for (int q = lane; q < N2; q += 64) {
-        const int p1 = q % N, p2 = q / N;
-        double r = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) r = fma(Mh[p2 * N + m], F[N2 + m * N + p1], r);
-        O3[d * N3 + plane_node<N>(d, e, p1, p2)] -= sg * r;
-      }
-      wave_sync();
+      const int p1 = t % N, p2 = t / N;
+      const double own = act ? P[plane_node<N>(d, e, p1, p2)] : 0.0;
+      const double other = (act && nb >= 0) ? p[nb * N3 + plane_node<N>(d, N - 1 - e, p1, p2)] : 0.0;
+      face_plane_term<N>(Mh, F, O3 + d * N3, own, other, nb >= 0, d, e, (sd ? 1.0 : -1.0) * area, t, act);
     }
   }
-  for (int e = lane; e < 3 * N3; e += 64) out[(e / N3) * Nd + cell * N3 + e % N3] = O3[e];
+  if (act)
+#pragma unroll
+    for (int r = 0; r < 3 * N; ++r) {
+      const int e = t + N2 * r;
+      out[(e / N3) * Nd + cell * N3 + e % N3] = O3[e];
+    }
 }
 
 // ------------------------------------------------------------------ tau_D --
@@ -448,15 +502,11 @@ __global__ void __launch_bounds__(64 * PShape<N>::WAVES) k_v3_projection(
 }
 
 template <int N>
-constexpr int xwaves() {
-  return (9 * N * N * N + 2 * N * N) * 8 * 4 <= 58000 ? 4 : ((9 * N * N * N + 2 * N * N) * 8 * 2 <= 58000 ? 2 : 1);
-}
-
-template <int N>
 dgmf_status div_n(bool grad, const CartGeom<double>& g, const double* tab, const double* in, double* out,
                   int64_t ncells, hipStream_t s) {
-  constexpr int W = xwaves<N>();
-  const int64_t blocks = (ncells + W - 1) / W;
+  constexpr int W = XPack<N>::WAVES, CPW = XPack<N>::CPW;
+  const int64_t waves = (ncells + CPW - 1) / CPW;
+  const int64_t blocks = (waves + W - 1) / W;
   if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "v3: too many cells for one launch");
   if (grad) {
     hipLaunchKernelGGL((k_v3_gradient<N, W>), dim3(static_cast<unsigned>(blocks)), dim3(64 * W), 0, s, in, out, g,
