@@ -27,6 +27,10 @@ CASES = {
     "k4_one_cell_periodic": (4, (1, 2, 2), (1, 1, 1), 0.0, (1, 0, 1), 0.0, 0.0, 2.0, 1.0),
     "k5_mixed": (5, (2, 1, 2), (0.5, 1, 1), 0.0, (0, 1, 1), 0.0, 1.0, 1.0, 1.0 / 3.0),
     "k6": (6, (1, 2, 1), (1, 1, 1), 0.0, (0, 0, 1), 0.0, 0.0, 1.0, 1.0),
+    # cell counts that leave the last wavefront partly filled (4 and 2 cells per wavefront)
+    "k3_ragged": (3, (3, 1, 3), (1, 1, 1), 0.0, (1, 1, 0), 0.0, 2.0, 0.5, 1.0),
+    "k4_ragged": (4, (3, 1, 1), (1.5, 1, 1), 0.0, (0, 1, 1), 0.0, 0.0, 1.0, 1.0),
+    "k7": (7, (1, 1, 2), (1, 1, 1), 0.0, (1, 0, 0), 0.0, 1.0, 1.0, 1.0),
 }
 
 
