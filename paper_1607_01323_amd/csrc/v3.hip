@@ -126,17 +126,23 @@ __device__ __forceinline__ void sweep1(const double* M, int axis, const double* 
 
 // Packing of the divergence and gradient kernels: 64/N^2 cells per
 // wavefront, N^2 lanes per cell; lane t of a cell owns one line in every
-// sweep and one node of every face plane.
-template <int N>
+// sweep and one node of every face plane.  Every sweep runs in place (a lane
+// reads its whole line before writing it), so a cell needs only three N^3
+// arrays (the gradient two face planes more); SLICE doubles per cell.
+template <int N, int SLICE_>
 struct XPack {
   static constexpr int N2 = N * N, N3 = N2 * N;
   static constexpr int CPW = 64 / N2 > 0 ? 64 / N2 : 1;
-  static constexpr int SLICE = 9 * N3 + 2 * N2;     // per cell
+  static constexpr int SLICE = SLICE_;
   static constexpr int BYTES = CPW * SLICE * 8;     // per wavefront
   static constexpr int lds_round(int b) { return (b + 1023) / 1024 * 1024; }
   static constexpr int per_cu(int w) { return w * (163840 / lds_round(w * BYTES + V3Shape<N>::TABN * 8)); }
   static constexpr int WAVES = per_cu(1) >= per_cu(2) && per_cu(1) >= per_cu(4) ? 1 : (per_cu(2) >= per_cu(4) ? 2 : 4);
 };
+template <int N>
+using DivPack = XPack<N, 3 * N * N * N>;
+template <int N>
+using GradPack = XPack<N, 3 * N * N * N + 2 * N * N>;
 
 // Face term of one face on this lane's plane node: O[plane] -= sigma area (Mh (x) Mh) avg,
 // avg = central average of the own plane `own` and the neighbour's (or own on a boundary face).
@@ -168,7 +174,7 @@ template <int N, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __restrict__ u, double* __restrict__ out,
                                                               const CartGeom<double> g,
                                                               const double* __restrict__ tab, int64_t ncells) {
-  using X = XPack<N>;
+  using X = DivPack<N>;
   constexpr int N2 = X::N2, N3 = X::N3, CPW = X::CPW, SLICE = X::SLICE;
   __shared__ double s_tab[V3Shape<N>::TABN];
   __shared__ double s_all[WAVES * CPW * SLICE];
@@ -183,12 +189,9 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __re
   const V3Tab L{N};
   const double* Mh = s_tab + L.Mh();
   const double* Ch = s_tab + L.Ch();
-  double* U = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;   // 3 N3
-  double* A3 = U + 3 * N3;              // 3 N3: after x sweeps
-  double* C1 = A3 + 3 * N3;             // N3
-  double* C2 = C1 + N3;                 // N3
-  double* O = C2 + N3;                  // N3
-  double* F = O + N3;                   // 2 N2: face plane scratch
+  double* P0 = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;   // u_x, then the output
+  double* P1 = P0 + N3;                 // u_y, then the face plane scratch (2 N2)
+  double* P2 = P1 + N3;                 // u_z
   const int64_t Nd = ncells * N3;
   const CellIdx ci = cell_of(g, cell);
   const double vol = ci.h[0] * ci.h[1] * ci.h[2];
@@ -199,24 +202,24 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __re
 #pragma unroll
     for (int r = 0; r < 3 * N; ++r) {
       const int e = t + N2 * r;
-      U[e] = u[(e / N3) * Nd + cell * N3 + e % N3];
+      P0[e] = u[(e / N3) * Nd + cell * N3 + e % N3];
     }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Ch, 0, U, A3, 1.0, t);                     // Ch_x u_x
-    sweep1<N, false, false>(Mh, 0, U + N3, A3 + N3, 1.0, t);           // Mh_x u_y
-    sweep1<N, false, false>(Mh, 0, U + 2 * N3, A3 + 2 * N3, 1.0, t);   // Mh_x u_z
+    sweep1<N, false, false>(Ch, 0, P0, P0, 1.0, t);                    // Ch_x u_x
+    sweep1<N, false, false>(Mh, 0, P1, P1, 1.0, t);                    // Mh_x u_y
+    sweep1<N, false, false>(Mh, 0, P2, P2, 1.0, t);                    // Mh_x u_z
   }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Mh, 1, A3, C1, s[0], t);                   // sx Mh_y Ch_x u_x
-    sweep1<N, false, true>(Ch, 1, A3 + N3, C1, s[1], t);               // + sy Ch_y Mh_x u_y (same line)
-    sweep1<N, false, false>(Mh, 1, A3 + 2 * N3, C2, s[2], t);          // sz Mh_y Mh_x u_z
+    sweep1<N, false, false>(Mh, 1, P0, P0, s[0], t);                   // sx Mh_y Ch_x u_x
+    sweep1<N, false, true>(Ch, 1, P1, P0, s[1], t);                    // + sy Ch_y Mh_x u_y (same line)
+    sweep1<N, false, false>(Mh, 1, P2, P2, s[2], t);                   // sz Mh_y Mh_x u_z
   }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Mh, 2, C1, O, 1.0, t);
-    sweep1<N, false, true>(Ch, 2, C2, O, 1.0, t);                      // same line
+    sweep1<N, false, false>(Mh, 2, P0, P0, 1.0, t);
+    sweep1<N, false, true>(Ch, 2, P2, P0, 1.0, t);                     // same line
   }
   wave_sync();
   // faces: O -= sign area (Mh (x) Mh) {{u_d}} on the face plane
@@ -229,14 +232,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __re
       const int e = sd ? N - 1 : 0;
       const int64_t nb = nb_of(g, ci, cell, d, sd);
       const int p1 = t % N, p2 = t / N;
-      const double own = act ? U[d * N3 + plane_node<N>(d, e, p1, p2)] : 0.0;
+      const double own = act ? u[d * Nd + cell * N3 + plane_node<N>(d, e, p1, p2)] : 0.0;
       const double other = (act && nb >= 0) ? u[d * Nd + nb * N3 + plane_node<N>(d, N - 1 - e, p1, p2)] : 0.0;
-      face_plane_term<N>(Mh, F, O, own, other, nb >= 0, d, e, (sd ? 1.0 : -1.0) * area, t, act);
+      face_plane_term<N>(Mh, P1, P0, own, other, nb >= 0, d, e, (sd ? 1.0 : -1.0) * area, t, act);
     }
   }
   if (act)
 #pragma unroll
-    for (int r = 0; r < N; ++r) out[cell * N3 + t + N2 * r] = O[t + N2 * r];
+    for (int r = 0; r < N; ++r) out[cell * N3 + t + N2 * r] = P0[t + N2 * r];
 }
 
 // -------------------------------------------------------------- gradient --
@@ -244,7 +247,7 @@ template <int N, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __restrict__ p, double* __restrict__ out,
                                                             const CartGeom<double> g, const double* __restrict__ tab,
                                                             int64_t ncells) {
-  using X = XPack<N>;
+  using X = GradPack<N>;
   constexpr int N2 = X::N2, N3 = X::N3, CPW = X::CPW, SLICE = X::SLICE;
   __shared__ double s_tab[V3Shape<N>::TABN];
   __shared__ double s_all[WAVES * CPW * SLICE];
@@ -259,10 +262,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __rest
   const V3Tab L{N};
   const double* Mh = s_tab + L.Mh();
   const double* Ch = s_tab + L.Ch();
-  double* P = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;   // N3
-  double* G = P + N3;                   // 2 N3: Ch_x p, Mh_x p
-  double* H = G + 2 * N3;               // 3 N3
-  double* O3 = H + 3 * N3;              // 3 N3: output components
+  double* O3 = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;  // 3 N3: output components
+  double* P = O3 + 2 * N3;              // p, in the slot of output component 2
   double* F = O3 + 3 * N3;              // 2 N2: face plane scratch
   const int64_t Nd = ncells * N3;
   const CellIdx ci = cell_of(g, cell);
@@ -275,20 +276,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __rest
     for (int r = 0; r < N; ++r) P[t + N2 * r] = p[cell * N3 + t + N2 * r];
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Ch, 0, P, G, 1.0, t);
-    sweep1<N, false, false>(Mh, 0, P, G + N3, 1.0, t);
+    sweep1<N, false, false>(Ch, 0, P, O3, 1.0, t);                     // Ch_x p
+    sweep1<N, false, false>(Mh, 0, P, P, 1.0, t);                      // Mh_x p (in place, after the read)
   }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Mh, 1, G, H, 1.0, t);
-    sweep1<N, false, false>(Ch, 1, G + N3, H + N3, 1.0, t);
-    sweep1<N, false, false>(Mh, 1, G + N3, H + 2 * N3, 1.0, t);
+    sweep1<N, false, false>(Mh, 1, O3, O3, 1.0, t);                    // Mh_y Ch_x p
+    sweep1<N, false, false>(Ch, 1, P, O3 + N3, 1.0, t);                // Ch_y Mh_x p
+    sweep1<N, false, false>(Mh, 1, P, P, 1.0, t);                      // Mh_y Mh_x p
   }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Mh, 2, H, O3, s[0], t);
-    sweep1<N, false, false>(Mh, 2, H + N3, O3 + N3, s[1], t);
-    sweep1<N, false, false>(Ch, 2, H + 2 * N3, O3 + 2 * N3, s[2], t);
+    sweep1<N, false, false>(Mh, 2, O3, O3, s[0], t);
+    sweep1<N, false, false>(Mh, 2, O3 + N3, O3 + N3, s[1], t);
+    sweep1<N, false, false>(Ch, 2, P, P, s[2], t);
   }
   wave_sync();
   // faces: O_d -= sign area (Mh (x) Mh) {{p}} on the face plane
@@ -301,7 +302,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __rest
       const int e = sd ? N - 1 : 0;
       const int64_t nb = nb_of(g, ci, cell, d, sd);
       const int p1 = t % N, p2 = t / N;
-      const double own = act ? P[plane_node<N>(d, e, p1, p2)] : 0.0;
+      const double own = act ? p[cell * N3 + plane_node<N>(d, e, p1, p2)] : 0.0;
       const double other = (act && nb >= 0) ? p[nb * N3 + plane_node<N>(d, N - 1 - e, p1, p2)] : 0.0;
       face_plane_term<N>(Mh, F, O3 + d * N3, own, other, nb >= 0, d, e, (sd ? 1.0 : -1.0) * area, t, act);
     }
@@ -504,15 +505,19 @@ __global__ void __launch_bounds__(64 * PShape<N>::WAVES) k_v3_projection(
 template <int N>
 dgmf_status div_n(bool grad, const CartGeom<double>& g, const double* tab, const double* in, double* out,
                   int64_t ncells, hipStream_t s) {
-  constexpr int W = XPack<N>::WAVES, CPW = XPack<N>::CPW;
+  constexpr int CPW = DivPack<N>::CPW;
   const int64_t waves = (ncells + CPW - 1) / CPW;
-  const int64_t blocks = (waves + W - 1) / W;
-  if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "v3: too many cells for one launch");
   if (grad) {
+    constexpr int W = GradPack<N>::WAVES;
+    const int64_t blocks = (waves + W - 1) / W;
+    if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "v3: too many cells for one launch");
     hipLaunchKernelGGL((k_v3_gradient<N, W>), dim3(static_cast<unsigned>(blocks)), dim3(64 * W), 0, s, in, out, g,
                        tab, ncells);
     DGMF_LAUNCH_CHECK("k_v3_gradient");
   } else {
+    constexpr int W = DivPack<N>::WAVES;
+    const int64_t blocks = (waves + W - 1) / W;
+    if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "v3: too many cells for one launch");
     hipLaunchKernelGGL((k_v3_divergence<N, W>), dim3(static_cast<unsigned>(blocks)), dim3(64 * W), 0, s, in, out, g,
                        tab, ncells);
     DGMF_LAUNCH_CHECK("k_v3_divergence");
