@@ -21,9 +21,9 @@
 // transposed sweeps.
 //
 // Layout: A and B pack 64/n^2 cells per wavefront with one line (and one face
-// node) per lane; the projection runs one cell per wavefront.  A few
-// wavefronts per workgroup (LDS bound), wavefront barriers only after the
-// tables are staged.
+// node) per lane; the projection packs 64/SS cells per wavefront, SS the
+// smallest power of two >= n^2.  A few wavefronts per workgroup (LDS bound),
+// wavefront barriers only after the tables are staged.
 #include "internal.h"
 
 namespace dgmf {
@@ -70,31 +70,6 @@ __device__ __forceinline__ int plane_node(int d, int e, int p1, int p2) {
   if (d == 0) return (p2 * N + p1) * N + e;
   if (d == 1) return (p2 * N + e) * N + p1;
   return (e * N + p2) * N + p1;
-}
-
-// out = M applied along `axis` of an N^3 array (lines along the axis), one
-// line per lane step; accumulate with scale when ACC.  M row-major [out][in],
-// or its transpose when TR.
-template <int N, bool TR, bool ACC>
-__device__ __forceinline__ void sweep(const double* M, int axis, const double* in, double* out, double scale,
-                                      int lane) {
-  constexpr int N2 = N * N;
-  const int stride = axis == 0 ? 1 : (axis == 1 ? N : N2);
-  for (int L = lane; L < N2; L += 64) {
-    const int a = L % N, b = L / N;
-    const int base = axis == 0 ? (b * N + a) * N : (axis == 1 ? b * N2 + a : b * N + a);
-    double v[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) v[m] = in[base + m * stride];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double r = 0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) r = fma(TR ? M[m * N + i] : M[i * N + m], v[m], r);
-      if (ACC) out[base + i * stride] += scale * r;
-      else out[base + i * stride] = scale * r;
-    }
-  }
 }
 
 template <int N>
@@ -345,161 +320,271 @@ __global__ void __launch_bounds__(256) k_v3_tau(const double* __restrict__ u, co
 }
 
 // ------------------------------------------------------ projection (CG) --
+// Packing: each cell owns an aligned group of SS lanes (the smallest power of
+// two >= N^2, so that a butterfly over the group sums a cell's partials), 64/SS
+// cells per wavefront.  Lane t < N^2 of a group owns one line of its cell in
+// every sweep and the nodes t + N^2 j (j < 3N) in vector operations, whose x
+// it keeps in registers.  Per cell the LDS slice holds r, p, q and one
+// 3-component temporary T, which also holds z = M_e^{-1} r between the
+// preconditioner and the update of p.
 template <int N>
-struct PShape {
+struct PPack {
   static constexpr int N2 = N * N, N3 = N2 * N, V = 3 * N3;
-  static constexpr int SLICE = 5 * V + 2 * V + N3;   // x r z p q, two 3-component temporaries, div at points
-  static constexpr int BYTES = SLICE * 8;
-  static constexpr int WAVES = BYTES * 4 <= 58000 ? 4 : (BYTES * 2 <= 58000 ? 2 : 1);
+  static constexpr int SS = N2 <= 4 ? 4 : (N2 <= 8 ? 8 : (N2 <= 16 ? 16 : (N2 <= 32 ? 32 : 64)));
+  static constexpr int CPW = 64 / SS;
+  static constexpr int SLICE = 4 * V;
+  static constexpr int BYTES = CPW * SLICE * 8;     // per wavefront
+  static constexpr int lds_round(int b) { return (b + 1023) / 1024 * 1024; }
+  static constexpr int per_cu(int w) { return w * (163840 / lds_round(w * BYTES + V3Shape<N>::TABN * 8)); }
+  static constexpr int WAVES = per_cu(1) >= per_cu(2) && per_cu(1) >= per_cu(4) ? 1 : (per_cu(2) >= per_cu(4) ? 2 : 4);
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
+// sum over the aligned group of SS lanes (every lane of the group gets the same value)
+template <int SS>
+__device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int o = SS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// q = (M_e (x) I_3 + tau D_e) p on one cell.  T1, T2: 3-component temporaries, DQ: N3.
+// Compiler-only ordering point (no instruction): keeps the scheduler from
+// interleaving consecutive sweeps, which bounds the live registers to one
+// sweep's line and matrix entries.
+__device__ __forceinline__ void cfence() { asm volatile("" ::: "memory"); }
+
+// q = (M_e (x) I_3 + tau D_e) p on one cell; T: 3-component temporary.  Lane t owns line t.
 template <int N>
-__device__ __forceinline__ void proj_apply(const double* tb, const double* p, double* q, double* T1, double* T2,
-                                           double* DQ, const double (&hinv)[3], double vol, double tau, int lane) {
+__device__ __forceinline__ void proj_apply(const double* tb, const double* p, double* q, double* T,
+                                           const double (&hinv)[3], double vol, double tau, int t, bool act) {
   constexpr int N3 = N * N * N;
   const V3Tab L{N};
   const double* Mh = tb + L.Mh();
   const double* S = tb + L.S();
   const double* D = tb + L.D();
   const double* w = tb + L.w();
-  // mass: q_a = vol Mh_z Mh_y Mh_x p_a
-  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mh, 0, p + a * N3, T1 + a * N3, 1.0, lane);
+  // mass: q_a = vol Mh_z Mh_y Mh_x p_a (the y and z sweeps in place)
+  if (act)
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) sweep1<N, false, false>(Mh, 0, p + a * N3, q + a * N3, 1.0, t);
   wave_sync();
-  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mh, 1, T1 + a * N3, T2 + a * N3, 1.0, lane);
+  if (act)
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) sweep1<N, false, false>(Mh, 1, q + a * N3, q + a * N3, 1.0, t);
   wave_sync();
-  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mh, 2, T2 + a * N3, q + a * N3, vol, lane);
+  if (act)
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) sweep1<N, false, false>(Mh, 2, q + a * N3, q + a * N3, vol, t);
   wave_sync();
-  if (tau == 0.0) return;   // uniform over the wavefront
+  if (tau == 0.0) return;   // uniform over the cell's lanes
   // div at the Gauss points: sum_b hinv_b (D along b, S along the others) p_b
-  for (int b = 0; b < 3; ++b) sweep<N, false, false>(b == 0 ? D : S, 0, p + b * N3, T1 + b * N3, 1.0, lane);
+  if (act) {
+    sweep1<N, false, false>(D, 0, p, T, 1.0, t);
+    cfence();
+    sweep1<N, false, false>(S, 0, p + N3, T + N3, 1.0, t);
+    cfence();
+    sweep1<N, false, false>(S, 0, p + 2 * N3, T + 2 * N3, 1.0, t);
+  }
   wave_sync();
-  for (int b = 0; b < 3; ++b) sweep<N, false, false>(b == 1 ? D : S, 1, T1 + b * N3, T2 + b * N3, 1.0, lane);
+  if (act) {
+    sweep1<N, false, false>(S, 1, T, T, 1.0, t);
+    cfence();
+    sweep1<N, false, false>(D, 1, T + N3, T + N3, 1.0, t);
+    cfence();
+    sweep1<N, false, false>(S, 1, T + 2 * N3, T + 2 * N3, 1.0, t);
+  }
   wave_sync();
-  sweep<N, false, false>(S, 2, T2, DQ, hinv[0], lane);
+  // along z on this lane's line: the divergence at the points, times tau vol w_i w_j w_k,
+  // then the transposed z sweeps: T_1 = S^T dq, T_2 = D^T dq
+  if (act) {
+    const int a = t % N, b = t / N;
+    const int base = b * N + a;
+    constexpr int N2 = N * N;
+    double v0[N], v1[N], v2[N], dq[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      v0[m] = T[base + m * N2];
+      v1[m] = T[N3 + base + m * N2];
+      v2[m] = T[2 * N3 + base + m * N2];
+    }
+    const double sw = tau * vol * w[a] * w[b];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double r0 = 0, r2 = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        r0 = fma(S[i * N + m], fma(hinv[0], v0[m], hinv[1] * v1[m]), r0);
+        r2 = fma(D[i * N + m], v2[m], r2);
+      }
+      dq[i] = sw * w[i] * fma(hinv[2], r2, r0);
+    }
+    cfence();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double rs = 0, rd = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        rs = fma(S[m * N + i], dq[m], rs);
+        rd = fma(D[m * N + i], dq[m], rd);
+      }
+      T[N3 + base + i * N2] = rs;
+      T[2 * N3 + base + i * N2] = rd;
+    }
+  }
   wave_sync();
-  sweep<N, false, true>(S, 2, T2 + N3, DQ, hinv[1], lane);
+  if (act) {
+    sweep1<N, true, false>(S, 1, T + N3, T, 1.0, t);              // S^T_y S^T_z dq (component 0)
+    cfence();
+    sweep1<N, true, false>(D, 1, T + N3, T + N3, 1.0, t);         // D^T_y S^T_z dq (component 1, in place)
+    cfence();
+    sweep1<N, true, false>(S, 1, T + 2 * N3, T + 2 * N3, 1.0, t); // S^T_y D^T_z dq (component 2, in place)
+  }
   wave_sync();
-  sweep<N, false, true>(D, 2, T2 + 2 * N3, DQ, hinv[2], lane);
-  wave_sync();
-  for (int e = lane; e < N3; e += 64) DQ[e] *= tau * vol * w[e % N] * w[(e / N) % N] * w[e / (N * N)];
-  wave_sync();
-  // q_a += hinv_a (D along a, S along the others)^T DQ
-  for (int a = 0; a < 3; ++a) sweep<N, true, false>(a == 2 ? D : S, 2, DQ, T1 + a * N3, 1.0, lane);
-  wave_sync();
-  for (int a = 0; a < 3; ++a) sweep<N, true, false>(a == 1 ? D : S, 1, T1 + a * N3, T2 + a * N3, 1.0, lane);
-  wave_sync();
-  for (int a = 0; a < 3; ++a) sweep<N, true, true>(a == 0 ? D : S, 0, T2 + a * N3, q + a * N3, hinv[a], lane);
+  if (act) {
+    sweep1<N, true, true>(D, 0, T, q, hinv[0], t);
+    cfence();
+    sweep1<N, true, true>(S, 0, T + N3, q + N3, hinv[1], t);
+    cfence();
+    sweep1<N, true, true>(S, 0, T + 2 * N3, q + 2 * N3, hinv[2], t);
+  }
   wave_sync();
 }
 
-// z = M_e^{-1} r = (1/vol) Mi_z Mi_y Mi_x r per component
+// z = M_e^{-1} r = (1/vol) Mi_z Mi_y Mi_x r per component (the y and z sweeps in place)
 template <int N>
-__device__ __forceinline__ void proj_precond(const double* tb, const double* r, double* z, double* T1, double* T2,
-                                             double vol, int lane) {
+__device__ __forceinline__ void proj_precond(const double* tb, const double* r, double* z, double vol, int t,
+                                             bool act) {
   constexpr int N3 = N * N * N;
   const double* Mi = tb + V3Tab{N}.Mi();
-  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mi, 0, r + a * N3, T1 + a * N3, 1.0, lane);
+  if (act)
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) sweep1<N, false, false>(Mi, 0, r + a * N3, z + a * N3, 1.0, t);
   wave_sync();
-  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mi, 1, T1 + a * N3, T2 + a * N3, 1.0, lane);
+  if (act)
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) sweep1<N, false, false>(Mi, 1, z + a * N3, z + a * N3, 1.0, t);
   wave_sync();
-  for (int a = 0; a < 3; ++a) sweep<N, false, false>(Mi, 2, T2 + a * N3, z + a * N3, 1.0 / vol, lane);
+  if (act)
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) sweep1<N, false, false>(Mi, 2, z + a * N3, z + a * N3, 1.0 / vol, t);
   wave_sync();
 }
 
-template <int N>
-__global__ void __launch_bounds__(64 * PShape<N>::WAVES) k_v3_projection(
+template <int N, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_v3_projection(
     const double* __restrict__ rhs, double* __restrict__ xg, const CartGeom<double> g,
     const double* __restrict__ tab, const double* __restrict__ taus, double rtol, int max_iter, int* iters,
     int64_t ncells) {
-  using SH = PShape<N>;
-  constexpr int N3 = SH::N3, V = SH::V;
+  using P = PPack<N>;
+  constexpr int N2 = P::N2, N3 = P::N3, V = P::V, SS = P::SS, CPW = P::CPW;
   __shared__ double s_tab[V3Shape<N>::TABN];
-  __shared__ double s_all[SH::WAVES * SH::SLICE];
+  __shared__ double s_all[WAVES * CPW * P::SLICE];
   for (int e = threadIdx.x; e < V3Shape<N>::TABN; e += blockDim.x) s_tab[e] = tab[e];
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t cell = static_cast<int64_t>(blockIdx.x) * SH::WAVES + wave;
+  const int slot = lane / SS, t = lane % SS;
+  const int64_t cell = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * CPW + slot;
+  // a cell's lanes leave together; the group sums read only lanes of the same cell
   if (cell >= ncells) return;
-  double* x = s_all + wave * SH::SLICE;
-  double* r = x + V;
-  double* z = r + V;
-  double* p = z + V;
+  const bool act = t < N2;
+  double* r = s_all + (wave * CPW + slot) * P::SLICE;
+  double* p = r + V;    // x for the first apply
   double* q = p + V;
-  double* T1 = q + V;
-  double* T2 = T1 + V;
-  double* DQ = T2 + V;
+  double* T = q + V;    // temporary of the apply; z between the preconditioner and the p update
   const int64_t Nd = ncells * N3;
   const CellIdx ci = cell_of(g, cell);
   const double vol = ci.h[0] * ci.h[1] * ci.h[2];
   const double hinv[3] = {1.0 / ci.h[0], 1.0 / ci.h[1], 1.0 / ci.h[2]};
   const double tau = taus[cell];
+  double xr[3 * N];    // x of this lane's nodes t + N^2 j, in registers
   double bb = 0;
-  for (int e = lane; e < V; e += 64) {
-    const int64_t at = (e / N3) * Nd + cell * N3 + e % N3;
-    x[e] = xg[at];
-    const double b = rhs[at];
-    r[e] = b;
-    bb = fma(b, b, bb);
-  }
-  bb = wave_sum(bb);
+#pragma unroll
+  for (int j = 0; j < 3 * N; ++j) xr[j] = 0.0;
+  if (act)
+#pragma unroll
+    for (int j = 0; j < 3 * N; ++j) {
+      const int e = t + N2 * j;
+      const int64_t at = (e / N3) * Nd + cell * N3 + e % N3;
+      xr[j] = xg[at];
+      p[e] = xr[j];
+      const double b = rhs[at];
+      r[e] = b;
+      bb = fma(b, b, bb);
+    }
+  bb = group_sum<SS>(bb);
   wave_sync();
-  proj_apply<N>(s_tab, x, q, T1, T2, DQ, hinv, vol, tau, lane);
+  proj_apply<N>(s_tab, p, q, T, hinv, vol, tau, t, act);
   double rr = 0;
-  for (int e = lane; e < V; e += 64) {
-    const double t = r[e] - q[e];
-    r[e] = t;
-    rr = fma(t, t, rr);
-  }
-  rr = wave_sum(rr);
+  if (act)
+#pragma unroll
+    for (int j = 0; j < 3 * N; ++j) {
+      const int e = t + N2 * j;
+      const double d = r[e] - q[e];
+      r[e] = d;
+      rr = fma(d, d, rr);
+    }
+  rr = group_sum<SS>(rr);
   wave_sync();
   const double tol2 = rtol * rtol * bb;
   int it = 0;
   if (rr > tol2) {
-    proj_precond<N>(s_tab, r, z, T1, T2, vol, lane);
+    proj_precond<N>(s_tab, r, T, vol, t, act);
     double rz = 0;
-    for (int e = lane; e < V; e += 64) {
-      p[e] = z[e];
-      rz = fma(r[e], z[e], rz);
-    }
-    rz = wave_sum(rz);
+    if (act)
+#pragma unroll
+      for (int j = 0; j < 3 * N; ++j) {
+        const int e = t + N2 * j;
+        p[e] = T[e];
+        rz = fma(r[e], T[e], rz);
+      }
+    rz = group_sum<SS>(rz);
     wave_sync();
     while (it < max_iter) {
-      proj_apply<N>(s_tab, p, q, T1, T2, DQ, hinv, vol, tau, lane);
+      proj_apply<N>(s_tab, p, q, T, hinv, vol, tau, t, act);
       double pq = 0;
-      for (int e = lane; e < V; e += 64) pq = fma(p[e], q[e], pq);
-      pq = wave_sum(pq);
+      if (act)
+#pragma unroll
+        for (int j = 0; j < 3 * N; ++j) pq = fma(p[t + N2 * j], q[t + N2 * j], pq);
+      pq = group_sum<SS>(pq);
       if (!(pq > 0)) break;    // breakdown (only for a non-positive tau)
       const double alpha = rz / pq;
       rr = 0;
-      for (int e = lane; e < V; e += 64) {
-        x[e] = fma(alpha, p[e], x[e]);
-        const double t = fma(-alpha, q[e], r[e]);
-        r[e] = t;
-        rr = fma(t, t, rr);
-      }
-      rr = wave_sum(rr);
+      if (act)
+#pragma unroll
+        for (int j = 0; j < 3 * N; ++j) {
+          const int e = t + N2 * j;
+          xr[j] = fma(alpha, p[e], xr[j]);
+          const double d = fma(-alpha, q[e], r[e]);
+          r[e] = d;
+          rr = fma(d, d, rr);
+        }
+      rr = group_sum<SS>(rr);
       ++it;
       wave_sync();
       if (rr <= tol2) break;
-      proj_precond<N>(s_tab, r, z, T1, T2, vol, lane);
+      proj_precond<N>(s_tab, r, T, vol, t, act);
       double rz1 = 0;
-      for (int e = lane; e < V; e += 64) rz1 = fma(r[e], z[e], rz1);
-      rz1 = wave_sum(rz1);
+      if (act)
+#pragma unroll
+        for (int j = 0; j < 3 * N; ++j) rz1 = fma(r[t + N2 * j], T[t + N2 * j], rz1);
+      rz1 = group_sum<SS>(rz1);
       const double beta = rz1 / rz;
       rz = rz1;
-      for (int e = lane; e < V; e += 64) p[e] = fma(beta, p[e], z[e]);
+      if (act)
+#pragma unroll
+        for (int j = 0; j < 3 * N; ++j) {
+          const int e = t + N2 * j;
+          p[e] = fma(beta, p[e], T[e]);
+        }
       wave_sync();
     }
   }
-  for (int e = lane; e < V; e += 64) xg[(e / N3) * Nd + cell * N3 + e % N3] = x[e];
-  if (iters && lane == 0) iters[cell] = it;
+  if (act)
+#pragma unroll
+    for (int j = 0; j < 3 * N; ++j) {
+      const int e = t + N2 * j;
+      xg[(e / N3) * Nd + cell * N3 + e % N3] = xr[j];
+    }
+  if (iters && t == 0) iters[cell] = it;
 }
 
 template <int N>
@@ -552,11 +637,12 @@ dgmf_status tau_n(const CartGeom<double>& g, const double* tab, const double* u,
 template <int N>
 dgmf_status proj_n(const CartGeom<double>& g, const double* tab, const double* tau, const double* rhs, double* x,
                    double rtol, int max_iter, int* iters, int64_t ncells, hipStream_t s) {
-  constexpr int W = PShape<N>::WAVES;
-  const int64_t blocks = (ncells + W - 1) / W;
+  constexpr int W = PPack<N>::WAVES, CPW = PPack<N>::CPW;
+  const int64_t waves = (ncells + CPW - 1) / CPW;
+  const int64_t blocks = (waves + W - 1) / W;
   if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "v3: too many cells for one launch");
-  hipLaunchKernelGGL((k_v3_projection<N>), dim3(static_cast<unsigned>(blocks)), dim3(64 * W), 0, s, rhs, x, g, tab,
-                     tau, rtol, max_iter, iters, ncells);
+  hipLaunchKernelGGL((k_v3_projection<N, W>), dim3(static_cast<unsigned>(blocks)), dim3(64 * W), 0, s, rhs, x, g,
+                     tab, tau, rtol, max_iter, iters, ncells);
   DGMF_LAUNCH_CHECK("k_v3_projection");
   return DGMF_OK;
 }
