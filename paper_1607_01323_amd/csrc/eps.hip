@@ -64,6 +64,10 @@ struct EPack {
   static constexpr int MINW = N > 5 || per_cu(WAVES) / 4 < 1 ? 1 : (per_cu(WAVES) / 4 > 3 ? 3 : per_cu(WAVES) / 4);
 };
 
+// Compiler-only ordering point (no instruction): keeps the scheduler from
+// interleaving consecutive line products, which bounds the live registers.
+__device__ __forceinline__ void cfence() { asm volatile("" ::: "memory"); }
+
 // base node and stride of line t along `axis` of an N^3 array
 template <int N>
 __device__ __forceinline__ void line_of(int axis, int t, int& base, int& stride) {
@@ -169,18 +173,24 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
     load_line<N>(S0, b, st, v);
     lmul<N, false, false>(Kh, v, 1.0, r);
     store_line<N>(S0, b, st, r);
+    cfence();
     lmul<N, false, false>(Ch, v, 1.0, r);
     store_line<N>(S1, b, st, r);
+    cfence();
     load_line<N>(S2, b, st, v);
     lmul<N, false, false>(Mh, v, 1.0, r);
     store_line<N>(S2, b, st, r);
+    cfence();
     lmul<N, true, false>(Ch, v, 1.0, r);
     store_line<N>(S3, b, st, r);
+    cfence();
     load_line<N>(S5, b, st, v);
     lmul<N, false, false>(Mh, v, 1.0, r);
     store_line<N>(S5, b, st, r);
+    cfence();
     lmul<N, true, false>(Ch, v, 1.0, r);
     store_line<N>(S4, b, st, r);
+    cfence();
   }
   wave_sync();
   // y: S0 = s00 Mh S0 + s01 Ch S3 (then Mh along z), S4 = s02 Mh S4 (then Ch),
@@ -195,22 +205,28 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
     lmul<N, false, false>(Mh, v, sc[0][0], r);
     lmul<N, false, true>(Ch, w, sc[0][1], r);
     store_line<N>(S0, b, st, r);
+    cfence();
     load_line<N>(S4, b, st, v);
     lmul<N, false, false>(Mh, v, sc[0][2], r);
     store_line<N>(S4, b, st, r);
+    cfence();
     load_line<N>(S1, b, st, v);
     load_line<N>(S2, b, st, w);
     lmul<N, true, false>(Ch, v, sc[1][0], r);
     lmul<N, false, true>(Kh, w, sc[1][1], r);
     store_line<N>(S1, b, st, r);
+    cfence();
     lmul<N, false, false>(Mh, v, sc[2][0], r);
     lmul<N, false, true>(Ch, w, sc[2][1], r);
     store_line<N>(S2, b, st, r);
+    cfence();
     load_line<N>(S5, b, st, v);
     lmul<N, true, false>(Ch, v, sc[1][2], r);
     store_line<N>(S5, b, st, r);
+    cfence();
     lmul<N, false, false>(Mh, v, sc[2][2], r);
     store_line<N>(S3, b, st, r);
+    cfence();
   }
   wave_sync();
   // z: O0 = Mh S0 + Ch S4 -> S0, O1 = Mh S1 + Ch S5 -> S1, O2 = Ch^T S2 + Kh S3 -> S2
@@ -223,16 +239,19 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
     lmul<N, false, false>(Mh, v, 1.0, r);
     lmul<N, false, true>(Ch, w, 1.0, r);
     store_line<N>(S0, b, st, r);
+    cfence();
     load_line<N>(S1, b, st, v);
     load_line<N>(S5, b, st, w);
     lmul<N, false, false>(Mh, v, 1.0, r);
     lmul<N, false, true>(Ch, w, 1.0, r);
     store_line<N>(S1, b, st, r);
+    cfence();
     load_line<N>(S2, b, st, v);
     load_line<N>(S3, b, st, w);
     lmul<N, true, false>(Ch, v, 1.0, r);
     lmul<N, false, true>(Kh, w, 1.0, r);
     store_line<N>(S2, b, st, r);
+    cfence();
   }
   wave_sync();
   // ---- faces; this lane's plane node (p1, p2)
