@@ -39,6 +39,8 @@ from .sipg import _kron3
 
 class Convective:
     def __init__(self, mesh, nq=None, g=None):
+        if mesh.has_neumann():
+            raise NotImplementedError("convective operator: outflow boundaries are not modelled")
         self.mesh = mesh
         k = mesh.k
         self.n = k + 1

@@ -4,7 +4,9 @@ Sec. 3.1 of the paper: a tessellation into hexahedra, interior faces shared
 by a minus and a plus element with opposite normals, exterior faces split into
 Dirichlet and Neumann parts.  Here: an axis-aligned box
 [0,lx] x [y0,y0+ly] x [0,lz] cut into nx*ny*nz cells, each direction either
-periodic (wrap-around faces count as interior faces) or Dirichlet at both ends.
+periodic (wrap-around faces count as interior faces) or bounded at both ends,
+each bounding side Dirichlet or homogeneous Neumann (``neumann``, six flags
+in face-id order; ignored in periodic directions).
 The y vertices may be graded with the hyperbolic channel mapping of Sec. 7.1,
 y = y0 + ly/2 * (1 + tanh(gamma (2t-1)) / tanh(gamma)), t in [0,1].
 
@@ -23,11 +25,12 @@ from . import basis
 
 class BoxMesh:
     def __init__(self, degree, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, y0=0.0,
-                 periodic=(True, True, True), y_tanh_gamma=0.0, shear=None):
+                 periodic=(True, True, True), y_tanh_gamma=0.0, shear=None, neumann=(False,) * 6):
         self.k = int(degree)
         self.n = self.k + 1
         self.nc = (int(nx), int(ny), int(nz))
         self.periodic = tuple(bool(p) for p in periodic)
+        self.neumann = tuple(bool(neumann[f]) and not self.periodic[f // 2] for f in range(6))
         self.gamma = float(y_tanh_gamma)
         t = np.arange(ny + 1) / ny
         if self.gamma > 0:
@@ -64,7 +67,7 @@ class BoxMesh:
         return J
 
     def neighbor(self, c, f):
-        """Cell across face f of cell c, or -1 on a Dirichlet boundary."""
+        """Cell across face f of cell c, or -1 on the boundary (Dirichlet or Neumann)."""
         d, s = divmod(f, 2)
         idx = list(self.cell_coords(c))
         idx[d] += 1 if s == 1 else -1
@@ -86,7 +89,15 @@ class BoxMesh:
 
     def boundary_faces(self):
         """(c, f) for every face of a cell on the Dirichlet boundary."""
-        return [(c, f) for c in range(self.ncells) for f in range(6) if self.neighbor(c, f) < 0]
+        return [(c, f) for c in range(self.ncells) for f in range(6)
+                if self.neighbor(c, f) < 0 and not self.neumann[f]]
+
+    def neumann_faces(self):
+        """(c, f) for every face of a cell on the Neumann boundary."""
+        return [(c, f) for c in range(self.ncells) for f in range(6) if self.neighbor(c, f) < 0 and self.neumann[f]]
+
+    def has_neumann(self):
+        return any(self.neumann)
 
     # -- geometry ------------------------------------------------------------
     def face_area(self, c, f):

@@ -52,7 +52,7 @@ def coarser_mesh(m, counts):
         raise ValueError("multigrid hierarchy: sheared meshes are not supported")
     vx, vy, vz = m.verts
     return omesh.BoxMesh(m.k, *counts, lx=vx[-1] - vx[0], ly=vy[-1] - vy[0], lz=vz[-1] - vz[0], y0=vy[0],
-                         periodic=m.periodic, y_tanh_gamma=m.gamma)
+                         periodic=m.periodic, y_tanh_gamma=m.gamma, neumann=m.neumann)
 
 
 def prolongation(fine, coarse):

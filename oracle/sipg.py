@@ -10,8 +10,15 @@ forms over both elements of every face gives, with [u] = u^- - u^+,
          - sum_{F interior or periodic} [ ({{grad v}}.n, [u]) + ([v], {{grad u}}.n) - tau_F ([v],[u]) ]_F
          - sum_{F Dirichlet}            [ (grad v.n, u) + (v, grad u.n) - 2 tau_F (v,u) ]_F
 
-  tau_e = s (k+1)^2 (A(interior faces)/2 + A(Dirichlet faces)) / V      (eq. taue; s = penalty scale)
+  tau_e = s (k+1)^2 (A(interior faces)/2 + A(boundary faces)) / V      (eq. taue; s = penalty scale)
   tau_F = max(tau_e^-, tau_e^+) on interior faces, tau_e^- on boundary faces  (eq. tau)
+
+Homogeneous Neumann faces add nothing to a(v,u): there the flux takes the
+cell's own trace (P* = p_h for the pressure on the velocity-Dirichlet part,
+U* = u_h for the velocity on the Neumann part) and the flux of the gradient
+is boundary data, which belongs to the right-hand side; their area still
+counts in tau_e (eq. taue sums A over both boundary parts).  Inhomogeneous
+Neumann data is not modelled here.
 
 Helmholtz (viscous step, scalar form applied per component): H = mu M + nu A,
 mu = gamma_0 / dt.  Right-hand side of the Dirichlet problem:
@@ -27,7 +34,10 @@ one-dimensional null space on periodic meshes, definiteness with Dirichlet
 walls, equality with the independent Kronecker-sum construction (``kron``),
 consistency (polynomials of degree <= k reproduced exactly), the coercivity
 threshold of the 1D penalty, the first Laplace eigenvalue (2 pi)^2, and
-optimal L2 convergence of order k+1 on a manufactured solution.
+optimal L2 convergence of order k+1 on a manufactured solution; with
+Neumann sides (tests/test_oracle_neumann.py): constants in the null space,
+the first Neumann eigenvalue pi^2, and order k+1 convergence on a
+manufactured solution with zero normal derivative on the Neumann sides.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -125,7 +135,8 @@ def dirichlet_face_block(T, J, f, tauF):
 
 
 def penalty_per_cell(mesh, penalty_scale=1.0):
-    """tau_e = s (k+1)^2 (A_int/2 + A_Dir)/V per cell (eq. taue)."""
+    """tau_e = s (k+1)^2 (A_int/2 + A_bnd)/V per cell (eq. taue; A_bnd: Dirichlet and
+    Neumann faces alike)."""
     k = mesh.k
     tau = np.empty(mesh.ncells)
     for c in range(mesh.ncells):
@@ -218,7 +229,8 @@ class SIPG:
                 d, s = divmod(f, 2)
                 cn = m.neighbor(c, f)
                 if cn < 0:
-                    y += self.bface_block(c, f) @ U[c]
+                    if not m.neumann[f]:
+                        y += self.bface_block(c, f) @ U[c]
                 elif s == 1:      # c is the minus side (L) of this face
                     B = self.face_block(c, cn, d)
                     y += B[:nb, :nb] @ U[c] + B[:nb, nb:] @ U[cn]
@@ -239,7 +251,8 @@ class SIPG:
                 d, s = divmod(f, 2)
                 cn = m.neighbor(c, f)
                 if cn < 0:
-                    dg += np.diag(self.bface_block(c, f))
+                    if not m.neumann[f]:
+                        dg += np.diag(self.bface_block(c, f))
                 elif s == 1:
                     B = self.face_block(c, cn, d)
                     dg += np.diag(B[:nb, :nb])

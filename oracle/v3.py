@@ -33,6 +33,8 @@ def _cell_grad(T, J):
 
 def _faces(m):
     """Interior faces (cL, cR, d) and boundary faces (c, f)."""
+    if m.has_neumann():
+        raise NotImplementedError("V3c operators: Neumann boundaries are not modelled")
     return m.interior_faces(), m.boundary_faces()
 
 

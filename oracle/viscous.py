@@ -80,6 +80,8 @@ def _face_terms(Tv, gradv, Tu, gradu, W, n, nu, pen):
 
 def viscous_matrix(m, mu, nu, penalty_scale=1.0):
     """Sparse 3N x 3N matrix of a(v, u)."""
+    if m.has_neumann():
+        raise NotImplementedError("viscous operator: Neumann boundaries are not modelled")
     T = sipg.Tables(m.k)
     nb, N = m.n ** 3, m.ndofs
     tau = sipg.penalty_per_cell(m, penalty_scale)
