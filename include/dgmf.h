@@ -88,6 +88,16 @@ int dgmf_version(void);
  * (a constant affine lattice, so cells are parallelepipeds); all zeros means
  * the identity.  A non-identity shear needs store_qp_metric = 1 and is not
  * supported by the convective operator.
+ * neumann[2d+s] = 1 makes the boundary side s (0 low, 1 high) of a
+ * non-periodic direction d a homogeneous Neumann boundary, 0 (default) a
+ * Dirichlet one; ignored in periodic directions.  Sec. 3.2: on such faces the
+ * flux takes the cell's own trace and the gradient flux is data, so the SIPG
+ * operator has no face term there (the pressure Poisson operator on the walls
+ * of a velocity-Dirichlet domain, the viscous operator on an outflow); their
+ * area still counts in tau_e (eq. taue).  Meshes with Neumann sides serve the
+ * SIPG operator, its diagonal, CG and multigrid, the mass matrices and the
+ * cell-local projection; the convective, divergence, gradient and viscous
+ * operators return DGMF_UNSUPPORTED on them.
  * degree k in 1..7; every cell count >= 1; lengths > 0. */
 typedef struct {
   int degree;
@@ -98,6 +108,7 @@ typedef struct {
   double y_tanh_gamma;
   int store_qp_metric;
   double shear[9];
+  int neumann[6];
 } dgmf_box_desc;
 
 /* Allocates device geometry on the current device.  *out receives the handle. */

@@ -67,6 +67,14 @@ void DevBuf::release() {
 }
 
 // Per-direction geometry arrays (x0, h, 1/h, tp) of a box mesh, contiguous.
+// bit 2d+s set: boundary side (d, s) is homogeneous Neumann (stored normalised: 0 in periodic directions)
+static int neumann_mask(const dgmf_box_desc& d) {
+  int mask = 0;
+  for (int f = 0; f < 6; ++f)
+    if (d.neumann[f] && !d.periodic[f / 2]) mask |= 1 << f;
+  return mask;
+}
+
 template <typename T>
 static dgmf_status upload_geometry(dgmf_mesh m, DevBuf& buf, CartGeom<T>& g) {
   const int nd[3] = {m->desc.nx, m->desc.ny, m->desc.nz};
@@ -93,6 +101,7 @@ static dgmf_status upload_geometry(dgmf_mesh m, DevBuf& buf, CartGeom<T>& g) {
   g.nx = nd[0];
   g.ny = nd[1];
   g.nz = nd[2];
+  g.neu = neumann_mask(m->desc);
   for (int d = 0; d < 3; ++d) {
     g.per[d] = m->desc.periodic[d] ? 1 : 0;
     g.x0[d] = base + off[d];
@@ -261,6 +270,7 @@ static dgmf_status setup_metric(dgmf_mesh m) {
     g.nx = nd[0];
     g.ny = nd[1];
     g.nz = nd[2];
+    g.neu = neumann_mask(m->desc);
     for (int d = 0; d < 3; ++d) {
       g.per[d] = m->desc.periodic[d] ? 1 : 0;
       g.lbase[d] = lbase[d];
@@ -389,6 +399,8 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
     return fail(DGMF_INVALID, "mesh_create: lengths must be finite and > 0");
   if (!(d.y_tanh_gamma >= 0) || !std::isfinite(d.y_tanh_gamma))
     return fail(DGMF_INVALID, "mesh_create: y_tanh_gamma must be finite and >= 0");
+  for (int f = 0; f < 6; ++f)
+    if (d.neumann[f] != 0 && d.neumann[f] != 1) return fail(DGMF_INVALID, "mesh_create: neumann[%d] must be 0 or 1", f);
   Shear sh{{1, 0, 0, 0, 1, 0, 0, 0, 1}, 1.0, 0};
   {
     bool zero = true, ident = true;
@@ -426,6 +438,7 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
   m->shear = sh;
   m->desc.store_qp_metric = d.store_qp_metric ? 1 : 0;
   for (int a = 0; a < 3; ++a) m->desc.periodic[a] = d.periodic[a] ? 1 : 0;
+  for (int f = 0; f < 6; ++f) m->desc.neumann[f] = (neumann_mask(m->desc) >> f) & 1;
   m->ncells = ncells;
   m->ndofs = ncells * n * n * n;
   if (hipGetDevice(&m->device) != hipSuccess) {
@@ -566,9 +579,11 @@ dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, cons
                                   false, stream);
 }
 
-static dgmf_status v3_check(dgmf_mesh mesh, const char* who) {
+static dgmf_status v3_check(dgmf_mesh mesh, const char* who, bool faces = true) {
   if (!mesh) return fail(DGMF_INVALID, "%s: null mesh", who);
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "%s: sheared meshes are not supported", who);
+  if (faces && neumann_mask(mesh->desc))
+    return fail(DGMF_UNSUPPORTED, "%s: Neumann boundaries are not supported by this operator", who);
   return DGMF_OK;
 }
 
@@ -613,7 +628,7 @@ dgmf_status dgmf_gradient_apply(dgmf_mesh mesh, const double* p, double* out, hi
 
 dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, double dt, double* tau,
                                 hipStream_t stream) {
-  dgmf_status e = v3_check(mesh, "divdiv_penalty");
+  dgmf_status e = v3_check(mesh, "divdiv_penalty", false);
   if (e) return e;
   if (!u || !tau || !aligned(u, 8) || !aligned(tau, 8))
     return fail(DGMF_INVALID, "divdiv_penalty: null or misaligned vector");
@@ -628,7 +643,7 @@ dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, do
 
 dgmf_status dgmf_projection_solve(dgmf_mesh mesh, const double* tau, const double* rhs, double* x, double rtol,
                                   int max_iter, int* iterations, hipStream_t stream) {
-  dgmf_status e = v3_check(mesh, "projection_solve");
+  dgmf_status e = v3_check(mesh, "projection_solve", false);
   if (e) return e;
   if (!v3_projection_supported(mesh->tab.n))
     return fail(DGMF_UNSUPPORTED, "projection_solve: degree %d not built (k <= 6)", mesh->tab.n - 1);
@@ -852,6 +867,8 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
   const int nq = desc->n_q > 0 ? desc->n_q : (3 * (k + 1)) / 2;
   if (desc->n_q < 0) return fail(DGMF_INVALID, "convective_create: n_q must be >= 0");
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "convective_create: sheared meshes are not supported");
+  if (neumann_mask(mesh->desc))
+    return fail(DGMF_UNSUPPORTED, "convective_create: outflow (Neumann) boundaries are not supported");
   if (!conv_supported(n, nq))
     return fail(DGMF_UNSUPPORTED, "convective_create: degree %d with %d points per direction not built", k, nq);
   DeviceGuard dg(mesh->device);

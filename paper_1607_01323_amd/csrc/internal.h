@@ -21,6 +21,7 @@ template <typename T>
 struct MetricGeom {
   int nx, ny, nz;
   int per[3];
+  int neu;         // bit 2d+s: the boundary side (d, s) is homogeneous Neumann (no face term)
   const T* cm;     // [ncells][7][n^3]: G00 G01 G02 G11 G12 G22 (w detJ J^-1 J^-T), w detJ
   const T* fm;     // [ncells][3][7][n^2]: high face of each direction: wdA, vL(3), vR(3)
   const T* ftau;   // [ncells][3]: penalty geometry of those faces
@@ -96,6 +97,7 @@ template <typename T>
 struct CartGeom {
   int nx, ny, nz;
   int per[3];
+  int neu;            // bit 2d+s: the boundary side (d, s) is homogeneous Neumann (no face term)
   const T* h[3];      // cell size
   const T* hinv[3];   // 1 / cell size
   const T* tp[3];     // w_d / h_d: contribution of direction d to tau_e / (s (k+1)^2)

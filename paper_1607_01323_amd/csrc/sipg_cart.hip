@@ -47,6 +47,12 @@ __device__ __forceinline__ void matvec(const T* __restrict__ A, const T (&x)[N],
   }
 }
 
+// Weight of the terms of boundary side f = 2d+s: 0 if it is homogeneous Neumann.
+template <typename T>
+__device__ __forceinline__ T bw_of(int neu, int f) {
+  return ((neu >> f) & 1) ? T(0) : T(1);
+}
+
 // One direction's line operator A_d for one line of the cell.
 //   u      : the line of this cell
 //   ul, ur : the same line of the low / high neighbour (unused on Dirichlet faces)
@@ -58,10 +64,11 @@ __device__ __forceinline__ void matvec(const T* __restrict__ A, const T (&x)[N],
 //   out_i += sigma (-1/2 l_i'(0)/h [u] + delta_{i,0} ({{u'}} - tau [u]))
 // Dirichlet high face: out_i += sigma (-l_i'(1)/h u_N-1 + delta_{i,N-1}(-l'(1).u/h + 2 tau u_N-1))
 // Dirichlet low face:  out_i += sigma ( l_i'(0)/h u_0   + delta_{i,0}  ( l'(0).u/h + 2 tau u_0))
+// bwL, bwR scale a boundary face's terms: 1 on Dirichlet, 0 on homogeneous Neumann faces.
 template <int N, typename T>
 __device__ __forceinline__ void sipg_line(const T* __restrict__ tab, const T (&u)[N], const T (&ul)[N],
-                                          const T (&ur)[N], bool dirL, bool dirR, T hinv, T hlinv, T hrinv,
-                                          T tauL, T tauR, T sigma, T massc, T (&out)[N]) {
+                                          const T (&ur)[N], bool dirL, bool dirR, T bwL, T bwR, T hinv, T hlinv,
+                                          T hrinv, T tauL, T tauR, T sigma, T massc, T (&out)[N]) {
   const T* Mh = tab;
   const T* Kh = tab + N * N;
   const T* g0 = tab + 2 * N * N;
@@ -76,8 +83,8 @@ __device__ __forceinline__ void sipg_line(const T* __restrict__ tab, const T (&u
   gu1 *= hinv;
   T jr, cr, jl, cl;
   if (dirR) {
-    jr = u[N - 1];
-    cr = -gu1 + T(2) * tauR * u[N - 1];
+    jr = bwR * u[N - 1];
+    cr = bwR * (-gu1 + T(2) * tauR * u[N - 1]);
   } else {
     T gr = 0;
 #pragma unroll
@@ -88,8 +95,8 @@ __device__ __forceinline__ void sipg_line(const T* __restrict__ tab, const T (&u
     cr = -avg + tauR * jump;
   }
   if (dirL) {
-    jl = u[0];
-    cl = gu0 + T(2) * tauL * u[0];
+    jl = bwL * u[0];
+    cl = bwL * (gu0 + T(2) * tauL * u[0]);
   } else {
     T gl = 0;
 #pragma unroll
@@ -180,13 +187,14 @@ __device__ __forceinline__ void matvec_acc(cptr<T> A, const T (&x)[N], T (&y)[N]
 //   -1/2 l'(1)_i/h [u] + delta_{i,N-1} (tau [u] - {{u'}});
 // interior low face, [u] = ul_N-1 - u_0, {{u'}} = (l'(1).ul/hl + l'(0).u/h)/2:
 //   -1/2 l'(0)_i/h [u] + delta_{i,0} ({{u'}} - tau [u]);
-// Dirichlet faces mirror these with [u] = u and the boundary penalty 2 tau.
+// Dirichlet faces mirror these with [u] = u and the boundary penalty 2 tau,
+// scaled by bwL / bwR (0 on homogeneous Neumann faces, which add nothing).
 // The low neighbour enters only through its end value ul_{N-1} and
 // gl = l'(1).ul (unscaled); bline_t takes those, bline the line.
 template <int N, typename T>
 __device__ __forceinline__ void bline_t(cptr<T> tab, const T (&u)[N], T ul_end, T gl,
-                                        const T (&ur)[N], bool dirL, bool dirR, T hinv, T hlinv, T hrinv, T tauL,
-                                        T tauR, T s, T (&w)[N]) {
+                                        const T (&ur)[N], bool dirL, bool dirR, T bwL, T bwR, T hinv, T hlinv,
+                                        T hrinv, T tauL, T tauR, T s, T (&w)[N]) {
   constexpr TabLayout L{N, N};
   cptr<T> g0 = tab + L.g0();
   cptr<T> g1 = tab + L.g1();
@@ -205,8 +213,8 @@ __device__ __forceinline__ void bline_t(cptr<T> tab, const T (&u)[N], T ul_end, 
   gu1 *= hinv;
   T cR, eR, cL, eL;
   if (dirR) {
-    cR = -hinv * u[N - 1];
-    eR = fma(T(2) * tauR, u[N - 1], -gu1);
+    cR = -bwR * hinv * u[N - 1];
+    eR = bwR * fma(T(2) * tauR, u[N - 1], -gu1);
   } else {
     T gr = g0[0] * ur[0];
 #pragma unroll
@@ -217,8 +225,8 @@ __device__ __forceinline__ void bline_t(cptr<T> tab, const T (&u)[N], T ul_end, 
     eR = fma(tauR, jump, -avg);
   }
   if (dirL) {
-    cL = hinv * u[0];
-    eL = fma(T(2) * tauL, u[0], gu0);
+    cL = bwL * hinv * u[0];
+    eL = bwL * fma(T(2) * tauL, u[0], gu0);
   } else {
     const T jump = ul_end - u[0];
     const T avg = T(0.5) * fma(gl, hlinv, gu0);
@@ -252,10 +260,11 @@ __device__ __forceinline__ T dot_row(cptr<T> r, const T (&v)[N]) {
 
 template <int N, typename T>
 __device__ __forceinline__ void bline(cptr<T> tab, const T (&u)[N], const T (&ul)[N], const T (&ur)[N], bool dirL,
-                                      bool dirR, T hinv, T hlinv, T hrinv, T tauL, T tauR, T s, T (&w)[N]) {
+                                      bool dirR, T bwL, T bwR, T hinv, T hlinv, T hrinv, T tauL, T tauR, T s,
+                                      T (&w)[N]) {
   constexpr TabLayout L{N, N};
   const T gl = dirL ? T(0) : dot_row<N, T>(tab + L.g1(), ul);
-  bline_t<N, T>(tab, u, ul[N - 1], gl, ur, dirL, dirR, hinv, hlinv, hrinv, tauL, tauR, s, w);
+  bline_t<N, T>(tab, u, ul[N - 1], gl, ur, dirL, dirR, bwL, bwR, hinv, hlinv, hrinv, tauL, tauR, s, w);
 }
 
 // ------------------------------------------------------ z-marching apply ---
@@ -411,7 +420,8 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
       const T mv = g.mu * vol;
 #pragma unroll
       for (int l = 0; l < N; ++l) w[l] = mv * uc[l];
-      bline_t<N, T>(tab, uc, up_end, up_dot, un, zl_dir, zr_dir, hinvz, zl_hinv, zr_hinv, tzl, tzr, vnu * hinvz, w);
+      bline_t<N, T>(tab, uc, up_end, up_dot, un, zl_dir, zr_dir, bw_of<T>(g.neu, 4), bw_of<T>(g.neu, 5), hinvz,
+                    zl_hinv, zr_hinv, tzl, tzr, vnu * hinvz, w);
     }
 #pragma unroll
     for (int l = 0; l < N; ++l) {
@@ -443,7 +453,8 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
     } else {
       const T tl = c.yl_dir ? tau_c : fmax(tau_c, g.pen * (c.tpx + c.yl_tp + tpz));
       const T tr = c.yr_dir ? tau_c : fmax(tau_c, g.pen * (c.tpx + c.yr_tp + tpz));
-      bline<N, T>(tab, uy, vl, vr, c.yl_dir, c.yr_dir, c.hinvy, c.yl_hinv, c.yr_hinv, tl, tr, vnu * c.hinvy, w);
+      bline<N, T>(tab, uy, vl, vr, c.yl_dir, c.yr_dir, bw_of<T>(g.neu, 2), bw_of<T>(g.neu, 3), c.hinvy, c.yl_hinv,
+                  c.yr_hinv, tl, tr, vnu * c.hinvy, w);
     }
 #pragma unroll
     for (int j = 0; j < N; ++j) sw[(l * N + j) * P + i] = w[j];
@@ -468,7 +479,8 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
     } else {
       const T tl = c.xl_dir ? tau_c : fmax(tau_c, g.pen * (c.xl_tp + c.tpy + tpz));
       const T tr = c.xr_dir ? tau_c : fmax(tau_c, g.pen * (c.xr_tp + c.tpy + tpz));
-      bline<N, T>(tab, ux, vl, vr, c.xl_dir, c.xr_dir, c.hinvx, c.xl_hinv, c.xr_hinv, tl, tr, vnu * c.hinvx, w);
+      bline<N, T>(tab, ux, vl, vr, c.xl_dir, c.xr_dir, bw_of<T>(g.neu, 0), bw_of<T>(g.neu, 1), c.hinvx, c.xl_hinv,
+                  c.xr_hinv, tl, tr, vnu * c.hinvx, w);
     }
     matvec_acc<N, T>(tab, w, o);
 #pragma unroll
@@ -766,7 +778,8 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
     const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
     const T sigma = g.nu * ci.h[d1] * ci.h[d2];
     const T massc = d == 0 ? g.mu * ci.h[0] * ci.h[1] * ci.h[2] : T(0);
-    sipg_line<N, T>(g.tab, e, el, er, !hasL, !hasR, ci.hinv[d], hl, hr, tauL, tauR, sigma, massc, out);
+    sipg_line<N, T>(g.tab, e, el, er, !hasL, !hasR, bw_of<T>(g.neu, 2 * d), bw_of<T>(g.neu, 2 * d + 1), ci.hinv[d],
+                    hl, hr, tauL, tauR, sigma, massc, out);
     T v = out[0];
 #pragma unroll
     for (int m = 1; m < N; ++m) v = (m == p) ? out[m] : v;

@@ -13,7 +13,8 @@
 //   (grad u . n) wdA   = hat(grad u) . (J^{-1} n wdA).
 // Interior faces (Sec. 3.2, eqs. ipflux, tau), [u] = uL - uR, {{du/dn}} over both sides:
 //   - ({{grad v}}.n, [u]) - ([v], {{grad u}}.n) + tau ([v], [u])
-// Dirichlet faces: - (grad v.n, u) - (v, grad u.n) + 2 tau (v, u).
+// Dirichlet faces: - (grad v.n, u) - (v, grad u.n) + 2 tau (v, u); homogeneous
+// Neumann faces: nothing (Sec. 3.2: own-trace flux, gradient flux is data).
 //
 // Kernel layout: the n^2 lanes of a cell sit in one wavefront (several cells
 // per wavefront when n^2 <= 32, four wavefronts per workgroup); the cell's
@@ -334,8 +335,10 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
         fv = own_is_L ? (-avg + tau * jump * wdA) : (avg - tau * jump * wdA);
         fgc = T(-0.5) * jump;
       } else {
-        fv = -ano + T(2) * tau * uo_f * wdA;
-        fgc = -uo_f;
+        // Dirichlet face; a homogeneous Neumann face adds nothing
+        const T bw = ((g.neu >> f) & 1) ? T(0) : T(1);
+        fv = bw * (-ano + T(2) * tau * uo_f * wdA);
+        fgc = -bw * uo_f;
       }
       fv *= g.nu;
       fgc *= g.nu;
@@ -445,6 +448,7 @@ __global__ void __launch_bounds__(256) k_sipg_metric_diag(TO* __restrict__ diag,
         if (g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
         else dir = true;
       }
+      if (dir && ((g.neu >> (2 * d + s)) & 1)) continue;   // homogeneous Neumann face: no term
       const double* fm;
       double tau;
       bool own_is_L;

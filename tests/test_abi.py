@@ -46,6 +46,10 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     d.nx, d.lx = 2, -1.0
     assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
     d.lx = 1.0
+    d.neumann = (ctypes.c_int * 6)(0, 0, 2, 0, 0, 0)                     # flags are 0 or 1
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    assert b"neumann" in dg._lib.dgmf_last_error()
+    d.neumann = (ctypes.c_int * 6)()
     d.shear = (ctypes.c_double * 9)(1, 0.3, 0, 0, 1, 0, 0, 0, 1)       # shear needs the stored metric
     assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
     assert b"store_qp_metric" in dg._lib.dgmf_last_error()
