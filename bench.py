@@ -245,6 +245,37 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     m3.close()
     ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4, "c4"))
     ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4_SMALL, "c4small", cg=False))
+    ex.update(pressure_measurements(dg, inp, torch, inp.CHANNEL_PRESSURE_C4, "c4p"))
+    return ex
+
+
+def pressure_measurements(dg, inp, torch, w, tag):
+    """Channel pressure Poisson (Neumann walls, singular): apply, and PCG to 1e-10 on a
+    mean-free random right-hand side with the fp32 multigrid V-cycle, the fp32
+    Chebyshev preconditioner and Jacobi."""
+    ex = {}
+    m = dg.Mesh.from_workload(w)
+    op = dg.SipgOperator(m, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    N = m.ndofs
+    v = torch.as_tensor(inp.uniform(3, N), device="cuda")
+    yv = torch.empty_like(v)
+    ta = _events_time(lambda: op.apply(v, yv), 20, 3)
+    ex[f"{tag}_apply_f64"] = {"us": ta * 1e6, "dofs_per_s": N / ta}
+    b = torch.as_tensor(inp.uniform(10, N), device="cuda")
+    b -= b.mean()
+    for name, kw in (("mixed_f32mg", dict(precond="multigrid", precond_dtype=torch.float32)),
+                     ("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
+                     ("jacobi_f64", dict(precond="jacobi"))):
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = op.cg(b, x, rtol=1e-10, max_iter=20000, check_every=8, seed=42, project_mean=True,
+                    raise_on_failure=False, **kw)
+        torch.cuda.synchronize()
+        ex[f"{tag}_cg_{name}"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
+                                  "status": out.status, "setup_s": out.setup_s, "solve_s": out.solve_s,
+                                  "rel_residual": out.rel_residual}
+    m.close()
     return ex
 
 
