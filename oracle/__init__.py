@@ -17,11 +17,14 @@ method) serve both.
 Modules
 -------
 basis       1D nodal Gauss-Lobatto Lagrange basis and Gauss rule (Sec. 3.1, Sec. 5)
-mesh        axis-aligned box meshes, periodic / Dirichlet faces, tanh grading
+mesh        axis-aligned box meshes, periodic / Dirichlet / Neumann faces, tanh grading
             (Sec. 3.1 tessellation; Sec. 7.1 hyperbolic channel mesh mapping)
 sipg        SIPG Laplace / Helmholtz element and face matrices, penalty
             (Sec. 3.2 eqs. poissonspat, ipflux, taue, tau and the viscous step;
             Sec. 4.4 matrix form)
+curved      SIPG operator on iso-parametric curved cells: the degree-k interpolant
+            of a smooth periodic deformation of the box, point-by-point
+            quadrature (Sec. 5, curved cells)
 kron        Kronecker-sum construction and fast-diagonalisation direct solve
             on uniform Cartesian meshes (a second, independent construction)
 solvers     textbook PCG, Lanczos, Chebyshev (Sec. 5.1 "Solving linear systems")
