@@ -76,6 +76,7 @@ class Workload:
     penalty_scale: float = 1.0
     conv_points: int = 0
     neumann: tuple = (False,) * 6      # per side x-, x+, y-, y+, z-, z+ (non-periodic directions)
+    curve_amp: float = 0.0             # amplitude of the curved-cell deformation (0: affine cells)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -101,9 +102,14 @@ CHANNEL_C4_SMALL = Workload("channel_32x24x32_k4", 4, (32, 24, 32), lengths=(TWO
 CHANNEL_PRESSURE_C4 = Workload("channel_pressure_48x32x48_k4", 4, (48, 32, 48), lengths=(TWO_PI, 2.0, math.pi),
                                y0=-1.0, periodic=(True, False, True), y_tanh_gamma=1.8, store_qp_metric=True,
                                mass_coeff=0.0, diff_coeff=1.0, neumann=(False, False, True, True, False, False))
+# the channel Helmholtz operator on curved (iso-parametric) cells: the box
+# deformation of amplitude 0.02 also curves the walls
+CHANNEL_CURVED_C4 = Workload("channel_curved_48x32x48_k4", 4, (48, 32, 48), lengths=(TWO_PI, 2.0, math.pi),
+                             y0=-1.0, periodic=(True, False, True), y_tanh_gamma=1.8, store_qp_metric=True,
+                             mass_coeff=1000.0, diff_coeff=0.01, curve_amp=0.02)
 
 WORKLOADS = {w.name: w for w in (POISSON_C0, HELMHOLTZ_C1, POISSON_C2, CONVECTIVE_C3, CHANNEL_C4,
-                                 CHANNEL_C4_SMALL, CHANNEL_PRESSURE_C4)}
+                                 CHANNEL_C4_SMALL, CHANNEL_PRESSURE_C4, CHANNEL_CURVED_C4)}
 
 
 def scaled(w, cells, name=None):

@@ -98,6 +98,16 @@ int dgmf_version(void);
  * SIPG operator, its diagonal, CG and multigrid, the mass matrices and the
  * cell-local projection; the convective, divergence, gradient and viscous
  * operators return DGMF_UNSUPPORTED on them.
+ * curve_amp = a != 0 makes the cells iso-parametric and curved (Sec. 5): the
+ * box point p (after the tanh grading) moves to
+ *   x = p + a (lx s(t_y) s(t_z), ly s(t_z) s(t_x), lz s(t_x) s(t_y)),
+ * s(t) = sin(2 pi t), t = (p - (0, y0, 0)) / (lx, ly, lz), and each cell's map is
+ * the degree-k interpolant of x at its GLL nodes.  The map is periodic in every
+ * direction; walls of non-periodic directions become curved.  |a| <= 0.1;
+ * needs store_qp_metric = 1 and no shear.  Curved meshes serve the SIPG
+ * operator, its diagonal and CG with the Jacobi or Chebyshev preconditioner;
+ * every other operator (and multigrid, coordinates, load vectors) returns
+ * DGMF_UNSUPPORTED on them.
  * degree k in 1..7; every cell count >= 1; lengths > 0. */
 typedef struct {
   int degree;
@@ -109,6 +119,7 @@ typedef struct {
   int store_qp_metric;
   double shear[9];
   int neumann[6];
+  double curve_amp;
 } dgmf_box_desc;
 
 /* Allocates device geometry on the current device.  *out receives the handle. */

@@ -117,7 +117,9 @@ def _phys_grads(Gref, Jinv):
 class CurvedSIPG:
     """mu M + nu A on a CurvedBoxMesh, point-by-point quadrature."""
 
-    def __init__(self, mesh, mass_coeff=0.0, diff_coeff=1.0, penalty_scale=1.0):
+    def __init__(self, mesh, mass_coeff=0.0, diff_coeff=1.0, penalty_scale=1.0, cells=None):
+        """cells: compute tau_e only for these cells and their face neighbours (for
+        row-restricted applications on large meshes); None: every cell."""
         self.mesh = mesh
         self.mu, self.nu = float(mass_coeff), float(diff_coeff)
         self.T = T = Tables(mesh.k)
@@ -140,8 +142,13 @@ class CurvedSIPG:
             self.face_tabs.append((Tr, G) + _face_points(T, f))
         self._faces = {}
         k = mesh.k
-        self.tau_e = np.empty(mesh.ncells)
-        for c in range(mesh.ncells):
+        self.tau_e = np.full(mesh.ncells, np.nan)
+        need = range(mesh.ncells)
+        if cells is not None:
+            need = set(cells)
+            for c in cells:
+                need.update(cn for cn in (mesh.neighbor(c, f) for f in range(6)) if cn >= 0)
+        for c in need:
             a = 0.0
             for f in range(6):
                 A = self.face(c, f)[2].sum()

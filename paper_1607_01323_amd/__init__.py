@@ -32,7 +32,7 @@ class BoxDesc(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double), ("y0", ctypes.c_double),
                 ("periodic", ctypes.c_int * 3), ("y_tanh_gamma", ctypes.c_double), ("store_qp_metric", ctypes.c_int),
-                ("shear", ctypes.c_double * 9), ("neumann", ctypes.c_int * 6)]
+                ("shear", ctypes.c_double * 9), ("neumann", ctypes.c_int * 6), ("curve_amp", ctypes.c_double)]
 
 
 class SipgDesc(ctypes.Structure):
@@ -130,16 +130,17 @@ def version():
 
 class Mesh:
     """Box mesh of affine hexahedra (see ``dgmf_box_desc``); ``neumann``: six per-side
-    flags (x-, x+, y-, y+, z-, z+), homogeneous Neumann instead of Dirichlet."""
+    flags (x-, x+, y-, y+, z-, z+), homogeneous Neumann instead of Dirichlet;
+    ``curve_amp``: amplitude of the iso-parametric curved-cell deformation."""
 
     def __init__(self, degree, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, y0=0.0, periodic=(1, 1, 1),
-                 y_tanh_gamma=0.0, store_qp_metric=False, shear=None, neumann=(0, 0, 0, 0, 0, 0)):
+                 y_tanh_gamma=0.0, store_qp_metric=False, shear=None, neumann=(0, 0, 0, 0, 0, 0), curve_amp=0.0):
         sh = [0.0] * 9 if shear is None else [float(v) for row in shear for v in row]
         if len(neumann) != 6:
             raise ValueError("neumann: six per-side flags")
         d = BoxDesc(degree, nx, ny, nz, lx, ly, lz, y0, (ctypes.c_int * 3)(*[int(bool(p)) for p in periodic]),
                     y_tanh_gamma, int(bool(store_qp_metric)), (ctypes.c_double * 9)(*sh),
-                    (ctypes.c_int * 6)(*[int(bool(f)) for f in neumann]))
+                    (ctypes.c_int * 6)(*[int(bool(f)) for f in neumann]), float(curve_amp))
         self._h = _vp()
         _check(_mesh_create(ctypes.byref(d), ctypes.byref(self._h)), "mesh_create")
         nc, nd = _i64(), _i64()
@@ -151,7 +152,8 @@ class Mesh:
     @classmethod
     def from_workload(cls, w):
         return cls(w.degree, *w.cells, *w.lengths, y0=w.y0, periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma,
-                   store_qp_metric=w.store_qp_metric, neumann=getattr(w, "neumann", (0,) * 6))
+                   store_qp_metric=w.store_qp_metric, neumann=getattr(w, "neumann", (0,) * 6),
+                   curve_amp=getattr(w, "curve_amp", 0.0))
 
     def node_coords(self):
         out = torch.empty(3 * self.ndofs, dtype=torch.float64, device="cuda")

@@ -292,9 +292,35 @@ static dgmf_status setup_metric(dgmf_mesh m) {
   double shi[9];
   for (int i = 0; i < 9; ++i) shi[i] = static_cast<double>(shinv[i]);
   const double* wdev = static_cast<const double*>(m->mtab64.p) + 3 * n * n + 2 * n;
-  if ((st = launch_metric_fill(n, m->mg64, x0, h, shi, m->shear.det, wdev, b64 + o_cm, b64 + o_fm, b64 + o_ft,
-                               b64 + o_lm, b64 + o_lt, nullptr)))
+  if (m->desc.curve_amp != 0.0) {
+    // GLL nodes, S, D (rows at the Gauss points), l(0), l(1), l'(0), l'(1), Gauss weights
+    std::vector<double> ct(6 * n + 2 * n * n, 0.0);
+    for (int i = 0; i < n; ++i) ct[i] = t.nodes[i];
+    for (int i = 0; i < n * n; ++i) {
+      ct[n + i] = t.S[i];
+      ct[n + n * n + i] = t.D[i];
+    }
+    ct[n + 2 * n * n] = 1.0;
+    ct[2 * n + 2 * n * n + n - 1] = 1.0;
+    for (int i = 0; i < n; ++i) {
+      ct[3 * n + 2 * n * n + i] = t.g0[i];
+      ct[4 * n + 2 * n * n + i] = t.g1[i];
+      ct[5 * n + 2 * n * n + i] = t.wq[i];
+    }
+    DevBuf ctab, taue;
+    if ((st = ctab.upload(ct.data(), ct.size() * sizeof(double)))) return st;
+    if ((st = taue.alloc(static_cast<size_t>(nc) * sizeof(double)))) return st;
+    const double lo[3] = {0.0, m->desc.y0, 0.0};
+    const double len[3] = {m->desc.lx, m->desc.ly, m->desc.lz};
+    if ((st = launch_metric_fill_curved(n, m->mg64, x0, h, lo, len, m->desc.curve_amp,
+                                        static_cast<const double*>(ctab.p), static_cast<double*>(taue.p),
+                                        b64 + o_cm, b64 + o_fm, b64 + o_ft, b64 + o_lm, b64 + o_lt, nullptr)))
+      return st;
+    DGMF_HIP_TRY(hipStreamSynchronize(nullptr));   // the scratch buffers are released at return
+  } else if ((st = launch_metric_fill(n, m->mg64, x0, h, shi, m->shear.det, wdev, b64 + o_cm, b64 + o_fm,
+                                      b64 + o_ft, b64 + o_lm, b64 + o_lt, nullptr))) {
     return st;
+  }
   if ((st = launch_to_f32(b64, static_cast<float*>(m->met32.p), total, nullptr))) return st;
   DGMF_HIP_TRY(hipStreamSynchronize(nullptr));
   return DGMF_OK;
@@ -423,6 +449,12 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
         return fail(DGMF_INVALID, "mesh_create: a non-identity shear needs store_qp_metric = 1");
     }
   }
+  if (!std::isfinite(d.curve_amp) || std::fabs(d.curve_amp) > 0.1)
+    return fail(DGMF_INVALID, "mesh_create: curve_amp must be finite with |curve_amp| <= 0.1");
+  if (d.curve_amp != 0.0) {
+    if (!d.store_qp_metric) return fail(DGMF_INVALID, "mesh_create: curved cells need store_qp_metric = 1");
+    if (sh.on) return fail(DGMF_INVALID, "mesh_create: curve_amp and a shear exclude each other");
+  }
   if (d.store_qp_metric) {
     const int ndc[3] = {d.nx, d.ny, d.nz};
     for (int a = 0; a < 3; ++a)
@@ -530,8 +562,14 @@ dgmf_status dgmf_mesh_destroy(dgmf_mesh mesh) {
   return DGMF_OK;
 }
 
+static dgmf_status flat_check(dgmf_mesh mesh, const char* who) {
+  if (mesh->desc.curve_amp != 0.0) return fail(DGMF_UNSUPPORTED, "%s: curved cells are not supported", who);
+  return DGMF_OK;
+}
+
 dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t stream) {
   if (!mesh || !xyz) return fail(DGMF_INVALID, "mesh_node_coords: null argument");
+  if (dgmf_status e = flat_check(mesh, "mesh_node_coords")) return e;
   if (!aligned(xyz, 8)) return fail(DGMF_INVALID, "mesh_node_coords: misaligned output");
   DeviceGuard dg(mesh->device);
   return launch_node_coords(mesh->tab.n, mesh->g64, mesh->shear, xyz, mesh->ncells, stream);
@@ -540,6 +578,7 @@ dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t strea
 dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
                                     hipStream_t stream) {
   if (!mesh || !src || !dst) return fail(DGMF_INVALID, "inverse_mass_apply: null argument");
+  if (dgmf_status e = flat_check(mesh, "inverse_mass_apply")) return e;
   const size_t es = dtype == DGMF_F64 ? 8 : (dtype == DGMF_F32 ? 4 : 0);
   if (!es) return fail(DGMF_INVALID, "inverse_mass_apply: unknown dtype %d", static_cast<int>(dtype));
   if (n_fields < 1 || n_fields > 64) return fail(DGMF_INVALID, "inverse_mass_apply: n_fields must be in 1..64");
@@ -561,6 +600,7 @@ dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fiel
 dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
                             hipStream_t stream) {
   if (!mesh || !src || !dst) return fail(DGMF_INVALID, "mass_apply: null argument");
+  if (dgmf_status e = flat_check(mesh, "mass_apply")) return e;
   const size_t es = dtype == DGMF_F64 ? 8 : (dtype == DGMF_F32 ? 4 : 0);
   if (!es) return fail(DGMF_INVALID, "mass_apply: unknown dtype %d", static_cast<int>(dtype));
   if (n_fields < 1 || n_fields > 64) return fail(DGMF_INVALID, "mass_apply: n_fields must be in 1..64");
@@ -582,6 +622,7 @@ dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, cons
 static dgmf_status v3_check(dgmf_mesh mesh, const char* who, bool faces = true) {
   if (!mesh) return fail(DGMF_INVALID, "%s: null mesh", who);
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "%s: sheared meshes are not supported", who);
+  if (dgmf_status e = flat_check(mesh, who)) return e;
   if (faces && neumann_mask(mesh->desc))
     return fail(DGMF_UNSUPPORTED, "%s: Neumann boundaries are not supported by this operator", who);
   return DGMF_OK;
@@ -784,12 +825,14 @@ dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hip
 dgmf_status dgmf_quadrature_points(dgmf_op op, double* xyz, hipStream_t stream) {
   if (!op || op->kind != 1) return fail(DGMF_INVALID, "quadrature_points: not an SIPG operator");
   if (!xyz || !aligned(xyz, 8)) return fail(DGMF_INVALID, "quadrature_points: null or misaligned output");
+  if (dgmf_status e = flat_check(op->mesh, "quadrature_points")) return e;
   DeviceGuard dg(op->mesh->device);
   return launch_qp_coords(op->tab.n, op->nq, op->g64, op->mesh->shear, xyz, op->mesh->ncells, stream);
 }
 
 dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_t stream) {
   if (!op || op->kind != 1) return fail(DGMF_INVALID, "integrate: not an SIPG operator");
+  if (dgmf_status e = flat_check(op->mesh, "integrate")) return e;
   if (!f_qp || !b || !aligned(f_qp, 8) || !aligned(b, 8))
     return fail(DGMF_INVALID, "integrate: null or misaligned vector");
   const int64_t nq3 = static_cast<int64_t>(op->nq) * op->nq * op->nq;
@@ -867,6 +910,7 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
   const int nq = desc->n_q > 0 ? desc->n_q : (3 * (k + 1)) / 2;
   if (desc->n_q < 0) return fail(DGMF_INVALID, "convective_create: n_q must be >= 0");
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "convective_create: sheared meshes are not supported");
+  if (dgmf_status e = flat_check(mesh, "convective_create")) return e;
   if (neumann_mask(mesh->desc))
     return fail(DGMF_UNSUPPORTED, "convective_create: outflow (Neumann) boundaries are not supported");
   if (!conv_supported(n, nq))

@@ -205,6 +205,14 @@ dgmf_status launch_metric_fill(int n, const MetricGeom<double>& g, const double*
                                const double shinv[9], double shdet, const double* wq, double* cm, double* fm,
                                double* ftau, double* lm, double* ltau, hipStream_t s);
 
+// Fills the same arrays for iso-parametric curved cells (the interpolated box
+// deformation of amplitude amp); ctab: GLL nodes, S, D, l(0), l(1), l'(0),
+// l'(1), Gauss weights; taue: scratch of one double per cell.
+dgmf_status launch_metric_fill_curved(int n, const MetricGeom<double>& g, const double* const x0[3],
+                                      const double* const h[3], const double lo[3], const double len[3], double amp,
+                                      const double* ctab, double* taue, double* cm, double* fm, double* ftau,
+                                      double* lm, double* ltau, hipStream_t s);
+
 dgmf_status launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
 // Layout of the metric tables: S, D, Dg = D S^{-1} (n x n), l'(0), l'(1), Gauss
 // weights w, and the Lagrange basis on the Gauss points at 0 and at 1 (n each).

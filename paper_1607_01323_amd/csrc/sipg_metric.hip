@@ -613,6 +613,249 @@ __global__ void __launch_bounds__(256) k_metric_fill_faces(FillArgs a, double* f
   }
 }
 
+// Curved (iso-parametric) geometry fill.  The cell map is the degree-k tensor
+// interpolant, at the cell's GLL nodes, of the box deformation
+//   x_r = p_r + amp L_r prod_{e != r} sin(2 pi (p_e - lo_e) / L_e);
+// the interpolant of the affine part is exact and the product separates, so
+//   x_h,r(xi) = x0_r + h_r xi_r + amp L_r prod_{e != r} sig_e(xi_e),
+//   sig_e(t) = sum_i sin(2 pi (x0_e + h_e xi_i - lo_e) / L_e) l_i(t),
+// and J_rd = h_r delta_rd + (r != d) amp L_r sig_d'(xi_d) sig_e'(xi_e') with e'
+// the third direction (no derivative on it).  ctab: GLL nodes, S and D rows at
+// the Gauss points, l(0), l(1), l'(0), l'(1), Gauss weights (n each / n x n).
+struct CurvArgs {
+  MetricGeom<double> g;
+  const double* x0[3];
+  const double* h[3];
+  double lo[3], len[3], amp;
+  double k1sq;
+  const double* ctab;
+  const double* taue;   // per-cell (k+1)^2 (A_int/2 + A_bnd) / V (faces kernel)
+};
+
+struct CurvTabs {
+  int n;
+  __device__ const double* nodes(const double* t) const { return t; }
+  __device__ const double* S(const double* t) const { return t + n; }
+  __device__ const double* D(const double* t) const { return t + n + n * n; }
+  __device__ const double* E(const double* t, int s) const { return t + n + 2 * n * n + s * n; }
+  __device__ const double* G(const double* t, int s) const { return t + 3 * n + 2 * n * n + s * n; }
+  __device__ const double* W(const double* t) const { return t + 5 * n + 2 * n * n; }
+};
+
+// sig and sig' of direction e of cell coordinate ce at the point with row values val, der
+template <int N>
+__device__ __forceinline__ void curv_sig(const CurvArgs& a, int e, int ce, const double* val, const double* der,
+                                         double& sg, double& dsg) {
+  const double* nodes = a.ctab;
+  const double x0 = a.x0[e][ce], h = a.h[e][ce];
+  sg = 0.0;
+  dsg = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double sv = sin(2.0 * M_PI * (x0 + h * nodes[i] - a.lo[e]) / a.len[e]);
+    sg = fma(sv, val[i], sg);
+    dsg = fma(sv, der[i], dsg);
+  }
+}
+
+// J (row-major J[r*3+d]) of cell c at the reference point whose per-direction rows are (val[e], der[e])
+template <int N>
+__device__ __forceinline__ void curv_jac(const CurvArgs& a, const int c[3], const double* const val[3],
+                                         const double* const der[3], double J[9]) {
+  double sg[3], dsg[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) curv_sig<N>(a, e, c[e], val[e], der[e], sg[e], dsg[e]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (r == d) {
+        J[r * 3 + d] = a.h[r][c[r]];
+      } else {
+        const int e = 3 - r - d;
+        J[r * 3 + d] = a.amp * a.len[r] * dsg[d] * sg[e];
+      }
+    }
+}
+
+__device__ __forceinline__ double inv3(const double J[9], double Ji[9]) {
+  const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+  const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+  const double r = 1.0 / det;
+  Ji[0] = c00 * r;
+  Ji[1] = (J[2] * J[7] - J[1] * J[8]) * r;
+  Ji[2] = (J[1] * J[5] - J[2] * J[4]) * r;
+  Ji[3] = c01 * r;
+  Ji[4] = (J[0] * J[8] - J[2] * J[6]) * r;
+  Ji[5] = (J[2] * J[3] - J[0] * J[5]) * r;
+  Ji[6] = c02 * r;
+  Ji[7] = (J[1] * J[6] - J[0] * J[7]) * r;
+  Ji[8] = (J[0] * J[4] - J[1] * J[3]) * r;
+  return det;
+}
+
+// rows of point index qe (0..N-1: Gauss point) or end point s (N + s) along one direction
+template <int N>
+__device__ __forceinline__ void curv_rows(const CurvArgs& a, int qe, const double*& val, const double*& der) {
+  const CurvTabs T{N};
+  if (qe < N) {
+    val = T.S(a.ctab) + qe * N;
+    der = T.D(a.ctab) + qe * N;
+  } else {
+    val = T.E(a.ctab, qe - N);
+    der = T.G(a.ctab, qe - N);
+  }
+}
+
+// face f = 2d+s of cell c at tangential Gauss indices (p1, p2): J^{-1}, det, the row d of J^{-1}
+template <int N>
+__device__ __forceinline__ double curv_face_jinv(const CurvArgs& a, const int c[3], int d, int s, int p1, int p2,
+                                                 double Ji[9]) {
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  int qi[3];
+  qi[d] = N + s;
+  qi[t1] = p1;
+  qi[t2] = p2;
+  const double* val[3];
+  const double* der[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) curv_rows<N>(a, qi[e], val[e], der[e]);
+  double J[9];
+  curv_jac<N>(a, c, val, der, J);
+  return fabs(inv3(J, Ji));
+}
+
+// tau_e / s of every cell: (k+1)^2 (sum over faces of w_f A_f) / V, w_f = 1/2 inside, 1 on the boundary
+template <int N>
+__global__ void __launch_bounds__(256) k_curved_tau(CurvArgs a, double* taue) {
+  const int64_t ncells = static_cast<int64_t>(a.g.nx) * a.g.ny * a.g.nz;
+  const int64_t cell = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= ncells) return;
+  const int c[3] = {static_cast<int>(cell % a.g.nx), static_cast<int>((cell / a.g.nx) % a.g.ny),
+                    static_cast<int>(cell / (static_cast<int64_t>(a.g.nx) * a.g.ny))};
+  const int nd[3] = {a.g.nx, a.g.ny, a.g.nz};
+  const double* w = CurvTabs{N}.W(a.ctab);
+  double vol = 0.0;
+  for (int q = 0; q < N * N * N; ++q) {
+    const int qi[3] = {q % N, (q / N) % N, q / (N * N)};
+    const double* val[3];
+    const double* der[3];
+    for (int e = 0; e < 3; ++e) curv_rows<N>(a, qi[e], val[e], der[e]);
+    double J[9], Ji[9];
+    curv_jac<N>(a, c, val, der, J);
+    vol += w[qi[0]] * w[qi[1]] * w[qi[2]] * fabs(inv3(J, Ji));
+  }
+  double area = 0.0;
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, s = f & 1;
+    const bool bnd = !a.g.per[d] && (s ? c[d] == nd[d] - 1 : c[d] == 0);
+    double A = 0.0;
+    for (int p = 0; p < N * N; ++p) {
+      double Ji[9];
+      const double det = curv_face_jinv<N>(a, c, d, s, p % N, p / N, Ji);
+      const double rn = sqrt(Ji[d * 3] * Ji[d * 3] + Ji[d * 3 + 1] * Ji[d * 3 + 1] + Ji[d * 3 + 2] * Ji[d * 3 + 2]);
+      A += w[p % N] * w[p / N] * det * rn;
+    }
+    area += (bnd ? 1.0 : 0.5) * A;
+  }
+  taue[cell] = a.k1sq * area / vol;
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_curved_fill_cells(CurvArgs a, double* cm) {
+  constexpr int N3 = N * N * N;
+  const int64_t ncells = static_cast<int64_t>(a.g.nx) * a.g.ny * a.g.nz;
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= ncells * N3) return;
+  const int64_t cell = gid / N3;
+  const int q = static_cast<int>(gid - cell * N3);
+  const int c[3] = {static_cast<int>(cell % a.g.nx), static_cast<int>((cell / a.g.nx) % a.g.ny),
+                    static_cast<int>(cell / (static_cast<int64_t>(a.g.nx) * a.g.ny))};
+  const int qi[3] = {q % N, (q / N) % N, q / (N * N)};
+  const double* val[3];
+  const double* der[3];
+  for (int e = 0; e < 3; ++e) curv_rows<N>(a, qi[e], val[e], der[e]);
+  double J[9], Ji[9];
+  curv_jac<N>(a, c, val, der, J);
+  const double* wq = CurvTabs{N}.W(a.ctab);
+  const double w = wq[qi[0]] * wq[qi[1]] * wq[qi[2]] * fabs(inv3(J, Ji));
+  double G[6];
+  int k = 0;
+  for (int r = 0; r < 3; ++r)
+    for (int col = r; col < 3; ++col) {
+      double s = 0.0;
+      for (int m = 0; m < 3; ++m) s += Ji[r * 3 + m] * Ji[col * 3 + m];
+      G[k++] = w * s;
+    }
+  double* out = cm + cell * 7 * N3;
+  for (int e = 0; e < 6; ++e) out[e * N3 + q] = G[e];
+  out[6 * N3 + q] = w;
+}
+
+// high faces (cell, d) and low boundary faces, as k_metric_fill_faces, with the
+// Jacobians of both cells at the face point
+template <int N>
+__global__ void __launch_bounds__(256) k_curved_fill_faces(CurvArgs a, double* fm, double* ftau, double* lm,
+                                                           double* ltau) {
+  constexpr int N2 = N * N;
+  const int64_t ncells = static_cast<int64_t>(a.g.nx) * a.g.ny * a.g.nz;
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= ncells * 6 * N2) return;
+  const int p = static_cast<int>(gid % N2);
+  const int64_t fc = gid / N2;
+  const int f = static_cast<int>(fc % 6);
+  const int64_t cell = fc / 6;
+  const int d = f >> 1, s = f & 1;
+  const int c[3] = {static_cast<int>(cell % a.g.nx), static_cast<int>((cell / a.g.nx) % a.g.ny),
+                    static_cast<int>(cell / (static_cast<int64_t>(a.g.nx) * a.g.ny))};
+  const int nd[3] = {a.g.nx, a.g.ny, a.g.nz};
+  int cn = c[d] + (s ? 1 : -1);
+  bool dir = false;
+  if (cn < 0 || cn >= nd[d]) {
+    if (a.g.per[d]) cn = cn < 0 ? nd[d] - 1 : 0;
+    else dir = true;
+  }
+  if (s == 0 && !dir) return;            // an interior low face is stored as the neighbour's high face
+  const int p1 = p % N, p2 = p / N;
+  double Jl[9];
+  const double detl = curv_face_jinv<N>(a, c, d, s, p1, p2, Jl);
+  double rn = 0.0;
+  for (int m = 0; m < 3; ++m) rn += Jl[d * 3 + m] * Jl[d * 3 + m];
+  rn = sqrt(rn);
+  double n[3];
+  for (int m = 0; m < 3; ++m) n[m] = (s ? 1.0 : -1.0) * Jl[d * 3 + m] / rn;   // outward from this cell
+  const double* wq = CurvTabs{N}.W(a.ctab);
+  const double wdA = wq[p1] * wq[p2] * detl * rn;
+  double vL[3], vR[3] = {0.0, 0.0, 0.0};
+  for (int r = 0; r < 3; ++r) vL[r] = wdA * (Jl[r * 3] * n[0] + Jl[r * 3 + 1] * n[1] + Jl[r * 3 + 2] * n[2]);
+  double tau = a.taue[cell];
+  if (!dir) {
+    int cr[3] = {c[0], c[1], c[2]};
+    cr[d] = cn;
+    double Jr[9];
+    curv_face_jinv<N>(a, cr, d, 1 - s, p1, p2, Jr);
+    for (int r = 0; r < 3; ++r) vR[r] = wdA * (Jr[r * 3] * n[0] + Jr[r * 3 + 1] * n[1] + Jr[r * 3 + 2] * n[2]);
+    const int64_t ncell = cell + static_cast<int64_t>(cn - c[d]) *
+                                     (d == 0 ? 1 : (d == 1 ? a.g.nx : static_cast<int64_t>(a.g.nx) * a.g.ny));
+    const double tr = a.taue[ncell];
+    tau = tau > tr ? tau : tr;
+  }
+  double* out;
+  if (s == 1) {
+    out = fm + (cell * 3 + d) * 7 * N2;
+    if (p == 0) ftau[cell * 3 + d] = tau;
+  } else {
+    const int pi = plane_index(a.g, d, c[0], c[1], c[2]);
+    out = lm + (static_cast<int64_t>(a.g.lbase[d]) + pi) * 7 * N2;
+    if (p == 0) ltau[a.g.lbase[d] + pi] = tau;
+  }
+  out[p] = wdA;
+  for (int r = 0; r < 3; ++r) {
+    out[(1 + r) * N2 + p] = vL[r];
+    out[(4 + r) * N2 + p] = vR[r];
+  }
+}
+
 __global__ void __launch_bounds__(256) k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -699,6 +942,41 @@ dgmf_status launch_metric_fill(int n, const MetricGeom<double>& g, const double*
     const unsigned b2 = static_cast<unsigned>((ncells * 6 * q * q + 255) / 256);                          \
     hipLaunchKernelGGL((k_metric_fill_faces<q>), dim3(b2), dim3(256), 0, s, a, fm, ftau, lm, ltau);       \
     DGMF_LAUNCH_CHECK("k_metric_fill_faces");                                                             \
+    return DGMF_OK;                                                                                        \
+  }
+  DGMF_MET_CASES(X)
+#undef X
+  return fail(DGMF_UNSUPPORTED, "metric fill: degree %d not built", n - 1);
+}
+
+dgmf_status launch_metric_fill_curved(int n, const MetricGeom<double>& g, const double* const x0[3],
+                                      const double* const h[3], const double lo[3], const double len[3], double amp,
+                                      const double* ctab, double* taue, double* cm, double* fm, double* ftau,
+                                      double* lm, double* ltau, hipStream_t s) {
+  CurvArgs a{};
+  a.g = g;
+  for (int d = 0; d < 3; ++d) {
+    a.x0[d] = x0[d];
+    a.h[d] = h[d];
+    a.lo[d] = lo[d];
+    a.len[d] = len[d];
+  }
+  a.amp = amp;
+  a.k1sq = static_cast<double>(n) * n;
+  a.ctab = ctab;
+  a.taue = taue;
+  const int64_t ncells = static_cast<int64_t>(g.nx) * g.ny * g.nz;
+#define X(q)                                                                                               \
+  if (n == q) {                                                                                            \
+    const unsigned b0 = static_cast<unsigned>((ncells + 255) / 256);                                      \
+    hipLaunchKernelGGL((k_curved_tau<q>), dim3(b0), dim3(256), 0, s, a, taue);                            \
+    DGMF_LAUNCH_CHECK("k_curved_tau");                                                                    \
+    const unsigned b1 = static_cast<unsigned>((ncells * q * q * q + 255) / 256);                          \
+    hipLaunchKernelGGL((k_curved_fill_cells<q>), dim3(b1), dim3(256), 0, s, a, cm);                       \
+    DGMF_LAUNCH_CHECK("k_curved_fill_cells");                                                             \
+    const unsigned b2 = static_cast<unsigned>((ncells * 6 * q * q + 255) / 256);                          \
+    hipLaunchKernelGGL((k_curved_fill_faces<q>), dim3(b2), dim3(256), 0, s, a, fm, ftau, lm, ltau);       \
+    DGMF_LAUNCH_CHECK("k_curved_fill_faces");                                                             \
     return DGMF_OK;                                                                                        \
   }
   DGMF_MET_CASES(X)

@@ -50,6 +50,12 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
     assert b"neumann" in dg._lib.dgmf_last_error()
     d.neumann = (ctypes.c_int * 6)()
+    d.curve_amp = 0.05                                                    # curved cells need the stored metric
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    assert b"store_qp_metric" in dg._lib.dgmf_last_error()
+    d.curve_amp = 0.5                                                     # beyond the admitted amplitude
+    assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
+    d.curve_amp = 0.0
     d.shear = (ctypes.c_double * 9)(1, 0.3, 0, 0, 1, 0, 0, 0, 1)       # shear needs the stored metric
     assert dg._mesh_create(ctypes.byref(d), ctypes.byref(h)) == dg.INVALID
     assert b"store_qp_metric" in dg._lib.dgmf_last_error()

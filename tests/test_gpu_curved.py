@@ -1,0 +1,125 @@
+"""GPU parity of the SIPG operator on iso-parametric curved cells.
+
+The library fills the per-point metric of the curved cells on the device (a
+closed form of the interpolated deformation); the oracle interpolates the node
+positions with the full tensor Lagrange basis and integrates point by point
+(``oracle.curved``).  Small meshes compare every entry of the apply and the
+diagonal with the oracle's assembled matrix (periodic, Dirichlet and Neumann
+walls, tanh grading, degrees 1-6); CG with Jacobi is compared with the
+oracle's iteration count and true residual; at the full channel size the
+apply is checked on sampled cells and the mixed-precision Chebyshev solve on
+the oracle's residual over sampled cells.  Operators that assume a constant
+Jacobian per cell refuse curved meshes.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import dgmf_inputs as inp
+from oracle import curved, solvers
+from tests.gpu_util import dev, host, rel_err, require_gpu, sample_cells
+
+pytestmark = pytest.mark.gpu
+
+YW = (0, 0, 1, 1, 0, 0)
+CASES = {
+    # name: (k, cells, lengths, y0, periodic, gamma, neumann, amp, mu, nu)
+    "k2_periodic": (2, (3, 2, 2), (1, 1, 1), 0.0, (1, 1, 1), 0.0, (0,) * 6, 0.05, 0.0, 1.0),
+    "k3_channel_dirichlet": (3, (2, 3, 2), (2 * math.pi, 2, math.pi), -1.0, (1, 0, 1), 1.5, (0,) * 6, 0.03,
+                             1000.0, 0.01),
+    "k4_channel_neumann": (4, (2, 2, 2), (2 * math.pi, 2, math.pi), -1.0, (1, 0, 1), 1.2, YW, 0.04, 0.0, 1.0),
+    "k1_dirichlet_box": (1, (3, 2, 3), (1, 0.8, 1.2), 0.0, (0, 0, 0), 0.0, (0,) * 6, 0.08, 1.0, 1.0),
+    "k5_periodic": (5, (2, 2, 2), (1, 1, 1), 0.0, (1, 1, 1), 0.0, (0,) * 6, 0.06, 1.0, 0.5),
+    "k6_mixed": (6, (2, 2, 1), (1, 1, 1), 0.0, (1, 1, 0), 0.0, (0, 0, 0, 0, 1, 0), 0.05, 0.0, 1.0),
+}
+
+
+def _pair(name):
+    import paper_1607_01323_amd as dg
+    k, cells, L, y0, per, gam, neu, amp, mu, nu = CASES[name]
+    om = curved.CurvedBoxMesh(k, *cells, lx=L[0], ly=L[1], lz=L[2], y0=y0, periodic=tuple(bool(p) for p in per),
+                              y_tanh_gamma=gam, neumann=tuple(bool(f) for f in neu), amp=amp)
+    oop = curved.CurvedSIPG(om, mu, nu, 1.0)
+    gm = dg.Mesh(k, *cells, *L, y0=y0, periodic=per, y_tanh_gamma=gam, store_qp_metric=True, neumann=neu,
+                 curve_amp=amp)
+    gop = dg.SipgOperator(gm, mu, nu, 1.0)
+    return om, oop, gm, gop
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_and_diagonal_match_assembled_matrix(name):
+    require_gpu()
+    print(f"[case] curved apply {name}", flush=True)
+    om, oop, gm, gop = _pair(name)
+    A = oop.assemble()
+    u = inp.uniform(120, om.ndofs)
+    ref = A @ u
+    assert rel_err(host(gop.apply(dev(u))), ref) < 1e-12
+    assert rel_err(host(gop.apply(dev(u, torch.float32))), ref) < 1e-5
+    assert rel_err(host(gop.diagonal()), A.diagonal()) < 1e-12
+    assert rel_err(host(gop.diagonal(torch.float32)), A.diagonal()) < 1e-6
+    gm.close()
+
+
+def test_jacobi_cg_matches_oracle():
+    require_gpu()
+    print("[case] curved jacobi cg k3_channel_dirichlet", flush=True)
+    om, oop, gm, gop = _pair("k3_channel_dirichlet")
+    A = oop.assemble()
+    b = inp.uniform(12, om.ndofs)
+    dinv = 1.0 / A.diagonal()
+    _, itr, st, _ = solvers.pcg(lambda v: A @ v, b, np.zeros(om.ndofs), lambda r: dinv * r, 1e-10, 500)
+    assert st == solvers.OK
+    xg = dev(np.zeros(om.ndofs))
+    out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=500)
+    assert out.status == 0 and abs(out.iterations - itr) <= 1
+    assert np.linalg.norm(b - A @ host(xg)) <= 2e-10 * np.linalg.norm(b)
+    gm.close()
+
+
+def test_flat_operators_refuse_curved_meshes():
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    gm = dg.Mesh(2, 2, 2, 2, store_qp_metric=True, curve_amp=0.05)
+    N = gm.ndofs
+    u = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    for call in (lambda: gm.mass(u), lambda: gm.inverse_mass(u), lambda: gm.divergence(u),
+                 lambda: gm.gradient(u[:N]), lambda: gm.node_coords(), lambda: dg.ConvectiveOperator(gm)):
+        with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
+            call()
+    gop = dg.SipgOperator(gm, 1.0, 1.0, 1.0)
+    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
+        gop.precond_apply(u[:N])
+    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
+        gop.quadrature_points()
+    gm.close()
+
+
+def test_full_size_curved_channel():
+    """Curved channel (48x32x48, k = 4, amplitude 0.02): sampled cells of the apply,
+    then fp32-Chebyshev PCG to 1e-10, checked on the oracle's residual rows."""
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    w = inp.CHANNEL_CURVED_C4
+    print(f"[case] curved full-size {w.name}", flush=True)
+    om = curved.CurvedBoxMesh(w.degree, *w.cells, lx=w.lengths[0], ly=w.lengths[1], lz=w.lengths[2], y0=w.y0,
+                              periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma, amp=w.curve_amp)
+    gm = dg.Mesh.from_workload(w)
+    gop = dg.SipgOperator(gm, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    cells = sample_cells(w.cells, 12, 13)
+    oop = curved.CurvedSIPG(om, w.mass_coeff, w.diff_coeff, w.penalty_scale, cells=cells)
+    u = inp.uniform(14, om.ndofs)
+    y = host(gop.apply(dev(u))).reshape(om.ncells, -1)
+    ref = oop.apply_cells(u, cells)
+    assert rel_err(y[cells], ref) < 1e-12
+    b = inp.uniform(15, om.ndofs)
+    xg = torch.zeros(om.ndofs, dtype=torch.float64, device="cuda")
+    out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=500, precond="chebyshev", precond_dtype=torch.float32)
+    assert out.status == 0
+    print(f"[result] curved channel mixed CG iterations {out.iterations}, solve {out.solve_s:.3f} s", flush=True)
+    r = b.reshape(om.ncells, -1)[cells] - oop.apply_cells(host(xg), cells)
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+    gm.close()
+
