@@ -246,6 +246,43 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4, "c4"))
     ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4_SMALL, "c4small", cg=False))
     ex.update(pressure_measurements(dg, inp, torch, inp.CHANNEL_PRESSURE_C4, "c4p"))
+    ex.update(curved_measurements(dg, inp, torch, inp.CHANNEL_CURVED_C4, "c4c"))
+    return ex
+
+
+def curved_measurements(dg, inp, torch, w, tag):
+    """Channel Helmholtz on iso-parametric curved cells: metric set-up, apply (fp64,
+    fp32; the stored-metric kernel, same algorithmic bytes as on affine cells), and
+    PCG to 1e-10 on a random right-hand side (mixed fp32 Chebyshev, fp64 Jacobi)."""
+    ex = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = dg.Mesh.from_workload(w)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    op = dg.SipgOperator(m, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    N, n = m.ndofs, w.degree + 1
+    v = torch.as_tensor(inp.uniform(3, N), device="cuda")
+    yv = torch.empty_like(v)
+    ta = _events_time(lambda: op.apply(v, yv), 20, 3)
+    v32 = v.float()
+    yv32 = torch.empty_like(v32)
+    tb = _events_time(lambda: op.apply(v32, yv32), 20, 3)
+    b64 = metric_bytes_per_launch(n, m.ncells, 8)
+    ex[f"{tag}_mesh_setup_s"] = ts
+    ex[f"{tag}_apply_f64"] = {"us": ta * 1e6, "dofs_per_s": N / ta, "hbm_frac": b64 / ta / 1e9 / HBM_PEAK_GBS}
+    ex[f"{tag}_apply_f32"] = {"us": tb * 1e6, "dofs_per_s": N / tb}
+    b = torch.as_tensor(inp.uniform(15, N), device="cuda")
+    for name, kw in (("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
+                     ("jacobi_f64", dict(precond="jacobi"))):
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = op.cg(b, x, rtol=1e-10, max_iter=5000, check_every=8, seed=42, raise_on_failure=False, **kw)
+        torch.cuda.synchronize()
+        ex[f"{tag}_cg_{name}"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
+                                  "status": out.status, "setup_s": out.setup_s, "solve_s": out.solve_s}
+    m.close()
     return ex
 
 
