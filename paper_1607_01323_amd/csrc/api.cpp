@@ -503,6 +503,25 @@ dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out) {
     std::vector<float> mi32(mi.begin(), mi.end());
     if (st == DGMF_OK) st = m->minv64.upload(mi.data(), mi.size() * sizeof(double));
     if (st == DGMF_OK) st = m->minv32.upload(mi32.data(), mi32.size() * sizeof(float));
+    if (st == DGMF_OK && d.curve_amp != 0.0) {
+      // S, S^T, S^{-T}, S^{-1} for the point-weight mass of curved cells
+      std::vector<long double> si;
+      if (!invert(static_cast<int>(n), m->tab.S.data(), si))
+        st = fail(DGMF_INVALID, "mesh_create: singular interpolation matrix");
+      std::vector<double> pm(4 * n * n);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          pm[i * n + j] = m->tab.S[i * n + j];
+          pm[n * n + i * n + j] = m->tab.S[j * n + i];
+          if (st == DGMF_OK) {
+            pm[2 * n * n + i * n + j] = static_cast<double>(si[j * n + i]);
+            pm[3 * n * n + i * n + j] = static_cast<double>(si[i * n + j]);
+          }
+        }
+      std::vector<float> pm32(pm.begin(), pm.end());
+      if (st == DGMF_OK) st = m->pmt64.upload(pm.data(), pm.size() * sizeof(double));
+      if (st == DGMF_OK) st = m->pmt32.upload(pm32.data(), pm32.size() * sizeof(float));
+    }
     // V3c tables: Mh, Ch, Mh^{-1}, S, D, w, gw
     const Tables1D& t = m->tab;
     const V3Tab L{static_cast<int>(n)};
@@ -575,10 +594,22 @@ dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t strea
   return launch_node_coords(mesh->tab.n, mesh->g64, mesh->shear, xyz, mesh->ncells, stream);
 }
 
+// curved cells: the point-weight form with w_q det J_q from the stored cell metric
+static dgmf_status point_mass(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst, bool inv,
+                              hipStream_t stream) {
+  const int n = mesh->tab.n;
+  if (dtype == DGMF_F64)
+    return launch_point_mass<double>(n, static_cast<const double*>(mesh->pmt64.p), mesh->mg64.cm,
+                                     static_cast<const double*>(src), static_cast<double*>(dst), mesh->ncells,
+                                     n_fields, inv, stream);
+  return launch_point_mass<float>(n, static_cast<const float*>(mesh->pmt32.p), mesh->mg32.cm,
+                                  static_cast<const float*>(src), static_cast<float*>(dst), mesh->ncells, n_fields,
+                                  inv, stream);
+}
+
 dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
                                     hipStream_t stream) {
   if (!mesh || !src || !dst) return fail(DGMF_INVALID, "inverse_mass_apply: null argument");
-  if (dgmf_status e = flat_check(mesh, "inverse_mass_apply")) return e;
   const size_t es = dtype == DGMF_F64 ? 8 : (dtype == DGMF_F32 ? 4 : 0);
   if (!es) return fail(DGMF_INVALID, "inverse_mass_apply: unknown dtype %d", static_cast<int>(dtype));
   if (n_fields < 1 || n_fields > 64) return fail(DGMF_INVALID, "inverse_mass_apply: n_fields must be in 1..64");
@@ -588,6 +619,7 @@ dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fiel
   DeviceGuard dg(mesh->device);
   const double js = 1.0 / std::fabs(mesh->shear.det);
   const int n = mesh->tab.n;
+  if (mesh->desc.curve_amp != 0.0) return point_mass(mesh, dtype, n_fields, src, dst, true, stream);
   if (dtype == DGMF_F64)
     return launch_block_mass<double>(n, mesh->g64, js, static_cast<const double*>(mesh->minv64.p),
                                      static_cast<const double*>(src), static_cast<double*>(dst), mesh->ncells,
@@ -600,7 +632,6 @@ dgmf_status dgmf_inverse_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fiel
 dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, const void* src, void* dst,
                             hipStream_t stream) {
   if (!mesh || !src || !dst) return fail(DGMF_INVALID, "mass_apply: null argument");
-  if (dgmf_status e = flat_check(mesh, "mass_apply")) return e;
   const size_t es = dtype == DGMF_F64 ? 8 : (dtype == DGMF_F32 ? 4 : 0);
   if (!es) return fail(DGMF_INVALID, "mass_apply: unknown dtype %d", static_cast<int>(dtype));
   if (n_fields < 1 || n_fields > 64) return fail(DGMF_INVALID, "mass_apply: n_fields must be in 1..64");
@@ -610,6 +641,7 @@ dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, cons
   DeviceGuard dg(mesh->device);
   const double js = std::fabs(mesh->shear.det);
   const int n = mesh->tab.n;
+  if (mesh->desc.curve_amp != 0.0) return point_mass(mesh, dtype, n_fields, src, dst, false, stream);
   if (dtype == DGMF_F64)
     return launch_block_mass<double>(n, mesh->g64, js, static_cast<const double*>(mesh->v3tab.p),
                                      static_cast<const double*>(src), static_cast<double*>(dst), mesh->ncells,

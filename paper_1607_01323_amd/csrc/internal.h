@@ -225,6 +225,12 @@ dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, d
 dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
                             int64_t ncells, hipStream_t s);
 
+// dst = M^{-1} src or dst = M src on nfields consecutive scalar fields of a
+// curved mesh, with the per-point weights m_q = w_q det J_q of the stored cell
+// metric cm; tab = [S | S^T | S^{-T} | S^{-1}].  src and dst may be the same array.
+template <typename T>
+dgmf_status launch_point_mass(int n, const T* tab, const T* cm, const T* src, T* dst, int64_t ncells, int nfields,
+                              bool inverse, hipStream_t s);
 // dst = M^{-1} src (inverse: table the n x n inverse 1D mass, jscale =
 // 1/|det shear|) or dst = M src (table the 1D mass, jscale = |det shear|) on
 // nfields consecutive scalar fields of an affine mesh (k+1 Gauss points).
@@ -338,6 +344,7 @@ struct dgmf_mesh_ {
   dgmf::DevBuf minv64, minv32;     // inverse 1D mass (n x n) for dgmf_inverse_mass_apply
   dgmf::DevBuf mh32;               // 1D mass in fp32 (the fp64 one heads v3tab)
   dgmf::DevBuf v3tab;              // V3Tab tables (fp64)
+  dgmf::DevBuf pmt64, pmt32;       // curved cells: S, S^T, S^{-T}, S^{-1} for the point-weight mass
   int nops = 0;                    // live operators built on this mesh
 };
 

@@ -109,6 +109,130 @@ __global__ void __launch_bounds__(256) k_block_mass(const T* src, T* dst, const 
   for (int e = lane; e < nc * N3; e += 64) out[e] = sw[(e / N3) * CP + e % N3];
 }
 
+// Curved cells (the Jacobian varies inside the cell): with m_q = w_q det J_q at
+// the Gauss points (the stored metric's last cell entry),
+//   M = S^T (x)3 diag(m) S (x)3,   M^{-1} = S^{-1} (x)3 diag(1/m) S^{-T} (x)3,
+// i.e. the paper's tensorial inverse with the point weights between the two
+// transforms: three sweeps by P, the pointwise scale, three sweeps by Q.
+// tab: [S | S^T | S^{-T} | S^{-1}] (n x n each, row-major [out][in]); the
+// mass uses (P, Q) = (S, S^T), the inverse (S^{-T}, S^{-1}).  Same lane layout as
+// k_block_mass; m read per node from the stored metric of the cell.
+template <int N, typename T, bool INV>
+__global__ void __launch_bounds__(256) k_point_mass(const T* src, T* dst, const T* tab_g, const T* cm,
+                                                      const int64_t ncells, const int64_t total) {
+  using SH = IMShape<N>;
+  constexpr int N2 = SH::N2, N3 = SH::N3, CP = SH::CP, CPW = SH::CPW;
+  __shared__ T s[SH::WAVES * CPW * CP];
+  const cptr<T> tab = (cptr<T>)tab_g;
+  const cptr<T> P = tab + (INV ? 2 : 0) * N * N;
+  const cptr<T> Q = tab + (INV ? 3 : 1) * N * N;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t first = (static_cast<int64_t>(blockIdx.x) * SH::WAVES + wave) * CPW;
+  if (first >= total) return;
+  T* sw = s + wave * CPW * CP;
+  const int cs = lane / N2, t = lane % N2;
+  const int64_t fc = first + cs;
+  const bool act = cs < CPW && fc < total;
+  T* cell = sw + cs * CP;
+  T v[N];
+  // along z (from memory), y, x by P; scale by m (or 1/m); along x, y, z by Q
+  if (act) {
+    const T* in = src + fc * N3 + t;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = in[m * N2];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      T r = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) r = fma(P[l * N + m], v[m], r);
+      cell[l * N2 + t] = r;
+    }
+  }
+  wave_sync();
+  if (act) {
+    T* p = cell + (t / N) * N2 + t % N;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = p[m * N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T r = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) r = fma(P[j * N + m], v[m], r);
+      p[j * N] = r;
+    }
+  }
+  wave_sync();
+  if (act) {                                   // x lines: (j, l), offset t * N; scale, then Q along x
+    const T* mw = cm + (fc % ncells) * 7 * N3 + 6 * N3 + t * N;
+    T* p = cell + t * N;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = p[m];
+    T u[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T r = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) r = fma(P[i * N + m], v[m], r);
+      u[i] = INV ? r / mw[i] : r * mw[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T r = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) r = fma(Q[i * N + m], u[m], r);
+      p[i] = r;
+    }
+  }
+  wave_sync();
+  if (act) {
+    T* p = cell + (t / N) * N2 + t % N;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = p[m * N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T r = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) r = fma(Q[j * N + m], v[m], r);
+      p[j * N] = r;
+    }
+  }
+  wave_sync();
+  if (act) {                                   // z lines, in place
+    T* p = cell + t;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = p[m * N2];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      T r = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) r = fma(Q[l * N + m], v[m], r);
+      p[l * N2] = r;
+    }
+  }
+  wave_sync();
+  const int64_t rem = total - first;
+  const int nc = rem < CPW ? static_cast<int>(rem) : CPW;
+  T* out = dst + first * N3;
+  for (int e = lane; e < nc * N3; e += 64) out[e] = sw[(e / N3) * CP + e % N3];
+}
+
+template <int N, typename T>
+dgmf_status launch_pn(const T* tab, const T* cm, const T* src, T* dst, int64_t ncells, int64_t total, bool inv,
+                      hipStream_t s) {
+  using SH = IMShape<N>;
+  const int64_t waves = (total + SH::CPW - 1) / SH::CPW;
+  const int64_t blocks = (waves + SH::WAVES - 1) / SH::WAVES;
+  if (blocks > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mass: too many cells for one launch");
+  if (inv)
+    hipLaunchKernelGGL((k_point_mass<N, T, true>), dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s,
+                       src, dst, tab, cm, ncells, total);
+  else
+    hipLaunchKernelGGL((k_point_mass<N, T, false>), dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s,
+                       src, dst, tab, cm, ncells, total);
+  DGMF_LAUNCH_CHECK("k_point_mass");
+  return DGMF_OK;
+}
+
 template <int N, typename T>
 dgmf_status launch_n(const CartGeom<T>& g, T jscale, const T* minv, const T* src, T* dst, int64_t ncells,
                      int64_t total, bool inv, hipStream_t s) {
@@ -144,6 +268,28 @@ dgmf_status launch_block_mass(int n, const CartGeom<T>& g, T jscale, const T* ta
     default: return fail(DGMF_UNSUPPORTED, "mass: n = %d not built", n);
   }
 }
+
+template <typename T>
+dgmf_status launch_point_mass(int n, const T* tab, const T* cm, const T* src, T* dst, int64_t ncells, int nfields,
+                              bool inverse, hipStream_t s) {
+  const int64_t total = ncells * nfields;
+  if (total == 0) return DGMF_OK;
+  switch (n) {
+    case 2: return launch_pn<2, T>(tab, cm, src, dst, ncells, total, inverse, s);
+    case 3: return launch_pn<3, T>(tab, cm, src, dst, ncells, total, inverse, s);
+    case 4: return launch_pn<4, T>(tab, cm, src, dst, ncells, total, inverse, s);
+    case 5: return launch_pn<5, T>(tab, cm, src, dst, ncells, total, inverse, s);
+    case 6: return launch_pn<6, T>(tab, cm, src, dst, ncells, total, inverse, s);
+    case 7: return launch_pn<7, T>(tab, cm, src, dst, ncells, total, inverse, s);
+    case 8: return launch_pn<8, T>(tab, cm, src, dst, ncells, total, inverse, s);
+    default: return fail(DGMF_UNSUPPORTED, "mass: n = %d not built", n);
+  }
+}
+
+template dgmf_status launch_point_mass<double>(int, const double*, const double*, const double*, double*, int64_t,
+                                               int, bool, hipStream_t);
+template dgmf_status launch_point_mass<float>(int, const float*, const float*, const float*, float*, int64_t, int,
+                                              bool, hipStream_t);
 
 template dgmf_status launch_block_mass<double>(int, const CartGeom<double>&, double, const double*, const double*,
                                                double*, int64_t, int, bool, hipStream_t);
