@@ -154,6 +154,14 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     tv = _events_time(lambda: op_c1.viscous_apply(Uv, Yv), 20, 3)
     ex["c1_viscous_eps"] = {"us": tv * 1e6, "velocity_nodes_per_s": N / tv, "alg_GBps": 48.0 * N / tv / 1e9,
                             "vs_three_scalar_applies": tv / (3 * t_c1)}
+    # the implicit viscous step in that form: Jacobi PCG to 1e-10 from zero
+    Yv.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = op_c1.viscous_cg(Uv, Yv, rtol=1e-10, max_iter=1000, check_every=8, raise_on_failure=False)
+    torch.cuda.synchronize()
+    ex["c1_viscous_cg"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations, "status": out.status,
+                           "solve_s": out.solve_s, "rel_residual": out.rel_residual}
     del Uv, Yv
     # the same apply with a 512 MiB write between repetitions, so that its 33 MB
     # working set is not resident in the 256 MB Infinity Cache

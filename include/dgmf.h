@@ -208,6 +208,7 @@ dgmf_status dgmf_operator_apply(dgmf_op op, dgmf_dtype dtype, const void* src, v
  * every component plus nu times the component coupling.  Axis-aligned meshes
  * (sheared: DGMF_UNSUPPORTED).  u, out must not overlap.  Asynchronous. */
 dgmf_status dgmf_viscous_apply(dgmf_op op, const double* u, double* out, hipStream_t stream);
+
 /* diag = diag(H), N values of dtype.  Asynchronous. */
 dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hipStream_t stream);
 /* Cell quadrature points of the operator's rule: xyz device double [3][n_cells*n_q^3],
@@ -288,6 +289,21 @@ dgmf_status dgmf_cg_workspace_bytes(dgmf_op op, const dgmf_cg_params* params, si
 dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params,
                           void* workspace, size_t workspace_bytes, hipStream_t stream,
                           dgmf_cg_result* out);
+/* The implicit viscous step in the symmetric-gradient form (Sec. 3.2; the
+ * solver of Sec. 5.1): H_eps x = b with H_eps the operator of
+ * dgmf_viscous_apply, by fp64 CG preconditioned with the inverse diagonal of
+ * this operator's scalar part on every component.  params: rtol (stop on
+ * ||r|| <= rtol ||b||), max_iter, check_every; precond must be 0 (else
+ * DGMF_UNSUPPORTED); the other fields are ignored.  b, x: device fp64 [3][N]
+ * (x: initial guess in, solution out); workspace: device memory of at least
+ * dgmf_viscous_cg_workspace_bytes, 256-byte aligned; none may overlap.
+ * Meshes with shear, curved cells or Neumann sides: DGMF_UNSUPPORTED.
+ * Synchronous like dgmf_cg_solve: *out is filled and the returned status
+ * equals out->status (NOT_CONVERGED, BREAKDOWN, NONFINITE on failure). */
+dgmf_status dgmf_viscous_cg_workspace_bytes(dgmf_op op, size_t* bytes);
+dgmf_status dgmf_viscous_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params,
+                                  void* workspace, size_t workspace_bytes, hipStream_t stream,
+                                  dgmf_cg_result* out);
 
 /* z = B r, one application of the multigrid preconditioner (params->precond
  * must be 2; other fields as for dgmf_cg_solve), no mean projection.  r, z:

@@ -75,6 +75,9 @@ _inv_mass = _sig("dgmf_inverse_mass_apply", _vp, ctypes.c_int, ctypes.c_int, _vp
 _mass = _sig("dgmf_mass_apply", _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp)
 _div = _sig("dgmf_divergence_apply", _vp, _vp, _vp, _vp)
 _visc = _sig("dgmf_viscous_apply", _vp, _vp, _vp, _vp)
+_visc_ws = _sig("dgmf_viscous_cg_workspace_bytes", _vp, ctypes.POINTER(ctypes.c_size_t))
+_visc_cg = _sig("dgmf_viscous_cg_solve", _vp, _vp, _vp, ctypes.POINTER(CgParams), _vp, ctypes.c_size_t, _vp,
+                ctypes.POINTER(CgResult))
 _grad = _sig("dgmf_gradient_apply", _vp, _vp, _vp, _vp)
 _divdiv_tau = _sig("dgmf_divdiv_penalty", _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp)
 _proj = _sig("dgmf_projection_solve", _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp)
@@ -349,6 +352,23 @@ class SipgOperator(_Op):
         out = CgOutcome(res.iterations, res.rel_residual, res.lambda_max, res.status, res.setup_s, res.solve_s)
         if st not in (OK, NOT_CONVERGED, BREAKDOWN, NONFINITE) or (raise_on_failure and st != OK):
             raise DgmfError(st, "cg_solve")
+        return out
+
+    def viscous_cg(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, raise_on_failure=True):
+        """Jacobi PCG on H_eps x = b (the symmetric-gradient viscous operator); b, x: fp64 [3][N],
+        x holds the initial guess and receives the solution."""
+        n = 3 * self.mesh.ndofs
+        p = CgParams()
+        p.rtol, p.max_iter, p.check_every, p.precond = rtol, max_iter, check_every, 0
+        nbytes = ctypes.c_size_t()
+        _check(_visc_ws(self._h, ctypes.byref(nbytes)), "viscous_cg_workspace_bytes")
+        ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device="cuda")
+        res = CgResult()
+        st = _visc_cg(self._h, _ptr(b, torch.float64, n, "b"), _ptr(x, torch.float64, n, "x"), ctypes.byref(p),
+                      ctypes.c_void_p(ws.data_ptr()), nbytes.value, _stream(), ctypes.byref(res))
+        out = CgOutcome(res.iterations, res.rel_residual, 0.0, res.status, res.setup_s, res.solve_s)
+        if st not in (OK, NOT_CONVERGED, BREAKDOWN, NONFINITE) or (raise_on_failure and st != OK):
+            raise DgmfError(st, "viscous_cg_solve")
         return out
 
 
