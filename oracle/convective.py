@@ -10,7 +10,8 @@ R = F*(u-, u+) n with n the outward normal of K:
   R = 1/2 (u- (u-.n) + u+ (u+.n)) + lam (u- - u+),  lam = max(|u-.n|, |u+.n|)
 (Lambda/2 of the paper, evaluated at every face quadrature point).  On
 Dirichlet faces the exterior state is the mirror u+ = 2 g - u-, which gives
-the paper's Dirichlet flux.  C equals F^c(U) of eq. advect, so the explicit
+the paper's Dirichlet flux; on outflow (Neumann) faces it is u+ = u-, which
+gives the paper's flux F^c(u-).n there (no Lax-Friedrichs term).  C equals F^c(U) of eq. advect, so the explicit
 update is gamma_0 U^ = sum alpha U - dt M^{-1} C + F.
 
 Integrals use Gauss quadrature with n_q points per direction on cells and
@@ -24,12 +25,14 @@ side is active in the max when |u-.n| >= |u+.n|, and sgn(0) = 0.
   faces: the face contributes int [w].R, hence g- += phi- J-^T [w], g+ += phi+ J+^T [w],
          J- = 1/2((u-.n) I + u- (x) n) + lam I + (u- - u+) (x) dlam/du-,
          J+ = 1/2((u+.n) I + u+ (x) n) - lam I + (u- - u+) (x) dlam/du+;
-  Dirichlet faces: g- += phi- (J- - J+)^T w-.
+  Dirichlet faces: g- += phi- (J- - J+)^T w-;  outflow faces: g- += phi- (J- + J+)^T w-.
 
 Pins (tests/test_oracle_convective.py): free stream, conservation,
 homogeneity of degree 2, Lax-Friedrichs dissipation identity, quadrature
 invariance with lam = 0, channel profile; JVP against central differences,
-VJP against the transpose of the brute-force Jacobian, Euler identity.
+VJP against the transpose of the brute-force Jacobian, Euler identity; with
+outflow sides (tests/test_oracle_conv_outflow.py): a constant field gives
+C = 0 exactly, JVP against central differences, VJP against the Jacobian.
 """
 import numpy as np
 
@@ -39,8 +42,6 @@ from .sipg import _kron3
 
 class Convective:
     def __init__(self, mesh, nq=None, g=None):
-        if mesh.has_neumann():
-            raise NotImplementedError("convective operator: outflow boundaries are not modelled")
         self.mesh = mesh
         k = mesh.k
         self.n = k + 1
@@ -160,7 +161,8 @@ class Convective:
                     nrm, dA = self._face_geo(c, d)
                     nout = nrm if s == 1 else -nrm
                     um = (self.Tr[f] @ V[:, c, :].T).T
-                    up = 2.0 * self._gvals(c, f) - um
+                    # outflow (Neumann) face: the flux of the own trace, F^c(u-).n
+                    up = um if m.neumann[f] else 2.0 * self._gvals(c, f) - um
                     R = self.flux(um, up, nout, lam_on)
                     out[:, r] += (self.Tr[f].T @ (dA * R).T).T
                 elif s == 1:
@@ -202,8 +204,8 @@ class Convective:
                     nout = nrm if s == 1 else -nrm
                     um = (self.Tr[f] @ V[:, c, :].T).T
                     dum = (self.Tr[f] @ dV[:, c, :].T).T
-                    up = 2.0 * self._gvals(c, f) - um
-                    dR = self.flux_jvp(um, up, nout, dum, -dum)
+                    up = um if m.neumann[f] else 2.0 * self._gvals(c, f) - um
+                    dR = self.flux_jvp(um, up, nout, dum, dum if m.neumann[f] else -dum)
                     out[:, c] += (self.Tr[f].T @ (dA * dR).T).T
                     continue
                 L, R_ = (c, cn) if s == 1 else (cn, c)
@@ -238,10 +240,11 @@ class Convective:
                     nrm, dA = self._face_geo(c, d)
                     nout = nrm if s == 1 else -nrm
                     um = (self.Tr[f] @ V[:, c, :].T).T
-                    up = 2.0 * self._gvals(c, f) - um
+                    up = um if m.neumann[f] else 2.0 * self._gvals(c, f) - um
                     wm = (self.Tr[f] @ Wc[:, c, :].T).T
                     Jm, Jp = self.flux_jac_T(um, up, nout, wm)
-                    out[:, r] += (self.Tr[f].T @ (dA * (Jm - Jp)).T).T
+                    # u+ = u- (outflow) or u+ = 2g - u- (Dirichlet)
+                    out[:, r] += (self.Tr[f].T @ (dA * (Jm + Jp if m.neumann[f] else Jm - Jp)).T).T
                     continue
                 L, R_ = (c, cn) if s == 1 else (cn, c)
                 nrm, dA = self._face_geo(L, d)
