@@ -94,9 +94,11 @@ int dgmf_version(void);
  * flux takes the cell's own trace and the gradient flux is data, so the SIPG
  * operator has no face term there (the pressure Poisson operator on the walls
  * of a velocity-Dirichlet domain, the viscous operator on an outflow); their
- * area still counts in tau_e (eq. taue).  Meshes with Neumann sides serve the
- * SIPG operator, its diagonal, CG and multigrid, the mass matrices and the
- * cell-local projection; the convective, divergence, gradient and viscous
+ * area still counts in tau_e (eq. taue).  For the convective operator such a
+ * side is an outflow: the flux is F^c of the own trace (exterior state u+ = u-).
+ * Meshes with Neumann sides serve the SIPG operator, its diagonal, CG and
+ * multigrid, the mass matrices, the cell-local projection and the convective
+ * operator, its VJP and substep; the divergence, gradient and viscous
  * operators return DGMF_UNSUPPORTED on them.
  * curve_amp = a != 0 makes the cells iso-parametric and curved (Sec. 5): the
  * box point p (after the tanh grading) moves to
@@ -323,8 +325,9 @@ dgmf_status dgmf_precond_info(dgmf_op op, int* levels, double* lambdas, int* coa
 /* Convective operator C(U)_{i,a} = -sum_K (d_b phi_i, u_a u_b)_K
  *   + sum_K (phi_i, R_a)_{dK}, R = 1/2 (u-(u-.n) + u+(u+.n)) + lam (u- - u+),
  * lam = max(|u-.n|, |u+.n|) per face quadrature point (Sec. 3.2); Dirichlet
- * faces use the mirror state u+ = 2g - u- with g = 0.  n_q Gauss points per
- * direction on cells and faces; 0 -> floor(3(k+1)/2). */
+ * faces use the mirror state u+ = 2g - u- with g = 0, outflow (Neumann) sides
+ * the own state u+ = u- (flux F^c(u-).n).  n_q Gauss points per direction on
+ * cells and faces; 0 -> floor(3(k+1)/2). */
 typedef struct { int n_q; } dgmf_conv_desc;
 
 dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, dgmf_op* out);

@@ -943,8 +943,6 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
   if (desc->n_q < 0) return fail(DGMF_INVALID, "convective_create: n_q must be >= 0");
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "convective_create: sheared meshes are not supported");
   if (dgmf_status e = flat_check(mesh, "convective_create")) return e;
-  if (neumann_mask(mesh->desc))
-    return fail(DGMF_UNSUPPORTED, "convective_create: outflow (Neumann) boundaries are not supported");
   if (!conv_supported(n, nq))
     return fail(DGMF_UNSUPPORTED, "convective_create: degree %d with %d points per direction not built", k, nq);
   DeviceGuard dg(mesh->device);
@@ -970,6 +968,7 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
     return st;
   }
   ConvGeom& g = op->cgeo;
+  g.neu = neumann_mask(mesh->desc);
   g.nx = mesh->g64.nx;
   g.ny = mesh->g64.ny;
   g.nz = mesh->g64.nz;

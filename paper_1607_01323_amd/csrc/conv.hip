@@ -5,7 +5,8 @@
 // C(U)_{i,a} = - sum_K (d_b phi_i, u_a u_b)_K + sum_K (phi_i, R_a)_{dK}      (Sec. 3.2, eq. convstepspat)
 //   R = 1/2 (u- (u-.n) + u+ (u+.n)) + lam (u- - u+),  lam = max(|u-.n|, |u+.n|)
 // evaluated at every face quadrature point; Dirichlet faces use the mirror
-// state u+ = -u- (no-slip, g = 0).  Quadrature: Q Gauss points per direction
+// state u+ = -u- (no-slip, g = 0), outflow (Neumann) faces the own state
+// u+ = u-, i.e. the flux F^c(u-).n of the paper's Neumann part.  Quadrature: Q Gauss points per direction
 // on cells and faces (Sec. 5 over-integration).
 //
 // VJP (transpose of the exact derivative of C, piecewise quadratic in U):
@@ -15,7 +16,8 @@
 //     J-^T v = 1/2 (a v + n (u-.v)) + lam v + dlam- ((u- - u+).v)
 //     J+^T v = 1/2 (b v + n (u+.v)) - lam v + dlam+ ((u- - u+).v)
 //     a = u-.n, b = u+.n, dlam- = sgn(a) n if |a| >= |b| else 0, dlam+ = sgn(b) n otherwise
-//   Dirichlet face: g += phi (J- - J+)^T w- with u+ = -u-.
+//   Dirichlet face: g += phi (J- - J+)^T w- with u+ = -u-;
+//   outflow face: g += phi (J- + J+)^T w- = phi ((u.n) w + n (u.w)) with u+ = u-.
 //
 // Kernel layout: one cell per workgroup.  Thread (qx, qy) owns the z-column
 // of quadrature points of its (qx, qy) in registers (values, fluxes, VJP
@@ -360,7 +362,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
       copy_plane<N>(sU, d, s, P + (s * 2 + 0) * 3 * N2, 1.0, tid, nthr);
       const int64_t nb = conv_nb(g, cg, cell, d, s);
       if (nb >= 0) load_plane<N>(U, Nd, nb, d, 1 - s, P + (s * 2 + 1) * 3 * N2, tid, nthr);
-      else copy_plane<N>(sU, d, s, P + (s * 2 + 1) * 3 * N2, -1.0, tid, nthr);   // mirror u+ = -u-
+      else   // mirror u+ = -u- (no-slip) or the own state u+ = u- (outflow)
+        copy_plane<N>(sU, d, s, P + (s * 2 + 1) * 3 * N2, ((g.neu >> (2 * d + s)) & 1) ? 1.0 : -1.0, tid, nthr);
     }
     __syncthreads();
     // P occupies the front of sX; interpolate into F1/F2 (disjoint)
@@ -653,6 +656,14 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
           for (int a = 0; a < 3; ++a) res[a] = 0.5 * bn * jw[a] - lam * jw[a];
           res[d] += 0.5 * ujw + dl * dj;
         }
+      } else if ((g.neu >> f) & 1) {
+        // outflow: R = u (u.n), (dR/du)^T w = (u.n) w + n (u.w), outward normal sg e_d
+        const double sg = s ? 1.0 : -1.0;
+        const double an = sg * uo[d];
+        const double ujm = uo[0] * wo[0] + uo[1] * wo[1] + uo[2] * wo[2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) res[a] = an * wo[a];
+        res[d] += sg * ujm;
       } else {
         // Dirichlet: (J- - J+)^T w- with u+ = -u-, outward normal sg e_d
         const double sg = s ? 1.0 : -1.0;

@@ -35,6 +35,7 @@ struct MetricGeom {
 struct ConvGeom {
   int nx, ny, nz;
   int per[3];
+  int neu;             // bit 2d+s: the boundary side (d, s) is an outflow (Neumann) side
   const double* h[3];
   const double* hinv[3];
   const double* tab;   // S[nq*n], D[nq*n], w[nq], Mh^{-1}[n*n] (k+1-point 1D mass, inverted)

@@ -183,3 +183,39 @@ def test_autograd_function():
     ref = op.vjp(U.detach(), Wt)
     assert torch.equal(U.grad, ref)
     gm.close()
+
+
+OUTFLOW = {
+    # name: (k, cells, lengths, y0, periodic, gamma, nq, neumann)
+    "k2_outflow_x": (2, (3, 2, 2), (1, 1, 1), 0, (0, 1, 1), 0, 4, (1, 1, 0, 0, 0, 0)),
+    "k3_inflow_outflow": (3, (3, 2, 2), (2, 1, 1), 0, (0, 1, 0), 0, 5, (0, 1, 0, 0, 1, 0)),
+    "k4_channel_outflow": (4, (3, 3, 2), (2 * math.pi, 2, math.pi), -1, (0, 0, 1), 1.8, 7, (0, 1, 0, 0, 0, 0)),
+    "k5_q9_outflow": (5, (2, 2, 2), (1, 1, 1), 0, (0, 1, 1), 0, 9, (1, 1, 0, 0, 0, 0)),
+}
+
+
+@pytest.mark.parametrize("name", list(OUTFLOW))
+def test_outflow_sides_match_oracle(name):
+    """Outflow (Neumann) sides: the flux of the own trace; forward, VJP and the
+    explicit substep against the oracle on every entry."""
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    from oracle import mass as omass
+    k, cells, L, y0, per, gam, nq, neu = OUTFLOW[name]
+    print(f"[case] convective outflow {name}", flush=True)
+    om = omesh.BoxMesh(k, *cells, lx=L[0], ly=L[1], lz=L[2], y0=y0, periodic=tuple(bool(p) for p in per),
+                       y_tanh_gamma=gam, neumann=tuple(bool(f) for f in neu))
+    oop = oconv.Convective(om, nq=nq)
+    gm = dg.Mesh(k, *cells, *L, y0=y0, periodic=per, y_tanh_gamma=gam, neumann=neu)
+    gop = dg.ConvectiveOperator(gm, n_q=nq)
+    U = _field(om, inp.taylor_green, 11, 0.3)
+    W = inp.uniform(12, U.size)
+    assert rel_err(host(gop.apply(dev(U))), oop.forward(U)) < 1e-12
+    assert rel_err(host(gop.vjp(dev(U), dev(W))), oop.vjp(U, W)) < 1e-12
+    ref = omass.convective_step(oop, U, 1e-3)
+    assert rel_err(host(gop.step(dev(U), 1e-3)), ref) < 1e-12
+    if not any(per[d] == 0 and not (neu[2 * d] and neu[2 * d + 1]) for d in range(3)):
+        n = om.ndofs                        # only outflow and periodic sides: a constant field is steady
+        Uc = np.concatenate([np.full(n, 0.6), np.full(n, -0.3), np.full(n, 0.2)])
+        assert np.abs(host(gop.apply(dev(Uc)))).max() < 1e-13
+    gm.close()

@@ -9,7 +9,8 @@ long z direction split into several z segments.  CG (Jacobi, fp32 multigrid)
 on singular Neumann problems is compared with the oracle's iteration counts
 and true residual; at the full channel size the apply is checked on sampled
 cells and the multigrid solve on the oracle's residual over all cells.
-Operators that do not model Neumann faces refuse such meshes.
+Operators that do not model Neumann faces refuse such meshes (the convective
+operator treats them as outflow sides: tests/test_gpu_convective.py).
 """
 import math
 
@@ -123,13 +124,12 @@ def test_multigrid_pcg_matches_oracle(name, metric):
 
 
 def test_operators_without_neumann_faces_refuse_such_meshes():
+    """Divergence, gradient and the viscous operator have no Neumann face terms."""
     require_gpu()
     import paper_1607_01323_amd as dg
     gm = dg.Mesh(2, 2, 2, 2, periodic=(1, 0, 1), neumann=YWALLS)
     N = gm.ndofs
     u = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
-    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
-        dg.ConvectiveOperator(gm)
     with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
         gm.divergence(u)
     with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
