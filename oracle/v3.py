@@ -6,7 +6,7 @@ Sec. 4.2, variants V3a and V3c, and Sec. 4 (matrix formulation):
 * gradient operator B (eq. bv3, without the factor dt/gamma_0):
     (B p)_{i,a} = (d_a phi_i, p)_K - (phi_i, {{p}}^ND n_a)_dK;
   with the central average on interior faces and {{w}}^ND = w^- (the cell's
-  own trace) on boundary faces (Sec. 3.1);
+  own trace) on boundary faces, Dirichlet and Neumann alike (Sec. 3.1);
 * block-diagonal mass matrix M and div-div penalty D_e = (div v, div u)_K
   (eq. div-div), penalty tau_D = zeta_D |u_bar| h dt per cell with u_bar the
   cell average of the velocity and h = V^(1/3) (eq. tauD);
@@ -32,10 +32,9 @@ def _cell_grad(T, J):
 
 
 def _faces(m):
-    """Interior faces (cL, cR, d) and boundary faces (c, f)."""
-    if m.has_neumann():
-        raise NotImplementedError("V3c operators: Neumann boundaries are not modelled")
-    return m.interior_faces(), m.boundary_faces()
+    """Interior faces (cL, cR, d) and boundary faces (c, f), Dirichlet and Neumann alike:
+    the ND average is the own trace on both boundary parts (Sec. 3.1)."""
+    return m.interior_faces(), sorted(m.boundary_faces() + m.neumann_faces())
 
 
 def divergence_matrix(m):

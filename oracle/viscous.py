@@ -1,19 +1,20 @@
 """Viscous operator in the symmetric-gradient form (oracle; test infrastructure).
 
 Sec. 3.2, implicit viscous step, with s = 1 (SIPG) and F^nu(u) = 2 nu eps(u),
-eps(u) = (grad u + grad u^T)/2, homogeneous Dirichlet data on boundary faces
-(g_u = 0) and no Neumann faces:
+eps(u) = (grad u + grad u^T)/2, homogeneous Dirichlet data on Dirichlet faces
+(g_u = 0) and homogeneous Neumann data (h = 0, g_p = 0) on Neumann faces:
 
   a(v, u) = mu (v, u) + sum_K (eps(v), 2 nu eps(u))_K
           - sum_F ({{2 nu eps(v)}}, [u] (x) n)_F - sum_F ([v], {{2 nu eps(u)}} n)_F
           + sum_F tau nu ([v], [u])_F,
 
 on interior faces with n the unit normal of the minus side and [w] = w- - w+;
-on a boundary face the averages are the own values, [w] = w, and the penalty
-is 2 tau nu.  tau is the SIPG penalty of eqs. taue/tau.  Cell and face
-integrals by Gauss quadrature with k+1 points, dense blocks from Kronecker
-evaluation matrices, assembled into a sparse 3N x 3N matrix acting on
-[u_x; u_y; u_z].
+on a Dirichlet face the averages are the own values, [w] = w, and the penalty
+is 2 tau nu; a Neumann face adds nothing (U* = u_h there, so the first face
+term vanishes, and the flux F^nu* is data, which belongs to the right-hand
+side).  tau is the SIPG penalty of eqs. taue/tau.  Cell and face integrals by
+Gauss quadrature with k+1 points, dense blocks from Kronecker evaluation
+matrices, assembled into a sparse 3N x 3N matrix acting on [u_x; u_y; u_z].
 """
 import numpy as np
 import scipy.sparse as sp
@@ -80,8 +81,6 @@ def _face_terms(Tv, gradv, Tu, gradu, W, n, nu, pen):
 
 def viscous_matrix(m, mu, nu, penalty_scale=1.0):
     """Sparse 3N x 3N matrix of a(v, u)."""
-    if m.has_neumann():
-        raise NotImplementedError("viscous operator: Neumann boundaries are not modelled")
     T = sipg.Tables(m.k)
     nb, N = m.n ** 3, m.ndofs
     tau = sipg.penalty_per_cell(m, penalty_scale)
