@@ -96,10 +96,10 @@ int dgmf_version(void);
  * of a velocity-Dirichlet domain, the viscous operator on an outflow); their
  * area still counts in tau_e (eq. taue).  For the convective operator such a
  * side is an outflow: the flux is F^c of the own trace (exterior state u+ = u-).
- * Meshes with Neumann sides serve the SIPG operator, its diagonal, CG and
- * multigrid, the mass matrices, the cell-local projection and the convective
- * operator, its VJP and substep; the divergence, gradient and viscous
- * operators return DGMF_UNSUPPORTED on them.
+ * The divergence and gradient operators take the own trace on both boundary
+ * parts (the ND average of Sec. 3.1), and the viscous operator in the
+ * symmetric-gradient form has no term on a Neumann side either (U* = u_h
+ * there, the flux F^nu* is data); every operator accepts Neumann sides.
  * curve_amp = a != 0 makes the cells iso-parametric and curved (Sec. 5): the
  * box point p (after the tanh grading) moves to
  *   x = p + a (lx s(t_y) s(t_z), ly s(t_z) s(t_x), lz s(t_x) s(t_y)),
@@ -299,7 +299,7 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
  * DGMF_UNSUPPORTED); the other fields are ignored.  b, x: device fp64 [3][N]
  * (x: initial guess in, solution out); workspace: device memory of at least
  * dgmf_viscous_cg_workspace_bytes, 256-byte aligned; none may overlap.
- * Meshes with shear, curved cells or Neumann sides: DGMF_UNSUPPORTED.
+ * Meshes with shear or curved cells: DGMF_UNSUPPORTED.
  * Synchronous like dgmf_cg_solve: *out is filled and the returned status
  * equals out->status (NOT_CONVERGED, BREAKDOWN, NONFINITE on failure). */
 dgmf_status dgmf_viscous_cg_workspace_bytes(dgmf_op op, size_t* bytes);

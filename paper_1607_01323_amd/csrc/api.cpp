@@ -651,12 +651,12 @@ dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, cons
                                   false, stream);
 }
 
-static dgmf_status v3_check(dgmf_mesh mesh, const char* who, bool faces = true) {
+// Neumann sides need no check here: the ND average is the own trace on both
+// boundary parts (A, B), and the viscous coupling kernel skips Neumann faces.
+static dgmf_status v3_check(dgmf_mesh mesh, const char* who) {
   if (!mesh) return fail(DGMF_INVALID, "%s: null mesh", who);
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "%s: sheared meshes are not supported", who);
   if (dgmf_status e = flat_check(mesh, who)) return e;
-  if (faces && neumann_mask(mesh->desc))
-    return fail(DGMF_UNSUPPORTED, "%s: Neumann boundaries are not supported by this operator", who);
   return DGMF_OK;
 }
 
@@ -701,7 +701,7 @@ dgmf_status dgmf_gradient_apply(dgmf_mesh mesh, const double* p, double* out, hi
 
 dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, double dt, double* tau,
                                 hipStream_t stream) {
-  dgmf_status e = v3_check(mesh, "divdiv_penalty", false);
+  dgmf_status e = v3_check(mesh, "divdiv_penalty");
   if (e) return e;
   if (!u || !tau || !aligned(u, 8) || !aligned(tau, 8))
     return fail(DGMF_INVALID, "divdiv_penalty: null or misaligned vector");
@@ -716,7 +716,7 @@ dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, do
 
 dgmf_status dgmf_projection_solve(dgmf_mesh mesh, const double* tau, const double* rhs, double* x, double rtol,
                                   int max_iter, int* iterations, hipStream_t stream) {
-  dgmf_status e = v3_check(mesh, "projection_solve", false);
+  dgmf_status e = v3_check(mesh, "projection_solve");
   if (e) return e;
   if (!v3_projection_supported(mesh->tab.n))
     return fail(DGMF_UNSUPPORTED, "projection_solve: degree %d not built (k <= 6)", mesh->tab.n - 1);

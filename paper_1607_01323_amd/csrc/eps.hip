@@ -9,8 +9,9 @@
 //     - sum_F ( {{d_c u_d}} sigma, phi_i )_F                  (every c; F normal to d)
 //     - sum_F ( d_c' phi_i sigma, [u_c'] )_F / 2              (c = d only)
 // on a face of direction d with outward normal sigma e_d, [u] the own trace
-// minus the neighbour's; on boundary faces (g_u = 0) the average is the own
-// value and the second face term has weight 1 instead of 1/2.
+// minus the neighbour's; on Dirichlet faces (g_u = 0) the average is the own
+// value and the second face term has weight 1 instead of 1/2; homogeneous
+// Neumann faces add nothing.
 //
 // 64/n^2 cells per wavefront.  Cell term: per output component c and input
 // component c' the tensor product of Kh along c when c' = c, else Ch along c'
@@ -340,7 +341,9 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
         }
         // term 2 on the plane of every component; term 1 on component d (plane: the
         // tangential test derivatives; the whole normal line: the test normal derivative)
-        const double w1 = (interior ? 0.5 : 1.0) * sigma * area;
+        // a Neumann side adds nothing (U* = u_h there; the flux F^nu* is data)
+        const double sa = (interior || !((g.neu >> (2 * d + sd)) & 1)) ? sigma * area : 0.0;
+        const double w1 = (interior ? 0.5 : 1.0) * sa;
         const double Yd = d == 0 ? Y[0] : (d == 1 ? Y[1] : Y[2]);
         const double Yt1 = t1 == 0 ? Y[0] : Y[1];
         const double Yt2 = t2 == 1 ? Y[1] : Y[2];
@@ -348,11 +351,11 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
 #pragma unroll
         for (int id = 0; id < N; ++id) {
           double v = w1 * hi[d] * gend[id] * Y[5];
-          if (id == e) v += sigma * area * Yd + w1 * (hi[t1] * Y[3] + hi[t2] * Y[4]);
+          if (id == e) v += sa * Yd + w1 * (hi[t1] * Y[3] + hi[t2] * Y[4]);
           Od[plane_node<N>(d, id, p1, p2)] -= v;
         }
-        S0[t1 * N3 + plane_node<N>(d, e, p1, p2)] -= sigma * area * Yt1;
-        S0[t2 * N3 + plane_node<N>(d, e, p1, p2)] -= sigma * area * Yt2;
+        S0[t1 * N3 + plane_node<N>(d, e, p1, p2)] -= sa * Yt1;
+        S0[t2 * N3 + plane_node<N>(d, e, p1, p2)] -= sa * Yt2;
       }
       wave_sync();
     }

@@ -216,8 +216,6 @@ dgmf_status vcheck(dgmf_op op) {
   const dgmf_mesh m = op->mesh;
   if (m->shear.on) return fail(DGMF_UNSUPPORTED, "viscous_cg: sheared meshes are not supported");
   if (m->desc.curve_amp != 0.0) return fail(DGMF_UNSUPPORTED, "viscous_cg: curved cells are not supported");
-  for (int f = 0; f < 6; ++f)
-    if (m->desc.neumann[f]) return fail(DGMF_UNSUPPORTED, "viscous_cg: Neumann boundaries are not supported");
   return DGMF_OK;
 }
 

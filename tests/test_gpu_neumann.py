@@ -9,8 +9,8 @@ long z direction split into several z segments.  CG (Jacobi, fp32 multigrid)
 on singular Neumann problems is compared with the oracle's iteration counts
 and true residual; at the full channel size the apply is checked on sampled
 cells and the multigrid solve on the oracle's residual over all cells.
-Operators that do not model Neumann faces refuse such meshes (the convective
-operator treats them as outflow sides: tests/test_gpu_convective.py).
+The convective (outflow sides), V3c and viscous operators on Neumann meshes
+are checked in their own test files.
 """
 import math
 
@@ -120,26 +120,6 @@ def test_multigrid_pcg_matches_oracle(name, metric):
     if singular:
         r -= r.mean()
     assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(bp)
-    gm.close()
-
-
-def test_operators_without_neumann_faces_refuse_such_meshes():
-    """Divergence, gradient and the viscous operator have no Neumann face terms."""
-    require_gpu()
-    import paper_1607_01323_amd as dg
-    gm = dg.Mesh(2, 2, 2, 2, periodic=(1, 0, 1), neumann=YWALLS)
-    N = gm.ndofs
-    u = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
-    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
-        gm.divergence(u)
-    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
-        gm.gradient(u[:N])
-    gop = dg.SipgOperator(gm, 1.0, 1.0, 1.0)
-    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
-        gop.viscous_apply(u)
-    # cell-local operators do not see faces
-    tau = torch.ones(gm.ncells, dtype=torch.float64, device="cuda")
-    gm.projection_solve(tau, gm.mass(u + 1.0))
     gm.close()
 
 

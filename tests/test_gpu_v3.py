@@ -172,3 +172,22 @@ def test_full_size(name):
         assert abs(tau_h[c] - np.linalg.norm(ubar) * V ** (1 / 3) * 1e-2) <= 1e-13 * max(tau_h[c], 1e-300)
     print(f"  projection iterations: max {int(its.max())}, mean {float(its.float().mean()):.1f}", flush=True)
     gm.close()
+
+
+def test_divergence_gradient_projection_with_neumann_sides():
+    """The ND average is the own trace on Neumann sides as on Dirichlet ones (Sec. 3.1)."""
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    print("[case] v3 operators with Neumann sides", flush=True)
+    neu = (1, 0, 1, 1, 0, 0)
+    om = omesh.BoxMesh(3, 3, 2, 2, lx=1.0, ly=2.0, lz=1.0, y0=-1.0, periodic=(False, False, True),
+                       y_tanh_gamma=1.2, neumann=tuple(bool(f) for f in neu))
+    gm = dg.Mesh(3, 3, 2, 2, 1.0, 2.0, 1.0, y0=-1.0, periodic=(0, 0, 1), y_tanh_gamma=1.2, neumann=neu)
+    U = inp.uniform(75, 3 * om.ndofs)
+    P = inp.uniform(76, om.ndofs)
+    assert rel_err(host(gm.divergence(dev(U))), ov3.divergence_matrix(om) @ U) < 1e-12
+    assert rel_err(host(gm.gradient(dev(P))), ov3.gradient_matrix(om) @ P) < 1e-12
+    tau = np.abs(inp.uniform(77, om.ncells)) * 10.0
+    x = host(gm.projection_solve(dev(tau), dev(U), rtol=1e-13, max_iter=3 * om.n ** 3))
+    assert rel_err(x, ov3.projection_solve(om, tau, U)) < 1e-9
+    gm.close()

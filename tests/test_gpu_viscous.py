@@ -139,3 +139,49 @@ def test_viscous_cg_full_size():
           flush=True)
     assert rel <= 2e-10
     gm.close()
+
+
+NEU = {
+    # name: (k, cells, lengths, y0, periodic, gamma, neumann, mu, nu)
+    "k2_all_neumann": (2, (2, 2, 3), (1, 0.8, 1.3), 0.0, (0, 0, 0), 0.0, (1, 1, 1, 1, 1, 1), 0.0, 1.0),
+    "k3_channel_outflow": (3, (3, 2, 2), (2, 2, 1), -1.0, (0, 0, 1), 1.5, (0, 1, 0, 0, 0, 0), 50.0, 0.02),
+    "k4_mixed": (4, (2, 2, 2), (1, 1, 1), 0.0, (0, 1, 0), 0.0, (1, 0, 0, 0, 0, 1), 1.0, 1.0),
+}
+
+
+def _neu_pair(name):
+    import paper_1607_01323_amd as dg
+    k, cells, L, y0, per, gam, neu, mu, nu = NEU[name]
+    om = omesh.BoxMesh(k, *cells, lx=L[0], ly=L[1], lz=L[2], y0=y0, periodic=tuple(bool(p) for p in per),
+                       y_tanh_gamma=gam, neumann=tuple(bool(f) for f in neu))
+    gm = dg.Mesh(k, *cells, *L, y0=y0, periodic=per, y_tanh_gamma=gam, neumann=neu)
+    return om, gm, dg.SipgOperator(gm, mu, nu, 1.0), mu, nu
+
+
+@pytest.mark.parametrize("name", list(NEU))
+def test_neumann_sides_match_oracle(name):
+    """No term on homogeneous Neumann faces (Sec. 3.2: U* = u_h, F^nu* is data)."""
+    require_gpu()
+    print(f"[case] viscous neumann {name}", flush=True)
+    om, gm, gop, mu, nu = _neu_pair(name)
+    A = ovisc.viscous_matrix(om, mu, nu, 1.0)
+    U = inp.uniform(94, 3 * om.ndofs)
+    assert rel_err(host(gop.viscous_apply(dev(U))), A @ U) < 1e-12
+    if name == "k2_all_neumann":
+        # rigid motions lie in the null space of the all-Neumann operator without mass
+        X = om.node_coords()
+        scale = np.abs(A @ U).max()
+        for w in np.eye(3):
+            R = np.cross(np.broadcast_to(w, X.shape), X).T.ravel()
+            assert np.abs(host(gop.viscous_apply(dev(R)))).max() <= 1e-11 * scale
+    else:
+        from oracle import sipg as osipg, solvers
+        dinv = np.tile(1.0 / osipg.SIPG(om, mu, nu, 1.0).assemble().diagonal(), 3)
+        b = inp.uniform(95, 3 * om.ndofs)
+        _, itr, st, _ = solvers.pcg(lambda v: A @ v, b, np.zeros_like(b), lambda r: dinv * r, 1e-10, 3000)
+        assert st == solvers.OK
+        xg = dev(np.zeros_like(b))
+        out = gop.viscous_cg(dev(b), xg, rtol=1e-10, max_iter=3000, check_every=4)
+        assert out.status == 0 and abs(out.iterations - itr) <= 1
+        assert np.linalg.norm(b - A @ host(xg)) <= 2e-10 * np.linalg.norm(b)
+    gm.close()
