@@ -11,7 +11,9 @@ tensorial embedding of a mother cell's polynomials into its children.
 Readings fixed here (and used identically by the GPU path):
 * hierarchy: halve every direction whose cell count is even, until no count
   is even (down to one cell on 2^m meshes); the operator is discretised anew
-  on every level with the same coefficients and penalty rule;
+  on every level with the same coefficients and penalty rule; on a curved
+  mesh the finest level keeps the curved operator and the coarse levels are
+  the undeformed box (sides and grading kept);
 * transfer: prolongation P evaluates the mother's nodal polynomial at the
   child's nodes, the child covering half of the mother's reference cell in
   every halved direction (reference-cell embedding); restriction is P^T;
@@ -33,7 +35,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-from . import basis, mesh as omesh, rng, sipg, solvers
+from . import basis, curved, mesh as omesh, rng, sipg, solvers
 
 
 def level_counts(nc):
@@ -141,7 +143,10 @@ class Multigrid:
         self.degree, self.range = int(degree), float(smoothing_range)
         counts = level_counts(mesh.nc)
         self.meshes = [mesh] + [coarser_mesh(mesh, c) for c in counts[1:]]
-        self.ops = [sipg.SIPG(m, mass_coeff, diff_coeff, penalty_scale) for m in self.meshes]
+        # a curved finest level keeps its curved operator; the coarse levels
+        # rediscretise on the undeformed box (coarser_mesh builds affine boxes)
+        self.ops = [(curved.CurvedSIPG if isinstance(m, curved.CurvedBoxMesh) else sipg.SIPG)(
+            m, mass_coeff, diff_coeff, penalty_scale) for m in self.meshes]
         self.A = [op.assemble() for op in self.ops]
         self.dinv = [1.0 / A.diagonal() for A in self.A]
         self.P = [prolongation(self.meshes[l], self.meshes[l + 1]) for l in range(len(self.meshes) - 1)]
