@@ -281,7 +281,8 @@ def curved_measurements(dg, inp, torch, w, tag):
     ex[f"{tag}_apply_f64"] = {"us": ta * 1e6, "dofs_per_s": N / ta, "hbm_frac": b64 / ta / 1e9 / HBM_PEAK_GBS}
     ex[f"{tag}_apply_f32"] = {"us": tb * 1e6, "dofs_per_s": N / tb}
     b = torch.as_tensor(inp.uniform(15, N), device="cuda")
-    for name, kw in (("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
+    for name, kw in (("mixed_f32mg", dict(precond="multigrid", precond_dtype=torch.float32)),
+                     ("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
                      ("jacobi_f64", dict(precond="jacobi"))):
         x = torch.zeros(N, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()

@@ -107,10 +107,11 @@ int dgmf_version(void);
  * the degree-k interpolant of x at its GLL nodes.  The map is periodic in every
  * direction; walls of non-periodic directions become curved.  |a| <= 0.1;
  * needs store_qp_metric = 1 and no shear.  Curved meshes serve the SIPG
- * operator, its diagonal, CG with the Jacobi or Chebyshev preconditioner,
- * and the mass matrix and its inverse (with the point weights w_q det J_q);
- * every other operator (and multigrid, coordinates, load vectors) returns
- * DGMF_UNSUPPORTED on them.
+ * operator, its diagonal, CG with every preconditioner (multigrid keeps the
+ * curved operator on the finest level and rediscretises the coarse levels on
+ * the undeformed box), and the mass matrix and its inverse (with the point
+ * weights w_q det J_q); every other operator (and coordinates, load vectors)
+ * returns DGMF_UNSUPPORTED on them.
  * degree k in 1..7; every cell count >= 1; lengths > 0. */
 typedef struct {
   int degree;

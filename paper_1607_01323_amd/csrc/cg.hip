@@ -714,7 +714,6 @@ dgmf_status coarse_interval(MgLevel& c, const std::vector<double>& diag, bool si
 template <typename T>
 dgmf_status mg_build(dgmf_op op, const dgmf_cg_params& prm, hipStream_t s, MgHierarchy*& out) {
   if (op->mesh->shear.on) return fail(DGMF_UNSUPPORTED, "multigrid: sheared meshes are not supported");
-  if (op->mesh->desc.curve_amp != 0.0) return fail(DGMF_UNSUPPORTED, "multigrid: curved cells are not supported");
   auto* h = new (std::nothrow) MgHierarchy;
   if (!h) return fail(DGMF_OOM, "multigrid: host allocation failed");
   std::unique_ptr<MgHierarchy> guard(h);
@@ -742,6 +741,7 @@ dgmf_status mg_build(dgmf_op op, const dgmf_cg_params& prm, hipStream_t s, MgHie
     d.ny = nxt[1];
     d.nz = nxt[2];
     d.store_qp_metric = 0;
+    d.curve_amp = 0.0;    // a curved finest level: the coarse levels are the undeformed box
     for (double& v : d.shear) v = 0.0;
     MgLevel l;
     l.owned = true;

@@ -106,6 +106,45 @@ def test_jacobi_cg_matches_oracle():
     gm.close()
 
 
+MG = {
+    # name: (k, cells, lengths, y0, periodic, gamma, neumann, amp, mu, nu)
+    "k2_periodic_mg": (2, (4, 4, 2), (1, 1, 1), 0.0, (1, 1, 1), 0.0, (0,) * 6, 0.05, 1.0, 1.0),
+    "k3_channel_mg": (3, (2, 4, 2), (2 * math.pi, 2, math.pi), -1.0, (1, 0, 1), 1.5, (0,) * 6, 0.03, 100.0, 0.01),
+}
+
+
+@pytest.mark.parametrize("pdtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", list(MG))
+def test_multigrid_with_curved_finest_level(name, pdtype):
+    """The finest level keeps the curved operator, the coarse levels are the
+    undeformed box: one V-cycle and MG-PCG against the oracle's hierarchy."""
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    from oracle import multigrid as omg
+    print(f"[case] curved multigrid {name} {pdtype}", flush=True)
+    k, cells, L, y0, per, gam, neu, amp, mu, nu = MG[name]
+    om = curved.CurvedBoxMesh(k, *cells, lx=L[0], ly=L[1], lz=L[2], y0=y0, periodic=tuple(bool(p) for p in per),
+                              y_tanh_gamma=gam, neumann=tuple(bool(f) for f in neu), amp=amp)
+    gm = dg.Mesh(k, *cells, *L, y0=y0, periodic=per, y_tanh_gamma=gam, store_qp_metric=True, neumann=neu,
+                 curve_amp=amp)
+    gop = dg.SipgOperator(gm, mu, nu, 1.0)
+    mg = omg.Multigrid(om, mu, nu, 1.0, seed=42)
+    r = inp.uniform(17, om.ndofs)
+    z = host(gop.precond_apply(dev(r), precond_dtype=pdtype, seed=42))
+    assert rel_err(z, mg.vcycle(r)) < (1e-9 if pdtype == torch.float64 else 1e-4)
+    A = mg.A[0]
+    b = inp.uniform(18, om.ndofs)
+    flex = pdtype == torch.float32
+    _, itr, st, _ = solvers.pcg(lambda v: A @ v, b, np.zeros(om.ndofs), mg.vcycle, 1e-10, 200, flexible=flex)
+    assert st == solvers.OK
+    xg = dev(np.zeros(om.ndofs))
+    out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=200, check_every=2, precond="multigrid", precond_dtype=pdtype,
+                 seed=42)
+    assert out.status == 0 and abs(out.iterations - itr) <= (1 if pdtype == torch.float64 else 2)
+    assert np.linalg.norm(b - A @ host(xg)) <= 2e-10 * np.linalg.norm(b)
+    gm.close()
+
+
 def test_flat_operators_refuse_curved_meshes():
     require_gpu()
     import paper_1607_01323_amd as dg
@@ -117,8 +156,6 @@ def test_flat_operators_refuse_curved_meshes():
         with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
             call()
     gop = dg.SipgOperator(gm, 1.0, 1.0, 1.0)
-    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
-        gop.precond_apply(u[:N])
     with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
         gop.quadrature_points()
     gm.close()
