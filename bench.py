@@ -162,6 +162,13 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     torch.cuda.synchronize()
     ex["c1_viscous_cg"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations, "status": out.status,
                            "solve_s": out.solve_s, "rel_residual": out.rel_residual}
+    Yv.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = op_c1.viscous_cg(Uv, Yv, rtol=1e-10, max_iter=1000, check_every=8, precond="mass", raise_on_failure=False)
+    torch.cuda.synchronize()
+    ex["c1_viscous_cg_mass"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
+                                "status": out.status, "solve_s": out.solve_s}
     del Uv, Yv
     # the same apply with a 512 MiB write between repetitions, so that its 33 MB
     # working set is not resident in the 256 MB Infinity Cache
@@ -190,6 +197,12 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     torch.cuda.synchronize()
     ex["c1_cg_jacobi_f64"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
                               "setup_s": out.setup_s, "solve_s": out.solve_s, "rel_residual": out.rel_residual}
+    x = torch.as_tensor(inp.uniform(11, N), device="cuda")
+    t0 = time.perf_counter()
+    out = op_c1.cg(b, x, rtol=1e-10, max_iter=5000, check_every=16, precond="mass")
+    torch.cuda.synchronize()
+    ex["c1_cg_mass_f64"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
+                            "setup_s": out.setup_s, "solve_s": out.solve_s, "rel_residual": out.rel_residual}
     # C2: fp64 and fp32 apply, mixed vs fp64 CG to 1e-10
     w2 = inp.POISSON_C2
     m2 = dg.Mesh.from_workload(w2)
@@ -424,7 +437,8 @@ def channel_measurements(dg, inp, torch, w, tag, cg=True):
         for name, kw in (("mixed_f32mg", dict(precond="multigrid", precond_dtype=torch.float32)),
                          ("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
                          ("f64cheb", dict(precond="chebyshev", precond_dtype=torch.float64)),
-                         ("jacobi_f64", dict(precond="jacobi"))):
+                         ("jacobi_f64", dict(precond="jacobi")),
+                         ("mass_f64", dict(precond="mass"))):
             best = None
             for _ in range(2):
                 x = torch.zeros(N, dtype=torch.float64, device="cuda")

@@ -258,7 +258,8 @@ typedef struct {
   double rtol;
   int max_iter;
   int check_every;
-  int precond;           /* 0 Jacobi, 1 Chebyshev, 2 geometric multigrid V-cycle */
+  int precond;           /* 0 Jacobi, 1 Chebyshev, 2 geometric multigrid V-cycle, 3 inverse mass
+                            matrix (fp64; the viscous-step preconditioner of Sec. 5.1) */
   int precond_dtype;     /* dgmf_dtype of the Chebyshev preconditioner */
   int cheb_degree;       /* >= 1 */
   double smoothing_range;/* > 1 */
@@ -295,9 +296,11 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
 /* The implicit viscous step in the symmetric-gradient form (Sec. 3.2; the
  * solver of Sec. 5.1): H_eps x = b with H_eps the operator of
  * dgmf_viscous_apply, by fp64 CG preconditioned with the inverse diagonal of
- * this operator's scalar part on every component.  params: rtol (stop on
- * ||r|| <= rtol ||b||), max_iter, check_every; precond must be 0 (else
- * DGMF_UNSUPPORTED); the other fields are ignored.  b, x: device fp64 [3][N]
+ * this operator's scalar part on every component (precond 0) or with the
+ * inverse mass matrix on every component (precond 3, the paper's viscous
+ * preconditioner).  params: rtol (stop on ||r|| <= rtol ||b||), max_iter,
+ * check_every, precond (0 or 3, else DGMF_UNSUPPORTED); the other fields
+ * are ignored.  b, x: device fp64 [3][N]
  * (x: initial guess in, solution out); workspace: device memory of at least
  * dgmf_viscous_cg_workspace_bytes, 256-byte aligned; none may overlap.
  * Meshes with shear or curved cells: DGMF_UNSUPPORTED.

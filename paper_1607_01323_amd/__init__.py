@@ -300,14 +300,14 @@ class SipgOperator(_Op):
                       _stream()), "integrate")
         return b
 
-    _PRECONDS = {"jacobi": 0, "chebyshev": 1, "multigrid": 2}
+    _PRECONDS = {"jacobi": 0, "chebyshev": 1, "multigrid": 2, "mass": 3}
 
     def _params(self, rtol, max_iter, check_every, precond, precond_dtype, cheb_degree, smoothing_range,
                 lanczos_steps, lambda_safety, seed, project_mean, flexible, mg_coarse_tol, mg_graph=True):
         if precond not in self._PRECONDS:
             raise ValueError(f"precond must be one of {sorted(self._PRECONDS)}")
         if flexible is None:
-            flexible = precond != "jacobi" and precond_dtype == torch.float32
+            flexible = precond in ("chebyshev", "multigrid") and precond_dtype == torch.float32
         return CgParams(rtol, max_iter, check_every, self._PRECONDS[precond],
                         F64 if precond_dtype == torch.float64 else F32, cheb_degree, smoothing_range, lanczos_steps,
                         lambda_safety, seed, int(bool(project_mean)), int(bool(flexible)), mg_coarse_tol,
@@ -338,7 +338,8 @@ class SipgOperator(_Op):
            flexible=None, raise_on_failure=True, mg_coarse_tol=0.0, mg_graph=True):
         """PCG on H x = b; x (fp64, device) holds the initial guess and receives the solution.
 
-        precond: "jacobi", "chebyshev" or "multigrid".  flexible=None picks the
+        precond: "jacobi", "chebyshev", "multigrid" or "mass" (inverse mass matrix, the
+        viscous-step preconditioner).  flexible=None picks the
         Polak-Ribiere (flexible) beta exactly when the preconditioner runs in fp32.
         """
         p = self._params(rtol, max_iter, check_every, precond, precond_dtype, cheb_degree, smoothing_range,
@@ -354,12 +355,15 @@ class SipgOperator(_Op):
             raise DgmfError(st, "cg_solve")
         return out
 
-    def viscous_cg(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, raise_on_failure=True):
-        """Jacobi PCG on H_eps x = b (the symmetric-gradient viscous operator); b, x: fp64 [3][N],
-        x holds the initial guess and receives the solution."""
+    def viscous_cg(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, precond="jacobi", raise_on_failure=True):
+        """PCG on H_eps x = b (the symmetric-gradient viscous operator); b, x: fp64 [3][N],
+        x holds the initial guess and receives the solution.  precond: "jacobi" (the scalar
+        operator's diagonal) or "mass" (the inverse mass matrix)."""
+        if precond not in ("jacobi", "mass"):
+            raise ValueError("precond must be 'jacobi' or 'mass'")
         n = 3 * self.mesh.ndofs
         p = CgParams()
-        p.rtol, p.max_iter, p.check_every, p.precond = rtol, max_iter, check_every, 0
+        p.rtol, p.max_iter, p.check_every, p.precond = rtol, max_iter, check_every, 0 if precond == "jacobi" else 3
         nbytes = ctypes.c_size_t()
         _check(_visc_ws(self._h, ctypes.byref(nbytes)), "viscous_cg_workspace_bytes")
         ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device="cuda")

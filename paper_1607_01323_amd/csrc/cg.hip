@@ -256,6 +256,17 @@ __device__ __forceinline__ void final_terms(double (&v)[3], double ri, double zi
   if (q) v[2] += zi * (q[i] - mq);
 }
 
+// z already holds M^{-1} r: the partials of the preconditioned update
+__global__ void __launch_bounds__(256) k_mass_out(const double* __restrict__ r, const double* __restrict__ z,
+                                                  const double* __restrict__ q, int64_t N, const CgState* st,
+                                                  double* partials) {
+  if (st->status != RUNNING) return;
+  const double mq = st->mean_q;
+  double v[3] = {0, 0, 0};
+  GRID_STRIDE(i, N) final_terms(v, r[i], z[i], q, i, mq);
+  block_partials<3>(v, partials, blockIdx.x);
+}
+
 // res = T(r); d = dinv res / theta; zc = d   (degree 1: z64 = d directly)
 template <typename T>
 __global__ void __launch_bounds__(256) k_cheb_init(const double* __restrict__ r, T* __restrict__ res,
@@ -426,8 +437,8 @@ dgmf_status validate(dgmf_op op, const dgmf_cg_params* p) {
   if (!p) return fail(DGMF_INVALID, "cg: null params");
   if (!(p->rtol >= 0) || !std::isfinite(p->rtol)) return fail(DGMF_INVALID, "cg: rtol must be finite and >= 0");
   if (p->max_iter < 0) return fail(DGMF_INVALID, "cg: max_iter must be >= 0");
-  if (p->precond < 0 || p->precond > 2) return fail(DGMF_INVALID, "cg: precond must be 0, 1 or 2");
-  if (p->precond >= 1) {
+  if (p->precond < 0 || p->precond > 3) return fail(DGMF_INVALID, "cg: precond must be 0, 1, 2 or 3");
+  if (p->precond == 1 || p->precond == 2) {
     if (p->precond_dtype != DGMF_F32 && p->precond_dtype != DGMF_F64)
       return fail(DGMF_INVALID, "cg: precond_dtype must be DGMF_F32 or DGMF_F64");
     if (p->cheb_degree < 1 || p->cheb_degree > 64) return fail(DGMF_INVALID, "cg: cheb_degree must be in 1..64");
@@ -1028,7 +1039,24 @@ struct Solver {
     return DGMF_OK;
   }
 
+  // z = M^{-1} r (fp64; the preconditioner of the viscous step, Sec. 5.1), then the partials
+  dgmf_status mass_apply(const double* r, double* z, const double* q) {
+    const dgmf_mesh m = op->mesh;
+    dgmf_status e;
+    if (m->desc.curve_amp != 0.0)
+      e = launch_point_mass<double>(n, static_cast<const double*>(m->pmt64.p), m->mg64.cm, r, z, m->ncells, 1, true,
+                                    s);
+    else
+      e = launch_block_mass<double>(n, m->g64, 1.0 / std::fabs(m->shear.det), static_cast<const double*>(m->minv64.p),
+                                    r, z, m->ncells, 1, true, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_mass_out, dim3(kVecBlocks), dim3(256), 0, s, r, z, q, N, st, partials);
+    DGMF_LAUNCH_CHECK("k_mass_out");
+    return DGMF_OK;
+  }
+
   dgmf_status precond(const double* r, double* z, const double* q) {
+    if (prm.precond == 3) return mass_apply(r, z, q);
     if (prm.precond == 2) {
       if (prm.precond_dtype == DGMF_F32) return mg_apply<float>(r, z, q);
       return mg_apply<double>(r, z, q);

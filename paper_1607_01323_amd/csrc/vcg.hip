@@ -3,7 +3,9 @@
 // Sec. 5.1: the viscous step is solved by CG).  The operator is
 // H_eps = mu M + (scalar SIPG operator on every component) + nu C(u) (the
 // component coupling of eps.hip); the preconditioner is the inverse diagonal
-// of the scalar part, the same on the three components.  Plain PCG in fp64
+// of the scalar part, the same on the three components, or the inverse mass
+// matrix on every component (the paper's viscous preconditioner, Sec. 5.1).
+// Plain PCG in fp64
 // with every scalar on the device: vector kernels write per-block partial
 // sums, one single-block kernel adds them in a fixed order and advances
 // alpha / beta, and a device status word idles the remaining kernels of a
@@ -151,6 +153,19 @@ __global__ void __launch_bounds__(kThreads) k_v_update(double* __restrict__ x, d
   }
 }
 
+// partials <r, z> into part[slot * kBlocks + block] (z from the inverse mass)
+__global__ void __launch_bounds__(kThreads) k_v_rz(const double* __restrict__ r, const double* __restrict__ z,
+                                                   int64_t n3, double* part, int slot, const VState* st, int always) {
+  if (!always && st->status != V_RUNNING) return;
+  __shared__ double sh[kThreads];
+  double s = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n3;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    s = fma(r[i], z[i], s);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[slot * kBlocks + blockIdx.x] = s;
+}
+
 // p = z + beta p (first: p = z)
 __global__ void __launch_bounds__(kThreads) k_v_pupdate(double* __restrict__ p, const double* __restrict__ z,
                                                         int64_t n3, const VState* st, int first) {
@@ -211,6 +226,13 @@ dgmf_status apply_eps(dgmf_op op, const double* u, double* out, hipStream_t s) {
                              op->sipg.diff_coeff, op->mesh->ncells, s);
 }
 
+// z = M^{-1} r on the three components (affine cells; curved meshes are refused)
+dgmf_status inv_mass3(dgmf_op op, const double* r, double* z, hipStream_t s) {
+  const dgmf_mesh m = op->mesh;
+  return launch_block_mass<double>(m->tab.n, m->g64, 1.0 / std::fabs(m->shear.det),
+                                   static_cast<const double*>(m->minv64.p), r, z, m->ncells, 3, true, s);
+}
+
 dgmf_status vcheck(dgmf_op op) {
   if (!op || op->kind != 1) return fail(DGMF_INVALID, "viscous_cg: not an SIPG operator");
   const dgmf_mesh m = op->mesh;
@@ -238,7 +260,9 @@ dgmf_status dgmf_viscous_cg_solve(dgmf_op op, const double* b, double* x, const 
                                   void* workspace, size_t workspace_bytes, hipStream_t stream, dgmf_cg_result* out) {
   if (dgmf_status e = vcheck(op)) return e;
   if (!b || !x || !params || !workspace || !out) return fail(DGMF_INVALID, "viscous_cg: null argument");
-  if (params->precond != 0) return fail(DGMF_UNSUPPORTED, "viscous_cg: only the Jacobi preconditioner (0)");
+  if (params->precond != 0 && params->precond != 3)
+    return fail(DGMF_UNSUPPORTED, "viscous_cg: preconditioner 0 (Jacobi) or 3 (inverse mass)");
+  const bool mass = params->precond == 3;
   if (!(params->rtol >= 0) || !std::isfinite(params->rtol) || params->max_iter < 0 || params->check_every < 0)
     return fail(DGMF_INVALID, "viscous_cg: rtol must be finite and >= 0, max_iter and check_every >= 0");
   if (reinterpret_cast<uintptr_t>(b) % 8 || reinterpret_cast<uintptr_t>(x) % 8 ||
@@ -280,6 +304,11 @@ dgmf_status dgmf_viscous_cg_solve(dgmf_op op, const double* b, double* x, const 
   if ((e = apply_eps(op, x, q, stream))) return e;
   hipLaunchKernelGGL(k_v_init, G, B, 0, stream, b, q, r, z, dinv, N, part);
   DGMF_LAUNCH_CHECK("k_v_init");
+  if (mass) {   // z = M^{-1} r replaces the diagonal scaling, and <r, z> with it
+    if ((e = inv_mass3(op, r, z, stream))) return e;
+    hipLaunchKernelGGL(k_v_rz, G, B, 0, stream, r, z, 3 * N, part, 0, st, 1);
+    DGMF_LAUNCH_CHECK("k_v_rz");
+  }
   hipLaunchKernelGGL(k_v_scalar, dim3(1), B, 0, stream, st, part, static_cast<int>(VM_INIT));
   DGMF_LAUNCH_CHECK("k_v_scalar");
   hipLaunchKernelGGL(k_v_pupdate, G, B, 0, stream, p, z, 3 * N, st, 1);
@@ -298,6 +327,11 @@ dgmf_status dgmf_viscous_cg_solve(dgmf_op op, const double* b, double* x, const 
       DGMF_LAUNCH_CHECK("k_v_scalar");
       hipLaunchKernelGGL(k_v_update, G, B, 0, stream, x, r, p, q, z, dinv, N, part, st);
       DGMF_LAUNCH_CHECK("k_v_update");
+      if (mass) {
+        if ((e = inv_mass3(op, r, z, stream))) return e;
+        hipLaunchKernelGGL(k_v_rz, G, B, 0, stream, r, z, 3 * N, part, 1, st, 0);
+        DGMF_LAUNCH_CHECK("k_v_rz");
+      }
       hipLaunchKernelGGL(k_v_scalar, dim3(1), B, 0, stream, st, part, static_cast<int>(VM_BETA));
       DGMF_LAUNCH_CHECK("k_v_scalar");
       hipLaunchKernelGGL(k_v_pupdate, G, B, 0, stream, p, z, 3 * N, st, 0);

@@ -206,3 +206,58 @@ def test_full_size_solves(case):
     print(f"[result] {case}: iterations {out.iterations}, rel. error vs exact discrete solution {err:.2e}")
     assert err < 1e-7
     gm.close()
+
+
+MASS_CASES = {
+    # name: (workload, cells or None)
+    "helmholtz_c1_small": (inp.HELMHOLTZ_C1, (4, 3, 5)),
+    "channel_helmholtz_small": (inp.CHANNEL_C4, (3, 4, 3)),
+}
+
+
+@pytest.mark.parametrize("name", list(MASS_CASES))
+def test_inverse_mass_preconditioned_cg_matches_oracle(name):
+    """The viscous-step preconditioner of Sec. 5.1: PCG with M^{-1}; the oracle runs the
+    same iteration with its dense per-cell inverse mass."""
+    require_gpu()
+    from oracle import mass as omass
+    print(f"[case] mass-preconditioned cg {name}", flush=True)
+    w, cells = MASS_CASES[name]
+    om, oop, gm, gop = _setup(w, cells)
+    A = oop.assemble()
+    b = inp.uniform(31, om.ndofs)
+    x0 = inp.uniform(32, om.ndofs)
+    xr, itr, st, _ = solvers.pcg(lambda v: A @ v, b, x0, lambda r: omass.inverse_mass_cells(om, r), 1e-10, 500)
+    assert st == solvers.OK
+    xg = dev(x0)
+    out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=500, check_every=4, precond="mass")
+    assert out.status == 0 and abs(out.iterations - itr) <= 1
+    assert np.linalg.norm(b - A @ host(xg)) <= 2e-10 * np.linalg.norm(b)
+    # ten fixed iterations: the iterates themselves
+    xr10, _, _, _ = solvers.pcg(lambda v: A @ v, b, x0, lambda r: omass.inverse_mass_cells(om, r), 1e-30, 10)
+    xg = dev(x0)
+    gop.cg(dev(b), xg, rtol=1e-30, max_iter=10, precond="mass", raise_on_failure=False)
+    assert rel_err(host(xg), xr10) < 1e-11
+    gm.close()
+
+
+def test_inverse_mass_preconditioned_cg_full_size():
+    """C1 (the viscous step's Helmholtz operator, mu = 1000, nu = 0.01): M^{-1} against
+    Jacobi; the true residual by the oracle on sampled cells."""
+    require_gpu()
+    from tests.gpu_util import sample_cells
+    w = inp.HELMHOLTZ_C1
+    print(f"[case] mass-preconditioned cg full-size {w.name}", flush=True)
+    om, oop, gm, gop = _setup(w)
+    b = inp.uniform(33, om.ndofs)
+    its = {}
+    for pc in ("mass", "jacobi"):
+        xg = torch.zeros(om.ndofs, dtype=torch.float64, device="cuda")
+        out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=1000, precond=pc)
+        assert out.status == 0
+        its[pc] = out.iterations
+        cells = sample_cells(w.cells, 16, 3)
+        r = b.reshape(om.ncells, -1)[cells] - oop.apply_cells(host(xg), cells)
+        assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+    print(f"[result] C1 CG iterations: inverse mass {its['mass']}, Jacobi {its['jacobi']}", flush=True)
+    gm.close()

@@ -185,3 +185,34 @@ def test_neumann_sides_match_oracle(name):
         assert out.status == 0 and abs(out.iterations - itr) <= 1
         assert np.linalg.norm(b - A @ host(xg)) <= 2e-10 * np.linalg.norm(b)
     gm.close()
+
+
+@pytest.mark.parametrize("name", ["k2_dirichlet", "k3_channel"])
+def test_viscous_cg_inverse_mass_matches_oracle(name):
+    """The paper's viscous preconditioner (Sec. 5.1): the inverse mass matrix on
+    every component, against the oracle's PCG with dense per-cell inverses."""
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    from oracle import mass as omass, solvers
+    k, cells, L, y0, per, gam, mu, nu, pen = CASES[name]
+    print(f"[case] viscous cg inverse mass {name}", flush=True)
+    om = omesh.BoxMesh(k, *cells, lx=L[0], ly=L[1], lz=L[2], y0=y0, periodic=tuple(bool(p) for p in per),
+                       y_tanh_gamma=gam)
+    gm = dg.Mesh(k, *cells, *L, y0=y0, periodic=per, y_tanh_gamma=gam)
+    gop = dg.SipgOperator(gm, mu, nu, pen)
+    A = ovisc.viscous_matrix(om, mu, nu, pen)
+    N = om.ndofs
+
+    def minv(r):
+        return np.concatenate([omass.inverse_mass_cells(om, r[a * N:(a + 1) * N]) for a in range(3)])
+
+    b = inp.uniform(96, 3 * N)
+    _, itr, st, _ = solvers.pcg(lambda v: A @ v, b, np.zeros(3 * N), minv, 1e-10, 3000)
+    assert st == solvers.OK
+    xg = dev(np.zeros(3 * N))
+    out = gop.viscous_cg(dev(b), xg, rtol=1e-10, max_iter=3000, check_every=4, precond="mass")
+    assert out.status == 0
+    print(f"  iterations: library {out.iterations}, oracle {itr}", flush=True)
+    assert abs(out.iterations - itr) <= 1
+    assert np.linalg.norm(b - A @ host(xg)) <= 2e-10 * np.linalg.norm(b)
+    gm.close()
