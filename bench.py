@@ -24,6 +24,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6    # vector and matrix fp64
+FP32_PEAK_TFLOPS = 157.3
+
+
+def reference_flops_per_dof(n):
+    """The method's own work count for the SIPG apply on affine cells (sum
+    factorisation, Sec. 5): cell 24 n^4 + faces 120 n^3 per cell, i.e. 24 n + 120
+    per DoF; the kernels do less on axis-aligned cells (precombined 1D matrices)."""
+    return 24 * n + 120
 
 
 def _events_time(fn, steps, warmup):
@@ -146,7 +155,9 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     y32 = torch.empty_like(u32)
     t32 = _events_time(lambda: op_c1.apply(u32, y32), 100, 5)
     ex["c1_apply_f32"] = {"dofs_per_s": N / t32, "alg_GBps": 8.0 * N / t32 / 1e9, "us": t32 * 1e6}
-    ex["c1_apply_f64"] = {"dofs_per_s": N / t_c1, "alg_GBps": 16.0 * N / t_c1 / 1e9, "us": t_c1 * 1e6}
+    fl1 = reference_flops_per_dof(mesh_c1.degree + 1) * N
+    ex["c1_apply_f64"] = {"dofs_per_s": N / t_c1, "alg_GBps": 16.0 * N / t_c1 / 1e9, "us": t_c1 * 1e6,
+                          "ref_tflops": fl1 / t_c1 / 1e12, "fp64_frac": fl1 / t_c1 / 1e12 / FP64_PEAK_TFLOPS}
     # symmetric-gradient viscous operator on a velocity (3 scalar applies + the coupling kernel);
     # algorithmic bytes 48 per velocity node (3 reads, 3 writes)
     Uv = torch.as_tensor(inp.uniform(12, 3 * N), device="cuda")
@@ -214,10 +225,13 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     v32 = v.float()
     yv32 = torch.empty_like(v32)
     tb = _events_time(lambda: op2.apply(v32, yv32), 50, 5)
+    fl2 = reference_flops_per_dof(w2.degree + 1) * N2
     ex["c2_apply_f64"] = {"dofs_per_s": N2 / ta, "alg_GBps": 16.0 * N2 / ta / 1e9, "us": ta * 1e6,
-                          "hbm_frac": 16.0 * N2 / ta / 1e9 / HBM_PEAK_GBS}
+                          "hbm_frac": 16.0 * N2 / ta / 1e9 / HBM_PEAK_GBS,
+                          "ref_tflops": fl2 / ta / 1e12, "fp64_frac": fl2 / ta / 1e12 / FP64_PEAK_TFLOPS}
     ex["c2_apply_f32"] = {"dofs_per_s": N2 / tb, "alg_GBps": 8.0 * N2 / tb / 1e9, "us": tb * 1e6,
-                          "hbm_frac": 8.0 * N2 / tb / 1e9 / HBM_PEAK_GBS}
+                          "hbm_frac": 8.0 * N2 / tb / 1e9 / HBM_PEAK_GBS,
+                          "ref_tflops": fl2 / tb / 1e12, "fp32_frac": fl2 / tb / 1e12 / FP32_PEAK_TFLOPS}
     qp = op2.quadrature_points()
     fq = torch.as_tensor(inp.poisson_rhs_sin3(*[qp[i].cpu().numpy() for i in range(3)]), device="cuda")
     del qp
