@@ -50,6 +50,22 @@ def _events_time(fn, steps, warmup):
     return s.elapsed_time(e) * 1e-3 / steps
 
 
+def _events_each(fn, reps, warmup):
+    """Median and minimum of reps individually event-timed calls (seconds)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for s, e in ev:
+        s.record()
+        fn()
+        e.record()
+    torch.cuda.synchronize()
+    t = sorted(s.elapsed_time(e) * 1e-3 for s, e in ev)
+    return t[len(t) // 2], t[0]
+
+
 def _traffic(kernel_key, n_launch_bytes_hint=None):
     """HBM bytes per launch from the committed counter summary, or None if stale/missing."""
     from paper_1607_01323_amd import profiling
@@ -155,9 +171,12 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     y32 = torch.empty_like(u32)
     t32 = _events_time(lambda: op_c1.apply(u32, y32), 100, 5)
     ex["c1_apply_f32"] = {"dofs_per_s": N / t32, "alg_GBps": 8.0 * N / t32 / 1e9, "us": t32 * 1e6}
+    y1 = torch.empty_like(u_c1)
+    med, mn = _events_each(lambda: op_c1.apply(u_c1, y1), 50, 5)
     fl1 = reference_flops_per_dof(mesh_c1.degree + 1) * N
     ex["c1_apply_f64"] = {"dofs_per_s": N / t_c1, "alg_GBps": 16.0 * N / t_c1 / 1e9, "us": t_c1 * 1e6,
-                          "ref_tflops": fl1 / t_c1 / 1e12, "fp64_frac": fl1 / t_c1 / 1e12 / FP64_PEAK_TFLOPS}
+                          "ref_tflops": fl1 / t_c1 / 1e12, "fp64_frac": fl1 / t_c1 / 1e12 / FP64_PEAK_TFLOPS,
+                          "single_launch_median_us": med * 1e6, "single_launch_min_us": mn * 1e6}
     # symmetric-gradient viscous operator on a velocity (3 scalar applies + the coupling kernel);
     # algorithmic bytes 48 per velocity node (3 reads, 3 writes)
     Uv = torch.as_tensor(inp.uniform(12, 3 * N), device="cuda")
