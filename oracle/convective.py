@@ -16,7 +16,10 @@ update is gamma_0 U^ = sum alpha U - dt M^{-1} C + F.
 
 Integrals use Gauss quadrature with n_q points per direction on cells and
 tangentially on faces (Sec. 5 over-integration; default floor(3(k+1)/2)).
-Dense per-cell evaluation matrices, no sum factorisation; fp64.
+Dense per-cell evaluation matrices, no sum factorisation; fp64.  On curved
+(iso-parametric) cells, Sec. 5, the Jacobian of the cell map is taken at
+every cell and face quadrature point, with face normals and surface measures
+from Nanson's formula; the flux is written for a normal per face point.
 
 The vector-Jacobian product is not in the paper; it is the exact transpose of
 the derivative of C (piecewise quadratic in U), with the tie rule: the minus
@@ -32,7 +35,11 @@ homogeneity of degree 2, Lax-Friedrichs dissipation identity, quadrature
 invariance with lam = 0, channel profile; JVP against central differences,
 VJP against the transpose of the brute-force Jacobian, Euler identity; with
 outflow sides (tests/test_oracle_conv_outflow.py): a constant field gives
-C = 0 exactly, JVP against central differences, VJP against the Jacobian.
+C = 0 exactly, JVP against central differences, VJP against the Jacobian; on
+curved cells (tests/test_oracle_conv_curved.py): zero amplitude gives the
+affine operator, free-stream preservation (exact quadrature of the cofactor
+integrands), conservation, order-k consistency with div(u (x) u), JVP, VJP
+and the Euler identity.
 """
 import numpy as np
 
@@ -70,27 +77,55 @@ class Convective:
         self.g = g      # Dirichlet velocity callable (x,y,z) -> (3, m); None means g = 0
 
     # -- geometry helpers ------------------------------------------------------
+    # Affine cells have one Jacobian; curved (iso-parametric) cells, meshes
+    # with a ``jac_at`` method, take the Jacobian of their map at every
+    # quadrature point (Sec. 5: the cell geometry enters through the Jacobian
+    # at each point).  Face normals follow Nanson's formula n dA = det J J^{-T}
+    # N_ref dA_ref, per point.
+    def _curved(self):
+        return hasattr(self.mesh, "jac_at")
+
+    def _face_ref(self, d, s):
+        axes = [self.xq, self.xq, self.xq]
+        axes[d] = np.array([float(s)])
+        Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+        return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
     def _cell_geo(self, c):
+        if self._curved():
+            Z, Y, X = np.meshgrid(self.xq, self.xq, self.xq, indexing="ij")
+            J = self.mesh.jac_at(c, np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
+            Jinv = np.linalg.inv(J)
+            detJ = np.abs(np.linalg.det(J))
+            Gphys = [sum(Jinv[:, b, a][:, None] * self.Gref[b] for b in range(3)) for a in range(3)]
+            return Gphys, self.wcell * detJ
         J = self.mesh.jacobian(c)
         Jinv = np.linalg.inv(J)
         detJ = abs(np.linalg.det(J))
         Gphys = [sum(Jinv[b, a] * self.Gref[b] for b in range(3)) for a in range(3)]
         return Gphys, self.wcell * detJ
 
-    def _face_geo(self, c, d):
+    def _face_geo(self, c, d, s):
+        """Unit normal along +xi_d (3, m) and surface weights (m,) of face (d, s) of cell c."""
+        mq = self.nq ** 2
+        if self._curved():
+            J = self.mesh.jac_at(c, self._face_ref(d, s))
+            Jinv = np.linalg.inv(J)
+            m = Jinv[:, d, :].T                                   # (3, mq): J^{-T} e_d
+            nm = np.linalg.norm(m, axis=0)
+            return m / nm, self.wface[d] * np.abs(np.linalg.det(J)) * nm
         J = self.mesh.jacobian(c)
         Jinv = np.linalg.inv(J)
         m = Jinv.T[:, d]
         nrm = m / np.linalg.norm(m)
         dA = self.wface[d] * abs(np.linalg.det(J)) * np.linalg.norm(m)
-        return nrm, dA
+        return np.repeat(nrm[:, None], mq, axis=1), dA
 
     def _face_points(self, c, f):
         d, s = divmod(f, 2)
-        axes = [self.xq, self.xq, self.xq]
-        axes[d] = np.array([float(s)])
-        Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
-        ref = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+        ref = self._face_ref(d, s)
+        if self._curved():
+            return self.mesh.map_at(c, ref)
         o, _ = self.mesh.cell_origin_h(c)
         x0 = o if self.mesh.shear is None else self.mesh.shear @ o
         return x0 + ref @ self.mesh.jacobian(c).T
@@ -105,9 +140,9 @@ class Convective:
     # -- flux and its derivative -------------------------------------------------
     @staticmethod
     def flux(um, up, n, lam_on=True):
-        """R(u-, u+; n) at face points; um, up shape (3, m), n shape (3,)."""
-        a = n @ um
-        b = n @ up
+        """R(u-, u+; n) at face points; um, up and the unit normals n have shape (3, m)."""
+        a = np.sum(n * um, axis=0)
+        b = np.sum(n * up, axis=0)
         R = 0.5 * (um * a + up * b)
         if lam_on:
             lam = np.maximum(np.abs(a), np.abs(b))
@@ -117,23 +152,23 @@ class Convective:
     @staticmethod
     def flux_jac_T(um, up, n, w):
         """(J-^T w, J+^T w) at each face point, with the tie rule of the module doc."""
-        a = n @ um
-        b = n @ up
+        a = np.sum(n * um, axis=0)
+        b = np.sum(n * up, axis=0)
         lam = np.maximum(np.abs(a), np.abs(b))
         minus_active = np.abs(a) >= np.abs(b)
-        dlm = np.where(minus_active, np.sign(a), 0.0)[None, :] * n[:, None]
-        dlp = np.where(minus_active, 0.0, np.sign(b))[None, :] * n[:, None]
+        dlm = np.where(minus_active, np.sign(a), 0.0)[None, :] * n
+        dlp = np.where(minus_active, 0.0, np.sign(b))[None, :] * n
         jump_u_w = np.sum((um - up) * w, axis=0)
-        Jm = 0.5 * (a * w + n[:, None] * np.sum(um * w, axis=0)) + lam * w + dlm * jump_u_w
-        Jp = 0.5 * (b * w + n[:, None] * np.sum(up * w, axis=0)) - lam * w + dlp * jump_u_w
+        Jm = 0.5 * (a * w + n * np.sum(um * w, axis=0)) + lam * w + dlm * jump_u_w
+        Jp = 0.5 * (b * w + n * np.sum(up * w, axis=0)) - lam * w + dlp * jump_u_w
         return Jm, Jp
 
     @staticmethod
     def flux_jvp(um, up, n, dum, dup):
-        a = n @ um
-        b = n @ up
-        da = n @ dum
-        db = n @ dup
+        a = np.sum(n * um, axis=0)
+        b = np.sum(n * up, axis=0)
+        da = np.sum(n * dum, axis=0)
+        db = np.sum(n * dup, axis=0)
         lam = np.maximum(np.abs(a), np.abs(b))
         minus_active = np.abs(a) >= np.abs(b)
         dlam = np.where(minus_active, np.sign(a) * da, np.sign(b) * db)
@@ -158,7 +193,7 @@ class Convective:
                 d, s = divmod(f, 2)
                 cn = m.neighbor(c, f)
                 if cn < 0:
-                    nrm, dA = self._face_geo(c, d)
+                    nrm, dA = self._face_geo(c, d, s)
                     nout = nrm if s == 1 else -nrm
                     um = (self.Tr[f] @ V[:, c, :].T).T
                     # outflow (Neumann) face: the flux of the own trace, F^c(u-).n
@@ -166,13 +201,13 @@ class Convective:
                     R = self.flux(um, up, nout, lam_on)
                     out[:, r] += (self.Tr[f].T @ (dA * R).T).T
                 elif s == 1:
-                    nrm, dA = self._face_geo(c, d)
+                    nrm, dA = self._face_geo(c, d, 1)
                     um = (self.Tr[2 * d + 1] @ V[:, c, :].T).T
                     up = (self.Tr[2 * d] @ V[:, cn, :].T).T
                     R = self.flux(um, up, nrm, lam_on)
                     out[:, r] += (self.Tr[f].T @ (dA * R).T).T
                 else:
-                    nrm, dA = self._face_geo(cn, d)
+                    nrm, dA = self._face_geo(cn, d, 1)
                     um = (self.Tr[2 * d + 1] @ V[:, cn, :].T).T
                     up = (self.Tr[2 * d] @ V[:, c, :].T).T
                     R = self.flux(um, up, nrm, lam_on)
@@ -200,7 +235,7 @@ class Convective:
                 d, s = divmod(f, 2)
                 cn = m.neighbor(c, f)
                 if cn < 0:
-                    nrm, dA = self._face_geo(c, d)
+                    nrm, dA = self._face_geo(c, d, s)
                     nout = nrm if s == 1 else -nrm
                     um = (self.Tr[f] @ V[:, c, :].T).T
                     dum = (self.Tr[f] @ dV[:, c, :].T).T
@@ -209,7 +244,7 @@ class Convective:
                     out[:, c] += (self.Tr[f].T @ (dA * dR).T).T
                     continue
                 L, R_ = (c, cn) if s == 1 else (cn, c)
-                nrm, dA = self._face_geo(L, d)
+                nrm, dA = self._face_geo(L, d, 1)
                 um = (self.Tr[2 * d + 1] @ V[:, L, :].T).T
                 up = (self.Tr[2 * d] @ V[:, R_, :].T).T
                 dum = (self.Tr[2 * d + 1] @ dV[:, L, :].T).T
@@ -237,7 +272,7 @@ class Convective:
                 d, s = divmod(f, 2)
                 cn = m.neighbor(c, f)
                 if cn < 0:
-                    nrm, dA = self._face_geo(c, d)
+                    nrm, dA = self._face_geo(c, d, s)
                     nout = nrm if s == 1 else -nrm
                     um = (self.Tr[f] @ V[:, c, :].T).T
                     up = um if m.neumann[f] else 2.0 * self._gvals(c, f) - um
@@ -247,7 +282,7 @@ class Convective:
                     out[:, r] += (self.Tr[f].T @ (dA * (Jm + Jp if m.neumann[f] else Jm - Jp)).T).T
                     continue
                 L, R_ = (c, cn) if s == 1 else (cn, c)
-                nrm, dA = self._face_geo(L, d)
+                nrm, dA = self._face_geo(L, d, 1)
                 um = (self.Tr[2 * d + 1] @ V[:, L, :].T).T
                 up = (self.Tr[2 * d] @ V[:, R_, :].T).T
                 jw = (self.Tr[2 * d + 1] @ Wc[:, L, :].T).T - (self.Tr[2 * d] @ Wc[:, R_, :].T).T
