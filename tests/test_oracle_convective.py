@@ -46,10 +46,10 @@ def test_lax_friedrichs_dissipation_identity(per):
     V = U.reshape(3, m.ncells, -1)
     rhs = 0.0
     for cL, cR, d in m.interior_faces():
-        nrm, dA = op._face_geo(cL, d)
+        nrm, dA = op._face_geo(cL, d, 1)          # unit normals (3, m), one per face point
         um = (op.Tr[2 * d + 1] @ V[:, cL, :].T).T
         up = (op.Tr[2 * d] @ V[:, cR, :].T).T
-        lam = np.maximum(np.abs(nrm @ um), np.abs(nrm @ up))
+        lam = np.maximum(np.abs(np.sum(nrm * um, axis=0)), np.abs(np.sum(nrm * up, axis=0)))
         rhs += np.sum(dA * lam * np.sum((um - up) ** 2, axis=0))
     assert rhs > 0
     assert abs(lhs - rhs) < 1e-12 * rhs
