@@ -307,7 +307,9 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
 def curved_measurements(dg, inp, torch, w, tag):
     """Channel Helmholtz on iso-parametric curved cells: metric set-up, apply (fp64,
     fp32; the stored-metric kernel, same algorithmic bytes as on affine cells), and
-    PCG to 1e-10 on a random right-hand side (mixed fp32 Chebyshev, fp64 Jacobi)."""
+    PCG to 1e-10 on a random right-hand side (mixed fp32 Chebyshev, fp64 Jacobi);
+    then the convective operator and its VJP on the same cells (the per-point
+    metric filled at create; U = (1, 0, 0) + 0.05 uniform[-1, 1])."""
     ex = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -337,6 +339,28 @@ def curved_measurements(dg, inp, torch, w, tag):
         torch.cuda.synchronize()
         ex[f"{tag}_cg_{name}"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
                                   "status": out.status, "setup_s": out.setup_s, "solve_s": out.solve_s}
+    del b
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    opc = dg.ConvectiveOperator(m)
+    torch.cuda.synchronize()
+    tc = time.perf_counter() - t0
+    nq = (3 * n) // 2
+    U = 0.05 * torch.as_tensor(inp.uniform(6, 3 * N), device="cuda")
+    U[:N] += 1.0
+    Wc = torch.as_tensor(inp.uniform(9, 3 * N), device="cuda")
+    Cout = torch.empty_like(U)
+    Gout = torch.empty_like(U)
+    tf = _events_time(lambda: opc.apply(U, Cout), 10, 2)
+    tv = _events_time(lambda: opc.vjp(U, Wc, Gout), 10, 2)
+    met = m.ncells * 8 * (9 * nq ** 3 + 18 * nq ** 2)     # per-point metric read once per launch
+    ex[f"{tag}_convective"] = {"create_s": tc, "fwd_us": tf * 1e6, "vjp_us": tv * 1e6,
+                               "fwd_dofs_per_s": 3 * N / tf, "vjp_dofs_per_s": 3 * N / tv,
+                               "fwd_plus_vjp_dofs_per_s": 3 * N / (tf + tv), "dofs": 3 * N, "n_q": nq,
+                               "metric_bytes": met,
+                               "fwd_hbm_frac": (16 * 3 * N + met) / tf / 1e9 / HBM_PEAK_GBS,
+                               "vjp_hbm_frac": (24 * 3 * N + met) / tv / 1e9 / HBM_PEAK_GBS}
+    opc.close()
     m.close()
     return ex
 

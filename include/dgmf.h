@@ -109,9 +109,11 @@ int dgmf_version(void);
  * needs store_qp_metric = 1 and no shear.  Curved meshes serve the SIPG
  * operator, its diagonal, CG with every preconditioner (multigrid keeps the
  * curved operator on the finest level and rediscretises the coarse levels on
- * the undeformed box), and the mass matrix and its inverse (with the point
- * weights w_q det J_q); every other operator (and coordinates, load vectors)
- * returns DGMF_UNSUPPORTED on them.
+ * the undeformed box), the mass matrix and its inverse (with the point
+ * weights w_q det J_q), and the convective operator and its VJP (with the
+ * Jacobian at every quadrature point); every other operator (and the fused
+ * convective substep, coordinates, load vectors) returns DGMF_UNSUPPORTED on
+ * them.
  * degree k in 1..7; every cell count >= 1; lengths > 0. */
 typedef struct {
   int degree;
@@ -331,7 +333,10 @@ dgmf_status dgmf_precond_info(dgmf_op op, int* levels, double* lambdas, int* coa
  * lam = max(|u-.n|, |u+.n|) per face quadrature point (Sec. 3.2); Dirichlet
  * faces use the mirror state u+ = 2g - u- with g = 0, outflow (Neumann) sides
  * the own state u+ = u- (flux F^c(u-).n).  n_q Gauss points per direction on
- * cells and faces; 0 -> floor(3(k+1)/2). */
+ * cells and faces; 0 -> floor(3(k+1)/2).  On curved cells (Sec. 5) create
+ * fills, on the device and synchronously, a per-point metric: w |det J| J^{-1}
+ * at every cell point and the weighted normal w dA n at every face point, of
+ * 8 (9 n_q^3 + 18 n_q^2) bytes per cell, owned by the operator. */
 typedef struct { int n_q; } dgmf_conv_desc;
 
 dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, dgmf_op* out);
@@ -344,6 +349,8 @@ dgmf_status dgmf_convective_apply(dgmf_op op, const double* u, double* out, hipS
  * combinations sum_i alpha_i U^{n-i} - dt M^{-1} sum_i beta_i F^c(U^{n-i})
  * follow from dgmf_convective_apply, dgmf_inverse_mass_apply and vector
  * sums.  u, out: device fp64 [3][N], must not overlap; dt finite.
+ * Curved cells (no block-diagonal mass): DGMF_UNSUPPORTED; there the same
+ * step is dgmf_convective_apply followed by dgmf_inverse_mass_apply.
  * Asynchronous. */
 dgmf_status dgmf_convective_step(dgmf_op op, double dt, const double* u, double* out, hipStream_t stream);
 /* grad = (dC/du)^T w; u, w, grad: device fp64 [3][N]; grad must not alias

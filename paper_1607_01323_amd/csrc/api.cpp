@@ -942,7 +942,6 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
   const int nq = desc->n_q > 0 ? desc->n_q : (3 * (k + 1)) / 2;
   if (desc->n_q < 0) return fail(DGMF_INVALID, "convective_create: n_q must be >= 0");
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "convective_create: sheared meshes are not supported");
-  if (dgmf_status e = flat_check(mesh, "convective_create")) return e;
   if (!conv_supported(n, nq))
     return fail(DGMF_UNSUPPORTED, "convective_create: degree %d with %d points per direction not built", k, nq);
   DeviceGuard dg(mesh->device);
@@ -962,12 +961,49 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
     return fail(DGMF_INVALID, "convective_create: singular interpolation matrix");
   }
   h.insert(h.end(), mi.begin(), mi.end());
+  // curved-cell metric fill: GLL nodes, l(0), l(1), l'(0), l'(1)
+  const int o_nodes = static_cast<int>(h.size());
+  h.insert(h.end(), op->tab.nodes.begin(), op->tab.nodes.end());
+  const int o_e = static_cast<int>(h.size());
+  h.resize(h.size() + 2 * n, 0.0);
+  h[o_e] = 1.0;
+  h[o_e + 2 * n - 1] = 1.0;
+  const int o_g = static_cast<int>(h.size());
+  h.insert(h.end(), op->tab.g0.begin(), op->tab.g0.end());
+  h.insert(h.end(), op->tab.g1.begin(), op->tab.g1.end());
   dgmf_status st = op->ctab.upload(h.data(), h.size() * sizeof(double));
   if (st != DGMF_OK) {
     delete op;
     return st;
   }
   ConvGeom& g = op->cgeo;
+  g.cmet = nullptr;
+  g.fmet = nullptr;
+  if (mesh->desc.curve_amp != 0.0) {
+    // per point: 9 cell values, 6 faces x 3 normal components
+    const int64_t nq2 = static_cast<int64_t>(nq) * nq, cper = 9 * nq2 * nq, fper = 18 * nq2;
+    if ((st = op->cmet.alloc(static_cast<size_t>(mesh->ncells * (cper + fper)) * sizeof(double)))) {
+      delete op;
+      return st;
+    }
+    double* cm = static_cast<double*>(op->cmet.p);
+    const double* x0[3] = {mesh->g64.x0[0], mesh->g64.x0[1], mesh->g64.x0[2]};
+    const double* hh[3] = {mesh->g64.h[0], mesh->g64.h[1], mesh->g64.h[2]};
+    const double lo[3] = {0.0, mesh->desc.y0, 0.0};
+    const double len[3] = {mesh->desc.lx, mesh->desc.ly, mesh->desc.lz};
+    const int off[6] = {o_nodes, 0, nq * n, 2 * nq * n, o_e, o_g};
+    st = launch_conv_fill_curved(n, nq, x0, hh, lo, len, mesh->desc.curve_amp, mesh->g64.nx, mesh->g64.ny,
+                                 mesh->ncells, static_cast<const double*>(op->ctab.p), off, cm,
+                                 cm + mesh->ncells * cper, nullptr);
+    if (st == DGMF_OK && hipStreamSynchronize(nullptr) != hipSuccess)
+      st = fail(DGMF_HIP_ERROR, "convective_create: curved metric fill failed");
+    if (st != DGMF_OK) {
+      delete op;
+      return st;
+    }
+    g.cmet = cm;
+    g.fmet = cm + mesh->ncells * cper;
+  }
   g.neu = neumann_mask(mesh->desc);
   g.nx = mesh->g64.nx;
   g.ny = mesh->g64.ny;
@@ -1002,6 +1038,7 @@ dgmf_status dgmf_convective_step(dgmf_op op, double dt, const double* u, double*
   if (!u || !out || !aligned(u, 8) || !aligned(out, 8))
     return fail(DGMF_INVALID, "convective_step: null or misaligned vector");
   if (overlap(u, out, 24 * op->mesh->ndofs)) return fail(DGMF_INVALID, "convective_step: u and out overlap");
+  if (op->cgeo.cmet) return fail(DGMF_UNSUPPORTED, "convective_step: curved cells are not supported");
   DeviceGuard dg(op->mesh->device);
   return launch_conv_fwd(op->tab.n, op->nq, op->cgeo, u, out, op->mesh->ncells, true, dt, stream);
 }

@@ -28,6 +28,7 @@
 // (Mh^{-1} along x, y and z, times 1/|det J|; Sec. 5, implementation) to the
 // cell's result in LDS and writes U - dt M^{-1} C(U) in the same store, so
 // C(U) never travels through HBM.
+#include "curv_map.h"
 #include "internal.h"
 
 namespace dgmf {
@@ -244,12 +245,13 @@ __device__ __forceinline__ void copy_plane(const double* sIn, int d, int s, doub
 }
 
 // ---------------------------------------------------------------- forward
-template <int N, int Q, bool STEP>
+template <int N, int Q, bool STEP, bool CURV>
 __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const double* __restrict__ U,
                                                                     double* __restrict__ C, const ConvGeom g,
                                                                     int64_t ncells, double dt) {
+  static_assert(!(STEP && CURV), "the fused substep needs the block inverse mass of affine cells");
   using SH = CShape<N, Q>;
-  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2;
+  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
   constexpr int XR = (3 * N2 * Q + 3 * N * Q2) > (3 * N * Q2 + 2 * N2 * Q) ? (3 * N2 * Q + 3 * N * Q2)
                                                                               : (3 * N * Q2 + 2 * N2 * Q);
   constexpr int XF = 12 * N2 + 12 * N * Q + 12 * Q2 + 6 * Q2;   // planes, stage, traces, fluxes
@@ -282,6 +284,20 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
   const double vol = cg.h[0] * cg.h[1] * cg.h[2];
   double* A = sX;                 // 3 * N*Q*Q  ([m][l][qy][qx])
   double* B = sX + 3 * N * Q2;    // 2 * N*N*Q  ([m][l][j][qx])
+  // curved cells: V_e = sum_b w adj(J)_eb u_b on this column, so that the
+  // flux of component a against d/dxi_e is u_a V_e
+  double V[3][CURV ? Q : 1];
+  if constexpr (CURV) {
+    if (own) {
+      const double* Mc = g.cmet + cell * 9 * Q3 + qy * Q + qx;
+#pragma unroll
+      for (int qz = 0; qz < Q; ++qz)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          V[e][qz] = fma(Mc[(3 * e + 0) * Q3 + qz * Q2], u[0][qz],
+                         fma(Mc[(3 * e + 1) * Q3 + qz * Q2], u[1][qz], Mc[(3 * e + 2) * Q3 + qz * Q2] * u[2][qz]));
+    }
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (own) {
@@ -289,10 +305,16 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
       double fx[Q], fy[Q], fz[Q];
 #pragma unroll
       for (int qz = 0; qz < Q; ++qz) {
-        const double f = wxy * w[qz] * u[a][qz];
-        fx[qz] = f * u[0][qz] * cg.hinv[0];
-        fy[qz] = f * u[1][qz] * cg.hinv[1];
-        fz[qz] = f * u[2][qz] * cg.hinv[2];
+        if constexpr (CURV) {
+          fx[qz] = u[a][qz] * V[0][qz];
+          fy[qz] = u[a][qz] * V[1][qz];
+          fz[qz] = u[a][qz] * V[2][qz];
+        } else {
+          const double f = wxy * w[qz] * u[a][qz];
+          fx[qz] = f * u[0][qz] * cg.hinv[0];
+          fy[qz] = f * u[1][qz] * cg.hinv[1];
+          fz[qz] = f * u[2][qz] * cg.hinv[2];
+        }
       }
       // one node l per step: the S and D columns of l only
 #pragma unroll kSweepUnroll<N, Q>
@@ -380,10 +402,23 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
         um[a] = F2[((s * 2 + 0) * 3 + a) * Q2 + pq];
         up[a] = F2[((s * 2 + 1) * 3 + a) * Q2 + pq];
       }
-      const double an = sg * um[d], bn = sg * up[d];
+      double an, bn, sc;
+      if constexpr (CURV) {
+        // the weighted normal w dA n (along +xi_d) of this face point; R is
+        // homogeneous of degree one in it
+        const double* fm = g.fmet + (cell * 18 + (2 * d + s) * 3) * Q2 + pq;
+        const double n0 = fm[0], n1 = fm[Q2], n2 = fm[2 * Q2];
+        an = sg * fma(n0, um[0], fma(n1, um[1], n2 * um[2]));
+        bn = sg * fma(n0, up[0], fma(n1, up[1], n2 * up[2]));
+        sc = 1.0;
+      } else {
+        an = sg * um[d];
+        bn = sg * up[d];
+        sc = wt;
+      }
       const double lam = fmax(fabs(an), fabs(bn));
 #pragma unroll
-      for (int a = 0; a < 3; ++a) R[(s * 3 + a) * Q2 + pq] = wt * (0.5 * (um[a] * an + up[a] * bn) + lam * (um[a] - up[a]));
+      for (int a = 0; a < 3; ++a) R[(s * 3 + a) * Q2 + pq] = sc * (0.5 * (um[a] * an + up[a] * bn) + lam * (um[a] - up[a]));
     }
     __syncthreads();
     face_lift<N, Q>(S, R, F1, sO, 6, d, -1, tid, nthr);
@@ -428,13 +463,13 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
 }
 
 // -------------------------------------------------------------------- VJP
-template <int N, int Q>
+template <int N, int Q, bool CURV>
 __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const double* __restrict__ U,
                                                                     const double* __restrict__ W,
                                                                     double* __restrict__ G, const ConvGeom g,
                                                                     int64_t ncells) {
   using SH = CShape<N, Q>;
-  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2;
+  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
   constexpr int XI = 3 * N2 * Q + 3 * N * Q2;          // interp3 scratch
   constexpr int XD = 2 * N2 * Q + 3 * N * Q2;          // gradient scratch
   constexpr int XF = 12 * N2 + 12 * N * Q + 12 * Q2 + 3 * Q2;   // one face: 12 planes + fluxes
@@ -534,9 +569,18 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         double gz = gzq[q], gy = gyq[q], gx = gxq[q];
-        gx *= cg.hinv[0];
-        gy *= cg.hinv[1];
-        gz *= cg.hinv[2];
+        if constexpr (CURV) {
+          // w det J times the physical gradient: sum_e w adj(J)_eb dw/dxi_e
+          const double* Mq = g.cmet + cell * 9 * Q3 + q * Q2 + qy * Q + qx;
+          const double r0 = gx, r1 = gy, r2 = gz;
+          gx = fma(Mq[0 * Q3], r0, fma(Mq[3 * Q3], r1, Mq[6 * Q3] * r2));
+          gy = fma(Mq[1 * Q3], r0, fma(Mq[4 * Q3], r1, Mq[7 * Q3] * r2));
+          gz = fma(Mq[2 * Q3], r0, fma(Mq[5 * Q3], r1, Mq[8 * Q3] * r2));
+        } else {
+          gx *= cg.hinv[0];
+          gy *= cg.hinv[1];
+          gz *= cg.hinv[2];
+        }
         // t_a += u . grad w_a ;  t_b += u_a d_b w_a
         t[a][q] = fma(u[0][q], gx, fma(u[1][q], gy, fma(u[2][q], gz, t[a][q])));
         t[0][q] = fma(u[a][q], gx, t[0][q]);
@@ -551,11 +595,13 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   double* Z = sX;                   // 3 * N*Q*Q  [c][l][qy][qx]
   double* Y = sX + 3 * N * Q2;      // 3 * N*N*Q  [c][l][j][qx]
   if (own) {
-    const double wxy = w[qx] * w[qy] * vol;
+    if constexpr (!CURV) {   // curved cells carry w det J in the metric already
+      const double wxy = w[qx] * w[qy] * vol;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int q = 0; q < Q; ++q) t[c][q] *= wxy * w[q];
+        for (int q = 0; q < Q; ++q) t[c][q] *= wxy * w[q];
+    }
     // one node l per step: the S column of l only
 #pragma unroll kSweepUnroll<N, Q>
     for (int l = 0; l < N; ++l) {
@@ -631,15 +677,42 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
         wo[a] = F2[(2 * 3 + a) * Q2 + pq];
         we[a] = nb >= 0 ? F2[(3 * 3 + a) * Q2 + pq] : 0.0;
       }
+      // normal along +xi_d: e_d on affine cells (weight wt), the weighted
+      // normal w dA n of the face point on curved cells (weight 1)
+      double nv[3] = {0.0, 0.0, 0.0};
+      double sc;
+      if constexpr (CURV) {
+        const double* fm = g.fmet + (cell * 18 + f * 3) * Q2 + pq;
+        nv[0] = fm[0];
+        nv[1] = fm[Q2];
+        nv[2] = fm[2 * Q2];
+        sc = 1.0;
+      } else {
+        sc = wt;
+      }
+      // n . v for the normal above
+      auto ndot = [&](const double* v) {
+        if constexpr (CURV) return fma(nv[0], v[0], fma(nv[1], v[1], nv[2] * v[2]));
+        else return v[d];
+      };
+      // res += n x
+      auto nadd = [&](double* res, double x) {
+        if constexpr (CURV) {
+#pragma unroll
+          for (int b = 0; b < 3; ++b) res[b] = fma(nv[b], x, res[b]);
+        } else {
+          res[d] += x;
+        }
+      };
       double res[3];
       if (nb >= 0) {
-        // orient with the low cell as the minus side, n = +e_d
+        // orient with the low cell as the minus side, n along +xi_d
         const double* um = s ? uo : ue;
         const double* up = s ? ue : uo;
         double jw[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) jw[a] = s ? (wo[a] - we[a]) : (we[a] - wo[a]);
-        const double an = um[d], bn = up[d];
+        const double an = ndot(um), bn = ndot(up);
         const double lam = fmax(fabs(an), fabs(bn));
         const bool mact = fabs(an) >= fabs(bn);
         const double dj = (um[0] - up[0]) * jw[0] + (um[1] - up[1]) * jw[1] + (um[2] - up[2]) * jw[2];
@@ -648,26 +721,26 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
           const double dl = mact ? (an > 0 ? 1.0 : (an < 0 ? -1.0 : 0.0)) : 0.0;
 #pragma unroll
           for (int a = 0; a < 3; ++a) res[a] = 0.5 * an * jw[a] + lam * jw[a];
-          res[d] += 0.5 * ujw + dl * dj;
+          nadd(res, 0.5 * ujw + dl * dj);
         } else {   // this cell is the plus side: J+^T [w]
           const double ujw = up[0] * jw[0] + up[1] * jw[1] + up[2] * jw[2];
           const double dl = mact ? 0.0 : (bn > 0 ? 1.0 : (bn < 0 ? -1.0 : 0.0));
 #pragma unroll
           for (int a = 0; a < 3; ++a) res[a] = 0.5 * bn * jw[a] - lam * jw[a];
-          res[d] += 0.5 * ujw + dl * dj;
+          nadd(res, 0.5 * ujw + dl * dj);
         }
       } else if ((g.neu >> f) & 1) {
         // outflow: R = u (u.n), (dR/du)^T w = (u.n) w + n (u.w), outward normal sg e_d
         const double sg = s ? 1.0 : -1.0;
-        const double an = sg * uo[d];
+        const double an = sg * ndot(uo);
         const double ujm = uo[0] * wo[0] + uo[1] * wo[1] + uo[2] * wo[2];
 #pragma unroll
         for (int a = 0; a < 3; ++a) res[a] = an * wo[a];
-        res[d] += sg * ujm;
+        nadd(res, sg * ujm);
       } else {
         // Dirichlet: (J- - J+)^T w- with u+ = -u-, outward normal sg e_d
         const double sg = s ? 1.0 : -1.0;
-        const double an = sg * uo[d], bn = sg * ue[d];
+        const double an = sg * ndot(uo), bn = sg * ndot(ue);
         const double lam = fmax(fabs(an), fabs(bn));
         const bool mact = fabs(an) >= fabs(bn);
         const double dj = (uo[0] - ue[0]) * wo[0] + (uo[1] - ue[1]) * wo[1] + (uo[2] - ue[2]) * wo[2];
@@ -678,10 +751,10 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
         const double dlm = mact ? sa : 0.0, dlp = mact ? 0.0 : sb;
 #pragma unroll
         for (int a = 0; a < 3; ++a) res[a] = 0.5 * (an - bn) * wo[a] + 2.0 * lam * wo[a];
-        res[d] += sg * (0.5 * (ujm - ujp) + (dlm - dlp) * dj);
+        nadd(res, sg * (0.5 * (ujm - ujp) + (dlm - dlp) * dj));
       }
 #pragma unroll
-      for (int a = 0; a < 3; ++a) R[a * Q2 + pq] = wt * res[a];
+      for (int a = 0; a < 3; ++a) R[a * Q2 + pq] = sc * res[a];
     }
     __syncthreads();
     face_lift<N, Q>(S, R, F1, sO, 3, d, s, tid, nthr);
@@ -693,16 +766,108 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   }
 }
 
+// ------------------------------------------------------ curved-cell metric
+// Per cell quadrature point, w_q |det J| J^{-1} = w_q sgn(det J) adj(J) (nine
+// values); per face point, the weighted normal w_q1 w_q2 |det J| J^{-T} e_d
+// (Nanson's formula, along +xi_d), i.e. sgn(det J) times row d of adj(J),
+// which only needs the two tangential columns of J.  Rows of a point: S/D at
+// Gauss points, E (l(0), l(1)) and Gd (l'(0), l'(1)) at the ends.
+struct FillTabs {
+  const double *S, *D, *w, *E, *Gd;
+};
+
+template <int N, int Q>
+__global__ void __launch_bounds__(256) k_conv_fill_cells(CurvMap m, int nx, int ny, int64_t ncells, FillTabs t,
+                                                         double* __restrict__ cmet) {
+  constexpr int Q3 = Q * Q * Q;
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= ncells * Q3) return;
+  const int64_t cell = gid / Q3;
+  const int q = static_cast<int>(gid - cell * Q3);
+  const int c[3] = {static_cast<int>(cell % nx), static_cast<int>((cell / nx) % ny),
+                    static_cast<int>(cell / (static_cast<int64_t>(nx) * ny))};
+  const int qi[3] = {q % Q, (q / Q) % Q, q / (Q * Q)};
+  const double* val[3];
+  const double* der[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    val[e] = t.S + qi[e] * N;
+    der[e] = t.D + qi[e] * N;
+  }
+  double J[9];
+  curv_jac_at<N>(m, c, val, der, J);
+  double A[3][3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) adj_row(J, e, A[e]);
+  const double det = J[0] * A[0][0] + J[3] * A[0][1] + J[6] * A[0][2];
+  const double wq = (det < 0.0 ? -1.0 : 1.0) * t.w[qi[0]] * t.w[qi[1]] * t.w[qi[2]];
+  double* out = cmet + cell * 9 * Q3 + q;
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) out[(3 * e + b) * Q3] = wq * A[e][b];
+}
+
+template <int N, int Q>
+__global__ void __launch_bounds__(256) k_conv_fill_faces(CurvMap m, int nx, int ny, int64_t ncells, FillTabs t,
+                                                         double* __restrict__ fmet) {
+  constexpr int Q2 = Q * Q;
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= ncells * 6 * Q2) return;
+  const int64_t cell = gid / (6 * Q2);
+  const int r = static_cast<int>(gid - cell * 6 * Q2);
+  const int f = r / Q2, pq = r % Q2;
+  const int d = f >> 1, s = f & 1;
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const int c[3] = {static_cast<int>(cell % nx), static_cast<int>((cell / nx) % ny),
+                    static_cast<int>(cell / (static_cast<int64_t>(nx) * ny))};
+  const double* val[3];
+  const double* der[3];
+  val[d] = t.E + s * N;
+  der[d] = t.Gd + s * N;
+  val[t1] = t.S + (pq % Q) * N;
+  der[t1] = t.D + (pq % Q) * N;
+  val[t2] = t.S + (pq / Q) * N;
+  der[t2] = t.D + (pq / Q) * N;
+  double J[9], nr[3];
+  curv_jac_at<N>(m, c, val, der, J);
+  adj_row(J, d, nr);
+  const double det = J[d] * nr[0] + J[3 + d] * nr[1] + J[6 + d] * nr[2];
+  const double wt = (det < 0.0 ? -1.0 : 1.0) * t.w[pq % Q] * t.w[pq / Q];
+  double* out = fmet + (cell * 18 + f * 3) * Q2 + pq;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) out[b * Q2] = wt * nr[b];
+}
+
+template <int N, int Q>
+dgmf_status launch_fill_nq(const CurvMap& m, int nx, int ny, int64_t ncells, const FillTabs& t, double* cmet,
+                           double* fmet, hipStream_t s) {
+  const int64_t nc = ncells * Q * Q * Q, nf = ncells * 6 * Q * Q;
+  if ((nc + 255) / 256 > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
+  hipLaunchKernelGGL((k_conv_fill_cells<N, Q>), dim3(static_cast<unsigned>((nc + 255) / 256)), dim3(256), 0, s, m,
+                     nx, ny, ncells, t, cmet);
+  DGMF_LAUNCH_CHECK("k_conv_fill_cells");
+  hipLaunchKernelGGL((k_conv_fill_faces<N, Q>), dim3(static_cast<unsigned>((nf + 255) / 256)), dim3(256), 0, s, m,
+                     nx, ny, ncells, t, fmet);
+  DGMF_LAUNCH_CHECK("k_conv_fill_faces");
+  return DGMF_OK;
+}
+
 template <int N, int Q>
 dgmf_status launch_fwd_nq(const ConvGeom& g, const double* U, double* C, int64_t ncells, bool step, double dt,
                           hipStream_t s) {
   if (ncells > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
+  const bool curv = g.cmet != nullptr;
+  if (curv && step) return fail(DGMF_UNSUPPORTED, "convective substep: curved cells are not supported");
   if (step)
-    hipLaunchKernelGGL((k_conv_fwd<N, Q, true>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0,
-                       s, U, C, g, ncells, dt);
+    hipLaunchKernelGGL((k_conv_fwd<N, Q, true, false>), dim3(static_cast<unsigned>(ncells)),
+                       dim3(CShape<N, Q>::THREADS), 0, s, U, C, g, ncells, dt);
+  else if (curv)
+    hipLaunchKernelGGL((k_conv_fwd<N, Q, false, true>), dim3(static_cast<unsigned>(ncells)),
+                       dim3(CShape<N, Q>::THREADS), 0, s, U, C, g, ncells, dt);
   else
-    hipLaunchKernelGGL((k_conv_fwd<N, Q, false>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0,
-                       s, U, C, g, ncells, dt);
+    hipLaunchKernelGGL((k_conv_fwd<N, Q, false, false>), dim3(static_cast<unsigned>(ncells)),
+                       dim3(CShape<N, Q>::THREADS), 0, s, U, C, g, ncells, dt);
   DGMF_LAUNCH_CHECK("k_conv_fwd");
   return DGMF_OK;
 }
@@ -711,8 +876,12 @@ template <int N, int Q>
 dgmf_status launch_vjp_nq(const ConvGeom& g, const double* U, const double* W, double* G, int64_t ncells,
                           hipStream_t s) {
   if (ncells > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
-  hipLaunchKernelGGL((k_conv_vjp<N, Q>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0, s, U,
-                     W, G, g, ncells);
+  if (g.cmet != nullptr)
+    hipLaunchKernelGGL((k_conv_vjp<N, Q, true>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0,
+                       s, U, W, G, g, ncells);
+  else
+    hipLaunchKernelGGL((k_conv_vjp<N, Q, false>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, Q>::THREADS), 0,
+                       s, U, W, G, g, ncells);
   DGMF_LAUNCH_CHECK("k_conv_vjp");
   return DGMF_OK;
 }
@@ -742,6 +911,26 @@ dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, d
 dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
                             int64_t ncells, hipStream_t s) {
 #define X(a, b) if (n == a && nq == b) return launch_vjp_nq<a, b>(g, U, W, G, ncells, s);
+  DGMF_CONV_CASES(X)
+#undef X
+  return fail(DGMF_UNSUPPORTED, "convective: (n, n_q) = (%d, %d) not built", n, nq);
+}
+
+dgmf_status launch_conv_fill_curved(int n, int nq, const double* const x0[3], const double* const h[3],
+                                    const double lo[3], const double len[3], double amp, int nx, int ny,
+                                    int64_t ncells, const double* tab, const int off[6], double* cmet, double* fmet,
+                                    hipStream_t s) {
+  CurvMap m{};
+  for (int d = 0; d < 3; ++d) {
+    m.x0[d] = x0[d];
+    m.h[d] = h[d];
+    m.lo[d] = lo[d];
+    m.len[d] = len[d];
+  }
+  m.amp = amp;
+  m.nodes = tab + off[0];
+  const FillTabs t{tab + off[1], tab + off[2], tab + off[3], tab + off[4], tab + off[5]};
+#define X(a, b) if (n == a && nq == b) return launch_fill_nq<a, b>(m, nx, ny, ncells, t, cmet, fmet, s);
   DGMF_CONV_CASES(X)
 #undef X
   return fail(DGMF_UNSUPPORTED, "convective: (n, n_q) = (%d, %d) not built", n, nq);

@@ -38,8 +38,14 @@ struct ConvGeom {
   int neu;             // bit 2d+s: the boundary side (d, s) is an outflow (Neumann) side
   const double* h[3];
   const double* hinv[3];
-  const double* tab;   // S[nq*n], D[nq*n], w[nq], Mh^{-1}[n*n] (k+1-point 1D mass, inverted)
+  const double* tab;   // S[nq*n], D[nq*n], w[nq], Mh^{-1}[n*n] (k+1-point 1D mass, inverted), GLL nodes[n]
   int S, D, w, Mi;     // offsets into tab
+  // curved cells (both null on affine meshes): per quadrature point
+  //   cmet[cell][3e+b][q]   = w_q adj(J)_eb  (q = (qz nq + qy) nq + qx)
+  //   fmet[cell][3f+r][pq]  = w_q1 w_q2 (adj J)_{d r} on face f = 2d+s, normal along +xi_d
+  //                          (pq = q2 nq + q1; t1 = y for d = 0 else x, t2 = y for d = 2 else z)
+  const double* cmet;
+  const double* fmet;
 };
 
 // ---------------------------------------------------------------- errors ---
@@ -225,6 +231,12 @@ dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, d
                             bool step, double dt, hipStream_t s);
 dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
                             int64_t ncells, hipStream_t s);
+// curved-cell metric of the convective operator (ConvGeom::cmet, fmet); off:
+// offsets into tab of the GLL nodes, S, D, the Gauss weights, l(0) l(1), l'(0) l'(1)
+dgmf_status launch_conv_fill_curved(int n, int nq, const double* const x0[3], const double* const h[3],
+                                    const double lo[3], const double len[3], double amp, int nx, int ny,
+                                    int64_t ncells, const double* tab, const int off[6], double* cmet, double* fmet,
+                                    hipStream_t s);
 
 // dst = M^{-1} src or dst = M src on nfields consecutive scalar fields of a
 // curved mesh, with the per-point weights m_q = w_q det J_q of the stored cell
@@ -360,6 +372,7 @@ struct dgmf_op_ {
   dgmf::CartGeom<double> g64{};
   dgmf::CartGeom<float> g32{};
   dgmf::DevBuf ctab;               // convective tables
+  dgmf::DevBuf cmet;               // convective metric of curved cells (cell part, then face part)
   dgmf::ConvGeom cgeo{};
   dgmf::MetricGeom<double> mg64{};   // metric path (mesh->desc.store_qp_metric)
   dgmf::MetricGeom<float> mg32{};

@@ -22,6 +22,7 @@
 // Own face traces are extrapolated from the Gauss-point data along the normal
 // lines and the face terms are injected back into the point fluxes, so the
 // transposed cell sweeps lift cell and face terms together.
+#include "curv_map.h"
 #include "internal.h"
 
 namespace dgmf {
@@ -613,20 +614,12 @@ __global__ void __launch_bounds__(256) k_metric_fill_faces(FillArgs a, double* f
   }
 }
 
-// Curved (iso-parametric) geometry fill.  The cell map is the degree-k tensor
-// interpolant, at the cell's GLL nodes, of the box deformation
-//   x_r = p_r + amp L_r prod_{e != r} sin(2 pi (p_e - lo_e) / L_e);
-// the interpolant of the affine part is exact and the product separates, so
-//   x_h,r(xi) = x0_r + h_r xi_r + amp L_r prod_{e != r} sig_e(xi_e),
-//   sig_e(t) = sum_i sin(2 pi (x0_e + h_e xi_i - lo_e) / L_e) l_i(t),
-// and J_rd = h_r delta_rd + (r != d) amp L_r sig_d'(xi_d) sig_e'(xi_e') with e'
-// the third direction (no derivative on it).  ctab: GLL nodes, S and D rows at
-// the Gauss points, l(0), l(1), l'(0), l'(1), Gauss weights (n each / n x n).
+// Curved (iso-parametric) geometry fill, with the closed-form Jacobian of
+// curv_map.h.  ctab: GLL nodes, S and D rows at the Gauss points, l(0), l(1),
+// l'(0), l'(1), Gauss weights (n each / n x n).
 struct CurvArgs {
   MetricGeom<double> g;
-  const double* x0[3];
-  const double* h[3];
-  double lo[3], len[3], amp;
+  CurvMap map;
   double k1sq;
   const double* ctab;
   const double* taue;   // per-cell (k+1)^2 (A_int/2 + A_bnd) / V (faces kernel)
@@ -642,40 +635,11 @@ struct CurvTabs {
   __device__ const double* W(const double* t) const { return t + 5 * n + 2 * n * n; }
 };
 
-// sig and sig' of direction e of cell coordinate ce at the point with row values val, der
-template <int N>
-__device__ __forceinline__ void curv_sig(const CurvArgs& a, int e, int ce, const double* val, const double* der,
-                                         double& sg, double& dsg) {
-  const double* nodes = a.ctab;
-  const double x0 = a.x0[e][ce], h = a.h[e][ce];
-  sg = 0.0;
-  dsg = 0.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const double sv = sin(2.0 * M_PI * (x0 + h * nodes[i] - a.lo[e]) / a.len[e]);
-    sg = fma(sv, val[i], sg);
-    dsg = fma(sv, der[i], dsg);
-  }
-}
-
 // J (row-major J[r*3+d]) of cell c at the reference point whose per-direction rows are (val[e], der[e])
 template <int N>
 __device__ __forceinline__ void curv_jac(const CurvArgs& a, const int c[3], const double* const val[3],
                                          const double* const der[3], double J[9]) {
-  double sg[3], dsg[3];
-#pragma unroll
-  for (int e = 0; e < 3; ++e) curv_sig<N>(a, e, c[e], val[e], der[e], sg[e], dsg[e]);
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (r == d) {
-        J[r * 3 + d] = a.h[r][c[r]];
-      } else {
-        const int e = 3 - r - d;
-        J[r * 3 + d] = a.amp * a.len[r] * dsg[d] * sg[e];
-      }
-    }
+  curv_jac_at<N>(a.map, c, val, der, J);
 }
 
 __device__ __forceinline__ double inv3(const double J[9], double Ji[9]) {
@@ -956,12 +920,13 @@ dgmf_status launch_metric_fill_curved(int n, const MetricGeom<double>& g, const 
   CurvArgs a{};
   a.g = g;
   for (int d = 0; d < 3; ++d) {
-    a.x0[d] = x0[d];
-    a.h[d] = h[d];
-    a.lo[d] = lo[d];
-    a.len[d] = len[d];
+    a.map.x0[d] = x0[d];
+    a.map.h[d] = h[d];
+    a.map.lo[d] = lo[d];
+    a.map.len[d] = len[d];
   }
-  a.amp = amp;
+  a.map.amp = amp;
+  a.map.nodes = ctab;
   a.k1sq = static_cast<double>(n) * n;
   a.ctab = ctab;
   a.taue = taue;
