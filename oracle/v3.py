@@ -13,7 +13,11 @@ Sec. 4.2, variants V3a and V3c, and Sec. 4 (matrix formulation):
 * local projection (eq. project, V3: tau_C = 0): per cell
   (M_e + tau_D,e D_e) u = rhs_e, solved here by a dense solve.
 All integrals by Gauss quadrature with k+1 points per direction (exact on
-affine cells), built from dense Kronecker-product evaluation matrices.
+affine cells), built from dense Kronecker-product evaluation matrices.  On
+curved (iso-parametric) cells, Sec. 5, A and B take the Jacobian of the cell
+map at every cell and face quadrature point (normals and surface measures by
+Nanson's formula); there the k+1-point rule defines the operators, and a
+larger ``nq`` is available for the pins that need exact integration.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -31,63 +35,108 @@ def _cell_grad(T, J):
     return grad, Phi, w
 
 
+def _curved(m):
+    return hasattr(m, "jac_at")
+
+
+def _tables(m, nq):
+    return sipg.Tables(m.k) if nq is None else sipg.Tables(m.k, nq)
+
+
+def _cell_geo(T, m, c):
+    """(grad, Phi, w) of cell c: per-point Jacobians on curved cells."""
+    if not _curved(m):
+        return _cell_grad(T, m.jacobian(c))
+    Z, Y, X = np.meshgrid(T.xq, T.xq, T.xq, indexing="ij")
+    J = m.jac_at(c, np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
+    Jinv = np.linalg.inv(J)
+    G = sipg._ref_gradients_cell(T)
+    grad = [sum(Jinv[:, b, a][:, None] * G[b] for b in range(3)) for a in range(3)]
+    w = sipg._kron3(T.wq, T.wq, T.wq) * np.abs(np.linalg.det(J))
+    return grad, sipg._kron3(T.S, T.S, T.S), w
+
+
+def _face_geo(T, m, c, f):
+    """(Tr, dA, nrm) of face f of cell c: traces at the face points, surface
+    weights, and unit normals towards +d, one row per point (mq, 3)."""
+    if not _curved(m):
+        Tr, _, dA, nrm = sipg.face_eval(T, m.jacobian(c), f)
+        return Tr, dA, np.repeat(np.asarray(nrm)[None, :], dA.size, axis=0)
+    d, s = divmod(f, 2)
+    val = [T.S, T.S, T.S]
+    val[d] = T.e[s]
+    Tr = sipg._kron3(val[2], val[1], val[0])
+    t = [T.xq, T.xq, T.xq]
+    t[d] = np.array([float(s)])
+    Z, Y, X = np.meshgrid(t[2], t[1], t[0], indexing="ij")
+    wt = [T.wq, T.wq, T.wq]
+    wt[d] = np.ones(1)
+    J = m.jac_at(c, np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
+    mv = np.linalg.inv(J)[:, d, :]                   # J^{-T} e_d per point
+    mn = np.linalg.norm(mv, axis=1)
+    dA = sipg._kron3(wt[2], wt[1], wt[0]) * np.abs(np.linalg.det(J)) * mn
+    return Tr, dA, mv / mn[:, None]
+
+
 def _faces(m):
     """Interior faces (cL, cR, d) and boundary faces (c, f), Dirichlet and Neumann alike:
     the ND average is the own trace on both boundary parts (Sec. 3.1)."""
     return m.interior_faces(), sorted(m.boundary_faces() + m.neumann_faces())
 
 
-def divergence_matrix(m):
-    """A as a sparse (N x 3N) matrix acting on [u_x; u_y; u_z]."""
-    T = sipg.Tables(m.k)
+def divergence_matrix(m, nq=None):
+    """A as a sparse (N x 3N) matrix acting on [u_x; u_y; u_z]; nq points per
+    direction (default k+1)."""
+    T = _tables(m, nq)
     nb, N = m.n ** 3, m.ndofs
     A = sp.lil_matrix((N, 3 * N))
     loc = np.arange(nb)
     for c in range(m.ncells):
-        grad, Phi, w = _cell_grad(T, m.jacobian(c))
+        grad, Phi, w = _cell_geo(T, m, c)
         for a in range(3):
             A[np.ix_(c * nb + loc, a * N + c * nb + loc)] += grad[a].T @ (w[:, None] * Phi)
     inner, bnd = _faces(m)
     for cL, cR, d in inner:
-        TrL, _, dA, nrm = sipg.face_eval(T, m.jacobian(cL), 2 * d + 1)
-        TrR, _, _, _ = sipg.face_eval(T, m.jacobian(cR), 2 * d)
+        TrL, dA, nrm = _face_geo(T, m, cL, 2 * d + 1)
+        TrR = _face_geo(T, m, cR, 2 * d)[0]
         for a in range(3):
             for (ct, Trt, sgn) in ((cL, TrL, 1.0), (cR, TrR, -1.0)):   # outward normal sgn * nrm
                 for (cu, Tru) in ((cL, TrL), (cR, TrR)):
-                    blk = -sgn * 0.5 * nrm[a] * (Trt.T @ (dA[:, None] * Tru))
+                    blk = -sgn * 0.5 * (Trt.T @ ((dA * nrm[:, a])[:, None] * Tru))
                     A[np.ix_(ct * nb + loc, a * N + cu * nb + loc)] += blk
     for c, f in bnd:
-        Tr, _, dA, nrm = sipg.face_eval(T, m.jacobian(c), f)
+        Tr, dA, nrm = _face_geo(T, m, c, f)
         sgn = 1.0 if f % 2 == 1 else -1.0
         for a in range(3):
-            A[np.ix_(c * nb + loc, a * N + c * nb + loc)] += -sgn * nrm[a] * (Tr.T @ (dA[:, None] * Tr))
+            A[np.ix_(c * nb + loc, a * N + c * nb + loc)] += -sgn * (Tr.T @ ((dA * nrm[:, a])[:, None] * Tr))
     return A.tocsr()
 
 
-def gradient_matrix(m):
-    """B as a sparse (3N x N) matrix, output [B_x; B_y; B_z]."""
-    T = sipg.Tables(m.k)
+def gradient_matrix(m, nq=None):
+    """B as a sparse (3N x N) matrix, output [B_x; B_y; B_z]; nq points per
+    direction (default k+1)."""
+    T = _tables(m, nq)
     nb, N = m.n ** 3, m.ndofs
     B = sp.lil_matrix((3 * N, N))
     loc = np.arange(nb)
     for c in range(m.ncells):
-        grad, Phi, w = _cell_grad(T, m.jacobian(c))
+        grad, Phi, w = _cell_geo(T, m, c)
         for a in range(3):
             B[np.ix_(a * N + c * nb + loc, c * nb + loc)] += grad[a].T @ (w[:, None] * Phi)
     inner, bnd = _faces(m)
     for cL, cR, d in inner:
-        TrL, _, dA, nrm = sipg.face_eval(T, m.jacobian(cL), 2 * d + 1)
-        TrR, _, _, _ = sipg.face_eval(T, m.jacobian(cR), 2 * d)
+        TrL, dA, nrm = _face_geo(T, m, cL, 2 * d + 1)
+        TrR = _face_geo(T, m, cR, 2 * d)[0]
         for a in range(3):
             for (ct, Trt, sgn) in ((cL, TrL, 1.0), (cR, TrR, -1.0)):
                 for (cp, Trp) in ((cL, TrL), (cR, TrR)):
-                    blk = -sgn * 0.5 * nrm[a] * (Trt.T @ (dA[:, None] * Trp))
+                    blk = -sgn * 0.5 * (Trt.T @ ((dA * nrm[:, a])[:, None] * Trp))
                     B[np.ix_(a * N + ct * nb + loc, cp * nb + loc)] += blk
     for c, f in bnd:
-        Tr, _, dA, nrm = sipg.face_eval(T, m.jacobian(c), f)
+        Tr, dA, nrm = _face_geo(T, m, c, f)
         sgn = 1.0 if f % 2 == 1 else -1.0
         for a in range(3):
-            B[np.ix_(a * N + c * nb + loc, c * nb + loc)] += -sgn * nrm[a] * (Tr.T @ (dA[:, None] * Tr))
+            B[np.ix_(a * N + c * nb + loc, c * nb + loc)] += -sgn * (Tr.T @ ((dA * nrm[:, a])[:, None] * Tr))
     return B.tocsr()
 
 

@@ -1,0 +1,85 @@
+"""Pins of the oracle's divergence A and gradient B (variant V3c) on curved cells.
+
+Sec. 4.2 (eqs. av3, bv3) with the curved iso-parametric cells of Sec. 5.
+Fixed by facts outside the oracle:
+  - zero amplitude gives the affine operators (pinned separately);
+  - with enough points to integrate exactly (the cofactors of J have degree
+    <= 2k per reference direction): A and B annihilate constants on a
+    periodic curved mesh (3k per direction, n_q >= (3k+1)/2), and A = -B^T
+    there (integration by parts of div(p u), 4k per direction,
+    n_q >= (4k+1)/2) -- a wrong cofactor, a transposed inverse or a normal
+    of the wrong size breaks these;
+  - with the defining k+1 points, A applied to the interpolant of a smooth
+    periodic field tends to -(phi_i, div u) at a rate that rises with the
+    degree.
+"""
+import numpy as np
+import pytest
+
+from oracle import curved, mesh as omesh, sipg, v3
+import dgmf_inputs as inp
+
+
+def test_zero_amplitude_is_the_affine_operator():
+    kw = dict(lx=2.0, ly=2.0, lz=1.0, y0=-1.0, periodic=(True, False, False), y_tanh_gamma=1.3,
+              neumann=(False, False, False, False, True, False))
+    cm = curved.CurvedBoxMesh(2, 2, 3, 2, amp=0.0, **kw)
+    am = omesh.BoxMesh(2, 2, 3, 2, **kw)
+    for f in (v3.divergence_matrix, v3.gradient_matrix):
+        A, B = f(cm), f(am)
+        assert abs(A - B).max() <= 1e-13 * abs(B).max()
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_exact_quadrature_identities_on_a_periodic_curved_mesh(k):
+    m = curved.CurvedBoxMesh(k, 2, 3, 2, amp=0.07, periodic=(True, True, True))
+    N = m.ndofs
+    nq = 2 * k + 1
+    A = v3.divergence_matrix(m, nq=nq)
+    B = v3.gradient_matrix(m, nq=nq)
+    one = np.ones(N)
+    for a in range(3):
+        u = np.zeros(3 * N)
+        u[a * N:(a + 1) * N] = 1.0
+        assert np.abs(A @ u).max() < 1e-13 * abs(A).max()
+    assert np.abs(B @ one).max() < 1e-13 * abs(B).max()
+    assert abs(A + B.T).max() < 1e-13 * abs(A).max()
+    # with the defining k+1 points neither identity is exact on curved cells
+    A1 = v3.divergence_matrix(m)
+    assert abs(A1 + v3.gradient_matrix(m).T).max() > 1e-8 * abs(A1).max()
+
+
+def _u(x, y, z):
+    tp = 2 * np.pi
+    return np.stack([np.sin(tp * y) * np.cos(tp * z) + np.sin(tp * x),
+                     np.sin(tp * z) + 0.2 * np.cos(tp * y),
+                     np.cos(tp * x) * np.sin(tp * z)])
+
+
+def _div_u(x, y, z):
+    tp = 2 * np.pi
+    return tp * np.cos(tp * x) - 0.2 * tp * np.sin(tp * y) + tp * np.cos(tp * x) * np.cos(tp * z)
+
+
+def _consistency_error(k, nc):
+    m = curved.CurvedBoxMesh(k, nc, nc, nc, amp=0.06, periodic=(True, True, True))
+    X = np.concatenate([m.node_xyz(c) for c in range(m.ncells)])
+    U = np.asarray(_u(X[:, 0], X[:, 1], X[:, 2])).ravel()
+    Au = (v3.divergence_matrix(m) @ U).reshape(m.ncells, -1)
+    T = sipg.Tables(k)
+    Z, Y, Xg = np.meshgrid(T.xq, T.xq, T.xq, indexing="ij")
+    xi = np.stack([Xg.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    Phi = sipg._kron3(T.S, T.S, T.S)
+    wq = sipg._kron3(T.wq, T.wq, T.wq)
+    ref = np.empty_like(Au)
+    for c in range(m.ncells):
+        xq = m.map_at(c, xi)
+        w = wq * np.abs(np.linalg.det(m.jac_at(c, xi)))
+        ref[c] = -Phi.T @ (w * _div_u(xq[:, 0], xq[:, 1], xq[:, 2]))
+    return np.linalg.norm(Au - ref) / np.linalg.norm(ref)
+
+
+def test_divergence_consistency_with_the_continuous_operator():
+    e2 = _consistency_error(3, 2)
+    e4 = _consistency_error(3, 4)
+    assert e4 < 0.2 * e2 and e4 < 0.02
