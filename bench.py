@@ -308,8 +308,9 @@ def curved_measurements(dg, inp, torch, w, tag):
     """Channel Helmholtz on iso-parametric curved cells: metric set-up, apply (fp64,
     fp32; the stored-metric kernel, same algorithmic bytes as on affine cells), and
     PCG to 1e-10 on a random right-hand side (mixed fp32 Chebyshev, fp64 Jacobi);
-    then the convective operator and its VJP on the same cells (the per-point
-    metric filled at create; U = (1, 0, 0) + 0.05 uniform[-1, 1])."""
+    then the convective operator and its VJP, and the V3c divergence and
+    gradient, on the same cells (per-point metrics; U = (1, 0, 0) + 0.05
+    uniform[-1, 1])."""
     ex = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -354,6 +355,17 @@ def curved_measurements(dg, inp, torch, w, tag):
     tf = _events_time(lambda: opc.apply(U, Cout), 10, 2)
     tv = _events_time(lambda: opc.vjp(U, Wc, Gout), 10, 2)
     met = m.ncells * 8 * (9 * nq ** 3 + 18 * nq ** 2)     # per-point metric read once per launch
+    # V3c divergence and gradient (first call fills their metric at k+1 points)
+    P = U[:N].clone()
+    out1 = torch.empty(N, dtype=torch.float64, device="cuda")
+    m.divergence(U, out1)
+    torch.cuda.synchronize()
+    td = _events_time(lambda: m.divergence(U, out1), 20, 3)
+    tg = _events_time(lambda: m.gradient(P, Cout), 20, 3)
+    qmet = m.ncells * 8 * (9 * n ** 3 + 18 * n ** 2)
+    ex[f"{tag}_divergence"] = {"us": td * 1e6, "metric_bytes": qmet,
+                               "hbm_frac": (32.0 * N + qmet) / td / 1e9 / HBM_PEAK_GBS}
+    ex[f"{tag}_gradient"] = {"us": tg * 1e6, "hbm_frac": (32.0 * N + qmet) / tg / 1e9 / HBM_PEAK_GBS}
     ex[f"{tag}_convective"] = {"create_s": tc, "fwd_us": tf * 1e6, "vjp_us": tv * 1e6,
                                "fwd_dofs_per_s": 3 * N / tf, "vjp_dofs_per_s": 3 * N / tv,
                                "fwd_plus_vjp_dofs_per_s": 3 * N / (tf + tv), "dofs": 3 * N, "n_q": nq,

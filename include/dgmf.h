@@ -110,10 +110,11 @@ int dgmf_version(void);
  * operator, its diagonal, CG with every preconditioner (multigrid keeps the
  * curved operator on the finest level and rediscretises the coarse levels on
  * the undeformed box), the mass matrix and its inverse (with the point
- * weights w_q det J_q), and the convective operator and its VJP (with the
- * Jacobian at every quadrature point); every other operator (and the fused
- * convective substep, coordinates, load vectors) returns DGMF_UNSUPPORTED on
- * them.
+ * weights w_q det J_q), the convective operator and its VJP, and the V3c
+ * divergence and gradient (with the Jacobian at every quadrature point);
+ * every other operator (the fused convective substep, the div-div penalty
+ * and projection, the symmetric-gradient viscous operator, coordinates, load
+ * vectors) returns DGMF_UNSUPPORTED on them.
  * degree k in 1..7; every cell count >= 1; lengths > 0. */
 typedef struct {
   int degree;
@@ -162,11 +163,17 @@ dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, cons
  * fields, [N] for scalar fields, [n_cells] for per-cell values. */
 /* out = A u, the divergence of eq. av3 without the factor gamma_0/dt:
  * (A u)_i = sum_K (grad phi_i, u)_K - (phi_i, {{u}}.n)_dK.  u [3][N],
- * out [N]; must not overlap.  Asynchronous. */
+ * out [N]; must not overlap.  Asynchronous, except that on a mesh with
+ * curved cells the first call of this or dgmf_gradient_apply fills (on the
+ * device, synchronously) a per-point metric of 8 (9 n^3 + 18 n^2) bytes per
+ * cell, n = k+1, held by the mesh: there both operators integrate with k+1
+ * Gauss points per direction and the Jacobian at every point. */
 dgmf_status dgmf_divergence_apply(dgmf_mesh mesh, const double* u, double* out, hipStream_t stream);
 /* out = B p, the gradient of eq. bv3 without the factor dt/gamma_0:
  * (B p)_{i,a} = sum_K (d_a phi_i, p)_K - (phi_i, {{p}} n_a)_dK.  p [N],
- * out [3][N]; must not overlap.  On periodic meshes B = -A^T.  Asynchronous. */
+ * out [3][N]; must not overlap.  On periodic affine meshes B = -A^T (on
+ * curved cells only up to the quadrature error).  Asynchronous, with the
+ * first-call metric fill on curved meshes as for dgmf_divergence_apply. */
 dgmf_status dgmf_gradient_apply(dgmf_mesh mesh, const double* p, double* out, hipStream_t stream);
 /* tau[c] = zeta |u_bar_c| V_c^(1/3) dt (eq. tauD), u_bar_c the volume average
  * of the velocity u [3][N] on cell c; zeta, dt finite and >= 0 (the paper

@@ -84,17 +84,33 @@ def _faces(m):
     return m.interior_faces(), sorted(m.boundary_faces() + m.neumann_faces())
 
 
+class _Blocks:
+    """Dense blocks added at (row offset, column offset), summed into a sparse matrix."""
+
+    def __init__(self, shape):
+        self.shape, self.r, self.c, self.v = shape, [], [], []
+
+    def add(self, r0, c0, blk):
+        rr, cc = np.meshgrid(r0 + np.arange(blk.shape[0]), c0 + np.arange(blk.shape[1]), indexing="ij")
+        self.r.append(rr.ravel())
+        self.c.append(cc.ravel())
+        self.v.append(blk.ravel())
+
+    def tocsr(self):
+        return sp.coo_matrix((np.concatenate(self.v), (np.concatenate(self.r), np.concatenate(self.c))),
+                             shape=self.shape).tocsr()
+
+
 def divergence_matrix(m, nq=None):
     """A as a sparse (N x 3N) matrix acting on [u_x; u_y; u_z]; nq points per
     direction (default k+1)."""
     T = _tables(m, nq)
     nb, N = m.n ** 3, m.ndofs
-    A = sp.lil_matrix((N, 3 * N))
-    loc = np.arange(nb)
+    A = _Blocks((N, 3 * N))
     for c in range(m.ncells):
         grad, Phi, w = _cell_geo(T, m, c)
         for a in range(3):
-            A[np.ix_(c * nb + loc, a * N + c * nb + loc)] += grad[a].T @ (w[:, None] * Phi)
+            A.add(c * nb, a * N + c * nb, grad[a].T @ (w[:, None] * Phi))
     inner, bnd = _faces(m)
     for cL, cR, d in inner:
         TrL, dA, nrm = _face_geo(T, m, cL, 2 * d + 1)
@@ -103,12 +119,12 @@ def divergence_matrix(m, nq=None):
             for (ct, Trt, sgn) in ((cL, TrL, 1.0), (cR, TrR, -1.0)):   # outward normal sgn * nrm
                 for (cu, Tru) in ((cL, TrL), (cR, TrR)):
                     blk = -sgn * 0.5 * (Trt.T @ ((dA * nrm[:, a])[:, None] * Tru))
-                    A[np.ix_(ct * nb + loc, a * N + cu * nb + loc)] += blk
+                    A.add(ct * nb, a * N + cu * nb, blk)
     for c, f in bnd:
         Tr, dA, nrm = _face_geo(T, m, c, f)
         sgn = 1.0 if f % 2 == 1 else -1.0
         for a in range(3):
-            A[np.ix_(c * nb + loc, a * N + c * nb + loc)] += -sgn * (Tr.T @ ((dA * nrm[:, a])[:, None] * Tr))
+            A.add(c * nb, a * N + c * nb, -sgn * (Tr.T @ ((dA * nrm[:, a])[:, None] * Tr)))
     return A.tocsr()
 
 
@@ -117,12 +133,11 @@ def gradient_matrix(m, nq=None):
     direction (default k+1)."""
     T = _tables(m, nq)
     nb, N = m.n ** 3, m.ndofs
-    B = sp.lil_matrix((3 * N, N))
-    loc = np.arange(nb)
+    B = _Blocks((3 * N, N))
     for c in range(m.ncells):
         grad, Phi, w = _cell_geo(T, m, c)
         for a in range(3):
-            B[np.ix_(a * N + c * nb + loc, c * nb + loc)] += grad[a].T @ (w[:, None] * Phi)
+            B.add(a * N + c * nb, c * nb, grad[a].T @ (w[:, None] * Phi))
     inner, bnd = _faces(m)
     for cL, cR, d in inner:
         TrL, dA, nrm = _face_geo(T, m, cL, 2 * d + 1)
@@ -131,12 +146,12 @@ def gradient_matrix(m, nq=None):
             for (ct, Trt, sgn) in ((cL, TrL, 1.0), (cR, TrR, -1.0)):
                 for (cp, Trp) in ((cL, TrL), (cR, TrR)):
                     blk = -sgn * 0.5 * (Trt.T @ ((dA * nrm[:, a])[:, None] * Trp))
-                    B[np.ix_(a * N + ct * nb + loc, cp * nb + loc)] += blk
+                    B.add(a * N + ct * nb, cp * nb, blk)
     for c, f in bnd:
         Tr, dA, nrm = _face_geo(T, m, c, f)
         sgn = 1.0 if f % 2 == 1 else -1.0
         for a in range(3):
-            B[np.ix_(a * N + c * nb + loc, c * nb + loc)] += -sgn * (Tr.T @ ((dA * nrm[:, a])[:, None] * Tr))
+            B.add(a * N + c * nb, c * nb, -sgn * (Tr.T @ ((dA * nrm[:, a])[:, None] * Tr)))
     return B.tocsr()
 
 

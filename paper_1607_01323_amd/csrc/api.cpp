@@ -653,10 +653,65 @@ dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, cons
 
 // Neumann sides need no check here: the ND average is the own trace on both
 // boundary parts (A, B), and the viscous coupling kernel skips Neumann faces.
-static dgmf_status v3_check(dgmf_mesh mesh, const char* who) {
+static dgmf_status v3_check(dgmf_mesh mesh, const char* who, bool curved_ok = false) {
   if (!mesh) return fail(DGMF_INVALID, "%s: null mesh", who);
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "%s: sheared meshes are not supported", who);
-  if (dgmf_status e = flat_check(mesh, who)) return e;
+  if (!curved_ok)
+    if (dgmf_status e = flat_check(mesh, who)) return e;
+  return DGMF_OK;
+}
+
+// Curved cells: tables and per-point metric of the divergence and gradient at
+// n_q = k+1 points, built (synchronously, on the null stream) on first use.
+static dgmf_status curved_v3_geometry(dgmf_mesh mesh) {
+  if (mesh->qgeo.cmet) return DGMF_OK;
+  const int n = mesh->tab.n, nq = n;
+  const dgmf::Tables1D& t = mesh->tab;
+  std::vector<double> h;
+  h.insert(h.end(), t.S.begin(), t.S.end());
+  h.insert(h.end(), t.D.begin(), t.D.end());
+  h.insert(h.end(), t.wq.begin(), t.wq.end());
+  const int o_nodes = static_cast<int>(h.size());
+  h.insert(h.end(), t.nodes.begin(), t.nodes.end());
+  const int o_e = static_cast<int>(h.size());
+  h.resize(h.size() + 2 * n, 0.0);
+  h[o_e] = 1.0;
+  h[o_e + 2 * n - 1] = 1.0;
+  const int o_g = static_cast<int>(h.size());
+  h.insert(h.end(), t.g0.begin(), t.g0.end());
+  h.insert(h.end(), t.g1.begin(), t.g1.end());
+  dgmf_status st;
+  if ((st = mesh->qtab.upload(h.data(), h.size() * sizeof(double)))) return st;
+  const int64_t nq2 = static_cast<int64_t>(nq) * nq, cper = 9 * nq2 * nq, fper = 18 * nq2;
+  if ((st = mesh->qmet.alloc(static_cast<size_t>(mesh->ncells * (cper + fper)) * sizeof(double)))) return st;
+  double* cm = static_cast<double*>(mesh->qmet.p);
+  const double* x0[3] = {mesh->g64.x0[0], mesh->g64.x0[1], mesh->g64.x0[2]};
+  const double* hh[3] = {mesh->g64.h[0], mesh->g64.h[1], mesh->g64.h[2]};
+  const double lo[3] = {0.0, mesh->desc.y0, 0.0};
+  const double len[3] = {mesh->desc.lx, mesh->desc.ly, mesh->desc.lz};
+  const int off[6] = {o_nodes, 0, nq * n, 2 * nq * n, o_e, o_g};
+  if ((st = launch_conv_fill_curved(n, nq, x0, hh, lo, len, mesh->desc.curve_amp, mesh->g64.nx, mesh->g64.ny,
+                                    mesh->ncells, static_cast<const double*>(mesh->qtab.p), off, cm,
+                                    cm + mesh->ncells * cper, nullptr)))
+    return st;
+  DGMF_HIP_TRY(hipStreamSynchronize(nullptr));
+  ConvGeom& g = mesh->qgeo;
+  g.nx = mesh->g64.nx;
+  g.ny = mesh->g64.ny;
+  g.nz = mesh->g64.nz;
+  g.neu = neumann_mask(mesh->desc);
+  for (int d = 0; d < 3; ++d) {
+    g.per[d] = mesh->g64.per[d];
+    g.h[d] = mesh->g64.h[d];
+    g.hinv[d] = mesh->g64.hinv[d];
+  }
+  g.tab = static_cast<const double*>(mesh->qtab.p);
+  g.S = 0;
+  g.D = nq * n;
+  g.w = 2 * nq * n;
+  g.Mi = -1;   // no inverse mass here
+  g.fmet = cm + mesh->ncells * cper;
+  g.cmet = cm;
   return DGMF_OK;
 }
 
@@ -676,25 +731,33 @@ dgmf_status dgmf_viscous_apply(dgmf_op op, const double* u, double* out, hipStre
 }
 
 dgmf_status dgmf_divergence_apply(dgmf_mesh mesh, const double* u, double* out, hipStream_t stream) {
-  dgmf_status e = v3_check(mesh, "divergence_apply");
+  dgmf_status e = v3_check(mesh, "divergence_apply", true);
   if (e) return e;
   if (!u || !out || !aligned(u, 8) || !aligned(out, 8))
     return fail(DGMF_INVALID, "divergence_apply: null or misaligned vector");
   if (overlap2(u, 24 * mesh->ndofs, out, 8 * mesh->ndofs))
     return fail(DGMF_INVALID, "divergence_apply: u and out overlap");
   DeviceGuard dg(mesh->device);
+  if (mesh->desc.curve_amp != 0.0) {
+    if ((e = curved_v3_geometry(mesh))) return e;
+    return launch_curv_v3(mesh->tab.n, false, mesh->qgeo, u, out, mesh->ncells, stream);
+  }
   return launch_v3_divergence(mesh->tab.n, mesh->g64, static_cast<const double*>(mesh->v3tab.p), u, out,
                               mesh->ncells, stream);
 }
 
 dgmf_status dgmf_gradient_apply(dgmf_mesh mesh, const double* p, double* out, hipStream_t stream) {
-  dgmf_status e = v3_check(mesh, "gradient_apply");
+  dgmf_status e = v3_check(mesh, "gradient_apply", true);
   if (e) return e;
   if (!p || !out || !aligned(p, 8) || !aligned(out, 8))
     return fail(DGMF_INVALID, "gradient_apply: null or misaligned vector");
   if (overlap2(p, 8 * mesh->ndofs, out, 24 * mesh->ndofs))
     return fail(DGMF_INVALID, "gradient_apply: p and out overlap");
   DeviceGuard dg(mesh->device);
+  if (mesh->desc.curve_amp != 0.0) {
+    if ((e = curved_v3_geometry(mesh))) return e;
+    return launch_curv_v3(mesh->tab.n, true, mesh->qgeo, p, out, mesh->ncells, stream);
+  }
   return launch_v3_gradient(mesh->tab.n, mesh->g64, static_cast<const double*>(mesh->v3tab.p), p, out, mesh->ncells,
                             stream);
 }

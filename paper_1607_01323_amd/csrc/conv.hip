@@ -94,13 +94,13 @@ __device__ __forceinline__ int face_node(int d, int s, int p1, int p2) {
   return (e * N + p2) * N + p1;                    // t1 = x, t2 = y
 }
 
-// Interpolate three nodal fields sIn[3][N^3] to the quadrature z-column of
-// this thread: out[a][qz].  T1 (3*N*N*Q) and T2 (3*N*Q*Q) are LDS scratch.
-template <int N, int Q>
+// Interpolate NC nodal fields sIn[NC][N^3] to the quadrature z-column of
+// this thread: out[a][qz].  T1 (NC*N*N*Q) and T2 (NC*N*Q*Q) are LDS scratch.
+template <int N, int Q, int NC = 3>
 __device__ __forceinline__ void interp3(const double* __restrict__ S, const double* sIn, double* T1, double* T2,
-                                        int tid, int nthr, bool own, int qx, int qy, double (&out)[3][Q]) {
+                                        int tid, int nthr, bool own, int qx, int qy, double (&out)[NC][Q]) {
   constexpr int N2 = N * N;
-  for (int job = tid; job < 3 * N2; job += nthr) {      // x: (a, l, j)
+  for (int job = tid; job < NC * N2; job += nthr) {     // x: (a, l, j)
     const double* in = sIn + job * N;
     double v[N];
 #pragma unroll
@@ -114,7 +114,7 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
     }
   }
   __syncthreads();
-  for (int job = tid; job < 3 * N * Q; job += nthr) {  // y: (a, l, qx)
+  for (int job = tid; job < NC * N * Q; job += nthr) {  // y: (a, l, qx)
     const int qxx = job % Q, al = job / Q;
     double v[N];
 #pragma unroll
@@ -130,20 +130,19 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
   __syncthreads();
   if (own) {                                            // z: registers, one table column per step
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < NC; ++a)
 #pragma unroll
       for (int q = 0; q < Q; ++q) out[a][q] = 0.0;
 #pragma unroll kSweepUnroll<N, Q>
     for (int l = 0; l < N; ++l) {
-      const double x0 = T2[((0 * N + l) * Q + qy) * Q + qx];
-      const double x1 = T2[((1 * N + l) * Q + qy) * Q + qx];
-      const double x2 = T2[((2 * N + l) * Q + qy) * Q + qx];
+      double xv[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) xv[a] = T2[((a * N + l) * Q + qy) * Q + qx];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const double c = S[q * N + l];
-        out[0][q] = fma(c, x0, out[0][q]);
-        out[1][q] = fma(c, x1, out[1][q]);
-        out[2][q] = fma(c, x2, out[2][q]);
+#pragma unroll
+        for (int a = 0; a < NC; ++a) out[a][q] = fma(c, xv[a], out[a][q]);
       }
     }
   }
@@ -218,6 +217,74 @@ __device__ __forceinline__ void face_lift(const double* __restrict__ S, const do
 #pragma unroll
       for (int q = 0; q < Q; ++q) s = fma(S[q * N + p1], v[q], s);
       o[face_node<N>(d, side, p1, p2)] += s;
+    }
+  }
+  __syncthreads();
+}
+
+// Transposed cell sweeps of one field against the reference gradients:
+//   dst[i] = sg * sum_q (d phi_i/dxi_x fx + d phi_i/dxi_y fy + d phi_i/dxi_z fz)
+// with fx, fy, fz the values at this thread's quadrature z-column (read by
+// owning threads only): z in registers (one node l per step, the S and D
+// columns of l only), then y and x through LDS.  A (3 N Q^2) and B (2 N^2 Q)
+// are LDS scratch; ends with a barrier.
+template <int N, int Q>
+__device__ __forceinline__ void cell_lift_grad(const double* __restrict__ S, const double* __restrict__ D,
+                                               const double (&fx)[Q], const double (&fy)[Q], const double (&fz)[Q],
+                                               bool own, int qx, int qy, double* A, double* B, double* dst,
+                                               double sg, int tid, int nthr) {
+  constexpr int N2 = N * N;
+  if (own) {
+#pragma unroll kSweepUnroll<N, Q>
+    for (int l = 0; l < N; ++l) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+      for (int qz = 0; qz < Q; ++qz) {
+        a0 = fma(S[qz * N + l], fx[qz], a0);
+        a1 = fma(S[qz * N + l], fy[qz], a1);
+        a2 = fma(D[qz * N + l], fz[qz], a2);
+      }
+      A[((0 * N + l) * Q + qy) * Q + qx] = a0;
+      A[((1 * N + l) * Q + qy) * Q + qx] = a1;
+      A[((2 * N + l) * Q + qy) * Q + qx] = a2;
+    }
+  }
+  __syncthreads();
+  for (int job = tid; job < N * Q; job += nthr) {       // y: (l, qx)
+    const int qxx = job % Q, l = job / Q;
+    double v1[Q], v2[Q], v3[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      v1[q] = A[((0 * N + l) * Q + q) * Q + qxx];
+      v2[q] = A[((1 * N + l) * Q + q) * Q + qxx];
+      v3[q] = A[((2 * N + l) * Q + q) * Q + qxx];
+    }
+#pragma unroll kSweepUnroll<N, Q>
+    for (int j = 0; j < N; ++j) {
+      double b1 = 0, b23 = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        b1 = fma(S[q * N + j], v1[q], b1);
+        b23 = fma(D[q * N + j], v2[q], fma(S[q * N + j], v3[q], b23));
+      }
+      B[(l * N + j) * Q + qxx] = b1;
+      B[N2 * Q + (l * N + j) * Q + qxx] = b23;
+    }
+  }
+  __syncthreads();
+  for (int job = tid; job < N2; job += nthr) {          // x: (l, j)
+    double v1[Q], v2[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      v1[q] = B[job * Q + q];
+      v2[q] = B[N2 * Q + job * Q + q];
+    }
+#pragma unroll kSweepUnroll<N, Q>
+    for (int i = 0; i < N; ++i) {
+      double s = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s = fma(D[q * N + i], v1[q], fma(S[q * N + i], v2[q], s));
+      dst[job * N + i] = sg * s;
     }
   }
   __syncthreads();
@@ -300,9 +367,9 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
+    double fx[Q], fy[Q], fz[Q];
     if (own) {
       const double wxy = w[qx] * w[qy] * vol;
-      double fx[Q], fy[Q], fz[Q];
 #pragma unroll
       for (int qz = 0; qz < Q; ++qz) {
         if constexpr (CURV) {
@@ -316,60 +383,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
           fz[qz] = f * u[2][qz] * cg.hinv[2];
         }
       }
-      // one node l per step: the S and D columns of l only
-#pragma unroll kSweepUnroll<N, Q>
-      for (int l = 0; l < N; ++l) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll
-        for (int qz = 0; qz < Q; ++qz) {
-          a0 = fma(S[qz * N + l], fx[qz], a0);
-          a1 = fma(S[qz * N + l], fy[qz], a1);
-          a2 = fma(D[qz * N + l], fz[qz], a2);
-        }
-        A[((0 * N + l) * Q + qy) * Q + qx] = a0;
-        A[((1 * N + l) * Q + qy) * Q + qx] = a1;
-        A[((2 * N + l) * Q + qy) * Q + qx] = a2;
-      }
     }
-    __syncthreads();
-    for (int job = tid; job < N * Q; job += nthr) {     // y: (l, qx)
-      const int qxx = job % Q, l = job / Q;
-      double v1[Q], v2[Q], v3[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        v1[q] = A[((0 * N + l) * Q + q) * Q + qxx];
-        v2[q] = A[((1 * N + l) * Q + q) * Q + qxx];
-        v3[q] = A[((2 * N + l) * Q + q) * Q + qxx];
-      }
-#pragma unroll kSweepUnroll<N, Q>
-      for (int j = 0; j < N; ++j) {
-        double b1 = 0, b23 = 0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          b1 = fma(S[q * N + j], v1[q], b1);
-          b23 = fma(D[q * N + j], v2[q], fma(S[q * N + j], v3[q], b23));
-        }
-        B[(l * N + j) * Q + qxx] = b1;
-        B[N2 * Q + (l * N + j) * Q + qxx] = b23;
-      }
-    }
-    __syncthreads();
-    for (int job = tid; job < N2; job += nthr) {        // x: (l, j)
-      double v1[Q], v2[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        v1[q] = B[job * Q + q];
-        v2[q] = B[N2 * Q + job * Q + q];
-      }
-#pragma unroll kSweepUnroll<N, Q>
-      for (int i = 0; i < N; ++i) {
-        double s = 0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) s = fma(D[q * N + i], v1[q], fma(S[q * N + i], v2[q], s));
-        sO[a * N3 + job * N + i] = -s;
-      }
-    }
-    __syncthreads();
+    cell_lift_grad<N, Q>(S, D, fx, fy, fz, own, qx, qy, A, B, sO + a * N3, -1.0, tid, nthr);
   }
   // faces, one direction at a time (the two faces of a direction touch disjoint node planes)
 #pragma unroll
@@ -766,6 +781,158 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   }
 }
 
+// ------------------------------------------ V3c divergence / gradient, curved
+// The divergence A (eq. av3) and gradient B (eq. bv3) of variant V3c on
+// curved cells, through the quadrature points with the per-point metric of
+// the fill below (n_q = k+1, the operators' own rule):
+//   (A u)_i     = sum_q sum_e dphi_i/dxi_e (w adj(J) u)_e   - sum_F sum_p phi_i {{u}} . nu
+//   (B p)_{i,a} = sum_q sum_e dphi_i/dxi_e (w adj(J))_{ea} p - sum_F sum_p phi_i {{p}} nu_a
+// nu the weighted outward normal, {{.}} the central average inside and the
+// own trace on boundary faces (Dirichlet and Neumann alike, Sec. 3.1).  One
+// cell per workgroup, the layout of the convective kernels.
+template <int N, int Q>
+__global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_div(const double* __restrict__ U,
+                                                                    double* __restrict__ out, const ConvGeom g,
+                                                                    int64_t ncells) {
+  using SH = CShape<N, Q>;
+  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
+  constexpr int XR = (3 * N2 * Q + 3 * N * Q2) > (3 * N * Q2 + 2 * N2 * Q) ? (3 * N2 * Q + 3 * N * Q2)
+                                                                              : (3 * N * Q2 + 2 * N2 * Q);
+  constexpr int XF = 6 * N2 + 6 * N * Q + 6 * Q2 + Q2;   // planes [own | ext][comp], stage, traces, flux
+  constexpr int X = XR > XF ? XR : XF;
+  __shared__ double sU[3 * N3];
+  __shared__ double sO[N3];
+  __shared__ double sX[X];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
+  if (cell >= ncells) return;
+  const int64_t Nd = ncells * N3;
+  const double* S = g.tab + g.S;
+  const double* D = g.tab + g.D;
+  CellGeo cg;
+  conv_cell(g, cell, cg);
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int a = e / N3, r = e % N3;
+    sU[e] = U[a * Nd + cell * N3 + r];
+  }
+  __syncthreads();
+  const bool own = tid < Q2;
+  const int qx = tid % Q, qy = (tid / Q) % Q;
+  double u[3][Q];
+  interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
+  __syncthreads();
+  double fe[3][Q];
+  if (own) {
+    const double* Mc = g.cmet + cell * 9 * Q3 + qy * Q + qx;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+        fe[e][q] = fma(Mc[(3 * e + 0) * Q3 + q * Q2], u[0][q],
+                       fma(Mc[(3 * e + 1) * Q3 + q * Q2], u[1][q], Mc[(3 * e + 2) * Q3 + q * Q2] * u[2][q]));
+  }
+  cell_lift_grad<N, Q>(S, D, fe[0], fe[1], fe[2], own, qx, qy, sX, sX + 3 * N * Q2, sO, 1.0, tid, nthr);
+  // faces, one at a time: out -= phi ({{u}} . nu_out)
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, s = f & 1;
+    double* P = sX;
+    double* F1 = sX + 6 * N2;
+    double* F2 = F1 + 6 * N * Q;
+    double* R = F2 + 6 * Q2;
+    const int64_t nb = conv_nb(g, cg, cell, d, s);
+    copy_plane<N>(sU, d, s, P, 1.0, tid, nthr);
+    if (nb >= 0) load_plane<N>(U, Nd, nb, d, 1 - s, P + 3 * N2, tid, nthr);
+    __syncthreads();
+    face_interp<N, Q>(S, P, F1, F2, nb >= 0 ? 6 : 3, tid, nthr);
+    const double sg = s ? -1.0 : 1.0;     // minus the outward sign
+    for (int pq = tid; pq < Q2; pq += nthr) {
+      const double* fm = g.fmet + (cell * 18 + f * 3) * Q2 + pq;
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double ua = nb >= 0 ? 0.5 * (F2[a * Q2 + pq] + F2[(3 + a) * Q2 + pq]) : F2[a * Q2 + pq];
+        acc = fma(fm[a * Q2], ua, acc);
+      }
+      R[pq] = sg * acc;
+    }
+    __syncthreads();
+    face_lift<N, Q>(S, R, F1, sO, 1, d, s, tid, nthr);
+  }
+  for (int e = tid; e < N3; e += nthr) out[cell * N3 + e] = sO[e];
+}
+
+template <int N, int Q>
+__global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_grad(const double* __restrict__ Pin,
+                                                                     double* __restrict__ out, const ConvGeom g,
+                                                                     int64_t ncells) {
+  using SH = CShape<N, Q>;
+  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
+  constexpr int XR = (N2 * Q + N * Q2) > (3 * N * Q2 + 2 * N2 * Q) ? (N2 * Q + N * Q2) : (3 * N * Q2 + 2 * N2 * Q);
+  constexpr int XF = 2 * N2 + 2 * N * Q + 2 * Q2 + 3 * Q2;   // planes [own | ext], stage, traces, fluxes
+  constexpr int X = XR > XF ? XR : XF;
+  __shared__ double sP[N3];
+  __shared__ double sO[3 * N3];
+  __shared__ double sX[X];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
+  if (cell >= ncells) return;
+  const int64_t Nd = ncells * N3;
+  const double* S = g.tab + g.S;
+  const double* D = g.tab + g.D;
+  CellGeo cg;
+  conv_cell(g, cell, cg);
+  for (int e = tid; e < N3; e += nthr) sP[e] = Pin[cell * N3 + e];
+  __syncthreads();
+  const bool own = tid < Q2;
+  const int qx = tid % Q, qy = (tid / Q) % Q;
+  double p[1][Q];
+  interp3<N, Q, 1>(S, sP, sX, sX + N2 * Q, tid, nthr, own, qx, qy, p);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double fe[3][Q];
+    if (own) {
+      const double* Mc = g.cmet + cell * 9 * Q3 + qy * Q + qx;
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) fe[e][q] = Mc[(3 * e + a) * Q3 + q * Q2] * p[0][q];
+    }
+    cell_lift_grad<N, Q>(S, D, fe[0], fe[1], fe[2], own, qx, qy, sX, sX + 3 * N * Q2, sO + a * N3, 1.0, tid,
+                         nthr);
+  }
+  // faces, one at a time: out_a -= phi {{p}} nu_out,a
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, s = f & 1;
+    double* P = sX;
+    double* F1 = sX + 2 * N2;
+    double* F2 = F1 + 2 * N * Q;
+    double* R = F2 + 2 * Q2;
+    const int64_t nb = conv_nb(g, cg, cell, d, s);
+    for (int e = tid; e < N2; e += nthr) {
+      P[e] = sP[face_node<N>(d, s, e % N, e / N)];
+      if (nb >= 0) P[N2 + e] = Pin[nb * N3 + face_node<N>(d, 1 - s, e % N, e / N)];
+    }
+    __syncthreads();
+    face_interp<N, Q>(S, P, F1, F2, nb >= 0 ? 2 : 1, tid, nthr);
+    const double sg = s ? -1.0 : 1.0;     // minus the outward sign
+    for (int pq = tid; pq < Q2; pq += nthr) {
+      const double* fm = g.fmet + (cell * 18 + f * 3) * Q2 + pq;
+      const double pa = nb >= 0 ? 0.5 * (F2[pq] + F2[Q2 + pq]) : F2[pq];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) R[a * Q2 + pq] = sg * fm[a * Q2] * pa;
+    }
+    __syncthreads();
+    face_lift<N, Q>(S, R, F1, sO, 3, d, s, tid, nthr);
+  }
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int a = e / N3, r = e % N3;
+    out[a * Nd + cell * N3 + r] = sO[e];
+  }
+}
+
 // ------------------------------------------------------ curved-cell metric
 // Per cell quadrature point, w_q |det J| J^{-1} = w_q sgn(det J) adj(J) (nine
 // values); per face point, the weighted normal w_q1 w_q2 |det J| J^{-T} e_d
@@ -886,12 +1053,30 @@ dgmf_status launch_vjp_nq(const ConvGeom& g, const double* U, const double* W, d
   return DGMF_OK;
 }
 
+template <int N>
+dgmf_status launch_curv_v3_n(bool grad, const ConvGeom& g, const double* in, double* out, int64_t ncells,
+                             hipStream_t s) {
+  if (ncells > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
+  if (grad) {
+    hipLaunchKernelGGL((k_curv_grad<N, N>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, N>::THREADS), 0, s,
+                       in, out, g, ncells);
+    DGMF_LAUNCH_CHECK("k_curv_grad");
+  } else {
+    hipLaunchKernelGGL((k_curv_div<N, N>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, N>::THREADS), 0, s,
+                       in, out, g, ncells);
+    DGMF_LAUNCH_CHECK("k_curv_div");
+  }
+  return DGMF_OK;
+}
+
 }  // namespace
 
 // Supported (n, n_q): the paper's floor(3k/2)+1 and floor(3(k+1)/2) for k = 1..6
 // (k = 7 would need more than 64 KiB of LDS per workgroup in this layout).
 #define DGMF_CONV_CASES(X) \
   X(2, 2) X(2, 3) X(3, 4) X(4, 5) X(4, 6) X(5, 7) X(6, 8) X(6, 9) X(7, 10) X(7, 11)
+// the curved V3c operators: n_q = n = k+1 for k = 2..7 (k = 1 is (2, 2) above)
+#define DGMF_QN_CASES(X) X(3, 3) X(4, 4) X(5, 5) X(6, 6) X(7, 7) X(8, 8)
 
 bool conv_supported(int n, int nq) {
 #define X(a, b) if (n == a && nq == b) return true;
@@ -932,8 +1117,23 @@ dgmf_status launch_conv_fill_curved(int n, int nq, const double* const x0[3], co
   const FillTabs t{tab + off[1], tab + off[2], tab + off[3], tab + off[4], tab + off[5]};
 #define X(a, b) if (n == a && nq == b) return launch_fill_nq<a, b>(m, nx, ny, ncells, t, cmet, fmet, s);
   DGMF_CONV_CASES(X)
+  DGMF_QN_CASES(X)
 #undef X
   return fail(DGMF_UNSUPPORTED, "convective: (n, n_q) = (%d, %d) not built", n, nq);
+}
+
+dgmf_status launch_curv_v3(int n, bool grad, const ConvGeom& g, const double* in, double* out, int64_t ncells,
+                           hipStream_t s) {
+  switch (n) {
+    case 2: return launch_curv_v3_n<2>(grad, g, in, out, ncells, s);
+    case 3: return launch_curv_v3_n<3>(grad, g, in, out, ncells, s);
+    case 4: return launch_curv_v3_n<4>(grad, g, in, out, ncells, s);
+    case 5: return launch_curv_v3_n<5>(grad, g, in, out, ncells, s);
+    case 6: return launch_curv_v3_n<6>(grad, g, in, out, ncells, s);
+    case 7: return launch_curv_v3_n<7>(grad, g, in, out, ncells, s);
+    case 8: return launch_curv_v3_n<8>(grad, g, in, out, ncells, s);
+    default: return fail(DGMF_UNSUPPORTED, "curved V3c operators: n = %d not built", n);
+  }
 }
 
 }  // namespace dgmf

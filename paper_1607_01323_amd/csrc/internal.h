@@ -231,6 +231,10 @@ dgmf_status launch_conv_fwd(int n, int nq, const ConvGeom& g, const double* U, d
                             bool step, double dt, hipStream_t s);
 dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, const double* W, double* G,
                             int64_t ncells, hipStream_t s);
+// V3c divergence (grad = false: [3][N] -> [N]) or gradient (grad = true:
+// [N] -> [3][N]) on curved cells, with a ConvGeom of n_q = n points and its metric
+dgmf_status launch_curv_v3(int n, bool grad, const ConvGeom& g, const double* in, double* out, int64_t ncells,
+                           hipStream_t s);
 // curved-cell metric of the convective operator (ConvGeom::cmet, fmet); off:
 // offsets into tab of the GLL nodes, S, D, the Gauss weights, l(0) l(1), l'(0) l'(1)
 dgmf_status launch_conv_fill_curved(int n, int nq, const double* const x0[3], const double* const h[3],
@@ -358,6 +362,10 @@ struct dgmf_mesh_ {
   dgmf::DevBuf mh32;               // 1D mass in fp32 (the fp64 one heads v3tab)
   dgmf::DevBuf v3tab;              // V3Tab tables (fp64)
   dgmf::DevBuf pmt64, pmt32;       // curved cells: S, S^T, S^{-T}, S^{-1} for the point-weight mass
+  // curved cells: tables and per-point metric (n_q = k+1) of the V3c divergence and
+  // gradient, filled on their first call
+  dgmf::DevBuf qtab, qmet;
+  dgmf::ConvGeom qgeo{};
   int nops = 0;                    // live operators built on this mesh
 };
 

@@ -151,7 +151,9 @@ def test_flat_operators_refuse_curved_meshes():
     gm = dg.Mesh(2, 2, 2, 2, store_qp_metric=True, curve_amp=0.05)
     N = gm.ndofs
     u = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
-    for call in (lambda: gm.divergence(u), lambda: gm.gradient(u[:N]), lambda: gm.node_coords()):
+    tau = torch.zeros(gm.ncells, dtype=torch.float64, device="cuda")
+    for call in (lambda: gm.node_coords(), lambda: gm.divdiv_penalty(u, 1.0, 1e-3),
+                 lambda: gm.projection_solve(tau, u)):
         with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
             call()
     gop = dg.SipgOperator(gm, 1.0, 1.0, 1.0)

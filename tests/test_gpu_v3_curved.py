@@ -1,0 +1,57 @@
+"""GPU parity of the V3c divergence A and gradient B on curved (iso-parametric) cells.
+
+The library fills a per-point metric at k+1 Gauss points on the first call
+(w sgn(det J) adj(J) per cell point, the weighted normal from the tangential
+columns of J per face point) and applies A and B through the quadrature
+points; the oracle assembles both as sparse matrices point by point with
+J^{-1} and Nanson's formula (``oracle.v3`` on an ``oracle.curved`` mesh).
+Bar: every entry of A u and B p within 1e-12 relative (max norm) of the
+oracle on small meshes (periodic sides, Dirichlet walls, Neumann sides, tanh
+grading, degrees 1-7) and on a 6x4x6-cell curved channel; a second call
+reuses the metric and gives the same bits.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dgmf_inputs as inp
+from oracle import curved, v3
+from tests.gpu_util import dev, host, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+CH = (2 * math.pi, 2, math.pi)
+CASES = {
+    # name: (k, cells, lengths, y0, periodic, gamma, neumann, amp)
+    "k1_periodic": (1, (3, 2, 2), (1, 1, 1), 0.0, (1, 1, 1), 0.0, (0,) * 6, 0.06),
+    "k2_walls": (2, (2, 3, 2), (1, 1.2, 0.9), 0.0, (1, 0, 1), 0.0, (0,) * 6, 0.05),
+    "k3_channel_neumann": (3, (2, 3, 2), CH, -1.0, (1, 0, 1), 1.5, (0, 0, 0, 1, 0, 0), 0.03),
+    "k4_all_walls": (4, (2, 2, 2), (1, 1, 1), 0.0, (0, 0, 0), 0.0, (0, 1, 0, 0, 0, 0), 0.07),
+    "k5_periodic": (5, (2, 2, 2), (1, 1, 1), 0.0, (1, 1, 1), 0.0, (0,) * 6, 0.06),
+    "k6_mixed": (6, (2, 2, 1), (1, 1, 1), 0.0, (1, 1, 0), 0.0, (0, 0, 0, 0, 1, 0), 0.05),
+    "k7_z_walls": (7, (2, 2, 1), (1, 1, 1), 0.0, (1, 1, 0), 0.0, (0,) * 6, 0.04),
+    "k4_channel_6x4x6": (4, (6, 4, 6), CH, -1.0, (1, 0, 1), 1.8, (0,) * 6, 0.03),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_divergence_and_gradient_match_assembled_matrices(name):
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    print(f"[case] curved V3c {name}", flush=True)
+    k, cells, L, y0, per, gam, neu, amp = CASES[name]
+    om = curved.CurvedBoxMesh(k, *cells, lx=L[0], ly=L[1], lz=L[2], y0=y0, periodic=tuple(bool(p) for p in per),
+                              y_tanh_gamma=gam, neumann=tuple(bool(f) for f in neu), amp=amp)
+    gm = dg.Mesh(k, *cells, *L, y0=y0, periodic=per, y_tanh_gamma=gam, store_qp_metric=True, neumann=neu,
+                 curve_amp=amp)
+    N = om.ndofs
+    u = inp.uniform(41, 3 * N)
+    p = inp.uniform(42, N)
+    A = v3.divergence_matrix(om)
+    B = v3.gradient_matrix(om)
+    d1 = host(gm.divergence(dev(u)))
+    assert rel_err(d1, A @ u) < 1e-12
+    assert np.array_equal(host(gm.divergence(dev(u))), d1)
+    assert rel_err(host(gm.gradient(dev(p))), B @ p) < 1e-12
+    gm.close()
