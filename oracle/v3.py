@@ -17,7 +17,9 @@ affine cells), built from dense Kronecker-product evaluation matrices.  On
 curved (iso-parametric) cells, Sec. 5, A and B take the Jacobian of the cell
 map at every cell and face quadrature point (normals and surface measures by
 Nanson's formula); there the k+1-point rule defines the operators, and a
-larger ``nq`` is available for the pins that need exact integration.
+larger ``nq`` is available for the pins that need exact integration.  The
+cell mass, the div-div matrix D_e, the penalty's volume average and the
+projection use the same per-point Jacobians on curved cells.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -173,14 +175,35 @@ def divdiv_cell(T, J):
     return np.block([[grad[a].T @ (w[:, None] * grad[b]) for b in range(3)] for a in range(3)])
 
 
+def cell_mass_divdiv(m, c, nq=None):
+    """(M_e, D_e) of cell c with per-point Jacobians (curved cells, Sec. 5):
+    M_e = (phi_i, phi_j)_K, D_e = (div v, div u)_K in [a][b] blocks."""
+    T = _tables(m, nq)
+    grad, Phi, w = _cell_geo(T, m, c)
+    M = Phi.T @ (w[:, None] * Phi)
+    D = np.block([[grad[a].T @ (w[:, None] * grad[b]) for b in range(3)] for a in range(3)])
+    return M, D
+
+
+def _weights_volume(m, c):
+    """Integral weights of the cell's basis functions and the cell volume."""
+    if not _curved(m):
+        return None, m.volume(c)
+    T = sipg.Tables(m.k)
+    _, Phi, w = _cell_geo(T, m, c)
+    return Phi.T @ w, w.sum()
+
+
 def penalty_tau(m, u, zeta, dt):
     """tau_D per cell = zeta |u_bar| V^(1/3) dt, u_bar the cell average of the velocity [3][N]."""
-    wts = sipg.integral_weights(m).reshape(m.ncells, -1)
+    wts = None if _curved(m) else sipg.integral_weights(m).reshape(m.ncells, -1)
     U = np.asarray(u, dtype=np.float64).reshape(3, m.ncells, -1)
     tau = np.empty(m.ncells)
     for c in range(m.ncells):
-        V = m.volume(c)
-        ubar = np.array([wts[c] @ U[a, c] for a in range(3)]) / V
+        wc, V = _weights_volume(m, c)
+        if wc is None:
+            wc = wts[c]
+        ubar = np.array([wc @ U[a, c] for a in range(3)]) / V
         tau[c] = zeta * np.linalg.norm(ubar) * V ** (1.0 / 3.0) * dt
     return tau
 
@@ -193,9 +216,12 @@ def projection_solve(m, tau, rhs, cells=None):
     R = np.asarray(rhs, dtype=np.float64).reshape(3, -1, nb)
     out = np.zeros((3, len(cl), nb))
     for r, c in enumerate(cl):
-        J = m.jacobian(c)
-        M = sipg.cell_matrices(T, J)[1]
-        Ae = np.kron(np.eye(3), M) + tau[c] * divdiv_cell(T, J)
+        if _curved(m):
+            M, D = cell_mass_divdiv(m, c)
+        else:
+            J = m.jacobian(c)
+            M, D = sipg.cell_matrices(T, J)[1], divdiv_cell(T, J)
+        Ae = np.kron(np.eye(3), M) + tau[c] * D
         src = R[:, c] if cells is None else R[:, r]
         out[:, r] = np.linalg.solve(Ae, src.ravel()).reshape(3, nb)
     return out.ravel() if cells is None else out

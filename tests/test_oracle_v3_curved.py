@@ -11,7 +11,12 @@ Fixed by facts outside the oracle:
     of the wrong size breaks these;
   - with the defining k+1 points, A applied to the interpolant of a smooth
     periodic field tends to -(phi_i, div u) at a rate that rises with the
-    degree.
+    degree;
+  - the coordinate functions lie in the iso-parametric space, so their
+    physical gradients are the unit vectors at every point; D_e annihilates
+    constant fields, is semi-definite and gives u.D u = V for u = (x, 0, 0);
+    the penalty of a constant field uses the curved volume; zero amplitude
+    gives the affine penalty and projection.
 """
 import numpy as np
 import pytest
@@ -83,3 +88,52 @@ def test_divergence_consistency_with_the_continuous_operator():
     e2 = _consistency_error(3, 2)
     e4 = _consistency_error(3, 4)
     assert e4 < 0.2 * e2 and e4 < 0.02
+
+
+def test_physical_gradient_of_the_coordinates_is_the_identity():
+    """The iso-parametric space holds the coordinate functions exactly, so their
+    physical gradients at every quadrature point are the unit vectors."""
+    m = curved.CurvedBoxMesh(3, 2, 2, 2, amp=0.08, ly=1.3, y_tanh_gamma=1.1, periodic=(True, False, True))
+    T = sipg.Tables(3)
+    for c in (0, 5):
+        grad, _, _ = v3._cell_geo(T, m, c)
+        X = m.node_xyz(c)
+        for a in range(3):
+            for r in range(3):
+                assert np.abs(grad[a] @ X[:, r] - (1.0 if a == r else 0.0)).max() < 1e-12
+
+
+def test_divdiv_and_penalty_on_curved_cells():
+    kw = dict(ly=2.0, y0=-1.0, periodic=(True, False, True), y_tanh_gamma=1.3)
+    m = curved.CurvedBoxMesh(3, 2, 3, 2, amp=0.06, **kw)
+    nb = m.n ** 3
+    M, D = v3.cell_mass_divdiv(m, 3)
+    # constant vector fields are divergence-free at every point
+    const = np.concatenate([np.full(nb, 0.3), np.full(nb, -1.2), np.full(nb, 0.7)])
+    assert np.abs(D @ const).max() < 1e-12 * np.abs(D).max()
+    assert np.all(np.linalg.eigvalsh(D) > -1e-12 * np.abs(D).max())
+    # u = (x, 0, 0): div u = 1 at every point, so v . D u = (div v, 1)_K and u . D u = V
+    X = m.node_xyz(3)
+    u = np.concatenate([X[:, 0], np.zeros(nb), np.zeros(nb)])
+    w, V = v3._weights_volume(m, 3)
+    assert abs(u @ D @ u - V) < 1e-12 * V
+    assert abs(w.sum() - V) < 1e-14 * V and abs(np.ones(nb) @ M @ np.ones(nb) - V) < 1e-13 * V
+    # penalty of a constant field: zeta |c| V^(1/3) dt with the curved volume
+    N = m.ndofs
+    U = np.concatenate([np.full(N, 0.3), np.full(N, -1.2), np.full(N, 0.7)])
+    tau = v3.penalty_tau(m, U, 2.0, 1e-2)
+    vols = np.array([v3._weights_volume(m, c)[1] for c in range(m.ncells)])
+    assert np.abs(tau - 2.0 * np.linalg.norm([0.3, -1.2, 0.7]) * vols ** (1 / 3) * 1e-2).max() < 1e-14
+    assert np.ptp(vols) > 1e-3 * vols.mean()          # graded cells: the volumes differ
+
+
+def test_curved_penalty_and_projection_reduce_to_affine():
+    kw = dict(lx=2.0, ly=2.0, lz=1.0, y0=-1.0, periodic=(True, False, False), y_tanh_gamma=1.3)
+    cm = curved.CurvedBoxMesh(2, 2, 3, 2, amp=0.0, **kw)
+    am = omesh.BoxMesh(2, 2, 3, 2, **kw)
+    U = inp.uniform(51, 3 * am.ndofs)
+    ta, tc = v3.penalty_tau(am, U, 1.0, 0.1), v3.penalty_tau(cm, U, 1.0, 0.1)
+    assert np.abs(ta - tc).max() < 1e-14 * np.abs(ta).max()
+    rhs = inp.uniform(52, 3 * am.ndofs)
+    xa, xc = v3.projection_solve(am, ta, rhs), v3.projection_solve(cm, ta, rhs)
+    assert np.abs(xa - xc).max() < 1e-11 * np.abs(xa).max()
