@@ -366,6 +366,19 @@ def curved_measurements(dg, inp, torch, w, tag):
     ex[f"{tag}_divergence"] = {"us": td * 1e6, "metric_bytes": qmet,
                                "hbm_frac": (32.0 * N + qmet) / td / 1e9 / HBM_PEAK_GBS}
     ex[f"{tag}_gradient"] = {"us": tg * 1e6, "hbm_frac": (32.0 * N + qmet) / tg / 1e9 / HBM_PEAK_GBS}
+    # element-local projection to 1e-12 from zero, tau_D = |u_bar| h dt (zeta = 1, dt = 1e-2)
+    tau = m.divdiv_penalty(U, 1.0, 1e-2)
+    rhs = m.mass(U)
+    xp = torch.zeros_like(U)
+    its = torch.zeros(m.ncells, dtype=torch.int32, device="cuda")
+
+    def solve():
+        xp.zero_()
+        m.projection_solve(tau, rhs, x=xp, rtol=1e-12, max_iter=2000, iterations=its)
+
+    tp = _events_time(solve, 3, 1)
+    ex[f"{tag}_projection"] = {"ms": tp * 1e3, "cells_per_s": m.ncells / tp, "iterations_max": int(its.max()),
+                               "iterations_mean": float(its.float().mean())}
     ex[f"{tag}_convective"] = {"create_s": tc, "fwd_us": tf * 1e6, "vjp_us": tv * 1e6,
                                "fwd_dofs_per_s": 3 * N / tf, "vjp_dofs_per_s": 3 * N / tv,
                                "fwd_plus_vjp_dofs_per_s": 3 * N / (tf + tv), "dofs": 3 * N, "n_q": nq,

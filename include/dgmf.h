@@ -111,10 +111,10 @@ int dgmf_version(void);
  * curved operator on the finest level and rediscretises the coarse levels on
  * the undeformed box), the mass matrix and its inverse (with the point
  * weights w_q det J_q), the convective operator and its VJP, and the V3c
- * divergence and gradient (with the Jacobian at every quadrature point);
- * every other operator (the fused convective substep, the div-div penalty
- * and projection, the symmetric-gradient viscous operator, coordinates, load
- * vectors) returns DGMF_UNSUPPORTED on them.
+ * divergence, gradient, div-div penalty and local projection (with the
+ * Jacobian at every quadrature point); every other operator (the fused
+ * convective substep, the symmetric-gradient viscous operator, coordinates,
+ * load vectors) returns DGMF_UNSUPPORTED on them.
  * degree k in 1..7; every cell count >= 1; lengths > 0. */
 typedef struct {
   int degree;
@@ -177,7 +177,9 @@ dgmf_status dgmf_divergence_apply(dgmf_mesh mesh, const double* u, double* out, 
 dgmf_status dgmf_gradient_apply(dgmf_mesh mesh, const double* p, double* out, hipStream_t stream);
 /* tau[c] = zeta |u_bar_c| V_c^(1/3) dt (eq. tauD), u_bar_c the volume average
  * of the velocity u [3][N] on cell c; zeta, dt finite and >= 0 (the paper
- * takes zeta = 1/CFL).  Asynchronous. */
+ * takes zeta = 1/CFL).  Asynchronous (curved meshes: k+1 Gauss points per
+ * direction with w |det J| per point, and the first-call metric fill of
+ * dgmf_divergence_apply). */
 dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, double dt, double* tau,
                                 hipStream_t stream);
 /* Solves the local projection of eq. project with the div-div penalty only
@@ -188,7 +190,11 @@ dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, do
  * at most rtol times its right-hand side or after max_iter iterations.  rhs,
  * x [3][N] (x in/out; must not overlap rhs); tau [n_cells] >= 0;
  * iterations: device int [n_cells] receiving each cell's iteration count, or
- * NULL.  Degrees k <= 6.  Asynchronous. */
+ * NULL.  Degrees k <= 6.  Asynchronous.  On curved meshes M_e and D_e take
+ * k+1 Gauss points per direction and the Jacobian at every point, the
+ * preconditioner is the point inverse mass S^{-1} diag(1/(w |det J|)) S^{-T}
+ * per direction, and the first call fills the metric as
+ * dgmf_divergence_apply does. */
 dgmf_status dgmf_projection_solve(dgmf_mesh mesh, const double* tau, const double* rhs, double* x, double rtol,
                                   int max_iter, int* iterations, hipStream_t stream);
 

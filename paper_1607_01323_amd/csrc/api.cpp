@@ -680,6 +680,11 @@ static dgmf_status curved_v3_geometry(dgmf_mesh mesh) {
   const int o_g = static_cast<int>(h.size());
   h.insert(h.end(), t.g0.begin(), t.g0.end());
   h.insert(h.end(), t.g1.begin(), t.g1.end());
+  // S^{-1} (S is square here) for the inverse mass of the projection
+  std::vector<long double> si;
+  if (!invert(n, t.S.data(), si)) return fail(DGMF_INVALID, "curved V3c: singular interpolation matrix");
+  const int o_si = static_cast<int>(h.size());
+  for (int i = 0; i < n * n; ++i) h.push_back(static_cast<double>(si[i]));
   dgmf_status st;
   if ((st = mesh->qtab.upload(h.data(), h.size() * sizeof(double)))) return st;
   const int64_t nq2 = static_cast<int64_t>(nq) * nq, cper = 9 * nq2 * nq, fper = 18 * nq2;
@@ -709,7 +714,7 @@ static dgmf_status curved_v3_geometry(dgmf_mesh mesh) {
   g.S = 0;
   g.D = nq * n;
   g.w = 2 * nq * n;
-  g.Mi = -1;   // no inverse mass here
+  g.Mi = o_si;   // S^{-1}
   g.fmet = cm + mesh->ncells * cper;
   g.cmet = cm;
   return DGMF_OK;
@@ -764,7 +769,7 @@ dgmf_status dgmf_gradient_apply(dgmf_mesh mesh, const double* p, double* out, hi
 
 dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, double dt, double* tau,
                                 hipStream_t stream) {
-  dgmf_status e = v3_check(mesh, "divdiv_penalty");
+  dgmf_status e = v3_check(mesh, "divdiv_penalty", true);
   if (e) return e;
   if (!u || !tau || !aligned(u, 8) || !aligned(tau, 8))
     return fail(DGMF_INVALID, "divdiv_penalty: null or misaligned vector");
@@ -773,13 +778,18 @@ dgmf_status dgmf_divdiv_penalty(dgmf_mesh mesh, const double* u, double zeta, do
   if (overlap2(u, 24 * mesh->ndofs, tau, 8 * mesh->ncells))
     return fail(DGMF_INVALID, "divdiv_penalty: u and tau overlap");
   DeviceGuard dg(mesh->device);
+  if (mesh->desc.curve_amp != 0.0) {
+    if ((e = curved_v3_geometry(mesh))) return e;
+    return launch_curv_cell(mesh->tab.n, false, mesh->qgeo, mesh->mg64.cm, u, zeta, dt, tau, nullptr, nullptr, nullptr,
+                            0.0, 0, nullptr, mesh->ncells, stream);
+  }
   return launch_v3_tau(mesh->tab.n, mesh->g64, static_cast<const double*>(mesh->v3tab.p), u, zeta, dt, tau,
                        mesh->ncells, stream);
 }
 
 dgmf_status dgmf_projection_solve(dgmf_mesh mesh, const double* tau, const double* rhs, double* x, double rtol,
                                   int max_iter, int* iterations, hipStream_t stream) {
-  dgmf_status e = v3_check(mesh, "projection_solve");
+  dgmf_status e = v3_check(mesh, "projection_solve", true);
   if (e) return e;
   if (!v3_projection_supported(mesh->tab.n))
     return fail(DGMF_UNSUPPORTED, "projection_solve: degree %d not built (k <= 6)", mesh->tab.n - 1);
@@ -792,6 +802,11 @@ dgmf_status dgmf_projection_solve(dgmf_mesh mesh, const double* tau, const doubl
   if (overlap2(rhs, vb, x, vb) || overlap2(tau, tb, x, vb) || (iterations && overlap2(iterations, ib, x, vb)))
     return fail(DGMF_INVALID, "projection_solve: x overlaps another argument");
   DeviceGuard dg(mesh->device);
+  if (mesh->desc.curve_amp != 0.0) {
+    if ((e = curved_v3_geometry(mesh))) return e;
+    return launch_curv_cell(mesh->tab.n, true, mesh->qgeo, mesh->mg64.cm, nullptr, 0.0, 0.0, nullptr, tau, rhs, x,
+                            rtol, max_iter, iterations, mesh->ncells, stream);
+  }
   return launch_v3_projection(mesh->tab.n, mesh->g64, static_cast<const double*>(mesh->v3tab.p), tau, rhs, x, rtol,
                               max_iter, iterations, mesh->ncells, stream);
 }

@@ -933,6 +933,246 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_grad(const dou
   }
 }
 
+// ------------------------------- V3c div-div penalty and projection, curved
+// Cell-local forms of eqs. tauD, div-div and project (tau_C = 0) on curved
+// cells with k+1 Gauss points per direction (n_q = n, so the point grid has
+// the node grid's size): one 64-lane workgroup per cell, every vector in LDS,
+// 1D operators applied line by line (one line per lane).  Per point: G =
+// w sgn(det J) adj(J) from the fill below and w |det J| from the SIPG metric.
+//   (M u)_{i,a}  = sum_q phi_i w|det J| u_a
+//   (D u)_{i,a}  = sum_q sum_e dphi_i/dxi_e G_ea s,   s = (sum_{e,b} G_eb du_b/dxi_e) / (w |det J|)
+// (w|det J| div v div u at every point), and M^{-1} = S^{-1} (x) 3 diag(1/(w|det J|)) S^{-T} (x) 3.
+
+// x <- A x along direction d on nb consecutive n^3 blocks (TR: A^T x); A row-major n x n
+template <int N, bool TR>
+__device__ __forceinline__ void qsweep(const double* __restrict__ A, double* buf, int nb, int d, int tid,
+                                       int nthr) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  const int stride = d == 0 ? 1 : (d == 1 ? N : N2);
+  for (int job = tid; job < nb * N2; job += nthr) {
+    const int b = job / N2, r = job % N2;
+    const int start = d == 0 ? r * N : (d == 1 ? (r / N) * N2 + r % N : r);
+    double* p = buf + b * N3 + start;
+    double v[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = p[m * stride];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) t = fma(TR ? A[m * N + i] : A[i * N + m], v[m], t);
+      p[i * stride] = t;
+    }
+  }
+}
+
+// sum over the 64 lanes of the (single-wavefront) workgroup; every lane gets the total
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+struct CurvCell {
+  const double* S;      // n x n: S[q][i] = l_i(x_q)
+  const double* D;      // n x n: l_i'(x_q)
+  const double* Si;     // n x n: S^{-1}
+  const double* G;      // 9 n^3 of this cell
+  const double* wd;     // n^3 of this cell: w |det J|
+};
+
+// out = (M + tau D) u on one cell; u, out [3][n^3]; W: 8 n^3 scratch
+template <int N>
+__device__ void curv_mdd(const CurvCell& c, double tau, const double* u, double* out, double* W, int tid, int nthr) {
+  constexpr int N3 = N * N * N;
+  double* X1 = W;
+  double* X2 = W + N3;
+  double* A = W + 2 * N3;
+  double* B = W + 3 * N3;
+  double* V = W + 4 * N3;       // 3 blocks: point values of the components
+  double* s = W + 7 * N3;
+  for (int e = tid; e < N3; e += nthr) s[e] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    for (int e = tid; e < N3; e += nthr) X1[e] = X2[e] = u[a * N3 + e];
+    __syncthreads();
+    qsweep<N, false>(c.S, X1, 1, 0, tid, nthr);
+    qsweep<N, false>(c.D, X2, 1, 0, tid, nthr);
+    __syncthreads();
+    for (int e = tid; e < N3; e += nthr) A[e] = B[e] = X1[e];
+    __syncthreads();
+    qsweep<N, false>(c.S, A, 1, 1, tid, nthr);   // SySx
+    qsweep<N, false>(c.D, B, 1, 1, tid, nthr);   // DySx
+    qsweep<N, false>(c.S, X2, 1, 1, tid, nthr);  // SyDx
+    __syncthreads();
+    for (int e = tid; e < N3; e += nthr) X1[e] = A[e];
+    __syncthreads();
+    qsweep<N, false>(c.S, X1, 1, 2, tid, nthr);  // value
+    qsweep<N, false>(c.D, A, 1, 2, tid, nthr);   // d/dxi_z
+    qsweep<N, false>(c.S, B, 1, 2, tid, nthr);   // d/dxi_y
+    qsweep<N, false>(c.S, X2, 1, 2, tid, nthr);  // d/dxi_x
+    __syncthreads();
+    for (int e = tid; e < N3; e += nthr) {
+      V[a * N3 + e] = X1[e];
+      s[e] = fma(c.G[(0 + a) * N3 + e], X2[e], fma(c.G[(3 + a) * N3 + e], B[e], fma(c.G[(6 + a) * N3 + e], A[e], s[e])));
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < N3; e += nthr) s[e] = tau * s[e] / c.wd[e];
+  __syncthreads();
+  for (int a = 0; a < 3; ++a) {
+    for (int e = tid; e < N3; e += nthr) {
+      X1[e] = c.wd[e] * V[a * N3 + e];
+      X2[e] = c.G[(0 + a) * N3 + e] * s[e];
+      A[e] = c.G[(3 + a) * N3 + e] * s[e];
+      B[e] = c.G[(6 + a) * N3 + e] * s[e];
+    }
+    __syncthreads();
+    qsweep<N, true>(c.S, X1, 1, 2, tid, nthr);
+    qsweep<N, true>(c.D, B, 1, 2, tid, nthr);
+    qsweep<N, true>(c.S, A, 1, 2, tid, nthr);
+    qsweep<N, true>(c.S, X2, 1, 2, tid, nthr);
+    __syncthreads();
+    for (int e = tid; e < N3; e += nthr) X1[e] += B[e];
+    __syncthreads();
+    qsweep<N, true>(c.S, X1, 1, 1, tid, nthr);
+    qsweep<N, true>(c.D, A, 1, 1, tid, nthr);
+    qsweep<N, true>(c.S, X2, 1, 1, tid, nthr);
+    __syncthreads();
+    for (int e = tid; e < N3; e += nthr) X1[e] += A[e];
+    __syncthreads();
+    qsweep<N, true>(c.S, X1, 1, 0, tid, nthr);
+    qsweep<N, true>(c.D, X2, 1, 0, tid, nthr);
+    __syncthreads();
+    for (int e = tid; e < N3; e += nthr) out[a * N3 + e] = X1[e] + X2[e];
+    __syncthreads();
+  }
+}
+
+// z = M^{-1} r on one cell, three components, in place on z (which holds r on entry)
+template <int N>
+__device__ void curv_minv(const CurvCell& c, double* z, int tid, int nthr) {
+  constexpr int N3 = N * N * N;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    qsweep<N, true>(c.Si, z, 3, d, tid, nthr);
+    __syncthreads();
+  }
+  for (int e = tid; e < 3 * N3; e += nthr) z[e] /= c.wd[e % N3];
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    qsweep<N, false>(c.Si, z, 3, d, tid, nthr);
+    __syncthreads();
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(64) k_curv_tau(const double* __restrict__ U, const ConvGeom g,
+                                                 const double* __restrict__ wdet, double zeta, double dt,
+                                                 double* __restrict__ tau, int64_t ncells) {
+  constexpr int N3 = N * N * N;
+  __shared__ double sU[3 * N3];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
+  if (cell >= ncells) return;
+  const int64_t Nd = ncells * N3;
+  for (int e = tid; e < 3 * N3; e += nthr) sU[e] = U[(e / N3) * Nd + cell * N3 + e % N3];
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    qsweep<N, false>(g.tab + g.S, sU, 3, d, tid, nthr);
+    __syncthreads();
+  }
+  const double* wd = wdet + cell * 7 * N3 + 6 * N3;
+  double v = 0.0, i0 = 0.0, i1 = 0.0, i2 = 0.0;
+  for (int e = tid; e < N3; e += nthr) {
+    v += wd[e];
+    i0 = fma(wd[e], sU[e], i0);
+    i1 = fma(wd[e], sU[N3 + e], i1);
+    i2 = fma(wd[e], sU[2 * N3 + e], i2);
+  }
+  v = wave_total(v);
+  i0 = wave_total(i0);
+  i1 = wave_total(i1);
+  i2 = wave_total(i2);
+  if (tid == 0) tau[cell] = zeta * sqrt(i0 * i0 + i1 * i1 + i2 * i2) / v * cbrt(v) * dt;
+}
+
+template <int N>
+__global__ void __launch_bounds__(64) k_curv_proj(const ConvGeom g, const double* __restrict__ wdet,
+                                                  const double* __restrict__ taus, const double* __restrict__ rhs,
+                                                  double* __restrict__ x, double rtol, int max_iter,
+                                                  int* __restrict__ iters, int64_t ncells) {
+  constexpr int N3 = N * N * N;
+  __shared__ double sX[3 * N3], sR[3 * N3], sP[3 * N3], sQ[3 * N3], sW[8 * N3];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
+  if (cell >= ncells) return;
+  const int64_t Nd = ncells * N3;
+  const CurvCell c{g.tab + g.S, g.tab + g.D, g.tab + g.Mi, g.cmet + cell * 9 * N3, wdet + cell * 7 * N3 + 6 * N3};
+  const double tau = taus[cell];
+  double bb = 0.0;
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int64_t gi = (e / N3) * Nd + cell * N3 + e % N3;
+    sX[e] = x[gi];
+    sR[e] = rhs[gi];
+    bb = fma(sR[e], sR[e], bb);
+  }
+  bb = wave_total(bb);
+  __syncthreads();
+  curv_mdd<N>(c, tau, sX, sQ, sW, tid, nthr);
+  double rr = 0.0;
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    sR[e] -= sQ[e];
+    rr = fma(sR[e], sR[e], rr);
+  }
+  rr = wave_total(rr);
+  const double tol2 = rtol * rtol * bb;
+  int it = 0;
+  if (rr > tol2) {
+    __syncthreads();
+    for (int e = tid; e < 3 * N3; e += nthr) sQ[e] = sR[e];
+    __syncthreads();
+    curv_minv<N>(c, sQ, tid, nthr);
+    double rz = 0.0;
+    for (int e = tid; e < 3 * N3; e += nthr) {
+      sP[e] = sQ[e];
+      rz = fma(sR[e], sQ[e], rz);
+    }
+    rz = wave_total(rz);
+    __syncthreads();
+    while (it < max_iter) {
+      curv_mdd<N>(c, tau, sP, sQ, sW, tid, nthr);
+      double pq = 0.0;
+      for (int e = tid; e < 3 * N3; e += nthr) pq = fma(sP[e], sQ[e], pq);
+      const double alpha = rz / wave_total(pq);
+      rr = 0.0;
+      for (int e = tid; e < 3 * N3; e += nthr) {
+        sX[e] = fma(alpha, sP[e], sX[e]);
+        sR[e] = fma(-alpha, sQ[e], sR[e]);
+        rr = fma(sR[e], sR[e], rr);
+      }
+      rr = wave_total(rr);
+      ++it;
+      if (rr <= tol2) break;
+      __syncthreads();
+      for (int e = tid; e < 3 * N3; e += nthr) sQ[e] = sR[e];
+      __syncthreads();
+      curv_minv<N>(c, sQ, tid, nthr);
+      double rz1 = 0.0;
+      for (int e = tid; e < 3 * N3; e += nthr) rz1 = fma(sR[e], sQ[e], rz1);
+      rz1 = wave_total(rz1);
+      const double beta = rz1 / rz;
+      rz = rz1;
+      for (int e = tid; e < 3 * N3; e += nthr) sP[e] = fma(beta, sP[e], sQ[e]);
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 3 * N3; e += nthr) x[(e / N3) * Nd + cell * N3 + e % N3] = sX[e];
+  if (iters && tid == 0) iters[cell] = it;
+}
+
 // ------------------------------------------------------ curved-cell metric
 // Per cell quadrature point, w_q |det J| J^{-1} = w_q sgn(det J) adj(J) (nine
 // values); per face point, the weighted normal w_q1 w_q2 |det J| J^{-T} e_d
@@ -1069,6 +1309,23 @@ dgmf_status launch_curv_v3_n(bool grad, const ConvGeom& g, const double* in, dou
   return DGMF_OK;
 }
 
+template <int N>
+dgmf_status launch_curv_cell_n(bool proj, const ConvGeom& g, const double* wdet, const double* u, double zeta,
+                               double dt, double* tau, const double* taus, const double* rhs, double* x, double rtol,
+                               int max_iter, int* iters, int64_t ncells, hipStream_t s) {
+  if (ncells > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
+  if (proj) {
+    hipLaunchKernelGGL((k_curv_proj<N>), dim3(static_cast<unsigned>(ncells)), dim3(64), 0, s, g, wdet, taus, rhs, x,
+                       rtol, max_iter, iters, ncells);
+    DGMF_LAUNCH_CHECK("k_curv_proj");
+  } else {
+    hipLaunchKernelGGL((k_curv_tau<N>), dim3(static_cast<unsigned>(ncells)), dim3(64), 0, s, u, g, wdet, zeta, dt,
+                       tau, ncells);
+    DGMF_LAUNCH_CHECK("k_curv_tau");
+  }
+  return DGMF_OK;
+}
+
 }  // namespace
 
 // Supported (n, n_q): the paper's floor(3k/2)+1 and floor(3(k+1)/2) for k = 1..6
@@ -1134,6 +1391,17 @@ dgmf_status launch_curv_v3(int n, bool grad, const ConvGeom& g, const double* in
     case 8: return launch_curv_v3_n<8>(grad, g, in, out, ncells, s);
     default: return fail(DGMF_UNSUPPORTED, "curved V3c operators: n = %d not built", n);
   }
+}
+
+dgmf_status launch_curv_cell(int n, bool proj, const ConvGeom& g, const double* wdet, const double* u, double zeta,
+                             double dt, double* tau, const double* taus, const double* rhs, double* x, double rtol,
+                             int max_iter, int* iters, int64_t ncells, hipStream_t s) {
+#define X(a)                                                                                                    \
+  if (n == a)                                                                                                   \
+    return launch_curv_cell_n<a>(proj, g, wdet, u, zeta, dt, tau, taus, rhs, x, rtol, max_iter, iters, ncells, s);
+  X(2) X(3) X(4) X(5) X(6) X(7)
+#undef X
+  return fail(DGMF_UNSUPPORTED, "curved div-div penalty / projection: n = %d not built", n);
 }
 
 }  // namespace dgmf

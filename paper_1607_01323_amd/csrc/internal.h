@@ -235,6 +235,12 @@ dgmf_status launch_conv_vjp(int n, int nq, const ConvGeom& g, const double* U, c
 // [N] -> [3][N]) on curved cells, with a ConvGeom of n_q = n points and its metric
 dgmf_status launch_curv_v3(int n, bool grad, const ConvGeom& g, const double* in, double* out, int64_t ncells,
                            hipStream_t s);
+// div-div penalty (proj = false: tau from u, zeta, dt) or local projection
+// (proj = true: x from taus, rhs, x, rtol, max_iter, iters) on curved cells, with
+// the ConvGeom of n_q = n points (tab + Mi: S^{-1}) and wdet the SIPG cell metric
+dgmf_status launch_curv_cell(int n, bool proj, const ConvGeom& g, const double* wdet, const double* u, double zeta,
+                             double dt, double* tau, const double* taus, const double* rhs, double* x, double rtol,
+                             int max_iter, int* iters, int64_t ncells, hipStream_t s);
 // curved-cell metric of the convective operator (ConvGeom::cmet, fmet); off:
 // offsets into tab of the GLL nodes, S, D, the Gauss weights, l(0) l(1), l'(0) l'(1)
 dgmf_status launch_conv_fill_curved(int n, int nq, const double* const x0[3], const double* const h[3],

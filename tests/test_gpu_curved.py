@@ -151,14 +151,12 @@ def test_flat_operators_refuse_curved_meshes():
     gm = dg.Mesh(2, 2, 2, 2, store_qp_metric=True, curve_amp=0.05)
     N = gm.ndofs
     u = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
-    tau = torch.zeros(gm.ncells, dtype=torch.float64, device="cuda")
-    for call in (lambda: gm.node_coords(), lambda: gm.divdiv_penalty(u, 1.0, 1e-3),
-                 lambda: gm.projection_solve(tau, u)):
+    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
+        gm.node_coords()
+    gop = dg.SipgOperator(gm, 1.0, 1.0, 1.0)
+    for call in (lambda: gop.quadrature_points(), lambda: gop.viscous_apply(u)):
         with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
             call()
-    gop = dg.SipgOperator(gm, 1.0, 1.0, 1.0)
-    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
-        gop.quadrature_points()
     gm.close()
 
 

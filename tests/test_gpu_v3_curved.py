@@ -8,7 +8,10 @@ J^{-1} and Nanson's formula (``oracle.v3`` on an ``oracle.curved`` mesh).
 Bar: every entry of A u and B p within 1e-12 relative (max norm) of the
 oracle on small meshes (periodic sides, Dirichlet walls, Neumann sides, tanh
 grading, degrees 1-7) and on a 6x4x6-cell curved channel; a second call
-reuses the metric and gives the same bits.
+reuses the metric and gives the same bits.  The div-div penalty (1e-12) and
+the element-local projection (CG with the point inverse mass to 1e-13,
+against the oracle's dense per-cell solve at 1e-9) on the same meshes up to
+degree 6.
 """
 import math
 
@@ -54,4 +57,46 @@ def test_divergence_and_gradient_match_assembled_matrices(name):
     assert rel_err(d1, A @ u) < 1e-12
     assert np.array_equal(host(gm.divergence(dev(u))), d1)
     assert rel_err(host(gm.gradient(dev(p))), B @ p) < 1e-12
+    gm.close()
+
+
+@pytest.mark.parametrize("name", [n for n in CASES if CASES[n][0] <= 6])
+def test_penalty_and_projection_match_oracle(name):
+    """tau_D against the oracle's volume averages (1e-12); the element-local
+    projection to rtol 1e-13 against the oracle's dense per-cell solve (1e-9),
+    with the penalty as computed and a hundred times larger."""
+    require_gpu()
+    import torch
+    import paper_1607_01323_amd as dg
+    print(f"[case] curved penalty/projection {name}", flush=True)
+    k, cells, L, y0, per, gam, neu, amp = CASES[name]
+    om = curved.CurvedBoxMesh(k, *cells, lx=L[0], ly=L[1], lz=L[2], y0=y0, periodic=tuple(bool(p) for p in per),
+                              y_tanh_gamma=gam, neumann=tuple(bool(f) for f in neu), amp=amp)
+    gm = dg.Mesh(k, *cells, *L, y0=y0, periodic=per, y_tanh_gamma=gam, store_qp_metric=True, neumann=neu,
+                 curve_amp=amp)
+    N = om.ndofs
+    U = inp.uniform(43, 3 * N)
+    U[:N] += 1.0
+    tau = host(gm.divdiv_penalty(dev(U), 1.0, 1e-2))
+    assert rel_err(tau, v3.penalty_tau(om, U, 1.0, 1e-2)) < 1e-12
+    rhs = inp.uniform(44, 3 * N)
+    for scale in (1.0, 100.0):
+        t = scale * tau
+        x = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+        its = torch.zeros(om.ncells, dtype=torch.int32, device="cuda")
+        gm.projection_solve(dev(t), dev(rhs), x=x, rtol=1e-13, max_iter=500, iterations=its)
+        assert rel_err(host(x), v3.projection_solve(om, t, rhs)) < 1e-9
+        assert 0 < int(its.max()) < 500
+    gm.close()
+
+
+def test_projection_refuses_degree_seven_on_curved_cells():
+    require_gpu()
+    import torch
+    import paper_1607_01323_amd as dg
+    gm = dg.Mesh(7, 2, 2, 1, periodic=(1, 1, 0), store_qp_metric=True, curve_amp=0.04)
+    z = torch.zeros(3 * gm.ndofs, dtype=torch.float64, device="cuda")
+    t = torch.zeros(gm.ncells, dtype=torch.float64, device="cuda")
+    with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
+        gm.projection_solve(t, z, x=z.clone())
     gm.close()
