@@ -35,6 +35,10 @@
  *   enqueues; the caller keeps buffers alive until the stream passes it.
  *   Work is enqueued on the given hipStream_t (0 = the null stream) and the
  *   call returns without waiting unless it says otherwise.
+ *   Calls that build something on first use (a multigrid hierarchy, the
+ *   curved-cell metric of the V3c operators) change the handle: the first
+ *   such call on one handle must not overlap another call on it from a
+ *   different host thread; later calls only read the handle.
  *
  * Errors: every function returns a dgmf_status; no exception crosses the
  * ABI.  Argument errors are detected before anything is enqueued and leave
