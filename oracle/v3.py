@@ -157,6 +157,63 @@ def gradient_matrix(m, nq=None):
     return B.tocsr()
 
 
+def _rows(m, cells, nq, fields, lift):
+    """Rows of the listed cells of A (fields = 3 -> 1) or B (1 -> 3): cell term
+    and the six faces of each cell, face by face as the assembled matrices
+    (interior faces with the low cell's geometry)."""
+    T = _tables(m, nq)
+    nb = m.n ** 3
+    out = np.zeros((3 if fields == 1 else 1, len(cells), nb))
+    for r, c in enumerate(cells):
+        grad, Phi, w = _cell_geo(T, m, c)
+        lift(out[:, r], c, [grad[a].T @ (w[:, None] * Phi) for a in range(3)], None, None)
+        for f in range(6):
+            d, s = divmod(f, 2)
+            cn = m.neighbor(c, f)
+            Tr = _face_geo(T, m, c, f)[0]
+            if cn >= 0:
+                _, dA, nrm = _face_geo(T, m, c if s == 1 else cn, 2 * d + 1)
+                Trn = _face_geo(T, m, cn, 2 * d + 1 - s)[0]
+            else:
+                _, dA, nrm = _face_geo(T, m, c, f)
+                Trn = None
+            sgn = 1.0 if s == 1 else -1.0
+            lift(out[:, r], c, None, (Tr, Trn, cn, dA, sgn * nrm), None)
+    return out
+
+
+def divergence_cells(m, u, cells, nq=None):
+    """(A u) on the rows of the listed cells, shape (len(cells), n^3)."""
+    U = np.asarray(u, dtype=np.float64).reshape(3, m.ncells, -1)
+
+    def lift(o, c, cellblk, face, _):
+        if cellblk is not None:
+            o[0] += sum(cellblk[a] @ U[a, c] for a in range(3))
+            return
+        Tr, Trn, cn, dA, nout = face
+        avg = [Tr @ U[a, c] if Trn is None else 0.5 * (Tr @ U[a, c] + Trn @ U[a, cn]) for a in range(3)]
+        o[0] -= Tr.T @ (dA * sum(nout[:, a] * avg[a] for a in range(3)))
+
+    return _rows(m, cells, nq, 3, lift)[0]
+
+
+def gradient_cells(m, p, cells, nq=None):
+    """(B p) on the rows of the listed cells, shape (3, len(cells), n^3)."""
+    P = np.asarray(p, dtype=np.float64).reshape(m.ncells, -1)
+
+    def lift(o, c, cellblk, face, _):
+        if cellblk is not None:
+            for a in range(3):
+                o[a] += cellblk[a] @ P[c]
+            return
+        Tr, Trn, cn, dA, nout = face
+        avg = Tr @ P[c] if Trn is None else 0.5 * (Tr @ P[c] + Trn @ P[cn])
+        for a in range(3):
+            o[a] -= Tr.T @ (dA * nout[:, a] * avg)
+
+    return _rows(m, cells, nq, 1, lift)
+
+
 def mass_apply(m, v):
     """M v for scalar fields stacked [n_fields][N] (flattened)."""
     T = sipg.Tables(m.k)

@@ -11,7 +11,8 @@ grading, degrees 1-7) and on a 6x4x6-cell curved channel; a second call
 reuses the metric and gives the same bits.  The div-div penalty (1e-12) and
 the element-local projection (CG with the point inverse mass to 1e-13,
 against the oracle's dense per-cell solve at 1e-9) on the same meshes up to
-degree 6.
+degree 6; all four on sampled cells of the full 48x32x48 curved channel
+against the oracle's row-restricted forms.
 """
 import math
 
@@ -99,4 +100,41 @@ def test_projection_refuses_degree_seven_on_curved_cells():
     t = torch.zeros(gm.ncells, dtype=torch.float64, device="cuda")
     with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
         gm.projection_solve(t, z, x=z.clone())
+    gm.close()
+
+
+def test_full_size_curved_channel_sampled():
+    """48x32x48 curved channel (k = 4): sampled cells of A u and B p (1e-12), tau_D
+    (1e-12) and the projection to rtol 1e-13 (1e-9) against the oracle's rows."""
+    require_gpu()
+    import torch
+    import paper_1607_01323_amd as dg
+    from tests.gpu_util import sample_cells
+    w = inp.CHANNEL_CURVED_C4
+    print(f"[case] curved V3c full-size {w.name}", flush=True)
+    om = curved.CurvedBoxMesh(w.degree, *w.cells, lx=w.lengths[0], ly=w.lengths[1], lz=w.lengths[2], y0=w.y0,
+                              periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma, amp=w.curve_amp)
+    gm = dg.Mesh.from_workload(w)
+    N = om.ndofs
+    u = inp.uniform(45, 3 * N)
+    u[:N] += 1.0
+    p = inp.uniform(46, N)
+    cells = sample_cells(w.cells, 8, 47)
+    d = host(gm.divergence(dev(u))).reshape(om.ncells, -1)[cells]
+    assert rel_err(d, v3.divergence_cells(om, u, cells)) < 1e-12
+    g = host(gm.gradient(dev(p))).reshape(3, om.ncells, -1)[:, cells]
+    assert rel_err(g, v3.gradient_cells(om, p, cells)) < 1e-12
+    tau = host(gm.divdiv_penalty(dev(u), 1.0, 1e-2))
+    U = u.reshape(3, om.ncells, -1)
+    for c in cells:
+        wc, V = v3._weights_volume(om, c)
+        ref = np.linalg.norm([wc @ U[a, c] for a in range(3)]) / V * V ** (1.0 / 3.0) * 1e-2
+        assert abs(tau[c] - ref) < 1e-12 * ref
+    rhs = inp.uniform(48, 3 * N)
+    t = 100.0 * tau
+    x = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    gm.projection_solve(dev(t), dev(rhs), x=x, rtol=1e-13, max_iter=500)
+    xs = host(x).reshape(3, om.ncells, -1)[:, cells]
+    ref = v3.projection_solve(om, t, rhs.reshape(3, om.ncells, -1)[:, cells], cells=cells)
+    assert rel_err(xs, ref) < 1e-9
     gm.close()

@@ -137,3 +137,17 @@ def test_curved_penalty_and_projection_reduce_to_affine():
     rhs = inp.uniform(52, 3 * am.ndofs)
     xa, xc = v3.projection_solve(am, ta, rhs), v3.projection_solve(cm, ta, rhs)
     assert np.abs(xa - xc).max() < 1e-11 * np.abs(xa).max()
+
+
+def test_row_restricted_operators_equal_the_assembled_rows():
+    kw = dict(lx=2.0, ly=2.0, lz=1.0, y0=-1.0, periodic=(True, False, True), y_tanh_gamma=1.3,
+              neumann=(False, False, False, True, False, False))
+    for m in (curved.CurvedBoxMesh(2, 3, 3, 2, amp=0.05, **kw), omesh.BoxMesh(2, 3, 3, 2, **kw)):
+        nb = m.n ** 3
+        u = inp.uniform(61, 3 * m.ndofs)
+        p = inp.uniform(62, m.ndofs)
+        cells = [0, 4, 8, 17]
+        Au = (v3.divergence_matrix(m) @ u).reshape(m.ncells, nb)[cells]
+        Bp = (v3.gradient_matrix(m) @ p).reshape(3, m.ncells, nb)[:, cells]
+        assert np.abs(v3.divergence_cells(m, u, cells) - Au).max() < 1e-13 * np.abs(Au).max()
+        assert np.abs(v3.gradient_cells(m, p, cells) - Bp).max() < 1e-13 * np.abs(Bp).max()
