@@ -653,6 +653,22 @@ dgmf_status dgmf_mass_apply(dgmf_mesh mesh, dgmf_dtype dtype, int n_fields, cons
 
 // Neumann sides need no check here: the ND average is the own trace on both
 // boundary parts (A, B), and the viscous coupling kernel skips Neumann faces.
+// Rows the curved-cell metric fill needs after a table's S, D and weights: the
+// GLL nodes, l(0) and l(1) (unit vectors: the end points are nodes), l'(0)
+// and l'(1); off receives their offsets {nodes, l(0), l'(0)}.
+static void append_curved_rows(const dgmf::Tables1D& t, std::vector<double>& h, int off[3]) {
+  const int n = t.n;
+  off[0] = static_cast<int>(h.size());
+  h.insert(h.end(), t.nodes.begin(), t.nodes.end());
+  off[1] = static_cast<int>(h.size());
+  h.resize(h.size() + 2 * n, 0.0);
+  h[off[1]] = 1.0;
+  h[off[1] + 2 * n - 1] = 1.0;
+  off[2] = static_cast<int>(h.size());
+  h.insert(h.end(), t.g0.begin(), t.g0.end());
+  h.insert(h.end(), t.g1.begin(), t.g1.end());
+}
+
 static dgmf_status v3_check(dgmf_mesh mesh, const char* who, bool curved_ok = false) {
   if (!mesh) return fail(DGMF_INVALID, "%s: null mesh", who);
   if (mesh->shear.on) return fail(DGMF_UNSUPPORTED, "%s: sheared meshes are not supported", who);
@@ -671,15 +687,8 @@ static dgmf_status curved_v3_geometry(dgmf_mesh mesh) {
   h.insert(h.end(), t.S.begin(), t.S.end());
   h.insert(h.end(), t.D.begin(), t.D.end());
   h.insert(h.end(), t.wq.begin(), t.wq.end());
-  const int o_nodes = static_cast<int>(h.size());
-  h.insert(h.end(), t.nodes.begin(), t.nodes.end());
-  const int o_e = static_cast<int>(h.size());
-  h.resize(h.size() + 2 * n, 0.0);
-  h[o_e] = 1.0;
-  h[o_e + 2 * n - 1] = 1.0;
-  const int o_g = static_cast<int>(h.size());
-  h.insert(h.end(), t.g0.begin(), t.g0.end());
-  h.insert(h.end(), t.g1.begin(), t.g1.end());
+  int rows[3];
+  append_curved_rows(t, h, rows);
   // S^{-1} (S is square here) for the inverse mass of the projection
   std::vector<long double> si;
   if (!invert(n, t.S.data(), si)) return fail(DGMF_INVALID, "curved V3c: singular interpolation matrix");
@@ -694,7 +703,7 @@ static dgmf_status curved_v3_geometry(dgmf_mesh mesh) {
   const double* hh[3] = {mesh->g64.h[0], mesh->g64.h[1], mesh->g64.h[2]};
   const double lo[3] = {0.0, mesh->desc.y0, 0.0};
   const double len[3] = {mesh->desc.lx, mesh->desc.ly, mesh->desc.lz};
-  const int off[6] = {o_nodes, 0, nq * n, 2 * nq * n, o_e, o_g};
+  const int off[6] = {rows[0], 0, nq * n, 2 * nq * n, rows[1], rows[2]};
   if ((st = launch_conv_fill_curved(n, nq, x0, hh, lo, len, mesh->desc.curve_amp, mesh->g64.nx, mesh->g64.ny,
                                     mesh->ncells, static_cast<const double*>(mesh->qtab.p), off, cm,
                                     cm + mesh->ncells * cper, nullptr)))
@@ -1039,16 +1048,8 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
     return fail(DGMF_INVALID, "convective_create: singular interpolation matrix");
   }
   h.insert(h.end(), mi.begin(), mi.end());
-  // curved-cell metric fill: GLL nodes, l(0), l(1), l'(0), l'(1)
-  const int o_nodes = static_cast<int>(h.size());
-  h.insert(h.end(), op->tab.nodes.begin(), op->tab.nodes.end());
-  const int o_e = static_cast<int>(h.size());
-  h.resize(h.size() + 2 * n, 0.0);
-  h[o_e] = 1.0;
-  h[o_e + 2 * n - 1] = 1.0;
-  const int o_g = static_cast<int>(h.size());
-  h.insert(h.end(), op->tab.g0.begin(), op->tab.g0.end());
-  h.insert(h.end(), op->tab.g1.begin(), op->tab.g1.end());
+  int rows[3];   // for the curved-cell metric fill
+  append_curved_rows(op->tab, h, rows);
   dgmf_status st = op->ctab.upload(h.data(), h.size() * sizeof(double));
   if (st != DGMF_OK) {
     delete op;
@@ -1069,7 +1070,7 @@ dgmf_status dgmf_convective_create(dgmf_mesh mesh, const dgmf_conv_desc* desc, d
     const double* hh[3] = {mesh->g64.h[0], mesh->g64.h[1], mesh->g64.h[2]};
     const double lo[3] = {0.0, mesh->desc.y0, 0.0};
     const double len[3] = {mesh->desc.lx, mesh->desc.ly, mesh->desc.lz};
-    const int off[6] = {o_nodes, 0, nq * n, 2 * nq * n, o_e, o_g};
+    const int off[6] = {rows[0], 0, nq * n, 2 * nq * n, rows[1], rows[2]};
     st = launch_conv_fill_curved(n, nq, x0, hh, lo, len, mesh->desc.curve_amp, mesh->g64.nx, mesh->g64.ny,
                                  mesh->ncells, static_cast<const double*>(op->ctab.p), off, cm,
                                  cm + mesh->ncells * cper, nullptr);
