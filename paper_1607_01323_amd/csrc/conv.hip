@@ -184,9 +184,9 @@ __device__ __forceinline__ void face_interp(const double* __restrict__ S, const 
 
 // Transposed tangential interpolation of `np` planes R ([q2][q1]) and
 // accumulation into sO at the face nodes: sO[comp][node(p1,p2)] += sum.
-// Plane pl is component pl % 3 of face (d, s), s = pl / 3 when s_all < 0,
+// Plane pl is component pl % NC of face (d, s), s = pl / NC when s_all < 0,
 // else s = s_all.
-template <int N, int Q>
+template <int N, int Q, int NC = 3>
 __device__ __forceinline__ void face_lift(const double* __restrict__ S, const double* R, double* L1, double* sO,
                                           int np, int d, int s_all, int tid, int nthr) {
   constexpr int N3 = N * N * N;
@@ -209,8 +209,8 @@ __device__ __forceinline__ void face_lift(const double* __restrict__ S, const do
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = L1[(pl * N + p2) * Q + q];
-    double* o = sO + (pl % 3) * N3;
-    const int side = s_all < 0 ? pl / 3 : s_all;
+    double* o = sO + (pl % NC) * N3;
+    const int side = s_all < 0 ? pl / NC : s_all;
 #pragma unroll kSweepUnroll<N, Q>
     for (int p1 = 0; p1 < N; ++p1) {
       double s = 0;
@@ -798,7 +798,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_div(const doub
   constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
   constexpr int XR = (3 * N2 * Q + 3 * N * Q2) > (3 * N * Q2 + 2 * N2 * Q) ? (3 * N2 * Q + 3 * N * Q2)
                                                                               : (3 * N * Q2 + 2 * N2 * Q);
-  constexpr int XF = 6 * N2 + 6 * N * Q + 6 * Q2 + Q2;   // planes [own | ext][comp], stage, traces, flux
+  constexpr int XF = 12 * N2 + 12 * N * Q + 12 * Q2 + 2 * Q2;   // planes [s][own | ext][comp], stage, traces, flux
   constexpr int X = XR > XF ? XR : XF;
   __shared__ double sU[3 * N3];
   __shared__ double sO[N3];
@@ -832,32 +832,38 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_div(const doub
                        fma(Mc[(3 * e + 1) * Q3 + q * Q2], u[1][q], Mc[(3 * e + 2) * Q3 + q * Q2] * u[2][q]));
   }
   cell_lift_grad<N, Q>(S, D, fe[0], fe[1], fe[2], own, qx, qy, sX, sX + 3 * N * Q2, sO, 1.0, tid, nthr);
-  // faces, one at a time: out -= phi ({{u}} . nu_out)
+  // faces, both of a direction at once (they touch disjoint node planes):
+  // out -= phi ({{u}} . nu_out)
 #pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const int d = f >> 1, s = f & 1;
-    double* P = sX;
-    double* F1 = sX + 6 * N2;
-    double* F2 = F1 + 6 * N * Q;
-    double* R = F2 + 6 * Q2;
-    const int64_t nb = conv_nb(g, cg, cell, d, s);
-    copy_plane<N>(sU, d, s, P, 1.0, tid, nthr);
-    if (nb >= 0) load_plane<N>(U, Nd, nb, d, 1 - s, P + 3 * N2, tid, nthr);
+  for (int d = 0; d < 3; ++d) {
+    double* P = sX;                   // 12 planes of N*N: [s][own | ext][comp]
+    double* F1 = sX + 12 * N2;
+    double* F2 = F1 + 12 * N * Q;
+    double* R = F2 + 12 * Q2;         // 2 planes: [s]
+    bool in0 = false, in1 = false;   // the face (d, s) has a neighbour
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int64_t nb = conv_nb(g, cg, cell, d, s);
+      (s ? in1 : in0) = nb >= 0;
+      copy_plane<N>(sU, d, s, P + (s * 2 + 0) * 3 * N2, 1.0, tid, nthr);
+      if (nb >= 0) load_plane<N>(U, Nd, nb, d, 1 - s, P + (s * 2 + 1) * 3 * N2, tid, nthr);
+      else copy_plane<N>(sU, d, s, P + (s * 2 + 1) * 3 * N2, 1.0, tid, nthr);   // own trace on boundary faces
+    }
     __syncthreads();
-    face_interp<N, Q>(S, P, F1, F2, nb >= 0 ? 6 : 3, tid, nthr);
-    const double sg = s ? -1.0 : 1.0;     // minus the outward sign
-    for (int pq = tid; pq < Q2; pq += nthr) {
-      const double* fm = g.fmet + (cell * 18 + f * 3) * Q2 + pq;
+    face_interp<N, Q>(S, P, F1, F2, 12, tid, nthr);
+    for (int e = tid; e < 2 * Q2; e += nthr) {
+      const int s = e / Q2, pq = e % Q2;
+      const double* fm = g.fmet + (cell * 18 + (2 * d + s) * 3) * Q2 + pq;
       double acc = 0.0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const double ua = nb >= 0 ? 0.5 * (F2[a * Q2 + pq] + F2[(3 + a) * Q2 + pq]) : F2[a * Q2 + pq];
-        acc = fma(fm[a * Q2], ua, acc);
+        const double uo = F2[((s * 2 + 0) * 3 + a) * Q2 + pq], ue = F2[((s * 2 + 1) * 3 + a) * Q2 + pq];
+        acc = fma(fm[a * Q2], (s ? in1 : in0) ? 0.5 * (uo + ue) : uo, acc);
       }
-      R[pq] = sg * acc;
+      R[s * Q2 + pq] = (s ? -1.0 : 1.0) * acc;   // minus the outward sign
     }
     __syncthreads();
-    face_lift<N, Q>(S, R, F1, sO, 1, d, s, tid, nthr);
+    face_lift<N, Q, 1>(S, R, F1, sO, 2, d, -1, tid, nthr);
   }
   for (int e = tid; e < N3; e += nthr) out[cell * N3 + e] = sO[e];
 }
@@ -869,7 +875,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_grad(const dou
   using SH = CShape<N, Q>;
   constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
   constexpr int XR = (N2 * Q + N * Q2) > (3 * N * Q2 + 2 * N2 * Q) ? (N2 * Q + N * Q2) : (3 * N * Q2 + 2 * N2 * Q);
-  constexpr int XF = 2 * N2 + 2 * N * Q + 2 * Q2 + 3 * Q2;   // planes [own | ext], stage, traces, fluxes
+  constexpr int XF = 4 * N2 + 4 * N * Q + 4 * Q2 + 6 * Q2;   // planes [s][own | ext], stage, traces, fluxes
   constexpr int X = XR > XF ? XR : XF;
   __shared__ double sP[N3];
   __shared__ double sO[3 * N3];
@@ -902,30 +908,36 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_grad(const dou
     cell_lift_grad<N, Q>(S, D, fe[0], fe[1], fe[2], own, qx, qy, sX, sX + 3 * N * Q2, sO + a * N3, 1.0, tid,
                          nthr);
   }
-  // faces, one at a time: out_a -= phi {{p}} nu_out,a
+  // faces, both of a direction at once: out_a -= phi {{p}} nu_out,a
 #pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const int d = f >> 1, s = f & 1;
-    double* P = sX;
-    double* F1 = sX + 2 * N2;
-    double* F2 = F1 + 2 * N * Q;
-    double* R = F2 + 2 * Q2;
-    const int64_t nb = conv_nb(g, cg, cell, d, s);
-    for (int e = tid; e < N2; e += nthr) {
-      P[e] = sP[face_node<N>(d, s, e % N, e / N)];
-      if (nb >= 0) P[N2 + e] = Pin[nb * N3 + face_node<N>(d, 1 - s, e % N, e / N)];
+  for (int d = 0; d < 3; ++d) {
+    double* P = sX;                   // 4 planes of N*N: [s][own | ext]
+    double* F1 = sX + 4 * N2;
+    double* F2 = F1 + 4 * N * Q;
+    double* R = F2 + 4 * Q2;          // 6 planes: [s][comp]
+    bool in0 = false, in1 = false;   // the face (d, s) has a neighbour
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int64_t nb = conv_nb(g, cg, cell, d, s);
+      (s ? in1 : in0) = nb >= 0;
+      for (int e = tid; e < N2; e += nthr) {
+        const double own = sP[face_node<N>(d, s, e % N, e / N)];
+        P[(s * 2 + 0) * N2 + e] = own;
+        P[(s * 2 + 1) * N2 + e] = nb >= 0 ? Pin[nb * N3 + face_node<N>(d, 1 - s, e % N, e / N)] : own;
+      }
     }
     __syncthreads();
-    face_interp<N, Q>(S, P, F1, F2, nb >= 0 ? 2 : 1, tid, nthr);
-    const double sg = s ? -1.0 : 1.0;     // minus the outward sign
-    for (int pq = tid; pq < Q2; pq += nthr) {
-      const double* fm = g.fmet + (cell * 18 + f * 3) * Q2 + pq;
-      const double pa = nb >= 0 ? 0.5 * (F2[pq] + F2[Q2 + pq]) : F2[pq];
+    face_interp<N, Q>(S, P, F1, F2, 4, tid, nthr);
+    for (int e = tid; e < 2 * Q2; e += nthr) {
+      const int s = e / Q2, pq = e % Q2;
+      const double* fm = g.fmet + (cell * 18 + (2 * d + s) * 3) * Q2 + pq;
+      const double po = F2[(s * 2 + 0) * Q2 + pq], pe = F2[(s * 2 + 1) * Q2 + pq];
+      const double pa = (s ? -1.0 : 1.0) * ((s ? in1 : in0) ? 0.5 * (po + pe) : po);   // minus the outward sign
 #pragma unroll
-      for (int a = 0; a < 3; ++a) R[a * Q2 + pq] = sg * fm[a * Q2] * pa;
+      for (int a = 0; a < 3; ++a) R[(s * 3 + a) * Q2 + pq] = fm[a * Q2] * pa;
     }
     __syncthreads();
-    face_lift<N, Q>(S, R, F1, sO, 3, d, s, tid, nthr);
+    face_lift<N, Q>(S, R, F1, sO, 6, d, -1, tid, nthr);
   }
   for (int e = tid; e < 3 * N3; e += nthr) {
     const int a = e / N3, r = e % N3;
