@@ -9,8 +9,9 @@ J^{-1} and Nanson's formula point by point (``oracle.convective`` on an
 norm) of the oracle on small meshes (every entry: periodic sides, no-slip
 walls, outflow sides, tanh grading, degrees 1-6) and on sampled cells of the
 full curved channel (48x32x48, k = 4, 7 points); free-stream preservation on a
-32^3-cell degree-5 curved periodic mesh; the fused substep refuses curved
-meshes.
+32^3-cell degree-5 curved periodic mesh; at full size the Euler identity of
+the VJP and central differences along interior-node directions; the fused
+substep refuses curved meshes.
 """
 import math
 
@@ -111,4 +112,34 @@ def test_free_stream_at_full_size():
     Ur = U + 0.1 * torch.as_tensor(inp.uniform(36, 3 * n), device="cuda")
     C1 = op.apply(Ur)
     assert C0.abs().max().item() < 1e-12 * C1.abs().max().item()
+    gm.close()
+
+
+def test_vjp_identities_at_full_size_on_curved_cells():
+    """On the 48x32x48 curved channel: the Euler identity <VJP(U,w), U> = 2 <w, C(U)>
+    (C is homogeneous of degree 2; exact) and central differences (eps = 1e-6) of
+    <w, C(U)> along 10 directions supported on cell-interior nodes, which move no
+    face trace and cross no kink of the Lax-Friedrichs max (agreement to 1e-8)."""
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    from tests.test_gpu_convective import _interior_mask
+    w = inp.CHANNEL_CURVED_C4
+    print(f"[case] curved convective VJP identities {w.name}", flush=True)
+    gm = dg.Mesh.from_workload(w)
+    op = dg.ConvectiveOperator(gm)
+    N = gm.ndofs
+    U = 0.3 * dev(inp.uniform(37, 3 * N))
+    U[:N] += 1.0
+    Wt = dev(inp.uniform(38, 3 * N))
+    g = op.vjp(U, Wt)
+    C = op.apply(U)
+    gu = torch.dot(g, U).item()
+    assert abs(gu - 2 * torch.dot(Wt, C).item()) < 1e-12 * abs(gu)
+    mask = dev(_interior_mask(w.degree + 1, gm.ncells))
+    eps = 1e-6
+    for j in range(10):
+        d = dev(inp.uniform(200 + j, 3 * N)) * mask
+        fd = torch.dot(Wt, op.apply(U + eps * d) - op.apply(U - eps * d)).item() / (2 * eps)
+        an = torch.dot(g, d).item()
+        assert abs(fd - an) < 1e-8 * abs(an)
     gm.close()
