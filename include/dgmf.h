@@ -65,7 +65,7 @@ typedef enum {
   DGMF_NOT_CONVERGED = 4,  /* CG reached max_iter; outputs hold the last iterate */
   DGMF_BREAKDOWN = 5,      /* CG: <r,z> <= 0 or <p,Ap> <= 0 (preconditioner/operator not SPD) */
   DGMF_NONFINITE = 6,      /* CG: NaN/Inf in the data or in a scalar of the iteration */
-  DGMF_UNSUPPORTED = 7     /* valid request outside what this build implements */
+  DGMF_UNSUPPORTED = 7     /* valid request outside what the library implements */
 } dgmf_status;
 
 typedef enum { DGMF_F64 = 0, DGMF_F32 = 1 } dgmf_dtype;

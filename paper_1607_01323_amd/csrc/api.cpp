@@ -826,7 +826,7 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
   if (desc->n_q != 0 && desc->n_q != n)
     return fail(DGMF_UNSUPPORTED, "sipg_create: n_q must be 0 or k+1 (got %d)", desc->n_q);
   if (mesh->ndofs >= (int64_t(1) << 31))
-    return fail(DGMF_UNSUPPORTED, "sipg_create: %lld DoF per field exceed the 32-bit indexing of this build",
+    return fail(DGMF_UNSUPPORTED, "sipg_create: %lld DoF per field exceed the 32-bit indexing of the kernels",
                 static_cast<long long>(mesh->ndofs));
   if (!std::isfinite(desc->mass_coeff) || !std::isfinite(desc->diff_coeff) || !std::isfinite(desc->penalty_scale) ||
       desc->mass_coeff < 0 || desc->diff_coeff < 0 || !(desc->penalty_scale > 0))
