@@ -105,6 +105,7 @@ __global__ void __launch_bounds__(1024) k_scalar(CgState* st, const double* __re
       st->iter = 0;
       if (!isfinite(s1) || !isfinite(st->bnorm2)) st->status = DGMF_NONFINITE;
       else if (s1 <= st->tol2) st->status = CONVERGED;
+      else if (st->max_iter <= 0) st->status = DGMF_NOT_CONVERGED;   // no iteration allowed: x stays x0
       else if (!(s0 > 0)) st->status = isfinite(s0) ? DGMF_BREAKDOWN : DGMF_NONFINITE;
       break;
     case M_ALPHA: {  // s0 = <p,Hp>, s1 = sum(Hp), s2 = sum(p)
@@ -1066,57 +1067,15 @@ struct Solver {
   }
 };
 
-}  // namespace
-
-}  // namespace dgmf
-
-using namespace dgmf;
-
-extern "C" {
-
-dgmf_status dgmf_cg_workspace_bytes(dgmf_op op, const dgmf_cg_params* params, size_t* bytes) {
-  dgmf_status e = validate(op, params);
-  if (e) return e;
-  if (!bytes) return fail(DGMF_INVALID, "cg_workspace_bytes: null output");
-  const size_t es = params->precond_dtype == DGMF_F32 ? 4 : 8;
-  *bytes = make_layout(op->mesh->ndofs, nparts_for(op), params->precond == 1, es).total;
-  return DGMF_OK;
-}
-
-dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params, void* workspace,
-                          size_t workspace_bytes, hipStream_t stream, dgmf_cg_result* out) {
-  dgmf_status e = validate(op, params);
-  if (e) return e;
-  if (!b || !x || !workspace || !out) return fail(DGMF_INVALID, "cg_solve: null argument");
-  if (reinterpret_cast<uintptr_t>(b) % 8 || reinterpret_cast<uintptr_t>(x) % 8 ||
-      reinterpret_cast<uintptr_t>(workspace) % 256)
-    return fail(DGMF_INVALID, "cg_solve: misaligned argument (vectors 8 B, workspace 256 B)");
+// The solve proper, on a workspace laid out as L.  Every non-OK return is
+// turned into out->status and a synchronised stream by the caller.
+dgmf_status cg_run(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params, char* ws,
+                   const Layout& L, hipStream_t stream, dgmf_cg_result* out) {
   const int64_t N = op->mesh->ndofs;
   const bool cheb = params->precond == 1;
   const bool poly = params->precond != 0;   // preconditioner kernels write z and the partials
-  const size_t es = params->precond_dtype == DGMF_F32 ? 4 : 8;
-  Layout L = make_layout(N, nparts_for(op), cheb, es);
-  if (workspace_bytes < L.total)
-    return fail(DGMF_INVALID, "cg_solve: workspace of %zu bytes, need %zu", workspace_bytes, L.total);
-  {
-    const char* wb = static_cast<const char*>(workspace);
-    const char* xb = reinterpret_cast<const char*>(x);
-    const char* bb = reinterpret_cast<const char*>(b);
-    if ((xb < wb + L.total && wb < xb + 8 * N) || (bb < wb + L.total && wb < bb + 8 * N) ||
-        (xb < bb + 8 * N && bb < xb + 8 * N))
-      return fail(DGMF_INVALID, "cg_solve: b, x and workspace must not overlap");
-  }
-  int prev_dev = -1;
-  (void)hipGetDevice(&prev_dev);
-  if (prev_dev != op->mesh->device) DGMF_HIP_TRY(hipSetDevice(op->mesh->device));
-  struct Restore {
-    int d;
-    ~Restore() { if (d >= 0) (void)hipSetDevice(d); }
-  } restore{prev_dev != op->mesh->device ? prev_dev : -1};
-
-  std::memset(out, 0, sizeof(*out));
-  out->status = DGMF_OK;
-  Solver S{op, *params, static_cast<char*>(workspace), L, stream, N, nparts_for(op), op->mesh->desc.degree + 1,
+  dgmf_status e = DGMF_OK;
+  Solver S{op, *params, ws, L, stream, N, nparts_for(op), op->mesh->desc.degree + 1,
            nullptr, nullptr};
   S.st = S.at<CgState>(L.state);
   S.partials = S.at<double>(L.partials);
@@ -1222,6 +1181,63 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
                 names[out->status], out->iterations, out->rel_residual);
   }
   return DGMF_OK;
+}
+
+}  // namespace
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" {
+
+dgmf_status dgmf_cg_workspace_bytes(dgmf_op op, const dgmf_cg_params* params, size_t* bytes) {
+  dgmf_status e = validate(op, params);
+  if (e) return e;
+  if (!bytes) return fail(DGMF_INVALID, "cg_workspace_bytes: null output");
+  const size_t es = params->precond_dtype == DGMF_F32 ? 4 : 8;
+  *bytes = make_layout(op->mesh->ndofs, nparts_for(op), params->precond == 1, es).total;
+  return DGMF_OK;
+}
+
+dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream, dgmf_cg_result* out) {
+  dgmf_status e = validate(op, params);
+  if (e) return e;
+  if (!b || !x || !workspace || !out) return fail(DGMF_INVALID, "cg_solve: null argument");
+  if (reinterpret_cast<uintptr_t>(b) % 8 || reinterpret_cast<uintptr_t>(x) % 8 ||
+      reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(DGMF_INVALID, "cg_solve: misaligned argument (vectors 8 B, workspace 256 B)");
+  const int64_t N = op->mesh->ndofs;
+  const bool cheb = params->precond == 1;
+  const size_t es = params->precond_dtype == DGMF_F32 ? 4 : 8;
+  Layout L = make_layout(N, nparts_for(op), cheb, es);
+  if (workspace_bytes < L.total)
+    return fail(DGMF_INVALID, "cg_solve: workspace of %zu bytes, need %zu", workspace_bytes, L.total);
+  {
+    const char* wb = static_cast<const char*>(workspace);
+    const char* xb = reinterpret_cast<const char*>(x);
+    const char* bb = reinterpret_cast<const char*>(b);
+    if ((xb < wb + L.total && wb < xb + 8 * N) || (bb < wb + L.total && wb < bb + 8 * N) ||
+        (xb < bb + 8 * N && bb < xb + 8 * N))
+      return fail(DGMF_INVALID, "cg_solve: b, x and workspace must not overlap");
+  }
+  int prev_dev = -1;
+  (void)hipGetDevice(&prev_dev);
+  if (prev_dev != op->mesh->device) DGMF_HIP_TRY(hipSetDevice(op->mesh->device));
+  struct Restore {
+    int d;
+    ~Restore() { if (d >= 0) (void)hipSetDevice(d); }
+  } restore{prev_dev != op->mesh->device ? prev_dev : -1};
+
+  std::memset(out, 0, sizeof(*out));
+  out->status = DGMF_OK;
+  e = cg_run(op, b, x, params, static_cast<char*>(workspace), L, stream, out);
+  if (e != DGMF_OK) {
+    (void)hipStreamSynchronize(stream);
+    out->status = e;
+  }
+  return e;
 }
 
 dgmf_status dgmf_precond_apply(dgmf_op op, const dgmf_cg_params* params, const double* r, double* z,

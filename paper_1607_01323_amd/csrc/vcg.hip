@@ -282,74 +282,83 @@ dgmf_status dgmf_viscous_cg_solve(dgmf_op op, const double* b, double* x, const 
   }
   DevScope dev(op->mesh->device);
   std::memset(out, 0, sizeof(*out));
-  char* ws = static_cast<char*>(workspace);
-  VState* st = reinterpret_cast<VState*>(ws + L.state);
-  double* part = reinterpret_cast<double*>(ws + L.part);
-  double* r = reinterpret_cast<double*>(ws + L.r);
-  double* z = reinterpret_cast<double*>(ws + L.z);
-  double* p = reinterpret_cast<double*>(ws + L.p);
-  double* q = reinterpret_cast<double*>(ws + L.q);
-  double* diag = reinterpret_cast<double*>(ws + L.diag);
-  double* dinv = reinterpret_cast<double*>(ws + L.dinv);
-  const dim3 G(kBlocks), B(kThreads);
-  dgmf_status e;
-  auto t0 = std::chrono::steady_clock::now();
-  VState init{};
-  init.tol2 = params->rtol * params->rtol;
-  init.max_iter = params->max_iter;
-  DGMF_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
-  if ((e = sipg_diag64(op, diag, stream))) return e;
-  hipLaunchKernelGGL(k_v_recip, G, B, 0, stream, diag, dinv, N);
-  DGMF_LAUNCH_CHECK("k_v_recip");
-  if ((e = apply_eps(op, x, q, stream))) return e;
-  hipLaunchKernelGGL(k_v_init, G, B, 0, stream, b, q, r, z, dinv, N, part);
-  DGMF_LAUNCH_CHECK("k_v_init");
-  if (mass) {   // z = M^{-1} r replaces the diagonal scaling, and <r, z> with it
-    if ((e = inv_mass3(op, r, z, stream))) return e;
-    hipLaunchKernelGGL(k_v_rz, G, B, 0, stream, r, z, 3 * N, part, 0, st, 1);
-    DGMF_LAUNCH_CHECK("k_v_rz");
-  }
-  hipLaunchKernelGGL(k_v_scalar, dim3(1), B, 0, stream, st, part, static_cast<int>(VM_INIT));
-  DGMF_LAUNCH_CHECK("k_v_scalar");
-  hipLaunchKernelGGL(k_v_pupdate, G, B, 0, stream, p, z, 3 * N, st, 1);
-  DGMF_LAUNCH_CHECK("k_v_pupdate");
-  VState h{};
-  DGMF_HIP_TRY(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, stream));
-  DGMF_HIP_TRY(hipStreamSynchronize(stream));
-  auto t1 = std::chrono::steady_clock::now();
-  const int batch = params->check_every > 0 ? params->check_every : 1;
-  while (h.status == V_RUNNING) {
-    for (int k = 0; k < batch; ++k) {
-      if ((e = apply_eps(op, p, q, stream))) return e;
-      hipLaunchKernelGGL(k_v_pq, G, B, 0, stream, p, q, 3 * N, part, st);
-      DGMF_LAUNCH_CHECK("k_v_pq");
-      hipLaunchKernelGGL(k_v_scalar, dim3(1), B, 0, stream, st, part, static_cast<int>(VM_ALPHA));
-      DGMF_LAUNCH_CHECK("k_v_scalar");
-      hipLaunchKernelGGL(k_v_update, G, B, 0, stream, x, r, p, q, z, dinv, N, part, st);
-      DGMF_LAUNCH_CHECK("k_v_update");
-      if (mass) {
-        if ((e = inv_mass3(op, r, z, stream))) return e;
-        hipLaunchKernelGGL(k_v_rz, G, B, 0, stream, r, z, 3 * N, part, 1, st, 0);
-        DGMF_LAUNCH_CHECK("k_v_rz");
-      }
-      hipLaunchKernelGGL(k_v_scalar, dim3(1), B, 0, stream, st, part, static_cast<int>(VM_BETA));
-      DGMF_LAUNCH_CHECK("k_v_scalar");
-      hipLaunchKernelGGL(k_v_pupdate, G, B, 0, stream, p, z, 3 * N, st, 0);
-      DGMF_LAUNCH_CHECK("k_v_pupdate");
+  // every non-OK return below leaves out->status equal to it and the stream drained
+  auto run = [&]() -> dgmf_status {
+    char* ws = static_cast<char*>(workspace);
+    VState* st = reinterpret_cast<VState*>(ws + L.state);
+    double* part = reinterpret_cast<double*>(ws + L.part);
+    double* r = reinterpret_cast<double*>(ws + L.r);
+    double* z = reinterpret_cast<double*>(ws + L.z);
+    double* p = reinterpret_cast<double*>(ws + L.p);
+    double* q = reinterpret_cast<double*>(ws + L.q);
+    double* diag = reinterpret_cast<double*>(ws + L.diag);
+    double* dinv = reinterpret_cast<double*>(ws + L.dinv);
+    const dim3 G(kBlocks), B(kThreads);
+    dgmf_status e;
+    auto t0 = std::chrono::steady_clock::now();
+    VState init{};
+    init.tol2 = params->rtol * params->rtol;
+    init.max_iter = params->max_iter;
+    DGMF_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
+    if ((e = sipg_diag64(op, diag, stream))) return e;
+    hipLaunchKernelGGL(k_v_recip, G, B, 0, stream, diag, dinv, N);
+    DGMF_LAUNCH_CHECK("k_v_recip");
+    if ((e = apply_eps(op, x, q, stream))) return e;
+    hipLaunchKernelGGL(k_v_init, G, B, 0, stream, b, q, r, z, dinv, N, part);
+    DGMF_LAUNCH_CHECK("k_v_init");
+    if (mass) {   // z = M^{-1} r replaces the diagonal scaling, and <r, z> with it
+      if ((e = inv_mass3(op, r, z, stream))) return e;
+      hipLaunchKernelGGL(k_v_rz, G, B, 0, stream, r, z, 3 * N, part, 0, st, 1);
+      DGMF_LAUNCH_CHECK("k_v_rz");
     }
+    hipLaunchKernelGGL(k_v_scalar, dim3(1), B, 0, stream, st, part, static_cast<int>(VM_INIT));
+    DGMF_LAUNCH_CHECK("k_v_scalar");
+    hipLaunchKernelGGL(k_v_pupdate, G, B, 0, stream, p, z, 3 * N, st, 1);
+    DGMF_LAUNCH_CHECK("k_v_pupdate");
+    VState h{};
     DGMF_HIP_TRY(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, stream));
     DGMF_HIP_TRY(hipStreamSynchronize(stream));
+    auto t1 = std::chrono::steady_clock::now();
+    const int batch = params->check_every > 0 ? params->check_every : 1;
+    while (h.status == V_RUNNING) {
+      for (int k = 0; k < batch; ++k) {
+        if ((e = apply_eps(op, p, q, stream))) return e;
+        hipLaunchKernelGGL(k_v_pq, G, B, 0, stream, p, q, 3 * N, part, st);
+        DGMF_LAUNCH_CHECK("k_v_pq");
+        hipLaunchKernelGGL(k_v_scalar, dim3(1), B, 0, stream, st, part, static_cast<int>(VM_ALPHA));
+        DGMF_LAUNCH_CHECK("k_v_scalar");
+        hipLaunchKernelGGL(k_v_update, G, B, 0, stream, x, r, p, q, z, dinv, N, part, st);
+        DGMF_LAUNCH_CHECK("k_v_update");
+        if (mass) {
+          if ((e = inv_mass3(op, r, z, stream))) return e;
+          hipLaunchKernelGGL(k_v_rz, G, B, 0, stream, r, z, 3 * N, part, 1, st, 0);
+          DGMF_LAUNCH_CHECK("k_v_rz");
+        }
+        hipLaunchKernelGGL(k_v_scalar, dim3(1), B, 0, stream, st, part, static_cast<int>(VM_BETA));
+        DGMF_LAUNCH_CHECK("k_v_scalar");
+        hipLaunchKernelGGL(k_v_pupdate, G, B, 0, stream, p, z, 3 * N, st, 0);
+        DGMF_LAUNCH_CHECK("k_v_pupdate");
+      }
+      DGMF_HIP_TRY(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, stream));
+      DGMF_HIP_TRY(hipStreamSynchronize(stream));
+    }
+    auto t2 = std::chrono::steady_clock::now();
+    out->iterations = h.iter;
+    out->rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    out->status = h.status == V_CONVERGED ? DGMF_OK : h.status;
+    out->setup_s = std::chrono::duration<double>(t1 - t0).count();
+    out->solve_s = std::chrono::duration<double>(t2 - t1).count();
+    if (out->status != DGMF_OK)
+      return fail(static_cast<dgmf_status>(out->status), "viscous_cg: status %d after %d iterations (rel. residual %g)",
+                  out->status, out->iterations, out->rel_residual);
+    return DGMF_OK;
+  };
+  const dgmf_status e = run();
+  if (e != DGMF_OK) {
+    (void)hipStreamSynchronize(stream);
+    out->status = e;
   }
-  auto t2 = std::chrono::steady_clock::now();
-  out->iterations = h.iter;
-  out->rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-  out->status = h.status == V_CONVERGED ? DGMF_OK : h.status;
-  out->setup_s = std::chrono::duration<double>(t1 - t0).count();
-  out->solve_s = std::chrono::duration<double>(t2 - t1).count();
-  if (out->status != DGMF_OK)
-    return fail(static_cast<dgmf_status>(out->status), "viscous_cg: status %d after %d iterations (rel. residual %g)",
-                out->status, out->iterations, out->rel_residual);
-  return DGMF_OK;
+  return e;
 }
 
 }  // extern "C"

@@ -146,6 +146,12 @@ def test_status_codes():
     out = gop.cg(dev(b), dev(np.zeros(om.ndofs)), rtol=1e-14, max_iter=3, project_mean=True,
                  raise_on_failure=False)
     assert out.status == dg.NOT_CONVERGED and out.iterations == 3
+    # max_iter = 0 runs no iteration: the guess comes back unchanged
+    x0 = inp.uniform(5, om.ndofs)
+    xg = dev(x0)
+    out = gop.cg(dev(b), xg, max_iter=0, project_mean=True, raise_on_failure=False)
+    assert out.status == dg.NOT_CONVERGED and out.iterations == 0
+    assert np.array_equal(xg.cpu().numpy(), x0)
     bn = b.copy()
     bn[7] = np.nan
     out = gop.cg(dev(bn), dev(np.zeros(om.ndofs)), project_mean=True, raise_on_failure=False)
