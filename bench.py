@@ -1,18 +1,23 @@
 """Benchmark of the matrix-free DG hot path on one MI355X.
 
-Headline (``value``): fp64 SIPG Helmholtz operator applications per second
-times DoF (DoF/s) on the 32^3-cell, degree-4 periodic cube (4.096M DoF,
-H = 1000 M + 0.01 A), inputs resident in HBM.  One step is one operator
+Headline (``value``): fp64 SIPG Poisson operator applications per second
+times DoF (DoF/s) on the 64^3-cell, degree-3 periodic cube (16.8M DoF, the
+largest SIPG-apply workload; its two vectors, 268 MB, exceed the 256 MB
+Infinity Cache), inputs resident in HBM.  One step is one operator
 application; the timed region is exactly ``--steps`` of them between two
 device synchronisations.  The same JSON line carries the roofline of that
 kernel (algorithmic bytes 16 B/DoF over the event-timed launch duration, the
-counter traffic when a committed profile matches the current kernel source),
-the fp32 apply, the CG time to 1e-10 (Jacobi fp64; mixed fp32-Chebyshev vs
-fp64), the convective forward + VJP throughput, the explicit convective
-substep U - dt M^{-1} C(U) (fused kernel vs the two-launch composition), the
-inverse mass apply, the variant-V3c divergence, gradient and element-local
-projection solve, the symmetric-gradient viscous operator, and the CPU oracle
-timed on a bounded sample.
+counter traffic when a committed profile matches the current kernel source)
+and, under ``extra``: the fp32 apply, cache-flushed timings, the apply at
+degrees 2..7, the Helmholtz apply on 32^3 cells at degree 4, the CG time to
+1e-10 (mixed fp32 multigrid / fp32 Chebyshev vs fp64 preconditioners), the
+convective forward + VJP throughput, the explicit convective substep, the
+inverse mass, the variant-V3c operators, the symmetric-gradient viscous
+operator, the channel meshes with the stored metric and on curved cells; and
+the CPU oracle (its block-stencil apply on all host cores) as baseline.
+
+``--only sweep|channel|convective`` runs one section alone (for profiler
+runs that need one kernel per configuration).
 """
 import argparse
 import json
@@ -84,28 +89,78 @@ def _traffic(kernel_key, n_launch_bytes_hint=None):
 
 
 def cpu_baseline(w, budget_s=10.0):
-    """The oracle's row-restricted dense-block apply on a sample of cells, 1 thread."""
+    """The oracle's block-stencil SIPG apply (all cells at once through BLAS) on the
+    headline workload, on every host core, repeated for about budget_s seconds."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
+    from threadpoolctl import threadpool_limits, threadpool_info
     import dgmf_inputs as inp
     from oracle import mesh as omesh, sipg as osipg
-    with threadpool_limits(limits=1):
+    cores = os.cpu_count() or 1
+    with threadpool_limits(limits=cores):
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
         om = omesh.BoxMesh(w.degree, *w.cells, lx=w.lengths[0], ly=w.lengths[1], lz=w.lengths[2], y0=w.y0,
                            periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma)
         op = osipg.SIPG(om, w.mass_coeff, w.diff_coeff, w.penalty_scale)
         u = inp.uniform(7, om.ndofs)
-        rng = np.random.default_rng(0)
-        op.apply_cells(u, [0])            # block set-up outside the timing
+        op.apply_block_stencil(u)           # block set-up and first touch outside the timing
         done, t0 = 0, time.perf_counter()
         while time.perf_counter() - t0 < budget_s:
-            cells = rng.integers(0, om.ncells, 256).tolist()
-            op.apply_cells(u, cells)
-            done += len(cells)
+            op.apply_block_stencil(u)
+            done += 1
         t = time.perf_counter() - t0
-    n3 = (w.degree + 1) ** 3
-    return {"value": done * n3 / t, "unit": "DoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} random cells of {w.name} ({done * n3} DoF rows) through the oracle's dense-block "
-                      f"SIPG apply, {t:.1f} s, 1 thread"}
+    return {"value": done * om.ndofs / t, "unit": "DoF/s", "cores": used, "kind": "oracle",
+            "sample": f"{done} whole applies of {w.name} ({om.ndofs} DoF each) through the oracle's "
+                      f"block-stencil SIPG apply (numpy/OpenBLAS, {used} threads of {cores} host cores), {t:.1f} s"}
+
+
+def _flushed(torch, fn, reps=20):
+    """Median duration of fn with a 512 MiB write before each call, so that no input
+    is resident in the 256 MB Infinity Cache."""
+    flush = torch.empty(512 * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+    s_ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    e_ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    fn()
+    for k in range(reps):
+        flush.fill_(float(k))
+        s_ev[k].record()
+        fn()
+        e_ev[k].record()
+    torch.cuda.synchronize()
+    del flush
+    return sorted(a.elapsed_time(b) for a, b in zip(s_ev, e_ev))[reps // 2] * 1e-3
+
+
+def apply_row(N, n, t, es):
+    """DoF/s, algorithmic GB/s and the two ceilings of one SIPG apply of t seconds."""
+    fl = reference_flops_per_dof(n) * N
+    peak = FP64_PEAK_TFLOPS if es == 8 else FP32_PEAK_TFLOPS
+    return {"us": t * 1e6, "dofs_per_s": N / t, "alg_GBps": es * 2.0 * N / t / 1e9,
+            "hbm_frac": es * 2.0 * N / t / 1e9 / HBM_PEAK_GBS, "ref_tflops": fl / t / 1e12,
+            "ref_flop_frac": fl / t / 1e12 / peak, "dofs": N}
+
+
+def sweep_measurements(dg, inp, torch):
+    """The periodic Poisson apply at degrees 2..7 (17-24M DoF each), fp64 and fp32,
+    and degree 5 on 32^3 cells with and without a cache flush."""
+    ex = {}
+    for w in inp.DEGREE_SWEEP + [inp.POISSON_32C_K5]:
+        m = dg.Mesh.from_workload(w)
+        op = dg.SipgOperator(m, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+        N, n = m.ndofs, w.degree + 1
+        v = torch.as_tensor(inp.uniform(3, N), device="cuda")
+        y = torch.empty_like(v)
+        ta = _events_time(lambda: op.apply(v, y), 30, 3)
+        row = apply_row(N, n, ta, 8)
+        if w is inp.POISSON_32C_K5:
+            row["flushed"] = apply_row(N, n, _flushed(torch, lambda: op.apply(v, y)), 8)
+        ex[f"apply_k{w.degree}_{w.cells[0]}c_f64"] = row
+        v32 = v.float()
+        y32 = torch.empty_like(v32)
+        tb = _events_time(lambda: op.apply(v32, y32), 30, 3)
+        ex[f"apply_k{w.degree}_{w.cells[0]}c_f32"] = apply_row(N, n, tb, 4)
+        del v, y, v32, y32
+        m.close()
+    return ex
 
 
 def main():
@@ -115,6 +170,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--only", choices=["sweep", "channel", "convective"],
+                    help="run one section alone and print its numbers (profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also fill (write) and sum (read) a 512 MiB buffer: counter calibration")
     args = ap.parse_args()
@@ -128,7 +185,17 @@ def main():
     import paper_1607_01323_amd as dg
     import dgmf_inputs as inp
 
-    w = inp.HELMHOLTZ_C1
+    if args.only:
+        if args.only == "sweep":
+            ex = sweep_measurements(dg, inp, torch)
+        elif args.only == "channel":
+            ex = channel_measurements(dg, inp, torch, inp.CHANNEL_C4, "c4", cg=False, conv=False)
+        else:
+            ex = convective_measurements(dg, inp, torch)
+        print(json.dumps({"only": args.only, "extra": ex}), flush=True)
+        return
+
+    w = inp.POISSON_C2
     mesh = dg.Mesh.from_workload(w)
     op = dg.SipgOperator(mesh, w.mass_coeff, w.diff_coeff, w.penalty_scale)
     N = mesh.ndofs
@@ -138,13 +205,15 @@ def main():
     value = N / t
     alg_bytes = 16.0 * N
     achieved = alg_bytes / t / 1e9
-    kernel = "k_sipg_zm_apply<5, double, true, true, false>"
+    kernel = "k_sipg_zm_apply<4, double, true, true, false>"
     traffic = _traffic(kernel)
     line = {
-        "metric": "SIPG apply DoF/s (fp64, Helmholtz)", "value": value, "unit": "DoF/s", "n_gpus": 1,
+        "metric": "SIPG apply DoF/s & HBM GB/s (FP64 vs FP32); CG time to 1e-10; conv fwd+VJP DoF/s",
+        "value": value, "unit": "DoF/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": w.name, "cells": list(w.cells), "degree": w.degree, "dofs": N,
+        "config": {"workload": w.name, "value_is": "fp64 SIPG Poisson apply, DoF per second",
+                   "cells": list(w.cells), "degree": w.degree, "dofs": N,
                    "mass_coeff": w.mass_coeff, "diff_coeff": w.diff_coeff, "penalty_scale": w.penalty_scale},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -164,19 +233,52 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
+def extra_measurements(dg, inp, torch, m2, op2, v, ta):
     ex = {}
+    # C2 (the headline mesh): fp32 apply, individually timed and cache-flushed launches
+    N2 = m2.ndofs
+    n2 = m2.degree + 1
+    yv = torch.empty_like(v)
+    med, mn = _events_each(lambda: op2.apply(v, yv), 50, 5)
+    ex["c2_apply_f64"] = dict(apply_row(N2, n2, ta, 8), single_launch_median_us=med * 1e6,
+                              single_launch_min_us=mn * 1e6)
+    ex["c2_apply_f64_flushed"] = apply_row(N2, n2, _flushed(torch, lambda: op2.apply(v, yv)), 8)
+    v32 = v.float()
+    yv32 = torch.empty_like(v32)
+    tb = _events_time(lambda: op2.apply(v32, yv32), 50, 5)
+    ex["c2_apply_f32"] = apply_row(N2, n2, tb, 4)
+    del v32, yv32, yv
+    ex.update(c2_cg_measurements(dg, inp, torch, m2, op2))
+    m2.close()
+    ex.update(c1_measurements(dg, inp, torch))
+    ex.update(sweep_measurements(dg, inp, torch))
+    ex.update(convective_measurements(dg, inp, torch))
+    ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4, "c4"))
+    ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4_SMALL, "c4small", cg=False))
+    ex.update(pressure_measurements(dg, inp, torch, inp.CHANNEL_PRESSURE_C4, "c4p"))
+    ex.update(curved_measurements(dg, inp, torch, inp.CHANNEL_CURVED_C4, "c4c"))
+    return ex
+
+
+def c1_measurements(dg, inp, torch):
+    """Helmholtz on 32^3 cells at degree 4 (4.1M DoF; its vectors fit the Infinity
+    Cache, so the flushed timing is the HBM figure), its CG, and the viscous
+    operator in the symmetric-gradient form."""
+    ex = {}
+    w = inp.HELMHOLTZ_C1
+    mesh_c1 = dg.Mesh.from_workload(w)
+    op_c1 = dg.SipgOperator(mesh_c1, w.mass_coeff, w.diff_coeff, w.penalty_scale)
     N = mesh_c1.ndofs
+    n = w.degree + 1
+    u_c1 = torch.as_tensor(inp.uniform(7, N), device="cuda")
+    y1 = torch.empty_like(u_c1)
+    t_c1 = _events_time(lambda: op_c1.apply(u_c1, y1), 100, 5)
+    ex["c1_apply_f64"] = apply_row(N, n, t_c1, 8)
+    ex["c1_apply_f64_flushed"] = apply_row(N, n, _flushed(torch, lambda: op_c1.apply(u_c1, y1)), 8)
     u32 = u_c1.float()
     y32 = torch.empty_like(u32)
     t32 = _events_time(lambda: op_c1.apply(u32, y32), 100, 5)
-    ex["c1_apply_f32"] = {"dofs_per_s": N / t32, "alg_GBps": 8.0 * N / t32 / 1e9, "us": t32 * 1e6}
-    y1 = torch.empty_like(u_c1)
-    med, mn = _events_each(lambda: op_c1.apply(u_c1, y1), 50, 5)
-    fl1 = reference_flops_per_dof(mesh_c1.degree + 1) * N
-    ex["c1_apply_f64"] = {"dofs_per_s": N / t_c1, "alg_GBps": 16.0 * N / t_c1 / 1e9, "us": t_c1 * 1e6,
-                          "ref_tflops": fl1 / t_c1 / 1e12, "fp64_frac": fl1 / t_c1 / 1e12 / FP64_PEAK_TFLOPS,
-                          "single_launch_median_us": med * 1e6, "single_launch_min_us": mn * 1e6}
+    ex["c1_apply_f32"] = apply_row(N, n, t32, 4)
     # symmetric-gradient viscous operator on a velocity (3 scalar applies + the coupling kernel);
     # algorithmic bytes 48 per velocity node (3 reads, 3 writes)
     Uv = torch.as_tensor(inp.uniform(12, 3 * N), device="cuda")
@@ -184,79 +286,44 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     tv = _events_time(lambda: op_c1.viscous_apply(Uv, Yv), 20, 3)
     ex["c1_viscous_eps"] = {"us": tv * 1e6, "velocity_nodes_per_s": N / tv, "alg_GBps": 48.0 * N / tv / 1e9,
                             "vs_three_scalar_applies": tv / (3 * t_c1)}
-    # the implicit viscous step in that form: Jacobi PCG to 1e-10 from zero
-    Yv.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = op_c1.viscous_cg(Uv, Yv, rtol=1e-10, max_iter=1000, check_every=8, raise_on_failure=False)
-    torch.cuda.synchronize()
-    ex["c1_viscous_cg"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations, "status": out.status,
-                           "solve_s": out.solve_s, "rel_residual": out.rel_residual}
-    Yv.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = op_c1.viscous_cg(Uv, Yv, rtol=1e-10, max_iter=1000, check_every=8, precond="mass", raise_on_failure=False)
-    torch.cuda.synchronize()
-    ex["c1_viscous_cg_mass"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
-                                "status": out.status, "solve_s": out.solve_s}
+    # the implicit viscous step in that form: Jacobi and inverse-mass PCG to 1e-10 from zero
+    for name, pc in (("c1_viscous_cg", "jacobi"), ("c1_viscous_cg_mass", "mass")):
+        Yv.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = op_c1.viscous_cg(Uv, Yv, rtol=1e-10, max_iter=1000, check_every=8, precond=pc, raise_on_failure=False)
+        torch.cuda.synchronize()
+        ex[name] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations, "status": out.status,
+                    "solve_s": out.solve_s, "rel_residual": out.rel_residual}
     del Uv, Yv
-    # the same apply with a 512 MiB write between repetitions, so that its 33 MB
-    # working set is not resident in the 256 MB Infinity Cache
-    flush = torch.empty(512 * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
-    s_ev = [torch.cuda.Event(enable_timing=True) for _ in range(20)]
-    e_ev = [torch.cuda.Event(enable_timing=True) for _ in range(20)]
-    y_c1 = torch.empty_like(u_c1)
-    for k in range(20):
-        flush.fill_(float(k))
-        s_ev[k].record()
-        op_c1.apply(u_c1, y_c1)
-        e_ev[k].record()
-    torch.cuda.synchronize()
-    tf = sorted(a.elapsed_time(b) for a, b in zip(s_ev, e_ev))[10] * 1e-3
-    del flush
-    ex["c1_apply_f64_flushed"] = {"dofs_per_s": N / tf, "alg_GBps": 16.0 * N / tf / 1e9, "us": tf * 1e6,
-                                  "hbm_frac": 16.0 * N / tf / 1e9 / HBM_PEAK_GBS}
-    # CG on C1: Jacobi fp64 from a random guess, b = (f, phi) through the library's quadrature
+    # CG on C1 from a random guess, b = (f, phi) through the library's quadrature
     qp = op_c1.quadrature_points()
-    f = inp.helm_rhs(inp.HELMHOLTZ_C1.mass_coeff, inp.HELMHOLTZ_C1.diff_coeff)
+    f = inp.helm_rhs(w.mass_coeff, w.diff_coeff)
     fq = torch.as_tensor(f(*[qp[i].cpu().numpy() for i in range(3)]), device="cuda")
     b = op_c1.integrate(fq)
-    x = torch.as_tensor(inp.uniform(11, N), device="cuda")
-    t0 = time.perf_counter()
-    out = op_c1.cg(b, x, rtol=1e-10, max_iter=5000, check_every=16)
-    torch.cuda.synchronize()
-    ex["c1_cg_jacobi_f64"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
-                              "setup_s": out.setup_s, "solve_s": out.solve_s, "rel_residual": out.rel_residual}
-    x = torch.as_tensor(inp.uniform(11, N), device="cuda")
-    t0 = time.perf_counter()
-    out = op_c1.cg(b, x, rtol=1e-10, max_iter=5000, check_every=16, precond="mass")
-    torch.cuda.synchronize()
-    ex["c1_cg_mass_f64"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
-                            "setup_s": out.setup_s, "solve_s": out.solve_s, "rel_residual": out.rel_residual}
-    # C2: fp64 and fp32 apply, mixed vs fp64 CG to 1e-10
-    w2 = inp.POISSON_C2
-    m2 = dg.Mesh.from_workload(w2)
-    op2 = dg.SipgOperator(m2, w2.mass_coeff, w2.diff_coeff, w2.penalty_scale)
+    for name, pc in (("c1_cg_jacobi_f64", "jacobi"), ("c1_cg_mass_f64", "mass")):
+        x = torch.as_tensor(inp.uniform(11, N), device="cuda")
+        t0 = time.perf_counter()
+        out = op_c1.cg(b, x, rtol=1e-10, max_iter=5000, check_every=16, precond=pc)
+        torch.cuda.synchronize()
+        ex[name] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
+                    "setup_s": out.setup_s, "solve_s": out.solve_s, "rel_residual": out.rel_residual}
+    mesh_c1.close()
+    return ex
+
+
+def c2_cg_measurements(dg, inp, torch, m2, op2):
+    """PCG to 1e-10 on the headline mesh: the configured smooth right-hand side
+    (nearly one eigenmode) and a random one; each solver runs twice and the
+    faster run is kept, so set-up that an operator keeps (the multigrid
+    hierarchy) is reported once as its own row."""
+    ex = {}
     N2 = m2.ndofs
-    v = torch.as_tensor(inp.uniform(3, N2), device="cuda")
-    yv = torch.empty_like(v)
-    ta = _events_time(lambda: op2.apply(v, yv), 50, 5)
-    v32 = v.float()
-    yv32 = torch.empty_like(v32)
-    tb = _events_time(lambda: op2.apply(v32, yv32), 50, 5)
-    fl2 = reference_flops_per_dof(w2.degree + 1) * N2
-    ex["c2_apply_f64"] = {"dofs_per_s": N2 / ta, "alg_GBps": 16.0 * N2 / ta / 1e9, "us": ta * 1e6,
-                          "hbm_frac": 16.0 * N2 / ta / 1e9 / HBM_PEAK_GBS,
-                          "ref_tflops": fl2 / ta / 1e12, "fp64_frac": fl2 / ta / 1e12 / FP64_PEAK_TFLOPS}
-    ex["c2_apply_f32"] = {"dofs_per_s": N2 / tb, "alg_GBps": 8.0 * N2 / tb / 1e9, "us": tb * 1e6,
-                          "hbm_frac": 8.0 * N2 / tb / 1e9 / HBM_PEAK_GBS,
-                          "ref_tflops": fl2 / tb / 1e12, "fp32_frac": fl2 / tb / 1e12 / FP32_PEAK_TFLOPS}
     qp = op2.quadrature_points()
     fq = torch.as_tensor(inp.poisson_rhs_sin3(*[qp[i].cpu().numpy() for i in range(3)]), device="cuda")
     del qp
     b_sin = op2.integrate(fq)
     del fq
-    # the configured smooth right-hand side (nearly one eigenmode) and a random one
     b_rand = torch.as_tensor(inp.uniform(5, N2), device="cuda")
     for rhs_name, b2 in (("sinrhs", b_sin), ("randrhs", b_rand)):
         for name, kw in (("mixed_f32mg", dict(precond="multigrid", precond_dtype=torch.float32)),
@@ -275,8 +342,13 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
                     best = {"time_s": tt, "iterations": out.iterations, "setup_s": out.setup_s,
                             "solve_s": out.solve_s, "rel_residual": out.rel_residual, "lambda_max": out.lambda_max}
             ex[f"c2_cg_{rhs_name}_{name}"] = best
-    m2.close()
-    # convective forward + VJP on the 32^3-cell degree-5 periodic cube (n_q = 9)
+    return ex
+
+
+def convective_measurements(dg, inp, torch):
+    """Convective forward + VJP on the 32^3-cell degree-5 periodic cube (n_q = 9),
+    the explicit substep and the V3c operators on the same mesh."""
+    ex = {}
     w3 = inp.CONVECTIVE_C3
     m3 = dg.Mesh.from_workload(w3)
     op3 = dg.ConvectiveOperator(m3, n_q=w3.conv_points)
@@ -285,6 +357,7 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     U = torch.stack([torch.sin(two_pi * X[0]) * torch.cos(two_pi * X[1]) * torch.cos(two_pi * X[2]),
                      -torch.cos(two_pi * X[0]) * torch.sin(two_pi * X[1]) * torch.cos(two_pi * X[2]),
                      torch.zeros_like(X[0])]).reshape(-1)
+    del X
     U += 0.01 * torch.as_tensor(inp.uniform(5, 3 * m3.ndofs), device="cuda")
     Wc = torch.as_tensor(inp.uniform(8, 3 * m3.ndofs), device="cuda")
     Cout = torch.empty_like(U)
@@ -297,10 +370,6 @@ def extra_measurements(dg, inp, torch, mesh_c1, op_c1, u_c1, t_c1):
     ex.update(step_measurements(m3, op3, U, Cout, "c3"))
     ex.update(v3_measurements(m3, U, "c3"))
     m3.close()
-    ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4, "c4"))
-    ex.update(channel_measurements(dg, inp, torch, inp.CHANNEL_C4_SMALL, "c4small", cg=False))
-    ex.update(pressure_measurements(dg, inp, torch, inp.CHANNEL_PRESSURE_C4, "c4p"))
-    ex.update(curved_measurements(dg, inp, torch, inp.CHANNEL_CURVED_C4, "c4c"))
     return ex
 
 
@@ -488,7 +557,7 @@ def metric_bytes_per_launch(n, ncells, es):
     return ncells * es * (2 * n ** 3 + 7 * n ** 3 + 21 * n ** 2 + 3)
 
 
-def channel_measurements(dg, inp, torch, w, tag, cg=True):
+def channel_measurements(dg, inp, torch, w, tag, cg=True, conv=True):
     """Stretched channel with the stored quadrature-point metric: apply (fp64, fp32),
     Helmholtz PCG to 1e-10 (mixed vs fp64), convective forward + VJP on the
     perturbed laminar profile."""
@@ -533,6 +602,9 @@ def channel_measurements(dg, inp, torch, w, tag, cg=True):
                     best = {"time_s": tt, "iterations": out.iterations, "setup_s": out.setup_s,
                             "solve_s": out.solve_s, "rel_residual": out.rel_residual, "lambda_max": out.lambda_max}
             ex[f"{tag}_cg_{name}"] = best
+    if not conv:
+        m.close()
+        return ex
     opc = dg.ConvectiveOperator(m, n_q=w.conv_points)
     X = m.node_coords()
     U = torch.stack([1.0 - X[1] ** 2, torch.zeros_like(X[0]), torch.zeros_like(X[0])]).reshape(-1)

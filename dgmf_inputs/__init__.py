@@ -108,8 +108,16 @@ CHANNEL_CURVED_C4 = Workload("channel_curved_48x32x48_k4", 4, (48, 32, 48), leng
                              y0=-1.0, periodic=(True, False, True), y_tanh_gamma=1.8, store_qp_metric=True,
                              mass_coeff=1000.0, diff_coeff=0.01, curve_amp=0.02)
 
+# the periodic Poisson apply at degrees 2..7 on meshes of 17-24M DoF (every
+# fp64 working set above the 256 MB Infinity Cache): cost per DoF against k
+DEGREE_SWEEP = [Workload(f"poisson_periodic_{c}c_k{k}", k, (c, c, c), penalty_scale=1.0 / 3.0)
+                for k, c in ((2, 88), (3, 64), (4, 56), (5, 48), (6, 40), (7, 32))]
+# degree 5 on 32^3 cells (7.08M DoF, the convective workload's mesh)
+POISSON_32C_K5 = Workload("poisson_periodic_32c_k5", 5, (32, 32, 32), penalty_scale=1.0 / 3.0)
+
 WORKLOADS = {w.name: w for w in (POISSON_C0, HELMHOLTZ_C1, POISSON_C2, CONVECTIVE_C3, CHANNEL_C4,
-                                 CHANNEL_C4_SMALL, CHANNEL_PRESSURE_C4, CHANNEL_CURVED_C4)}
+                                 CHANNEL_C4_SMALL, CHANNEL_PRESSURE_C4, CHANNEL_CURVED_C4, POISSON_32C_K5,
+                                 *DEGREE_SWEEP)}
 
 
 def scaled(w, cells, name=None):

@@ -138,6 +138,19 @@ def penalty_per_cell(mesh, penalty_scale=1.0):
     """tau_e = s (k+1)^2 (A_int/2 + A_bnd)/V per cell (eq. taue; A_bnd: Dirichlet and
     Neumann faces alike)."""
     k = mesh.k
+    if mesh.shear is None:
+        # axis-aligned box cells: face areas are products of two edge lengths,
+        # all cells at once (the same formula as the loop below)
+        cx, cy, cz = mesh.cell_coords(np.arange(mesh.ncells))
+        idx = (cx, cy, cz)
+        h = [np.diff(mesh.verts[d])[idx[d]] for d in range(3)]
+        a = np.zeros(mesh.ncells)
+        for d in range(3):
+            area = h[(d + 1) % 3] * h[(d + 2) % 3]
+            for s, end in ((0, 0), (1, mesh.nc[d] - 1)):
+                bnd = (~np.bool_(mesh.periodic[d])) & (idx[d] == end)
+                a += np.where(bnd, area, 0.5 * area)
+        return penalty_scale * (k + 1) ** 2 * a / (h[0] * h[1] * h[2])
     tau = np.empty(mesh.ncells)
     for c in range(mesh.ncells):
         a = 0.0
@@ -239,6 +252,35 @@ class SIPG:
                     y += B[nb:, :nb] @ U[cn] + B[nb:, nb:] @ U[c]
             out[r] = y
         return out
+
+    def apply_block_stencil(self, u):
+        """H u on a uniform periodic box mesh (every cell a translate of one cell,
+        one penalty): the assembled matrix is one diagonal block plus, per
+        direction, the two off-diagonal blocks of the face matrix, so the product
+        is a few dense block products over all cells at once.  Same operator as
+        ``assemble``; u and the result are flat [N]."""
+        m = self.mesh
+        if not all(m.periodic) or m.shear is not None or m.gamma > 0:
+            raise ValueError("block stencil needs a uniform periodic box mesh")
+        nb = m.n ** 3
+        U = u.reshape(m.ncells, nb)
+        cells = np.arange(m.ncells)
+        cx, cy, cz = m.cell_coords(cells)
+        nx, ny, nz = m.nc
+        diag = self.cell_block(0).copy()
+        Y = np.zeros_like(U)
+        for d in range(3):
+            idx = [cx, cy, cz]
+            up, dn = list(idx), list(idx)
+            up[d] = (idx[d] + 1) % m.nc[d]
+            dn[d] = (idx[d] - 1) % m.nc[d]
+            plus = m.cell_index(*up)
+            minus = m.cell_index(*dn)
+            B = self.face_block(0, m.neighbor(0, 2 * d + 1), d)
+            diag += B[:nb, :nb] + B[nb:, nb:]        # the cell as minus side of its +d face and plus side of its -d face
+            Y += U[plus] @ B[:nb, nb:].T + U[minus] @ B[nb:, :nb].T
+        Y += U @ diag.T
+        return Y.ravel()
 
     def diagonal_cells(self, cells):
         """diag(H) restricted to the listed cells."""

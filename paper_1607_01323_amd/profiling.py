@@ -2,6 +2,14 @@
 
 ``python -m paper_1607_01323_amd.profiling stats <kernel_stats.csv> <out.md> --cmd "..."``
     writes the per-kernel duration table of a --kernel-trace --stats run.
+``python -m paper_1607_01323_amd.profiling trace <kernel_trace.csv> <out.md> --cmd "..."``
+    writes per-configuration rows (kernel, grid size, workgroup size) of a
+    --kernel-trace run, so launches of one kernel on different meshes are not
+    averaged together.
+``python -m paper_1607_01323_amd.profiling counters <out.md> <counter_collection.csv>... --trace <kernel_trace.csv> --cmd "..."``
+    per-configuration means of SQ_* counters (per dispatch), with the fp64 /
+    fp32 operation counts they imply and, from the durations of the trace run,
+    the achieved FLOP rates against the chip's peaks.
 ``python -m paper_1607_01323_amd.profiling pmc <fetch_csv> <write_csv> <out.json> --cmd-fetch ... --cmd-write ...``
     reduces FETCH_SIZE / WRITE_SIZE counter collections (KiB per dispatch) to
     a per-kernel average and the copy-kernel calibration factor, tagged with
@@ -40,6 +48,102 @@ def stats_table(csv_path, out_md, cmd):
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+def _col(row, *names):
+    for n in names:
+        if n in row and row[n] != "":
+            return row[n]
+    return ""
+
+
+def _grid(row):
+    g = _col(row, "Grid_Size")
+    if g:
+        return g
+    return "x".join(_col(row, f"Grid_Size_{a}") or "1" for a in "XYZ")
+
+
+def _wg(row):
+    g = _col(row, "Workgroup_Size")
+    if g:
+        return g
+    return "x".join(_col(row, f"Workgroup_Size_{a}") or "1" for a in "XYZ")
+
+
+def trace_durations(csv_path):
+    """{(kernel, grid): [durations in ns]} from a kernel_trace.csv."""
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        k = short_name(_col(r, "Kernel_Name"))
+        d = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        agg[(k, _grid(r), _wg(r))].append(d)
+    return agg
+
+
+def trace_table(csv_path, out_md, cmd):
+    agg = trace_durations(csv_path)
+    total = sum(sum(v) for v in agg.values()) or 1.0
+    rows = sorted(agg.items(), key=lambda kv: -sum(kv[1]))
+    lines = ["# rocprofv3 kernel trace, per configuration", "", f"Command: `{cmd}`", "",
+             "One row per kernel and launch shape (grid size = total work-items), so launches on "
+             "different meshes are listed apart.", "",
+             "| kernel | grid | workgroup | calls | avg (us) | median (us) | min (us) | max (us) | share % |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for (k, g, wg), v in rows:
+        v = sorted(v)
+        lines.append(f"| `{k[:80]}` | {g} | {wg} | {len(v)} | {sum(v) / len(v) / 1e3:.2f} | "
+                     f"{v[len(v) // 2] / 1e3:.2f} | {v[0] / 1e3:.2f} | {v[-1] / 1e3:.2f} | "
+                     f"{100.0 * sum(v) / total:.1f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+FLOP_F64 = {"SQ_INSTS_VALU_ADD_F64": 1, "SQ_INSTS_VALU_MUL_F64": 1, "SQ_INSTS_VALU_FMA_F64": 2,
+            "SQ_INSTS_VALU_TRANS_F64": 1}
+FLOP_F32 = {"SQ_INSTS_VALU_ADD_F32": 1, "SQ_INSTS_VALU_MUL_F32": 1, "SQ_INSTS_VALU_FMA_F32": 2,
+            "SQ_INSTS_VALU_TRANS_F32": 1}
+
+
+def counters_table(out_md, csv_paths, trace_csv, cmd, peaks=(78.6, 157.3)):
+    """Mean counter value per dispatch for each (kernel, grid); FLOPs per dispatch as
+    64 lanes x the weighted VALU instruction counts (the counters count wavefront
+    instructions); rates from the trace run's median durations."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    regs = {}
+    for p in csv_paths:
+        for r in csv.DictReader(open(p)):
+            key = (short_name(_col(r, "Kernel_Name")), _grid(r))
+            vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            regs[key] = (_col(r, "VGPR_Count", "Arch_VGPR_Count"), _col(r, "Accum_VGPR_Count"),
+                         _col(r, "SGPR_Count"), _col(r, "LDS_Block_Size", "Group_Segment_Size"),
+                         _col(r, "Scratch_Size", "Private_Segment_Size"))
+    dur = {}
+    if trace_csv:
+        for (k, g, _), v in trace_durations(trace_csv).items():
+            v = sorted(v)
+            dur[(k, g)] = v[len(v) // 2]
+    names = sorted({c for d in vals.values() for c in d})
+    lines = ["# rocprofv3 counters, per configuration", "", f"Command: `{cmd}`", "",
+             "Mean value per dispatch.  fp64 / fp32 FLOP = 64 x (ADD + MUL + TRANS + 2 FMA) of the "
+             "wavefront instruction counts (every lane counted as active); the rate uses the median "
+             "duration of the same kernel and grid in the kernel-trace run.", ""]
+    hdr = ["kernel", "grid", "VGPR", "AGPR", "SGPR", "LDS", "scratch"] + names + \
+          ["fp64 GFLOP", "fp64 TFLOP/s", "fp64 frac", "fp32 GFLOP", "fp32 TFLOP/s", "fp32 frac"]
+    lines.append("| " + " | ".join(hdr) + " |")
+    lines.append("|" + "---|" * len(hdr))
+    for key in sorted(vals):
+        d = {c: sum(v) / len(v) for c, v in vals[key].items()}
+        f64 = 64.0 * sum(w * d.get(c, 0.0) for c, w in FLOP_F64.items())
+        f32 = 64.0 * sum(w * d.get(c, 0.0) for c, w in FLOP_F32.items())
+        t = dur.get(key)
+        r64 = f"{f64 / t / 1e3:.2f}" if t and f64 else ""
+        r32 = f"{f32 / t / 1e3:.2f}" if t and f32 else ""
+        fr64 = f"{f64 / t / 1e3 / peaks[0]:.3f}" if t and f64 else ""
+        fr32 = f"{f32 / t / 1e3 / peaks[1]:.3f}" if t and f32 else ""
+        row = [f"`{key[0][:70]}`", key[1], *regs.get(key, ("",) * 5)] + [f"{d.get(c, float('nan')):.4g}" for c in names]
+        row += [f"{f64 / 1e9:.4g}", r64, fr64, f"{f32 / 1e9:.4g}", r32, fr32]
+        lines.append("| " + " | ".join(str(x) for x in row) + " |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 def _per_kernel(csv_path, counter):
     agg = collections.defaultdict(list)
     for r in csv.DictReader(open(csv_path)):
@@ -75,6 +179,15 @@ if __name__ == "__main__":
     a.add_argument("csv")
     a.add_argument("out")
     a.add_argument("--cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("csv")
+    t.add_argument("out")
+    t.add_argument("--cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("csvs", nargs="+")
+    c.add_argument("--trace", default=None)
+    c.add_argument("--cmd", required=True)
     b = sub.add_parser("pmc")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
@@ -85,5 +198,9 @@ if __name__ == "__main__":
     args = ap.parse_args()
     if args.what == "stats":
         stats_table(args.csv, args.out, args.cmd)
+    elif args.what == "trace":
+        trace_table(args.csv, args.out, args.cmd)
+    elif args.what == "counters":
+        counters_table(args.out, args.csvs, args.trace, args.cmd)
     else:
         pmc_summary(args.fetch_csv, args.write_csv, args.out, args.cmd_fetch, args.cmd_write, args.copy_bytes)

@@ -199,3 +199,16 @@ def test_fdm_solution_solves_assembled_system():
     wts = sipg.integral_weights(m)
     assert abs(wts @ x) < 1e-12 * np.abs(x).max()          # zero integral mean
     assert abs(wts.sum() - 1.0) < 1e-14                     # partition of unity on the unit cube
+
+
+@pytest.mark.parametrize("k,cells,lengths", [(1, (3, 2, 4), (1.0, 1.0, 1.0)), (2, (2, 3, 1), (0.7, 1.1, 0.4)),
+                                             (3, (4, 4, 4), (1.0, 1.0, 1.0)), (4, (2, 2, 3), (1.0, 2.0, 1.5))])
+def test_block_stencil_apply(k, cells, lengths):
+    """The block-stencil product (all cells at once) equals the assembled matrix, including
+    directions with a single periodic cell."""
+    m = mesh.BoxMesh(k, *cells, *lengths)
+    op = sipg.SIPG(m, mass_coeff=3.0, diff_coeff=0.5, penalty_scale=1.0 / 3.0)
+    u = inp.uniform(21 + k, m.ndofs)
+    want = op.assemble() @ u
+    got = op.apply_block_stencil(u)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
