@@ -137,3 +137,58 @@ def _interior_pair(Tv, gv, sv, Tu, gu, su, W, n, nu, pen):
                 B = B + pen * sv * su * (Tv.T @ (W[:, None] * Tu))
             blk[c][cp] = B
     return blk
+
+
+def viscous_apply_cells(m, U, cells, mu, nu, penalty_scale=1.0):
+    """(H U) restricted to the rows of the listed cells, shape (3, len(cells), n^3).
+
+    The same blocks as ``viscous_matrix``, built for each listed cell from its
+    own cell integral and its six faces (blocks cached by geometry), so that
+    sampled rows of full-size meshes can be checked without assembling."""
+    T = sipg.Tables(m.k)
+    nb = m.n ** 3
+    tau = sipg.penalty_per_cell(m, penalty_scale)
+    Uc = U.reshape(3, m.ncells, nb)
+    cache = {}
+
+    def key(*arrs):
+        return tuple(np.round(np.concatenate([np.ravel(a) for a in arrs]), 15).tolist())
+
+    def mult(blk, V):
+        return np.stack([sum(blk[c][cp] @ V[cp] for cp in range(3)) for c in range(3)])
+
+    out = np.zeros((3, len(cells), nb))
+    for r, cell in enumerate(cells):
+        J = m.jacobian(cell)
+        kc = ("cell", key(J))
+        if kc not in cache:
+            cache[kc] = _cell_block(T, J, mu, nu)
+        y = mult(cache[kc], Uc[:, cell])
+        for f in range(6):
+            d, s = divmod(f, 2)
+            cn = m.neighbor(cell, f)
+            if cn < 0:
+                if m.neumann[f]:
+                    continue
+                kb = ("bnd", f, key(J, [tau[cell]]))
+                if kb not in cache:
+                    Tr, g, dA, nrm = _face_grads(T, J, f)
+                    n_out = nrm if s == 1 else -nrm
+                    cache[kb] = _face_terms(Tr, g, Tr, g, dA, n_out, nu, 2.0 * nu * tau[cell])
+                y += mult(cache[kb], Uc[:, cell])
+                continue
+            cL, cR = (cell, cn) if s == 1 else (cn, cell)
+            JL, JR = m.jacobian(cL), m.jacobian(cR)
+            pen = nu * max(tau[cL], tau[cR])
+            kf = ("int", d, s, key(JL, JR, [pen]))
+            if kf not in cache:
+                TrL, gL, dA, nrm = _face_grads(T, JL, 2 * d + 1)
+                TrR, gR, _, _ = _face_grads(T, JR, 2 * d)
+                sideL, sideR = (TrL, gL, 1.0), (TrR, gR, -1.0)
+                own, other = (sideL, sideR) if s == 1 else (sideR, sideL)
+                cache[kf] = (_interior_pair(*own, *own, dA, nrm, nu, pen),
+                             _interior_pair(*own, *other, dA, nrm, nu, pen))
+            b_own, b_other = cache[kf]
+            y += mult(b_own, Uc[:, cell]) + mult(b_other, Uc[:, cn])
+        out[:, r] = y
+    return out

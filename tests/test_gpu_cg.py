@@ -262,8 +262,15 @@ def test_inverse_mass_preconditioned_cg_full_size():
         out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=1000, precond=pc)
         assert out.status == 0
         its[pc] = out.iterations
-        cells = sample_cells(w.cells, 16, 3)
-        r = b.reshape(om.ncells, -1)[cells] - oop.apply_cells(host(xg), cells)
-        assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+        # the oracle's residual on sampled rows against the same rows of b: the
+        # solve's 1e-10 (x2 for the true against the recursive residual) with a
+        # factor 4 for how unevenly the residual spreads over the cells
+        cells = sample_cells(w.cells, 64, 3)
+        bs = b.reshape(om.ncells, -1)[cells]
+        r = bs - oop.apply_cells(host(xg), cells)
+        assert np.linalg.norm(r) <= 8e-10 * np.linalg.norm(bs)
+        # and the whole true residual through the library's apply
+        rg = dev(b) - gop.apply(xg)
+        assert torch.linalg.norm(rg).item() <= 2e-10 * np.linalg.norm(b)
     print(f"[result] C1 CG iterations: inverse mass {its['mass']}, Jacobi {its['jacobi']}", flush=True)
     gm.close()

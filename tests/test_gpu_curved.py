@@ -182,7 +182,12 @@ def test_full_size_curved_channel():
     out = gop.cg(dev(b), xg, rtol=1e-10, max_iter=500, precond="chebyshev", precond_dtype=torch.float32)
     assert out.status == 0
     print(f"[result] curved channel mixed CG iterations {out.iterations}, solve {out.solve_s:.3f} s", flush=True)
-    r = b.reshape(om.ncells, -1)[cells] - oop.apply_cells(host(xg), cells)
-    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+    # the oracle's residual on the sampled rows against the same rows of b (1e-10,
+    # x2 for true against recursive, x4 for the uneven spread over cells), and
+    # the whole true residual through the library's apply
+    bs = b.reshape(om.ncells, -1)[cells]
+    r = bs - oop.apply_cells(host(xg), cells)
+    assert np.linalg.norm(r) <= 8e-10 * np.linalg.norm(bs)
+    assert torch.linalg.norm(dev(b) - gop.apply(xg)).item() <= 2e-10 * np.linalg.norm(b)
     gm.close()
 

@@ -2,10 +2,11 @@
 
 Small meshes are compared entry by entry with the oracle's assembled 3N x 3N
 matrix (every degree, periodic and Dirichlet faces, tanh grading, a single
-periodic cell); at the full Helmholtz and channel sizes the operator is
-checked through properties that hold at any size: symmetry <v, H u> = <u, H v>
-and, on the periodic cube without mass, constant translations in the null
-space.
+periodic cell); at the full Helmholtz and channel sizes the rows of sampled
+cells are compared with the oracle's row-restricted blocks, and the operator
+is checked through properties that hold at any size: symmetry
+<v, H u> = <u, H v> and, on the periodic cube without mass, constant
+translations in the null space.
 """
 import math
 
@@ -215,4 +216,25 @@ def test_viscous_cg_inverse_mass_matches_oracle(name):
     print(f"  iterations: library {out.iterations}, oracle {itr}", flush=True)
     assert abs(out.iterations - itr) <= 1
     assert np.linalg.norm(b - A @ host(xg)) <= 2e-10 * np.linalg.norm(b)
+    gm.close()
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_size_sampled_cells_match_oracle(name):
+    """Full-size meshes: the rows of sampled cells (corners included) against the oracle's
+    row-restricted blocks, 1e-12 relative."""
+    require_gpu()
+    import paper_1607_01323_amd as dg
+    from tests.gpu_util import sample_cells
+    w = FULL[name]
+    print(f"[case] viscous full-size sampled cells {name}", flush=True)
+    om = omesh.BoxMesh(w.degree, *w.cells, lx=w.lengths[0], ly=w.lengths[1], lz=w.lengths[2], y0=w.y0,
+                       periodic=w.periodic, y_tanh_gamma=w.y_tanh_gamma)
+    gm = dg.Mesh.from_workload(w)
+    gop = dg.SipgOperator(gm, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    U = inp.uniform(93, 3 * om.ndofs)
+    Y = host(gop.viscous_apply(dev(U))).reshape(3, om.ncells, -1)
+    cells = sample_cells(w.cells, 24, 5)
+    ref = ovisc.viscous_apply_cells(om, U, cells, w.mass_coeff, w.diff_coeff, w.penalty_scale)
+    assert rel_err(Y[:, cells], ref) < 1e-12
     gm.close()

@@ -130,3 +130,31 @@ def test_vjp_cells_matches_full(per):
     np.testing.assert_allclose(op.vjp_cells(U, W, cells), full[:, cells], rtol=0, atol=1e-14 * np.abs(full).max())
     Cf = op.forward(U).reshape(3, m.ncells, -1)
     np.testing.assert_allclose(op.forward_cells(U, cells), Cf[:, cells], rtol=0, atol=1e-14 * np.abs(Cf).max())
+
+
+def test_kink_aware_central_differences():
+    """Central differences of <w, C(U)> with a step large enough to cross many LF kinks,
+    minus the exact per-point correction at the points that may cross one
+    (tests/fd_kinks.py), equal <VJP(U, w), d>; without the correction they do not."""
+    import torch
+    from tests.fd_kinks import kink_correction
+    k, nc, nq = 2, (3, 3, 3), 4
+    m = mesh.BoxMesh(k, *nc)
+    op = convective.Convective(m, nq=nq)
+    X = m.node_coords()
+    U = (inp.taylor_green(X[:, 0], X[:, 1], X[:, 2]) + 0.01 * inp.uniform(31, 3 * m.ndofs).reshape(3, -1)).ravel()
+    W = inp.uniform(32, U.size)
+    g = op.vjp(U, W)
+    eps = 2e-3
+    worst_raw, worst = 0.0, 0.0
+    for j in range(4):
+        D = inp.uniform(40 + j, U.size)
+        fd = W @ (op.forward(U + eps * D) - op.forward(U - eps * D)) / (2 * eps)
+        corr, count = kink_correction(torch.as_tensor(U), torch.as_tensor(D), torch.as_tensor(W), k, nc, nq,
+                                      1.0 / 3, eps)
+        an = g @ D
+        assert count > 0
+        worst_raw = max(worst_raw, abs(fd - an) / abs(an))
+        worst = max(worst, abs(fd - corr - an) / abs(an))
+    assert worst_raw > 1e-6          # the kinks are crossed ...
+    assert worst < 1e-11             # ... and the correction accounts for all of them

@@ -94,3 +94,23 @@ def test_definite_with_dirichlet_faces():
     m = mesh.BoxMesh(2, 2, 2, 2, lx=1.0, ly=2.0, lz=1.0, y0=-1.0, periodic=(True, False, True), y_tanh_gamma=1.0)
     A = viscous.viscous_matrix(m, 0.0, 1.0).toarray()
     assert np.linalg.eigvalsh(0.5 * (A + A.T))[0] > 0
+
+
+@pytest.mark.parametrize("case", ["periodic_k2", "channel_k3", "one_cell_k2", "neumann_k2"])
+def test_row_restricted_apply_equals_matrix(case):
+    """viscous_apply_cells (per-cell blocks, for sampling full-size meshes) equals the
+    assembled matrix on every row."""
+    if case == "periodic_k2":
+        m = mesh.BoxMesh(2, 3, 2, 2, lx=1.0, ly=0.8, lz=1.2)
+    elif case == "channel_k3":
+        m = mesh.BoxMesh(3, 2, 3, 2, lx=2.0, ly=2.0, lz=1.0, y0=-1.0, periodic=(True, False, True),
+                         y_tanh_gamma=1.5)
+    elif case == "one_cell_k2":
+        m = mesh.BoxMesh(2, 1, 2, 1, periodic=(True, False, True))
+    else:
+        m = mesh.BoxMesh(2, 2, 2, 2, periodic=(False, False, True), neumann=(True, False, False, True, False, False))
+    U = inp.uniform(77, 3 * m.ndofs)
+    want = viscous.viscous_matrix(m, 3.0, 0.4, 1.0) @ U
+    got = viscous.viscous_apply_cells(m, U, list(range(m.ncells)), 3.0, 0.4, 1.0)
+    want = want.reshape(3, m.ncells, -1)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
