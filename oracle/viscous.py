@@ -192,3 +192,137 @@ def viscous_apply_cells(m, U, cells, mu, nu, penalty_scale=1.0):
             y += mult(b_own, Uc[:, cell]) + mult(b_other, Uc[:, cn])
         out[:, r] = y
     return out
+
+
+# ---------------------------------------------------------------- curved cells
+# The same bilinear form on iso-parametric curved cells (Sec. 5): the Jacobian,
+# and with it the physical gradients, the unit normal and the surface measure,
+# are taken at every quadrature point (k+1 Gauss points per direction on
+# cells and faces), and tau_e comes from the curved areas and volumes (the
+# penalty of the curved SIPG oracle).  The blocks are those above with the
+# normal moved inside the point sums.
+
+def _pair_pts(Tv, gv, sv, Tu, gu, su, W, n, nu, pen):
+    """_interior_pair with a normal n (m, 3) that varies over the face points."""
+    Gnv = sum(n[:, a][:, None] * gv[a] for a in range(3))
+    Gnu = sum(n[:, a][:, None] * gu[a] for a in range(3))
+    blk = [[None] * 3 for _ in range(3)]
+    for c in range(3):
+        for cp in range(3):
+            B = -nu * (0.5 * su * (gv[cp].T @ ((W * n[:, c])[:, None] * Tu))
+                       + 0.5 * sv * (Tv.T @ ((W * n[:, cp])[:, None] * gu[c])))
+            if c == cp:
+                B = B - nu * (0.5 * su * (Gnv.T @ (W[:, None] * Tu)) + 0.5 * sv * (Tv.T @ (W[:, None] * Gnu)))
+                B = B + pen * sv * su * (Tv.T @ (W[:, None] * Tu))
+            blk[c][cp] = B
+    return blk
+
+
+def _bnd_pts(Tr, g, W, n, nu, pen):
+    """_face_terms (own traces on both sides of the form) with a per-point outward normal n (m, 3)."""
+    Gn = sum(n[:, a][:, None] * g[a] for a in range(3))
+    blk = [[None] * 3 for _ in range(3)]
+    for c in range(3):
+        for cp in range(3):
+            B = -nu * ((g[cp].T @ ((W * n[:, c])[:, None] * Tr)) + (Tr.T @ ((W * n[:, cp])[:, None] * g[c])))
+            if c == cp:
+                B = B - nu * (Gn.T @ (W[:, None] * Tr) + Tr.T @ (W[:, None] * Gn)) + pen * (Tr.T @ (W[:, None] * Tr))
+            blk[c][cp] = B
+    return blk
+
+
+class CurvedViscous:
+    """The symmetric-gradient viscous operator on a CurvedBoxMesh, point by point."""
+
+    def __init__(self, mesh, mass_coeff, diff_coeff, penalty_scale=1.0, cells=None):
+        from .curved import CurvedSIPG
+        self.mesh = mesh
+        self.mu, self.nu = float(mass_coeff), float(diff_coeff)
+        # tables, face geometry and tau_e (curved areas and volumes) of the scalar operator
+        self.s = CurvedSIPG(mesh, mass_coeff, diff_coeff, penalty_scale, cells=cells)
+
+    def cell_block(self, c):
+        from .curved import _phys_grads
+        s, m = self.s, self.mesh
+        J = m.jac_at(c, s.xq_cell)
+        w = s.wq_cell * np.abs(np.linalg.det(J))
+        grad = _phys_grads(s.Gref, np.linalg.inv(J))
+        M = s.Phi.T @ (w[:, None] * s.Phi)
+        K = sum(g.T @ (w[:, None] * g) for g in grad)
+        blk = [[None] * 3 for _ in range(3)]
+        for c1 in range(3):
+            for c2 in range(3):
+                B = self.nu * (grad[c2].T @ (w[:, None] * grad[c1]))
+                if c1 == c2:
+                    B = B + self.mu * M + self.nu * K
+                blk[c1][c2] = B
+        return blk
+
+    def face_pairs(self, cL, cR, d):
+        """{(test side, trial side): blocks} for sides 'L' and 'R' of an interior face (normal of L)."""
+        s = self.s
+        TrL, gL, dA, nL = s.face(cL, 2 * d + 1)
+        TrR, gR, _, _ = s.face(cR, 2 * d)
+        pen = self.nu * max(s.tau_e[cL], s.tau_e[cR])
+        sides = {"L": (TrL, gL, 1.0), "R": (TrR, gR, -1.0)}
+        return {(a, b): _pair_pts(*sides[a], *sides[b], dA, nL, self.nu, pen) for a in "LR" for b in "LR"}
+
+    def bface_block(self, c, f):
+        Tr, g, dA, nrm = self.s.face(c, f)
+        n_out = nrm if f % 2 == 1 else -nrm
+        return _bnd_pts(Tr, g, dA, n_out, self.nu, 2.0 * self.nu * self.s.tau_e[c])
+
+    def assemble(self):
+        m = self.mesh
+        nb, N = m.n ** 3, m.ndofs
+        rows, cols, vals = [], [], []
+
+        def add(cell_r, cell_c, blk):
+            for c1 in range(3):
+                for c2 in range(3):
+                    r = c1 * N + cell_r * nb + np.arange(nb)
+                    cc = c2 * N + cell_c * nb + np.arange(nb)
+                    R, C = np.meshgrid(r, cc, indexing="ij")
+                    rows.append(R.ravel())
+                    cols.append(C.ravel())
+                    vals.append(blk[c1][c2].ravel())
+
+        for cell in range(m.ncells):
+            add(cell, cell, self.cell_block(cell))
+        for cL, cR, d in m.interior_faces():
+            P = self.face_pairs(cL, cR, d)
+            idx = {"L": cL, "R": cR}
+            for (a, b), blk in P.items():
+                add(idx[a], idx[b], blk)
+        for cell, f in m.boundary_faces():
+            add(cell, cell, self.bface_block(cell, f))
+        A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(3 * N, 3 * N))
+        return A.tocsr()
+
+    def apply_cells(self, U, cells):
+        """(H U) on the rows of the listed cells, shape (3, len(cells), n^3)."""
+        m = self.mesh
+        nb = m.n ** 3
+        Uc = U.reshape(3, m.ncells, nb)
+
+        def mult(blk, V):
+            return np.stack([sum(blk[c][cp] @ V[cp] for cp in range(3)) for c in range(3)])
+
+        out = np.zeros((3, len(cells), nb))
+        for r, cell in enumerate(cells):
+            y = mult(self.cell_block(cell), Uc[:, cell])
+            for f in range(6):
+                d, s = divmod(f, 2)
+                cn = m.neighbor(cell, f)
+                if cn < 0:
+                    if not m.neumann[f]:
+                        y += mult(self.bface_block(cell, f), Uc[:, cell])
+                    continue
+                if s == 1:
+                    P = self.face_pairs(cell, cn, d)
+                    y += mult(P[("L", "L")], Uc[:, cell]) + mult(P[("L", "R")], Uc[:, cn])
+                else:
+                    P = self.face_pairs(cn, cell, d)
+                    y += mult(P[("R", "R")], Uc[:, cell]) + mult(P[("R", "L")], Uc[:, cn])
+            out[:, r] = y
+        return out
