@@ -312,6 +312,23 @@ dgmf_status dgmf_cg_workspace_bytes(dgmf_op op, const dgmf_cg_params* params, si
 dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params,
                           void* workspace, size_t workspace_bytes, hipStream_t stream,
                           dgmf_cg_result* out);
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation):
+ * dgmf_cg_solve with its workspace taken from a static buffer of the library
+ * (DGMF_CG_NOALLOC_MAX_BYTES per device, held by every device the library
+ * runs on from module load to the end of the process), so the call allocates
+ * no device memory.  Arguments, results and synchronisation as for
+ * dgmf_cg_solve, without the workspace.  precond 0, 1 and 3 only (the
+ * multigrid hierarchy of precond 2 is allocated on first use:
+ * DGMF_UNSUPPORTED); a workspace need (dgmf_cg_workspace_bytes) above
+ * DGMF_CG_NOALLOC_MAX_BYTES is DGMF_INVALID.  Every call on one device shares
+ * that device's buffer and leaves its contents behind; calls on one device
+ * are serialised by a lock held for the whole (synchronous) solve, so calls
+ * from several host threads run one after the other, and the buffer is
+ * rewritten before it is read.  b and x must not lie in the buffer. */
+#define DGMF_CG_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+dgmf_status dgmf_cg_solve_noalloc(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params,
+                                  hipStream_t stream, dgmf_cg_result* out);
 /* The implicit viscous step in the symmetric-gradient form (Sec. 3.2; the
  * solver of Sec. 5.1): H_eps x = b with H_eps the operator of
  * dgmf_viscous_apply, by fp64 CG preconditioned with the inverse diagonal of

@@ -89,6 +89,7 @@ _integ = _sig("dgmf_integrate", _vp, _vp, _vp, _vp)
 _ws_bytes = _sig("dgmf_cg_workspace_bytes", _vp, ctypes.POINTER(CgParams), ctypes.POINTER(ctypes.c_size_t))
 _cg = _sig("dgmf_cg_solve", _vp, _vp, _vp, ctypes.POINTER(CgParams), _vp, ctypes.c_size_t, _vp,
            ctypes.POINTER(CgResult))
+_cg_noalloc = _sig("dgmf_cg_solve_noalloc", _vp, _vp, _vp, ctypes.POINTER(CgParams), _vp, ctypes.POINTER(CgResult))
 _pc_apply = _sig("dgmf_precond_apply", _vp, ctypes.POINTER(CgParams), _vp, _vp, _vp)
 _pc_info = _sig("dgmf_precond_info", _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double))
@@ -353,6 +354,22 @@ class SipgOperator(_Op):
         out = CgOutcome(res.iterations, res.rel_residual, res.lambda_max, res.status, res.setup_s, res.solve_s)
         if st not in (OK, NOT_CONVERGED, BREAKDOWN, NONFINITE) or (raise_on_failure and st != OK):
             raise DgmfError(st, "cg_solve")
+        return out
+
+    def cg_noalloc(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, precond="jacobi",
+                   precond_dtype=torch.float64, cheb_degree=5, smoothing_range=20.0, lanczos_steps=15,
+                   lambda_safety=1.2, seed=0, project_mean=False, flexible=None, raise_on_failure=True):
+        """cg() on the library's static workspace (dgmf_cg_solve_noalloc): no device
+        allocation by the library or here; precond "jacobi", "chebyshev" or "mass"."""
+        p = self._params(rtol, max_iter, check_every, precond, precond_dtype, cheb_degree, smoothing_range,
+                         lanczos_steps, lambda_safety, seed, project_mean, flexible, 0.0, False)
+        res = CgResult()
+        st = _cg_noalloc(self._h, _ptr(b, torch.float64, self.mesh.ndofs, "b"),
+                         _ptr(x, torch.float64, self.mesh.ndofs, "x"), ctypes.byref(p), _stream(),
+                         ctypes.byref(res))
+        out = CgOutcome(res.iterations, res.rel_residual, res.lambda_max, res.status, res.setup_s, res.solve_s)
+        if st not in (OK, NOT_CONVERGED, BREAKDOWN, NONFINITE) or (raise_on_failure and st != OK):
+            raise DgmfError(st, "cg_solve_noalloc")
         return out
 
     def viscous_cg(self, b, x, rtol=1e-10, max_iter=1000, check_every=8, precond="jacobi", raise_on_failure=True):

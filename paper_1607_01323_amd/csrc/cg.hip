@@ -21,6 +21,8 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
+#include <vector>
 
 #include "internal.h"
 
@@ -1233,6 +1235,97 @@ dgmf_status dgmf_cg_solve(dgmf_op op, const double* b, double* x, const dgmf_cg_
   std::memset(out, 0, sizeof(*out));
   out->status = DGMF_OK;
   e = cg_run(op, b, x, params, static_cast<char*>(workspace), L, stream, out);
+  if (e != DGMF_OK) {
+    (void)hipStreamSynchronize(stream);
+    out->status = e;
+  }
+  return e;
+}
+
+}  // extern "C"
+
+namespace dgmf {
+namespace {
+
+// Workspace of dgmf_cg_solve_noalloc: a static array of the code object, so
+// every device the library runs on holds one copy from module load to the
+// end of the process.  Host code never uses the name `scratch` as an address
+// (on the host it is a stand-in, not device memory): it asks the runtime for
+// the current device's address once per device and passes that pointer on.
+static __device__ __align__(256) char scratch[DGMF_CG_NOALLOC_MAX_BYTES];
+
+struct NoAllocSlot {
+  std::mutex lock;       // held for a whole (synchronous) solve on this device
+  char* ptr = nullptr;   // device address of this device's copy of scratch
+};
+
+NoAllocSlot* noalloc_slot(int dev) {
+  static std::mutex table_lock;
+  static std::vector<std::unique_ptr<NoAllocSlot>> slots;
+  std::lock_guard<std::mutex> g(table_lock);
+  if (dev >= static_cast<int>(slots.size())) slots.resize(dev + 1);
+  if (!slots[dev]) slots[dev] = std::make_unique<NoAllocSlot>();
+  return slots[dev].get();
+}
+
+}  // namespace
+}  // namespace dgmf
+
+extern "C" {
+
+dgmf_status dgmf_cg_solve_noalloc(dgmf_op op, const double* b, double* x, const dgmf_cg_params* params,
+                                  hipStream_t stream, dgmf_cg_result* out) {
+  dgmf_status e = validate(op, params);
+  if (e) return e;
+  if (params->precond == 2)
+    return fail(DGMF_UNSUPPORTED, "cg_solve_noalloc: the multigrid hierarchy allocates; use precond 0, 1 or 3");
+  if (!b || !x || !out) return fail(DGMF_INVALID, "cg_solve_noalloc: null argument");
+  if (reinterpret_cast<uintptr_t>(b) % 8 || reinterpret_cast<uintptr_t>(x) % 8)
+    return fail(DGMF_INVALID, "cg_solve_noalloc: misaligned vector (8 B)");
+  const int64_t N = op->mesh->ndofs;
+  const size_t es = params->precond_dtype == DGMF_F32 ? 4 : 8;
+  Layout L = make_layout(N, nparts_for(op), params->precond == 1, es);
+  if (L.total > DGMF_CG_NOALLOC_MAX_BYTES)
+    return fail(DGMF_INVALID, "cg_solve_noalloc: %lld DoF need %zu bytes of workspace, more than the %zu bytes "
+                "of the static buffer; use dgmf_cg_solve with a caller workspace",
+                static_cast<long long>(N), L.total, static_cast<size_t>(DGMF_CG_NOALLOC_MAX_BYTES));
+  {
+    const char* xb = reinterpret_cast<const char*>(x);
+    const char* bb = reinterpret_cast<const char*>(b);
+    if (xb < bb + 8 * N && bb < xb + 8 * N) return fail(DGMF_INVALID, "cg_solve_noalloc: b and x overlap");
+  }
+  const int dev = op->mesh->device;
+  int prev_dev = -1;
+  (void)hipGetDevice(&prev_dev);
+  if (prev_dev != dev) DGMF_HIP_TRY(hipSetDevice(dev));
+  struct Restore {
+    int d;
+    ~Restore() { if (d >= 0) (void)hipSetDevice(d); }
+  } restore{prev_dev != dev ? prev_dev : -1};
+  NoAllocSlot* slot = noalloc_slot(dev);
+  std::lock_guard<std::mutex> g(slot->lock);
+  if (!slot->ptr) {
+    // first call on this device, with the device current: its copy's address
+    void* p = nullptr;
+    const hipError_t he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (he != hipSuccess || !p)
+      return fail(DGMF_HIP_ERROR, "cg_solve_noalloc: hipGetSymbolAddress of the static buffer failed: %s",
+                  hipGetErrorString(he));
+    slot->ptr = static_cast<char*>(p);
+  }
+  {
+    const char* wb = slot->ptr;
+    const char* xb = reinterpret_cast<const char*>(x);
+    const char* bb = reinterpret_cast<const char*>(b);
+    if ((xb < wb + L.total && wb < xb + 8 * N) || (bb < wb + L.total && wb < bb + 8 * N))
+      return fail(DGMF_INVALID, "cg_solve_noalloc: b or x lies in the library's static buffer");
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->status = DGMF_OK;
+  // every value of the workspace is written before it is read (state by a
+  // copy, partials and vectors by the kernels), so the previous call's
+  // contents need no clearing
+  e = cg_run(op, b, x, params, slot->ptr, L, stream, out);
   if (e != DGMF_OK) {
     (void)hipStreamSynchronize(stream);
     out->status = e;
