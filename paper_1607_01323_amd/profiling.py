@@ -56,10 +56,15 @@ def _col(row, *names):
 
 
 def _grid(row):
+    """Total work-items of the launch (counter files give the total, trace files
+    the three extents), as a string, so that both files key alike."""
     g = _col(row, "Grid_Size")
     if g:
-        return g
-    return "x".join(_col(row, f"Grid_Size_{a}") or "1" for a in "XYZ")
+        return str(int(float(g)))
+    t = 1
+    for a in "XYZ":
+        t *= int(float(_col(row, f"Grid_Size_{a}") or "1"))
+    return str(t)
 
 
 def _wg(row):
