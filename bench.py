@@ -377,6 +377,7 @@ def curved_measurements(dg, inp, torch, w, tag):
     """Channel Helmholtz on iso-parametric curved cells: metric set-up, apply (fp64,
     fp32; the stored-metric kernel, same algorithmic bytes as on affine cells), and
     PCG to 1e-10 on a random right-hand side (mixed fp32 Chebyshev, fp64 Jacobi);
+    the symmetric-gradient viscous operator and its inverse-mass PCG;
     then the convective operator and its VJP, and the V3c divergence and
     gradient, on the same cells (per-point metrics; U = (1, 0, 0) + 0.05
     uniform[-1, 1])."""
@@ -410,6 +411,22 @@ def curved_measurements(dg, inp, torch, w, tag):
         ex[f"{tag}_cg_{name}"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
                                   "status": out.status, "setup_s": out.setup_s, "solve_s": out.solve_s}
     del b
+    # the viscous operator in the symmetric-gradient form on the curved cells and its
+    # implicit step (inverse-mass PCG to 1e-10 from zero on a random right-hand side)
+    Uv = torch.as_tensor(inp.uniform(12, 3 * N), device="cuda")
+    Yv = torch.empty_like(Uv)
+    op.viscous_apply(Uv, Yv)
+    tev = _events_time(lambda: op.viscous_apply(Uv, Yv), 5, 1)
+    ex[f"{tag}_viscous_eps"] = {"us": tev * 1e6, "velocity_nodes_per_s": N / tev,
+                                "vs_three_scalar_applies": tev / (3 * ta)}
+    Yv.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = op.viscous_cg(Uv, Yv, rtol=1e-10, max_iter=2000, check_every=8, precond="mass", raise_on_failure=False)
+    torch.cuda.synchronize()
+    ex[f"{tag}_viscous_cg_mass"] = {"time_s": time.perf_counter() - t0, "iterations": out.iterations,
+                                    "status": out.status, "solve_s": out.solve_s}
+    del Uv, Yv
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     opc = dg.ConvectiveOperator(m)

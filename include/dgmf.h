@@ -114,11 +114,11 @@ int dgmf_version(void);
  * operator, its diagonal, CG with every preconditioner (multigrid keeps the
  * curved operator on the finest level and rediscretises the coarse levels on
  * the undeformed box), the mass matrix and its inverse (with the point
- * weights w_q det J_q), the convective operator and its VJP, and the V3c
- * divergence, gradient, div-div penalty and local projection (with the
- * Jacobian at every quadrature point); every other operator (the fused
- * convective substep, the symmetric-gradient viscous operator, coordinates,
- * load vectors) returns DGMF_UNSUPPORTED on them.
+ * weights w_q det J_q), the convective operator and its VJP, the V3c
+ * divergence, gradient, div-div penalty and local projection, the viscous
+ * operator in the symmetric-gradient form and its CG (with the Jacobian at
+ * every quadrature point), node and quadrature-point coordinates and load
+ * vectors; the fused convective substep returns DGMF_UNSUPPORTED on them.
  * degree k in 1..7; every cell count >= 1; lengths > 0. */
 typedef struct {
   int degree;
@@ -137,7 +137,9 @@ typedef struct {
 dgmf_status dgmf_mesh_create(const dgmf_box_desc* desc, dgmf_mesh* out);
 /* Host outputs (either may be NULL). */
 dgmf_status dgmf_mesh_info(dgmf_mesh mesh, int64_t* n_cells, int64_t* n_dofs_per_field);
-/* Physical coordinates of every DoF: xyz is a device double array [3][N]. */
+/* Physical coordinates of every DoF: xyz is a device double array [3][N]
+ * (on curved cells the deformed node positions, which the cell maps
+ * interpolate). */
 dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t stream);
 /* dst = M^{-1} src for n_fields consecutive scalar fields ([n_fields][N],
  * dtype DGMF_F64 or DGMF_F32), M the block-diagonal DG mass matrix of the
@@ -227,18 +229,23 @@ dgmf_status dgmf_operator_apply(dgmf_op op, dgmf_dtype dtype, const void* src, v
  * F^nu(u) = 2 nu eps(u), fluxes U* and F^nu* with penalty tau nu, boundary
  * faces with g_u = 0 and penalty 2 tau nu), plus mass_coeff M, with the
  * operator's coefficients and penalty.  Computed as this operator applied to
- * every component plus nu times the component coupling.  Axis-aligned meshes
- * (sheared: DGMF_UNSUPPORTED).  u, out must not overlap.  Asynchronous. */
+ * every component plus nu times the component coupling.  Axis-aligned and
+ * curved cells (curved: the stored-metric apply per component, the coupling
+ * with the Jacobian of the cell map evaluated at every Gauss point of cells
+ * and faces; sheared: DGMF_UNSUPPORTED).  u, out must not overlap.
+ * Asynchronous (curved meshes upload small tables on the first call). */
 dgmf_status dgmf_viscous_apply(dgmf_op op, const double* u, double* out, hipStream_t stream);
 
 /* diag = diag(H), N values of dtype.  Asynchronous. */
 dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hipStream_t stream);
 /* Cell quadrature points of the operator's rule: xyz device double [3][n_cells*n_q^3],
- * point index c*n_q^3 + (qz*n_q + qy)*n_q + qx.  Asynchronous. */
+ * point index c*n_q^3 + (qz*n_q + qy)*n_q + qx (curved cells: the cell map
+ * at the Gauss points).  Asynchronous. */
 dgmf_status dgmf_quadrature_points(dgmf_op op, double* xyz, hipStream_t stream);
 /* b_i = sum_K (f, phi_i)_K by the operator's Gauss rule, f given at the
  * quadrature points (layout of dgmf_quadrature_points), fp64.  This is the
- * load vector of the right-hand sides in Sec. 4.4.  Asynchronous. */
+ * load vector of the right-hand sides in Sec. 4.4; on curved cells with the
+ * point weights w_q det J_q.  Asynchronous. */
 dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_t stream);
 
 /* ------------------------------------------------------------------ CG --- */
@@ -339,7 +346,8 @@ dgmf_status dgmf_cg_solve_noalloc(dgmf_op op, const double* b, double* x, const 
  * are ignored.  b, x: device fp64 [3][N]
  * (x: initial guess in, solution out); workspace: device memory of at least
  * dgmf_viscous_cg_workspace_bytes, 256-byte aligned; none may overlap.
- * Meshes with shear or curved cells: DGMF_UNSUPPORTED.
+ * Curved cells: the curved operator, and for precond 3 the point-weight
+ * inverse mass.  Meshes with shear: DGMF_UNSUPPORTED.
  * Synchronous like dgmf_cg_solve: *out is filled and the returned status
  * equals out->status (NOT_CONVERGED, BREAKDOWN, NONFINITE on failure). */
 dgmf_status dgmf_viscous_cg_workspace_bytes(dgmf_op op, size_t* bytes);

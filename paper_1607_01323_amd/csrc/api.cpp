@@ -586,11 +586,25 @@ static dgmf_status flat_check(dgmf_mesh mesh, const char* who) {
   return DGMF_OK;
 }
 
+static void curved_box(dgmf_mesh mesh, double lo[3], double len[3]) {
+  lo[0] = 0.0;
+  lo[1] = mesh->desc.y0;
+  lo[2] = 0.0;
+  len[0] = mesh->desc.lx;
+  len[1] = mesh->desc.ly;
+  len[2] = mesh->desc.lz;
+}
+
 dgmf_status dgmf_mesh_node_coords(dgmf_mesh mesh, double* xyz, hipStream_t stream) {
   if (!mesh || !xyz) return fail(DGMF_INVALID, "mesh_node_coords: null argument");
-  if (dgmf_status e = flat_check(mesh, "mesh_node_coords")) return e;
   if (!aligned(xyz, 8)) return fail(DGMF_INVALID, "mesh_node_coords: misaligned output");
   DeviceGuard dg(mesh->device);
+  if (mesh->desc.curve_amp != 0.0) {
+    double lo[3], len[3];
+    curved_box(mesh, lo, len);
+    return launch_curved_coords(mesh->tab.n, mesh->tab.n, false, mesh->g64, lo, len, mesh->desc.curve_amp, xyz,
+                                mesh->ncells, stream);
+  }
   return launch_node_coords(mesh->tab.n, mesh->g64, mesh->shear, xyz, mesh->ncells, stream);
 }
 
@@ -729,19 +743,81 @@ static dgmf_status curved_v3_geometry(dgmf_mesh mesh) {
   return DGMF_OK;
 }
 
+// Curved cells: 1D tables of the viscous coupling (S, D, w at the k+1 Gauss
+// points, then the GLL nodes, l(0) l(1) and l'(0) l'(1)), uploaded on first use.
+static dgmf_status curved_eps_tables(dgmf_mesh mesh) {
+  if (mesh->egeo.tab) return DGMF_OK;
+  const int n = mesh->tab.n, nq = n;
+  const dgmf::Tables1D& t = mesh->tab;
+  std::vector<double> h;
+  h.insert(h.end(), t.S.begin(), t.S.end());
+  h.insert(h.end(), t.D.begin(), t.D.end());
+  h.insert(h.end(), t.wq.begin(), t.wq.end());
+  int rows[3];
+  append_curved_rows(t, h, rows);
+  dgmf_status st;
+  if ((st = mesh->etab.upload(h.data(), h.size() * sizeof(double)))) return st;
+  ConvGeom& g = mesh->egeo;
+  g.nx = mesh->g64.nx;
+  g.ny = mesh->g64.ny;
+  g.nz = mesh->g64.nz;
+  g.neu = neumann_mask(mesh->desc);
+  for (int d = 0; d < 3; ++d) {
+    g.per[d] = mesh->g64.per[d];
+    g.h[d] = mesh->g64.h[d];
+    g.hinv[d] = mesh->g64.hinv[d];
+  }
+  g.S = 0;
+  g.D = nq * n;
+  g.w = 2 * nq * n;
+  g.Mi = 0;
+  g.cmet = g.fmet = nullptr;
+  for (int k = 0; k < 3; ++k) mesh->eoff[k] = rows[k];
+  g.tab = static_cast<const double*>(mesh->etab.p);
+  return DGMF_OK;
+}
+
+// out = H_eps u on curved cells: the stored-metric scalar apply per component, then the coupling
+static dgmf_status viscous_apply_curved(dgmf_op op, const double* u, double* out, hipStream_t stream) {
+  dgmf_mesh mesh = op->mesh;
+  dgmf_status e = curved_eps_tables(mesh);
+  if (e) return e;
+  const int64_t N = mesh->ndofs;
+  for (int a = 0; a < 3; ++a)
+    if ((e = sipg_apply<double>(op, u + a * N, out + a * N, nullptr, nullptr, stream))) return e;
+  const double* x0[3] = {mesh->g64.x0[0], mesh->g64.x0[1], mesh->g64.x0[2]};
+  const double* hh[3] = {mesh->g64.h[0], mesh->g64.h[1], mesh->g64.h[2]};
+  const double lo[3] = {0.0, mesh->desc.y0, 0.0};
+  const double len[3] = {mesh->desc.lx, mesh->desc.ly, mesh->desc.lz};
+  return launch_eps_curved(mesh->tab.n, mesh->egeo, x0, hh, lo, len, mesh->desc.curve_amp, mesh->eoff[0],
+                           mesh->eoff[1], mesh->eoff[2], u, out, op->sipg.diff_coeff, mesh->ncells, stream);
+}
+
+}  // extern "C"
+
+namespace dgmf {
+dgmf_status viscous_apply_any(dgmf_op op, const double* u, double* out, hipStream_t stream) {
+  if (op->mesh->desc.curve_amp != 0.0) return viscous_apply_curved(op, u, out, stream);
+  const int64_t N = op->mesh->ndofs;
+  for (int a = 0; a < 3; ++a)
+    if (dgmf_status e = sipg_apply<double>(op, u + a * N, out + a * N, nullptr, nullptr, stream)) return e;
+  return launch_eps_coupling(op->mesh->tab.n, op->mesh->g64, static_cast<const double*>(op->mesh->v3tab.p), u, out,
+                             op->sipg.diff_coeff, op->mesh->ncells, stream);
+}
+}  // namespace dgmf
+
+extern "C" {
+
 dgmf_status dgmf_viscous_apply(dgmf_op op, const double* u, double* out, hipStream_t stream) {
   if (!op || op->kind != 1) return fail(DGMF_INVALID, "viscous_apply: not an SIPG operator");
-  dgmf_status e = v3_check(op->mesh, "viscous_apply");
+  dgmf_status e = v3_check(op->mesh, "viscous_apply", true);
   if (e) return e;
   if (!u || !out || !aligned(u, 8) || !aligned(out, 8))
     return fail(DGMF_INVALID, "viscous_apply: null or misaligned vector");
   const int64_t N = op->mesh->ndofs;
   if (overlap(u, out, 24 * N)) return fail(DGMF_INVALID, "viscous_apply: u and out overlap");
   DeviceGuard dg(op->mesh->device);
-  for (int a = 0; a < 3; ++a)
-    if ((e = sipg_apply<double>(op, u + a * N, out + a * N, nullptr, nullptr, stream))) return e;
-  return launch_eps_coupling(op->mesh->tab.n, op->mesh->g64, static_cast<const double*>(op->mesh->v3tab.p), u, out,
-                             op->sipg.diff_coeff, op->mesh->ncells, stream);
+  return viscous_apply_any(op, u, out, stream);
 }
 
 dgmf_status dgmf_divergence_apply(dgmf_mesh mesh, const double* u, double* out, hipStream_t stream) {
@@ -944,20 +1020,27 @@ dgmf_status dgmf_operator_diagonal(dgmf_op op, dgmf_dtype dtype, void* diag, hip
 dgmf_status dgmf_quadrature_points(dgmf_op op, double* xyz, hipStream_t stream) {
   if (!op || op->kind != 1) return fail(DGMF_INVALID, "quadrature_points: not an SIPG operator");
   if (!xyz || !aligned(xyz, 8)) return fail(DGMF_INVALID, "quadrature_points: null or misaligned output");
-  if (dgmf_status e = flat_check(op->mesh, "quadrature_points")) return e;
   DeviceGuard dg(op->mesh->device);
+  if (op->mesh->desc.curve_amp != 0.0) {
+    double lo[3], len[3];
+    curved_box(op->mesh, lo, len);
+    return launch_curved_coords(op->tab.n, op->nq, true, op->g64, lo, len, op->mesh->desc.curve_amp, xyz,
+                                op->mesh->ncells, stream);
+  }
   return launch_qp_coords(op->tab.n, op->nq, op->g64, op->mesh->shear, xyz, op->mesh->ncells, stream);
 }
 
 dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_t stream) {
   if (!op || op->kind != 1) return fail(DGMF_INVALID, "integrate: not an SIPG operator");
-  if (dgmf_status e = flat_check(op->mesh, "integrate")) return e;
   if (!f_qp || !b || !aligned(f_qp, 8) || !aligned(b, 8))
     return fail(DGMF_INVALID, "integrate: null or misaligned vector");
   const int64_t nq3 = static_cast<int64_t>(op->nq) * op->nq * op->nq;
   if (overlap(f_qp, b, 8 * std::min<int64_t>(op->mesh->ndofs, op->mesh->ncells * nq3)))
     return fail(DGMF_INVALID, "integrate: input and output overlap");
   DeviceGuard dg(op->mesh->device);
+  if (op->mesh->desc.curve_amp != 0.0)   // n_q = k+1 here (sipg_create), the rule of the stored metric
+    return launch_integrate_curved(op->tab.n, op->g64.tab + TabLayout{op->tab.n, op->nq}.S(), op->mesh->mg64.cm, f_qp,
+                                   b, op->mesh->ncells, stream);
   return launch_integrate(op->tab.n, op->nq, op->g64, op->mesh->shear, f_qp, b, op->mesh->ncells, stream);
 }
 

@@ -1338,6 +1338,437 @@ dgmf_status launch_curv_cell_n(bool proj, const ConvGeom& g, const double* wdet,
   return DGMF_OK;
 }
 
+// ------------------------------------- viscous coupling on curved cells
+// The component coupling nu C(u) of the viscous operator in the
+// symmetric-gradient form (Sec. 3.2, implicit viscous step, s = 1,
+// F^nu(u) = 2 nu eps(u)) on iso-parametric curved cells; the rest of that
+// operator is the scalar SIPG Helmholtz operator of every component (the
+// stored-metric apply).  With d_b u_a the physical gradient, k+1 Gauss points
+// per direction, w|J| the weighted Jacobian determinant at a cell point, nw
+// the weighted outward normal (w dA n) at a face point and [u] the own trace
+// minus the neighbour's:
+//   (C u)_{c,i} = sum_q w|J| sum_a d_a phi_i d_c u_a
+//     - sum_p [ 1/2 nw_c (grad phi_i . [u]) + 1/2 phi_i (nw . d_c u_own + nw . d_c u_nb) ]   interior faces
+//     - sum_p [ nw_c (grad phi_i . u) + phi_i (nw . d_c u) ]                                  Dirichlet faces
+// (nw . d_c u = sum_a nw_a d_c u_a); homogeneous Neumann sides add nothing.
+// The Jacobian is evaluated in closed form at every point (curv_map.h), so
+// nothing is stored per point.  Reference gradients at face points: the
+// tangential ones from the nodal trace plane, the normal one from the nodal
+// normal-derivative plane (l'(0) or l'(1) along every normal line), for the
+// own cell and, from global memory, its neighbour.  One cell per workgroup.
+struct EpsCurvGeom {
+  ConvGeom g;    // tab: S, D, w at the Gauss points; E (l(0), l(1)) and Gd (l'(0), l'(1)) at offsets E, Gd
+  CurvMap m;
+  int E, Gd;
+};
+
+// node (l, j, i) at position m along the normal line of face direction d through face-plane entry (p1, p2)
+template <int N>
+__device__ __forceinline__ int line_node(int d, int m, int p1, int p2) {
+  if (d == 0) return (p2 * N + p1) * N + m;
+  if (d == 1) return (p2 * N + m) * N + p1;
+  return (m * N + p2) * N + p1;
+}
+
+// J of a point from the per-direction values sg[e] = sig_e and dsg[e] = sig_e'
+// there (curv_map.h), with the cell sizes h[e]; returns J^{-1} and det J.
+__device__ __forceinline__ double jinv_from(const CurvMap& m, const double h[3], const double sg[3],
+                                            const double dsg[3], double Ji[3][3]) {
+  double J[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) J[r * 3 + d] = r == d ? h[r] : m.amp * m.len[r] * dsg[d] * sg[3 - r - d];
+  double A[3][3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) adj_row(J, e, A[e]);
+  const double det = J[0] * A[0][0] + J[3] * A[0][1] + J[6] * A[0][2];
+  const double inv = 1.0 / det;
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Ji[e][b] = A[e][b] * inv;
+  return det;
+}
+
+// Reference gradient of the nodal field sIn[N^3] at this thread's quadrature
+// z-column (gx, gy, gz).  T1 (2 N^2 Q) and T2 (3 N Q^2) are LDS scratch; ends
+// with a barrier.
+template <int N, int Q>
+__device__ __forceinline__ void grad3(const double* __restrict__ S, const double* __restrict__ D, const double* sIn,
+                                      double* T1, double* T2, int tid, int nthr, bool own, int qx, int qy,
+                                      double (&gx)[Q], double (&gy)[Q], double (&gz)[Q]) {
+  constexpr int N2 = N * N, Q2 = Q * Q;
+  for (int job = tid; job < N2; job += nthr) {          // x: line (l, j), values and x-derivatives
+    double v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = sIn[job * N + i];
+#pragma unroll kSweepUnroll<N, Q>
+    for (int q = 0; q < Q; ++q) {
+      double a = 0, b = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        a = fma(S[q * N + i], v[i], a);
+        b = fma(D[q * N + i], v[i], b);
+      }
+      T1[job * Q + q] = a;
+      T1[N2 * Q + job * Q + q] = b;
+    }
+  }
+  __syncthreads();
+  for (int job = tid; job < 2 * N * Q; job += nthr) {   // y: (input plane, l, qx)
+    const int qxx = job % Q, l = (job / Q) % N, w = job / (N * Q);
+    double v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = T1[w * N2 * Q + (l * N + j) * Q + qxx];
+#pragma unroll kSweepUnroll<N, Q>
+    for (int q = 0; q < Q; ++q) {
+      double a = 0, b = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        a = fma(S[q * N + j], v[j], a);
+        b = fma(D[q * N + j], v[j], b);
+      }
+      if (w == 0) {
+        T2[(l * Q + q) * Q + qxx] = a;                // S_y S_x u
+        T2[N * Q2 + (l * Q + q) * Q + qxx] = b;       // D_y S_x u
+      } else {
+        T2[2 * N * Q2 + (l * Q + q) * Q + qxx] = a;   // S_y D_x u
+      }
+    }
+  }
+  __syncthreads();
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) gx[q] = gy[q] = gz[q] = 0.0;
+#pragma unroll kSweepUnroll<N, Q>
+    for (int l = 0; l < N; ++l) {
+      const double a = T2[(l * Q + qy) * Q + qx], b = T2[N * Q2 + (l * Q + qy) * Q + qx],
+                   c = T2[2 * N * Q2 + (l * Q + qy) * Q + qx];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        gz[q] = fma(D[q * N + l], a, gz[q]);
+        gy[q] = fma(S[q * N + l], b, gy[q]);
+        gx[q] = fma(S[q * N + l], c, gx[q]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int N>
+__global__ void __launch_bounds__((CShape<N, N>::THREADS)) k_eps_curved(const double* __restrict__ U,
+                                                                      double* __restrict__ out,
+                                                                      const EpsCurvGeom eg, double nu,
+                                                                      int64_t ncells) {
+  constexpr int Q = N;
+  using SH = CShape<N, Q>;
+  constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2;
+  constexpr int XC = 2 * N2 * Q + 3 * N * Q2 > 3 * N * Q2 + 2 * N2 * Q ? 2 * N2 * Q + 3 * N * Q2
+                                                                         : 3 * N * Q2 + 2 * N2 * Q;
+  // faces: nodal planes [side][comp][value | normal derivative], first sweep [side][comp][3],
+  // face-point data [side][comp][4], fluxes [comp][4], lift stage [comp][4] and lifted planes [comp][2]
+  constexpr int XF = 12 * N2 + 18 * N * Q + 24 * Q2 + 12 * Q2 + 12 * N * Q + 6 * N2;
+  constexpr int X = XC > XF ? XC : XF;
+  __shared__ double sU[3 * N3];
+  __shared__ double sO[3 * N3];
+  __shared__ double sX[X];
+  __shared__ double sSG[3][Q + 2], sDSG[3][Q + 2];
+  const ConvGeom& g = eg.g;
+  const CurvMap& m = eg.m;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
+  if (cell >= ncells) return;
+  const int64_t Nd = ncells * N3;
+  const double* S = g.tab + g.S;
+  const double* D = g.tab + g.D;
+  const double* W = g.tab + g.w;
+  const double* E = g.tab + eg.E;
+  const double* Gd = g.tab + eg.Gd;
+  CellGeo cg;
+  conv_cell(g, cell, cg);
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int a = e / N3, r = e % N3;
+    sU[e] = U[a * Nd + cell * N3 + r];
+  }
+  // sig and sig' of the map per direction at the Gauss points (0..Q-1) and the ends (Q, Q+1)
+  for (int e = tid; e < 3 * (Q + 2); e += nthr) {
+    const int dir = e / (Q + 2), t = e % (Q + 2);
+    const double* val = t < Q ? S + t * N : E + (t - Q) * N;
+    const double* der = t < Q ? D + t * N : Gd + (t - Q) * N;
+    curv_sig_at<N>(m, dir, cg.c[dir], val, der, sSG[dir][t], sDSG[dir][t]);
+  }
+  __syncthreads();
+  const bool own = tid < Q2;
+  const int qx = tid % Q, qy = (tid / Q) % Q;
+  // ---- cell term: fe_c[r] = w|J| sum_a Ji[r][a] d_c u_a, lifted by the reference gradients
+  double gr[3][3][Q];   // [component][reference direction][qz]; becomes fe[c][r][qz]
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    grad3<N, Q>(S, D, sU + a * N3, sX, sX + 2 * N2 * Q, tid, nthr, own, qx, qy, gr[a][0], gr[a][1], gr[a][2]);
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int qi[3] = {qx, qy, q};
+      double sg[3], dsg[3], Ji[3][3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        sg[e] = sSG[e][qi[e]];
+        dsg[e] = sDSG[e][qi[e]];
+      }
+      const double det = jinv_from(m, cg.h, sg, dsg, Ji);
+      const double wj = fabs(det) * W[qx] * W[qy] * W[q];
+      double Gp[3][3];   // Gp[a][b] = d_b u_a
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          Gp[a][b] = fma(gr[a][0][q], Ji[0][b], fma(gr[a][1][q], Ji[1][b], gr[a][2][q] * Ji[2][b]));
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          gr[c][r][q] = wj * fma(Ji[r][0], Gp[0][c], fma(Ji[r][1], Gp[1][c], Ji[r][2] * Gp[2][c]));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    cell_lift_grad<N, Q>(S, D, gr[c][0], gr[c][1], gr[c][2], own, qx, qy, sX, sX + 3 * N * Q2, sO + c * N3, nu, tid,
+                         nthr);
+  // ---- faces
+  double* P = sX;                    // [side][comp][2][N2]
+  double* F1 = P + 12 * N2;          // [side][comp][3][N][Q]
+  double* F2 = F1 + 18 * N * Q;      // [side][comp][4][Q2]: value, d/dt2, d/dt1, d/dn
+  double* R = F2 + 24 * Q2;          // [comp][4][Q2]: value flux, reference gradient flux along t1, t2, d
+  double* L1 = R + 12 * Q2;          // [comp][4][N][Q]
+  double* LP = L1 + 12 * N * Q;      // [comp][2][N2]: tangential lift, normal lift
+#pragma unroll 1
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, s = f & 1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const int64_t nb = conv_nb(g, cg, cell, d, s);
+    if (nb < 0 && ((g.neu >> f) & 1)) continue;   // homogeneous Neumann side: no term
+    const bool inner = nb >= 0;
+    const int nsides = inner ? 2 : 1;
+    const double* gs = Gd + s * N;          // l'(end) of the own side
+    const double* gn = Gd + (1 - s) * N;    // of the neighbour side
+    for (int e = tid; e < nsides * 3 * N2; e += nthr) {
+      const int side = e / (3 * N2), a = (e / N2) % 3, p = e % N2, p1 = p % N, p2 = p / N;
+      double v = 0.0, dn = 0.0;
+      if (side == 0) {
+        const double* u = sU + a * N3;
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm) dn = fma(gs[mm], u[line_node<N>(d, mm, p1, p2)], dn);
+        v = u[line_node<N>(d, s ? N - 1 : 0, p1, p2)];
+      } else {
+        const double* u = U + a * Nd + nb * N3;
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm) dn = fma(gn[mm], u[line_node<N>(d, mm, p1, p2)], dn);
+        v = u[line_node<N>(d, s ? 0 : N - 1, p1, p2)];
+      }
+      P[((side * 3 + a) * 2 + 0) * N2 + p] = v;
+      P[((side * 3 + a) * 2 + 1) * N2 + p] = dn;
+    }
+    __syncthreads();
+    for (int job = tid; job < nsides * 3 * N; job += nthr) {   // along t1: (side, comp, p2)
+      const int p2 = job % N, sa = job / N;
+      double v[N], w[N];
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        v[p] = P[(sa * 2 + 0) * N2 + p2 * N + p];
+        w[p] = P[(sa * 2 + 1) * N2 + p2 * N + p];
+      }
+#pragma unroll kSweepUnroll<N, Q>
+      for (int q = 0; q < Q; ++q) {
+        double a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+          a0 = fma(S[q * N + p], v[p], a0);
+          a1 = fma(D[q * N + p], v[p], a1);
+          a2 = fma(S[q * N + p], w[p], a2);
+        }
+        F1[((sa * 3 + 0) * N + p2) * Q + q] = a0;
+        F1[((sa * 3 + 1) * N + p2) * Q + q] = a1;
+        F1[((sa * 3 + 2) * N + p2) * Q + q] = a2;
+      }
+    }
+    __syncthreads();
+    for (int job = tid; job < nsides * 3 * Q; job += nthr) {   // along t2: (side, comp, q1)
+      const int q1 = job % Q, sa = job / Q;
+      double v0[N], v1[N], v2[N];
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        v0[p] = F1[((sa * 3 + 0) * N + p) * Q + q1];
+        v1[p] = F1[((sa * 3 + 1) * N + p) * Q + q1];
+        v2[p] = F1[((sa * 3 + 2) * N + p) * Q + q1];
+      }
+#pragma unroll kSweepUnroll<N, Q>
+      for (int q = 0; q < Q; ++q) {
+        double val = 0, dt2 = 0, dt1 = 0, dnn = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+          val = fma(S[q * N + p], v0[p], val);
+          dt2 = fma(D[q * N + p], v0[p], dt2);
+          dt1 = fma(S[q * N + p], v1[p], dt1);
+          dnn = fma(S[q * N + p], v2[p], dnn);
+        }
+        F2[((sa * 4 + 0) * Q + q) * Q + q1] = val;
+        F2[((sa * 4 + 1) * Q + q) * Q + q1] = dt2;
+        F2[((sa * 4 + 2) * Q + q) * Q + q1] = dt1;
+        F2[((sa * 4 + 3) * Q + q) * Q + q1] = dnn;
+      }
+    }
+    __syncthreads();
+    // fluxes at the face points
+    double sgn_nb = 0.0, dsg_nb = 0.0, h_nb = 0.0;
+    if (inner) {
+      const int nd = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+      int cc = cg.c[d] + (s ? 1 : -1);
+      cc = cc < 0 ? nd - 1 : (cc >= nd ? 0 : cc);
+      curv_sig_at<N>(m, d, cc, E + (1 - s) * N, Gd + (1 - s) * N, sgn_nb, dsg_nb);
+      h_nb = m.h[d][cc];
+    }
+    for (int pq = tid; pq < Q2; pq += nthr) {
+      const int q1 = pq % Q, q2 = pq / Q;
+      double sg[3], dsg[3], Jo[3][3], Je[3][3];
+      sg[d] = sSG[d][Q + s];
+      dsg[d] = sDSG[d][Q + s];
+      sg[t1] = sSG[t1][q1];
+      dsg[t1] = sDSG[t1][q1];
+      sg[t2] = sSG[t2][q2];
+      dsg[t2] = sDSG[t2][q2];
+      const double det = jinv_from(m, cg.h, sg, dsg, Jo);
+      // weighted outward normal: w_t1 w_t2 det J J^{-T} e_d, oriented out of this cell
+      const double wn = (s ? 1.0 : -1.0) * W[q1] * W[q2] * fabs(det);
+      const double nw[3] = {wn * Jo[d][0], wn * Jo[d][1], wn * Jo[d][2]};
+      double uo[3], Go[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double* Fa = F2 + (0 * 3 + a) * 4 * Q2 + pq;
+        double gref[3];
+        uo[a] = Fa[0];
+        gref[t2] = Fa[Q2];
+        gref[t1] = Fa[2 * Q2];
+        gref[d] = Fa[3 * Q2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Go[a][b] = fma(gref[0], Jo[0][b], fma(gref[1], Jo[1][b], gref[2] * Jo[2][b]));
+      }
+      double jmp[3], fac;
+      double Rv[3];   // value flux per output component, before the factor -fac nu
+      if (inner) {
+        double h3[3] = {cg.h[0], cg.h[1], cg.h[2]};
+        h3[d] = h_nb;
+        sg[d] = sgn_nb;
+        dsg[d] = dsg_nb;
+        jinv_from(m, h3, sg, dsg, Je);
+        double ue[3], Ge[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double* Fa = F2 + (1 * 3 + a) * 4 * Q2 + pq;
+          double gref[3];
+          ue[a] = Fa[0];
+          gref[t2] = Fa[Q2];
+          gref[t1] = Fa[2 * Q2];
+          gref[d] = Fa[3 * Q2];
+#pragma unroll
+          for (int b = 0; b < 3; ++b) Ge[a][b] = fma(gref[0], Je[0][b], fma(gref[1], Je[1][b], gref[2] * Je[2][b]));
+          jmp[a] = uo[a] - ue[a];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          Rv[c] = fma(nw[0], Go[0][c] + Ge[0][c], fma(nw[1], Go[1][c] + Ge[1][c], nw[2] * (Go[2][c] + Ge[2][c])));
+        fac = 0.5;
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) jmp[a] = uo[a];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Rv[c] = fma(nw[0], Go[0][c], fma(nw[1], Go[1][c], nw[2] * Go[2][c]));
+        fac = 1.0;
+      }
+      double z[3];   // sum_b Ji[r][b] [u]_b: grad phi . [u] = sum_r dphi/dxi_r z_r
+#pragma unroll
+      for (int r = 0; r < 3; ++r) z[r] = fma(Jo[r][0], jmp[0], fma(Jo[r][1], jmp[1], Jo[r][2] * jmp[2]));
+      const double sc = -fac * nu;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double* Rc = R + c * 4 * Q2 + pq;
+        Rc[0] = sc * Rv[c];
+        Rc[Q2] = sc * nw[c] * z[t1];
+        Rc[2 * Q2] = sc * nw[c] * z[t2];
+        Rc[3 * Q2] = sc * nw[c] * z[d];
+      }
+    }
+    __syncthreads();
+    for (int job = tid; job < 3 * Q; job += nthr) {   // transposed, along t2: [q2][q1] -> [p2][q1]
+      const int q1 = job % Q, c = job / Q;
+      double v[4][Q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[k][q] = R[(c * 4 + k) * Q2 + q * Q + q1];
+#pragma unroll kSweepUnroll<N, Q>
+      for (int p = 0; p < N; ++p) {
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          a0 = fma(S[q * N + p], v[0][q], a0);
+          a1 = fma(S[q * N + p], v[1][q], a1);
+          a2 = fma(D[q * N + p], v[2][q], a2);
+          a3 = fma(S[q * N + p], v[3][q], a3);
+        }
+        L1[((c * 4 + 0) * N + p) * Q + q1] = a0;
+        L1[((c * 4 + 1) * N + p) * Q + q1] = a1;
+        L1[((c * 4 + 2) * N + p) * Q + q1] = a2;
+        L1[((c * 4 + 3) * N + p) * Q + q1] = a3;
+      }
+    }
+    __syncthreads();
+    for (int job = tid; job < 3 * N; job += nthr) {   // transposed, along t1: [p2][q1] -> [p2][p1]
+      const int p2 = job % N, c = job / N;
+      double v[4][Q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[k][q] = L1[((c * 4 + k) * N + p2) * Q + q];
+#pragma unroll kSweepUnroll<N, Q>
+      for (int p1 = 0; p1 < N; ++p1) {
+        double tg = 0, nn = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          tg = fma(S[q * N + p1], v[0][q] + v[2][q], fma(D[q * N + p1], v[1][q], tg));
+          nn = fma(S[q * N + p1], v[3][q], nn);
+        }
+        LP[(c * 2 + 0) * N2 + p2 * N + p1] = tg;
+        LP[(c * 2 + 1) * N2 + p2 * N + p1] = nn;
+      }
+    }
+    __syncthreads();
+    for (int job = tid; job < 3 * N2; job += nthr) {  // onto the face nodes and along the normal lines
+      const int c = job / N2, p = job % N2, p1 = p % N, p2 = p / N;
+      const double tg = LP[(c * 2 + 0) * N2 + p], nn = LP[(c * 2 + 1) * N2 + p];
+      double* o = sO + c * N3;
+#pragma unroll
+      for (int mm = 0; mm < N; ++mm) o[line_node<N>(d, mm, p1, p2)] = fma(gs[mm], nn, o[line_node<N>(d, mm, p1, p2)]);
+      o[line_node<N>(d, s ? N - 1 : 0, p1, p2)] += tg;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 3 * N3; e += nthr) {
+    const int a = e / N3, r = e % N3;
+    out[a * Nd + cell * N3 + r] += sO[e];
+  }
+}
+
+template <int N>
+dgmf_status launch_eps_curved_n(const EpsCurvGeom& eg, const double* u, double* out, double nu, int64_t ncells,
+                                hipStream_t s) {
+  if (ncells > 0x7fffffff) return fail(DGMF_UNSUPPORTED, "mesh too large for one launch");
+  hipLaunchKernelGGL((k_eps_curved<N>), dim3(static_cast<unsigned>(ncells)), dim3(CShape<N, N>::THREADS), 0, s, u,
+                     out, eg, nu, ncells);
+  DGMF_LAUNCH_CHECK("k_eps_curved");
+  return DGMF_OK;
+}
+
 }  // namespace
 
 // Supported (n, n_q): the paper's floor(3k/2)+1 and floor(3(k+1)/2) for k = 1..6
@@ -1414,6 +1845,32 @@ dgmf_status launch_curv_cell(int n, bool proj, const ConvGeom& g, const double* 
   X(2) X(3) X(4) X(5) X(6) X(7)
 #undef X
   return fail(DGMF_UNSUPPORTED, "curved div-div penalty / projection: n = %d not built", n);
+}
+
+dgmf_status launch_eps_curved(int n, const ConvGeom& g, const double* const x0[3], const double* const h[3],
+                              const double lo[3], const double len[3], double amp, int off_nodes, int off_e,
+                              int off_gd, const double* u, double* out, double nu, int64_t ncells, hipStream_t s) {
+  EpsCurvGeom eg{};
+  eg.g = g;
+  for (int d = 0; d < 3; ++d) {
+    eg.m.x0[d] = x0[d];
+    eg.m.h[d] = h[d];
+    eg.m.lo[d] = lo[d];
+    eg.m.len[d] = len[d];
+  }
+  eg.m.amp = amp;
+  eg.m.nodes = g.tab + off_nodes;
+  eg.E = off_e;
+  eg.Gd = off_gd;
+  switch (n) {
+    case 2: return launch_eps_curved_n<2>(eg, u, out, nu, ncells, s);
+    case 3: return launch_eps_curved_n<3>(eg, u, out, nu, ncells, s);
+    case 4: return launch_eps_curved_n<4>(eg, u, out, nu, ncells, s);
+    case 5: return launch_eps_curved_n<5>(eg, u, out, nu, ncells, s);
+    case 6: return launch_eps_curved_n<6>(eg, u, out, nu, ncells, s);
+    case 7: return launch_eps_curved_n<7>(eg, u, out, nu, ncells, s);
+    default: return fail(DGMF_UNSUPPORTED, "curved viscous operator: n = %d not built", n);
+  }
 }
 
 }  // namespace dgmf

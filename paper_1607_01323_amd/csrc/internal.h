@@ -170,6 +170,14 @@ dgmf_status launch_qp_coords(int n, int nq, const CartGeom<double>& g, const She
                              int64_t ncells, hipStream_t s);
 dgmf_status launch_integrate(int n, int nq, const CartGeom<double>& g, const Shear& sh, const double* f, double* b,
                              int64_t ncells, hipStream_t s);
+// Curved cells: node (quadrature = false) or Gauss-point (true) positions of
+// the deformed box (amplitude amp, origin lo, lengths len); the load vector
+// with the point weights w_q det J_q of the stored cell metric cm (n_q = k+1,
+// S the n_q x n interpolation table).
+dgmf_status launch_curved_coords(int n, int nq, bool quadrature, const CartGeom<double>& g, const double lo[3],
+                                 const double len[3], double amp, double* xyz, int64_t ncells, hipStream_t s);
+dgmf_status launch_integrate_curved(int n, const double* S, const double* cm, const double* f, double* b,
+                                    int64_t ncells, hipStream_t s);
 
 // Chebyshev-Jacobi step fused into the store of an operator apply: with x_k
 // the apply's input and y = H x_k, the kernel overwrites dst (holding x_{k-1})
@@ -292,6 +300,15 @@ dgmf_status launch_v3_tau(int n, const CartGeom<double>& g, const double* tab, c
 // operator (u, out: [3][N]); see eps.hip.
 dgmf_status launch_eps_coupling(int n, const CartGeom<double>& g, const double* tab, const double* u, double* out,
                                 double nu, int64_t ncells, hipStream_t s);
+// out += nu C(u) on iso-parametric curved cells (the coupling of the same
+// operator, Jacobians in closed form from the box deformation; see conv.hip).
+// g: tables S, D, w at the k+1 Gauss points; off_*: offsets into g.tab of
+// the GLL nodes, l(0) l(1) and l'(0) l'(1).
+dgmf_status launch_eps_curved(int n, const ConvGeom& g, const double* const x0[3], const double* const h[3],
+                              const double lo[3], const double len[3], double amp, int off_nodes, int off_e,
+                              int off_gd, const double* u, double* out, double nu, int64_t ncells, hipStream_t s);
+// H_eps u of an SIPG operator on affine or curved cells (u, out: [3][N]); device already current
+dgmf_status viscous_apply_any(dgmf_op op, const double* u, double* out, hipStream_t stream);
 bool v3_projection_supported(int n);
 dgmf_status launch_v3_projection(int n, const CartGeom<double>& g, const double* tab, const double* tau,
                                  const double* rhs, double* x, double rtol, int max_iter, int* iters, int64_t ncells,
@@ -372,6 +389,11 @@ struct dgmf_mesh_ {
   // gradient, filled on their first call
   dgmf::DevBuf qtab, qmet;
   dgmf::ConvGeom qgeo{};
+  // curved cells: 1D tables of the viscous coupling (no per-point data), set up on first use;
+  // eoff: offsets of the GLL nodes, l(0) l(1) and l'(0) l'(1) in etab
+  dgmf::DevBuf etab;
+  dgmf::ConvGeom egeo{};
+  int eoff[3] = {0, 0, 0};
   int nops = 0;                    // live operators built on this mesh
 };
 
@@ -392,4 +414,11 @@ struct dgmf_op_ {
   dgmf::MetricGeom<float> mg32{};
   bool metric = false;
   dgmf::MgHierarchy* mgh = nullptr;   // multigrid levels, built on first use
+  // largest Ritz value of the Chebyshev preconditioner's Lanczos run, kept for
+  // later solves with the same precision, step count, seed and projection
+  struct {
+    int valid = 0, dtype = 0, steps = 0, project = 0;
+    uint64_t seed = 0;
+    double theta = 0.0;
+  } lz;
 };

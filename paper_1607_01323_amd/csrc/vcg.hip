@@ -219,16 +219,15 @@ __global__ void __launch_bounds__(kThreads) k_v_scalar(VState* st, const double*
 }
 
 dgmf_status apply_eps(dgmf_op op, const double* u, double* out, hipStream_t s) {
-  const int64_t N = op->mesh->ndofs;
-  for (int a = 0; a < 3; ++a)
-    if (dgmf_status e = sipg_apply<double>(op, u + a * N, out + a * N, nullptr, nullptr, s)) return e;
-  return launch_eps_coupling(op->mesh->tab.n, op->mesh->g64, static_cast<const double*>(op->mesh->v3tab.p), u, out,
-                             op->sipg.diff_coeff, op->mesh->ncells, s);
+  return viscous_apply_any(op, u, out, s);
 }
 
-// z = M^{-1} r on the three components (affine cells; curved meshes are refused)
+// z = M^{-1} r on the three components (the point-weight form on curved cells)
 dgmf_status inv_mass3(dgmf_op op, const double* r, double* z, hipStream_t s) {
   const dgmf_mesh m = op->mesh;
+  if (m->desc.curve_amp != 0.0)
+    return launch_point_mass<double>(m->tab.n, static_cast<const double*>(m->pmt64.p), m->mg64.cm, r, z, m->ncells,
+                                     3, true, s);
   return launch_block_mass<double>(m->tab.n, m->g64, 1.0 / std::fabs(m->shear.det),
                                    static_cast<const double*>(m->minv64.p), r, z, m->ncells, 3, true, s);
 }
@@ -237,7 +236,6 @@ dgmf_status vcheck(dgmf_op op) {
   if (!op || op->kind != 1) return fail(DGMF_INVALID, "viscous_cg: not an SIPG operator");
   const dgmf_mesh m = op->mesh;
   if (m->shear.on) return fail(DGMF_UNSUPPORTED, "viscous_cg: sheared meshes are not supported");
-  if (m->desc.curve_amp != 0.0) return fail(DGMF_UNSUPPORTED, "viscous_cg: curved cells are not supported");
   return DGMF_OK;
 }
 

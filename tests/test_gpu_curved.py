@@ -8,8 +8,8 @@ diagonal with the oracle's assembled matrix (periodic, Dirichlet and Neumann
 walls, tanh grading, degrees 1-6); CG with Jacobi is compared with the
 oracle's iteration count and true residual; at the full channel size the
 apply is checked on sampled cells and the mixed-precision Chebyshev solve on
-the oracle's residual over sampled cells.  Operators that assume a constant
-Jacobian per cell refuse curved meshes.
+the oracle's residual over sampled cells.  The fused convective substep, which
+assumes a constant Jacobian per cell, refuses curved meshes.
 """
 import math
 
@@ -145,18 +145,19 @@ def test_multigrid_with_curved_finest_level(name, pdtype):
     gm.close()
 
 
-def test_flat_operators_refuse_curved_meshes():
+def test_fused_substep_refuses_curved_meshes():
+    """The fused convective substep assumes the constant-Jacobian inverse mass of an
+    affine cell; on curved cells it is refused (the apply and the point-weight
+    inverse mass serve there)."""
     require_gpu()
     import paper_1607_01323_amd as dg
     gm = dg.Mesh(2, 2, 2, 2, store_qp_metric=True, curve_amp=0.05)
     N = gm.ndofs
     u = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    cop = dg.ConvectiveOperator(gm)
     with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
-        gm.node_coords()
-    gop = dg.SipgOperator(gm, 1.0, 1.0, 1.0)
-    for call in (lambda: gop.quadrature_points(), lambda: gop.viscous_apply(u)):
-        with pytest.raises(dg.DgmfError, match="UNSUPPORTED"):
-            call()
+        cop.step(u, 1e-3)
+    cop.close()
     gm.close()
 
 
