@@ -315,8 +315,10 @@ def c1_measurements(dg, inp, torch):
 def c2_cg_measurements(dg, inp, torch, m2, op2):
     """PCG to 1e-10 on the headline mesh: the configured smooth right-hand side
     (nearly one eigenmode) and a random one; each solver runs twice and the
-    faster run is kept, so set-up that an operator keeps (the multigrid
-    hierarchy) is reported once as its own row."""
+    faster run is kept, so set-up that an operator keeps
+    (the multigrid hierarchy, the Chebyshev eigenvalue estimate) is not in the
+    kept row; multigrid and Chebyshev run in fp32 (mixed) and in fp64 (the
+    same algorithm all in fp64)."""
     ex = {}
     N2 = m2.ndofs
     qp = op2.quadrature_points()
@@ -327,20 +329,23 @@ def c2_cg_measurements(dg, inp, torch, m2, op2):
     b_rand = torch.as_tensor(inp.uniform(5, N2), device="cuda")
     for rhs_name, b2 in (("sinrhs", b_sin), ("randrhs", b_rand)):
         for name, kw in (("mixed_f32mg", dict(precond="multigrid", precond_dtype=torch.float32)),
+                         ("f64mg", dict(precond="multigrid", precond_dtype=torch.float64)),
                          ("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
                          ("f64cheb", dict(precond="chebyshev", precond_dtype=torch.float64)),
                          ("jacobi_f64", dict(precond="jacobi"))):
             best = None
-            for _ in range(2 if rhs_name == "sinrhs" else 1):
+            for _ in range(2):
                 x2 = torch.zeros(N2, dtype=torch.float64, device="cuda")
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 out = op2.cg(b2, x2, rtol=1e-10, max_iter=20000, check_every=16, project_mean=True, seed=42, **kw)
                 torch.cuda.synchronize()
                 tt = time.perf_counter() - t0
+                first = out.setup_s if best is None else best["first_setup_s"]
                 if best is None or tt < best["time_s"]:
                     best = {"time_s": tt, "iterations": out.iterations, "setup_s": out.setup_s,
                             "solve_s": out.solve_s, "rel_residual": out.rel_residual, "lambda_max": out.lambda_max}
+                best["first_setup_s"] = first
             ex[f"c2_cg_{rhs_name}_{name}"] = best
     return ex
 
@@ -603,6 +608,7 @@ def channel_measurements(dg, inp, torch, w, tag, cg=True, conv=True):
         b = op.integrate(fq)
         del fq
         for name, kw in (("mixed_f32mg", dict(precond="multigrid", precond_dtype=torch.float32)),
+                         ("f64mg", dict(precond="multigrid", precond_dtype=torch.float64)),
                          ("mixed_f32cheb", dict(precond="chebyshev", precond_dtype=torch.float32)),
                          ("f64cheb", dict(precond="chebyshev", precond_dtype=torch.float64)),
                          ("jacobi_f64", dict(precond="jacobi")),
@@ -615,9 +621,11 @@ def channel_measurements(dg, inp, torch, w, tag, cg=True, conv=True):
                 out = op.cg(b, x, rtol=1e-10, max_iter=5000, check_every=8, seed=42, **kw)
                 torch.cuda.synchronize()
                 tt = time.perf_counter() - t0
+                first = out.setup_s if best is None else best["first_setup_s"]
                 if best is None or tt < best["time_s"]:
                     best = {"time_s": tt, "iterations": out.iterations, "setup_s": out.setup_s,
                             "solve_s": out.solve_s, "rel_residual": out.rel_residual, "lambda_max": out.lambda_max}
+                best["first_setup_s"] = first
             ex[f"{tag}_cg_{name}"] = best
     if not conv:
         m.close()

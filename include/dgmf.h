@@ -256,7 +256,9 @@ dgmf_status dgmf_integrate(dgmf_op op, const double* f_qp, double* b, hipStream_
  * [lambda/smoothing_range, lambda] started from zero (cheb_degree-1 operator
  * products in precond_dtype), lambda = lambda_safety * the largest Ritz value
  * of lanczos_steps Lanczos steps on D^{-1/2} H D^{-1/2} in precond_dtype from
- * a SplitMix64(seed) start vector (mean removed when project_mean).  With
+ * a SplitMix64(seed) start vector (mean removed when project_mean); the Ritz
+ * value is kept with the operator and reused by later solves with the same
+ * precond_dtype, lanczos_steps, seed and project_mean.  With
  * precond_dtype DGMF_F32 the preconditioner runs in fp32 while residual, dot
  * products and updates stay fp64 (mixed precision).  project_mean = 1
  * projects b and every operator product onto zero-mean vectors (singular

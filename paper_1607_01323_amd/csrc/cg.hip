@@ -22,6 +22,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -1001,8 +1002,21 @@ struct Solver {
   dgmf_status lanczos_and_coeffs() {
     LzBufs<T> B{at<T>(L.cdsq), at<T>(L.cres), at<T>(L.cd), at<T>(L.czc), at<T>(L.ct), at<double>(L.v64)};
     double theta = 0;
-    dgmf_status e = lanczos_max<T>(op, N, B, st, partials, prm.lanczos_steps, prm.seed, s, theta);
-    if (e) return e;
+    const int dt = std::is_same<T, float>::value ? DGMF_F32 : DGMF_F64;
+    const int proj = prm.project_mean ? 1 : 0;
+    auto& c = op->lz;
+    if (c.valid && c.dtype == dt && c.steps == prm.lanczos_steps && c.seed == prm.seed && c.project == proj) {
+      theta = c.theta;
+    } else {
+      dgmf_status e = lanczos_max<T>(op, N, B, st, partials, prm.lanczos_steps, prm.seed, s, theta);
+      if (e) return e;
+      c.valid = 1;
+      c.dtype = dt;
+      c.steps = prm.lanczos_steps;
+      c.seed = prm.seed;
+      c.project = proj;
+      c.theta = theta;
+    }
     lambda = prm.lambda_safety * theta;
     cheb_coeffs(lambda / prm.smoothing_range, lambda, prm.cheb_degree, cheb_inv_theta, c1, c2);
     return DGMF_OK;

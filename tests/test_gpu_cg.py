@@ -122,6 +122,31 @@ def test_chebyshev_preconditioned_cg(pdtype):
     gm.close()
 
 
+def test_chebyshev_interval_is_kept_per_operator():
+    """A second Chebyshev solve with the same precision, Lanczos steps, seed and
+    projection reuses the first one's eigenvalue estimate (same lambda, bitwise
+    the same iterates); another seed runs Lanczos anew, and its lambda matches
+    the oracle's Lanczos from that seed."""
+    require_gpu()
+    w = inp.scaled(inp.HELMHOLTZ_C1, (4, 3, 4))
+    om, oop, gm, gop = _setup(w)
+    A = oop.assemble()
+    d = A.diagonal()
+    b = dev(inp.uniform(31, om.ndofs))
+    runs = []
+    for seed in (5, 5, 6):
+        x = torch.zeros(om.ndofs, dtype=torch.float64, device="cuda")
+        out = gop.cg(b, x, rtol=1e-10, max_iter=500, precond="chebyshev", precond_dtype=torch.float32, seed=seed)
+        runs.append((out, host(x)))
+    assert runs[1][0].lambda_max == runs[0][0].lambda_max
+    assert runs[1][0].iterations == runs[0][0].iterations and np.array_equal(runs[1][1], runs[0][1])
+    assert runs[2][0].lambda_max != runs[0][0].lambda_max
+    v0 = rng.uniform_pm1(6, om.ndofs)
+    ritz, _ = solvers.lanczos_ritz(lambda v: (A @ (v / np.sqrt(d))) / np.sqrt(d), v0, 15)
+    assert abs(runs[2][0].lambda_max - 1.2 * ritz[-1]) < 1e-3 * 1.2 * ritz[-1]
+    gm.close()
+
+
 def test_flexible_beta_matches_oracle_fp64():
     require_gpu()
     w = inp.scaled(inp.HELMHOLTZ_C1, (3, 4, 3))
