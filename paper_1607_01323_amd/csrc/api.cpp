@@ -982,6 +982,21 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
     op->mg32.nu = static_cast<float>(desc->diff_coeff);
     op->mg32.pen = static_cast<float>(desc->penalty_scale);
   }
+  {
+    // the diagonal, computed once (Sec. 5.1: precomputed before time stepping) for the
+    // Jacobi and Chebyshev preconditioners and the multigrid smoothers
+    DeviceGuard dg(mesh->device);
+    dgmf_status sd = op->diag64.alloc(static_cast<size_t>(mesh->ndofs) * sizeof(double));
+    if (sd == DGMF_OK) sd = sipg_diag64(op, static_cast<double*>(op->diag64.p), nullptr);
+    if (sd == DGMF_OK) {
+      const hipError_t he = hipStreamSynchronize(nullptr);
+      if (he != hipSuccess) sd = fail(DGMF_HIP_ERROR, "sipg_create: diagonal: %s", hipGetErrorString(he));
+    }
+    if (sd != DGMF_OK) {
+      delete op;
+      return sd;
+    }
+  }
   mesh->nops++;
   *out = op;
   return DGMF_OK;

@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(256) k_lz_next(const T* __restrict__ w, T* __r
 }
 
 struct Layout {
-  size_t state, partials, bp, r, z, p, q, dinv, diag, v64;       // fp64 part
+  size_t state, partials, bp, r, z, p, q, dinv, v64;             // fp64 part
   size_t cdinv, cdsq, cres, cd, czc, ct;                       // precond dtype part
   size_t total;
 };
@@ -426,7 +426,6 @@ Layout make_layout(int64_t N, int64_t nparts, bool cheb, size_t es) {
   L.partials = take(sizeof(double) * 4 * nparts);
   const size_t v8 = sizeof(double) * N;
   L.bp = take(v8); L.r = take(v8); L.z = take(v8); L.p = take(v8); L.q = take(v8); L.dinv = take(v8);
-  L.diag = take(v8);
   if (cheb) {
     L.v64 = take(v8);
     const size_t vc = es * N;
@@ -814,8 +813,8 @@ dgmf_status mg_build(dgmf_op op, const dgmf_cg_params& prm, hipStream_t s, MgHie
   DGMF_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
   for (int l = 0; l < L; ++l) {
     MgLevel& a = h->lv[l];
-    if ((e = sipg_diag64(a.op, d64, s))) return e;
-    if ((e = launch_mg_diag<T>(d64, a.v<T>(5), a.v<T>(6), a.N, s))) return e;
+    const double* dg = static_cast<const double*>(a.op->diag64.p);   // computed at the level's create
+    if ((e = launch_mg_diag<T>(dg, a.v<T>(5), a.v<T>(6), a.N, s))) return e;
     if (l + 1 < L) {
       LzBufs<T> B{a.v<T>(6), a.v<T>(0), a.v<T>(1), a.v<T>(2), a.v<T>(3), v64};
       double theta = 0;
@@ -826,7 +825,7 @@ dgmf_status mg_build(dgmf_op op, const dgmf_cg_params& prm, hipStream_t s, MgHie
       a.m = prm.cheb_degree;
     } else {
       std::vector<double> dh(a.N);
-      DGMF_HIP_TRY(hipMemcpyAsync(dh.data(), d64, sizeof(double) * a.N, hipMemcpyDeviceToHost, s));
+      DGMF_HIP_TRY(hipMemcpyAsync(dh.data(), dg, sizeof(double) * a.N, hipMemcpyDeviceToHost, s));
       DGMF_HIP_TRY(hipStreamSynchronize(s));
       double tmin = 0, tmax = 0;
       if ((e = coarse_interval(a, dh, prm.project_mean != 0, prm.seed + l, v64, d64, s, tmin, tmax))) return e;
@@ -1101,7 +1100,7 @@ dgmf_status cg_run(dgmf_op op, const double* b, double* x, const dgmf_cg_params*
   double* p = S.at<double>(L.p);
   double* q = S.at<double>(L.q);
   double* dinv = S.at<double>(L.dinv);
-  double* diag = S.at<double>(L.diag);
+  const double* diag = static_cast<const double*>(op->diag64.p);   // computed at create
   const dim3 G(kVecBlocks), B(256);
   const int napply = static_cast<int>(sipg_apply_blocks(op));
   auto t0 = std::chrono::steady_clock::now();
@@ -1112,7 +1111,6 @@ dgmf_status cg_run(dgmf_op op, const double* b, double* x, const dgmf_cg_params*
   init.flexible = params->flexible ? 1 : 0;
   init.max_iter = params->max_iter;
   DGMF_HIP_TRY(hipMemcpyAsync(S.st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
-  if ((e = sipg_diag64(op, diag, stream))) return e;
   hipLaunchKernelGGL(k_recip, G, B, 0, stream, diag, dinv, N);
   DGMF_LAUNCH_CHECK("k_recip");
   if (cheb) {

@@ -413,6 +413,7 @@ struct dgmf_op_ {
   dgmf::MetricGeom<double> mg64{};   // metric path (mesh->desc.store_qp_metric)
   dgmf::MetricGeom<float> mg32{};
   bool metric = false;
+  dgmf::DevBuf diag64;             // SIPG operators: diag(H) in fp64, computed at create
   dgmf::MgHierarchy* mgh = nullptr;   // multigrid levels, built on first use
   // largest Ritz value of the Chebyshev preconditioner's Lanczos run, kept for
   // later solves with the same precision, step count, seed and projection

@@ -284,7 +284,7 @@ template <> struct ZmTile<2> { static constexpr int TX = 8, TY = 8; };
 template <> struct ZmTile<3> { static constexpr int TX = 4, TY = 7; };
 template <> struct ZmTile<4> { static constexpr int TX = 4, TY = 4; };
 template <> struct ZmTile<5> { static constexpr int TX = 4, TY = 2; };
-template <> struct ZmTile<6> { static constexpr int TX = 3, TY = 2; };
+template <> struct ZmTile<6> { static constexpr int TX = 4, TY = 2; };
 template <> struct ZmTile<7> { static constexpr int TX = 2, TY = 2; };
 template <> struct ZmTile<8> { static constexpr int TX = 2, TY = 2; };
 

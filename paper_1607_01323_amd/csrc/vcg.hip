@@ -41,7 +41,7 @@ struct VState {
 };
 
 struct VLayout {
-  size_t state, part, r, z, p, q, diag, dinv, total;
+  size_t state, part, r, z, p, q, dinv, total;
 };
 
 VLayout vlayout(int64_t N) {
@@ -61,8 +61,6 @@ VLayout vlayout(int64_t N) {
   o += v3;
   L.q = o;
   o += v3;
-  L.diag = o;
-  o += v1;
   L.dinv = o;
   o += v1;
   L.total = o;
@@ -289,7 +287,6 @@ dgmf_status dgmf_viscous_cg_solve(dgmf_op op, const double* b, double* x, const 
     double* z = reinterpret_cast<double*>(ws + L.z);
     double* p = reinterpret_cast<double*>(ws + L.p);
     double* q = reinterpret_cast<double*>(ws + L.q);
-    double* diag = reinterpret_cast<double*>(ws + L.diag);
     double* dinv = reinterpret_cast<double*>(ws + L.dinv);
     const dim3 G(kBlocks), B(kThreads);
     dgmf_status e;
@@ -298,8 +295,7 @@ dgmf_status dgmf_viscous_cg_solve(dgmf_op op, const double* b, double* x, const 
     init.tol2 = params->rtol * params->rtol;
     init.max_iter = params->max_iter;
     DGMF_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
-    if ((e = sipg_diag64(op, diag, stream))) return e;
-    hipLaunchKernelGGL(k_v_recip, G, B, 0, stream, diag, dinv, N);
+    hipLaunchKernelGGL(k_v_recip, G, B, 0, stream, static_cast<const double*>(op->diag64.p), dinv, N);
     DGMF_LAUNCH_CHECK("k_v_recip");
     if ((e = apply_eps(op, x, q, stream))) return e;
     hipLaunchKernelGGL(k_v_init, G, B, 0, stream, b, q, r, z, dinv, N, part);
