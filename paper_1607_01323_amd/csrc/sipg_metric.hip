@@ -273,84 +273,109 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
     // through the transpose of that extrapolation into the point fluxes, so
     // the transposed cell sweeps below lift them.  The neighbour's traces
     // come from its nodal face plane and normal-derivative plane.
+    // The two faces of a direction share the normal lines: both own traces
+    // come from one pass over the line and both face terms go back in one
+    // read-modify-write of it.
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      const int d = f >> 1, s = f & 1;
+    for (int d = 0; d < 3; ++d) {
       const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-      const int nb = nbc[f];
-      const T* Es = s ? E1 : E0;
-      const T* gn = s ? g0 : g1;      // normal derivative row at the neighbour's face
-      const int en = s ? 0 : N - 1;
-      if (nb >= 0) {
-        if constexpr (!kHoistNb) {
-          const T* un = src + static_cast<int64_t>(nb) * N3;
+      // neighbour traces of both faces at this face point: value, d/dt1, d/dt2, d/dn
+      T nbt[2][4];
 #pragma unroll
-          for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * d + s;
+        const int nb = nbc[f];
+        const T* gn = s ? g0 : g1;      // normal derivative row at the neighbour's face
+        const int en = s ? 0 : N - 1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nbt[s][k] = T(0);
+        if (nb >= 0) {
+          if constexpr (!kHoistNb) {
+            const T* un = src + static_cast<int64_t>(nb) * N3;
+#pragma unroll
+            for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
+          }
+          sF[0 * N2 + t] = nbv[f][en];
+          T dnn = T(0);
+#pragma unroll
+          for (int m = 0; m < N; ++m) dnn = fma(gn[m], nbv[f][m], dnn);
+          sF[1 * N2 + t] = dnn;
+          wave_sync();
+          // along t1 (p1): S P, D P, S PN; along t2 (p2): val, dt1, dt2, dn
+          plane_ops<N, 0, false, T>(3, codes(0, 0, 1), codes(2, 3, 4), 0b010u, 0u, S, D, sF, t);
+          wave_sync();
+          plane_ops<N, 1, false, T>(4, codes(2, 3, 2, 4), codes(5, 6, 7, 8), 0b0100u, 0u, S, D, sF, t);
+          wave_sync();
+#pragma unroll
+          for (int k = 0; k < 4; ++k) nbt[s][k] = sF[(5 + k) * N2 + t];
+          wave_sync();   // the next face's planes overwrite sF
         }
-        sF[0 * N2 + t] = nbv[f][en];
-        T dnn = T(0);
-#pragma unroll
-        for (int m = 0; m < N; ++m) dnn = fma(gn[m], nbv[f][m], dnn);
-        sF[1 * N2 + t] = dnn;
-        wave_sync();
-        // along t1 (p1): S P, D P, S PN; along t2 (p2): val, dt1, dt2, dn
-        plane_ops<N, 0, false, T>(3, codes(0, 0, 1), codes(2, 3, 4), 0b010u, 0u, S, D, sF, t);
-        wave_sync();
-        plane_ops<N, 1, false, T>(4, codes(2, 3, 2, 4), codes(5, 6, 7, 8), 0b0100u, 0u, S, D, sF, t);
-        wave_sync();
       }
-      if constexpr (!kHoist) {
-#pragma unroll
-        for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
-      }
-      const bool own_is_L = ownL[f];
-      const T tau = ftau[f] * g.pen;
-      const T wdA = fmv[f][0];
-      T vo[3], vn[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        vo[k] = own_is_L ? fmv[f][1 + k] : fmv[f][4 + k];
-        vn[k] = own_is_L ? fmv[f][4 + k] : fmv[f][1 + k];
-      }
-      // own traces
-      T uo_f = T(0), go[3] = {T(0), T(0), T(0)};
+      // own traces at both ends of the normal line
+      T uf[2] = {T(0), T(0)}, gf[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
 #pragma unroll
       for (int m = 0; m < N; ++m) {
         const int q = fnode<N>(d, m, p1, p2);
-        uo_f = fma(Es[m], sA[q], uo_f);
-        go[0] = fma(Es[m], sB[q], go[0]);
-        go[1] = fma(Es[m], sB[N3 + q], go[1]);
-        go[2] = fma(Es[m], sB[2 * N3 + q], go[2]);
+        const T a = sA[q], b0 = sB[q], b1 = sB[N3 + q], b2 = sB[2 * N3 + q];
+        uf[0] = fma(E0[m], a, uf[0]);
+        uf[1] = fma(E1[m], a, uf[1]);
+        gf[0][0] = fma(E0[m], b0, gf[0][0]);
+        gf[1][0] = fma(E1[m], b0, gf[1][0]);
+        gf[0][1] = fma(E0[m], b1, gf[0][1]);
+        gf[1][1] = fma(E1[m], b1, gf[1][1]);
+        gf[0][2] = fma(E0[m], b2, gf[0][2]);
+        gf[1][2] = fma(E1[m], b2, gf[1][2]);
       }
-      const T ano = go[0] * vo[0] + go[1] * vo[1] + go[2] * vo[2];
-      T fv, fgc;
-      if (nb >= 0) {
-        T gnb[3];
-        gnb[d] = sF[8 * N2 + t];
-        gnb[t1] = sF[6 * N2 + t];
-        gnb[t2] = sF[7 * N2 + t];
-        const T un = sF[5 * N2 + t];
-        const T ann = gnb[0] * vn[0] + gnb[1] * vn[1] + gnb[2] * vn[2];
-        const T jump = own_is_L ? uo_f - un : un - uo_f;
-        const T avg = T(0.5) * (ano + ann);
-        fv = own_is_L ? (-avg + tau * jump * wdA) : (avg - tau * jump * wdA);
-        fgc = T(-0.5) * jump;
-      } else {
-        // Dirichlet face; a homogeneous Neumann face adds nothing
-        const T bw = ((g.neu >> f) & 1) ? T(0) : T(1);
-        fv = bw * (-ano + T(2) * tau * uo_f * wdA);
-        fgc = -bw * uo_f;
+      T fvs[2], fgs[2][3];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * d + s;
+        const int nb = nbc[f];
+        if constexpr (!kHoist) {
+#pragma unroll
+          for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
+        }
+        const bool own_is_L = ownL[f];
+        const T tau = ftau[f] * g.pen;
+        const T wdA = fmv[f][0];
+        T vo[3], vn[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          vo[k] = own_is_L ? fmv[f][1 + k] : fmv[f][4 + k];
+          vn[k] = own_is_L ? fmv[f][4 + k] : fmv[f][1 + k];
+        }
+        const T uo_f = uf[s];
+        const T ano = gf[s][0] * vo[0] + gf[s][1] * vo[1] + gf[s][2] * vo[2];
+        T fv, fgc;
+        if (nb >= 0) {
+          T gnb[3];
+          gnb[d] = nbt[s][3];
+          gnb[t1] = nbt[s][1];
+          gnb[t2] = nbt[s][2];
+          const T un = nbt[s][0];
+          const T ann = gnb[0] * vn[0] + gnb[1] * vn[1] + gnb[2] * vn[2];
+          const T jump = own_is_L ? uo_f - un : un - uo_f;
+          const T avg = T(0.5) * (ano + ann);
+          fv = own_is_L ? (-avg + tau * jump * wdA) : (avg - tau * jump * wdA);
+          fgc = T(-0.5) * jump;
+        } else {
+          // Dirichlet face; a homogeneous Neumann face adds nothing
+          const T bw = ((g.neu >> f) & 1) ? T(0) : T(1);
+          fv = bw * (-ano + T(2) * tau * uo_f * wdA);
+          fgc = -bw * uo_f;
+        }
+        fvs[s] = fv * g.nu;
+        fgc *= g.nu;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fgs[s][k] = fgc * vo[k];
       }
-      fv *= g.nu;
-      fgc *= g.nu;
-      const T f0 = fgc * vo[0], f1 = fgc * vo[1], f2 = fgc * vo[2];
 #pragma unroll
       for (int m = 0; m < N; ++m) {
         const int q = fnode<N>(d, m, p1, p2);
-        sC[q] = fma(Es[m], fv, sC[q]);
-        sG[q] = fma(Es[m], f0, sG[q]);
-        sG[N3 + q] = fma(Es[m], f1, sG[N3 + q]);
-        sG[2 * N3 + q] = fma(Es[m], f2, sG[2 * N3 + q]);
+        sC[q] = fma(E1[m], fvs[1], fma(E0[m], fvs[0], sC[q]));
+        sG[q] = fma(E1[m], fgs[1][0], fma(E0[m], fgs[0][0], sG[q]));
+        sG[N3 + q] = fma(E1[m], fgs[1][1], fma(E0[m], fgs[0][1], sG[N3 + q]));
+        sG[2 * N3 + q] = fma(E1[m], fgs[1][2], fma(E0[m], fgs[0][2], sG[2 * N3 + q]));
       }
       wave_sync();
     }
