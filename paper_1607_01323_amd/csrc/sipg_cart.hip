@@ -278,26 +278,38 @@ __device__ __forceinline__ void bline(cptr<T> tab, const T (&u)[N], const T (&ul
 // from L2.  Tiles are handed to XCDs in compact bands (workgroup b runs on XCD
 // b % 8), so the rim cells a workgroup reads were loaded by a tile on the same
 // XCD at about the same z.
-template <int N>
-struct ZmTile;
-template <> struct ZmTile<2> { static constexpr int TX = 8, TY = 8; };
-template <> struct ZmTile<3> { static constexpr int TX = 4, TY = 7; };
-template <> struct ZmTile<4> { static constexpr int TX = 4, TY = 4; };
-template <> struct ZmTile<5> { static constexpr int TX = 4, TY = 2; };
-template <> struct ZmTile<6> { static constexpr int TX = 4, TY = 2; };
-template <> struct ZmTile<7> { static constexpr int TX = 2, TY = 2; };
-template <> struct ZmTile<8> { static constexpr int TX = 2, TY = 2; };
+//
+// Tile per degree and element size (bytes).  Where n^2 divides 64 or one cell
+// nearly fills a wavefront, a cell's n^2 threads stay inside one wavefront
+// and the transposes of its own lines need only wavefront ordering.  Where
+// that would idle many lanes (n = 5: 50 of 64, n = 6: 36, n = 7: 49), PACK
+// numbers the threads of the tile's cells consecutively across wavefronts,
+// so a cell may straddle two of them and those transposes take workgroup
+// barriers.  BLOCKS: the workgroup count the z-segments of a large mesh aim
+// at (whole rounds of resident workgroups).
+template <int N, int ES>
+struct ZmTile {
+  static constexpr int TX = 2, TY = 2, BLOCKS = 1024;
+  static constexpr bool PACK = false;
+};
+template <int ES> struct ZmTile<2, ES> { static constexpr int TX = 8, TY = 8, BLOCKS = 1024; static constexpr bool PACK = false; };
+template <int ES> struct ZmTile<3, ES> { static constexpr int TX = 4, TY = 7, BLOCKS = 1024; static constexpr bool PACK = false; };
+template <int ES> struct ZmTile<4, ES> { static constexpr int TX = 4, TY = 4, BLOCKS = 1024; static constexpr bool PACK = false; };
+template <int ES> struct ZmTile<5, ES> { static constexpr int TX = 5, TY = 2, BLOCKS = 768; static constexpr bool PACK = true; };
+template <> struct ZmTile<6, 8> { static constexpr int TX = 7, TY = 2, BLOCKS = 512; static constexpr bool PACK = true; };
+template <> struct ZmTile<6, 4> { static constexpr int TX = 3, TY = 2, BLOCKS = 768; static constexpr bool PACK = true; };
+template <> struct ZmTile<7, 8> { static constexpr int TX = 5, TY = 1, BLOCKS = 1024; static constexpr bool PACK = true; };
 
-template <int N>
+template <int N, typename T>
 struct Zm {
+  using Tile = ZmTile<N, int(sizeof(T))>;
   static constexpr int N2 = N * N, N3 = N2 * N;
   static constexpr int P = (N % 2) ? N : N + 1;
   static constexpr int CL = N2 * P;
-  static constexpr int TX = ZmTile<N>::TX, TY = ZmTile<N>::TY, NC = TX * TY;
-  // a cell's n^2 threads never straddle two wavefronts, so transposes of a
-  // cell's own lines through LDS need no workgroup barrier
-  static constexpr int CPW = 64 / N2;                       // cells per wavefront
-  static constexpr int THREADS = ((NC + CPW - 1) / CPW) * 64;
+  static constexpr int TX = Tile::TX, TY = Tile::TY, NC = TX * TY;
+  static constexpr bool PACK = Tile::PACK;
+  static constexpr int CPW = 64 / N2;                       // whole cells per wavefront
+  static constexpr int THREADS = PACK ? ((NC * N2 + 63) / 64) * 64 : ((NC + CPW - 1) / CPW) * 64;
 };
 
 
@@ -306,6 +318,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Orders the LDS accesses of every thread of a cell: the wavefront when a
+// cell never leaves it, else the workgroup.
+template <bool PACK>
+__device__ __forceinline__ void cell_sync() {
+  if constexpr (PACK) __syncthreads();
+  else wave_sync();
 }
 
 // The z-line (i, j) = off of a cell: n values, stride n^2 (coalesced across the
@@ -352,9 +372,9 @@ __device__ __forceinline__ void uline(cptr<T> ut, int d, const T (&u)[N], const 
 // Work state of one workgroup of the z-marching apply.
 template <int N, typename T>
 struct ZmCtx {
-  static constexpr int N2 = N * N, N3 = N2 * N, P = Zm<N>::P, CL = Zm<N>::CL;
-  static constexpr int NR = 2 * (Zm<N>::TX + Zm<N>::TY);                    // rim cells per layer
-  static constexpr int RPT = (NR * N3 + Zm<N>::THREADS - 1) / Zm<N>::THREADS;  // rim values per thread
+  static constexpr int N2 = N * N, N3 = N2 * N, P = Zm<N, T>::P, CL = Zm<N, T>::CL;
+  static constexpr int NR = 2 * (Zm<N, T>::TX + Zm<N, T>::TY);                    // rim cells per layer
+  static constexpr int RPT = (NR * N3 + Zm<N, T>::THREADS - 1) / Zm<N, T>::THREADS;  // rim values per thread
   bool act, zper;
   int col, nxy, zoff, slot, t0, t1;
   T hx, hy, hinvx, hinvy, tpx, tpy;
@@ -374,7 +394,7 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
                                          T (&unn)[N], bool want_partials, double& pq, double& sq, double& sp,
                                          const ChebEpi<T>& epi) {
   using C = ZmCtx<N, T>;
-  constexpr int N2 = C::N2, N3 = C::N3, P = C::P, NR = C::NR, RPT = C::RPT, TH = Zm<N>::THREADS;
+  constexpr int N2 = C::N2, N3 = C::N3, P = C::P, NR = C::NR, RPT = C::RPT, TH = Zm<N, T>::THREADS;
   const int tid = threadIdx.x;
   const int t0 = c.t0, t1 = c.t1;
   T* su = s_u + c.slot;
@@ -459,7 +479,7 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
 #pragma unroll
     for (int j = 0; j < N; ++j) sw[(l * N + j) * P + i] = w[j];
   }
-  wave_sync();
+  cell_sync<Zm<N, T>::PACK>();
   // pass 3: x-lines (j, l) = (t0, t1): w += B_x u, then w = Mx w
   if (c.act) {
     const int lo = (t1 * N + t0) * P;
@@ -500,7 +520,7 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
 #pragma unroll
     for (int j = 0; j < N; ++j) sw[(l * N + j) * P + i] = o[j];
   }
-  wave_sync();
+  cell_sync<Zm<N, T>::PACK>();
   // pass 5: z-lines: dst = Mz w (coalesced store); the rim of the next layer goes to LDS
   if (c.act) {
     T w[N], o[N];
@@ -550,12 +570,12 @@ __device__ __forceinline__ void zm_layer(const T* __restrict__ src, T* __restric
 }
 
 template <int N, typename T, bool PER, bool UNI, bool EPI>
-__global__ void __launch_bounds__(Zm<N>::THREADS) k_sipg_zm_apply(const T* __restrict__ src, T* __restrict__ dst,
+__global__ void __launch_bounds__((Zm<N, T>::THREADS)) k_sipg_zm_apply(const T* __restrict__ src, T* __restrict__ dst,
                                                                  const CartGeom<T> g, const ZmPlan pl,
                                                                  double* __restrict__ partials, const int* stop,
                                                                  const ChebEpi<T> epi) {
   if (stop && *stop) return;   // uniform for the whole grid: CG already finished
-  using Z = Zm<N>;
+  using Z = Zm<N, T>;
   using C = ZmCtx<N, T>;
   constexpr int N3 = Z::N3, P = Z::P, CL = Z::CL, TX = Z::TX, TY = Z::TY, NC = Z::NC, NR = C::NR;
   // s_u holds the tile cells followed by the rim cells: neighbour lines are
@@ -584,9 +604,16 @@ __global__ void __launch_bounds__(Zm<N>::THREADS) k_sipg_zm_apply(const T* __res
     const int z0 = seg * pl.seglen;
     const int z1 = z0 + pl.seglen < g.nz ? z0 + pl.seglen : g.nz;
     C c;
-    const int lane = tid & 63, cw = lane / Z::N2;
-    const int lc = cw < Z::CPW ? (tid >> 6) * Z::CPW + cw : NC;
-    const int t = lane - cw * Z::N2;
+    int lc, t;   // tile cell (NC: none) and thread within the cell
+    if constexpr (Z::PACK) {
+      lc = tid / Z::N2;
+      t = tid - lc * Z::N2;
+      lc = lc < NC ? lc : NC;
+    } else {
+      const int lane = tid & 63, cw = lane / Z::N2;
+      lc = cw < Z::CPW ? (tid >> 6) * Z::CPW + cw : NC;
+      t = lane - cw * Z::N2;
+    }
     c.t0 = t % N;
     c.t1 = t / N;
     const int a = lc % TX, b = lc / TX;
@@ -730,7 +757,7 @@ __global__ void __launch_bounds__(Zm<N>::THREADS) k_sipg_zm_apply(const T* __res
     __syncthreads();
     if (tid == 0) {
       double x = 0, y = 0, zz = 0;
-      for (int k = 0; k < Zm<N>::THREADS / 64; ++k) {
+      for (int k = 0; k < Zm<N, T>::THREADS / 64; ++k) {
         x += s_red[3 * k];
         y += s_red[3 * k + 1];
         zz += s_red[3 * k + 2];
@@ -790,10 +817,8 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
 
 template <int N, typename T>
 ZmPlan zm_plan_n(int nx, int ny, int nz) {
-  constexpr int TX = Zm<N>::TX, TY = Zm<N>::TY;
-  // one round of resident workgroups: four per compute unit, three for the
-  // fp64 kernel at k = 4 (three waves per SIMD)
-  constexpr int kTargetBlocks = (N == 5 && sizeof(T) == 8) ? 768 : 1024;
+  constexpr int TX = Zm<N, T>::TX, TY = Zm<N, T>::TY;
+  constexpr int kTargetBlocks = Zm<N, T>::Tile::BLOCKS;
   constexpr int kMinLayers = 4;         // shortest z segment of a large mesh
   ZmPlan p{};
   p.tx = (nx + TX - 1) / TX;
@@ -829,17 +854,19 @@ template <int N, typename T, bool EPI>
 dgmf_status launch_apply_n(const CartGeom<T>& g, const T* src, T* dst, int64_t ncells, double* partials,
                            const int* stop, const ChebEpi<T>& epi, hipStream_t s) {
   (void)ncells;
-  // with partial sums, the decomposition whose row count sipg_cart_blocks reports
-  const ZmPlan pl = partials ? zm_plan_n<N, double>(g.nx, g.ny, g.nz) : zm_plan_n<N, T>(g.nx, g.ny, g.nz);
+  // partial sums come with the fp64 apply only: one row per workgroup of the
+  // fp64 plan, the count sipg_cart_blocks reports
+  if (partials && sizeof(T) != 8) return fail(DGMF_UNSUPPORTED, "k_sipg_zm_apply: partial sums need fp64");
+  const ZmPlan pl = zm_plan_n<N, T>(g.nx, g.ny, g.nz);
   const int blocks = 8 * pl.per_xcd;
   if (g.utab)
-    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, true, EPI>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src, dst,
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, true, EPI>), dim3(blocks), dim3(Zm<N, T>::THREADS), 0, s, src, dst,
                        g, pl, partials, stop, epi);
   else if (g.allper)
-    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, false, EPI>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src,
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, false, EPI>), dim3(blocks), dim3(Zm<N, T>::THREADS), 0, s, src,
                        dst, g, pl, partials, stop, epi);
   else
-    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, false, false, EPI>), dim3(blocks), dim3(Zm<N>::THREADS), 0, s, src,
+    hipLaunchKernelGGL((k_sipg_zm_apply<N, T, false, false, EPI>), dim3(blocks), dim3(Zm<N, T>::THREADS), 0, s, src,
                        dst, g, pl, partials, stop, epi);
   DGMF_LAUNCH_CHECK("k_sipg_zm_apply");
   return DGMF_OK;
