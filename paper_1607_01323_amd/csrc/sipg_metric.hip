@@ -64,8 +64,9 @@ struct MetShape {
   static constexpr int THREADS = 64 * WAVES;
   // LDS words per cell: u at the points, its three reference gradients, the
   // three gradient fluxes, the value flux (8 n^3), and the neighbour face
-  // planes (9 n^2)
-  static constexpr int CELL = 8 * N3 + 9 * N2;
+  // planes of one direction (10 n^2: P and PN of both faces, then their
+  // interpolations and derivatives along p1)
+  static constexpr int CELL = 8 * N3 + 10 * N2;
 };
 
 // 3D array [z][y][x] of extent N^3: lane t (0..n^2-1) owns line t along `axis`:
@@ -86,44 +87,6 @@ __device__ __forceinline__ void sweep3(const T* __restrict__ A, const T* in, T* 
     for (int m = 0; m < N; ++m) s = fma(TR ? A[m * N + q] : A[q * N + m], v[m], s);
     out[base + q * st] = s;
   }
-}
-
-// Several independent sweeps over 2D planes [p2][p1] of extent N^2 (planes of
-// the face buffer F, n^2 words each), one job per (op, line).  Op k reads
-// plane in(k), writes plane out(k) (5-bit fields of icode / ocode), uses D
-// when bit k of dmask is set (else S), accumulates when bit k of amask is set.
-template <int N, int AXIS, bool TR, typename T>
-__device__ __forceinline__ void plane_ops(int nops, unsigned long long icode, unsigned long long ocode, unsigned dmask,
-                                          unsigned amask, const T* __restrict__ S, const T* __restrict__ D, T* F,
-                                          int t) {
-  constexpr int N2 = N * N;
-  constexpr int st = AXIS == 0 ? 1 : N;
-  for (int job = t; job < nops * N; job += N2) {
-    const int k = job / N, line = job - k * N;
-    const int pin = static_cast<int>((icode >> (5 * k)) & 31), pout = static_cast<int>((ocode >> (5 * k)) & 31);
-    const T* A = ((dmask >> k) & 1) ? D : S;
-    const bool acc = (amask >> k) & 1;
-    const int base = AXIS == 0 ? line * N : line;
-    const T* in = F + pin * N2;
-    T* out = F + pout * N2;
-    T v[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) v[m] = in[base + m * st];
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s = acc ? out[base + q * st] : T(0);
-#pragma unroll
-      for (int m = 0; m < N; ++m) s = fma(TR ? A[m * N + q] : A[q * N + m], v[m], s);
-      out[base + q * st] = s;
-    }
-  }
-}
-
-constexpr unsigned long long codes(int a0, int a1 = 0, int a2 = 0, int a3 = 0, int a4 = 0, int a5 = 0, int a6 = 0,
-                                   int a7 = 0) {
-  return (unsigned long long)a0 | ((unsigned long long)a1 << 5) | ((unsigned long long)a2 << 10) |
-         ((unsigned long long)a3 << 15) | ((unsigned long long)a4 << 20) | ((unsigned long long)a5 << 25) |
-         ((unsigned long long)a6 << 30) | ((unsigned long long)a7 << 35);
 }
 
 // node index of face-plane entry (p1 along t1, p2 along t2) of the plane at
@@ -163,7 +126,7 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
   T* sB = sA + N3;           // 3 n^3: reference gradients at the points
   T* sG = sA + 4 * N3;       // 3 n^3: gradient fluxes (nodal u on entry)
   T* sC = sA + 7 * N3;       // value flux
-  T* sF = sA + 8 * N3;       // neighbour face planes: 0 P, 1 PN, 2..4 stages, 5 val, 6 dt1, 7 dt2, 8 dn
+  T* sF = sA + 8 * N3;       // neighbour face planes: P, PN of faces 0 and 1, then 3 stage planes per face
   const T* S = g.tab + MTab{N}.S();
   const T* D = g.tab + MTab{N}.D();
   const T* Dg = g.tab + MTab{N}.Dg();
@@ -279,36 +242,66 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-      // neighbour traces of both faces at this face point: value, d/dt1, d/dt2, d/dn
+      // neighbour traces of both faces at this face point (p1, p2): value,
+      // d/dt1, d/dt2, d/dn from the neighbour's nodal face plane P and its
+      // normal-derivative plane PN, interpolated (S) or differentiated (D)
+      // along p1, then along p2; each lane forms its own point of every
+      // plane, so both faces of the direction share two wavefront syncs.
       T nbt[2][4];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int f = 2 * d + s;
-        const int nb = nbc[f];
-        const T* gn = s ? g0 : g1;      // normal derivative row at the neighbour's face
-        const int en = s ? 0 : N - 1;
 #pragma unroll
         for (int k = 0; k < 4; ++k) nbt[s][k] = T(0);
-        if (nb >= 0) {
+        if (nbc[f] >= 0) {
           if constexpr (!kHoistNb) {
-            const T* un = src + static_cast<int64_t>(nb) * N3;
+            const T* un = src + static_cast<int64_t>(nbc[f]) * N3;
 #pragma unroll
             for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
           }
-          sF[0 * N2 + t] = nbv[f][en];
+          const T* gn = s ? g0 : g1;      // normal derivative row at the neighbour's face
           T dnn = T(0);
 #pragma unroll
           for (int m = 0; m < N; ++m) dnn = fma(gn[m], nbv[f][m], dnn);
-          sF[1 * N2 + t] = dnn;
-          wave_sync();
-          // along t1 (p1): S P, D P, S PN; along t2 (p2): val, dt1, dt2, dn
-          plane_ops<N, 0, false, T>(3, codes(0, 0, 1), codes(2, 3, 4), 0b010u, 0u, S, D, sF, t);
-          wave_sync();
-          plane_ops<N, 1, false, T>(4, codes(2, 3, 2, 4), codes(5, 6, 7, 8), 0b0100u, 0u, S, D, sF, t);
-          wave_sync();
+          sF[(2 * s) * N2 + t] = nbv[f][s ? 0 : N - 1];
+          sF[(2 * s + 1) * N2 + t] = dnn;
+        }
+      }
+      wave_sync();
 #pragma unroll
-          for (int k = 0; k < 4; ++k) nbt[s][k] = sF[(5 + k) * N2 + t];
-          wave_sync();   // the next face's planes overwrite sF
+      for (int s = 0; s < 2; ++s) {
+        if (nbc[2 * d + s] >= 0) {
+          const T* P = sF + (2 * s) * N2 + p2 * N;
+          const T* PN = sF + (2 * s + 1) * N2 + p2 * N;
+          T sp = T(0), dp = T(0), spn = T(0);
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const T a = P[m], b = PN[m];
+            sp = fma(S[p1 * N + m], a, sp);
+            dp = fma(D[p1 * N + m], a, dp);
+            spn = fma(S[p1 * N + m], b, spn);
+          }
+          sF[(4 + 3 * s) * N2 + t] = sp;
+          sF[(5 + 3 * s) * N2 + t] = dp;
+          sF[(6 + 3 * s) * N2 + t] = spn;
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        if (nbc[2 * d + s] >= 0) {
+          const T* SP = sF + (4 + 3 * s) * N2 + p1;
+          const T* DP = sF + (5 + 3 * s) * N2 + p1;
+          const T* SPN = sF + (6 + 3 * s) * N2 + p1;
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const T a = SP[m * N], b = DP[m * N], c2 = SPN[m * N];
+            const T sm = S[p2 * N + m];
+            nbt[s][0] = fma(sm, a, nbt[s][0]);
+            nbt[s][1] = fma(sm, b, nbt[s][1]);
+            nbt[s][2] = fma(D[p2 * N + m], a, nbt[s][2]);
+            nbt[s][3] = fma(sm, c2, nbt[s][3]);
+          }
         }
       }
       // own traces at both ends of the normal line
