@@ -1100,7 +1100,7 @@ dgmf_status sipg_diag64(dgmf_op op, double* diag, hipStream_t s) {
 }
 
 int64_t sipg_apply_blocks(dgmf_op op) {
-  if (op->metric) return metric_apply_blocks(op->mesh->desc.degree + 1, op->mesh->ncells);
+  if (op->metric) return metric_apply_blocks(op->mesh->desc.degree + 1, op->mg64.nx, op->mg64.ny, op->mg64.nz);
   return sipg_cart_blocks(op->mesh->desc.degree + 1, op->g64);
 }
 

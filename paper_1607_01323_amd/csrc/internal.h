@@ -208,8 +208,8 @@ dgmf_status launch_sipg_cart_diag(int n, const CartGeom<T>& g, T* diag, int64_t 
 int sipg_cart_blocks(int n, const CartGeom<double>& g);
 
 // Apply with the metric stored at the quadrature points; partials/stop as
-// above, metric_apply_blocks(n, ncells) partial rows.
-int metric_apply_blocks(int n, int64_t ncells);
+// above, metric_apply_blocks(n, nx, ny, nz) partial rows.
+int metric_apply_blocks(int n, int nx, int ny, int nz);
 template <typename T>
 dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials,
                                      const int* stop, hipStream_t s);

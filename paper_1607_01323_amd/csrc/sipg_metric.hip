@@ -62,10 +62,14 @@ struct MetShape {
   static constexpr int WAVES = 4;
   static constexpr int CPB = CPW * WAVES;          // cells per workgroup
   static constexpr int THREADS = 64 * WAVES;
+  // When the workgroup holds a whole number of 2x2x2 blocks of cells, it
+  // takes such blocks, and the two cells on either side of a face inside a
+  // block hand each other their traces of that face through LDS.
+  static constexpr bool SUB = CPB % 8 == 0;
   // LDS words per cell: u at the points, its three reference gradients, the
-  // three gradient fluxes, the value flux (8 n^3), and the neighbour face
-  // planes of one direction (10 n^2: P and PN of both faces, then their
-  // interpolations and derivatives along p1)
+  // three gradient fluxes, the value flux (8 n^3), and five face planes per
+  // face of the current direction (P, PN, and P and PN interpolated or
+  // differentiated along p1; or the four trace planes handed to the partner)
   static constexpr int CELL = 8 * N3 + 10 * N2;
 };
 
@@ -113,20 +117,39 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
   if (stop && *stop) return;
   using M = MetShape<N>;
   constexpr int N2 = M::N2, N3 = M::N3;
+  constexpr bool SUB = M::SUB;
   __shared__ T s_cells[M::CPB * M::CELL];
   __shared__ double s_red[3 * M::WAVES];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int cw = lane / N2;
   const int t = lane - cw * N2;
-  const int ncells = g.nx * g.ny * g.nz;
-  const int cell = blockIdx.x * M::CPB + w * M::CPW + cw;
-  const bool act = cw < M::CPW && cell < ncells;
-  T* sA = s_cells + (w * M::CPW + (cw < M::CPW ? cw : 0)) * M::CELL;   // u at the Gauss points
+  const int lc = w * M::CPW + (cw < M::CPW ? cw : 0);   // the cell's slot in the workgroup
+  const int nd[3] = {g.nx, g.ny, g.nz};
+  int c[3], cell;
+  bool act;
+  if constexpr (SUB) {
+    // workgroup b takes the 2x2x2 blocks b * CPB / 8 ... (x fastest)
+    const int bx = (g.nx + 1) >> 1, by = (g.ny + 1) >> 1, bz = (g.nz + 1) >> 1;
+    const int blk = blockIdx.x * (M::CPB / 8) + (lc >> 3), j = lc & 7;
+    const int sx = blk % bx, sy = (blk / bx) % by, sz = blk / (bx * by);
+    c[0] = 2 * sx + (j & 1);
+    c[1] = 2 * sy + ((j >> 1) & 1);
+    c[2] = 2 * sz + (j >> 2);
+    act = cw < M::CPW && sz < bz && c[0] < g.nx && c[1] < g.ny && c[2] < g.nz;
+    cell = act ? (c[2] * g.ny + c[1]) * g.nx + c[0] : 0;
+  } else {
+    cell = blockIdx.x * M::CPB + lc;
+    act = cw < M::CPW && cell < g.nx * g.ny * g.nz;
+    c[0] = cell % g.nx;
+    c[1] = (cell / g.nx) % g.ny;
+    c[2] = cell / (g.nx * g.ny);
+  }
+  T* sA = s_cells + lc * M::CELL;   // u at the Gauss points
   T* sB = sA + N3;           // 3 n^3: reference gradients at the points
   T* sG = sA + 4 * N3;       // 3 n^3: gradient fluxes (nodal u on entry)
   T* sC = sA + 7 * N3;       // value flux
-  T* sF = sA + 8 * N3;       // neighbour face planes: P, PN of faces 0 and 1, then 3 stage planes per face
+  T* sF = sA + 8 * N3;       // face planes of the current direction, five per face
   const T* S = g.tab + MTab{N}.S();
   const T* D = g.tab + MTab{N}.D();
   const T* Dg = g.tab + MTab{N}.Dg();
@@ -135,21 +158,23 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
   const T* E0 = g.tab + MTab{N}.e0();
   const T* E1 = g.tab + MTab{N}.e1();
   double pq = 0.0, sq = 0.0, sp = 0.0;
+  const int p1 = t % N, p2 = t / N;
+  // ---- every global load of this cell is issued up front, so that their
+  // latencies overlap the cell integral (in fp64 the cell and face metric
+  // are loaded where they are used: hoisting them too would cost the
+  // registers of a second wavefront per SIMD)
+  constexpr bool kHoist = sizeof(T) == 4;
+  // neighbour face lines: up front unless that alone exhausts the fp64
+  // register file (n >= 7), where they are read per face
+  constexpr bool kHoistNb = sizeof(T) == 4 || N <= 6;
+  T uo[N], cmv[7][N];
+  int nbc[6];
+  bool ownL[6];
+  const T* fmp[6];
+  T ftau[6], nbv[6][N], fmv[6][7];
   if (act) {
-    const int c[3] = {cell % g.nx, (cell / g.nx) % g.ny, cell / (g.nx * g.ny)};
-    const int nd[3] = {g.nx, g.ny, g.nz};
     const int stride[3] = {1, g.nx, g.nx * g.ny};
-    const int p1 = t % N, p2 = t / N;
-    // ---- every global load of this cell is issued up front, so that their
-    // latencies overlap the cell integral (in fp64 the cell and face metric
-    // are loaded where they are used: hoisting them too would cost the
-    // registers of a second wavefront per SIMD)
-    constexpr bool kHoist = sizeof(T) == 4;
-    // neighbour face lines: up front unless that alone exhausts the fp64
-    // register file (n >= 7), where they are read per face
-    constexpr bool kHoistNb = sizeof(T) == 4 || N <= 6;
     const T* cm = g.cm + static_cast<int64_t>(cell) * 7 * N3;
-    T uo[N], cmv[7][N];
 #pragma unroll
     for (int m = 0; m < N; ++m) uo[m] = src[cell * N3 + t + m * N2];
     if constexpr (kHoist) {
@@ -158,10 +183,6 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
 #pragma unroll
         for (int m = 0; m < N; ++m) cmv[k][m] = cm[k * N3 + t + m * N2];
     }
-    int nbc[6];
-    bool ownL[6];
-    const T* fmp[6];
-    T ftau[6], nbv[6][N], fmv[6][7];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1, s = f & 1;
@@ -190,7 +211,10 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
 #pragma unroll
         for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
       }
-      if (kHoistNb && nbc[f] >= 0) {
+      // neighbour face lines (not across the face shared with the block
+      // partner: those traces come through LDS)
+      const bool partner = SUB && (c[d] ^ 1) < nd[d] && s == 1 - (c[d] & 1);
+      if (kHoistNb && nbc[f] >= 0 && !partner) {
         const T* un = src + static_cast<int64_t>(nbc[f]) * N3;
 #pragma unroll
         for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
@@ -230,82 +254,25 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
       sC[q] = g.mu * cmv[6][m] * sA[q];
     }
     wave_sync();
-    // ---- faces.  Lane t is face point (p1, p2).  Own traces are the values
-    // of the Gauss-point data extrapolated along the normal line (exact: every
-    // field is a polynomial of degree < n along it); the face terms go back
-    // through the transpose of that extrapolation into the point fluxes, so
-    // the transposed cell sweeps below lift them.  The neighbour's traces
-    // come from its nodal face plane and normal-derivative plane.
-    // The two faces of a direction share the normal lines: both own traces
-    // come from one pass over the line and both face terms go back in one
-    // read-modify-write of it.
+  }
+  // ---- faces.  Lane t is face point (p1, p2).  Own traces are the values
+  // of the Gauss-point data extrapolated along the normal line (exact: every
+  // field is a polynomial of degree < n along it); the face terms go back
+  // through the transpose of that extrapolation into the point fluxes, so
+  // the transposed cell sweeps below lift them.  The two faces of a direction
+  // share the normal lines: both own traces come from one pass over the line
+  // and both face terms go back in one read-modify-write of it.  A
+  // neighbour's traces (value, d/dt1, d/dt2, d/dn at the face point) are
+  // the own traces of the partner cell across a face inside a 2x2x2 block;
+  // otherwise they come from the neighbour's nodal face plane P and its
+  // normal-derivative plane PN, interpolated (S) or differentiated (D) along
+  // p1, then along p2, each lane forming its own point of every plane.  The
+  // workgroup barriers of the block exchange are reached by every thread.
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-      // neighbour traces of both faces at this face point (p1, p2): value,
-      // d/dt1, d/dt2, d/dn from the neighbour's nodal face plane P and its
-      // normal-derivative plane PN, interpolated (S) or differentiated (D)
-      // along p1, then along p2; each lane forms its own point of every
-      // plane, so both faces of the direction share two wavefront syncs.
-      T nbt[2][4];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int f = 2 * d + s;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) nbt[s][k] = T(0);
-        if (nbc[f] >= 0) {
-          if constexpr (!kHoistNb) {
-            const T* un = src + static_cast<int64_t>(nbc[f]) * N3;
-#pragma unroll
-            for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
-          }
-          const T* gn = s ? g0 : g1;      // normal derivative row at the neighbour's face
-          T dnn = T(0);
-#pragma unroll
-          for (int m = 0; m < N; ++m) dnn = fma(gn[m], nbv[f][m], dnn);
-          sF[(2 * s) * N2 + t] = nbv[f][s ? 0 : N - 1];
-          sF[(2 * s + 1) * N2 + t] = dnn;
-        }
-      }
-      wave_sync();
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        if (nbc[2 * d + s] >= 0) {
-          const T* P = sF + (2 * s) * N2 + p2 * N;
-          const T* PN = sF + (2 * s + 1) * N2 + p2 * N;
-          T sp = T(0), dp = T(0), spn = T(0);
-#pragma unroll
-          for (int m = 0; m < N; ++m) {
-            const T a = P[m], b = PN[m];
-            sp = fma(S[p1 * N + m], a, sp);
-            dp = fma(D[p1 * N + m], a, dp);
-            spn = fma(S[p1 * N + m], b, spn);
-          }
-          sF[(4 + 3 * s) * N2 + t] = sp;
-          sF[(5 + 3 * s) * N2 + t] = dp;
-          sF[(6 + 3 * s) * N2 + t] = spn;
-        }
-      }
-      wave_sync();
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        if (nbc[2 * d + s] >= 0) {
-          const T* SP = sF + (4 + 3 * s) * N2 + p1;
-          const T* DP = sF + (5 + 3 * s) * N2 + p1;
-          const T* SPN = sF + (6 + 3 * s) * N2 + p1;
-#pragma unroll
-          for (int m = 0; m < N; ++m) {
-            const T a = SP[m * N], b = DP[m * N], c2 = SPN[m * N];
-            const T sm = S[p2 * N + m];
-            nbt[s][0] = fma(sm, a, nbt[s][0]);
-            nbt[s][1] = fma(sm, b, nbt[s][1]);
-            nbt[s][2] = fma(D[p2 * N + m], a, nbt[s][2]);
-            nbt[s][3] = fma(sm, c2, nbt[s][3]);
-          }
-        }
-      }
-      // own traces at both ends of the normal line
-      T uf[2] = {T(0), T(0)}, gf[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    T uf[2] = {T(0), T(0)}, gf[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+    if (act) {
 #pragma unroll
       for (int m = 0; m < N; ++m) {
         const int q = fnode<N>(d, m, p1, p2);
@@ -318,6 +285,93 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
         gf[1][1] = fma(E1[m], b1, gf[1][1]);
         gf[0][2] = fma(E0[m], b2, gf[0][2]);
         gf[1][2] = fma(E1[m], b2, gf[1][2]);
+      }
+    }
+    // the face shared with the block partner (-1: none)
+    int fx = -1;
+    if constexpr (SUB) {
+      if (act && (c[d] ^ 1) < nd[d]) fx = 1 - (c[d] & 1);
+    }
+    T nbt[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) nbt[s][k] = T(0);
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * d + s;
+        T* F = sF + 5 * s * N2;
+        if (s == fx) {
+          F[t] = uf[s];
+          F[N2 + t] = gf[s][0];
+          F[2 * N2 + t] = gf[s][1];
+          F[3 * N2 + t] = gf[s][2];
+        } else if (nbc[f] >= 0) {
+          if constexpr (!kHoistNb) {
+            const T* un = src + static_cast<int64_t>(nbc[f]) * N3;
+#pragma unroll
+            for (int m = 0; m < N; ++m) nbv[f][m] = un[fnode<N>(d, m, p1, p2)];
+          }
+          const T* gn = s ? g0 : g1;      // normal derivative row at the neighbour's face
+          T dnn = T(0);
+#pragma unroll
+          for (int m = 0; m < N; ++m) dnn = fma(gn[m], nbv[f][m], dnn);
+          F[t] = nbv[f][s ? 0 : N - 1];
+          F[N2 + t] = dnn;
+        }
+      }
+    }
+    // (the partner is in this wavefront when 2^d < cells per wavefront)
+    if (SUB && (1 << d) >= M::CPW) __syncthreads();
+    else wave_sync();
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        T* F = sF + 5 * s * N2;
+        if (s == fx) {
+          const T* X = s_cells + (lc ^ (1 << d)) * M::CELL + 8 * N3 + 5 * (1 - s) * N2;
+          const T gx[3] = {X[N2 + t], X[2 * N2 + t], X[3 * N2 + t]};
+          nbt[s][0] = X[t];
+          nbt[s][1] = gx[t1];
+          nbt[s][2] = gx[t2];
+          nbt[s][3] = gx[d];
+        } else if (nbc[2 * d + s] >= 0) {
+          const T* P = F + p2 * N;
+          const T* PN = F + N2 + p2 * N;
+          T sp = T(0), dp = T(0), spn = T(0);
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const T a = P[m], b = PN[m];
+            sp = fma(S[p1 * N + m], a, sp);
+            dp = fma(D[p1 * N + m], a, dp);
+            spn = fma(S[p1 * N + m], b, spn);
+          }
+          F[2 * N2 + t] = sp;
+          F[3 * N2 + t] = dp;
+          F[4 * N2 + t] = spn;
+        }
+      }
+    }
+    wave_sync();
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        if (s != fx && nbc[2 * d + s] >= 0) {
+          const T* F = sF + 5 * s * N2;
+          const T* SP = F + 2 * N2 + p1;
+          const T* DP = F + 3 * N2 + p1;
+          const T* SPN = F + 4 * N2 + p1;
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const T a = SP[m * N], b = DP[m * N], c2 = SPN[m * N];
+            const T sm = S[p2 * N + m];
+            nbt[s][0] = fma(sm, a, nbt[s][0]);
+            nbt[s][1] = fma(sm, b, nbt[s][1]);
+            nbt[s][2] = fma(D[p2 * N + m], a, nbt[s][2]);
+            nbt[s][3] = fma(sm, c2, nbt[s][3]);
+          }
+        }
       }
       T fvs[2], fgs[2][3];
 #pragma unroll
@@ -370,8 +424,12 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
         sG[N3 + q] = fma(E1[m], fgs[1][1], fma(E0[m], fgs[0][1], sG[N3 + q]));
         sG[2 * N3 + q] = fma(E1[m], fgs[1][2], fma(E0[m], fgs[0][2], sG[2 * N3 + q]));
       }
-      wave_sync();
     }
+    // the partner's reads of this cell's planes end before the next direction writes them
+    if (SUB && (1 << d) >= M::CPW) __syncthreads();
+    else wave_sync();
+  }
+  if (act) {
     // ---- transposed sweeps: sC += sum_d Dg_d^T sG_d, then S^T in every direction
     sweep3<N, 0, true, true>(Dg, sG, sC, t);
     wave_sync();
@@ -848,16 +906,19 @@ __global__ void __launch_bounds__(256) k_to_f32(const double* __restrict__ a, fl
 
 #define DGMF_MET_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
-int metric_apply_blocks(int n, int64_t ncells) {
+int metric_apply_blocks(int n, int nx, int ny, int nz) {
   const int cpb = 4 * (64 / (n * n));
-  return static_cast<int>((ncells + cpb - 1) / cpb);
+  if (cpb % 8 == 0) {   // cpb / 8 blocks of 2x2x2 cells per workgroup
+    const int64_t blocks = static_cast<int64_t>((nx + 1) / 2) * ((ny + 1) / 2) * ((nz + 1) / 2);
+    return static_cast<int>((blocks + cpb / 8 - 1) / (cpb / 8));
+  }
+  return static_cast<int>((static_cast<int64_t>(nx) * ny * nz + cpb - 1) / cpb);
 }
 
 template <typename T>
 dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials,
                                      const int* stop, hipStream_t s) {
-  const int64_t ncells = static_cast<int64_t>(g.nx) * g.ny * g.nz;
-  const unsigned blocks = static_cast<unsigned>(metric_apply_blocks(n, ncells));
+  const unsigned blocks = static_cast<unsigned>(metric_apply_blocks(n, g.nx, g.ny, g.nz));
 #define X(a)                                                                                                 \
   if (n == a) {                                                                                              \
     hipLaunchKernelGGL((k_sipg_metric_apply<a, T>), dim3(blocks), dim3(MetShape<a>::THREADS), 0, s, src, dst, \
