@@ -323,6 +323,23 @@ __global__ void __launch_bounds__(256) k_cheb_step(T* __restrict__ res, T* __res
   if (z64) block_partials<3>(v, partials, blockIdx.x);
 }
 
+// z64 = x (the last Chebyshev iterate, fused path), with the partials of the
+// preconditioned update
+template <typename T>
+__global__ void __launch_bounds__(256) k_cheb_fin(const T* __restrict__ x, const double* __restrict__ r,
+                                                  double* __restrict__ z64, const double* __restrict__ q, int64_t N,
+                                                  const CgState* st, double* partials) {
+  if (st->status != RUNNING) return;
+  const double mq = st->mean_q;
+  double v[3] = {0, 0, 0};
+  GRID_STRIDE(i, N) {
+    const double zd = static_cast<double>(x[i]);
+    z64[i] = zd;
+    final_terms(v, r[i], zd, q, i, mq);
+  }
+  block_partials<3>(v, partials, blockIdx.x);
+}
+
 // ------------------------------------------------------------ Lanczos -----
 // SplitMix64 (Steele, Lea & Flood 2014): output i = mix(seed + (i+1) gamma),
 // mapped to [-1, 1) by its top 53 bits.
@@ -1034,6 +1051,25 @@ struct Solver {
     hipLaunchKernelGGL((k_cheb_init<T>), G, B, 0, s, r, res, d, zc, dinv, static_cast<T>(cheb_inv_theta),
                        m == 1 ? z : nullptr, q, N, st, partials);
     DGMF_LAUNCH_CHECK("k_cheb_init");
+    if (m > 1 && !op->metric) {
+      // axis-aligned cells: the same polynomial in the three-term form
+      // x_{j+1} = x_j + c1 (x_j - x_{j-1}) + c2 D^{-1} (r - H x_j), x_0 = 0,
+      // x_1 = d, each step fused into the apply's store (5 vectors instead of
+      // 10); the buffers of x_j and x_{j-1} swap after every step
+      T* cur = d;
+      T* prev = zc;
+      for (int j = 1; j < m; ++j) {
+        const ChebEpi<T> epi{res, dinv, static_cast<T>(c1[j]), static_cast<T>(c2[j]), j == 1 ? 1 : 0};
+        dgmf_status e = sipg_cheb<T>(op, cur, prev, epi, &st->status, s);
+        if (e) return e;
+        T* tmp = cur;
+        cur = prev;
+        prev = tmp;
+      }
+      hipLaunchKernelGGL((k_cheb_fin<T>), G, B, 0, s, cur, r, z, q, N, st, partials);
+      DGMF_LAUNCH_CHECK("k_cheb_fin");
+      return DGMF_OK;
+    }
     for (int j = 1; j < m; ++j) {
       dgmf_status e = apply<T>(d, t, false);
       if (e) return e;
