@@ -996,6 +996,9 @@ dgmf_status dgmf_sipg_create(dgmf_mesh mesh, const dgmf_sipg_desc* desc, dgmf_op
       delete op;
       return sd;
     }
+    // launch plans of the axis-aligned apply depend on its occupancy: query it
+    // here, outside any stream capture (the multigrid V-cycle is captured)
+    if (!op->metric) sipg_cart_prime(n);
   }
   mesh->nops++;
   *out = op;

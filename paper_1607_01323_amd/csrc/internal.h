@@ -206,6 +206,9 @@ template <typename T>
 dgmf_status launch_sipg_cart_diag(int n, const CartGeom<T>& g, T* diag, int64_t ncells, hipStream_t s);
 // Grid size of the apply kernel (also the number of partial-sum rows it writes).
 int sipg_cart_blocks(int n, const CartGeom<double>& g);
+// Queries (once per device) the occupancy of every axis-aligned apply variant
+// of degree n - 1, which the launch plans use.
+void sipg_cart_prime(int n);
 
 // Apply with the metric stored at the quadrature points; partials/stop as
 // above, metric_apply_blocks(n, nx, ny, nz) partial rows.

@@ -19,6 +19,8 @@
 // in five line passes (z, y, x + Mx, My, Mz) of a z-marching tile kernel
 // (k_sipg_zm_apply, below); the diagonal kernel applies each A_d to unit
 // vectors.
+#include <atomic>
+
 #include "internal.h"
 
 namespace dgmf {
@@ -285,20 +287,19 @@ __device__ __forceinline__ void bline(cptr<T> tab, const T (&u)[N], const T (&ul
 // that would idle many lanes (n = 5: 50 of 64, n = 6: 36, n = 7: 49), PACK
 // numbers the threads of the tile's cells consecutively across wavefronts,
 // so a cell may straddle two of them and those transposes take workgroup
-// barriers.  BLOCKS: the workgroup count the z-segments of a large mesh aim
-// at (whole rounds of resident workgroups).
+// barriers.
 template <int N, int ES>
 struct ZmTile {
-  static constexpr int TX = 2, TY = 2, BLOCKS = 1024;
+  static constexpr int TX = 2, TY = 2;
   static constexpr bool PACK = false;
 };
-template <int ES> struct ZmTile<2, ES> { static constexpr int TX = 8, TY = 8, BLOCKS = 1024; static constexpr bool PACK = false; };
-template <int ES> struct ZmTile<3, ES> { static constexpr int TX = 4, TY = 7, BLOCKS = 1024; static constexpr bool PACK = false; };
-template <int ES> struct ZmTile<4, ES> { static constexpr int TX = 4, TY = 4, BLOCKS = 1024; static constexpr bool PACK = false; };
-template <int ES> struct ZmTile<5, ES> { static constexpr int TX = 5, TY = 2, BLOCKS = 768; static constexpr bool PACK = true; };
-template <> struct ZmTile<6, 8> { static constexpr int TX = 7, TY = 2, BLOCKS = 512; static constexpr bool PACK = true; };
-template <> struct ZmTile<6, 4> { static constexpr int TX = 3, TY = 2, BLOCKS = 768; static constexpr bool PACK = true; };
-template <> struct ZmTile<7, 8> { static constexpr int TX = 5, TY = 1, BLOCKS = 1024; static constexpr bool PACK = true; };
+template <int ES> struct ZmTile<2, ES> { static constexpr int TX = 8, TY = 8; static constexpr bool PACK = false; };
+template <int ES> struct ZmTile<3, ES> { static constexpr int TX = 4, TY = 7; static constexpr bool PACK = false; };
+template <int ES> struct ZmTile<4, ES> { static constexpr int TX = 4, TY = 4; static constexpr bool PACK = false; };
+template <int ES> struct ZmTile<5, ES> { static constexpr int TX = 5, TY = 2; static constexpr bool PACK = true; };
+template <> struct ZmTile<6, 8> { static constexpr int TX = 7, TY = 2; static constexpr bool PACK = true; };
+template <> struct ZmTile<6, 4> { static constexpr int TX = 3, TY = 2; static constexpr bool PACK = true; };
+template <> struct ZmTile<7, 8> { static constexpr int TX = 5, TY = 1; static constexpr bool PACK = true; };
 
 template <int N, typename T>
 struct Zm {
@@ -815,38 +816,81 @@ __global__ void __launch_bounds__(256) k_sipg_cart_diag(T* __restrict__ diag, co
   diag[gid] = dd[0] * md[1] * md[2] + md[0] * dd[1] * md[2] + md[0] * md[1] * dd[2];
 }
 
+// Workgroups of `kernel` (`threads` each) resident on the current device at
+// once, by the runtime's occupancy calculator (registers, LDS, wavefronts).
+int resident_blocks(const void* kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
+  return per * cus;
+}
+
+// resident_blocks of one apply kernel, kept per device after the first query
+template <int N, typename T, bool PER, bool UNI, bool EPI>
+int zm_resident() {
+  static std::atomic<int> cache[16];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const void* k = reinterpret_cast<const void*>(&k_sipg_zm_apply<N, T, PER, UNI, EPI>);
+  if (dev < 0 || dev >= 16) return resident_blocks(k, Zm<N, T>::THREADS);
+  int r = cache[dev].load(std::memory_order_relaxed);
+  if (r == 0) {
+    r = resident_blocks(k, Zm<N, T>::THREADS);
+    cache[dev].store(r, std::memory_order_relaxed);
+  }
+  return r;
+}
+
+// z-segments of the march: a workgroup per (tile, segment), `resident` of them
+// running at once.  The segment count minimises rounds x (layers per segment
+// + 2), the 2 standing for the set-up of a segment (its first two z-lines);
+// a mesh whose every layer fits one round (coarse multigrid levels) may go
+// down to one layer per workgroup, a larger one to kMinLayers.
 template <int N, typename T>
-ZmPlan zm_plan_n(int nx, int ny, int nz) {
+ZmPlan zm_plan_n(int nx, int ny, int nz, int resident) {
   constexpr int TX = Zm<N, T>::TX, TY = Zm<N, T>::TY;
-  constexpr int kTargetBlocks = Zm<N, T>::Tile::BLOCKS;
-  constexpr int kMinLayers = 4;         // shortest z segment of a large mesh
+  constexpr int kMinLayers = 4;
   ZmPlan p{};
   p.tx = (nx + TX - 1) / TX;
   p.ty = (ny + TY - 1) / TY;
-  const int tiles = p.tx * p.ty;
-  int segs = (kTargetBlocks + tiles - 1) / tiles;
-  // a mesh whose every layer fits one round of workgroups (coarse multigrid
-  // levels) marches one layer per workgroup: latency, not the z-window set-up,
-  // bounds those launches
-  const int minl = tiles * nz <= kTargetBlocks ? 1 : kMinLayers;
+  const int64_t tiles = static_cast<int64_t>(p.tx) * p.ty;
+  const int minl = tiles * nz <= resident ? 1 : kMinLayers;
   const int maxseg = nz / minl > 1 ? nz / minl : 1;
-  segs = segs < 1 ? 1 : (segs > maxseg ? maxseg : segs);
-  p.seglen = (nz + segs - 1) / segs;
+  int64_t best = -1;
+  p.seglen = nz;
+  for (int segs = 1; segs <= maxseg; ++segs) {
+    const int len = (nz + segs - 1) / segs;
+    const int64_t sg = (nz + len - 1) / len;
+    const int64_t cost = ((tiles * sg + resident - 1) / resident) * (len + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      p.seglen = len;
+    }
+  }
   p.segs = (nz + p.seglen - 1) / p.seglen;
-  p.total = tiles * p.segs;
+  p.total = static_cast<int>(tiles * p.segs);
   p.per_xcd = (p.total + 7) / 8;
   return p;
 }
 
-ZmPlan zm_plan(int n, int nx, int ny, int nz) {
+// plan and grid of the apply variant that geometry g selects
+template <int N, typename T, bool EPI>
+ZmPlan zm_plan_for(const CartGeom<T>& g) {
+  const int r = g.utab ? zm_resident<N, T, true, true, EPI>()
+                       : (g.allper ? zm_resident<N, T, true, false, EPI>() : zm_resident<N, T, false, false, EPI>());
+  return zm_plan_n<N, T>(g.nx, g.ny, g.nz, r);
+}
+
+ZmPlan zm_plan(int n, const CartGeom<double>& g) {
   switch (n) {
-    case 2: return zm_plan_n<2, double>(nx, ny, nz);
-    case 3: return zm_plan_n<3, double>(nx, ny, nz);
-    case 4: return zm_plan_n<4, double>(nx, ny, nz);
-    case 5: return zm_plan_n<5, double>(nx, ny, nz);
-    case 6: return zm_plan_n<6, double>(nx, ny, nz);
-    case 7: return zm_plan_n<7, double>(nx, ny, nz);
-    default: return zm_plan_n<8, double>(nx, ny, nz);
+    case 2: return zm_plan_for<2, double, false>(g);
+    case 3: return zm_plan_for<3, double, false>(g);
+    case 4: return zm_plan_for<4, double, false>(g);
+    case 5: return zm_plan_for<5, double, false>(g);
+    case 6: return zm_plan_for<6, double, false>(g);
+    case 7: return zm_plan_for<7, double, false>(g);
+    default: return zm_plan_for<8, double, false>(g);
   }
 }
 
@@ -857,7 +901,7 @@ dgmf_status launch_apply_n(const CartGeom<T>& g, const T* src, T* dst, int64_t n
   // partial sums come with the fp64 apply only: one row per workgroup of the
   // fp64 plan, the count sipg_cart_blocks reports
   if (partials && sizeof(T) != 8) return fail(DGMF_UNSUPPORTED, "k_sipg_zm_apply: partial sums need fp64");
-  const ZmPlan pl = zm_plan_n<N, T>(g.nx, g.ny, g.nz);
+  const ZmPlan pl = zm_plan_for<N, T, EPI>(g);
   const int blocks = 8 * pl.per_xcd;
   if (g.utab)
     hipLaunchKernelGGL((k_sipg_zm_apply<N, T, true, true, EPI>), dim3(blocks), dim3(Zm<N, T>::THREADS), 0, s, src, dst,
@@ -884,7 +928,38 @@ dgmf_status launch_diag_n(const CartGeom<T>& g, T* diag, int64_t ncells, hipStre
 
 }  // namespace
 
-int sipg_cart_blocks(int n, const CartGeom<double>& g) { return 8 * zm_plan(n, g.nx, g.ny, g.nz).per_xcd; }
+int sipg_cart_blocks(int n, const CartGeom<double>& g) { return 8 * zm_plan(n, g).per_xcd; }
+
+namespace {
+template <int N>
+void prime_n() {
+  (void)zm_resident<N, double, true, true, false>();
+  (void)zm_resident<N, double, true, false, false>();
+  (void)zm_resident<N, double, false, false, false>();
+  (void)zm_resident<N, double, true, true, true>();
+  (void)zm_resident<N, double, true, false, true>();
+  (void)zm_resident<N, double, false, false, true>();
+  (void)zm_resident<N, float, true, true, false>();
+  (void)zm_resident<N, float, true, false, false>();
+  (void)zm_resident<N, float, false, false, false>();
+  (void)zm_resident<N, float, true, true, true>();
+  (void)zm_resident<N, float, true, false, true>();
+  (void)zm_resident<N, float, false, false, true>();
+}
+}  // namespace
+
+void sipg_cart_prime(int n) {
+  switch (n) {
+    case 2: prime_n<2>(); break;
+    case 3: prime_n<3>(); break;
+    case 4: prime_n<4>(); break;
+    case 5: prime_n<5>(); break;
+    case 6: prime_n<6>(); break;
+    case 7: prime_n<7>(); break;
+    case 8: prime_n<8>(); break;
+    default: break;
+  }
+}
 
 template <typename T>
 dgmf_status launch_sipg_cart_apply(int n, const CartGeom<T>& g, const T* src, T* dst, int64_t ncells,
