@@ -120,6 +120,7 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
   constexpr bool SUB = M::SUB;
   __shared__ T s_cells[M::CPB * M::CELL];
   __shared__ double s_red[3 * M::WAVES];
+  __shared__ T s_sd[2 * N2];   // S and D: the face-plane steps read a row per lane
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int cw = lane / N2;
@@ -152,6 +153,10 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
   T* sF = sA + 8 * N3;       // face planes of the current direction, five per face
   const T* S = g.tab + MTab{N}.S();
   const T* D = g.tab + MTab{N}.D();
+  for (int i = tid; i < 2 * N2; i += M::THREADS) s_sd[i] = i < N2 ? S[i] : D[i - N2];
+  __syncthreads();
+  const T* Sl = s_sd;
+  const T* Dl = s_sd + N2;
   const T* Dg = g.tab + MTab{N}.Dg();
   const T* g0 = g.tab + MTab{N}.g0();
   const T* g1 = g.tab + MTab{N}.g1();
@@ -343,9 +348,9 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
 #pragma unroll
           for (int m = 0; m < N; ++m) {
             const T a = P[m], b = PN[m];
-            sp = fma(S[p1 * N + m], a, sp);
-            dp = fma(D[p1 * N + m], a, dp);
-            spn = fma(S[p1 * N + m], b, spn);
+            sp = fma(Sl[p1 * N + m], a, sp);
+            dp = fma(Dl[p1 * N + m], a, dp);
+            spn = fma(Sl[p1 * N + m], b, spn);
           }
           F[2 * N2 + t] = sp;
           F[3 * N2 + t] = dp;
@@ -365,10 +370,10 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
 #pragma unroll
           for (int m = 0; m < N; ++m) {
             const T a = SP[m * N], b = DP[m * N], c2 = SPN[m * N];
-            const T sm = S[p2 * N + m];
+            const T sm = Sl[p2 * N + m];
             nbt[s][0] = fma(sm, a, nbt[s][0]);
             nbt[s][1] = fma(sm, b, nbt[s][1]);
-            nbt[s][2] = fma(D[p2 * N + m], a, nbt[s][2]);
+            nbt[s][2] = fma(Dl[p2 * N + m], a, nbt[s][2]);
             nbt[s][3] = fma(sm, c2, nbt[s][3]);
           }
         }
