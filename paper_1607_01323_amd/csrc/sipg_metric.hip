@@ -55,6 +55,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// load through a global-memory pointer (the face metric pointers are chosen
+// among several arrays, which hides their address space from the compiler)
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 template <int N>
 struct MetShape {
   static constexpr int N2 = N * N, N3 = N2 * N;
@@ -214,7 +221,7 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
       }
       if constexpr (kHoist) {
 #pragma unroll
-        for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
+        for (int k = 0; k < 7; ++k) fmv[f][k] = gld(fmp[f] + k * N2 + t);
       }
       // neighbour face lines (not across the face shared with the block
       // partner: those traces come through LDS)
@@ -385,7 +392,7 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
         const int nb = nbc[f];
         if constexpr (!kHoist) {
 #pragma unroll
-          for (int k = 0; k < 7; ++k) fmv[f][k] = fmp[f][k * N2 + t];
+          for (int k = 0; k < 7; ++k) fmv[f][k] = gld(fmp[f] + k * N2 + t);
         }
         const bool own_is_L = ownL[f];
         const T tau = ftau[f] * g.pen;
