@@ -10,6 +10,9 @@
     per-configuration means of SQ_* counters (per dispatch), with the fp64 /
     fp32 operation counts they imply and, from the durations of the trace run,
     the achieved FLOP rates against the chip's peaks.
+``python -m paper_1607_01323_amd.profiling window <kernel_trace.csv> <out.md> --kernel K --grid G --skip S --count C --cmd "..."``
+    durations of launches S .. S+C-1 of one kernel and grid size, in launch
+    order (the timed loop of a benchmark, apart from other uses of the kernel).
 ``python -m paper_1607_01323_amd.profiling pmc <fetch_csv> <write_csv> <out.json> --cmd-fetch ... --cmd-write ...``
     reduces FETCH_SIZE / WRITE_SIZE counter collections (KiB per dispatch) to
     a per-kernel average and the copy-kernel calibration factor, tagged with
@@ -98,6 +101,23 @@ def trace_table(csv_path, out_md, cmd):
         lines.append(f"| `{k[:80]}` | {g} | {wg} | {len(v)} | {sum(v) / len(v) / 1e3:.2f} | "
                      f"{v[len(v) // 2] / 1e3:.2f} | {v[0] / 1e3:.2f} | {v[-1] / 1e3:.2f} | "
                      f"{100.0 * sum(v) / total:.1f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def window_table(csv_path, out_md, kernel, grid, skip, count, cmd):
+    rows = [r for r in csv.DictReader(open(csv_path))
+            if short_name(_col(r, "Kernel_Name")) == kernel and _grid(r) == str(grid)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    sel = rows[skip:skip + count]
+    d = sorted((float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3 for r in sel)
+    if not d:
+        raise SystemExit("no launches of %s with grid %s" % (kernel, grid))
+    period = (float(sel[-1]["Start_Timestamp"]) - float(sel[0]["Start_Timestamp"])) / 1e3 / max(1, len(sel) - 1)
+    lines = ["# rocprofv3 kernel trace, one timed loop", "", f"Command: `{cmd}`", "",
+             f"Launches {skip} to {skip + len(sel) - 1} (in launch order) of `{kernel}` with grid {grid} "
+             f"({len(rows)} launches of that kernel and grid in the run).", "",
+             "| launches | mean (us) | median (us) | min (us) | max (us) | start-to-start (us) |", "|---|---|---|---|---|---|",
+             f"| {len(d)} | {sum(d) / len(d):.2f} | {d[len(d) // 2]:.2f} | {d[0]:.2f} | {d[-1]:.2f} | {period:.2f} |"]
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
@@ -193,6 +213,14 @@ if __name__ == "__main__":
     c.add_argument("csvs", nargs="+")
     c.add_argument("--trace", default=None)
     c.add_argument("--cmd", required=True)
+    wdw = sub.add_parser("window")
+    wdw.add_argument("csv")
+    wdw.add_argument("out")
+    wdw.add_argument("--kernel", required=True)
+    wdw.add_argument("--grid", required=True)
+    wdw.add_argument("--skip", type=int, default=0)
+    wdw.add_argument("--count", type=int, required=True)
+    wdw.add_argument("--cmd", required=True)
     b = sub.add_parser("pmc")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
@@ -205,6 +233,8 @@ if __name__ == "__main__":
         stats_table(args.csv, args.out, args.cmd)
     elif args.what == "trace":
         trace_table(args.csv, args.out, args.cmd)
+    elif args.what == "window":
+        window_table(args.csv, args.out, args.kernel, args.grid, args.skip, args.count, args.cmd)
     elif args.what == "counters":
         counters_table(args.out, args.csvs, args.trace, args.cmd)
     else:
