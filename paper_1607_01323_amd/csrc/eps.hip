@@ -90,9 +90,27 @@ __device__ __forceinline__ void store_line(double* out, int base, int stride, co
   for (int i = 0; i < N; ++i) out[base + i * stride] = r[i];
 }
 
+// Tables read with indices uniform over the wavefront: for n <= 5 through the
+// constant address space (scalar loads into SGPRs, which the FMAs take
+// directly); larger tables would overflow the scalar registers and stay in LDS.
+using cdptr = const __attribute__((address_space(4))) double*;
+template <bool C>
+struct TabPtr {
+  using type = const double*;
+};
+template <>
+struct TabPtr<true> {
+  using type = cdptr;
+};
+template <bool C>
+__device__ __forceinline__ typename TabPtr<C>::type tab_ptr(const double* global, const double* lds) {
+  if constexpr (C) return (cdptr)global;
+  else return lds;
+}
+
 // r (=, or += when ACC) s M v on one line; M row-major [out][in], transposed when TR
-template <int N, bool TR, bool ACC>
-__device__ __forceinline__ void lmul(const double* M, const double (&v)[N], double s, double (&r)[N]) {
+template <int N, bool TR, bool ACC, typename PT>
+__device__ __forceinline__ void lmul(PT M, const double (&v)[N], double s, double (&r)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     double a = 0;
@@ -123,8 +141,10 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
   const V3Tab L{N};
   const double* Mh = s_tab + L.Mh();
   const double* Ch = s_tab + L.Ch();
-  const double* Kh = s_tab + L.Kh();
   const double* Dn = s_tab + L.Dn();
+  const auto cMh = tab_ptr<(N <= 5)>(tab + L.Mh(), Mh);
+  const auto cCh = tab_ptr<(N <= 5)>(tab + L.Ch(), Ch);
+  const auto cKh = tab_ptr<(N <= 5)>(tab + L.Kh(), s_tab + L.Kh());
   const double* g0 = s_tab + L.g0();
   const double* g1 = s_tab + L.g1();
   double* S0 = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;
@@ -172,24 +192,24 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
     line_of<N>(0, t, b, st);
     double v[N], r[N];
     load_line<N>(S0, b, st, v);
-    lmul<N, false, false>(Kh, v, 1.0, r);
+    lmul<N, false, false>(cKh, v, 1.0, r);
     store_line<N>(S0, b, st, r);
     cfence();
-    lmul<N, false, false>(Ch, v, 1.0, r);
+    lmul<N, false, false>(cCh, v, 1.0, r);
     store_line<N>(S1, b, st, r);
     cfence();
     load_line<N>(S2, b, st, v);
-    lmul<N, false, false>(Mh, v, 1.0, r);
+    lmul<N, false, false>(cMh, v, 1.0, r);
     store_line<N>(S2, b, st, r);
     cfence();
-    lmul<N, true, false>(Ch, v, 1.0, r);
+    lmul<N, true, false>(cCh, v, 1.0, r);
     store_line<N>(S3, b, st, r);
     cfence();
     load_line<N>(S5, b, st, v);
-    lmul<N, false, false>(Mh, v, 1.0, r);
+    lmul<N, false, false>(cMh, v, 1.0, r);
     store_line<N>(S5, b, st, r);
     cfence();
-    lmul<N, true, false>(Ch, v, 1.0, r);
+    lmul<N, true, false>(cCh, v, 1.0, r);
     store_line<N>(S4, b, st, r);
     cfence();
   }
@@ -203,29 +223,29 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
     double v[N], w[N], r[N];
     load_line<N>(S0, b, st, v);
     load_line<N>(S3, b, st, w);
-    lmul<N, false, false>(Mh, v, sc[0][0], r);
-    lmul<N, false, true>(Ch, w, sc[0][1], r);
+    lmul<N, false, false>(cMh, v, sc[0][0], r);
+    lmul<N, false, true>(cCh, w, sc[0][1], r);
     store_line<N>(S0, b, st, r);
     cfence();
     load_line<N>(S4, b, st, v);
-    lmul<N, false, false>(Mh, v, sc[0][2], r);
+    lmul<N, false, false>(cMh, v, sc[0][2], r);
     store_line<N>(S4, b, st, r);
     cfence();
     load_line<N>(S1, b, st, v);
     load_line<N>(S2, b, st, w);
-    lmul<N, true, false>(Ch, v, sc[1][0], r);
-    lmul<N, false, true>(Kh, w, sc[1][1], r);
+    lmul<N, true, false>(cCh, v, sc[1][0], r);
+    lmul<N, false, true>(cKh, w, sc[1][1], r);
     store_line<N>(S1, b, st, r);
     cfence();
-    lmul<N, false, false>(Mh, v, sc[2][0], r);
-    lmul<N, false, true>(Ch, w, sc[2][1], r);
+    lmul<N, false, false>(cMh, v, sc[2][0], r);
+    lmul<N, false, true>(cCh, w, sc[2][1], r);
     store_line<N>(S2, b, st, r);
     cfence();
     load_line<N>(S5, b, st, v);
-    lmul<N, true, false>(Ch, v, sc[1][2], r);
+    lmul<N, true, false>(cCh, v, sc[1][2], r);
     store_line<N>(S5, b, st, r);
     cfence();
-    lmul<N, false, false>(Mh, v, sc[2][2], r);
+    lmul<N, false, false>(cMh, v, sc[2][2], r);
     store_line<N>(S3, b, st, r);
     cfence();
   }
@@ -237,20 +257,20 @@ __global__ void __launch_bounds__(64 * WAVES, EPack<N>::MINW) k_eps_coupling(con
     double v[N], w[N], r[N];
     load_line<N>(S0, b, st, v);
     load_line<N>(S4, b, st, w);
-    lmul<N, false, false>(Mh, v, 1.0, r);
-    lmul<N, false, true>(Ch, w, 1.0, r);
+    lmul<N, false, false>(cMh, v, 1.0, r);
+    lmul<N, false, true>(cCh, w, 1.0, r);
     store_line<N>(S0, b, st, r);
     cfence();
     load_line<N>(S1, b, st, v);
     load_line<N>(S5, b, st, w);
-    lmul<N, false, false>(Mh, v, 1.0, r);
-    lmul<N, false, true>(Ch, w, 1.0, r);
+    lmul<N, false, false>(cMh, v, 1.0, r);
+    lmul<N, false, true>(cCh, w, 1.0, r);
     store_line<N>(S1, b, st, r);
     cfence();
     load_line<N>(S2, b, st, v);
     load_line<N>(S3, b, st, w);
-    lmul<N, true, false>(Ch, v, 1.0, r);
-    lmul<N, false, true>(Kh, w, 1.0, r);
+    lmul<N, true, false>(cCh, v, 1.0, r);
+    lmul<N, false, true>(cKh, w, 1.0, r);
     store_line<N>(S2, b, st, r);
     cfence();
   }
