@@ -78,10 +78,29 @@ struct V3Shape {
   static constexpr int TABN = 5 * N2 + 2 * N;   // the V3Tab entries these kernels use
 };
 
+// Tables read with indices uniform over the wavefront: up to n = NMAX through
+// the constant address space (scalar loads into SGPRs, which the FMAs take
+// directly); for larger n the kernel's tables would overflow the scalar
+// registers (hundreds of spills) and stay in LDS.  NMAX: 7 for the divergence
+// and gradient, 6 for the projection, which keeps more tables live.
+using cdptr = const __attribute__((address_space(4))) double*;
+template <bool C>
+struct TabPtr {
+  using type = const double*;
+};
+template <>
+struct TabPtr<true> {
+  using type = cdptr;
+};
+template <int N, int NMAX>
+__device__ __forceinline__ typename TabPtr<(N <= NMAX)>::type tab_ptr(const double* global, const double* lds) {
+  if constexpr (N <= NMAX) return (cdptr)global;
+  else return lds;
+}
+
 // One line along `axis` of an N^3 array per lane (line t = a + N b), as sweep().
-template <int N, bool TR, bool ACC>
-__device__ __forceinline__ void sweep1(const double* M, int axis, const double* in, double* out, double scale,
-                                       int t) {
+template <int N, bool TR, bool ACC, typename PT>
+__device__ __forceinline__ void sweep1(PT M, int axis, const double* in, double* out, double scale, int t) {
   constexpr int N2 = N * N;
   const int stride = axis == 0 ? 1 : (axis == 1 ? N : N2);
   const int a = t % N, b = t / N;
@@ -163,7 +182,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __re
   const int64_t cell = act ? first + slot : first;
   const V3Tab L{N};
   const double* Mh = s_tab + L.Mh();
-  const double* Ch = s_tab + L.Ch();
+  const auto cMh = tab_ptr<N, 7>(tab + L.Mh(), Mh);
+  const auto cCh = tab_ptr<N, 7>(tab + L.Ch(), s_tab + L.Ch());
   double* P0 = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;   // u_x, then the output
   double* P1 = P0 + N3;                 // u_y, then the face plane scratch (2 N2)
   double* P2 = P1 + N3;                 // u_z
@@ -181,20 +201,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_divergence(const double* __re
     }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Ch, 0, P0, P0, 1.0, t);                    // Ch_x u_x
-    sweep1<N, false, false>(Mh, 0, P1, P1, 1.0, t);                    // Mh_x u_y
-    sweep1<N, false, false>(Mh, 0, P2, P2, 1.0, t);                    // Mh_x u_z
+    sweep1<N, false, false>(cCh, 0, P0, P0, 1.0, t);                    // Ch_x u_x
+    sweep1<N, false, false>(cMh, 0, P1, P1, 1.0, t);                    // Mh_x u_y
+    sweep1<N, false, false>(cMh, 0, P2, P2, 1.0, t);                    // Mh_x u_z
   }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Mh, 1, P0, P0, s[0], t);                   // sx Mh_y Ch_x u_x
-    sweep1<N, false, true>(Ch, 1, P1, P0, s[1], t);                    // + sy Ch_y Mh_x u_y (same line)
-    sweep1<N, false, false>(Mh, 1, P2, P2, s[2], t);                   // sz Mh_y Mh_x u_z
+    sweep1<N, false, false>(cMh, 1, P0, P0, s[0], t);                   // sx Mh_y Ch_x u_x
+    sweep1<N, false, true>(cCh, 1, P1, P0, s[1], t);                    // + sy Ch_y Mh_x u_y (same line)
+    sweep1<N, false, false>(cMh, 1, P2, P2, s[2], t);                   // sz Mh_y Mh_x u_z
   }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Mh, 2, P0, P0, 1.0, t);
-    sweep1<N, false, true>(Ch, 2, P2, P0, 1.0, t);                     // same line
+    sweep1<N, false, false>(cMh, 2, P0, P0, 1.0, t);
+    sweep1<N, false, true>(cCh, 2, P2, P0, 1.0, t);                     // same line
   }
   wave_sync();
   // faces: O -= sign area (Mh (x) Mh) {{u_d}} on the face plane
@@ -236,7 +256,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __rest
   const int64_t cell = act ? first + slot : first;
   const V3Tab L{N};
   const double* Mh = s_tab + L.Mh();
-  const double* Ch = s_tab + L.Ch();
+  const auto cMh = tab_ptr<N, 7>(tab + L.Mh(), Mh);
+  const auto cCh = tab_ptr<N, 7>(tab + L.Ch(), s_tab + L.Ch());
   double* O3 = s_all + (wave * CPW + (slot < CPW ? slot : 0)) * SLICE;  // 3 N3: output components
   double* P = O3 + 2 * N3;              // p, in the slot of output component 2
   double* F = O3 + 3 * N3;              // 2 N2: face plane scratch
@@ -251,20 +272,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_gradient(const double* __rest
     for (int r = 0; r < N; ++r) P[t + N2 * r] = p[cell * N3 + t + N2 * r];
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Ch, 0, P, O3, 1.0, t);                     // Ch_x p
-    sweep1<N, false, false>(Mh, 0, P, P, 1.0, t);                      // Mh_x p (in place, after the read)
+    sweep1<N, false, false>(cCh, 0, P, O3, 1.0, t);                     // Ch_x p
+    sweep1<N, false, false>(cMh, 0, P, P, 1.0, t);                      // Mh_x p (in place, after the read)
   }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Mh, 1, O3, O3, 1.0, t);                    // Mh_y Ch_x p
-    sweep1<N, false, false>(Ch, 1, P, O3 + N3, 1.0, t);                // Ch_y Mh_x p
-    sweep1<N, false, false>(Mh, 1, P, P, 1.0, t);                      // Mh_y Mh_x p
+    sweep1<N, false, false>(cMh, 1, O3, O3, 1.0, t);                    // Mh_y Ch_x p
+    sweep1<N, false, false>(cCh, 1, P, O3 + N3, 1.0, t);                // Ch_y Mh_x p
+    sweep1<N, false, false>(cMh, 1, P, P, 1.0, t);                      // Mh_y Mh_x p
   }
   wave_sync();
   if (act) {
-    sweep1<N, false, false>(Mh, 2, O3, O3, s[0], t);
-    sweep1<N, false, false>(Mh, 2, O3 + N3, O3 + N3, s[1], t);
-    sweep1<N, false, false>(Ch, 2, P, P, s[2], t);
+    sweep1<N, false, false>(cMh, 2, O3, O3, s[0], t);
+    sweep1<N, false, false>(cMh, 2, O3 + N3, O3 + N3, s[1], t);
+    sweep1<N, false, false>(cCh, 2, P, P, s[2], t);
   }
   wave_sync();
   // faces: O_d -= sign area (Mh (x) Mh) {{p}} on the face plane
@@ -354,13 +375,13 @@ __device__ __forceinline__ void cfence() { asm volatile("" ::: "memory"); }
 
 // q = (M_e (x) I_3 + tau D_e) p on one cell; T: 3-component temporary.  Lane t owns line t.
 template <int N>
-__device__ __forceinline__ void proj_apply(const double* tb, const double* p, double* q, double* T,
+__device__ __forceinline__ void proj_apply(const double* tg, const double* tb, const double* p, double* q, double* T,
                                            const double (&hinv)[3], double vol, double tau, int t, bool act) {
   constexpr int N3 = N * N * N;
   const V3Tab L{N};
-  const double* Mh = tb + L.Mh();
-  const double* S = tb + L.S();
-  const double* D = tb + L.D();
+  const auto Mh = tab_ptr<N, 6>(tg + L.Mh(), tb + L.Mh());
+  const auto S = tab_ptr<N, 6>(tg + L.S(), tb + L.S());
+  const auto D = tab_ptr<N, 6>(tg + L.D(), tb + L.D());
   const double* w = tb + L.w();
   // mass: q_a = vol Mh_z Mh_y Mh_x p_a (the y and z sweeps in place)
   if (act)
@@ -451,10 +472,10 @@ __device__ __forceinline__ void proj_apply(const double* tb, const double* p, do
 
 // z = M_e^{-1} r = (1/vol) Mi_z Mi_y Mi_x r per component (the y and z sweeps in place)
 template <int N>
-__device__ __forceinline__ void proj_precond(const double* tb, const double* r, double* z, double vol, int t,
-                                             bool act) {
+__device__ __forceinline__ void proj_precond(const double* tg, const double* tb, const double* r, double* z,
+                                             double vol, int t, bool act) {
   constexpr int N3 = N * N * N;
-  const double* Mi = tb + V3Tab{N}.Mi();
+  const auto Mi = tab_ptr<N, 6>(tg + V3Tab{N}.Mi(), tb + V3Tab{N}.Mi());
   if (act)
 #pragma unroll 1
     for (int a = 0; a < 3; ++a) sweep1<N, false, false>(Mi, 0, r + a * N3, z + a * N3, 1.0, t);
@@ -512,7 +533,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_projection(
     }
   bb = group_sum<SS>(bb);
   wave_sync();
-  proj_apply<N>(s_tab, p, q, T, hinv, vol, tau, t, act);
+  proj_apply<N>(tab, s_tab, p, q, T, hinv, vol, tau, t, act);
   double rr = 0;
   if (act)
 #pragma unroll
@@ -527,7 +548,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_projection(
   const double tol2 = rtol * rtol * bb;
   int it = 0;
   if (rr > tol2) {
-    proj_precond<N>(s_tab, r, T, vol, t, act);
+    proj_precond<N>(tab, s_tab, r, T, vol, t, act);
     double rz = 0;
     if (act)
 #pragma unroll
@@ -539,7 +560,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_projection(
     rz = group_sum<SS>(rz);
     wave_sync();
     while (it < max_iter) {
-      proj_apply<N>(s_tab, p, q, T, hinv, vol, tau, t, act);
+      proj_apply<N>(tab, s_tab, p, q, T, hinv, vol, tau, t, act);
       double pq = 0;
       if (act)
 #pragma unroll
@@ -561,7 +582,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_v3_projection(
       ++it;
       wave_sync();
       if (rr <= tol2) break;
-      proj_precond<N>(s_tab, r, T, vol, t, act);
+      proj_precond<N>(tab, s_tab, r, T, vol, t, act);
       double rz1 = 0;
       if (act)
 #pragma unroll
