@@ -955,10 +955,16 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_grad(const dou
 //   (D u)_{i,a}  = sum_q sum_e dphi_i/dxi_e G_ea s,   s = (sum_{e,b} G_eb du_b/dxi_e) / (w |det J|)
 // (w|det J| div v div u at every point), and M^{-1} = S^{-1} (x) 3 diag(1/(w|det J|)) S^{-T} (x) 3.
 
+// Pointers whose address space the compiler could not infer through the
+// per-cell structure below (flat loads, which also stall the LDS waits):
+// tables read with wavefront-uniform indices go through the constant address
+// space (scalar loads), per-point data through global memory.
+using ctab_ptr = const __attribute__((address_space(4))) double*;
+using gmem_ptr = const __attribute__((address_space(1))) double*;
+
 // x <- A x along direction d on nb consecutive n^3 blocks (TR: A^T x); A row-major n x n
-template <int N, bool TR>
-__device__ __forceinline__ void qsweep(const double* __restrict__ A, double* buf, int nb, int d, int tid,
-                                       int nthr) {
+template <int N, bool TR, typename PT>
+__device__ __forceinline__ void qsweep(PT A, double* buf, int nb, int d, int tid, int nthr) {
   constexpr int N2 = N * N, N3 = N2 * N;
   const int stride = d == 0 ? 1 : (d == 1 ? N : N2);
   for (int job = tid; job < nb * N2; job += nthr) {
@@ -986,11 +992,11 @@ __device__ __forceinline__ double wave_total(double v) {
 }
 
 struct CurvCell {
-  const double* S;      // n x n: S[q][i] = l_i(x_q)
-  const double* D;      // n x n: l_i'(x_q)
-  const double* Si;     // n x n: S^{-1}
-  const double* G;      // 9 n^3 of this cell
-  const double* wd;     // n^3 of this cell: w |det J|
+  ctab_ptr S;      // n x n: S[q][i] = l_i(x_q)
+  ctab_ptr D;      // n x n: l_i'(x_q)
+  ctab_ptr Si;     // n x n: S^{-1}
+  gmem_ptr G;      // 9 n^3 of this cell
+  gmem_ptr wd;     // n^3 of this cell: w |det J|
 };
 
 // out = (M + tau D) u on one cell; u, out [3][n^3]; W: 8 n^3 scratch
@@ -1121,7 +1127,8 @@ __global__ void __launch_bounds__(64) k_curv_proj(const ConvGeom g, const double
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
-  const CurvCell c{g.tab + g.S, g.tab + g.D, g.tab + g.Mi, g.cmet + cell * 9 * N3, wdet + cell * 7 * N3 + 6 * N3};
+  const CurvCell c{(ctab_ptr)(g.tab + g.S), (ctab_ptr)(g.tab + g.D), (ctab_ptr)(g.tab + g.Mi),
+                   (gmem_ptr)(g.cmet + cell * 9 * N3), (gmem_ptr)(wdet + cell * 7 * N3 + 6 * N3)};
   const double tau = taus[cell];
   double bb = 0.0;
   for (int e = tid; e < 3 * N3; e += nthr) {
