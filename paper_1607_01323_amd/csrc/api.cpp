@@ -1086,7 +1086,12 @@ template dgmf_status sipg_apply<float>(dgmf_op, const float*, float*, double*, c
 template <typename T>
 dgmf_status sipg_cheb(dgmf_op op, const T* xk, T* dst, const ChebEpi<T>& epi, const int* stop, hipStream_t s) {
   const int n = op->mesh->desc.degree + 1;
-  if (op->metric) return DGMF_UNSUPPORTED;
+  if (op->metric) {
+    if constexpr (std::is_same<T, double>::value)
+      return launch_sipg_metric_cheb<double>(n, op->mg64, xk, dst, epi, stop, s);
+    else
+      return launch_sipg_metric_cheb<float>(n, op->mg32, xk, dst, epi, stop, s);
+  }
   if constexpr (std::is_same<T, double>::value)
     return launch_sipg_cart_cheb<double>(n, op->g64, xk, dst, epi, stop, s);
   else

@@ -1051,8 +1051,8 @@ struct Solver {
     hipLaunchKernelGGL((k_cheb_init<T>), G, B, 0, s, r, res, d, zc, dinv, static_cast<T>(cheb_inv_theta),
                        m == 1 ? z : nullptr, q, N, st, partials);
     DGMF_LAUNCH_CHECK("k_cheb_init");
-    if (m > 1 && !op->metric) {
-      // axis-aligned cells: the same polynomial in the three-term form
+    if (m > 1) {
+      // the same polynomial in the three-term form
       // x_{j+1} = x_j + c1 (x_j - x_{j-1}) + c2 D^{-1} (r - H x_j), x_0 = 0,
       // x_1 = d, each step fused into the apply's store (5 vectors instead of
       // 10); the buffers of x_j and x_{j-1} swap after every step

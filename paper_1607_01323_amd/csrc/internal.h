@@ -216,6 +216,11 @@ int metric_apply_blocks(int n, int nx, int ny, int nz);
 template <typename T>
 dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials,
                                      const int* stop, hipStream_t s);
+// The apply with the Chebyshev step of ChebEpi fused into its store (dst holds
+// x_{k-1} on entry, xk is x_k).
+template <typename T>
+dgmf_status launch_sipg_metric_cheb(int n, const MetricGeom<T>& g, const T* xk, T* dst, const ChebEpi<T>& epi,
+                                    const int* stop, hipStream_t s);
 template <typename TO>
 dgmf_status launch_sipg_metric_diag(int n, const MetricGeom<double>& g, TO* diag, hipStream_t s);
 // Fills cm, fm, ftau, lm, ltau of a lattice mesh with J = Sh diag(h_c).

@@ -17,8 +17,9 @@
 // Jacobi (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1) in
 // three-term form on the iterate: x_1 = x_0 + dinv (b - A x_0) / theta and
 //   x_{k+1} = x_k + c1_k (x_k - x_{k-1}) + c2_k dinv (b - A x_k);
-// on axis-aligned levels the update is fused into the apply kernel's store,
-// elsewhere k_mg_cheb_vec applies it after a plain apply.
+// the update is fused into the apply kernel's store (axis-aligned and
+// stored-metric levels alike); k_mg_cheb_vec applies it after a plain apply
+// for an operator without that fusion.
 #include "internal.h"
 
 namespace dgmf {

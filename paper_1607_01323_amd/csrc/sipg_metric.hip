@@ -116,11 +116,13 @@ __device__ __forceinline__ int plane_index(const MetricGeom<T>& g, int d, int c0
   return c1 * g.nx + c0;
 }
 
-template <int N, typename T>
+// EPI: dst holds x_{k-1} on entry and receives the Chebyshev step
+// x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^{-1} (b - H x_k), x_k = src, at the store.
+template <int N, typename T, bool EPI>
 __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(const T* __restrict__ src,
                                                                              T* __restrict__ dst, const MetricGeom<T> g,
                                                                              double* __restrict__ partials,
-                                                                             const int* stop) {
+                                                                             const int* stop, const ChebEpi<T> epi) {
   if (stop && *stop) return;
   using M = MetShape<N>;
   constexpr int N2 = M::N2, N3 = M::N3;
@@ -443,6 +445,16 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
   }
   if (act) {
     // ---- transposed sweeps: sC += sum_d Dg_d^T sG_d, then S^T in every direction
+    T eb[N], ed[N], ep[N];
+    if constexpr (EPI) {   // issued before the sweeps so that their latency overlaps them
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        const int64_t at = static_cast<int64_t>(cell) * N3 + t + m * N2;
+        eb[m] = epi.b[at];
+        ed[m] = epi.dinv[at];
+        ep[m] = epi.prev_zero ? T(0) : dst[at];
+      }
+    }
     sweep3<N, 0, true, true>(Dg, sG, sC, t);
     wave_sync();
     sweep3<N, 1, true, true>(Dg, sG + N3, sC, t);
@@ -458,7 +470,8 @@ __global__ void __launch_bounds__(MetShape<N>::THREADS) k_sipg_metric_apply(cons
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       const int e = t + m * N2;
-      const T v = sC[e];
+      T v = sC[e];
+      if constexpr (EPI) v = fma(epi.c2 * ed[m], eb[m] - v, fma(epi.c1, uo[m] - ep[m], uo[m]));
       dst[cell * N3 + e] = v;
       if (partials) {
         pq += static_cast<double>(uo[m]) * v;
@@ -927,14 +940,14 @@ int metric_apply_blocks(int n, int nx, int ny, int nz) {
   return static_cast<int>((static_cast<int64_t>(nx) * ny * nz + cpb - 1) / cpb);
 }
 
-template <typename T>
-dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials,
-                                     const int* stop, hipStream_t s) {
+template <typename T, bool EPI>
+dgmf_status launch_metric(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials, const int* stop,
+                          const ChebEpi<T>& epi, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>(metric_apply_blocks(n, g.nx, g.ny, g.nz));
 #define X(a)                                                                                                 \
   if (n == a) {                                                                                              \
-    hipLaunchKernelGGL((k_sipg_metric_apply<a, T>), dim3(blocks), dim3(MetShape<a>::THREADS), 0, s, src, dst, \
-                       g, partials, stop);                                                                   \
+    hipLaunchKernelGGL((k_sipg_metric_apply<a, T, EPI>), dim3(blocks), dim3(MetShape<a>::THREADS), 0, s, src, \
+                       dst, g, partials, stop, epi);                                                         \
     DGMF_LAUNCH_CHECK("k_sipg_metric_apply");                                                                \
     return DGMF_OK;                                                                                          \
   }
@@ -943,10 +956,27 @@ dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src
   return fail(DGMF_UNSUPPORTED, "metric apply: degree %d not built", n - 1);
 }
 
+template <typename T>
+dgmf_status launch_sipg_metric_apply(int n, const MetricGeom<T>& g, const T* src, T* dst, double* partials,
+                                     const int* stop, hipStream_t s) {
+  const ChebEpi<T> none{nullptr, nullptr, T(0), T(0), 1};
+  return launch_metric<T, false>(n, g, src, dst, partials, stop, none, s);
+}
+
+template <typename T>
+dgmf_status launch_sipg_metric_cheb(int n, const MetricGeom<T>& g, const T* xk, T* dst, const ChebEpi<T>& epi,
+                                    const int* stop, hipStream_t s) {
+  return launch_metric<T, true>(n, g, xk, dst, nullptr, stop, epi, s);
+}
+
 template dgmf_status launch_sipg_metric_apply<double>(int, const MetricGeom<double>&, const double*, double*,
                                                       double*, const int*, hipStream_t);
 template dgmf_status launch_sipg_metric_apply<float>(int, const MetricGeom<float>&, const float*, float*, double*,
                                                      const int*, hipStream_t);
+template dgmf_status launch_sipg_metric_cheb<double>(int, const MetricGeom<double>&, const double*, double*,
+                                                     const ChebEpi<double>&, const int*, hipStream_t);
+template dgmf_status launch_sipg_metric_cheb<float>(int, const MetricGeom<float>&, const float*, float*,
+                                                    const ChebEpi<float>&, const int*, hipStream_t);
 
 dgmf_status launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
   if (n <= 0) return DGMF_OK;
