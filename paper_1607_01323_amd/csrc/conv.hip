@@ -1487,11 +1487,23 @@ __global__ void __launch_bounds__((CShape<N, N>::THREADS)) k_eps_curved(const do
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
-  const double* S = g.tab + g.S;
-  const double* D = g.tab + g.D;
-  const double* W = g.tab + g.w;
-  const double* E = g.tab + eg.E;
-  const double* Gd = g.tab + eg.Gd;
+  // the 1D tables in LDS: read from there they leave the scalar registers to
+  // the map and the geometry (read as scalar loads they spilled)
+  __shared__ double sT[2 * N * Q + Q + 4 * N];
+  for (int e = tid; e < N * Q; e += nthr) {
+    sT[e] = g.tab[g.S + e];
+    sT[N * Q + e] = g.tab[g.D + e];
+  }
+  for (int e = tid; e < Q; e += nthr) sT[2 * N * Q + e] = g.tab[g.w + e];
+  for (int e = tid; e < 2 * N; e += nthr) {
+    sT[2 * N * Q + Q + e] = g.tab[eg.E + e];
+    sT[2 * N * Q + Q + 2 * N + e] = g.tab[eg.Gd + e];
+  }
+  const double* S = sT;
+  const double* D = sT + N * Q;
+  const double* W = sT + 2 * N * Q;
+  const double* E = sT + 2 * N * Q + Q;
+  const double* Gd = sT + 2 * N * Q + Q + 2 * N;
   CellGeo cg;
   conv_cell(g, cell, cg);
   for (int e = tid; e < 3 * N3; e += nthr) {
