@@ -295,7 +295,8 @@ struct ZmTile {
 };
 template <int ES> struct ZmTile<2, ES> { static constexpr int TX = 8, TY = 8; static constexpr bool PACK = false; };
 template <int ES> struct ZmTile<3, ES> { static constexpr int TX = 4, TY = 7; static constexpr bool PACK = false; };
-template <int ES> struct ZmTile<4, ES> { static constexpr int TX = 4, TY = 4; static constexpr bool PACK = false; };
+template <> struct ZmTile<4, 8> { static constexpr int TX = 4, TY = 4; static constexpr bool PACK = false; };
+template <> struct ZmTile<4, 4> { static constexpr int TX = 8, TY = 4; static constexpr bool PACK = false; };
 template <int ES> struct ZmTile<5, ES> { static constexpr int TX = 5, TY = 2; static constexpr bool PACK = true; };
 template <> struct ZmTile<6, 8> { static constexpr int TX = 7, TY = 2; static constexpr bool PACK = true; };
 template <> struct ZmTile<6, 4> { static constexpr int TX = 3, TY = 2; static constexpr bool PACK = true; };
