@@ -301,6 +301,7 @@ template <int ES> struct ZmTile<5, ES> { static constexpr int TX = 5, TY = 2; st
 template <> struct ZmTile<6, 8> { static constexpr int TX = 7, TY = 2; static constexpr bool PACK = true; };
 template <> struct ZmTile<6, 4> { static constexpr int TX = 3, TY = 2; static constexpr bool PACK = true; };
 template <> struct ZmTile<7, 8> { static constexpr int TX = 5, TY = 1; static constexpr bool PACK = true; };
+template <> struct ZmTile<8, 8> { static constexpr int TX = 4, TY = 2; static constexpr bool PACK = false; };
 
 template <int N, typename T>
 struct Zm {
