@@ -21,7 +21,11 @@
 // point fields live in LDS and the sweeps go line by line over its lanes.
 // Own face traces are extrapolated from the Gauss-point data along the normal
 // lines and the face terms are injected back into the point fluxes, so the
-// transposed cell sweeps lift cell and face terms together.
+// transposed cell sweeps lift cell and face terms together.  A neighbour's
+// traces come through LDS from the neighbouring cell itself when both sit in
+// one 2x2x2 block of the workgroup (degrees 1, 3, 4), else from the
+// neighbour's nodal face planes.  An optional epilogue fuses the Chebyshev
+// step of the smoother and preconditioner into the store.
 #include "curv_map.h"
 #include "internal.h"
 
