@@ -326,7 +326,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
   __shared__ double sU[3 * N3];
   __shared__ double sO[3 * N3];
   __shared__ double sX[X];
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nthr = SH::THREADS;
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
@@ -340,9 +341,19 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
     sU[e] = U[a * Nd + cell * N3 + r];
     sO[e] = 0.0;
   }
-  __syncthreads();
   const bool own = tid < Q2;
   const int qx = tid % Q, qy = (tid / Q) % Q;
+  // per-lane quadrature weights, read once: w_x w_y of this thread's column
+  // and w_q1 w_q2 of its face points (the same points on every face)
+  const double wxy = w[qx] * w[qy];
+  constexpr int KF = (2 * Q2 + nthr - 1) / nthr;
+  double wf[KF];
+#pragma unroll
+  for (int k = 0; k < KF; ++k) {
+    const int pq = (tid + k * nthr) % Q2;
+    wf[k] = w[pq % Q] * w[pq / Q];
+  }
+  __syncthreads();
   double u[3][Q];
   interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
   __syncthreads();
@@ -369,7 +380,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
   for (int a = 0; a < 3; ++a) {
     double fx[Q], fy[Q], fz[Q];
     if (own) {
-      const double wxy = w[qx] * w[qy] * vol;
+      const double wv = wxy * vol;
 #pragma unroll
       for (int qz = 0; qz < Q; ++qz) {
         if constexpr (CURV) {
@@ -377,7 +388,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
           fy[qz] = u[a][qz] * V[1][qz];
           fz[qz] = u[a][qz] * V[2][qz];
         } else {
-          const double f = wxy * w[qz] * u[a][qz];
+          const double f = wv * w[qz] * u[a][qz];
           fx[qz] = f * u[0][qz] * cg.hinv[0];
           fy[qz] = f * u[1][qz] * cg.hinv[1];
           fz[qz] = f * u[2][qz] * cg.hinv[2];
@@ -406,9 +417,12 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
     // P occupies the front of sX; interpolate into F1/F2 (disjoint)
     face_interp<N, Q>(S, P, F1, F2, 12, tid, nthr);
     double* R = F2 + 12 * Q2;         // 6 planes of Q*Q: [face s][comp]
-    for (int e = tid; e < 2 * Q2; e += nthr) {
+#pragma unroll
+    for (int kf = 0; kf < KF; ++kf) {
+      const int e = tid + kf * nthr;
+      if (e >= 2 * Q2) continue;
       const int s = e / Q2, pq = e % Q2;
-      const double wt = w[pq % Q] * w[pq / Q] * area;
+      const double wt = wf[kf] * area;
       // own state and exterior state at this face point, outward normal sign
       const double sg = s ? 1.0 : -1.0;
       double um[3], up[3];
@@ -493,7 +507,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   __shared__ double sW[3 * N3];
   __shared__ double sO[3 * N3];
   __shared__ double sX[X];
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nthr = SH::THREADS;
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
@@ -508,9 +523,13 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     sW[e] = W[a * Nd + cell * N3 + r];
     sO[e] = 0.0;
   }
-  __syncthreads();
   const bool own = tid < Q2;
   const int qx = tid % Q, qy = (tid / Q) % Q;
+  // w_x w_y of this thread's column, which is also the weight of its face
+  // point (at most one per face: the workgroup has at least Q^2 threads)
+  static_assert(nthr >= Q2, "one face point per thread");
+  const double wxy = w[qx] * w[qy];
+  __syncthreads();
   double u[3][Q];
   interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
   __syncthreads();
@@ -611,11 +630,11 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   double* Y = sX + 3 * N * Q2;      // 3 * N*N*Q  [c][l][j][qx]
   if (own) {
     if constexpr (!CURV) {   // curved cells carry w det J in the metric already
-      const double wxy = w[qx] * w[qy] * vol;
+      const double wv = wxy * vol;
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) t[c][q] *= wxy * w[q];
+        for (int q = 0; q < Q; ++q) t[c][q] *= wv * w[q];
     }
     // one node l per step: the S column of l only
 #pragma unroll kSweepUnroll<N, Q>
@@ -682,8 +701,9 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     __syncthreads();
     face_interp<N, Q>(S, P, F1, F2, nb >= 0 ? 12 : 9, tid, nthr);
     double* R = F2 + 12 * Q2;       // 3 planes of Q*Q
-    for (int pq = tid; pq < Q2; pq += nthr) {
-      const double wt = w[pq % Q] * w[pq / Q] * area;
+    if (own) {
+      const int pq = tid;
+      const double wt = wxy * area;
       double uo[3], ue[3], wo[3], we[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -803,7 +823,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_div(const doub
   __shared__ double sU[3 * N3];
   __shared__ double sO[N3];
   __shared__ double sX[X];
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nthr = SH::THREADS;
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
@@ -880,7 +901,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_curv_grad(const dou
   __shared__ double sP[N3];
   __shared__ double sO[3 * N3];
   __shared__ double sX[X];
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nthr = SH::THREADS;
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
@@ -1483,7 +1505,8 @@ __global__ void __launch_bounds__((CShape<N, N>::THREADS)) k_eps_curved(const do
   __shared__ double sSG[3][Q + 2], sDSG[3][Q + 2];
   const ConvGeom& g = eg.g;
   const CurvMap& m = eg.m;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nthr = SH::THREADS;
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
