@@ -148,6 +148,82 @@ __device__ __forceinline__ void interp3(const double* __restrict__ S, const doub
   }
 }
 
+// Interpolation of NC nodal fields sIn[NC][N^3] to the quadrature z-column
+// of this thread, with the y direction taken point by point: the x sweep
+// runs one line per thread into T1 ([a][l][qx][j], NC N^2 Q doubles of LDS),
+// then each column thread forms its (qx, qy) values of every (a, l) from its
+// own row of S (the y sweep; lanes of one qx read the same T1 entries) and
+// sweeps them along z in registers.  Against interp3 this needs no second
+// scratch array and one barrier less.
+template <int N, int Q, int NC, int NTHR>
+__device__ __forceinline__ void interp3_col(const double* __restrict__ S, const double* sIn, double* T1, int tid,
+                                            bool own, int qx, int qy, double (&out)[NC][Q]) {
+  constexpr int N2 = N * N;
+  for (int job = tid; job < NC * N2; job += NTHR) {    // x: (a, l, j)
+    const int al = job / N, j = job - al * N;
+    const double* in = sIn + job * N;
+    double v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = in[i];
+#pragma unroll kSweepUnroll<N, Q>
+    for (int q = 0; q < Q; ++q) {
+      double acc = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc = fma(S[q * N + i], v[i], acc);
+      T1[(al * Q + q) * N + j] = acc;
+    }
+  }
+  __syncthreads();
+  if (own) {
+    double sy[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) sy[j] = S[qy * N + j];
+#pragma unroll
+    for (int a = 0; a < NC; ++a)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) out[a][q] = 0.0;
+#pragma unroll kSweepUnroll<N, Q>
+    for (int l = 0; l < N; ++l) {
+      double xv[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        const double* t = T1 + ((a * N + l) * Q + qx) * N;
+        double acc = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc = fma(sy[j], t[j], acc);
+        xv[a] = acc;
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const double c = S[q * N + l];
+#pragma unroll
+        for (int a = 0; a < NC; ++a) out[a][q] = fma(c, xv[a], out[a][q]);
+      }
+    }
+  }
+}
+
+// First step of face_interp with the result laid out [plane][q1][p2], for
+// a second step taken point by point (each thread its own rows of S).
+template <int N, int Q, int NTHR>
+__device__ __forceinline__ void face_interp_t1(const double* __restrict__ S, const double* P, double* F1, int np,
+                                               int tid) {
+  for (int job = tid; job < np * N; job += NTHR) {     // along t1: (plane, p2)
+    const int pl = job / N, p2 = job - pl * N;
+    double v[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) v[p] = P[job * N + p];
+#pragma unroll kSweepUnroll<N, Q>
+    for (int q = 0; q < Q; ++q) {
+      double acc = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) acc = fma(S[q * N + p], v[p], acc);
+      F1[(pl * Q + q) * N + p2] = acc;
+    }
+  }
+  __syncthreads();
+}
+
 // Tangential interpolation of `np` face planes (N x N, index [p2][p1]) to
 // Q x Q points ([q2][q1]); F1 (np*N*Q) scratch, F2 (np*Q*Q) result.
 template <int N, int Q>
@@ -312,6 +388,18 @@ __device__ __forceinline__ void copy_plane(const double* sIn, int d, int s, doub
 }
 
 // ---------------------------------------------------------------- forward
+// Layout choices of the forward kernel per (n, n_q): ICOL takes the y
+// interpolation point by point in the column threads (interp3_col), FPT the
+// face interpolation along t2 point by point with the flux; both save LDS
+// (and a barrier each) for more LDS reads.  Measured on periodic boxes of
+// about 7M DoF per component, FPT is faster or level at every pair and ICOL
+// at all but (3, 4), (4, 5) and (6, 9).
+template <int N, int Q>
+struct FwdPlan {
+  static constexpr bool ICOL = !((N == 3 && Q == 4) || (N == 4 && Q == 5) || (N == 6 && Q == 9));
+  static constexpr bool FPT = true;
+};
+
 template <int N, int Q, bool STEP, bool CURV>
 __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const double* __restrict__ U,
                                                                     double* __restrict__ C, const ConvGeom g,
@@ -319,9 +407,11 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
   static_assert(!(STEP && CURV), "the fused substep needs the block inverse mass of affine cells");
   using SH = CShape<N, Q>;
   constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
-  constexpr int XR = (3 * N2 * Q + 3 * N * Q2) > (3 * N * Q2 + 2 * N2 * Q) ? (3 * N2 * Q + 3 * N * Q2)
-                                                                              : (3 * N * Q2 + 2 * N2 * Q);
-  constexpr int XF = 12 * N2 + 12 * N * Q + 12 * Q2 + 6 * Q2;   // planes, stage, traces, fluxes
+  constexpr bool ICOL = FwdPlan<N, Q>::ICOL, FPT = FwdPlan<N, Q>::FPT;
+  constexpr int XI = ICOL ? 3 * N2 * Q : 3 * N2 * Q + 3 * N * Q2;           // interpolation scratch
+  constexpr int XC = 3 * N * Q2 + 2 * N2 * Q;                               // cell lift scratch
+  constexpr int XR = XI > XC ? XI : XC;
+  constexpr int XF = 12 * N2 + 12 * N * Q + (FPT ? 0 : 12 * Q2) + 6 * Q2;   // planes, traces, fluxes
   constexpr int X = XR > XF ? XR : XF;
   __shared__ double sU[3 * N3];
   __shared__ double sO[3 * N3];
@@ -355,7 +445,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
   }
   __syncthreads();
   double u[3][Q];
-  interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
+  if constexpr (ICOL) interp3_col<N, Q, 3, nthr>(S, sU, sX, tid, own, qx, qy, u);
+  else interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
   __syncthreads();
   // cell term: for each a, A1 = Sz^T F_ax, A2 = Sz^T F_ay, A3 = Dz^T F_az  (z-columns in registers),
   // then B1 = Sy^T A1, B23 = Dy^T A2 + Sy^T A3, out = -(Dx^T B1 + Sx^T B23)
@@ -397,14 +488,24 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
     }
     cell_lift_grad<N, Q>(S, D, fx, fy, fz, own, qx, qy, A, B, sO + a * N3, -1.0, tid, nthr);
   }
-  // faces, one direction at a time (the two faces of a direction touch disjoint node planes)
+  // faces, one direction at a time (the two faces of a direction touch disjoint node planes);
+  // the rows of S for this thread's face points along t2 (the same on every face)
+  double sr[FPT ? KF : 1][N];
+  if constexpr (FPT) {
+#pragma unroll
+    for (int kf = 0; kf < KF; ++kf) {
+      const int q2 = ((tid + kf * nthr) % Q2) / Q;
+#pragma unroll
+      for (int p = 0; p < N; ++p) sr[kf][p] = S[q2 * N + p];
+    }
+  }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const double area = cg.h[t1] * cg.h[t2];
     double* P = sX;                   // 12 planes of N*N: [face s][side m][comp]
-    double* F1 = sX + 12 * N2;        // 12 * N*Q
-    double* F2 = F1 + 12 * N * Q;     // 12 * Q*Q
+    double* F1 = sX + 12 * N2;        // 12 * N*Q: [plane][q1][p2] (FPT), else [plane][p2][q1]
+    double* F2 = F1 + 12 * N * Q;     // 12 * Q*Q, without FPT
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       copy_plane<N>(sU, d, s, P + (s * 2 + 0) * 3 * N2, 1.0, tid, nthr);
@@ -414,9 +515,11 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
         copy_plane<N>(sU, d, s, P + (s * 2 + 1) * 3 * N2, ((g.neu >> (2 * d + s)) & 1) ? 1.0 : -1.0, tid, nthr);
     }
     __syncthreads();
-    // P occupies the front of sX; interpolate into F1/F2 (disjoint)
-    face_interp<N, Q>(S, P, F1, F2, 12, tid, nthr);
-    double* R = F2 + 12 * Q2;         // 6 planes of Q*Q: [face s][comp]
+    // P occupies the front of sX; interpolate along t1 into F1 (disjoint),
+    // then along t2 one face point per thread, with the flux
+    if constexpr (FPT) face_interp_t1<N, Q, nthr>(S, P, F1, 12, tid);
+    else face_interp<N, Q>(S, P, F1, F2, 12, tid, nthr);
+    double* R = FPT ? F2 : F2 + 12 * Q2;   // 6 planes of Q*Q: [face s][comp]
 #pragma unroll
     for (int kf = 0; kf < KF; ++kf) {
       const int e = tid + kf * nthr;
@@ -425,11 +528,25 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
       const double wt = wf[kf] * area;
       // own state and exterior state at this face point, outward normal sign
       const double sg = s ? 1.0 : -1.0;
+      const int q1 = pq % Q;
       double um[3], up[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        um[a] = F2[((s * 2 + 0) * 3 + a) * Q2 + pq];
-        up[a] = F2[((s * 2 + 1) * 3 + a) * Q2 + pq];
+        if constexpr (FPT) {
+          const double* fo = F1 + (((s * 2 + 0) * 3 + a) * Q + q1) * N;
+          const double* fe = F1 + (((s * 2 + 1) * 3 + a) * Q + q1) * N;
+          double vo = 0.0, ve = 0.0;
+#pragma unroll
+          for (int p = 0; p < N; ++p) {
+            vo = fma(sr[kf][p], fo[p], vo);
+            ve = fma(sr[kf][p], fe[p], ve);
+          }
+          um[a] = vo;
+          up[a] = ve;
+        } else {
+          um[a] = F2[((s * 2 + 0) * 3 + a) * Q2 + pq];
+          up[a] = F2[((s * 2 + 1) * 3 + a) * Q2 + pq];
+        }
       }
       double an, bn, sc;
       if constexpr (CURV) {
