@@ -609,6 +609,15 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
 }
 
 // -------------------------------------------------------------------- VJP
+// Layout choices of the VJP kernel per (n, n_q), as FwdPlan for the forward
+// (the cell lift's scratch bounds the LDS here, so ICOL saves a barrier but
+// no LDS).  Measured as for the forward: both are faster or level at every
+// pair but (3, 4).
+template <int N, int Q>
+struct VjpPlan {
+  static constexpr bool ICOL = !(N == 3 && Q == 4), FPT = !(N == 3 && Q == 4);
+};
+
 template <int N, int Q, bool CURV>
 __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const double* __restrict__ U,
                                                                     const double* __restrict__ W,
@@ -616,10 +625,13 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
                                                                     int64_t ncells) {
   using SH = CShape<N, Q>;
   constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
-  constexpr int XI = 3 * N2 * Q + 3 * N * Q2;          // interp3 scratch
-  constexpr int XD = 2 * N2 * Q + 3 * N * Q2;          // gradient scratch
-  constexpr int XF = 12 * N2 + 12 * N * Q + 12 * Q2 + 3 * Q2;   // one face: 12 planes + fluxes
-  constexpr int X = XI > XD ? (XI > XF ? XI : XF) : (XD > XF ? XD : XF);
+  constexpr bool ICOL = VjpPlan<N, Q>::ICOL, FPT = VjpPlan<N, Q>::FPT;
+  constexpr int XI = ICOL ? 3 * N2 * Q : 3 * N2 * Q + 3 * N * Q2;            // interpolation scratch
+  constexpr int XD = 2 * N2 * Q + 3 * N * Q2;                                 // gradient scratch
+  constexpr int XL = 3 * N * Q2 + 3 * N2 * Q;                                 // cell lift scratch
+  constexpr int XF = 12 * N2 + 12 * N * Q + (FPT ? 0 : 12 * Q2) + 3 * Q2;     // one face: 12 planes + fluxes
+  constexpr int XID = XI > XD ? XI : XD, XLF = XL > XF ? XL : XF;
+  constexpr int X = XID > XLF ? XID : XLF;
   __shared__ double sU[3 * N3];
   __shared__ double sW[3 * N3];
   __shared__ double sO[3 * N3];
@@ -648,7 +660,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   const double wxy = w[qx] * w[qy];
   __syncthreads();
   double u[3][Q];
-  interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
+  if constexpr (ICOL) interp3_col<N, Q, 3, nthr>(S, sU, sX, tid, own, qx, qy, u);
+  else interp3<N, Q>(S, sU, sX, sX + 3 * N2 * Q, tid, nthr, own, qx, qy, u);
   __syncthreads();
   double t[3][Q];
 #pragma unroll
@@ -797,6 +810,10 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     }
   }
   __syncthreads();
+  // row qy of S, for the face points of this thread along t2 (FPT)
+  double sy[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) sy[p] = S[qy * N + p];
   // faces, one at a time: 12 planes = [u own, u ext, w own, w ext] x 3 components
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -804,8 +821,8 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const double area = cg.h[t1] * cg.h[t2];
     double* P = sX;
-    double* F1 = sX + 12 * N2;
-    double* F2 = F1 + 12 * N * Q;
+    double* F1 = sX + 12 * N2;        // 12 * N*Q: [plane][q1][p2] (FPT), else [plane][p2][q1]
+    double* F2 = F1 + 12 * N * Q;     // 12 * Q*Q, without FPT
     const int64_t nb = conv_nb(g, cg, cell, d, s);
     copy_plane<N>(sU, d, s, P + 0 * 3 * N2, 1.0, tid, nthr);
     copy_plane<N>(sW, d, s, P + 2 * 3 * N2, 1.0, tid, nthr);
@@ -816,18 +833,38 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
       copy_plane<N>(sU, d, s, P + 1 * 3 * N2, -1.0, tid, nthr);
     }
     __syncthreads();
-    face_interp<N, Q>(S, P, F1, F2, nb >= 0 ? 12 : 9, tid, nthr);
-    double* R = F2 + 12 * Q2;       // 3 planes of Q*Q
+    if constexpr (FPT) face_interp_t1<N, Q, nthr>(S, P, F1, nb >= 0 ? 12 : 9, tid);
+    else face_interp<N, Q>(S, P, F1, F2, nb >= 0 ? 12 : 9, tid, nthr);
+    double* R = FPT ? F2 : F2 + 12 * Q2;   // 3 planes of Q*Q
     if (own) {
       const int pq = tid;
       const double wt = wxy * area;
       double uo[3], ue[3], wo[3], we[3];
+      if constexpr (FPT) {
+        // along t2 at this point: row qy of S (t1 = qx, t2 = qy on the
+        // face's point grid pq = q2 Q + q1)
+        auto along_t2 = [&](int pl) {
+          const double* f = F1 + (pl * Q + qx) * N;
+          double acc = 0.0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        uo[a] = F2[(0 * 3 + a) * Q2 + pq];
-        ue[a] = F2[(1 * 3 + a) * Q2 + pq];
-        wo[a] = F2[(2 * 3 + a) * Q2 + pq];
-        we[a] = nb >= 0 ? F2[(3 * 3 + a) * Q2 + pq] : 0.0;
+          for (int p = 0; p < N; ++p) acc = fma(sy[p], f[p], acc);
+          return acc;
+        };
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          uo[a] = along_t2(0 * 3 + a);
+          ue[a] = along_t2(1 * 3 + a);
+          wo[a] = along_t2(2 * 3 + a);
+          we[a] = nb >= 0 ? along_t2(3 * 3 + a) : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          uo[a] = F2[(0 * 3 + a) * Q2 + pq];
+          ue[a] = F2[(1 * 3 + a) * Q2 + pq];
+          wo[a] = F2[(2 * 3 + a) * Q2 + pq];
+          we[a] = nb >= 0 ? F2[(3 * 3 + a) * Q2 + pq] : 0.0;
+        }
       }
       // normal along +xi_d: e_d on affine cells (weight wt), the weighted
       // normal w dA n of the face point on curved cells (weight 1)
