@@ -611,12 +611,103 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
 // -------------------------------------------------------------------- VJP
 // Layout choices of the VJP kernel per (n, n_q), as FwdPlan for the forward
 // (the cell lift's scratch bounds the LDS here, so ICOL saves a barrier but
-// no LDS).  Measured as for the forward: both are faster or level at every
-// pair but (3, 4).
+// no LDS); PAIR treats both faces of a direction in one pass (half the face
+// barriers, twice the face scratch).  Measured as for the forward: ICOL and
+// FPT are faster or level at every pair but (3, 4); PAIR at all but (4, 6),
+// (5, 7) and (6, 8), where the larger scratch costs resident cells.
 template <int N, int Q>
 struct VjpPlan {
   static constexpr bool ICOL = !(N == 3 && Q == 4), FPT = !(N == 3 && Q == 4);
+  static constexpr bool PAIR = FPT && !((N == 4 && Q == 6) || (N == 5 && Q == 7) || (N == 6 && Q == 8));
 };
+
+// Transposed flux Jacobian of the VJP at one face point of face f = 2d + s:
+// out = sc (dR/du)^T [w] on the own side, with the own and exterior traces
+// of u and w (uo, ue, wo, we; we unused without neighbour).
+template <bool CURV>
+__device__ __forceinline__ void vjp_face_point(const ConvGeom& g, int64_t cell, int d, int s, bool hasnb, int pq,
+                                               int Q2, double wt, const double (&uo)[3], const double (&ue)[3],
+                                               const double (&wo)[3], const double (&we)[3], double (&out)[3]) {
+  const int f = 2 * d + s;
+  // normal along +xi_d: e_d on affine cells (weight wt), the weighted
+  // normal w dA n of the face point on curved cells (weight 1)
+  double nv[3] = {0.0, 0.0, 0.0};
+  double sc;
+  if constexpr (CURV) {
+    const double* fm = g.fmet + (cell * 18 + f * 3) * Q2 + pq;
+    nv[0] = fm[0];
+    nv[1] = fm[Q2];
+    nv[2] = fm[2 * Q2];
+    sc = 1.0;
+  } else {
+    sc = wt;
+  }
+  // n . v for the normal above
+  auto ndot = [&](const double* v) {
+    if constexpr (CURV) return fma(nv[0], v[0], fma(nv[1], v[1], nv[2] * v[2]));
+    else return v[d];
+  };
+  // res += n x
+  auto nadd = [&](double* res, double x) {
+    if constexpr (CURV) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) res[b] = fma(nv[b], x, res[b]);
+    } else {
+      res[d] += x;
+    }
+  };
+  double res[3];
+  if (hasnb) {
+    // orient with the low cell as the minus side, n along +xi_d
+    const double* um = s ? uo : ue;
+    const double* up = s ? ue : uo;
+    double jw[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jw[a] = s ? (wo[a] - we[a]) : (we[a] - wo[a]);
+    const double an = ndot(um), bn = ndot(up);
+    const double lam = fmax(fabs(an), fabs(bn));
+    const bool mact = fabs(an) >= fabs(bn);
+    const double dj = (um[0] - up[0]) * jw[0] + (um[1] - up[1]) * jw[1] + (um[2] - up[2]) * jw[2];
+    if (s) {   // this cell is the minus side: J-^T [w]
+      const double ujw = um[0] * jw[0] + um[1] * jw[1] + um[2] * jw[2];
+      const double dl = mact ? (an > 0 ? 1.0 : (an < 0 ? -1.0 : 0.0)) : 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) res[a] = 0.5 * an * jw[a] + lam * jw[a];
+      nadd(res, 0.5 * ujw + dl * dj);
+    } else {   // this cell is the plus side: J+^T [w]
+      const double ujw = up[0] * jw[0] + up[1] * jw[1] + up[2] * jw[2];
+      const double dl = mact ? 0.0 : (bn > 0 ? 1.0 : (bn < 0 ? -1.0 : 0.0));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) res[a] = 0.5 * bn * jw[a] - lam * jw[a];
+      nadd(res, 0.5 * ujw + dl * dj);
+    }
+  } else if ((g.neu >> f) & 1) {
+    // outflow: R = u (u.n), (dR/du)^T w = (u.n) w + n (u.w), outward normal sg e_d
+    const double sg = s ? 1.0 : -1.0;
+    const double an = sg * ndot(uo);
+    const double ujm = uo[0] * wo[0] + uo[1] * wo[1] + uo[2] * wo[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) res[a] = an * wo[a];
+    nadd(res, sg * ujm);
+  } else {
+    // Dirichlet: (J- - J+)^T w- with u+ = -u-, outward normal sg e_d
+    const double sg = s ? 1.0 : -1.0;
+    const double an = sg * ndot(uo), bn = sg * ndot(ue);
+    const double lam = fmax(fabs(an), fabs(bn));
+    const bool mact = fabs(an) >= fabs(bn);
+    const double dj = (uo[0] - ue[0]) * wo[0] + (uo[1] - ue[1]) * wo[1] + (uo[2] - ue[2]) * wo[2];
+    const double ujm = uo[0] * wo[0] + uo[1] * wo[1] + uo[2] * wo[2];
+    const double ujp = ue[0] * wo[0] + ue[1] * wo[1] + ue[2] * wo[2];
+    const double sa = an > 0 ? 1.0 : (an < 0 ? -1.0 : 0.0);
+    const double sb = bn > 0 ? 1.0 : (bn < 0 ? -1.0 : 0.0);
+    const double dlm = mact ? sa : 0.0, dlp = mact ? 0.0 : sb;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) res[a] = 0.5 * (an - bn) * wo[a] + 2.0 * lam * wo[a];
+    nadd(res, sg * (0.5 * (ujm - ujp) + (dlm - dlp) * dj));
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[a] = sc * res[a];
+}
 
 template <int N, int Q, bool CURV>
 __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const double* __restrict__ U,
@@ -625,11 +716,12 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
                                                                     int64_t ncells) {
   using SH = CShape<N, Q>;
   constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
-  constexpr bool ICOL = VjpPlan<N, Q>::ICOL, FPT = VjpPlan<N, Q>::FPT;
+  constexpr bool ICOL = VjpPlan<N, Q>::ICOL, FPT = VjpPlan<N, Q>::FPT, PAIR = VjpPlan<N, Q>::PAIR;
   constexpr int XI = ICOL ? 3 * N2 * Q : 3 * N2 * Q + 3 * N * Q2;            // interpolation scratch
   constexpr int XD = 2 * N2 * Q + 3 * N * Q2;                                 // gradient scratch
   constexpr int XL = 3 * N * Q2 + 3 * N2 * Q;                                 // cell lift scratch
-  constexpr int XF = 12 * N2 + 12 * N * Q + (FPT ? 0 : 12 * Q2) + 3 * Q2;     // one face: 12 planes + fluxes
+  constexpr int XF = PAIR ? 24 * N2 + 24 * N * Q + 6 * Q2                      // two faces: 24 planes + fluxes
+                          : 12 * N2 + 12 * N * Q + (FPT ? 0 : 12 * Q2) + 3 * Q2;   // one face: 12 planes + fluxes
   constexpr int XID = XI > XD ? XI : XD, XLF = XL > XF ? XL : XF;
   constexpr int X = XID > XLF ? XID : XLF;
   __shared__ double sU[3 * N3];
@@ -814,6 +906,71 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
   double sy[N];
 #pragma unroll
   for (int p = 0; p < N; ++p) sy[p] = S[qy * N + p];
+  if constexpr (PAIR) {
+    // faces, both of a direction at once: 24 planes = [side s][u own, u ext, w own, w ext][component]
+    constexpr int KV = (2 * Q2 + nthr - 1) / nthr;
+    double wv[KV], sv[KV][N];   // weights and rows of S along t2 of this thread's face points
+#pragma unroll
+    for (int k2 = 0; k2 < KV; ++k2) {
+      const int pq = (tid + k2 * nthr) % Q2;
+      wv[k2] = w[pq % Q] * w[pq / Q];
+#pragma unroll
+      for (int p = 0; p < N; ++p) sv[k2][p] = S[(pq / Q) * N + p];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      const double area = cg.h[t1] * cg.h[t2];
+      double* P = sX;
+      double* F1 = sX + 24 * N2;        // 24 * N*Q, [plane][q1][p2]
+      double* R = F1 + 24 * N * Q;      // 6 planes of Q*Q: [side s][component]
+      const int64_t nb0 = conv_nb(g, cg, cell, d, 0), nb1 = conv_nb(g, cg, cell, d, 1);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        double* Ps = P + s * 12 * N2;
+        const int64_t nb = s ? nb1 : nb0;
+        copy_plane<N>(sU, d, s, Ps + 0 * 3 * N2, 1.0, tid, nthr);
+        copy_plane<N>(sW, d, s, Ps + 2 * 3 * N2, 1.0, tid, nthr);
+        if (nb >= 0) {
+          load_plane<N>(U, Nd, nb, d, 1 - s, Ps + 1 * 3 * N2, tid, nthr);
+          load_plane<N>(W, Nd, nb, d, 1 - s, Ps + 3 * 3 * N2, tid, nthr);
+        } else {
+          copy_plane<N>(sU, d, s, Ps + 1 * 3 * N2, -1.0, tid, nthr);
+          copy_plane<N>(sW, d, s, Ps + 3 * 3 * N2, 0.0, tid, nthr);   // not used
+        }
+      }
+      __syncthreads();
+      face_interp_t1<N, Q, nthr>(S, P, F1, 24, tid);
+#pragma unroll
+      for (int k2 = 0; k2 < KV; ++k2) {
+        const int e = tid + k2 * nthr;
+        if (e >= 2 * Q2) continue;
+        const int s = e / Q2, pq = e - s * Q2, q1 = pq % Q;
+        const bool hb = (s ? nb1 : nb0) >= 0;
+        auto along_t2 = [&](int pl) {
+          const double* f = F1 + ((s * 12 + pl) * Q + q1) * N;
+          double acc = 0.0;
+#pragma unroll
+          for (int p = 0; p < N; ++p) acc = fma(sv[k2][p], f[p], acc);
+          return acc;
+        };
+        double uo[3], ue[3], wo[3], we[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          uo[a] = along_t2(0 * 3 + a);
+          ue[a] = along_t2(1 * 3 + a);
+          wo[a] = along_t2(2 * 3 + a);
+          we[a] = hb ? along_t2(3 * 3 + a) : 0.0;
+        }
+        double rr[3];
+        vjp_face_point<CURV>(g, cell, d, s, hb, pq, Q2, wv[k2] * area, uo, ue, wo, we, rr);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) R[(s * 3 + a) * Q2 + pq] = rr[a];
+      }
+      __syncthreads();
+      face_lift<N, Q>(S, R, F1, sO, 6, d, -1, tid, nthr);
+    }
+  } else {
   // faces, one at a time: 12 planes = [u own, u ext, w own, w ext] x 3 components
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -866,87 +1023,14 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
           we[a] = nb >= 0 ? F2[(3 * 3 + a) * Q2 + pq] : 0.0;
         }
       }
-      // normal along +xi_d: e_d on affine cells (weight wt), the weighted
-      // normal w dA n of the face point on curved cells (weight 1)
-      double nv[3] = {0.0, 0.0, 0.0};
-      double sc;
-      if constexpr (CURV) {
-        const double* fm = g.fmet + (cell * 18 + f * 3) * Q2 + pq;
-        nv[0] = fm[0];
-        nv[1] = fm[Q2];
-        nv[2] = fm[2 * Q2];
-        sc = 1.0;
-      } else {
-        sc = wt;
-      }
-      // n . v for the normal above
-      auto ndot = [&](const double* v) {
-        if constexpr (CURV) return fma(nv[0], v[0], fma(nv[1], v[1], nv[2] * v[2]));
-        else return v[d];
-      };
-      // res += n x
-      auto nadd = [&](double* res, double x) {
-        if constexpr (CURV) {
+      double rr[3];
+      vjp_face_point<CURV>(g, cell, d, s, nb >= 0, pq, Q2, wt, uo, ue, wo, we, rr);
 #pragma unroll
-          for (int b = 0; b < 3; ++b) res[b] = fma(nv[b], x, res[b]);
-        } else {
-          res[d] += x;
-        }
-      };
-      double res[3];
-      if (nb >= 0) {
-        // orient with the low cell as the minus side, n along +xi_d
-        const double* um = s ? uo : ue;
-        const double* up = s ? ue : uo;
-        double jw[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) jw[a] = s ? (wo[a] - we[a]) : (we[a] - wo[a]);
-        const double an = ndot(um), bn = ndot(up);
-        const double lam = fmax(fabs(an), fabs(bn));
-        const bool mact = fabs(an) >= fabs(bn);
-        const double dj = (um[0] - up[0]) * jw[0] + (um[1] - up[1]) * jw[1] + (um[2] - up[2]) * jw[2];
-        if (s) {   // this cell is the minus side: J-^T [w]
-          const double ujw = um[0] * jw[0] + um[1] * jw[1] + um[2] * jw[2];
-          const double dl = mact ? (an > 0 ? 1.0 : (an < 0 ? -1.0 : 0.0)) : 0.0;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) res[a] = 0.5 * an * jw[a] + lam * jw[a];
-          nadd(res, 0.5 * ujw + dl * dj);
-        } else {   // this cell is the plus side: J+^T [w]
-          const double ujw = up[0] * jw[0] + up[1] * jw[1] + up[2] * jw[2];
-          const double dl = mact ? 0.0 : (bn > 0 ? 1.0 : (bn < 0 ? -1.0 : 0.0));
-#pragma unroll
-          for (int a = 0; a < 3; ++a) res[a] = 0.5 * bn * jw[a] - lam * jw[a];
-          nadd(res, 0.5 * ujw + dl * dj);
-        }
-      } else if ((g.neu >> f) & 1) {
-        // outflow: R = u (u.n), (dR/du)^T w = (u.n) w + n (u.w), outward normal sg e_d
-        const double sg = s ? 1.0 : -1.0;
-        const double an = sg * ndot(uo);
-        const double ujm = uo[0] * wo[0] + uo[1] * wo[1] + uo[2] * wo[2];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) res[a] = an * wo[a];
-        nadd(res, sg * ujm);
-      } else {
-        // Dirichlet: (J- - J+)^T w- with u+ = -u-, outward normal sg e_d
-        const double sg = s ? 1.0 : -1.0;
-        const double an = sg * ndot(uo), bn = sg * ndot(ue);
-        const double lam = fmax(fabs(an), fabs(bn));
-        const bool mact = fabs(an) >= fabs(bn);
-        const double dj = (uo[0] - ue[0]) * wo[0] + (uo[1] - ue[1]) * wo[1] + (uo[2] - ue[2]) * wo[2];
-        const double ujm = uo[0] * wo[0] + uo[1] * wo[1] + uo[2] * wo[2];
-        const double ujp = ue[0] * wo[0] + ue[1] * wo[1] + ue[2] * wo[2];
-        const double sa = an > 0 ? 1.0 : (an < 0 ? -1.0 : 0.0);
-        const double sb = bn > 0 ? 1.0 : (bn < 0 ? -1.0 : 0.0);
-        const double dlm = mact ? sa : 0.0, dlp = mact ? 0.0 : sb;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) res[a] = 0.5 * (an - bn) * wo[a] + 2.0 * lam * wo[a];
-        nadd(res, sg * (0.5 * (ujm - ujp) + (dlm - dlp) * dj));
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) R[a * Q2 + pq] = sc * res[a];
+      for (int a = 0; a < 3; ++a) R[a * Q2 + pq] = rr[a];
     }
     __syncthreads();
     face_lift<N, Q>(S, R, F1, sO, 3, d, s, tid, nthr);
+  }
   }
   __syncthreads();
   for (int e = tid; e < 3 * N3; e += nthr) {
