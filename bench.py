@@ -40,6 +40,24 @@ def reference_flops_per_dof(n):
     return 24 * n + 120
 
 
+def convective_flops_per_cell(n, q):
+    """Sum-factorised work of the convective operator per cell (Sec. 5: 1D
+    sweeps of the tensor-product basis at n_q = q points), counting 2 flops per
+    multiply-add of the sweeps and leaving out the pointwise flux arithmetic:
+    forward = interpolation of 3 components (3 sweeps each), the divergence
+    lift of 3 flux vectors (8 sweeps each) and, per direction, 12 trace planes
+    interpolated and 6 lifted back; VJP = the same interpolation, the gradient
+    of 3 components of w (7 sweeps each), the lift of 3 components and, per
+    face, 12 planes interpolated and 3 lifted."""
+    interp = 3 * (n ** 3 * q + n ** 2 * q ** 2 + n * q ** 3)
+    div_lift = 3 * (3 * n * q ** 3 + 3 * n ** 2 * q ** 2 + 2 * n ** 3 * q)
+    fwd_faces = 3 * (12 * n ** 2 * q + 12 * n * q ** 2 + 6 * n * q ** 2 + 6 * n ** 2 * q)
+    grad = 3 * (2 * n ** 3 * q + 3 * n ** 2 * q ** 2 + 3 * n * q ** 3)
+    lift = 3 * (n * q ** 3 + n ** 2 * q ** 2 + n ** 3 * q)
+    vjp_faces = 6 * (12 * n ** 2 * q + 12 * n * q ** 2 + 3 * n * q ** 2 + 3 * n ** 2 * q)
+    return 2.0 * (interp + div_lift + fwd_faces), 2.0 * (interp + grad + lift + vjp_faces)
+
+
 def _events_time(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -370,8 +388,11 @@ def convective_measurements(dg, inp, torch):
     tf = _events_time(lambda: op3.apply(U, Cout), 20, 3)
     tv = _events_time(lambda: op3.vjp(U, Wc, Gout), 20, 3)
     n3 = 3 * m3.ndofs
+    ff, fv = convective_flops_per_cell(w3.degree + 1, w3.conv_points)
     ex["c3_convective"] = {"fwd_us": tf * 1e6, "vjp_us": tv * 1e6, "fwd_dofs_per_s": n3 / tf, "vjp_dofs_per_s": n3 / tv,
-                           "fwd_plus_vjp_dofs_per_s": n3 / (tf + tv), "dofs": n3}
+                           "fwd_plus_vjp_dofs_per_s": n3 / (tf + tv), "dofs": n3,
+                           "fwd_fp64_frac": ff * m3.ncells / tf / 1e12 / FP64_PEAK_TFLOPS,
+                           "vjp_fp64_frac": fv * m3.ncells / tv / 1e12 / FP64_PEAK_TFLOPS}
     ex.update(step_measurements(m3, op3, U, Cout, "c3"))
     ex.update(v3_measurements(m3, U, "c3"))
     m3.close()
@@ -640,9 +661,13 @@ def channel_measurements(dg, inp, torch, w, tag, cg=True, conv=True):
     Gout = torch.empty_like(U)
     tf = _events_time(lambda: opc.apply(U, Cout), 10, 2)
     tv = _events_time(lambda: opc.vjp(U, Wc, Gout), 10, 2)
+    nq = w.conv_points or (3 * n) // 2
+    ff, fv = convective_flops_per_cell(n, nq)
     ex[f"{tag}_convective"] = {"fwd_us": tf * 1e6, "vjp_us": tv * 1e6, "fwd_dofs_per_s": 3 * N / tf,
                                "vjp_dofs_per_s": 3 * N / tv, "fwd_plus_vjp_dofs_per_s": 3 * N / (tf + tv),
-                               "dofs": 3 * N, "n_q": w.conv_points or (3 * n) // 2}
+                               "dofs": 3 * N, "n_q": nq,
+                               "fwd_fp64_frac": ff * m.ncells / tf / 1e12 / FP64_PEAK_TFLOPS,
+                               "vjp_fp64_frac": fv * m.ncells / tv / 1e12 / FP64_PEAK_TFLOPS}
     ex.update(step_measurements(m, opc, U, Cout, tag))
     if cg:
         ex.update(v3_measurements(m, U, tag))
