@@ -377,6 +377,17 @@ __device__ __forceinline__ void load_plane(const double* __restrict__ U, int64_t
   }
 }
 
+// load_plane times a factor (the own cell's plane as a mirror state)
+template <int N>
+__device__ __forceinline__ void load_plane_scaled(const double* __restrict__ U, int64_t Nd, int64_t c, int d, int s,
+                                                  double* P, double scale, int tid, int nthr) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  for (int e = tid; e < 3 * N2; e += nthr) {
+    const int a = e / N2, r = e % N2;
+    P[e] = scale * U[a * Nd + c * N3 + face_node<N>(d, s, r % N, r / N)];
+  }
+}
+
 template <int N>
 __device__ __forceinline__ void copy_plane(const double* sIn, int d, int s, double* P, double scale, int tid,
                                            int nthr) {
@@ -408,14 +419,19 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
   using SH = CShape<N, Q>;
   constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
   constexpr bool ICOL = FwdPlan<N, Q>::ICOL, FPT = FwdPlan<N, Q>::FPT;
-  constexpr int XI = ICOL ? 3 * N2 * Q : 3 * N2 * Q + 3 * N * Q2;           // interpolation scratch
+  // The nodal values of the cell (sU) are needed only by the interpolation's
+  // x sweep: they sit in the scratch behind its first stage (T1, 3 N^2 Q),
+  // where the second stage (without ICOL) overwrites them; the faces read the
+  // cell's own planes from global memory again.
+  constexpr int XT = 3 * N2 * Q;                                            // interpolation stage 1
+  constexpr int XI = XT + (ICOL ? 3 * N3 : (3 * N3 > 3 * N * Q2 ? 3 * N3 : 3 * N * Q2));
   constexpr int XC = 3 * N * Q2 + 2 * N2 * Q;                               // cell lift scratch
   constexpr int XR = XI > XC ? XI : XC;
   constexpr int XF = 12 * N2 + 12 * N * Q + (FPT ? 0 : 12 * Q2) + 6 * Q2;   // planes, traces, fluxes
   constexpr int X = XR > XF ? XR : XF;
-  __shared__ double sU[3 * N3];
   __shared__ double sO[3 * N3];
   __shared__ double sX[X];
+  double* sU = sX + XT;
   const int tid = threadIdx.x;
   constexpr int nthr = SH::THREADS;
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
@@ -508,11 +524,12 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
     double* F2 = F1 + 12 * N * Q;     // 12 * Q*Q, without FPT
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      copy_plane<N>(sU, d, s, P + (s * 2 + 0) * 3 * N2, 1.0, tid, nthr);
+      load_plane<N>(U, Nd, cell, d, s, P + (s * 2 + 0) * 3 * N2, tid, nthr);
       const int64_t nb = conv_nb(g, cg, cell, d, s);
       if (nb >= 0) load_plane<N>(U, Nd, nb, d, 1 - s, P + (s * 2 + 1) * 3 * N2, tid, nthr);
       else   // mirror u+ = -u- (no-slip) or the own state u+ = u- (outflow)
-        copy_plane<N>(sU, d, s, P + (s * 2 + 1) * 3 * N2, ((g.neu >> (2 * d + s)) & 1) ? 1.0 : -1.0, tid, nthr);
+        load_plane_scaled<N>(U, Nd, cell, d, s, P + (s * 2 + 1) * 3 * N2, ((g.neu >> (2 * d + s)) & 1) ? 1.0 : -1.0,
+                             tid, nthr);
     }
     __syncthreads();
     // P occupies the front of sX; interpolate along t1 into F1 (disjoint),
@@ -598,7 +615,7 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_fwd(const doub
     const double sc = -dt * cg.hinv[0] * cg.hinv[1] * cg.hinv[2];
     for (int e = tid; e < 3 * N3; e += nthr) {
       const int a = e / N3, r = e % N3;
-      C[a * Nd + cell * N3 + r] = fma(sc, sO[e], sU[e]);
+      C[a * Nd + cell * N3 + r] = fma(sc, sO[e], U[a * Nd + cell * N3 + r]);
     }
   } else {
     for (int e = tid; e < 3 * N3; e += nthr) {
