@@ -636,6 +636,11 @@ template <int N, int Q>
 struct VjpPlan {
   static constexpr bool ICOL = !(N == 3 && Q == 4), FPT = !(N == 3 && Q == 4);
   static constexpr bool PAIR = FPT && !((N == 4 && Q == 6) || (N == 5 && Q == 7) || (N == 6 && Q == 8));
+  // SUX keeps u's nodal values in the interpolation scratch (as the forward
+  // does) and reads u's own face planes from global memory: one more resident
+  // cell per CU at (6, 8); elsewhere the registers bound the occupancy and
+  // the extra reads cost more
+  static constexpr bool SUX = N == 6 && Q == 8;
 };
 
 // Transposed flux Jacobian of the VJP at one face point of face f = 2d + s:
@@ -733,18 +738,24 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
                                                                     int64_t ncells) {
   using SH = CShape<N, Q>;
   constexpr int N2 = SH::N2, N3 = SH::N3, Q2 = SH::Q2, Q3 = Q2 * Q;
-  constexpr bool ICOL = VjpPlan<N, Q>::ICOL, FPT = VjpPlan<N, Q>::FPT, PAIR = VjpPlan<N, Q>::PAIR;
-  constexpr int XI = ICOL ? 3 * N2 * Q : 3 * N2 * Q + 3 * N * Q2;            // interpolation scratch
+  constexpr bool ICOL = VjpPlan<N, Q>::ICOL, FPT = VjpPlan<N, Q>::FPT, PAIR = VjpPlan<N, Q>::PAIR,
+                 SUX = VjpPlan<N, Q>::SUX;
+  // with SUX, the cell's nodal values of u sit in the interpolation scratch
+  // behind its first stage (as in the forward)
+  constexpr int XT = 3 * N2 * Q;                                              // interpolation stage 1
+  constexpr int XS = ICOL ? 0 : 3 * N * Q2;                                   // interpolation stage 2
+  constexpr int XI = XT + (SUX ? (3 * N3 > XS ? 3 * N3 : XS) : XS);
   constexpr int XD = 2 * N2 * Q + 3 * N * Q2;                                 // gradient scratch
   constexpr int XL = 3 * N * Q2 + 3 * N2 * Q;                                 // cell lift scratch
   constexpr int XF = PAIR ? 24 * N2 + 24 * N * Q + 6 * Q2                      // two faces: 24 planes + fluxes
                           : 12 * N2 + 12 * N * Q + (FPT ? 0 : 12 * Q2) + 3 * Q2;   // one face: 12 planes + fluxes
   constexpr int XID = XI > XD ? XI : XD, XLF = XL > XF ? XL : XF;
   constexpr int X = XID > XLF ? XID : XLF;
-  __shared__ double sU[3 * N3];
   __shared__ double sW[3 * N3];
   __shared__ double sO[3 * N3];
   __shared__ double sX[X];
+  __shared__ double sUa[SUX ? 1 : 3 * N3];
+  double* sU = SUX ? sX + XT : sUa;
   const int tid = threadIdx.x;
   constexpr int nthr = SH::THREADS;
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
@@ -946,13 +957,15 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
       for (int s = 0; s < 2; ++s) {
         double* Ps = P + s * 12 * N2;
         const int64_t nb = s ? nb1 : nb0;
-        copy_plane<N>(sU, d, s, Ps + 0 * 3 * N2, 1.0, tid, nthr);
+        if constexpr (SUX) load_plane<N>(U, Nd, cell, d, s, Ps + 0 * 3 * N2, tid, nthr);
+        else copy_plane<N>(sU, d, s, Ps + 0 * 3 * N2, 1.0, tid, nthr);
         copy_plane<N>(sW, d, s, Ps + 2 * 3 * N2, 1.0, tid, nthr);
         if (nb >= 0) {
           load_plane<N>(U, Nd, nb, d, 1 - s, Ps + 1 * 3 * N2, tid, nthr);
           load_plane<N>(W, Nd, nb, d, 1 - s, Ps + 3 * 3 * N2, tid, nthr);
         } else {
-          copy_plane<N>(sU, d, s, Ps + 1 * 3 * N2, -1.0, tid, nthr);
+          if constexpr (SUX) load_plane_scaled<N>(U, Nd, cell, d, s, Ps + 1 * 3 * N2, -1.0, tid, nthr);
+          else copy_plane<N>(sU, d, s, Ps + 1 * 3 * N2, -1.0, tid, nthr);
           copy_plane<N>(sW, d, s, Ps + 3 * 3 * N2, 0.0, tid, nthr);   // not used
         }
       }
@@ -998,13 +1011,15 @@ __global__ void __launch_bounds__((CShape<N, Q>::THREADS)) k_conv_vjp(const doub
     double* F1 = sX + 12 * N2;        // 12 * N*Q: [plane][q1][p2] (FPT), else [plane][p2][q1]
     double* F2 = F1 + 12 * N * Q;     // 12 * Q*Q, without FPT
     const int64_t nb = conv_nb(g, cg, cell, d, s);
-    copy_plane<N>(sU, d, s, P + 0 * 3 * N2, 1.0, tid, nthr);
+    if constexpr (SUX) load_plane<N>(U, Nd, cell, d, s, P + 0 * 3 * N2, tid, nthr);
+    else copy_plane<N>(sU, d, s, P + 0 * 3 * N2, 1.0, tid, nthr);
     copy_plane<N>(sW, d, s, P + 2 * 3 * N2, 1.0, tid, nthr);
     if (nb >= 0) {
       load_plane<N>(U, Nd, nb, d, 1 - s, P + 1 * 3 * N2, tid, nthr);
       load_plane<N>(W, Nd, nb, d, 1 - s, P + 3 * 3 * N2, tid, nthr);
     } else {
-      copy_plane<N>(sU, d, s, P + 1 * 3 * N2, -1.0, tid, nthr);
+      if constexpr (SUX) load_plane_scaled<N>(U, Nd, cell, d, s, P + 1 * 3 * N2, -1.0, tid, nthr);
+      else copy_plane<N>(sU, d, s, P + 1 * 3 * N2, -1.0, tid, nthr);
     }
     __syncthreads();
     if constexpr (FPT) face_interp_t1<N, Q, nthr>(S, P, F1, nb >= 0 ? 12 : 9, tid);
