@@ -31,6 +31,13 @@ SMALL = {
     "k6_q10_dirichlet": (6, (1, 2, 1), (1, 1, 1), 0, (0, 0, 1), 0, 10),
     "k2_all_dirichlet": (2, (2, 2, 2), (1, 1, 1), 0, (0, 0, 0), 0, 4),
     "k3_one_cell_periodic": (3, (1, 1, 2), (1, 1, 1), 0, (1, 1, 1), 0, 6),
+    # the per-(n, n_q) layouts of the kernels with walls: both faces of a
+    # direction in one VJP pass (k = 1, k = 5 with 9 points), u's nodal
+    # values in the interpolation scratch (k = 5 with 8 points), n_q = 11
+    "k1_q2_walls": (1, (2, 2, 3), (1, 1, 1), 0, (0, 0, 1), 0, 2),
+    "k5_q9_walls": (5, (2, 2, 2), (1, 1.3, 1), 0, (1, 0, 1), 0, 9),
+    "k5_q8_walls": (5, (2, 3, 1), (1, 1, 1), 0, (0, 1, 1), 0, 8),
+    "k6_q11": (6, (1, 1, 2), (1, 1, 1), 0, (1, 1, 1), 0, 11),
 }
 
 
