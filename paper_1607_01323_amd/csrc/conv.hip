@@ -22,7 +22,8 @@
 // Kernel layout: one cell per workgroup.  Thread (qx, qy) owns the z-column
 // of quadrature points of its (qx, qy) in registers (values, fluxes, VJP
 // accumulators); sweeps along x and y are staged through LDS with one thread
-// per line; faces are processed one direction (or one face) at a time and
+// per line, or per point where that saves LDS and a barrier (FwdPlan,
+// VjpPlan); faces are processed one direction (or one face) at a time and
 // their lifts land on the cell's boundary node planes before a single
 // coalesced store.  The substep variant applies the inverse mass block
 // (Mh^{-1} along x, y and z, times 1/|det J|; Sec. 5, implementation) to the
