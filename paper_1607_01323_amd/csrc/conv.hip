@@ -52,10 +52,11 @@ struct CShape {
 // Unroll factor of the sweep loops that step over table rows / columns: small
 // tables fit the scalar registers whole and are unrolled completely; large
 // ones (n * n_q > 48) step one row or column at a time, which keeps the
-// compiler from spilling table entries (three rows in flight, so the scalar
-// loads of the next rows overlap the arithmetic of the current one).
+// compiler from spilling table entries (six rows in flight, so the scalar
+// loads of the next rows overlap the arithmetic of the current one; two and
+// three measured slower at k = 5, n_q = 9, with no spills at six).
 template <int N, int Q>
-constexpr int kSweepUnroll = N * Q > 48 ? 3 : 16;
+constexpr int kSweepUnroll = N * Q > 48 ? 6 : 16;
 
 struct CellGeo {
   int c[3];
