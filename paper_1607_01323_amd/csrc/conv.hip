@@ -1295,7 +1295,8 @@ struct CurvCell {
 
 // out = (M + tau D) u on one cell; u, out [3][n^3]; W: 8 n^3 scratch
 template <int N>
-__device__ void curv_mdd(const CurvCell& c, double tau, const double* u, double* out, double* W, int tid, int nthr) {
+__device__ __forceinline__ void curv_mdd(const CurvCell& c, double tau, const double* u, double* out, double* W,
+                                         int tid, int nthr) {
   constexpr int N3 = N * N * N;
   double* X1 = W;
   double* X2 = W + N3;
@@ -1362,7 +1363,7 @@ __device__ void curv_mdd(const CurvCell& c, double tau, const double* u, double*
 
 // z = M^{-1} r on one cell, three components, in place on z (which holds r on entry)
 template <int N>
-__device__ void curv_minv(const CurvCell& c, double* z, int tid, int nthr) {
+__device__ __forceinline__ void curv_minv(const CurvCell& c, double* z, int tid, int nthr) {
   constexpr int N3 = N * N * N;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -1384,7 +1385,8 @@ __global__ void __launch_bounds__(64) k_curv_tau(const double* __restrict__ U, c
                                                  double* __restrict__ tau, int64_t ncells) {
   constexpr int N3 = N * N * N;
   __shared__ double sU[3 * N3];
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nthr = 64;   // the launch size
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
@@ -1417,7 +1419,8 @@ __global__ void __launch_bounds__(64) k_curv_proj(const ConvGeom g, const double
                                                   int* __restrict__ iters, int64_t ncells) {
   constexpr int N3 = N * N * N;
   __shared__ double sX[3 * N3], sR[3 * N3], sP[3 * N3], sQ[3 * N3], sW[8 * N3];
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nthr = 64;   // the launch size
   const int64_t cell = xcd_cell(blockIdx.x, gridDim.x);
   if (cell >= ncells) return;
   const int64_t Nd = ncells * N3;
