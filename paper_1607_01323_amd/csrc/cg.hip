@@ -228,6 +228,71 @@ __global__ void __launch_bounds__(256) k_update(double* __restrict__ x, double* 
   if (z) block_partials<3>(v, partials, blockIdx.x);
 }
 
+// k_update on element pairs (16-byte loads and stores; every vector 16-byte
+// aligned), the odd last element by the first thread of the grid
+__global__ void __launch_bounds__(256) k_update2(double* __restrict__ x, double* __restrict__ r,
+                                                 const double* __restrict__ p, const double* __restrict__ q,
+                                                 const double* __restrict__ dinv, double* __restrict__ z, int64_t N,
+                                                 const CgState* st, double* partials) {
+  if (st->status != RUNNING) return;
+  const double a = st->alpha, mq = st->mean_q;
+  double v[3] = {0, 0, 0};
+  auto one = [&](double& xi, double& ri, double& zi, double pi, double qi, double di) {
+    xi = fma(a, pi, xi);
+    const double qm = qi - mq;
+    ri = fma(-a, qm, ri);
+    v[1] += ri * ri;
+    if (z) {
+      zi = di * ri;
+      v[0] += ri * zi;
+      v[2] += zi * qm;
+    }
+  };
+  const int64_t N2 = N >> 1;
+  double2* x2 = reinterpret_cast<double2*>(x);
+  double2* r2 = reinterpret_cast<double2*>(r);
+  double2* z2 = reinterpret_cast<double2*>(z);
+  const double2* p2 = reinterpret_cast<const double2*>(p);
+  const double2* q2 = reinterpret_cast<const double2*>(q);
+  const double2* d2 = reinterpret_cast<const double2*>(dinv);
+  GRID_STRIDE(i, N2) {
+    double2 xv = x2[i], rv = r2[i];
+    const double2 pv = p2[i], qv = q2[i];
+    double2 dv = make_double2(0.0, 0.0), zv;
+    if (z) dv = d2[i];
+    one(xv.x, rv.x, zv.x, pv.x, qv.x, dv.x);
+    one(xv.y, rv.y, zv.y, pv.y, qv.y, dv.y);
+    x2[i] = xv;
+    r2[i] = rv;
+    if (z) z2[i] = zv;
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t k = N - 1;
+    double zk = 0.0;
+    one(x[k], r[k], zk, p[k], q[k], z ? dinv[k] : 0.0);
+    if (z) z[k] = zk;
+  }
+  if (z) block_partials<3>(v, partials, blockIdx.x);
+}
+
+// p = z + beta p on element pairs, as k_update2
+__global__ void __launch_bounds__(256) k_update_p2(double* __restrict__ p, const double* __restrict__ z, int64_t N,
+                                                   const CgState* st, int first) {
+  if (st->status != RUNNING) return;
+  const double b = first ? 0.0 : st->beta;
+  const int64_t N2 = N >> 1;
+  double2* p2 = reinterpret_cast<double2*>(p);
+  const double2* z2 = reinterpret_cast<const double2*>(z);
+  GRID_STRIDE(i, N2) {
+    const double2 zv = z2[i];
+    double2 pv = first ? make_double2(0.0, 0.0) : p2[i];
+    pv.x = fma(b, pv.x, zv.x);
+    pv.y = fma(b, pv.y, zv.y);
+    p2[i] = pv;
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[N - 1] = first ? z[N - 1] : fma(b, p[N - 1], z[N - 1]);
+}
+
 // p = z + beta p  (first = 1: p = z)
 __global__ void __launch_bounds__(256) k_update_p(double* __restrict__ p, const double* __restrict__ z, int64_t N,
                                                   const CgState* st, int first) {
@@ -1203,16 +1268,23 @@ dgmf_status cg_run(dgmf_op op, const double* b, double* x, const dgmf_cg_params*
 
   // ---- iteration
   const int batch = params->check_every > 0 ? params->check_every : 1;
+  // pairs of elements per thread where x is 16-byte aligned (the workspace
+  // vectors always are)
+  const bool pairs = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
   while (h.status == RUNNING) {
     for (int k = 0; k < batch; ++k) {
       if ((e = S.apply<double>(p, q, true))) return e;
       if ((e = S.scalar(M_ALPHA, napply))) return e;
-      hipLaunchKernelGGL(k_update, G, B, 0, stream, x, r, p, q, dinv, poly ? static_cast<double*>(nullptr) : z, N,
-                         S.st, S.partials);
+      if (pairs)
+        hipLaunchKernelGGL(k_update2, G, B, 0, stream, x, r, p, q, dinv, poly ? static_cast<double*>(nullptr) : z, N,
+                           S.st, S.partials);
+      else
+        hipLaunchKernelGGL(k_update, G, B, 0, stream, x, r, p, q, dinv, poly ? static_cast<double*>(nullptr) : z, N,
+                           S.st, S.partials);
       DGMF_LAUNCH_CHECK("k_update");
       if (poly && (e = S.precond(r, z, q))) return e;
       if ((e = S.scalar(M_BETA, kVecBlocks))) return e;
-      hipLaunchKernelGGL(k_update_p, G, B, 0, stream, p, z, N, S.st, 0);
+      hipLaunchKernelGGL(k_update_p2, G, B, 0, stream, p, z, N, S.st, 0);
       DGMF_LAUNCH_CHECK("k_update_p");
     }
     DGMF_HIP_TRY(hipMemcpyAsync(&h, S.st, sizeof(h), hipMemcpyDeviceToHost, stream));
